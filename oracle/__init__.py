@@ -1,0 +1,262 @@
+"""CPU oracle for the FIt-SNE per-iteration t-SNE gradient.
+
+TEST INFRASTRUCTURE ONLY: used by ``tests/``, the package smoke check and the
+benchmark's CPU-baseline leg, never by the GPU library.  It shares no code
+with the GPU path; both are fed from ``paper_1712_09005_amd.inputs``, which
+holds no gradient arithmetic.
+
+The arithmetic lives in ``oracle.c`` (plain FP64 C, OpenMP over independent
+rows), loaded here with ctypes.  Function-by-function citations of the paper
+are in that file.  Every routine is pinned by the ``-m "not gpu"`` tests
+against closed forms, hand-computed values, brute force on tiny inputs and
+invariants, except the constants of the descent step (``update``), which the
+paper does not state: the rule is pinned by hand-computed steps, its constants
+are a reading (parity unpinned by the paper).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+KERNEL_TSNE, KERNEL_POLY = 0, 1
+FORM_A, FORM_B = 0, 1
+POLICY_PAPER, POLICY_FIXED = 0, 1
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (FP64, no fast-math, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared",
+                               "-fno-fast-math", "-ffp-contract=off",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        _lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64, i32, f64 = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        sig = {
+            "oracle_direct_sums": [i64, i32, P, i32, P, i64, P, P],
+            "oracle_direct_rep": [i64, i32, P, i32, P, P],
+            "oracle_attr": [i64, i32, P, P, P, P, P],
+            "oracle_geometry": [i64, i32, P, i32, i32, f64, P, P, P],
+            "oracle_lagrange": [i32, f64, P],
+            "oracle_grid_conv": [i32, i32, f64, i32, i32, P, P],
+            "oracle_interp_rep": [i64, i32, P, P, f64, i32, i32, i32, i32,
+                                  P, P, P, P, P, P],
+            "oracle_interp_spread": [i64, i32, P, P, f64, i32, i32, i32, P],
+            "oracle_interp_rows": [i64, i32, P, P, f64, i32, i32, i32, i32,
+                                   P, P, i64, P],
+            "oracle_update": [i64, i32, P, P, P, P, P, f64, f64, f64, f64,
+                              f64, f64, i32],
+        }
+        for name, args in sig.items():
+            fn = getattr(_lib, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int if name.startswith("oracle_interp") else None
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a):
+    return a.ctypes.data if a is not None else None
+
+
+def threads() -> int:
+    """OpenMP threads the oracle will use."""
+    n = os.environ.get("OMP_NUM_THREADS")
+    return int(n) if n else (os.cpu_count() or 1)
+
+
+# ---------------------------------------------------------------- direct sums
+def direct_sums(Y, rows=None, kind=KERNEL_TSNE):
+    """Per-row h1 [r] and unnormalised repulsive numerators [r, s] by the direct
+    O(N) sum per row.  ``rows`` None means every row."""
+    Y = _f64(Y)
+    n, s = Y.shape
+    if rows is None:
+        r = None
+        nr = n
+    else:
+        r = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+        nr = r.shape[0]
+    h1 = np.empty(nr)
+    num = np.empty((nr, s))
+    _load().oracle_direct_sums(n, s, _ptr(Y), kind, _ptr(r), nr, _ptr(h1), _ptr(num))
+    return h1, num
+
+
+def direct_rep(Y, kind=KERNEL_TSNE):
+    """(F_rep [N, s], Z) by the O(N^2) definitions."""
+    Y = _f64(Y)
+    n, s = Y.shape
+    F = np.empty((n, s))
+    Z = ctypes.c_double()
+    _load().oracle_direct_rep(n, s, _ptr(Y), kind, _ptr(F), ctypes.addressof(Z))
+    return F, Z.value
+
+
+def attr(Y, P):
+    """F_attr [N, s] over the CSR P (``inputs.CSR``)."""
+    Y = _f64(Y)
+    n, s = Y.shape
+    rp = np.ascontiguousarray(P.row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(P.col, dtype=np.int32)
+    val = _f64(P.val)
+    F = np.empty((n, s))
+    _load().oracle_attr(n, s, _ptr(Y), _ptr(rp), _ptr(col), _ptr(val), _ptr(F))
+    return F
+
+
+# ---------------------------------------------------------------- geometry
+def geometry(Y, policy, min_intervals=1, interval_width=1.0):
+    """(origin [s], w_int, N_int) of the box policy."""
+    Y = _f64(Y)
+    n, s = Y.shape
+    o = np.empty(s)
+    w = ctypes.c_double()
+    m = ctypes.c_int()
+    pol = POLICY_PAPER if policy in ("paper", POLICY_PAPER) else POLICY_FIXED
+    _load().oracle_geometry(n, s, _ptr(Y), pol, int(min_intervals), float(interval_width),
+                            _ptr(o), ctypes.addressof(w), ctypes.addressof(m))
+    return o, w.value, m.value
+
+
+# ---------------------------------------------------------------- interpolation
+def lagrange(p, t):
+    L = np.empty(p)
+    _load().oracle_lagrange(p, float(t), _ptr(L))
+    return L
+
+
+def grid_conv(W, h, kernel, kind=KERNEL_TSNE):
+    """Step 2 directly on a 1-D [ng] or 2-D [ng, ng] (index [g1, g0]) grid."""
+    W = _f64(W)
+    s = W.ndim
+    ng = W.shape[0]
+    V = np.empty_like(W)
+    _load().oracle_grid_conv(s, ng, float(h), kind, int(kernel), _ptr(W), _ptr(V))
+    return V
+
+
+def interp_rep(Y, origin, w_int, n_int, p=3, form=FORM_A, kind=KERNEL_TSNE,
+               want_grids=False):
+    """Interpolation scheme with direct Step 2.  Returns a dict with F [N, s],
+    Z, phi [N, s+2], h1 [N] and (``want_grids``) W [C, ng(, ng)], V [s+2, ...]."""
+    Y = _f64(Y)
+    n, s = Y.shape
+    o = _f64(origin)
+    ng = n_int * p
+    tn = ng ** s
+    nc = s + 1 if form == FORM_A else s + 2
+    F = np.empty((n, s))
+    Z = ctypes.c_double()
+    phi = np.empty((n, s + 2))
+    h1 = np.empty(n)
+    W = np.empty((nc, tn)) if want_grids else None
+    V = np.empty((s + 2, tn)) if want_grids else None
+    rc = _load().oracle_interp_rep(n, s, _ptr(Y), _ptr(o), float(w_int), int(n_int), int(p),
+                                   int(form), int(kind), _ptr(F), ctypes.addressof(Z),
+                                   _ptr(W), _ptr(V), _ptr(phi), _ptr(h1))
+    if rc != 0:
+        raise ValueError("oracle_interp_rep: bad arguments")
+    out = dict(F=F, Z=Z.value, phi=phi, h1=h1)
+    if want_grids:
+        shape = (ng,) if s == 1 else (ng, ng)
+        out["W"] = W.reshape((nc,) + shape)
+        out["V"] = V.reshape((s + 2,) + shape)
+    return out
+
+
+def interp_spread(Y, origin, w_int, n_int, p=3, form=FORM_A):
+    Y = _f64(Y)
+    n, s = Y.shape
+    ng = n_int * p
+    nc = s + 1 if form == FORM_A else s + 2
+    W = np.empty((nc, ng ** s))
+    rc = _load().oracle_interp_spread(n, s, _ptr(Y), _ptr(_f64(origin)), float(w_int),
+                                      int(n_int), int(p), int(form), _ptr(W))
+    if rc != 0:
+        raise ValueError("oracle_interp_spread: bad arguments")
+    return W
+
+
+def interp_rows(Y, origin, w_int, n_int, rows, W, p=3, form=FORM_A, kind=KERNEL_TSNE):
+    """phi [len(rows), s+2] at the listed points, node values by direct sums."""
+    Y = _f64(Y)
+    n, s = Y.shape
+    r = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+    phi = np.empty((r.shape[0], s + 2))
+    rc = _load().oracle_interp_rows(n, s, _ptr(Y), _ptr(_f64(origin)), float(w_int),
+                                    int(n_int), int(p), int(form), int(kind), _ptr(_f64(W)),
+                                    _ptr(r), r.shape[0], _ptr(phi))
+    if rc != 0:
+        raise ValueError("oracle_interp_rows: bad arguments")
+    return phi
+
+
+def centre(origin, w_int, n_int):
+    """Box centre used to centre the charges."""
+    return _f64(origin) + 0.5 * n_int * w_int
+
+
+def assemble_rows(Y, origin, w_int, n_int, phi, form=FORM_A):
+    """Unnormalised (h1 [r], numerator [r, s]) for rows whose potentials are
+    ``phi`` (Appendix assembly; see oracle_interp_rep)."""
+    Y = _f64(Y)
+    s = Y.shape[1]
+    yc = Y - centre(origin, w_int, n_int)
+    if form == FORM_A:
+        h1 = phi[:, 0].copy()
+    else:
+        r2 = (yc * yc).sum(1)
+        h1 = (1.0 + r2) * phi[:, 1] - 2.0 * (yc * phi[:, 2:2 + s]).sum(1) + phi[:, 0]
+    num = yc * phi[:, 1:2] - phi[:, 2:2 + s]
+    return h1, num
+
+
+# ---------------------------------------------------------------- update
+def update(Y, uY, gains, Fattr, Frep, alpha, mom, eta, gain_inc=0.2, gain_dec=0.8,
+           gain_min=0.01, recentre=True):
+    """One descent step; returns new (Y, uY, gains) as float64 arrays."""
+    Y = _f64(Y).copy()
+    uY = _f64(uY).copy()
+    gains = _f64(gains).copy()
+    n, s = Y.shape
+    _load().oracle_update(n, s, _ptr(Y), _ptr(uY), _ptr(gains), _ptr(_f64(Fattr)),
+                          _ptr(_f64(Frep)), float(alpha), float(mom), float(eta),
+                          float(gain_inc), float(gain_dec), float(gain_min), int(bool(recentre)))
+    return Y, uY, gains
+
+
+def schedule(it, ee_alpha=12.0, ee_stop=250, le_alpha=1.0, le_start=1 << 30,
+             mom0=0.5, mom1=0.8, mom_switch=250):
+    """(alpha, momentum) at iteration ``it`` (early exaggeration Section 1.2,
+    late exaggeration Section 4; the momentum switch is not in the paper)."""
+    if it >= le_start:
+        alpha = le_alpha
+    elif it < ee_stop:
+        alpha = ee_alpha
+    else:
+        alpha = 1.0
+    mom = mom0 if it < mom_switch else mom1
+    return alpha, mom

@@ -1,0 +1,527 @@
+/*
+ * CPU oracle for the FIt-SNE per-iteration gradient (Linderman et al.,
+ * "Efficient Algorithms for t-distributed Stochastic Neighborhood Embedding").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, FP64 statement of
+ * what the GPU library must compute.  It shares no code, header, table or
+ * constant generator with the GPU library and is used only by the tests, the
+ * package's smoke check and the benchmark's CPU-baseline leg.
+ *
+ * Everything is double precision, no fast-math, no blocking or reordering of
+ * sums beyond what the definitions state; OpenMP only splits independent
+ * output rows.
+ *
+ * Parts:
+ *   (1) direct sums: Z, the repulsive and attractive forces by their definitions
+ *       (Section 1.1; Section 2, eq. (frep); Section 3);
+ *   (2) the interpolation scheme with Step 2 done directly (Section 2.2 steps
+ *       1-3 and Algorithm 1 without the FFT; Section 2.4 for s = 2; the
+ *       Appendix for assembling the forces from the s+2 kernel sums);
+ *   (3) the gradient-descent update (gradient of Section 1.1 with the
+ *       exaggeration factor of Section 1.2 / Section 4; the step rule itself
+ *       is not in the paper, see oracle_update).
+ *
+ * Readings of the paper used here (silent or inconsistent passages):
+ *   - sign: F_rep,i = sum_j K2_ij (y_i - y_j) / Z, the sign of the
+ *     attractive/repulsive split in Section 1.1, so that the gradient is
+ *     4 (alpha F_attr - F_rep); eq. (frep) and the Appendix print the
+ *     opposite sign;
+ *   - nodes of interval l sit at origin + (l p + m + 1/2) h, m = 0..p-1, the
+ *     affine image of eq. (equinodes) on the box;
+ *   - a point belongs to interval floor((y - origin)/w), clamped to
+ *     [0, N_int - 1];
+ *   - Z = sum_i h1_i - N K1(0): the grid sums include the self pair, whose
+ *     exact kernel value K1(0) is removed (force numerators cancel the self
+ *     pair identically);
+ *   - charges are centred at the box centre (translation invariance).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Kernel families.  ORACLE_KERNEL_TSNE is the pair of Section 2, eq. (kers):
+ * K1 = 1/(1+r^2), K2 = K1^2.  ORACLE_KERNEL_POLY is a test family that keeps
+ * the identity K1 = (1 + r^2) K2 but is polynomial (K2 of degree 2 and K1 of
+ * degree 4 in each coordinate), so that interpolation with enough nodes per
+ * interval is exact and the scheme must reproduce the direct sum to rounding. */
+enum { ORACLE_KERNEL_TSNE = 0, ORACLE_KERNEL_POLY = 1 };
+/* Charge sets: FORM_A follows the Appendix (K1 with charge 1, K2 with charges
+ * 1 and y(d)); FORM_B uses K2 with charges 1, y(d) and |y|^2, and gets the K1
+ * sum from K1 = (1 + r^2) K2. */
+enum { ORACLE_FORM_A = 0, ORACLE_FORM_B = 1 };
+enum { ORACLE_POLICY_PAPER = 0, ORACLE_POLICY_FIXED = 1 };
+
+static double kern1(int kind, double r2)
+{
+    if (kind == ORACLE_KERNEL_TSNE) return 1.0 / (1.0 + r2);
+    return (1.0 + r2) * (2.0 + r2 / 8.0);
+}
+
+static double kern2(int kind, double r2)
+{
+    if (kind == ORACLE_KERNEL_TSNE) {
+        double a = 1.0 / (1.0 + r2);
+        return a * a;
+    }
+    return 2.0 + r2 / 8.0;
+}
+
+static double sqdist(int s, const double* a, const double* b)
+{
+    double r2 = 0.0;
+    for (int d = 0; d < s; ++d) {
+        double t = a[d] - b[d];
+        r2 += t * t;
+    }
+    return r2;
+}
+
+/* ------------------------------------------------------------------------ */
+/* (1) Direct sums                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* Unnormalised per-point sums for the listed rows (all rows if rows == NULL):
+ *   h1[r]      = sum_{j != i} K1(|y_i - y_j|^2)                 (Appendix, h1)
+ *   num[r*s+d] = sum_{j != i} K2(|y_i - y_j|^2) (y_i(d) - y_j(d))  (eq. (frep)
+ *                numerator with the Section 1.1 sign)
+ * with i = rows[r].  Y is [n, s] row-major. */
+void oracle_direct_sums(int64_t n, int s, const double* Y, int kind,
+                        const int64_t* rows, int64_t nrows,
+                        double* h1, double* num)
+{
+    if (rows == NULL) nrows = n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < nrows; ++r) {
+        int64_t i = rows ? rows[r] : r;
+        const double* yi = Y + i * s;
+        double a = 0.0, f[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double* yj = Y + j * s;
+            double r2 = sqdist(s, yi, yj);
+            a += kern1(kind, r2);
+            double w = kern2(kind, r2);
+            for (int d = 0; d < s; ++d) f[d] += w * (yi[d] - yj[d]);
+        }
+        h1[r] = a;
+        for (int d = 0; d < s; ++d) num[r * s + d] = f[d];
+    }
+}
+
+/* Z = sum_{k != l} K1 (Section 1.1) and F_rep,i = num_i / Z for every point. */
+void oracle_direct_rep(int64_t n, int s, const double* Y, int kind,
+                       double* F, double* Z)
+{
+    double* h1 = (double*)malloc((size_t)n * sizeof(double));
+    oracle_direct_sums(n, s, Y, kind, NULL, n, h1, F);
+    double z = 0.0;
+    for (int64_t i = 0; i < n; ++i) z += h1[i];
+    for (int64_t k = 0; k < n * s; ++k) F[k] /= z;
+    *Z = z;
+    free(h1);
+}
+
+/* Attractive force over the sparse P (Section 3):
+ *   F_attr,i = sum_j p_ij q_ij Z (y_i - y_j) = sum_j p_ij (y_i - y_j) / (1 + |y_i - y_j|^2). */
+void oracle_attr(int64_t n, int s, const double* Y, const int64_t* row_ptr,
+                 const int32_t* col, const double* val, double* F)
+{
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        const double* yi = Y + i * s;
+        double f[3] = {0.0, 0.0, 0.0};
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            const double* yj = Y + (int64_t)col[k] * s;
+            double r2 = sqdist(s, yi, yj);
+            double w = val[k] / (1.0 + r2);
+            for (int d = 0; d < s; ++d) f[d] += w * (yi[d] - yj[d]);
+        }
+        for (int d = 0; d < s; ++d) F[i * s + d] = f[d];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Box geometry (the square box of Section 2.4; interval count of Section    */
+/* 2.5 or a fixed interval width)                                            */
+/* ------------------------------------------------------------------------ */
+
+/* Per-dimension origin = min_i y_i(d); side L = max_d (max - min), floored at
+ * 1e-6.  PAPER: N_int = max(min_intervals, ceil(L)), w = L / N_int.
+ * FIXED: w = interval_width, N_int = max(min_intervals, ceil(L / w)).
+ * Y holds the float32 inputs widened to double. */
+void oracle_geometry(int64_t n, int s, const double* Y, int policy,
+                     int min_intervals, double interval_width,
+                     double* origin, double* w_int, int* n_int)
+{
+    double lo[3], hi[3];
+    for (int d = 0; d < s; ++d) { lo[d] = Y[d]; hi[d] = Y[d]; }
+    for (int64_t i = 0; i < n; ++i)
+        for (int d = 0; d < s; ++d) {
+            double v = Y[i * s + d];
+            if (v < lo[d]) lo[d] = v;
+            if (v > hi[d]) hi[d] = v;
+        }
+    double L = 0.0;
+    for (int d = 0; d < s; ++d) {
+        origin[d] = lo[d];
+        if (hi[d] - lo[d] > L) L = hi[d] - lo[d];
+    }
+    if (L < 1e-6) L = 1e-6;
+    int m;
+    if (policy == ORACLE_POLICY_PAPER) {
+        m = (int)ceil(L);
+        if (m < min_intervals) m = min_intervals;
+        *w_int = L / m;
+    } else {
+        m = (int)ceil(L / interval_width);
+        if (m < min_intervals) m = min_intervals;
+        *w_int = interval_width;
+    }
+    *n_int = m;
+}
+
+/* ------------------------------------------------------------------------ */
+/* (2) Interpolation scheme, Step 2 done directly                            */
+/* ------------------------------------------------------------------------ */
+
+/* Lagrange basis on the p equispaced nodes tau_m = (m + 1/2)/p of the unit
+ * interval (Section 2.1, the Lagrange polynomials; nodes of eq. (equinodes)):
+ *   L_m(t) = prod_{k != m} (t - tau_k) / (tau_m - tau_k). */
+void oracle_lagrange(int p, double t, double* L)
+{
+    for (int m = 0; m < p; ++m) {
+        double tm = (m + 0.5) / p, a = 1.0;
+        for (int k = 0; k < p; ++k) {
+            if (k == m) continue;
+            double tk = (k + 0.5) / p;
+            a *= (t - tk) / (tm - tk);
+        }
+        L[m] = a;
+    }
+}
+
+/* Interval index and local coordinate of a coordinate value. */
+static void locate(double y, double o, double w, int n_int, int* cell, double* t)
+{
+    double u = (y - o) / w;
+    double f = floor(u);
+    int c = (int)f;
+    if (f < 0.0) c = 0;
+    if (f > (double)(n_int - 1)) c = n_int - 1;
+    *cell = c;
+    *t = u - (double)c;
+}
+
+/* Step 2 directly (eq. (equikereval2)): on a grid with ng nodes per dimension
+ * and spacing h,
+ *   V[g] = sum_{g'} K(h^2 |g - g'|^2) W[g'],
+ * where kernel selects K1 (1) or K2 (2).  2-D grids are indexed g1*ng + g0.
+ * The kernel values are taken from a table over the lag (|g0-g0'|, |g1-g1'|),
+ * which is the translation invariance that makes the matrix Toeplitz. */
+void oracle_grid_conv(int s, int ng, double h, int kind, int kernel,
+                      const double* W, double* V)
+{
+    int64_t tn = (s == 1) ? ng : (int64_t)ng * ng;
+    double* T = (double*)malloc((size_t)tn * sizeof(double));
+    for (int64_t a = 0; a < tn; ++a) {
+        double dx = (double)(a % ng), dy = (s == 1) ? 0.0 : (double)(a / ng);
+        double r2 = h * h * (dx * dx + dy * dy);
+        T[a] = (kernel == 1) ? kern1(kind, r2) : kern2(kind, r2);
+    }
+    if (s == 1) {
+#pragma omp parallel for schedule(static)
+        for (int g = 0; g < ng; ++g) {
+            double acc = 0.0;
+            for (int q = 0; q < ng; ++q) acc += T[abs(g - q)] * W[q];
+            V[g] = acc;
+        }
+    } else {
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int64_t g = 0; g < tn; ++g) {
+            int g0 = (int)(g % ng), g1 = (int)(g / ng);
+            double acc = 0.0;
+            for (int q1 = 0; q1 < ng; ++q1) {
+                const double* Trow = T + (int64_t)abs(g1 - q1) * ng;
+                const double* Wrow = W + (int64_t)q1 * ng;
+                for (int q0 = 0; q0 < ng; ++q0) acc += Trow[abs(g0 - q0)] * Wrow[q0];
+            }
+            V[g] = acc;
+        }
+    }
+    free(T);
+}
+
+/* The interpolation-based repulsion for s = 1 or 2 with the given box
+ * (origin[s], interval width w, N_int intervals, p nodes per interval).
+ *
+ * Charges (centred at the box centre c): form A {1, y'(d)}, form B
+ * {1, y'(d), |y'|^2}; y' = y - c.  Potentials (s + 2 of them):
+ *   pot[0] = K1 * 1 (form A)  or  K2 * |y'|^2 (form B)
+ *   pot[1] = K2 * 1
+ *   pot[2+d] = K2 * y'(d)
+ * Step 1 spreads each charge onto the nodes of its point's interval (square),
+ * Step 2 is oracle_grid_conv, Step 3 interpolates back (Section 2.2,
+ * Algorithm 1; tensor-product nodes for s = 2, Section 2.4).  Assembly
+ * (Appendix): h1 = pot[0] (form A) or
+ * h1 = (1 + |y'|^2) pot[1] - 2 y'.pot[2..] + pot[0] (form B);
+ * Z = sum_i h1_i - N K1(0); F_i(d) = (y'_i(d) pot[1]_i - pot[2+d]_i) / Z.
+ *
+ * Outputs: F [n*s], Z; optional (may be NULL): Wout [C][ng^s] charge grids
+ * (C = s+1 form A, s+2 form B, charge order 1, y'(0..s-1), |y'|^2),
+ * Vout [s+2][ng^s] potential grids, phi [n][s+2] potentials at the points,
+ * h1 [n].  Returns 0, or -1 on bad arguments. */
+int oracle_interp_rep(int64_t n, int s, const double* Y, const double* origin,
+                      double w, int n_int, int p, int form, int kind,
+                      double* F, double* Z, double* Wout, double* Vout,
+                      double* phi, double* h1out)
+{
+    if (s < 1 || s > 2 || p < 1 || n_int < 1 || n < 1) return -1;
+    int ng = n_int * p;
+    int64_t tn = (s == 1) ? ng : (int64_t)ng * ng;
+    int nc = (form == ORACLE_FORM_A) ? s + 1 : s + 2;
+    int np = s + 2;
+    double h = w / p;
+    double centre[2];
+    for (int d = 0; d < s; ++d) centre[d] = origin[d] + 0.5 * n_int * w;
+
+    int* cells = (int*)malloc((size_t)n * s * sizeof(int));
+    double* wts = (double*)malloc((size_t)n * s * p * sizeof(double));
+    double* q = (double*)malloc((size_t)n * nc * sizeof(double));
+    for (int64_t i = 0; i < n; ++i) {
+        double r2c = 0.0;
+        q[i * nc + 0] = 1.0;
+        for (int d = 0; d < s; ++d) {
+            double t;
+            locate(Y[i * s + d], origin[d], w, n_int, &cells[i * s + d], &t);
+            oracle_lagrange(p, t, wts + (i * s + d) * p);
+            double yc = Y[i * s + d] - centre[d];
+            q[i * nc + 1 + d] = yc;
+            r2c += yc * yc;
+        }
+        if (form == ORACLE_FORM_B) q[i * nc + 1 + s] = r2c;
+    }
+
+    /* Step 1: w_{m,l} = sum_{y_i in I_l} L_m(y_i) q_i */
+    double* W = (double*)calloc((size_t)nc * tn, sizeof(double));
+    for (int64_t i = 0; i < n; ++i) {
+        if (s == 1) {
+            for (int m = 0; m < p; ++m) {
+                int64_t g = (int64_t)cells[i] * p + m;
+                double l = wts[i * p + m];
+                for (int c = 0; c < nc; ++c) W[c * tn + g] += l * q[i * nc + c];
+            }
+        } else {
+            for (int m1 = 0; m1 < p; ++m1)
+                for (int m0 = 0; m0 < p; ++m0) {
+                    int64_t g0 = (int64_t)cells[i * 2 + 0] * p + m0;
+                    int64_t g1 = (int64_t)cells[i * 2 + 1] * p + m1;
+                    double l = wts[(i * 2 + 0) * p + m0] * wts[(i * 2 + 1) * p + m1];
+                    for (int c = 0; c < nc; ++c)
+                        W[c * tn + g1 * ng + g0] += l * q[i * nc + c];
+                }
+        }
+    }
+
+    /* Step 2: v = K~ w for every (kernel, charge) pair */
+    double* V = (double*)malloc((size_t)np * tn * sizeof(double));
+    int pk[5], pc[5];
+    if (form == ORACLE_FORM_A) { pk[0] = 1; pc[0] = 0; }
+    else                       { pk[0] = 2; pc[0] = s + 1; }
+    pk[1] = 2; pc[1] = 0;
+    for (int d = 0; d < s; ++d) { pk[2 + d] = 2; pc[2 + d] = 1 + d; }
+    for (int k = 0; k < np; ++k)
+        oracle_grid_conv(s, ng, h, kind, pk[k], W + (int64_t)pc[k] * tn, V + (int64_t)k * tn);
+
+    /* Step 3: phi(y_i) = sum_m L_m(y_i) v_{m,l} */
+    double* ph = (double*)calloc((size_t)n * np, sizeof(double));
+    for (int64_t i = 0; i < n; ++i) {
+        for (int k = 0; k < np; ++k) {
+            double acc = 0.0;
+            if (s == 1) {
+                for (int m = 0; m < p; ++m)
+                    acc += wts[i * p + m] * V[k * tn + (int64_t)cells[i] * p + m];
+            } else {
+                for (int m1 = 0; m1 < p; ++m1)
+                    for (int m0 = 0; m0 < p; ++m0) {
+                        int64_t g0 = (int64_t)cells[i * 2 + 0] * p + m0;
+                        int64_t g1 = (int64_t)cells[i * 2 + 1] * p + m1;
+                        acc += wts[(i * 2 + 0) * p + m0] * wts[(i * 2 + 1) * p + m1]
+                               * V[k * tn + g1 * ng + g0];
+                    }
+            }
+            ph[i * np + k] = acc;
+        }
+    }
+
+    /* Assembly (Appendix) */
+    double z = 0.0;
+    double* h1 = (double*)malloc((size_t)n * sizeof(double));
+    for (int64_t i = 0; i < n; ++i) {
+        const double* f = ph + i * np;
+        double a;
+        if (form == ORACLE_FORM_A) {
+            a = f[0];
+        } else {
+            double r2c = q[i * nc + 1 + s], dot = 0.0;
+            for (int d = 0; d < s; ++d) dot += q[i * nc + 1 + d] * f[2 + d];
+            a = (1.0 + r2c) * f[1] - 2.0 * dot + f[0];
+        }
+        h1[i] = a;
+        z += a;
+    }
+    z -= (double)n * kern1(kind, 0.0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int d = 0; d < s; ++d)
+            F[i * s + d] = (q[i * nc + 1 + d] * ph[i * np + 1] - ph[i * np + 2 + d]) / z;
+    *Z = z;
+
+    if (Wout) memcpy(Wout, W, (size_t)nc * tn * sizeof(double));
+    if (Vout) memcpy(Vout, V, (size_t)np * tn * sizeof(double));
+    if (phi) memcpy(phi, ph, (size_t)n * np * sizeof(double));
+    if (h1out) memcpy(h1out, h1, (size_t)n * sizeof(double));
+    free(cells); free(wts); free(q); free(W); free(V); free(ph); free(h1);
+    return 0;
+}
+
+/* Step 1 alone: the charge grids W [C][ng^s] of oracle_interp_rep. */
+int oracle_interp_spread(int64_t n, int s, const double* Y, const double* origin,
+                         double w, int n_int, int p, int form, double* Wout)
+{
+    if (s < 1 || s > 2 || p < 1 || n_int < 1) return -1;
+    int ng = n_int * p;
+    int64_t tn = (s == 1) ? ng : (int64_t)ng * ng;
+    int nc = (form == ORACLE_FORM_A) ? s + 1 : s + 2;
+    double centre[2], L0[16], L1[16];
+    for (int d = 0; d < s; ++d) centre[d] = origin[d] + 0.5 * n_int * w;
+    memset(Wout, 0, (size_t)nc * tn * sizeof(double));
+    for (int64_t i = 0; i < n; ++i) {
+        int c0 = 0, c1 = 0;
+        double t0, t1 = 0.0, qv[4], r2c = 0.0;
+        locate(Y[i * s], origin[0], w, n_int, &c0, &t0);
+        oracle_lagrange(p, t0, L0);
+        if (s == 2) {
+            locate(Y[i * s + 1], origin[1], w, n_int, &c1, &t1);
+            oracle_lagrange(p, t1, L1);
+        } else {
+            L1[0] = 1.0;
+        }
+        qv[0] = 1.0;
+        for (int d = 0; d < s; ++d) {
+            qv[1 + d] = Y[i * s + d] - centre[d];
+            r2c += qv[1 + d] * qv[1 + d];
+        }
+        if (form == ORACLE_FORM_B) qv[1 + s] = r2c;
+        int p1 = (s == 2) ? p : 1;
+        for (int m1 = 0; m1 < p1; ++m1)
+            for (int m0 = 0; m0 < p; ++m0) {
+                int64_t g = (int64_t)(c1 * p + m1) * ((s == 2) ? ng : 0) + c0 * p + m0;
+                double l = L0[m0] * L1[m1];
+                for (int c = 0; c < nc; ++c) Wout[c * tn + g] += l * qv[c];
+            }
+    }
+    return 0;
+}
+
+/* Per-point interpolated sums for a few listed rows, computing V only at the
+ * nodes those rows read: each node value is the full direct sum of Step 2
+ * over every node.  Needs the complete charge grids W (oracle_interp_spread).
+ * Outputs phi [nrows][s+2] in the potential order of oracle_interp_rep. */
+int oracle_interp_rows(int64_t n, int s, const double* Y, const double* origin,
+                       double w, int n_int, int p, int form, int kind,
+                       const double* W, const int64_t* rows, int64_t nrows,
+                       double* phi)
+{
+    (void)n;
+    if (s < 1 || s > 2 || p < 1 || n_int < 1) return -1;
+    int ng = n_int * p;
+    int64_t tn = (s == 1) ? ng : (int64_t)ng * ng;
+    int np = s + 2;
+    double h = w / p;
+    int pk[5], pc[5];
+    if (form == ORACLE_FORM_A) { pk[0] = 1; pc[0] = 0; }
+    else                       { pk[0] = 2; pc[0] = s + 1; }
+    pk[1] = 2; pc[1] = 0;
+    for (int d = 0; d < s; ++d) { pk[2 + d] = 2; pc[2 + d] = 1 + d; }
+    /* kernel values by lag (|dg0|, |dg1|), as in oracle_grid_conv */
+    double* T = (double*)malloc((size_t)2 * tn * sizeof(double));
+    for (int64_t a = 0; a < tn; ++a) {
+        double dx = (double)(a % ng), dy = (s == 1) ? 0.0 : (double)(a / ng);
+        double r2 = h * h * (dx * dx + dy * dy);
+        T[a] = kern1(kind, r2);
+        T[tn + a] = kern2(kind, r2);
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < nrows; ++r) {
+        int64_t i = rows[r];
+        int c0 = 0, c1 = 0;
+        double t0, t1 = 0.0, L0[16], L1[16];
+        locate(Y[i * s], origin[0], w, n_int, &c0, &t0);
+        oracle_lagrange(p, t0, L0);
+        if (s == 2) {
+            locate(Y[i * s + 1], origin[1], w, n_int, &c1, &t1);
+            oracle_lagrange(p, t1, L1);
+        } else {
+            L1[0] = 1.0;
+        }
+        int p1 = (s == 2) ? p : 1;
+        for (int k = 0; k < np; ++k) {
+            double acc = 0.0;
+            for (int m1 = 0; m1 < p1; ++m1)
+                for (int m0 = 0; m0 < p; ++m0) {
+                    int g0 = c0 * p + m0, g1 = (s == 2) ? c1 * p + m1 : 0;
+                    /* node value by the direct sum over all nodes */
+                    const double* Tk = T + (pk[k] == 1 ? 0 : tn);
+                    const double* Wc = W + (int64_t)pc[k] * tn;
+                    double v = 0.0;
+                    for (int q1 = 0; q1 < ((s == 2) ? ng : 1); ++q1) {
+                        const double* Trow = Tk + (int64_t)abs(g1 - q1) * ng;
+                        const double* Wrow = Wc + (int64_t)q1 * ng;
+                        for (int q0 = 0; q0 < ng; ++q0) v += Trow[abs(g0 - q0)] * Wrow[q0];
+                    }
+                    acc += L0[m0] * L1[m1] * v;
+                }
+            phi[r * np + k] = acc;
+        }
+    }
+    free(T);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* (3) Gradient-descent update                                               */
+/* ------------------------------------------------------------------------ */
+
+/* One step for every component y_i(d):
+ *   grad = 4 (alpha F_attr - F_rep)                 (Section 1.1, Section 1.2)
+ *   gain = (grad > 0) != (uY > 0) ? gain + gain_inc : gain * gain_dec,
+ *          then max(gain, gain_min)
+ *   uY   = mom uY - eta gain grad
+ *   Y    = (Y - mean(Y)) + uY   if recentre, else Y + uY
+ * The paper does not state the step rule; this is the momentum and
+ * per-component-gain descent of the t-SNE implementations it builds on, and
+ * its constants come from the caller (parity of the rule itself is unpinned
+ * by the paper).  mean(Y) is taken over the Y passed in. */
+void oracle_update(int64_t n, int s, double* Y, double* uY, double* gains,
+                   const double* Fattr, const double* Frep, double alpha,
+                   double mom, double eta, double gain_inc, double gain_dec,
+                   double gain_min, int recentre)
+{
+    double mean[3] = {0.0, 0.0, 0.0};
+    if (recentre) {
+        for (int64_t i = 0; i < n; ++i)
+            for (int d = 0; d < s; ++d) mean[d] += Y[i * s + d];
+        for (int d = 0; d < s; ++d) mean[d] /= (double)n;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int d = 0; d < s; ++d) {
+            int64_t k = i * s + d;
+            double g = 4.0 * (alpha * Fattr[k] - Frep[k]);
+            double gn = ((g > 0.0) != (uY[k] > 0.0)) ? gains[k] + gain_inc
+                                                      : gains[k] * gain_dec;
+            if (gn < gain_min) gn = gain_min;
+            gains[k] = gn;
+            uY[k] = mom * uY[k] - eta * gn * g;
+            Y[k] = (Y[k] - mean[d]) + uY[k];
+        }
+}

@@ -1,0 +1,191 @@
+"""Seeded synthetic inputs for the t-SNE gradient path.
+
+This module builds *inputs only*: embeddings Y, the sparse joint-probability
+matrix P in CSR form, and high-dimensional point clouds for the perplexity
+workloads.  It holds none of the gradient arithmetic (no kernels, no
+interpolation, no forces), so both the GPU library's tests and the CPU oracle
+can be fed from it without sharing any of the method's code.
+
+Every generator uses ``numpy.random.default_rng(seed)`` (PCG64).  Mixture
+components are equiprobable: each point's label is drawn uniformly, then the
+point is drawn from N(centre, sd^2 I).
+
+The paper measures on datasets that are not available here (Infinite MNIST,
+retinal and brain single-cell data, Section 2.5 and Section 5); the Gaussian
+mixtures below stand in for them at the paper's scale of one million points.
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+
+__all__ = [
+    "CSR", "mixture_embedding", "random_graph_P", "mixture_highdim",
+    "perplexity_P", "config_inputs",
+]
+
+
+@dataclasses.dataclass
+class CSR:
+    """Sparse symmetric P: ``row_ptr`` int64 [N+1], ``col`` int32 [nnz]
+    (sorted within each row), ``val`` float32 [nnz]; sum(val) == 1."""
+    row_ptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return int(self.row_ptr.shape[0] - 1)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.shape[0])
+
+
+def mixture_embedding(n: int, s: int, n_clusters: int, lo: float, hi: float,
+                      sd: float, seed: int, dtype=np.float32) -> np.ndarray:
+    """Y [n, s]: ``n_clusters`` isotropic Gaussians with centres uniform in
+    [lo, hi]^s and standard deviation ``sd``.  Row-major, C-contiguous."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(lo, hi, size=(n_clusters, s))
+    labels = rng.integers(0, n_clusters, size=n)
+    y = centres[labels] + sd * rng.standard_normal(size=(n, s))
+    return np.ascontiguousarray(y.astype(dtype))
+
+
+def _csr_from_edges(n: int, r: np.ndarray, c: np.ndarray, w: np.ndarray) -> CSR:
+    import scipy.sparse as sp
+    a = sp.csr_matrix((w, (r, c)), shape=(n, n))   # sums repeated (r, c)
+    a = (a + a.T).tocsr()
+    a.sum_duplicates()
+    a.sort_indices()
+    total = float(a.data.sum())
+    val = (a.data / total).astype(np.float32)
+    return CSR(row_ptr=a.indptr.astype(np.int64),
+               col=a.indices.astype(np.int32), val=val)
+
+
+def random_graph_P(n: int, k: int, seed: int) -> CSR:
+    """Symmetric P from a random k-neighbour graph.
+
+    Each row draws k/2 out-neighbours j != i uniformly (a repeated draw merges
+    with the earlier one), each directed edge gets weight exp(-u) with
+    u ~ U(0, 5), then W + W^T is normalised to sum 1.  The average row degree
+    is about k, which gives ~9e7 non-zeros at n = 1e6, k = 90."""
+    if n < 2:
+        raise ValueError("random_graph_P needs n >= 2")
+    half = max(1, k // 2)
+    rng = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(n, dtype=np.int64), half)
+    cols = rng.integers(0, n - 1, size=n * half, dtype=np.int64)
+    cols += cols >= rows                      # skip the diagonal
+    w = np.exp(-rng.uniform(0.0, 5.0, size=n * half))
+    return _csr_from_edges(n, rows, cols, w)
+
+
+def mixture_highdim(n: int, d: int, n_clusters: int, centre_sd: float,
+                    seed: int) -> np.ndarray:
+    """X [n, d] float32: unit-variance clusters with centres ~ N(0, centre_sd^2 I)."""
+    rng = np.random.default_rng(seed)
+    centres = centre_sd * rng.standard_normal(size=(n_clusters, d))
+    labels = rng.integers(0, n_clusters, size=n)
+    x = centres[labels] + rng.standard_normal(size=(n, d))
+    return np.ascontiguousarray(x.astype(np.float32))
+
+
+def _knn(x: np.ndarray, k: int, chunk: int = 1024, device=None):
+    """Exact k nearest neighbours (excluding self) by brute force.
+    Returns (idx int64 [n,k], sqdist float64 [n,k]).  With ``device`` set to a
+    torch device the distance blocks are formed there (input tooling only)."""
+    n = x.shape[0]
+    if device is not None:
+        import torch
+        xt = torch.as_tensor(x, device=device, dtype=torch.float32)
+        sq = (xt * xt).sum(1)
+        idx_out = np.empty((n, k), np.int64)
+        d_out = np.empty((n, k), np.float64)
+        for a in range(0, n, chunk):
+            b = min(n, a + chunk)
+            d2 = sq[a:b, None] + sq[None, :] - 2.0 * (xt[a:b] @ xt.T)
+            d2[torch.arange(b - a, device=device), torch.arange(a, b, device=device)] = float("inf")
+            vals, ids = torch.topk(d2, k, dim=1, largest=False, sorted=True)
+            idx_out[a:b] = ids.cpu().numpy()
+            d_out[a:b] = vals.clamp_min(0).double().cpu().numpy()
+        return idx_out, d_out
+    xd = x.astype(np.float64)
+    sq = (xd * xd).sum(1)
+    idx_out = np.empty((n, k), np.int64)
+    d_out = np.empty((n, k), np.float64)
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        d2 = sq[a:b, None] + sq[None, :] - 2.0 * (xd[a:b] @ xd.T)
+        d2[np.arange(b - a), np.arange(a, b)] = np.inf
+        part = np.argpartition(d2, k, axis=1)[:, :k]
+        pd = np.take_along_axis(d2, part, 1)
+        order = np.argsort(pd, axis=1, kind="stable")
+        idx_out[a:b] = np.take_along_axis(part, order, 1)
+        d_out[a:b] = np.maximum(np.take_along_axis(pd, order, 1), 0.0)
+    return idx_out, d_out
+
+
+def perplexity_P(x: np.ndarray, k: int = 90, perplexity: float = 30.0,
+                 device=None) -> CSR:
+    """Input affinities from exact k-NN: per row a Gaussian bandwidth found by
+    bisection so that exp(entropy) of the conditional row equals
+    ``perplexity`` (Section 1.1), normalised over the k neighbours; then
+    p_ij = (p_{j|i} + p_{i|j}) / (2N).  This is input construction: the
+    gradient path takes P as given."""
+    n = x.shape[0]
+    idx, d2 = _knn(x, k, device=device)
+    target = np.log(perplexity)
+    beta = np.ones(n)
+    lo = np.full(n, -np.inf)
+    hi = np.full(n, np.inf)
+    d2s = d2 - d2[:, :1]                       # shift for stability
+    for _ in range(200):
+        e = np.exp(-d2s * beta[:, None])
+        z = e.sum(1)
+        h = np.log(z) + beta * (d2s * e).sum(1) / z
+        diff = h - target
+        if np.all(np.abs(diff) < 1e-10):
+            break
+        up = diff > 0                          # entropy too high -> raise beta
+        lo = np.where(up, beta, lo)
+        hi = np.where(up, hi, beta)
+        beta = np.where(up, np.where(np.isinf(hi), beta * 2, (beta + hi) / 2),
+                        np.where(np.isinf(lo), beta / 2, (beta + lo) / 2))
+    e = np.exp(-d2s * beta[:, None])
+    pc = e / e.sum(1, keepdims=True)
+    rows = np.repeat(np.arange(n, dtype=np.int64), k)
+    return _csr_from_edges(n, rows, idx.ravel(), pc.ravel())
+
+
+def config_inputs(name: str, small: bool = False, device=None):
+    """Inputs of the named workload.  Returns a dict with ``Y`` (float32
+    [N, s]), ``P`` (CSR) and workload metadata.
+
+    c1: N=2048 2-D check; c3: N=1e6 2-D; c4: N=1e6 1-D; c2: N=1e5 2-D full run
+    from a 50-d mixture.  ``small`` shrinks c2/c3/c4 for CPU tests while
+    keeping their structure."""
+    if name == "c1":
+        y = mixture_embedding(2048, 2, 10, -30.0, 30.0, 2.0, seed=0)
+        return dict(Y=y, P=random_graph_P(2048, 90, seed=1), s=2,
+                    policy="paper", min_intervals=50)
+    if name == "c3":
+        n = 20_000 if small else 1_000_000
+        y = mixture_embedding(n, 2, 50, -95.0, 95.0, 2.0, seed=0)
+        return dict(Y=y, P=random_graph_P(n, 90, seed=1), s=2,
+                    policy="fixed", min_intervals=1)
+    if name == "c4":
+        n = 20_000 if small else 1_000_000
+        y = mixture_embedding(n, 1, 30, -195.0, 195.0, 1.5, seed=0)
+        return dict(Y=y, P=random_graph_P(n, 90, seed=1), s=1,
+                    policy="fixed", min_intervals=1)
+    if name == "c2":
+        n = 5_000 if small else 100_000
+        x = mixture_highdim(n, 50, 20, 5.0, seed=0)
+        rng = np.random.default_rng(2)
+        y = np.ascontiguousarray((1e-2 * rng.standard_normal((n, 2))).astype(np.float32))
+        return dict(Y=y, P=perplexity_P(x, 90, 30.0, device=device), s=2,
+                    policy="paper", min_intervals=50)
+    raise KeyError(name)

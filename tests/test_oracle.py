@@ -1,0 +1,400 @@
+"""Pins for the CPU oracle: closed forms, hand-computed values, brute force on
+tiny inputs, special cases that reduce to textbook routines, and invariants.
+
+Each test names the passage of the paper (Linderman et al., arXiv 1712.09005)
+that fixes the value it checks.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1712_09005_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+# --------------------------------------------------------------------------
+# Direct sums (Section 1.1, eq. (frep), Section 3)
+# --------------------------------------------------------------------------
+
+def test_direct_two_points_closed_form():
+    """N = 2: Z = 2/(1+r^2), F_rep,1 = (y1-y2)/(2(1+r^2)) (Z cancels one
+    factor of K1), F_attr,1 = p12 (y1-y2)/(1+r^2) with p12 = 1/2."""
+    y1, y2 = np.array([0.3, -1.2]), np.array([2.1, 0.4])
+    Y = np.stack([y1, y2])
+    r2 = float(((y1 - y2) ** 2).sum())
+    F, Z = oracle.direct_rep(Y)
+    assert Z == pytest.approx(2.0 / (1.0 + r2), rel=1e-15)
+    np.testing.assert_allclose(F[0], (y1 - y2) / (2.0 * (1.0 + r2)), rtol=1e-14)
+    np.testing.assert_allclose(F[1], (y2 - y1) / (2.0 * (1.0 + r2)), rtol=1e-14)
+    P = inputs.CSR(np.array([0, 1, 2]), np.array([1, 0], np.int32), np.array([0.5, 0.5]))
+    Fa = oracle.attr(Y, P)
+    np.testing.assert_allclose(Fa[0], 0.5 * (y1 - y2) / (1.0 + r2), rtol=1e-14)
+
+
+def test_direct_three_points_hand_computed():
+    g = _golden("three_points_1d.json")
+    Y = np.array(g["Y"])[:, None]
+    F, Z = oracle.direct_rep(Y)
+    assert Z == pytest.approx(g["Z"], rel=1e-15)
+    np.testing.assert_allclose(F[:, 0], g["F_rep"], rtol=1e-14)
+    h1, num = oracle.direct_sums(Y)
+    np.testing.assert_allclose(h1, g["h1"], rtol=1e-14)
+    np.testing.assert_allclose(num[:, 0], g["num"], rtol=1e-14)
+    P = inputs.CSR(np.array(g["P_row_ptr"]), np.array(g["P_col"], np.int32), np.array(g["P_val"]))
+    np.testing.assert_allclose(oracle.attr(Y, P)[:, 0], g["F_attr"], rtol=1e-14, atol=1e-16)
+
+
+def test_direct_rows_subset_matches_full():
+    Y = inputs.mixture_embedding(300, 2, 4, -5, 5, 1.0, seed=3).astype(np.float64)
+    h1, num = oracle.direct_sums(Y)
+    rows = np.array([0, 17, 299, 5])
+    h1r, numr = oracle.direct_sums(Y, rows)
+    np.testing.assert_array_equal(h1r, h1[rows])
+    np.testing.assert_array_equal(numr, num[rows])
+
+
+@pytest.fixture(scope="module")
+def cloud():
+    Y = inputs.mixture_embedding(400, 2, 5, -8, 8, 1.5, seed=11).astype(np.float64)
+    P = inputs.random_graph_P(400, 20, seed=12)
+    return Y, P
+
+
+def test_direct_invariants(cloud):
+    """Antisymmetry (forces sum to zero), translation invariance, rotation and
+    reflection equivariance, permutation equivariance."""
+    Y, P = cloud
+    F, Z = oracle.direct_rep(Y)
+    scale = np.abs(F).sum()
+    assert np.abs(F.sum(0)).max() < 1e-13 * scale
+    Fa = oracle.attr(Y, P)
+    assert np.abs(Fa.sum(0)).max() < 1e-12 * np.abs(Fa).sum()
+    # translation
+    F2, Z2 = oracle.direct_rep(Y + np.array([17.3, -4.25]))
+    assert Z2 == pytest.approx(Z, rel=1e-12)
+    np.testing.assert_allclose(F2, F, rtol=1e-9, atol=1e-12 * np.abs(F).max())
+    # rotation and reflection
+    th = 0.7
+    R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]]) @ np.diag([1.0, -1.0])
+    F3, Z3 = oracle.direct_rep(Y @ R.T)
+    assert Z3 == pytest.approx(Z, rel=1e-12)
+    np.testing.assert_allclose(F3, F @ R.T, atol=1e-10 * np.abs(F).max())
+    Fa3 = oracle.attr(Y @ R.T, P)
+    np.testing.assert_allclose(Fa3, Fa @ R.T, atol=1e-10 * np.abs(Fa).max())
+    # permutation
+    perm = np.random.default_rng(0).permutation(Y.shape[0])
+    F4, _ = oracle.direct_rep(Y[perm])
+    np.testing.assert_allclose(F4, F[perm], rtol=1e-10, atol=1e-13 * np.abs(F).max())
+
+
+# --------------------------------------------------------------------------
+# Geometry readings (square box of Section 2.4, interval count of Section 2.5)
+# --------------------------------------------------------------------------
+
+def test_geometry_policies():
+    Y = np.array([[1.0, -2.0], [38.2, 3.0], [5.0, 10.0]])        # width 37.2 in x
+    o, w, m = oracle.geometry(Y, "paper", 50)
+    np.testing.assert_array_equal(o, [1.0, -2.0])
+    assert m == 50 and w == pytest.approx(37.2 / 50, rel=1e-15)
+    o, w, m = oracle.geometry(Y, "paper", 20)
+    assert m == 38 and w == pytest.approx(37.2 / 38, rel=1e-15)
+    o, w, m = oracle.geometry(Y, "fixed", 1, 0.75)
+    assert m == 50 and w == 0.75                               # ceil(49.6)
+    Yc = np.zeros((5, 2))                                      # coincident points
+    o, w, m = oracle.geometry(Yc, "paper", 50)
+    assert m == 50 and w == pytest.approx(1e-6 / 50)
+
+
+# --------------------------------------------------------------------------
+# Lagrange basis (Section 2.1) on the nodes of eq. (equinodes)
+# --------------------------------------------------------------------------
+
+def test_lagrange_hand_values():
+    g = _golden("lagrange_p3.json")
+    for t, L in zip(g["t"], g["L"]):
+        np.testing.assert_allclose(oracle.lagrange(3, t), L, atol=1e-15)
+
+
+@pytest.mark.parametrize("p", [2, 3, 4, 5, 6])
+def test_lagrange_identities(p):
+    """Partition of unity and exact reproduction of t^k, k < p; L_m(tau_k) = delta."""
+    tau = (np.arange(p) + 0.5) / p
+    for t in np.linspace(-0.1, 1.1, 13):
+        L = oracle.lagrange(p, t)
+        for k in range(p):
+            assert (L * tau ** k).sum() == pytest.approx(t ** k, abs=1e-12)
+    for k in range(p):
+        np.testing.assert_allclose(oracle.lagrange(p, tau[k]), np.eye(p)[k], atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# Step 2 directly (eq. (equikereval2)) vs the circulant-embedded FFT
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("s,ng", [(1, 37), (2, 12), (2, 9)])
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_grid_conv_vs_numpy_fft(s, ng, kernel):
+    """The Toeplitz (block-Toeplitz) product equals the circulant convolution
+    of size 2ng computed with numpy's FFT (Section 2.2, Section 2.4)."""
+    rng = np.random.default_rng(s * 100 + ng)
+    h = 0.37
+    W = rng.standard_normal((ng,) * s)
+    V = oracle.grid_conv(W, h, kernel)
+    M = 2 * ng
+    j = np.arange(M)
+    j = np.minimum(j, M - j).astype(float)
+    r2 = h * h * (j ** 2 if s == 1 else j[:, None] ** 2 + j[None, :] ** 2)
+    K = 1.0 / (1.0 + r2)
+    if kernel == 2:
+        K = K * K
+    ax = tuple(range(s))
+    Vf = np.real(np.fft.ifftn(np.fft.fftn(W, (M,) * s, axes=ax) * np.fft.fftn(K, axes=ax), axes=ax))
+    Vf = Vf[tuple(slice(0, ng) for _ in range(s))]
+    np.testing.assert_allclose(V, Vf, atol=1e-12 * np.abs(Vf).max())
+
+
+# --------------------------------------------------------------------------
+# Interpolation scheme (Sections 2.1-2.4, Appendix)
+# --------------------------------------------------------------------------
+
+def _vander_lagrange(p, t):
+    """Lagrange weights by solving the Vandermonde system sum_m L_m tau_m^k = t^k
+    (an independent route to the same basis)."""
+    tau = (np.arange(p) + 0.5) / p
+    A = np.vander(tau, p, increasing=True).T
+    return np.linalg.solve(A, np.array([t ** k for k in range(p)]))
+
+
+def _brute_phi(Y, o, w, nint, p, kind_fn):
+    """phi~(y_i) = sum_j K_p(y_i, y_j) q_j with K_p the piecewise tensor-product
+    interpolant of Section 2.1/2.4, built pair by pair."""
+    n, s = Y.shape
+    h = w / p
+    cells = np.clip(np.floor((Y - o) / w), 0, nint - 1).astype(int)
+    t = (Y - o) / w - cells
+    Ls = [[_vander_lagrange(p, t[i, d]) for d in range(s)] for i in range(n)]
+    node = [[o[d] + (cells[i, d] * p + np.arange(p) + 0.5) * h for d in range(s)] for i in range(n)]
+
+    def kp(i, j, K):
+        if s == 1:
+            dy = node[i][0][:, None] - node[j][0][None, :]
+            return Ls[i][0] @ K(dy ** 2) @ Ls[j][0]
+        a = node[i][0][:, None, None, None] - node[j][0][None, None, :, None]
+        b = node[i][1][None, :, None, None] - node[j][1][None, None, None, :]
+        T = K(a ** 2 + b ** 2)       # [m0, m1, l0, l1]
+        return np.einsum("abcd,a,b,c,d->", T, Ls[i][0], Ls[i][1], Ls[j][0], Ls[j][1])
+    K1, K2 = kind_fn
+    Kp1 = np.array([[kp(i, j, K1) for j in range(n)] for i in range(n)])
+    Kp2 = np.array([[kp(i, j, K2) for j in range(n)] for i in range(n)])
+    return Kp1, Kp2
+
+
+TSNE = (lambda r2: 1.0 / (1.0 + r2), lambda r2: 1.0 / (1.0 + r2) ** 2)
+
+
+@pytest.mark.parametrize("s,nint,p", [(1, 5, 3), (2, 3, 3), (2, 2, 4)])
+def test_interp_matches_pairwise_interpolant(s, nint, p):
+    """The three-step grid algorithm equals the pairwise sum with the
+    interpolated kernel K_p (the rewrite of Section 2.1 applied interval by
+    interval, Section 2.2), brute force on a tiny input; also the per-point
+    bound |phi~ - phi| <= eps sum|q| of Section 2.1, with eps the largest
+    |K_p - K| over the pairs that occur."""
+    rng = np.random.default_rng(7 + s)
+    n = 40 if s == 1 else 25
+    Y = rng.uniform(-2.0, -2.0 + 0.9 * nint, size=(n, s))
+    o, w, m = oracle.geometry(Y, "paper", nint)
+    assert m == nint
+    r = oracle.interp_rep(Y, o, w, m, p, oracle.FORM_A)
+    Kp1, Kp2 = _brute_phi(Y, o, w, m, p, TSNE)
+    yc = Y - oracle.centre(o, w, m)
+    phi_b = np.column_stack([Kp1.sum(1), Kp2.sum(1)] + [Kp2 @ yc[:, d] for d in range(s)])
+    np.testing.assert_allclose(r["phi"], phi_b, rtol=1e-11, atol=1e-12)
+    # error bound per point, exact phi includes the self pair like phi~
+    d2 = ((Y[:, None, :] - Y[None, :, :]) ** 2).sum(-1)
+    for k, (Kp, K, q) in enumerate([(Kp1, TSNE[0], np.ones(n)), (Kp2, TSNE[1], np.ones(n))]
+                                   + [(Kp2, TSNE[1], yc[:, d]) for d in range(s)]):
+        exact = K(d2) @ q
+        eps = np.abs(Kp - K(d2)).max(1)
+        assert np.all(np.abs(r["phi"][:, k] - exact) <= eps * np.abs(q).sum() * (1 + 1e-9) + 1e-13)
+
+
+@pytest.mark.parametrize("s", [1, 2])
+def test_interp_single_interval_is_textbook_lagrange(s):
+    """N_int = 1 is the single-interval three-step scheme of Section 2.1: with
+    scipy's Lagrange polynomial through the p nodes, phi~ must agree."""
+    from scipy.interpolate import lagrange as sp_lagrange
+    rng = np.random.default_rng(21)
+    n, p = 30, 4
+    Y = rng.uniform(0.0, 0.9, size=(n, s))
+    o, w, m = oracle.geometry(Y, "paper", 1)
+    assert m == 1
+    r = oracle.interp_rep(Y, o, w, 1, p, oracle.FORM_A)
+    nodes = [o[d] + (np.arange(p) + 0.5) * w / p for d in range(s)]
+    # basis polynomials L_m(y) as scipy polynomials in y
+    basis = [[sp_lagrange(nodes[d], np.eye(p)[mm]) for mm in range(p)] for d in range(s)]
+    Lval = np.array([[[basis[d][mm](Y[i, d]) for mm in range(p)] for d in range(s)] for i in range(n)])
+    if s == 1:
+        nk = nodes[0]
+        K = 1.0 / (1.0 + (nk[:, None] - nk[None, :]) ** 2)
+        wgt = Lval[:, 0, :]                               # [n, p]
+        phi = wgt @ K @ wgt.sum(0)
+    else:
+        gx, gy = np.meshgrid(nodes[0], nodes[1], indexing="ij")
+        pts = np.stack([gx.ravel(), gy.ravel()], 1)
+        K = 1.0 / (1.0 + ((pts[:, None, :] - pts[None, :, :]) ** 2).sum(-1))
+        wgt = np.einsum("ia,ib->iab", Lval[:, 0, :], Lval[:, 1, :]).reshape(n, -1)
+        phi = wgt @ K @ wgt.sum(0)
+    np.testing.assert_allclose(r["phi"][:, 0], phi, rtol=1e-10)
+
+
+@pytest.mark.parametrize("s", [1, 2])
+@pytest.mark.parametrize("form,p", [(oracle.FORM_B, 3), (oracle.FORM_A, 5), (oracle.FORM_B, 4)])
+def test_interp_exact_for_polynomial_kernels(s, form, p):
+    """With kernels polynomial of degree < p in each coordinate the
+    interpolant is the kernel itself (Section 2.1), so Z and F_rep equal the
+    direct sums to rounding.  Form B needs only K2 (degree 2, p >= 3); form A
+    also interpolates K1 = (1 + r^2) K2 (degree 4, p >= 5)."""
+    rng = np.random.default_rng(5 + s + p)
+    n = 300 if s == 1 else 150
+    Y = rng.uniform(-3.0, 4.0, size=(n, s))
+    o, w, m = oracle.geometry(Y, "paper", 7)
+    r = oracle.interp_rep(Y, o, w, m, p, form, oracle.KERNEL_POLY)
+    F, Z = oracle.direct_rep(Y, oracle.KERNEL_POLY)
+    assert r["Z"] == pytest.approx(Z, rel=1e-11)
+    assert _rel(r["F"], F) < 1e-10
+
+
+def test_interp_not_exact_for_polynomial_form_a_p3():
+    """Counter-check of the previous test: form A with p = 3 cannot reproduce
+    the degree-4 K1, so the same comparison must fail."""
+    rng = np.random.default_rng(9)
+    Y = rng.uniform(-3.0, 4.0, size=(150, 2))
+    o, w, m = oracle.geometry(Y, "paper", 7)
+    r = oracle.interp_rep(Y, o, w, m, 3, oracle.FORM_A, oracle.KERNEL_POLY)
+    _, Z = oracle.direct_rep(Y, oracle.KERNEL_POLY)
+    assert abs(r["Z"] - Z) / Z > 1e-8
+
+
+def test_interp_third_order_convergence():
+    """Halving the interval width cuts the error by ~2^p = 8 for p = 3
+    (the interpolation error of Section 2.1 for a smooth kernel)."""
+    Y = inputs.mixture_embedding(500, 1, 4, -20, 20, 2.0, seed=4).astype(np.float64)
+    F, Z = oracle.direct_rep(Y)
+    errs = []
+    for w in (1.0, 0.5, 0.25):
+        o, ww, m = oracle.geometry(Y, "fixed", 1, w)
+        r = oracle.interp_rep(Y, o, ww, m, 3)
+        errs.append(_rel(r["F"], F))
+    for a, b in zip(errs, errs[1:]):
+        assert 5.0 < a / b < 14.0, errs
+
+
+def test_interp_forms_agree_and_sum_to_zero(cloud):
+    """Forms A and B approximate the same forces; the interpolated kernel is
+    symmetric (same nodes for sources and targets), so forces still sum to zero."""
+    Y, _ = cloud
+    o, w, m = oracle.geometry(Y, "paper", 20)
+    ra = oracle.interp_rep(Y, o, w, m, 3, oracle.FORM_A)
+    rb = oracle.interp_rep(Y, o, w, m, 3, oracle.FORM_B)
+    F, Z = oracle.direct_rep(Y)
+    assert _rel(ra["F"], F) < 5e-2 and _rel(rb["F"], F) < 5e-2
+    assert abs(ra["Z"] - Z) / Z < 5e-3
+    for r in (ra, rb):
+        assert np.abs(r["F"].sum(0)).max() < 1e-10 * np.abs(r["F"]).sum()
+
+
+def test_interp_translation_invariance(cloud):
+    Y, _ = cloud
+    o, w, m = oracle.geometry(Y, "paper", 20)
+    r = oracle.interp_rep(Y, o, w, m, 3)
+    d = np.array([1024.0, -256.0])                       # exact in binary
+    o2, w2, m2 = oracle.geometry(Y + d, "paper", 20)
+    assert m2 == m and w2 == w
+    r2 = oracle.interp_rep(Y + d, o2, w2, m2, 3)
+    assert r2["Z"] == pytest.approx(r["Z"], rel=1e-12)
+    np.testing.assert_allclose(r2["F"], r["F"], atol=1e-9 * np.abs(r["F"]).max())
+
+
+def test_interp_coincident_points():
+    Y = np.full((50, 2), 3.25)
+    o, w, m = oracle.geometry(Y, "paper", 50)
+    r = oracle.interp_rep(Y, o, w, m, 3)
+    assert np.abs(r["F"]).max() < 1e-12
+    assert r["Z"] == pytest.approx(50 * 49, rel=1e-3)
+
+
+def test_interp_rows_matches_full():
+    Y = inputs.mixture_embedding(300, 2, 3, -6, 6, 1.0, seed=8).astype(np.float64)
+    o, w, m = oracle.geometry(Y, "fixed", 1, 0.75)
+    for form in (oracle.FORM_A, oracle.FORM_B):
+        r = oracle.interp_rep(Y, o, w, m, 5, form, want_grids=True)
+        W = oracle.interp_spread(Y, o, w, m, 5, form)
+        np.testing.assert_allclose(W, r["W"].reshape(W.shape), rtol=0, atol=1e-12)
+        rows = np.array([3, 100, 299])
+        phi = oracle.interp_rows(Y, o, w, m, rows, W, 5, form)
+        np.testing.assert_allclose(phi, r["phi"][rows], rtol=1e-11, atol=1e-11)
+        h1, num = oracle.assemble_rows(Y[rows], o, w, m, phi, form)
+        np.testing.assert_allclose(num / r["Z"], r["F"][rows], rtol=1e-10, atol=1e-13)
+        np.testing.assert_allclose(h1, r["h1"][rows], rtol=1e-11)
+
+
+# --------------------------------------------------------------------------
+# Update (gradient of Section 1.1 with exaggeration, Section 1.2 / Section 4)
+# --------------------------------------------------------------------------
+
+def test_update_hand_computed_step():
+    g = _golden("update_step.json")
+    a = lambda k: np.array(g[k])[:, None]
+    Y, uY, gains = oracle.update(a("Y"), a("uY"), a("gains"), a("F_attr"), a("F_rep"),
+                                 **g["params"])
+    np.testing.assert_allclose(Y[:, 0], g["Y_new"], rtol=1e-14)
+    np.testing.assert_allclose(uY[:, 0], g["uY_new"], rtol=1e-14)
+    np.testing.assert_allclose(gains[:, 0], g["gains_new"], rtol=1e-14)
+
+
+def test_schedule_phases():
+    assert oracle.schedule(0) == (12.0, 0.5)
+    assert oracle.schedule(249) == (12.0, 0.5)
+    assert oracle.schedule(250) == (1.0, 0.8)
+    assert oracle.schedule(600, ee_stop=0, le_alpha=4.0, le_start=500) == (4.0, 0.8)
+
+
+# --------------------------------------------------------------------------
+# Inputs (recipes of the workloads)
+# --------------------------------------------------------------------------
+
+def test_random_graph_P_structure():
+    P = inputs.random_graph_P(2000, 90, seed=1)
+    assert P.row_ptr[0] == 0 and P.row_ptr[-1] == P.nnz
+    assert abs(float(P.val.astype(np.float64).sum()) - 1.0) < 1e-5
+    deg = np.diff(P.row_ptr)
+    assert 85 < deg.mean() < 91
+    import scipy.sparse as sp
+    A = sp.csr_matrix((P.val, P.col, P.row_ptr), shape=(2000, 2000))
+    assert abs(A - A.T).max() == 0
+    assert A.diagonal().max() == 0
+    for i in range(0, 2000, 97):
+        c = P.col[P.row_ptr[i]:P.row_ptr[i + 1]]
+        assert np.all(np.diff(c) > 0)
+
+
+def test_perplexity_P_rows():
+    x = inputs.mixture_highdim(600, 10, 3, 5.0, seed=0)
+    P = inputs.perplexity_P(x, k=30, perplexity=10.0)
+    assert abs(float(P.val.astype(np.float64).sum()) - 1.0) < 1e-5
+    import scipy.sparse as sp
+    A = sp.csr_matrix((P.val, P.col, P.row_ptr), shape=(600, 600))
+    assert abs(A - A.T).max() < 1e-9
