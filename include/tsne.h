@@ -1,0 +1,234 @@
+/*
+ * tsne.h - C ABI of the MI355X (gfx950) t-SNE gradient library.
+ *
+ * One t-SNE gradient iteration as in Linderman et al., "Efficient Algorithms
+ * for t-distributed Stochastic Neighborhood Embedding" (FIt-SNE):
+ *   - repulsion by piecewise Lagrange interpolation of the Cauchy kernels on an
+ *     equispaced grid and a circulant-embedded FFT convolution (Section 2,
+ *     Algorithm 1, Section 2.4 for s = 2, the Appendix for the s+2 sums),
+ *   - attraction over a sparse symmetric P (Section 3),
+ *   - the gradient with early/late exaggeration (Section 1.1, Section 1.2,
+ *     Section 4) and a momentum/gain descent step.
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns tsne_status and never throws.  Argument errors are
+ *     detected on the host before anything is enqueued (TSNE_E_ARG,
+ *     TSNE_E_UNSUPPORTED, TSNE_E_WORKSPACE).  Conditions found on the device
+ *     (grid capacity exceeded, non-finite coordinates) are latched in a status
+ *     word of the plan; the iteration that meets them is not committed (Y, uY,
+ *     gains and outputs are left as they were) and every later call on the
+ *     plan is a no-op until tsne_query reports and clears them.
+ *   - Pointers are DEVICE pointers unless marked "host".  They are owned by
+ *     the caller, borrowed for the duration of the call (P: until rebound or
+ *     the plan is destroyed) and must stay valid until the enqueued work has
+ *     completed on the plan's stream.
+ *   - Y is [n, s] row-major: y_i(d) = Y[i*s + d].  Arrays of per-point
+ *     vectors (F_rep, F_attr, uY, gains) share that layout.  The element type
+ *     is float (TSNE_F32) or double (TSNE_F64) as set in the descriptor.
+ *   - F_rep follows the sign of the attractive/repulsive split of Section 1.1:
+ *     F_rep,i = sum_{j != i} (y_i - y_j) / (1 + |y_i - y_j|^2)^2 / Z, pointing
+ *     away from the other points; Z = sum_{k != l} 1/(1 + |y_k - y_l|^2).
+ *     F_attr,i = sum_j p_ij (y_i - y_j) / (1 + |y_i - y_j|^2) (Section 3).
+ *     The gradient is 4 (alpha F_attr - F_rep).
+ *   - The library allocates no device memory and creates no streams: the
+ *     caller provides a workspace and a stream (hipStream_t, or NULL for the
+ *     default stream).  All work is enqueued asynchronously on that stream;
+ *     only tsne_query and tsne_batch_poll synchronise.
+ *   - A plan is used by one host thread at a time; distinct plans are
+ *     independent.
+ */
+#ifndef TSNE_MI355X_H
+#define TSNE_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TSNE_OK = 0,
+    TSNE_E_ARG = 1,          /* invalid argument (host check) */
+    TSNE_E_UNSUPPORTED = 2,  /* valid but not built (e.g. p outside 2..6) */
+    TSNE_E_WORKSPACE = 3,    /* workspace missing, misaligned or too small */
+    TSNE_E_CAPACITY = 4,     /* the box needs more intervals than max_intervals */
+    TSNE_E_NONFINITE = 5,    /* a coordinate of Y is NaN or infinite */
+    TSNE_E_HIP = 6,          /* a HIP runtime call failed */
+    TSNE_E_STATE = 7         /* call not valid in the plan's state (e.g. no P bound) */
+} tsne_status;
+
+typedef enum { TSNE_F32 = 0, TSNE_F64 = 1 } tsne_dtype;
+
+/* Box / interval policy.  In both the box is square with side
+ * L = max_d (max_i y_i(d) - min_i y_i(d)) (Section 2.4), origin at the
+ * per-dimension minimum, and the nodes of interval l at
+ * origin + (l p + m + 1/2) w/p, m = 0..p-1 (eq. (equinodes) mapped onto the box).
+ *   TSNE_GRID_PAPER: N_int = max(min_intervals, ceil(L)), w = L / N_int
+ *                    (the interval count of the experiments of Section 2.5);
+ *   TSNE_GRID_FIXED: w = interval_width, N_int = max(min_intervals, ceil(L/w)).
+ * Under FIXED the node spacing never changes, so the kernel spectra are
+ * computed once per plan; under PAPER they are recomputed at every call. */
+typedef enum { TSNE_GRID_PAPER = 0, TSNE_GRID_FIXED = 1 } tsne_grid_policy;
+
+/* Which s+2 kernel sums are formed (Section 2 and the Appendix).
+ *   TSNE_FORM_A: K1 with charge 1; K2 with charges 1 and y(d) (the Appendix);
+ *   TSNE_FORM_B: K2 with charges 1, y(d) and |y|^2; the K1 sum follows from
+ *                K1 = (1 + r^2) K2.
+ * Charges are centred at the box centre. */
+typedef enum { TSNE_FORM_A = 0, TSNE_FORM_B = 1 } tsne_form;
+
+typedef struct {
+    int64_t n;               /* number of points, >= 2 (< 2^31) */
+    int32_t s;               /* embedding dimension: 1 or 2 */
+    int32_t dtype;           /* tsne_dtype of Y, forces, uY, gains, P values */
+    int32_t p;               /* Lagrange nodes per interval, 2..6 (Section 2.3) */
+    int32_t policy;          /* tsne_grid_policy */
+    int32_t form;            /* tsne_form */
+    int32_t min_intervals;   /* lower bound on N_int, >= 1 */
+    int32_t max_intervals;   /* capacity: the largest N_int the plan holds */
+    double interval_width;   /* w for TSNE_GRID_FIXED (> 0); ignored otherwise */
+    int64_t nnz;             /* non-zeros of P; 0 if attraction is not used */
+    int32_t lanes_per_row;   /* CSR lanes per row: 0 (auto), 16, 32 or 64 */
+    int32_t points_per_lane; /* spreading points per lane: 0 (auto), 4..32 */
+} tsne_desc;
+
+/* Descent schedule, indexed by the absolute iteration it:
+ *   alpha(it) = le_alpha if it >= le_start, else ee_alpha if it < ee_stop, else 1
+ *               (early exaggeration, Section 1.2; late exaggeration, Section 4);
+ *   mom(it)   = mom0 if it < mom_switch else mom1.
+ * Per component: grad = 4 (alpha F_attr - F_rep);
+ *   gain = ((grad > 0) != (uY > 0)) ? gain + gain_inc : gain * gain_dec,
+ *   gain = max(gain, gain_min); uY = mom uY - eta gain grad;
+ *   Y = (Y - mean(Y)) + uY if recentre, else Y + uY.
+ * The momentum/gain rule is not stated in the paper; it is the rule of the
+ * t-SNE implementations the paper builds on. */
+typedef struct {
+    double eta;
+    double mom0, mom1;
+    int32_t mom_switch;
+    double ee_alpha;
+    int32_t ee_stop;
+    double le_alpha;
+    int32_t le_start;
+    double gain_inc, gain_dec, gain_min;
+    int32_t recentre;
+} tsne_sched;
+
+/* Snapshot returned by tsne_query (host struct). */
+typedef struct {
+    int32_t status;          /* latched tsne_status of the device, then cleared */
+    int32_t n_int;           /* N_int of the last iteration */
+    int32_t n_nodes;         /* N_int * p */
+    int32_t fft_len;         /* circulant length M per dimension */
+    int32_t iter;            /* device iteration counter (next iteration to run) */
+    int32_t max_intervals;   /* capacity of the plan */
+    double origin[2];        /* box origin of the last iteration */
+    double w_int;            /* interval width of the last iteration */
+    double box_side;         /* L of the last iteration */
+    double Z;                /* normalisation of the last repulsion */
+} tsne_stats;
+
+typedef struct tsne_plan tsne_plan;
+
+/* Device workspace needed by a plan for this descriptor (bytes; 0 if the
+ * descriptor is invalid). */
+size_t tsne_workspace_bytes(const tsne_desc* desc);
+
+/* Create a plan over a caller-owned device workspace (256-byte aligned, at
+ * least tsne_workspace_bytes(desc) bytes) for the given stream.  Initialises
+ * the workspace (twiddle tables, counters, kernel spectra under FIXED) with
+ * work enqueued on the stream.  *out receives the plan (host object). */
+tsne_status tsne_plan_create(const tsne_desc* desc, void* workspace, size_t bytes,
+                             void* stream, tsne_plan** out);
+
+/* Release the host object.  The workspace belongs to the caller. */
+tsne_status tsne_plan_destroy(tsne_plan* plan);
+
+/* Bind the sparse symmetric P in CSR form (Section 3): row_ptr int64 [n+1]
+ * (row_ptr[0] = 0, row_ptr[n] = desc.nnz), col int32 [nnz], val [nnz] of the
+ * plan's dtype.  Preconditions (not checked on the device): symmetric, zero
+ * diagonal, sum of values 1, columns in [0, n). */
+tsne_status tsne_bind_P(tsne_plan* plan, const int64_t* row_ptr,
+                        const int32_t* col, const void* val);
+
+/* Repulsion (steps of Algorithm 1 / Section 2.4 with FFT convolution):
+ * writes F_rep [n, s] and *Z (device double). */
+tsne_status tsne_repulsive(tsne_plan* plan, const void* Y, void* F_rep, double* Z);
+
+/* Attraction over the bound P: writes F_attr [n, s]. */
+tsne_status tsne_attractive(tsne_plan* plan, const void* Y, void* F_attr);
+
+/* One full iteration at absolute iteration index iter (>= 0): repulsion,
+ * attraction and the descent step of tsne_sched, updating Y, uY and gains in
+ * place.  Sets the device iteration counter to iter + 1. */
+tsne_status tsne_step(tsne_plan* plan, void* Y, void* uY, void* gains,
+                      const tsne_sched* sched, int32_t iter);
+
+/* n_iter iterations starting at absolute iteration iter0 (the schedule is
+ * indexed by absolute iteration, so a run can be split and resumed).  The
+ * iteration is captured once in a HIP graph (device-side iteration counter and
+ * schedule) and replayed n_iter times. */
+tsne_status tsne_run(tsne_plan* plan, void* Y, void* uY, void* gains,
+                     const tsne_sched* sched, int32_t iter0, int32_t n_iter);
+
+/* Synchronise the plan's stream, fill *out (host) and clear the latched
+ * device status. */
+tsne_status tsne_query(tsne_plan* plan, tsne_stats* out);
+
+/* Copy an internal array of the last iteration to host memory (testing and
+ * inspection; synchronises).  what: 0 = charge grids W [C][n_cap][n_cap] (s=2)
+ * or [C][n_cap] (s=1), 1 = potential grids V [s+2][...] same layout,
+ * 2 = unnormalised repulsion numerators [n, s], 3 = cell start offsets
+ * [N_int^s + 1] (int32).  *bytes is the size copied (or needed if dst_host
+ * is NULL). */
+tsne_status tsne_debug_export(tsne_plan* plan, int32_t what, void* dst_host,
+                              size_t* bytes);
+
+const char* tsne_status_str(tsne_status status);
+
+/* ---------------------------------------------------------------------- */
+/* Batching: independent embeddings of uneven n sharing every launch.      */
+/* ---------------------------------------------------------------------- */
+
+/* A batch holds up to max_slots instances that have the same s, dtype, p and
+ * form.  Each admitted job has its own plan workspace (tsne_workspace_bytes of
+ * its descriptor) and its own n, nnz, capacity and grid; one tick runs one
+ * iteration of every live slot with a single launch per kernel, each launch
+ * covering every slot's work (per-slot grid sizes come from a device table). */
+typedef struct tsne_batch tsne_batch;
+
+/* Workspace for the batch's own tables (bytes). */
+size_t tsne_batch_workspace_bytes(int32_t max_slots);
+
+tsne_status tsne_batch_create(int32_t max_slots, int32_t s, int32_t dtype, int32_t p,
+                              int32_t form, void* workspace, size_t bytes,
+                              void* stream, tsne_batch** out);
+tsne_status tsne_batch_destroy(tsne_batch* batch);
+
+/* Admit a job into a free slot.  The job runs iterations [iter0, iter0+n_iter)
+ * of sched on Y, uY, gains with the bound CSR P.  plan_ws is the job's plan
+ * workspace.  *slot receives the slot index. */
+tsne_status tsne_batch_admit(tsne_batch* batch, const tsne_desc* desc, void* plan_ws,
+                             size_t plan_ws_bytes, void* Y, void* uY, void* gains,
+                             const int64_t* row_ptr, const int32_t* col, const void* val,
+                             const tsne_sched* sched, int32_t iter0, int32_t n_iter,
+                             int32_t* slot);
+
+/* Run n_ticks iterations of every live slot (a slot that has finished its
+ * n_iter iterations is skipped on the device).  Replays a captured graph of
+ * one tick when the set of slots is unchanged. */
+tsne_status tsne_batch_tick(tsne_batch* batch, int32_t n_ticks);
+
+/* Synchronise and report a slot: iterations done and latched status. */
+tsne_status tsne_batch_poll(tsne_batch* batch, int32_t slot, int32_t* iters_done,
+                            int32_t* status);
+
+/* Free a slot (its buffers belong to the caller). */
+tsne_status tsne_batch_retire(tsne_batch* batch, int32_t slot);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSNE_MI355X_H */

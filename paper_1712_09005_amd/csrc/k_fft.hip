@@ -1,0 +1,517 @@
+// Step 2 of Algorithm 1 on gfx950: the grid sums v = K~ w evaluated as a
+// circulant (block-circulant for s = 2) convolution by FFT (Section 2.2,
+// Section 2.4).  Hand-written mixed-radix (2, 3, 4, 5) Stockham transforms run
+// in LDS; each stage reads its butterflies into registers, synchronises and
+// writes them back, so one LDS buffer per transform suffices.
+//
+// 2-D layout and passes (M = circulant length per dimension, M even):
+//   rows:  two real node rows of one charge grid packed into one complex
+//          transform; the two half spectra are unpacked and stored in column
+//          tiles X[c][k0 / tw][row][k0 % tw] (tw complex = 128 bytes);
+//   cols:  for each potential, tiles of columns: forward transform, multiply
+//          by the (real, even) kernel spectrum, inverse transform, keep the n
+//          node rows;
+//   irows: two potentials packed per complex inverse transform, keep n nodes.
+// The kernel spectra are built in double by direct cosine sums (the circulant
+// of an even kernel has a real, even spectrum) and stored pre-scaled by 1/M^s.
+#include <math.h>
+
+#include "launch.h"
+
+namespace tsne {
+
+constexpr int kMaxB = 8;   // butterflies per thread per stage (host-enforced)
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b)
+{
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T> __device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T> __device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+// multiply by -i
+template <typename T> __device__ __forceinline__ cplx<T> mnegi(cplx<T> a) { return {a.y, -a.x}; }
+template <typename T> __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return {a.x * s, a.y * s}; }
+template <typename T> __device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return {a.x, -a.y}; }
+
+// Forward DFTs of length R (kernel exp(-2 pi i k n / R)).
+template <typename T, int R> struct Dft;
+
+template <typename T> struct Dft<T, 2> {
+    static __device__ __forceinline__ void run(cplx<T> (&v)[2])
+    {
+        const cplx<T> a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+
+template <typename T> struct Dft<T, 3> {
+    static __device__ __forceinline__ void run(cplx<T> (&v)[3])
+    {
+        const T s3 = (T)0.86602540378443864676;   // sin(2 pi / 3)
+        const cplx<T> t1 = cadd(v[1], v[2]);
+        const cplx<T> t2 = csub(v[0], cscale(t1, (T)0.5));
+        const cplx<T> t3 = cscale(csub(v[1], v[2]), s3);
+        v[0] = cadd(v[0], t1);
+        v[1] = cadd(t2, mnegi(t3));
+        v[2] = csub(t2, mnegi(t3));
+    }
+};
+
+template <typename T> struct Dft<T, 4> {
+    static __device__ __forceinline__ void run(cplx<T> (&v)[4])
+    {
+        const cplx<T> a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+        const cplx<T> c = cadd(v[1], v[3]), d = mnegi(csub(v[1], v[3]));
+        v[0] = cadd(a, c);
+        v[2] = csub(a, c);
+        v[1] = cadd(b, d);
+        v[3] = csub(b, d);
+    }
+};
+
+template <typename T> struct Dft<T, 5> {
+    static __device__ __forceinline__ void run(cplx<T> (&v)[5])
+    {
+        const T c1 = (T)0.30901699437494742410;    // cos(2 pi / 5)
+        const T c2 = (T)-0.80901699437494742410;   // cos(4 pi / 5)
+        const T s1 = (T)0.95105651629515357212;    // sin(2 pi / 5)
+        const T s2 = (T)0.58778525229247312917;    // sin(4 pi / 5)
+        const cplx<T> a = cadd(v[1], v[4]), b = cadd(v[2], v[3]);
+        const cplx<T> c = csub(v[1], v[4]), d = csub(v[2], v[3]);
+        const cplx<T> x0 = v[0];
+        const cplx<T> p1 = cadd(x0, cadd(cscale(a, c1), cscale(b, c2)));
+        const cplx<T> p2 = cadd(x0, cadd(cscale(a, c2), cscale(b, c1)));
+        const cplx<T> q1 = mnegi(cadd(cscale(c, s1), cscale(d, s2)));
+        const cplx<T> q2 = mnegi(csub(cscale(c, s2), cscale(d, s1)));
+        v[0] = cadd(x0, cadd(a, b));
+        v[1] = cadd(p1, q1);
+        v[4] = csub(p1, q1);
+        v[2] = cadd(p2, q2);
+        v[3] = csub(p2, q2);
+    }
+};
+
+// One Stockham stage of radix R over G transforms of length M stored
+// back-to-back in buf; Ns = product of the radices of earlier stages.
+template <typename T, int R>
+__device__ __forceinline__ void fft_stage(cplx<T>* buf, int M, int G, int Ns,
+                                          const cplx<T>* __restrict__ tw)
+{
+    const int Mr = M / R;
+    const int nb = G * Mr;
+    const int stw = M / (Ns * R);
+    const int nthr = blockDim.x;
+    cplx<T> v[kMaxB][R];
+    int dst[kMaxB];
+#pragma unroll
+    for (int b = 0; b < kMaxB; ++b) {
+        const int idx = threadIdx.x + b * nthr;
+        dst[b] = -1;
+        if (idx < nb) {
+            const int g = idx / Mr;
+            const int j = idx - g * Mr;
+            const cplx<T>* src = buf + g * M;
+            const int k = j % Ns;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b][r] = src[j + r * Mr];
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[r * k * stw]);
+            Dft<T, R>::run(v[b]);
+            dst[b] = g * M + (j / Ns) * Ns * R + k;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < kMaxB; ++b) {
+        if (dst[b] >= 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[dst[b] + r * Ns] = v[b][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Forward transforms (exp(-2 pi i k n / M)) of G length-M sequences in LDS.
+template <typename T>
+__device__ void block_fft(cplx<T>* buf, int G, const Inst& I)
+{
+    const cplx<T>* tw = static_cast<const cplx<T>*>(I.tw);
+    const int M = I.M;
+    int Ns = 1;
+    for (int s = 0; s < I.nstages; ++s) {
+        const int R = I.radix[s];
+        switch (R) {
+        case 2: fft_stage<T, 2>(buf, M, G, Ns, tw); break;
+        case 3: fft_stage<T, 3>(buf, M, G, Ns, tw); break;
+        case 4: fft_stage<T, 4>(buf, M, G, Ns, tw); break;
+        default: fft_stage<T, 5>(buf, M, G, Ns, tw); break;
+        }
+        Ns *= R;
+    }
+}
+
+__device__ __forceinline__ bool okay(const Inst& I) { return live(I); }
+
+__device__ __forceinline__ bool occupied(const int* __restrict__ cs, int c)
+{
+    return cs[c + 1] > cs[c];
+}
+
+// Charge index and kernel (0: K1, 1: K2) of potential pot.
+template <int S, int FORM>
+__device__ __forceinline__ void pot_of(int pot, int& ch, int& kern)
+{
+    if (pot == 0) { ch = (FORM == 0) ? 0 : S + 1; kern = (FORM == 0) ? 0 : 1; }
+    else if (pot == 1) { ch = 0; kern = 1; }
+    else { ch = pot - 1; kern = 1; }
+}
+
+// ---------------------------------------------------------------- 2-D passes
+
+template <typename T, int P>
+__global__ __launch_bounds__(1024) void k_fft_rows(LaunchMap map)
+{
+    extern __shared__ __align__(16) char smem[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
+    VB_BEGIN(map, K_FFT_ROWS)
+    if (okay(I)) {
+        const Geom& G = *I.geom;
+        const int n = G.n, n_int = G.n_int, M = I.M, n_cap = I.n_cap, tw_ = I.tile_w;
+        const int npairs = (n_cap + 1) / 2;
+        const int ch = lb / npairs, j = lb - ch * npairs;
+        const int ra = 2 * j, rb = 2 * j + 1;
+        if (ra < n) {
+            const T* W = static_cast<const T*>(I.W) + (int64_t)ch * n_cap * n_cap;
+            const int* cs = I.cell_start;
+            const int cya = ra / P, cyb = rb / P;
+            for (int g = threadIdx.x; g < M; g += blockDim.x) {
+                T a = (T)0, b = (T)0;
+                if (g < n) {
+                    const int cx = g / P;
+                    if (occupied(cs, cya * n_int + cx)) a = W[(int64_t)ra * n_cap + g];
+                    if (rb < n && occupied(cs, cyb * n_int + cx)) b = W[(int64_t)rb * n_cap + g];
+                }
+                buf[g] = {a, b};
+            }
+            __syncthreads();
+            block_fft<T>(buf, 1, I);
+            cplx<T>* X = static_cast<cplx<T>*>(I.X) + (int64_t)ch * I.ntiles * n_cap * tw_;
+            const T hlf = (T)0.5;
+            for (int k = threadIdx.x; k < I.half; k += blockDim.x) {
+                const cplx<T> z = buf[k], zc = buf[k == 0 ? 0 : M - k];
+                const cplx<T> A = {(z.x + zc.x) * hlf, (z.y - zc.y) * hlf};
+                const cplx<T> B = {(z.y + zc.y) * hlf, (zc.x - z.x) * hlf};
+                const int tile = k / tw_, kk = k - tile * tw_;
+                X[((int64_t)tile * n_cap + ra) * tw_ + kk] = A;
+                if (rb < n) X[((int64_t)tile * n_cap + rb) * tw_ + kk] = B;
+            }
+            __syncthreads();
+        }
+    }
+    VB_END
+}
+
+template <typename T, int S, int FORM>
+__global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
+{
+    extern __shared__ __align__(16) char smem[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
+    VB_BEGIN(map, K_FFT_COLS)
+    if (okay(I)) {
+        const Geom& Gm = *I.geom;
+        const int n = Gm.n, M = I.M, n_cap = I.n_cap, tw_ = I.tile_w, half = I.half;
+        const int Gc = I.col_group;
+        const int ncg = (half + Gc - 1) / Gc;
+        const int pot = lb / ncg, cg = lb - pot * ncg;
+        int ch, kern;
+        pot_of<S, FORM>(pot, ch, kern);
+        const cplx<T>* X = static_cast<const cplx<T>*>(I.X) + (int64_t)ch * I.ntiles * n_cap * tw_;
+        for (int idx = threadIdx.x; idx < Gc * M; idx += blockDim.x) {
+            const int g = idx / M, r = idx - g * M;
+            const int k0 = cg * Gc + g;
+            cplx<T> v = {(T)0, (T)0};
+            if (k0 < half && r < n) {
+                const int tile = k0 / tw_;
+                v = X[((int64_t)tile * n_cap + r) * tw_ + (k0 - tile * tw_)];
+            }
+            buf[idx] = v;
+        }
+        __syncthreads();
+        block_fft<T>(buf, Gc, I);
+        // multiply by the real kernel spectrum, conjugate for the inverse
+        const T* sp = static_cast<const T*>(I.spec) + (int64_t)kern * half * half;
+        for (int idx = threadIdx.x; idx < Gc * M; idx += blockDim.x) {
+            const int g = idx / M, k1 = idx - g * M;
+            const int k0 = cg * Gc + g;
+            const T sv = (k0 < half) ? sp[(int64_t)k0 * half + (k1 <= M - k1 ? k1 : M - k1)] : (T)0;
+            const cplx<T> v = buf[idx];
+            buf[idx] = {v.x * sv, -v.y * sv};
+        }
+        __syncthreads();
+        block_fft<T>(buf, Gc, I);
+        cplx<T>* Xc = static_cast<cplx<T>*>(I.Xc) + (int64_t)pot * I.ntiles * n_cap * tw_;
+        for (int idx = threadIdx.x; idx < Gc * M; idx += blockDim.x) {
+            const int g = idx / M, r = idx - g * M;
+            const int k0 = cg * Gc + g;
+            if (k0 < half && r < n) {
+                const int tile = k0 / tw_;
+                Xc[((int64_t)tile * n_cap + r) * tw_ + (k0 - tile * tw_)] = cconj(buf[idx]);
+            }
+        }
+        __syncthreads();
+    }
+    VB_END
+}
+
+template <typename T, int S>
+__global__ __launch_bounds__(1024) void k_fft_irows(LaunchMap map)
+{
+    constexpr int NP = S + 2;
+    extern __shared__ __align__(16) char smem[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
+    VB_BEGIN(map, K_FFT_IROWS)
+    if (okay(I)) {
+        const Geom& G = *I.geom;
+        const int n = G.n, M = I.M, n_cap = I.n_cap, tw_ = I.tile_w;
+        const int q = lb / n_cap, r = lb - q * n_cap;
+        const int pa = 2 * q, pb = 2 * q + 1;
+        if (r < n) {
+            const cplx<T>* Xa = static_cast<const cplx<T>*>(I.Xc) + (int64_t)pa * I.ntiles * n_cap * tw_;
+            const cplx<T>* Xb = static_cast<const cplx<T>*>(I.Xc) + (int64_t)pb * I.ntiles * n_cap * tw_;
+            const int mh = M / 2;
+            for (int k = threadIdx.x; k < M; k += blockDim.x) {
+                const bool up = k > mh;
+                const int kk = up ? M - k : k;
+                const int tile = kk / tw_;
+                const int64_t off = ((int64_t)tile * n_cap + r) * tw_ + (kk - tile * tw_);
+                cplx<T> A = Xa[off];
+                cplx<T> B = (pb < NP) ? Xb[off] : cplx<T>{(T)0, (T)0};
+                if (up) { A = cconj(A); B = cconj(B); }
+                // Z = A + i B, stored conjugated (inverse by forward transform)
+                buf[k] = {A.x - B.y, -(A.y + B.x)};
+            }
+            __syncthreads();
+            block_fft<T>(buf, 1, I);
+            T* Va = static_cast<T*>(I.V) + (int64_t)pa * n_cap * n_cap + (int64_t)r * n_cap;
+            T* Vb = static_cast<T*>(I.V) + (int64_t)pb * n_cap * n_cap + (int64_t)r * n_cap;
+            for (int g = threadIdx.x; g < n; g += blockDim.x) {
+                const cplx<T> z = buf[g];       // conj of the inverse
+                Va[g] = z.x;
+                if (pb < NP) Vb[g] = -z.y;
+            }
+            __syncthreads();
+        }
+    }
+    VB_END
+}
+
+// ---------------------------------------------------------------- 1-D pass
+
+template <typename T, int P, int FORM>
+__global__ __launch_bounds__(1024) void k_fft_1d(LaunchMap map)
+{
+    extern __shared__ __align__(16) char smem[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
+    VB_BEGIN(map, K_FFT_1D)
+    if (okay(I)) {
+        const Geom& G = *I.geom;
+        const int n = G.n, M = I.M, n_cap = I.n_cap, half = I.half;
+        const int pot = lb;
+        int ch, kern;
+        pot_of<1, FORM>(pot, ch, kern);
+        const T* W = static_cast<const T*>(I.W) + (int64_t)ch * n_cap;
+        const int* cs = I.cell_start;
+        for (int g = threadIdx.x; g < M; g += blockDim.x) {
+            T a = (T)0;
+            if (g < n && occupied(cs, g / P)) a = W[g];
+            buf[g] = {a, (T)0};
+        }
+        __syncthreads();
+        block_fft<T>(buf, 1, I);
+        const T* sp = static_cast<const T*>(I.spec) + (int64_t)kern * half;
+        for (int k = threadIdx.x; k < M; k += blockDim.x) {
+            const T sv = sp[k <= M - k ? k : M - k];
+            const cplx<T> v = buf[k];
+            buf[k] = {v.x * sv, -v.y * sv};
+        }
+        __syncthreads();
+        block_fft<T>(buf, 1, I);
+        T* Vp = static_cast<T*>(I.V) + (int64_t)pot * n_cap;
+        for (int g = threadIdx.x; g < n; g += blockDim.x) Vp[g] = buf[g].x;
+        __syncthreads();
+    }
+    VB_END
+}
+
+// ---------------------------------------------------------------- kernel spectra (double)
+
+__device__ __forceinline__ double kern_val(int kern, double r2)
+{
+    const double a = 1.0 / (1.0 + r2);
+    return kern == 0 ? a : a * a;
+}
+
+// The spectra are rebuilt when the box kernel found a new node spacing (every
+// call under the paper policy, the first call under a fixed width).
+__device__ __forceinline__ bool spec_needed(const Inst& I, double& h)
+{
+    if (!okay(I)) return false;
+    h = I.geom->h;
+    return I.geom->spec_dirty != 0;
+}
+
+// First cosine pass.  s = 2: A[kern][j1][k0] = sum_{j0=0}^{M/2} wt(j0)
+// K(h^2 (j1^2 + j0^2)) cos(2 pi k0 j0 / M); s = 1: the whole spectrum
+// K^[kern][k] = sum_j wt(j) K(h^2 j^2) cos(2 pi k j / M) / M.
+// wt = 1 at j = 0 and j = M/2, else 2 (the circulant folds j and M - j).
+template <typename T, int S>
+__global__ __launch_bounds__(256) void k_spec1(LaunchMap map)
+{
+    VB_BEGIN(map, K_SPEC1)
+    double h;
+    if (spec_needed(I, h)) {
+        const int M = I.M, half = I.half, mh = M / 2;
+        const double h2 = h * h;
+        const double* ct = I.costab;
+        if (S == 2) {
+            const int64_t idx = (int64_t)lb * 256 + threadIdx.x;
+            if (idx < (int64_t)2 * half * half) {
+                const int kern = (int)(idx / ((int64_t)half * half));
+                const int rem = (int)(idx - (int64_t)kern * half * half);
+                const int j1 = rem / half, k0 = rem - j1 * half;
+                double acc = 0.0;
+                int ph = 0;
+                for (int j0 = 0; j0 <= mh; ++j0) {
+                    const double wt = (j0 == 0 || j0 == mh) ? 1.0 : 2.0;
+                    acc += wt * kern_val(kern, h2 * ((double)j1 * j1 + (double)j0 * j0)) * ct[ph];
+                    ph += k0;
+                    if (ph >= M) ph -= M;
+                }
+                I.spec_tmp[idx] = acc;
+            }
+        } else {
+            const int idx = lb * 256 + threadIdx.x;
+            if (idx < 2 * half) {
+                const int kern = idx / half, k = idx - kern * half;
+                double acc = 0.0;
+                int ph = 0;
+                for (int j = 0; j <= mh; ++j) {
+                    const double wt = (j == 0 || j == mh) ? 1.0 : 2.0;
+                    acc += wt * kern_val(kern, h2 * (double)j * j) * ct[ph];
+                    ph += k;
+                    if (ph >= M) ph -= M;
+                }
+                static_cast<T*>(I.spec)[idx] = (T)(acc / M);
+            }
+        }
+    }
+    VB_END
+}
+
+// Second pass (s = 2): K^[kern][k0][k1] = sum_{j1} wt(j1) A[kern][j1][k0]
+// cos(2 pi k1 j1 / M) / M^2, stored [kern][k0][k1], k0, k1 <= M/2.
+template <typename T, int S>
+__global__ __launch_bounds__(256) void k_spec2(LaunchMap map)
+{
+    VB_BEGIN(map, K_SPEC2)
+    double h;
+    if (S == 2 && spec_needed(I, h)) {
+        const int M = I.M, half = I.half, mh = M / 2;
+        const int64_t idx = (int64_t)lb * 256 + threadIdx.x;
+        if (idx < (int64_t)2 * half * half) {
+            const int kern = (int)(idx / ((int64_t)half * half));
+            const int rem = (int)(idx - (int64_t)kern * half * half);
+            const int k0 = rem / half, k1 = rem - k0 * half;
+            const double* A = I.spec_tmp + (int64_t)kern * half * half;
+            const double* ct = I.costab;
+            double acc = 0.0;
+            int ph = 0;
+            for (int j1 = 0; j1 <= mh; ++j1) {
+                const double wt = (j1 == 0 || j1 == mh) ? 1.0 : 2.0;
+                acc += wt * A[(int64_t)j1 * half + k0] * ct[ph];
+                ph += k1;
+                if (ph >= M) ph -= M;
+            }
+            static_cast<T*>(I.spec)[idx] = (T)(acc / ((double)M * (double)M));
+        }
+    }
+    VB_END
+}
+
+// ---------------------------------------------------------------- dispatch
+
+// Allow up to the full 160 KB of LDS for a kernel's dynamic allocation.
+template <typename K>
+static void allow_lds(K kernel, size_t lds)
+{
+    if (lds > 48 * 1024)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+template <typename T, int S, int P, int FORM>
+static hipError_t fft_go(int kind, const LaunchMap& map, const Launch& l, hipStream_t st)
+{
+    dim3 g(l.grid), b(l.block);
+    switch (kind) {
+    case K_FFT_ROWS:
+        if (S == 2) {
+            allow_lds(k_fft_rows<T, P>, l.lds);
+            hipLaunchKernelGGL((k_fft_rows<T, P>), g, b, l.lds, st, map);
+        }
+        break;
+    case K_FFT_COLS:
+        if (S == 2) {
+            allow_lds(k_fft_cols<T, S, FORM>, l.lds);
+            hipLaunchKernelGGL((k_fft_cols<T, S, FORM>), g, b, l.lds, st, map);
+        }
+        break;
+    case K_FFT_IROWS:
+        if (S == 2) {
+            allow_lds(k_fft_irows<T, S>, l.lds);
+            hipLaunchKernelGGL((k_fft_irows<T, S>), g, b, l.lds, st, map);
+        }
+        break;
+    case K_FFT_1D:
+        if (S == 1) {
+            allow_lds(k_fft_1d<T, P, FORM>, l.lds);
+            hipLaunchKernelGGL((k_fft_1d<T, P, FORM>), g, b, l.lds, st, map);
+        }
+        break;
+    case K_SPEC1: hipLaunchKernelGGL((k_spec1<T, S>), g, b, 0, st, map); break;
+    case K_SPEC2: hipLaunchKernelGGL((k_spec2<T, S>), g, b, 0, st, map); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int S, int P>
+static hipError_t fft_form(int kind, const Cfg& c, const LaunchMap& m, const Launch& l, hipStream_t st)
+{
+    return c.form == 0 ? fft_go<T, S, P, 0>(kind, m, l, st) : fft_go<T, S, P, 1>(kind, m, l, st);
+}
+
+template <typename T, int S>
+static hipError_t fft_p(int kind, const Cfg& c, const LaunchMap& m, const Launch& l, hipStream_t st)
+{
+    switch (c.p) {
+    case 2: return fft_form<T, S, 2>(kind, c, m, l, st);
+    case 3: return fft_form<T, S, 3>(kind, c, m, l, st);
+    case 4: return fft_form<T, S, 4>(kind, c, m, l, st);
+    case 5: return fft_form<T, S, 5>(kind, c, m, l, st);
+    case 6: return fft_form<T, S, 6>(kind, c, m, l, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fft_kind(int kind, const Cfg& c, const LaunchMap& map, const Launch& l,
+                           hipStream_t st)
+{
+    if (c.dtype == 0)
+        return c.s == 1 ? fft_p<float, 1>(kind, c, map, l, st) : fft_p<float, 2>(kind, c, map, l, st);
+    return c.s == 1 ? fft_p<double, 1>(kind, c, map, l, st) : fft_p<double, 2>(kind, c, map, l, st);
+}
+
+}  // namespace tsne

@@ -1,0 +1,938 @@
+// Host runtime of the t-SNE gradient library: plan layout over a caller
+// workspace, launch tables, the C ABI of include/tsne.h, HIP-graph capture of
+// an iteration, and the batch of independent embeddings.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/tsne.h"
+#include "launch.h"
+
+using namespace tsne;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxM = 16384;
+constexpr int kMaxBfly = 8;          // must match the kernels' per-thread butterfly bound
+constexpr int kGridCap = 4096;       // virtual blocks are looped over beyond this
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// Smallest even M >= lo whose prime factors are 2, 3, 5.
+int fft_len(int lo)
+{
+    for (int m = std::max(lo, 2); m <= kMaxM; ++m) {
+        if (m & 1) continue;
+        int r = m;
+        for (int f : {2, 3, 5})
+            while (r % f == 0) r /= f;
+        if (r == 1) return m;
+    }
+    return -1;
+}
+
+// Radix stages: 4s, then a 2 if needed, then 3s, then 5s.
+int radix_plan(int M, int* radix, int* rmin)
+{
+    int r = M, n2 = 0, n3 = 0, n5 = 0, k = 0;
+    while (r % 2 == 0) { r /= 2; ++n2; }
+    while (r % 3 == 0) { r /= 3; ++n3; }
+    while (r % 5 == 0) { r /= 5; ++n5; }
+    if (r != 1) return -1;
+    for (int i = 0; i < n2 / 2; ++i) radix[k++] = 4;
+    if (n2 & 1) radix[k++] = 2;
+    for (int i = 0; i < n3; ++i) radix[k++] = 3;
+    for (int i = 0; i < n5; ++i) radix[k++] = 5;
+    if (k > kMaxStages) return -1;
+    int mn = 5;
+    for (int i = 0; i < k; ++i) mn = std::min(mn, radix[i]);
+    *rmin = mn;
+    return k;
+}
+
+int pow2_at_least(int x)
+{
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+struct Layout {
+    size_t off[40];
+    size_t total;
+};
+
+enum Region {
+    R_INST, R_PREFIX, R_GEOM, R_SCHED, R_SMALL, R_BOX, R_COUNTS, R_CSTART, R_ISTART, R_SCAN,
+    R_ICELL, R_KEY, R_RANK, R_PERM, R_SY, R_CARRY, R_W, R_X, R_XC, R_V, R_SPEC, R_TW, R_COS,
+    R_SPECTMP, R_R, R_FA, R_ZPART, R_N
+};
+
+struct Derived {
+    int s, p, nc, np, tsz, max_int, n_cap, M, half, ncell_cap, items_cap, kpts, lpr;
+    int nstages, radix[kMaxStages], rmin;
+    int tile_w, ntiles, col_group;
+    int nb_box, nb_gather, nb_scan, nwaves;
+    int row_threads, col_threads;
+    size_t row_lds, col_lds;
+    int vb[K_NKINDS];
+    Layout L;
+};
+
+tsne_status derive(const tsne_desc* d, Derived& o)
+{
+    if (!d) return TSNE_E_ARG;
+    if (d->n < 2 || d->n > (int64_t)INT_MAX / 4) return TSNE_E_ARG;
+    if (d->s != 1 && d->s != 2) return TSNE_E_ARG;
+    if (d->dtype != TSNE_F32 && d->dtype != TSNE_F64) return TSNE_E_ARG;
+    if (d->p < 2 || d->p > kMaxP) return TSNE_E_UNSUPPORTED;
+    if (d->policy != TSNE_GRID_PAPER && d->policy != TSNE_GRID_FIXED) return TSNE_E_ARG;
+    if (d->form != TSNE_FORM_A && d->form != TSNE_FORM_B) return TSNE_E_ARG;
+    if (d->min_intervals < 1 || d->max_intervals < d->min_intervals) return TSNE_E_ARG;
+    if (d->policy == TSNE_GRID_FIXED && !(d->interval_width > 0.0)) return TSNE_E_ARG;
+    if (d->nnz < 0 || d->nnz > (int64_t)INT_MAX * 8) return TSNE_E_ARG;
+    if (d->lanes_per_row != 0 && d->lanes_per_row != 16 && d->lanes_per_row != 32 &&
+        d->lanes_per_row != 64)
+        return TSNE_E_ARG;
+    if (d->points_per_lane != 0 && (d->points_per_lane < 1 || d->points_per_lane > 64))
+        return TSNE_E_ARG;
+
+    o.s = d->s;
+    o.p = d->p;
+    o.nc = (d->form == TSNE_FORM_A) ? d->s + 1 : d->s + 2;
+    o.np = d->s + 2;
+    o.tsz = (d->dtype == TSNE_F32) ? 4 : 8;
+    o.max_int = d->max_intervals;
+    const int64_t ncap64 = (int64_t)d->max_intervals * d->p;
+    if (ncap64 * 2 > kMaxM) return TSNE_E_UNSUPPORTED;
+    o.n_cap = (int)ncap64;
+    if (d->s == 2 && (int64_t)o.max_int * o.max_int > (int64_t)INT_MAX / 8) return TSNE_E_UNSUPPORTED;
+    o.M = fft_len(2 * o.n_cap);
+    if (o.M < 0) return TSNE_E_UNSUPPORTED;
+    o.half = o.M / 2 + 1;
+    o.nstages = radix_plan(o.M, o.radix, &o.rmin);
+    if (o.nstages < 0) return TSNE_E_UNSUPPORTED;
+    o.ncell_cap = (d->s == 2) ? o.max_int * o.max_int : o.max_int;
+    o.kpts = d->points_per_lane ? d->points_per_lane : 8;
+    o.lpr = d->lanes_per_row ? d->lanes_per_row : 32;
+    const int64_t n = d->n;
+    o.items_cap = cdiv(n, o.kpts) + (int)std::min<int64_t>(n, o.ncell_cap);
+    o.nwaves = cdiv(o.items_cap, 64);
+
+    const int csz = 2 * o.tsz;                         // complex element
+    o.tile_w = 128 / csz;                              // 16 (float) or 8 (double)
+    o.ntiles = cdiv(o.half, o.tile_w);
+    // FFT thread counts: every stage must fit kMaxBfly butterflies per thread
+    const int need_row = cdiv(o.M, (int64_t)o.rmin * kMaxBfly);
+    o.row_threads = std::max(256, pow2_at_least(need_row));
+    if (o.row_threads > 1024) return TSNE_E_UNSUPPORTED;
+    o.row_lds = (size_t)o.M * csz;
+    o.col_group = 1;
+    for (int g = o.tile_w; g >= 1; g >>= 1) {
+        if ((size_t)g * o.M * csz <= 96 * 1024 && cdiv((int64_t)g * o.M, (int64_t)o.rmin * kMaxBfly) <= 1024) {
+            o.col_group = g;
+            break;
+        }
+    }
+    o.col_threads = std::max(256, pow2_at_least(cdiv((int64_t)o.col_group * o.M, (int64_t)o.rmin * kMaxBfly)));
+    if (o.col_threads > 1024) return TSNE_E_UNSUPPORTED;
+    o.col_lds = (size_t)o.col_group * o.M * csz;
+    if (o.row_lds > 160 * 1024) return TSNE_E_UNSUPPORTED;
+
+    o.nb_box = std::min(512, std::max(1, cdiv(n, 256 * 4)));
+    o.nb_gather = cdiv(n, 256);
+    o.nb_scan = cdiv(o.ncell_cap, 1024);
+
+    int* vb = o.vb;
+    for (int k = 0; k < K_NKINDS; ++k) vb[k] = 0;
+    vb[K_BOX] = o.nb_box;
+    vb[K_KEY] = cdiv(n, 256);
+    vb[K_SCAN_A] = o.nb_scan;
+    vb[K_SCAN_B] = o.nb_scan;
+    vb[K_SCATTER] = cdiv(n, 256);
+    vb[K_SPREAD] = cdiv(o.items_cap, 256);
+    vb[K_FIX] = cdiv(o.ncell_cap, 256);
+    if (d->s == 2) {
+        vb[K_FFT_ROWS] = o.nc * cdiv(o.n_cap, 2);
+        vb[K_FFT_COLS] = o.np * cdiv(o.half, o.col_group);
+        vb[K_FFT_IROWS] = cdiv(o.np, 2) * o.n_cap;
+        vb[K_SPEC1] = cdiv((int64_t)2 * o.half * o.half, 256);
+        vb[K_SPEC2] = vb[K_SPEC1];
+    } else {
+        vb[K_FFT_1D] = o.np;
+        vb[K_SPEC1] = cdiv(2 * o.half, 256);
+    }
+    vb[K_GATHER] = o.nb_gather;
+    vb[K_NORM] = cdiv(n * d->s, 256);
+    vb[K_ATTR] = d->nnz > 0 ? cdiv(n, 256 / o.lpr) : 0;
+    vb[K_UPDATE] = cdiv(n, 256);
+
+    // workspace layout
+    const int64_t grid = (d->s == 2) ? (int64_t)o.n_cap * o.n_cap : o.n_cap;
+    const int64_t nn = (d->s == 2) ? o.p * o.p : o.p;
+    size_t sz[R_N];
+    sz[R_INST] = sizeof(Inst);
+    sz[R_PREFIX] = sizeof(int) * K_NKINDS * 2;
+    sz[R_GEOM] = sizeof(Geom);
+    sz[R_SCHED] = sizeof(Sched);
+    sz[R_SMALL] = 64;                                   // status, iter, tickets[8]
+    sz[R_BOX] = sizeof(double) * 8 * o.nb_box;
+    sz[R_COUNTS] = sizeof(int) * o.ncell_cap;
+    sz[R_CSTART] = sizeof(int) * (o.ncell_cap + 1);
+    sz[R_ISTART] = sizeof(int) * (o.ncell_cap + 1);
+    sz[R_SCAN] = sizeof(int) * 2 * o.nb_scan;
+    sz[R_ICELL] = sizeof(int) * o.items_cap;
+    sz[R_KEY] = sizeof(int) * n;
+    sz[R_RANK] = sizeof(int) * n;
+    sz[R_PERM] = sizeof(int) * n;
+    sz[R_SY] = (size_t)o.tsz * n * d->s;
+    sz[R_CARRY] = (size_t)o.tsz * 2 * o.nwaves * nn * o.nc;
+    sz[R_W] = (size_t)o.tsz * o.nc * grid;
+    if (d->s == 2) {
+        sz[R_X] = (size_t)csz * o.nc * o.ntiles * o.n_cap * o.tile_w;
+        sz[R_XC] = (size_t)csz * o.np * o.ntiles * o.n_cap * o.tile_w;
+        sz[R_SPEC] = (size_t)o.tsz * 2 * o.half * o.half;
+        sz[R_SPECTMP] = sizeof(double) * 2 * (size_t)o.half * o.half;
+    } else {
+        sz[R_X] = 0;
+        sz[R_XC] = 0;
+        sz[R_SPEC] = (size_t)o.tsz * 2 * o.half;
+        sz[R_SPECTMP] = 0;
+    }
+    sz[R_V] = (size_t)o.tsz * o.np * grid;
+    sz[R_TW] = (size_t)csz * o.M;
+    sz[R_COS] = sizeof(double) * o.M;
+    sz[R_R] = (size_t)o.tsz * n * d->s;
+    sz[R_FA] = (size_t)o.tsz * n * d->s;
+    sz[R_ZPART] = sizeof(double) * o.nb_gather;
+    size_t cur = 0;
+    for (int r = 0; r < R_N; ++r) {
+        o.L.off[r] = cur;
+        cur = align_up(cur + sz[r]);
+    }
+    o.L.total = cur;
+    return TSNE_OK;
+}
+
+bool hip_ok(hipError_t e) { return e == hipSuccess; }
+
+Cfg cfg_of(const tsne_desc& d, const Derived& o)
+{
+    return Cfg{d.dtype, d.s, d.p, d.form, o.lpr};
+}
+
+Launch launch_of(int kind, const Derived& o, int vblocks)
+{
+    Launch l{std::min(vblocks, kGridCap), 256, 0};
+    switch (kind) {
+    case K_FFT_ROWS: case K_FFT_IROWS: case K_FFT_1D:
+        l.block = o.row_threads;
+        l.lds = o.row_lds;
+        break;
+    case K_FFT_COLS:
+        l.block = o.col_threads;
+        l.lds = o.col_lds;
+        break;
+    default:
+        break;
+    }
+    return l;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- plan
+
+struct tsne_plan {
+    tsne_desc d;
+    Derived o;
+    hipStream_t st;
+    char* ws;
+    Inst h;                 // host copy of the device record
+    Inst* dinst;
+    int* dprefix;
+    Cfg cfg;
+    bool P_bound;
+    bool spec_built;
+    bool graph_ok;
+    hipGraphExec_t gexec;
+    hipGraph_t graph;
+};
+
+static tsne_status enqueue(tsne_plan* pl, int kind)
+{
+    const int vb = pl->o.vb[kind];
+    if (vb <= 0) return TSNE_OK;
+    LaunchMap map{pl->dinst, pl->dprefix, 1};
+    const Launch l = launch_of(kind, pl->o, vb);
+    return hip_ok(launch_kind(kind, pl->cfg, map, l, pl->st)) ? TSNE_OK : TSNE_E_HIP;
+}
+
+static tsne_status enqueue_repulsion(tsne_plan* pl, bool normalise)
+{
+    static const int chain2[] = {K_BOX, K_SPEC1, K_SPEC2, K_KEY, K_SCAN_A, K_SCAN_B, K_SCATTER,
+                                 K_SPREAD, K_FIX, K_FFT_ROWS, K_FFT_COLS, K_FFT_IROWS, K_GATHER};
+    static const int chain1[] = {K_BOX, K_SPEC1, K_KEY, K_SCAN_A, K_SCAN_B, K_SCATTER,
+                                 K_SPREAD, K_FIX, K_FFT_1D, K_GATHER};
+    const int* ch = (pl->d.s == 2) ? chain2 : chain1;
+    const int nk = (pl->d.s == 2) ? (int)(sizeof(chain2) / sizeof(int)) : (int)(sizeof(chain1) / sizeof(int));
+    const bool spec = (pl->d.policy == TSNE_GRID_PAPER) || !pl->spec_built;
+    for (int k = 0; k < nk; ++k) {
+        if ((ch[k] == K_SPEC1 || ch[k] == K_SPEC2) && !spec) continue;
+        tsne_status s = enqueue(pl, ch[k]);
+        if (s != TSNE_OK) return s;
+    }
+    pl->spec_built = true;
+    if (normalise) return enqueue(pl, K_NORM);
+    return TSNE_OK;
+}
+
+static CallArgs no_args()
+{
+    CallArgs a;
+    std::memset(&a, 0, sizeof(a));
+    return a;
+}
+
+static void fill_sched(Sched& s, const tsne_sched* c)
+{
+    s.eta = c->eta;
+    s.mom0 = c->mom0;
+    s.mom1 = c->mom1;
+    s.mom_switch = c->mom_switch;
+    s.ee_alpha = c->ee_alpha;
+    s.ee_stop = c->ee_stop;
+    s.le_alpha = c->le_alpha;
+    s.le_start = c->le_start;
+    s.gain_inc = c->gain_inc;
+    s.gain_dec = c->gain_dec;
+    s.gain_min = c->gain_min;
+    s.recentre = c->recentre;
+}
+
+extern "C" {
+
+size_t tsne_workspace_bytes(const tsne_desc* desc)
+{
+    Derived o;
+    if (derive(desc, o) != TSNE_OK) return 0;
+    return o.L.total;
+}
+
+const char* tsne_status_str(tsne_status s)
+{
+    switch (s) {
+    case TSNE_OK: return "ok";
+    case TSNE_E_ARG: return "invalid argument";
+    case TSNE_E_UNSUPPORTED: return "unsupported configuration";
+    case TSNE_E_WORKSPACE: return "workspace missing, misaligned or too small";
+    case TSNE_E_CAPACITY: return "box needs more intervals than max_intervals";
+    case TSNE_E_NONFINITE: return "non-finite coordinate in Y";
+    case TSNE_E_HIP: return "HIP runtime error";
+    case TSNE_E_STATE: return "call not valid in this plan state";
+    }
+    return "unknown status";
+}
+
+tsne_status tsne_plan_create(const tsne_desc* desc, void* workspace, size_t bytes, void* stream,
+                             tsne_plan** out)
+{
+    if (!out) return TSNE_E_ARG;
+    *out = nullptr;
+    Derived o;
+    tsne_status rs = derive(desc, o);
+    if (rs != TSNE_OK) return rs;
+    if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || bytes < o.L.total) return TSNE_E_WORKSPACE;
+
+    tsne_plan* pl = new (std::nothrow) tsne_plan();
+    if (!pl) return TSNE_E_HIP;
+    pl->d = *desc;
+    pl->o = o;
+    pl->st = static_cast<hipStream_t>(stream);
+    pl->ws = static_cast<char*>(workspace);
+    pl->cfg = cfg_of(*desc, o);
+    pl->P_bound = false;
+    pl->spec_built = false;
+    pl->graph_ok = false;
+
+    char* b = pl->ws;
+    const size_t* off = o.L.off;
+    Inst& h = pl->h;
+    std::memset(&h, 0, sizeof(h));
+    h.n = desc->n;
+    h.nnz = desc->nnz;
+    h.s = desc->s;
+    h.p = desc->p;
+    h.form = desc->form;
+    h.nc = o.nc;
+    h.np = o.np;
+    h.policy = desc->policy;
+    h.min_int = desc->min_intervals;
+    h.max_int = desc->max_intervals;
+    h.n_cap = o.n_cap;
+    h.M = o.M;
+    h.half = o.half;
+    h.ncell_cap = o.ncell_cap;
+    h.items_cap = o.items_cap;
+    h.kpts = o.kpts;
+    h.lpr = o.lpr;
+    h.col_group = o.col_group;
+    h.tile_w = o.tile_w;
+    h.ntiles = o.ntiles;
+    h.nstages = o.nstages;
+    for (int i = 0; i < o.nstages; ++i) h.radix[i] = o.radix[i];
+    h.interval_width = desc->interval_width;
+    h.iter_end = INT_MAX;
+    h.geom = reinterpret_cast<Geom*>(b + off[R_GEOM]);
+    h.sched = reinterpret_cast<Sched*>(b + off[R_SCHED]);
+    h.status = reinterpret_cast<int*>(b + off[R_SMALL]);
+    h.iter = reinterpret_cast<int*>(b + off[R_SMALL] + 4);
+    h.tickets = reinterpret_cast<unsigned*>(b + off[R_SMALL] + 16);
+    h.box_part = reinterpret_cast<double*>(b + off[R_BOX]);
+    h.counts = reinterpret_cast<int*>(b + off[R_COUNTS]);
+    h.cell_start = reinterpret_cast<int*>(b + off[R_CSTART]);
+    h.item_start = reinterpret_cast<int*>(b + off[R_ISTART]);
+    h.scan_part = reinterpret_cast<int*>(b + off[R_SCAN]);
+    h.item_cell = reinterpret_cast<int*>(b + off[R_ICELL]);
+    h.key = reinterpret_cast<int*>(b + off[R_KEY]);
+    h.rank = reinterpret_cast<int*>(b + off[R_RANK]);
+    h.perm = reinterpret_cast<int*>(b + off[R_PERM]);
+    h.sY = b + off[R_SY];
+    h.carry = b + off[R_CARRY];
+    h.W = b + off[R_W];
+    h.X = b + off[R_X];
+    h.Xc = b + off[R_XC];
+    h.V = b + off[R_V];
+    h.spec = b + off[R_SPEC];
+    h.tw = b + off[R_TW];
+    h.costab = reinterpret_cast<double*>(b + off[R_COS]);
+    h.spec_tmp = reinterpret_cast<double*>(b + off[R_SPECTMP]);
+    h.R = b + off[R_R];
+    h.Fa_ws = b + off[R_FA];
+    h.z_part = reinterpret_cast<double*>(b + off[R_ZPART]);
+    h.nb_box = o.nb_box;
+    h.nb_gather = o.nb_gather;
+    h.nb_scan = o.nb_scan;
+    h.nwaves = o.nwaves;
+    pl->dinst = reinterpret_cast<Inst*>(b + off[R_INST]);
+    pl->dprefix = reinterpret_cast<int*>(b + off[R_PREFIX]);
+
+    // host images of the tables
+    std::vector<int> prefix(K_NKINDS * 2);
+    for (int k = 0; k < K_NKINDS; ++k) {
+        prefix[2 * k] = 0;
+        prefix[2 * k + 1] = o.vb[k];
+    }
+    std::vector<double> costab(o.M);
+    std::vector<char> tw((size_t)o.M * 2 * o.tsz);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int k = 0; k < o.M; ++k) {
+        const double a = two_pi * (double)k / (double)o.M;
+        const double c = std::cos(a), s = -std::sin(a);
+        costab[k] = c;
+        if (o.tsz == 4) {
+            float* t = reinterpret_cast<float*>(tw.data());
+            t[2 * k] = (float)c;
+            t[2 * k + 1] = (float)s;
+        } else {
+            double* t = reinterpret_cast<double*>(tw.data());
+            t[2 * k] = c;
+            t[2 * k + 1] = s;
+        }
+    }
+    hipStream_t st = pl->st;
+    bool ok = hip_ok(hipMemcpyAsync(pl->dinst, &h, sizeof(Inst), hipMemcpyHostToDevice, st)) &&
+              hip_ok(hipMemcpyAsync(pl->dprefix, prefix.data(), prefix.size() * sizeof(int),
+                                    hipMemcpyHostToDevice, st)) &&
+              hip_ok(hipMemcpyAsync(h.tw, tw.data(), tw.size(), hipMemcpyHostToDevice, st)) &&
+              hip_ok(hipMemcpyAsync(h.costab, costab.data(), costab.size() * sizeof(double),
+                                    hipMemcpyHostToDevice, st)) &&
+              hip_ok(hipMemsetAsync(b + off[R_GEOM], 0, sizeof(Geom), st)) &&
+              hip_ok(hipMemsetAsync(b + off[R_SCHED], 0, sizeof(Sched), st)) &&
+              hip_ok(hipMemsetAsync(b + off[R_SMALL], 0, 64, st)) &&
+              hip_ok(hipMemsetAsync(h.counts, 0, sizeof(int) * o.ncell_cap, st)) &&
+              hip_ok(hipStreamSynchronize(st));
+    if (!ok) {
+        delete pl;
+        return TSNE_E_HIP;
+    }
+    *out = pl;
+    return TSNE_OK;
+}
+
+tsne_status tsne_plan_destroy(tsne_plan* plan)
+{
+    if (!plan) return TSNE_E_ARG;
+    if (plan->graph_ok) {
+        hipGraphExecDestroy(plan->gexec);
+        hipGraphDestroy(plan->graph);
+    }
+    delete plan;
+    return TSNE_OK;
+}
+
+tsne_status tsne_bind_P(tsne_plan* pl, const int64_t* row_ptr, const int32_t* col, const void* val)
+{
+    if (!pl) return TSNE_E_ARG;
+    if (pl->d.nnz > 0 && (!row_ptr || !col || !val)) return TSNE_E_ARG;
+    // host check of the CSR shape: row_ptr[0] = 0, row_ptr[n] = nnz, monotone,
+    // columns in range (a device-side read would fault on a bad index)
+    if (pl->d.nnz > 0) {
+        const int64_t n = pl->d.n;
+        std::vector<int64_t> rp(n + 1);
+        std::vector<int32_t> cc(pl->d.nnz);
+        if (!hip_ok(hipStreamSynchronize(pl->st)) ||
+            !hip_ok(hipMemcpy(rp.data(), row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost)) ||
+            !hip_ok(hipMemcpy(cc.data(), col, sizeof(int32_t) * pl->d.nnz, hipMemcpyDeviceToHost)))
+            return TSNE_E_HIP;
+        if (rp[0] != 0 || rp[n] != pl->d.nnz) return TSNE_E_ARG;
+        for (int64_t i = 0; i < n; ++i)
+            if (rp[i + 1] < rp[i]) return TSNE_E_ARG;
+        for (int64_t k = 0; k < pl->d.nnz; ++k)
+            if (cc[k] < 0 || cc[k] >= n) return TSNE_E_ARG;
+    }
+    CallArgs a = no_args();
+    a.set_P = 1;
+    a.row_ptr = row_ptr;
+    a.col = col;
+    a.val = val;
+    if (!hip_ok(launch_set_args(pl->dinst, a, pl->st))) return TSNE_E_HIP;
+    pl->P_bound = pl->d.nnz > 0;
+    return TSNE_OK;
+}
+
+tsne_status tsne_repulsive(tsne_plan* pl, const void* Y, void* F_rep, double* Z)
+{
+    if (!pl || !Y || !F_rep) return TSNE_E_ARG;
+    CallArgs a = no_args();
+    a.set_ptrs = 1;
+    a.Yin = Y;
+    a.Frep = F_rep;
+    a.Zout = Z;
+    a.Fattr = pl->h.Fa_ws;
+    if (!hip_ok(launch_set_args(pl->dinst, a, pl->st))) return TSNE_E_HIP;
+    return enqueue_repulsion(pl, true);
+}
+
+tsne_status tsne_attractive(tsne_plan* pl, const void* Y, void* F_attr)
+{
+    if (!pl || !Y || !F_attr) return TSNE_E_ARG;
+    if (!pl->P_bound) return TSNE_E_STATE;
+    CallArgs a = no_args();
+    a.set_ptrs = 1;
+    a.Yin = Y;
+    a.Fattr = F_attr;
+    if (!hip_ok(launch_set_args(pl->dinst, a, pl->st))) return TSNE_E_HIP;
+    return enqueue(pl, K_ATTR);
+}
+
+static tsne_status step_args(tsne_plan* pl, void* Y, void* uY, void* gains, const tsne_sched* sc,
+                             int32_t iter)
+{
+    CallArgs a = no_args();
+    a.set_ptrs = 1;
+    a.Yin = Y;
+    a.Y = Y;
+    a.uY = uY;
+    a.gains = gains;
+    a.Fattr = pl->h.Fa_ws;
+    a.set_sched = 1;
+    fill_sched(a.sched, sc);
+    a.set_iter = 1;
+    a.iter = iter;
+    return hip_ok(launch_set_args(pl->dinst, a, pl->st)) ? TSNE_OK : TSNE_E_HIP;
+}
+
+static tsne_status enqueue_iteration(tsne_plan* pl)
+{
+    tsne_status s = enqueue_repulsion(pl, false);
+    if (s != TSNE_OK) return s;
+    if (pl->P_bound) {
+        s = enqueue(pl, K_ATTR);
+        if (s != TSNE_OK) return s;
+    }
+    return enqueue(pl, K_UPDATE);
+}
+
+static bool sched_ok(const tsne_sched* sc)
+{
+    return sc && std::isfinite(sc->eta) && std::isfinite(sc->mom0) && std::isfinite(sc->mom1) &&
+           std::isfinite(sc->ee_alpha) && std::isfinite(sc->le_alpha) && sc->gain_min >= 0.0;
+}
+
+tsne_status tsne_step(tsne_plan* pl, void* Y, void* uY, void* gains, const tsne_sched* sc, int32_t iter)
+{
+    if (!pl || !Y || !uY || !gains || !sched_ok(sc) || iter < 0) return TSNE_E_ARG;
+    if (pl->d.nnz > 0 && !pl->P_bound) return TSNE_E_STATE;
+    tsne_status s = step_args(pl, Y, uY, gains, sc, iter);
+    if (s != TSNE_OK) return s;
+    return enqueue_iteration(pl);
+}
+
+tsne_status tsne_run(tsne_plan* pl, void* Y, void* uY, void* gains, const tsne_sched* sc,
+                     int32_t iter0, int32_t n_iter)
+{
+    if (!pl || !Y || !uY || !gains || !sched_ok(sc) || iter0 < 0 || n_iter < 0) return TSNE_E_ARG;
+    if (pl->d.nnz > 0 && !pl->P_bound) return TSNE_E_STATE;
+    if (n_iter == 0) return TSNE_OK;
+    tsne_status s = step_args(pl, Y, uY, gains, sc, iter0);
+    if (s != TSNE_OK) return s;
+    // the first iteration runs eagerly (it builds the kernel spectra under the
+    // fixed policy); the rest replay a captured graph of one iteration
+    s = enqueue_iteration(pl);
+    if (s != TSNE_OK || n_iter == 1) return s;
+    if (pl->st == nullptr) {
+        for (int32_t i = 1; i < n_iter; ++i) {
+            s = enqueue_iteration(pl);
+            if (s != TSNE_OK) return s;
+        }
+        return TSNE_OK;
+    }
+    if (!pl->graph_ok) {
+        if (!hip_ok(hipStreamBeginCapture(pl->st, hipStreamCaptureModeThreadLocal))) return TSNE_E_HIP;
+        tsne_status cs = enqueue_iteration(pl);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(pl->st, &g);
+        if (cs != TSNE_OK || e != hipSuccess || !g) {
+            if (g) hipGraphDestroy(g);
+            return cs != TSNE_OK ? cs : TSNE_E_HIP;
+        }
+        if (!hip_ok(hipGraphInstantiate(&pl->gexec, g, nullptr, nullptr, 0))) {
+            hipGraphDestroy(g);
+            return TSNE_E_HIP;
+        }
+        pl->graph = g;
+        pl->graph_ok = true;
+    }
+    for (int32_t i = 1; i < n_iter; ++i)
+        if (!hip_ok(hipGraphLaunch(pl->gexec, pl->st))) return TSNE_E_HIP;
+    return TSNE_OK;
+}
+
+tsne_status tsne_query(tsne_plan* pl, tsne_stats* out)
+{
+    if (!pl || !out) return TSNE_E_ARG;
+    Geom g;
+    int small[2];
+    if (!hip_ok(hipStreamSynchronize(pl->st)) ||
+        !hip_ok(hipMemcpy(&g, pl->h.geom, sizeof(Geom), hipMemcpyDeviceToHost)) ||
+        !hip_ok(hipMemcpy(small, pl->h.status, sizeof(small), hipMemcpyDeviceToHost)) ||
+        !hip_ok(hipMemset(pl->h.status, 0, sizeof(int))))
+        return TSNE_E_HIP;
+    std::memset(out, 0, sizeof(*out));
+    out->status = small[0];
+    out->iter = small[1];
+    out->n_int = g.n_int;
+    out->n_nodes = g.n;
+    out->fft_len = pl->o.M;
+    out->max_intervals = pl->d.max_intervals;
+    out->origin[0] = g.origin[0];
+    out->origin[1] = g.origin[1];
+    out->w_int = g.w;
+    out->box_side = g.side;
+    out->Z = g.Z;
+    return TSNE_OK;
+}
+
+tsne_status tsne_debug_export(tsne_plan* pl, int32_t what, void* dst, size_t* bytes)
+{
+    if (!pl || !bytes) return TSNE_E_ARG;
+    const Derived& o = pl->o;
+    const size_t grid = (pl->d.s == 2) ? (size_t)o.n_cap * o.n_cap : (size_t)o.n_cap;
+    const void* src;
+    size_t nb;
+    switch (what) {
+    case 0: src = pl->h.W; nb = (size_t)o.tsz * o.nc * grid; break;
+    case 1: src = pl->h.V; nb = (size_t)o.tsz * o.np * grid; break;
+    case 2: src = pl->h.R; nb = (size_t)o.tsz * pl->d.n * pl->d.s; break;
+    case 3: {
+        Geom g;
+        if (!hip_ok(hipStreamSynchronize(pl->st)) ||
+            !hip_ok(hipMemcpy(&g, pl->h.geom, sizeof(Geom), hipMemcpyDeviceToHost)))
+            return TSNE_E_HIP;
+        src = pl->h.cell_start;
+        nb = sizeof(int) * ((size_t)std::min(g.n_cells, o.ncell_cap) + 1);
+        break;
+    }
+    default: return TSNE_E_ARG;
+    }
+    if (!dst) {
+        *bytes = nb;
+        return TSNE_OK;
+    }
+    if (*bytes < nb) return TSNE_E_ARG;
+    if (!hip_ok(hipStreamSynchronize(pl->st)) || !hip_ok(hipMemcpy(dst, src, nb, hipMemcpyDeviceToHost)))
+        return TSNE_E_HIP;
+    *bytes = nb;
+    return TSNE_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batch
+
+namespace {
+
+struct Slot {
+    bool used;
+    tsne_plan* plan;
+};
+
+}  // namespace
+
+struct tsne_batch {
+    int max_slots, s, dtype, p, form;
+    hipStream_t st;
+    char* ws;
+    Inst* dtable;
+    int* dprefix;
+    std::vector<Slot> slots;
+    std::vector<int> live;              // slot ids in table order
+    std::vector<int> prefix_host;       // [K_NKINDS][nlive + 1]
+    Launch launch[K_NKINDS];
+    Cfg cfg;
+    bool dirty;
+    bool spec_pending;
+    bool any_paper;
+    bool graph_ok;
+    hipGraph_t graph;
+    hipGraphExec_t gexec;
+};
+
+static size_t batch_table_bytes(int max_slots)
+{
+    return align_up(sizeof(Inst) * (size_t)max_slots);
+}
+
+static void batch_drop_graph(tsne_batch* b)
+{
+    if (b->graph_ok) {
+        hipGraphExecDestroy(b->gexec);
+        hipGraphDestroy(b->graph);
+        b->graph_ok = false;
+    }
+}
+
+// Rebuild the device instance table and the per-kind block tables for the
+// current set of slots.
+static tsne_status batch_refresh(tsne_batch* b)
+{
+    b->live.clear();
+    for (int i = 0; i < b->max_slots; ++i)
+        if (b->slots[i].used) b->live.push_back(i);
+    const int nl = (int)b->live.size();
+    b->prefix_host.assign((size_t)K_NKINDS * (nl + 1), 0);
+    b->any_paper = false;
+    for (int k = 0; k < K_NKINDS; ++k) {
+        b->launch[k] = Launch{0, 256, 0};
+    }
+    for (int j = 0; j < nl; ++j) {
+        tsne_plan* pl = b->slots[b->live[j]].plan;
+        if (!hip_ok(hipMemcpyAsync(b->dtable + j, pl->dinst, sizeof(Inst), hipMemcpyDeviceToDevice, b->st)))
+            return TSNE_E_HIP;
+        if (pl->d.policy == TSNE_GRID_PAPER) b->any_paper = true;
+        for (int k = 0; k < K_NKINDS; ++k) {
+            int* pre = b->prefix_host.data() + (size_t)k * (nl + 1);
+            pre[j + 1] = pre[j] + pl->o.vb[k];
+            const Launch l = launch_of(k, pl->o, pl->o.vb[k]);
+            b->launch[k].block = std::max(b->launch[k].block, l.block);
+            b->launch[k].lds = std::max(b->launch[k].lds, l.lds);
+        }
+    }
+    for (int k = 0; k < K_NKINDS; ++k) {
+        const int total = b->prefix_host[(size_t)k * (nl + 1) + nl];
+        b->launch[k].grid = std::min(total, kGridCap);
+    }
+    if (nl > 0 &&
+        !hip_ok(hipMemcpyAsync(b->dprefix, b->prefix_host.data(), b->prefix_host.size() * sizeof(int),
+                               hipMemcpyHostToDevice, b->st)))
+        return TSNE_E_HIP;
+    if (!hip_ok(hipStreamSynchronize(b->st))) return TSNE_E_HIP;
+    batch_drop_graph(b);
+    b->dirty = false;
+    return TSNE_OK;
+}
+
+static tsne_status batch_enqueue_tick(tsne_batch* b, bool with_spec)
+{
+    const int nl = (int)b->live.size();
+    LaunchMap map{b->dtable, b->dprefix, nl};
+    static const int chain2[] = {K_BOX, K_SPEC1, K_SPEC2, K_KEY, K_SCAN_A, K_SCAN_B, K_SCATTER,
+                                 K_SPREAD, K_FIX, K_FFT_ROWS, K_FFT_COLS, K_FFT_IROWS, K_GATHER,
+                                 K_ATTR, K_UPDATE};
+    static const int chain1[] = {K_BOX, K_SPEC1, K_KEY, K_SCAN_A, K_SCAN_B, K_SCATTER, K_SPREAD,
+                                 K_FIX, K_FFT_1D, K_GATHER, K_ATTR, K_UPDATE};
+    const int* ch = (b->s == 2) ? chain2 : chain1;
+    const int nk = (b->s == 2) ? (int)(sizeof(chain2) / sizeof(int)) : (int)(sizeof(chain1) / sizeof(int));
+    for (int i = 0; i < nk; ++i) {
+        const int k = ch[i];
+        if ((k == K_SPEC1 || k == K_SPEC2) && !with_spec) continue;
+        if (b->launch[k].grid <= 0) continue;
+        if (!hip_ok(launch_kind(k, b->cfg, map, b->launch[k], b->st))) return TSNE_E_HIP;
+    }
+    return TSNE_OK;
+}
+
+extern "C" {
+
+size_t tsne_batch_workspace_bytes(int32_t max_slots)
+{
+    if (max_slots < 1 || max_slots > 4096) return 0;
+    return batch_table_bytes(max_slots) + align_up(sizeof(int) * K_NKINDS * (size_t)(max_slots + 1));
+}
+
+tsne_status tsne_batch_create(int32_t max_slots, int32_t s, int32_t dtype, int32_t p, int32_t form,
+                              void* workspace, size_t bytes, void* stream, tsne_batch** out)
+{
+    if (!out) return TSNE_E_ARG;
+    *out = nullptr;
+    if (max_slots < 1 || max_slots > 4096 || (s != 1 && s != 2) || (dtype != 0 && dtype != 1) ||
+        (form != 0 && form != 1))
+        return TSNE_E_ARG;
+    if (p < 2 || p > kMaxP) return TSNE_E_UNSUPPORTED;
+    if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || bytes < tsne_batch_workspace_bytes(max_slots))
+        return TSNE_E_WORKSPACE;
+    tsne_batch* b = new (std::nothrow) tsne_batch();
+    if (!b) return TSNE_E_HIP;
+    b->max_slots = max_slots;
+    b->s = s;
+    b->dtype = dtype;
+    b->p = p;
+    b->form = form;
+    b->st = static_cast<hipStream_t>(stream);
+    b->ws = static_cast<char*>(workspace);
+    b->dtable = reinterpret_cast<Inst*>(b->ws);
+    b->dprefix = reinterpret_cast<int*>(b->ws + batch_table_bytes(max_slots));
+    b->slots.assign(max_slots, Slot{false, nullptr});
+    b->dirty = true;
+    b->spec_pending = false;
+    b->any_paper = false;
+    b->graph_ok = false;
+    b->cfg = Cfg{dtype, s, p, form, 32};
+    *out = b;
+    return TSNE_OK;
+}
+
+tsne_status tsne_batch_destroy(tsne_batch* b)
+{
+    if (!b) return TSNE_E_ARG;
+    batch_drop_graph(b);
+    for (auto& sl : b->slots)
+        if (sl.used) tsne_plan_destroy(sl.plan);
+    delete b;
+    return TSNE_OK;
+}
+
+tsne_status tsne_batch_admit(tsne_batch* b, const tsne_desc* desc, void* plan_ws, size_t plan_ws_bytes,
+                             void* Y, void* uY, void* gains, const int64_t* row_ptr,
+                             const int32_t* col, const void* val, const tsne_sched* sc,
+                             int32_t iter0, int32_t n_iter, int32_t* slot)
+{
+    if (!b || !desc || !slot || !Y || !uY || !gains || !sched_ok(sc) || iter0 < 0 || n_iter < 0)
+        return TSNE_E_ARG;
+    if (desc->s != b->s || desc->dtype != b->dtype || desc->p != b->p || desc->form != b->form)
+        return TSNE_E_ARG;
+    if (desc->lanes_per_row != 0 && desc->lanes_per_row != 32) return TSNE_E_UNSUPPORTED;
+    int free_id = -1;
+    for (int i = 0; i < b->max_slots; ++i)
+        if (!b->slots[i].used) { free_id = i; break; }
+    if (free_id < 0) return TSNE_E_CAPACITY;
+    tsne_plan* pl = nullptr;
+    tsne_status s = tsne_plan_create(desc, plan_ws, plan_ws_bytes, b->st, &pl);
+    if (s != TSNE_OK) return s;
+    if (desc->nnz > 0) {
+        s = tsne_bind_P(pl, row_ptr, col, val);
+        if (s != TSNE_OK) { tsne_plan_destroy(pl); return s; }
+    }
+    s = step_args(pl, Y, uY, gains, sc, iter0);
+    CallArgs a = no_args();
+    a.set_end = 1;
+    a.iter_end = iter0 + n_iter;
+    if (s != TSNE_OK || !hip_ok(launch_set_args(pl->dinst, a, b->st))) {
+        tsne_plan_destroy(pl);
+        return TSNE_E_HIP;
+    }
+    pl->h.iter_end = iter0 + n_iter;
+    b->slots[free_id] = Slot{true, pl};
+    b->dirty = true;
+    b->spec_pending = true;
+    *slot = free_id;
+    return TSNE_OK;
+}
+
+tsne_status tsne_batch_tick(tsne_batch* b, int32_t n_ticks)
+{
+    if (!b || n_ticks < 0) return TSNE_E_ARG;
+    if (b->dirty) {
+        tsne_status s = batch_refresh(b);
+        if (s != TSNE_OK) return s;
+    }
+    if (b->live.empty() || n_ticks == 0) return TSNE_OK;
+    int t = 0;
+    if (b->spec_pending || b->st == nullptr) {
+        // first tick after an admission builds the new slots' spectra eagerly
+        tsne_status s = batch_enqueue_tick(b, true);
+        if (s != TSNE_OK) return s;
+        b->spec_pending = false;
+        ++t;
+        if (b->st == nullptr) {
+            for (; t < n_ticks; ++t) {
+                s = batch_enqueue_tick(b, b->any_paper);
+                if (s != TSNE_OK) return s;
+            }
+            return TSNE_OK;
+        }
+    }
+    if (t >= n_ticks) return TSNE_OK;
+    if (!b->graph_ok) {
+        if (!hip_ok(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal))) return TSNE_E_HIP;
+        tsne_status cs = batch_enqueue_tick(b, b->any_paper);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(b->st, &g);
+        if (cs != TSNE_OK || e != hipSuccess || !g) {
+            if (g) hipGraphDestroy(g);
+            return cs != TSNE_OK ? cs : TSNE_E_HIP;
+        }
+        if (!hip_ok(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0))) {
+            hipGraphDestroy(g);
+            return TSNE_E_HIP;
+        }
+        b->graph = g;
+        b->graph_ok = true;
+    }
+    for (; t < n_ticks; ++t)
+        if (!hip_ok(hipGraphLaunch(b->gexec, b->st))) return TSNE_E_HIP;
+    return TSNE_OK;
+}
+
+tsne_status tsne_batch_poll(tsne_batch* b, int32_t slot, int32_t* iters_done, int32_t* status)
+{
+    if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].used) return TSNE_E_ARG;
+    tsne_plan* pl = b->slots[slot].plan;
+    int small[2];
+    if (!hip_ok(hipStreamSynchronize(b->st)) ||
+        !hip_ok(hipMemcpy(small, pl->h.status, sizeof(small), hipMemcpyDeviceToHost)))
+        return TSNE_E_HIP;
+    if (iters_done) *iters_done = small[1];
+    if (status) *status = small[0];
+    return TSNE_OK;
+}
+
+tsne_status tsne_batch_retire(tsne_batch* b, int32_t slot)
+{
+    if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].used) return TSNE_E_ARG;
+    if (!hip_ok(hipStreamSynchronize(b->st))) return TSNE_E_HIP;
+    tsne_plan_destroy(b->slots[slot].plan);
+    b->slots[slot] = Slot{false, nullptr};
+    b->dirty = true;
+    return TSNE_OK;
+}
+
+}  // extern "C"

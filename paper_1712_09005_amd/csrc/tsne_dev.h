@@ -1,0 +1,182 @@
+// Internal definitions shared by the HIP kernels and the host runtime.
+//
+// Everything a kernel needs about one embedding ("instance") sits in an Inst
+// record in device memory: sizes, the caller's buffers and the workspace
+// regions.  A launch covers a list of instances: each kernel kind has a
+// per-instance count of virtual blocks and a prefix table over them, so a
+// single plan and a batch of uneven embeddings go through the same kernels.
+#pragma once
+
+#include <stdint.h>
+
+#ifndef TSNE_HOST_ONLY
+#include <hip/hip_runtime.h>
+#endif
+
+namespace tsne {
+
+constexpr int kMaxStages = 24;   // FFT radix stages
+constexpr int kMaxP = 6;         // Lagrange nodes per interval
+constexpr int kWave = 64;
+
+// Kernel kinds with their own virtual-block tables.
+enum Kind : int {
+    K_ARGS = 0, K_BOX, K_KEY, K_SCAN_A, K_SCAN_B, K_SCATTER, K_SPREAD, K_FIX,
+    K_FFT_ROWS, K_FFT_COLS, K_FFT_IROWS, K_FFT_1D, K_GATHER, K_NORM, K_ATTR,
+    K_UPDATE, K_SPEC1, K_SPEC2, K_NKINDS
+};
+
+// Status bits latched on the device (values of tsne_status).
+enum : int { ST_OK = 0, ST_CAPACITY = 4, ST_NONFINITE = 5 };
+
+// Geometry of the current iteration, written by the box kernel (double).
+struct Geom {
+    double origin[2];
+    double centre[2];
+    double mean[2];
+    double w;          // interval width
+    double inv_w;
+    double h;          // node spacing w / p
+    double side;       // L
+    double qscale;     // power-of-two charge scale
+    double Z;          // normalisation of the last repulsion
+    int n_int;         // intervals per dimension
+    int n;             // nodes per dimension, n_int * p
+    int n_cells;       // n_int^s
+    int spec_dirty;    // node spacing changed: spectra must be rebuilt
+    double spec_h;     // spacing the current spectra were built for
+    int pad[2];
+};
+
+struct Sched {
+    double eta, mom0, mom1, ee_alpha, le_alpha, gain_inc, gain_dec, gain_min;
+    int mom_switch, ee_stop, le_start, recentre;
+};
+
+struct Inst {
+    // ---- configuration (fixed for the plan)
+    int64_t n;
+    int64_t nnz;
+    int s, p, form, nc, np, policy;
+    int min_int, max_int, n_cap, M, half;      // half = M/2 + 1
+    int ncell_cap, items_cap, kpts, lpr;
+    int col_group, tile_w, ntiles;              // FFT column kernel grouping
+    int nstages;
+    int radix[kMaxStages];
+    double interval_width;
+    int iter_end;                               // iterations stop at this index
+
+    // ---- caller buffers (set per call by k_set_args)
+    const void* Yin;       // positions read by repulsion / attraction
+    void* Y;               // positions updated by the step
+    void* uY;
+    void* gains;
+    void* Frep;            // tsne_repulsive output (normalised)
+    double* Zout;          // tsne_repulsive output
+    void* Fattr;           // attraction output (caller's or workspace)
+    const int64_t* row_ptr;
+    const int32_t* col;
+    const void* val;
+
+    // ---- workspace regions
+    Geom* geom;
+    Sched* sched;
+    int* status;
+    int* iter;
+    unsigned* tickets;     // [8]
+    double* box_part;      // [nb_box][2*s+... ] partial min/max/sum
+    int* counts;           // [ncell_cap]
+    int* cell_start;       // [ncell_cap + 1]
+    int* item_start;       // [ncell_cap + 1]
+    int* scan_part;        // [2 * nb_scan] tile sums
+    int* item_cell;        // [items_cap]
+    int* key;              // [n]
+    int* rank;             // [n]
+    int* perm;             // [n] sorted position -> point
+    void* sY;              // [n][s] sorted positions
+    void* carry;           // [2 * nwaves][1 + p^s * nc] spread carries
+    void* W;               // [nc][n_cap][n_cap] (s = 2) or [nc][n_cap]
+    void* X;               // [nc][ntiles][n_cap][tile_w] complex (row spectra)
+    void* Xc;              // [np][ntiles][n_cap][tile_w] complex (after columns)
+    void* V;               // [np][n_cap][n_cap] or [np][n_cap]
+    void* spec;            // [2][half][half] (s = 2) or [2][half], pre-scaled
+    void* tw;              // [M] complex roots exp(-2 pi i k / M)
+    double* costab;        // [M] cos(2 pi k / M) in double
+    double* spec_tmp;      // [half][half] first cosine pass (double)
+    void* R;               // [n][s] unnormalised repulsion numerators
+    void* Fa_ws;           // [n][s] attraction (workspace copy for the step)
+    double* z_part;        // [nb_gather]
+    int nb_box, nb_gather, nb_scan, nwaves;
+};
+
+// Launch table: first virtual block of each instance per kernel kind.
+struct LaunchMap {
+    const Inst* insts;     // device array
+    const int* prefix;     // device [K_NKINDS][ninst + 1]
+    int ninst;
+};
+
+#ifndef TSNE_HOST_ONLY
+
+template <typename T> struct cplx { T x, y; };
+
+__device__ __forceinline__ int find_inst(const int* __restrict__ pre, int ninst, int vb)
+{
+    int lo = 0, hi = ninst - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= vb) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// The instance takes part in this iteration: no latched status and its
+// iteration counter has not reached iter_end.
+__device__ __forceinline__ bool live(const Inst& I)
+{
+    return __hip_atomic_load(I.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
+           __hip_atomic_load(I.iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < I.iter_end;
+}
+
+// Iterate over this launch's virtual blocks of kernel kind K:
+//   VB_LOOP(map, K) { const Inst& I = ...; int lb = ...; ... }
+#define VB_BEGIN(map, KIND)                                                    \
+    {                                                                          \
+        const int* __pre = (map).prefix + (KIND) * ((map).ninst + 1);          \
+        const int __total = __pre[(map).ninst];                                \
+        for (int __vb = blockIdx.x; __vb < __total; __vb += gridDim.x) {       \
+            const int inst_id = find_inst(__pre, (map).ninst, __vb);           \
+            const Inst& I = (map).insts[inst_id];                              \
+            const int lb = __vb - __pre[inst_id];                              \
+            (void)lb;
+#define VB_END \
+        }      \
+    }
+
+template <typename T> __device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block-wide sum of a double (result valid in thread 0).  Needs blockDim.x a
+// multiple of 64 and <= 1024.
+__device__ __forceinline__ double block_sum_d(double v, double* sh)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) r += sh[i];
+    }
+    return r;
+}
+
+#endif  // TSNE_HOST_ONLY
+
+}  // namespace tsne

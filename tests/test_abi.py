@@ -1,0 +1,74 @@
+"""The C-ABI library loads and exports every entry point include/tsne.h
+declares; host-side argument checks work without a GPU (no compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tsne.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1712_09005_amd import tsne
+    if not os.path.exists(tsne.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return tsne.lib()
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tsne_\w+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ("tsne_plan_create", "tsne_repulsive", "tsne_attractive", "tsne_step",
+                 "tsne_run", "tsne_batch_tick"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    for name in declared():
+        assert hasattr(L, name), name
+
+
+def test_workspace_bytes_and_argument_checks(L):
+    from paper_1712_09005_amd import tsne
+    d = tsne.make_desc(1_000_000, 2, p=5, max_intervals=320, nnz=90_000_000)
+    nb = tsne.workspace_bytes(d)
+    assert 100 << 20 < nb < 4 << 30
+    # invalid descriptors: zero bytes
+    for kw in (dict(n=1, s=2), dict(n=100, s=3), dict(n=100, s=2, p=9),
+               dict(n=100, s=2, max_intervals=0)):
+        n = kw.pop("n")
+        s = kw.pop("s")
+        assert tsne.workspace_bytes(tsne.make_desc(n, s, **kw)) == 0
+    # 1-D plans need no 2-D FFT buffers
+    assert tsne.workspace_bytes(tsne.make_desc(10_000, 1, max_intervals=600)) < \
+        tsne.workspace_bytes(tsne.make_desc(10_000, 2, max_intervals=600))
+    # plan creation rejects a missing or misaligned workspace before any device work
+    out = ctypes.c_void_p()
+    assert L.tsne_plan_create(ctypes.byref(d), None, 0, None, ctypes.byref(out)) == 3
+    assert L.tsne_plan_create(ctypes.byref(d), ctypes.c_void_p(4096 + 8), 1 << 40, None,
+                              ctypes.byref(out)) == 3
+    bad = tsne.make_desc(100, 2, p=7)
+    assert L.tsne_plan_create(ctypes.byref(bad), ctypes.c_void_p(4096), 1 << 30, None,
+                              ctypes.byref(out)) == 2
+    assert L.tsne_status_str(4) == b"box needs more intervals than max_intervals"
+    assert L.tsne_batch_workspace_bytes(0) == 0 and L.tsne_batch_workspace_bytes(64) > 0
+
+
+def test_fft_length_ladder(L):
+    """Capacity determines the circulant length: the smallest even 2^a 3^b 5^c
+    at least twice the node count."""
+    from paper_1712_09005_amd import tsne
+    small = tsne.workspace_bytes(tsne.make_desc(5000, 1, p=5, max_intervals=100))
+    large = tsne.workspace_bytes(tsne.make_desc(5000, 1, p=5, max_intervals=1600))
+    assert large > small
+    # n_cap * 2 above the supported 16384 is refused
+    assert tsne.workspace_bytes(tsne.make_desc(5000, 1, p=6, max_intervals=2000)) == 0

@@ -1,0 +1,274 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle on the
+same seeded inputs.
+
+Tolerances (relative L2 over all N*s entries; per component where stated):
+  - FP64 mode vs the interpolation oracle (same geometry, Step 2 direct):
+    contract 1e-5; tested at 1e-9 (FFT rounding in double is ~1e-13).
+  - FP32 mode vs the interpolation oracle: 2e-5.  FP32 unit roundoff 6e-8,
+    times the cancellation in y'(d) h4 - h_{1+d} (|y'| / cluster radius, <= ~50
+    here) and the growth of FFT rounding with log M, stays below 1e-5.
+  - default settings (p = 5, interval width 0.75) vs the direct O(N^2) sum:
+    1e-3 (the accuracy target); the paper's settings of the 2,048-point check
+    (p = 3, max(50, ceil(width)) intervals) reach only ~1.6e-2 and are tested
+    at 3e-2.
+  - attraction vs oracle: 1e-6 (FP32 terms, double accumulation).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1712_09005_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def T():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1712_09005_amd import tsne
+    tsne.lib()
+    return tsne
+
+
+DEV = "cuda:0"
+
+
+def gpu_rep(T, Y, dtype=torch.float32, p=5, policy="fixed", w=0.75, min_int=1, max_int=256,
+            form="A", P=None, ppl=0):
+    n, s = Y.shape
+    plan = T.Plan(n, s, dtype, p=p, policy=policy, form=form, min_intervals=min_int,
+                  max_intervals=max_int, interval_width=w, nnz=(P.nnz if P is not None else 0),
+                  points_per_lane=ppl, device=DEV)
+    Yt = torch.from_numpy(np.ascontiguousarray(Y)).to(DEV, dtype)
+    F, Z = plan.repulsive(Yt)
+    torch.cuda.synchronize()
+    st = plan.query()
+    return plan, Yt, F.cpu().numpy().astype(np.float64), float(Z.item()), st
+
+
+def oracle_rep(Y, p, policy, w, min_int, form="A"):
+    Yd = np.asarray(Y, np.float64)
+    o, ww, m = oracle.geometry(Yd, policy, min_int, w)
+    r = oracle.interp_rep(Yd, o, ww, m, p, oracle.FORM_A if form == "A" else oracle.FORM_B,
+                          want_grids=True)
+    return (o, ww, m), r
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-9), (torch.float32, 2e-5)])
+@pytest.mark.parametrize("n", [2048, 1000, 3001])
+def test_repulsion_2d_vs_interp_oracle(T, dtype, tol, n):
+    print("case: repulsion 2-D n=%d %s" % (n, dtype), flush=True)
+    Y = inputs.mixture_embedding(n, 2, 10, -30, 30, 2.0, seed=0)
+    plan, _, F, Z, st = gpu_rep(T, Y, dtype, p=5, policy="fixed", w=0.75, max_int=128)
+    assert st["status"] == 0, st
+    (o, w, m), r = oracle_rep(Y, 5, "fixed", 0.75, 1)
+    assert st["n_int"] == m and st["w_int"] == w
+    np.testing.assert_array_equal(st["origin"], o)
+    e = rel(F, r["F"])
+    ez = abs(Z - r["Z"]) / r["Z"]
+    print("  rel err F %.3e  Z %.3e" % (e, ez))
+    assert e < tol and ez < tol
+    for d in range(2):
+        assert rel(F[:, d], r["F"][:, d]) < tol
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_grids_match_oracle(T, dtype):
+    """Charge grids W on occupied cells and potential grids V on every node."""
+    print("case: grids %s" % dtype, flush=True)
+    n = 2500
+    Y = inputs.mixture_embedding(n, 2, 6, -12, 12, 1.5, seed=5)
+    plan, _, F, Z, st = gpu_rep(T, Y, dtype, p=4, policy="paper", min_int=20, max_int=64)
+    (o, w, m), r = oracle_rep(Y, 4, "paper", 1.0, 20)
+    assert st["n_int"] == m
+    ng = m * 4
+    ncap = 64 * 4
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    Wg = np.frombuffer(plan.export(0), npdt).reshape(3, ncap, ncap)[:, :ng, :ng]
+    Vg = np.frombuffer(plan.export(1), npdt).reshape(4, ncap, ncap)[:, :ng, :ng]
+    Yd = Y.astype(np.float64)
+    cells = np.clip(np.floor((Yd - o) / w), 0, m - 1).astype(int)
+    occ = np.zeros((m, m), bool)
+    occ[cells[:, 1], cells[:, 0]] = True
+    mask = np.kron(occ, np.ones((4, 4), bool))
+    qs = 2.0 ** -(np.floor(np.log2(0.5 * m * w)) + 1)      # charge scale of the library
+    scale = np.array([1.0, qs, qs])[:, None, None]
+    tol = 1e-10 if dtype == torch.float64 else 1e-5
+    for c in range(3):
+        assert rel(Wg[c][mask], (r["W"][c] * scale[c])[mask]) < tol, c
+    vscale = np.array([1.0, 1.0, qs, qs])[:, None, None]
+    for k in range(4):
+        assert rel(Vg[k], r["V"][k] * vscale[k]) < (1e-9 if dtype == torch.float64 else 2e-5), k
+    cs = np.frombuffer(plan.export(3), np.int32)
+    counts = np.bincount(cells[:, 1] * m + cells[:, 0], minlength=m * m)
+    np.testing.assert_array_equal(np.diff(cs), counts)
+
+
+@pytest.mark.parametrize("p", [3, 4, 5])
+@pytest.mark.parametrize("form", ["A", "B"])
+def test_repulsion_p_and_form(T, p, form):
+    print("case: p=%d form %s" % (p, form), flush=True)
+    Y = inputs.mixture_embedding(1500, 2, 5, -10, 10, 1.0, seed=2)
+    _, _, F, Z, st = gpu_rep(T, Y, torch.float64, p=p, policy="paper", min_int=20, max_int=64,
+                             form=form)
+    (o, w, m), r = oracle_rep(Y, p, "paper", 1.0, 20, form)
+    assert rel(F, r["F"]) < 1e-9 and abs(Z - r["Z"]) / r["Z"] < 1e-9
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-9), (torch.float32, 2e-5)])
+@pytest.mark.parametrize("form", ["A", "B"])
+def test_repulsion_1d(T, dtype, tol, form):
+    print("case: 1-D %s %s" % (dtype, form), flush=True)
+    Y = inputs.mixture_embedding(4000, 1, 12, -60, 60, 1.5, seed=0)
+    _, _, F, Z, st = gpu_rep(T, Y, dtype, p=5, policy="fixed", w=0.75, max_int=256, form=form)
+    assert st["status"] == 0
+    (o, w, m), r = oracle_rep(Y, 5, "fixed", 0.75, 1, form)
+    assert st["n_int"] == m
+    assert rel(F, r["F"]) < tol and abs(Z - r["Z"]) / r["Z"] < tol
+
+
+def test_c1_against_direct_sum(T):
+    """The 2,048-point check: FP32 GPU against the direct O(N^2) sum, at the
+    paper's settings and at the default settings."""
+    print("case: c1 vs direct", flush=True)
+    c1 = inputs.config_inputs("c1")
+    Y, P = c1["Y"], c1["P"]
+    Fd, Zd = oracle.direct_rep(Y.astype(np.float64))
+    _, _, F, Z, st = gpu_rep(T, Y, torch.float32, p=3, policy="paper", min_int=50, max_int=128)
+    e_paper = rel(F, Fd)
+    _, _, F2, Z2, _ = gpu_rep(T, Y, torch.float32, p=5, policy="fixed", w=0.75, max_int=128)
+    e_def = rel(F2, Fd)
+    print("  paper settings %.3e (Z %.2e); default %.3e (Z %.2e)"
+          % (e_paper, abs(Z - Zd) / Zd, e_def, abs(Z2 - Zd) / Zd))
+    assert e_paper < 3e-2 and e_def < 1e-3
+    assert abs(Z2 - Zd) / Zd < 1e-4
+    for d in range(2):
+        assert rel(F2[:, d], Fd[:, d]) < 1e-3
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("lpr", [16, 32, 64])
+def test_attraction(T, dtype, lpr):
+    print("case: attraction %s lpr=%d" % (dtype, lpr), flush=True)
+    n = 3001
+    Y = inputs.mixture_embedding(n, 2, 10, -30, 30, 2.0, seed=0)
+    P = inputs.random_graph_P(n, 90, seed=1)
+    plan = T.Plan(n, 2, dtype, nnz=P.nnz, lanes_per_row=lpr, max_intervals=128, device=DEV)
+    plan.bind_P(torch.from_numpy(P.row_ptr).to(DEV), torch.from_numpy(P.col).to(DEV),
+                torch.from_numpy(P.val).to(DEV, dtype))
+    Yt = torch.from_numpy(Y).to(DEV, dtype)
+    Fa = plan.attractive(Yt).cpu().numpy()
+    Pd = inputs.CSR(P.row_ptr, P.col, P.val.astype(np.float64))
+    ref = oracle.attr(Y.astype(np.float64), Pd)
+    assert rel(Fa, ref) < (1e-6 if dtype == torch.float32 else 1e-13)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-9), (torch.float32, 1e-5)])
+def test_step_vs_oracle(T, dtype, tol):
+    """One full iteration (repulsion, attraction, update) against the oracle
+    composed step by step, in the early-exaggeration phase and after it."""
+    n = 2048
+    c1 = inputs.config_inputs("c1")
+    Y, P = c1["Y"], c1["P"]
+    plan = T.Plan(n, 2, dtype, p=5, policy="fixed", interval_width=0.75, max_intervals=128,
+                  nnz=P.nnz, device=DEV)
+    plan.bind_P(torch.from_numpy(P.row_ptr).to(DEV), torch.from_numpy(P.col).to(DEV),
+                torch.from_numpy(P.val).to(DEV, dtype))
+    rng = np.random.default_rng(3)
+    uY0 = rng.standard_normal((n, 2)) * 0.1
+    g0 = 1.0 + rng.uniform(0, 0.5, (n, 2))
+    for it in (0, 300):
+        print("case: step it=%d %s" % (it, dtype), flush=True)
+        Yt = torch.from_numpy(Y).to(DEV, dtype)
+        uY = torch.from_numpy(uY0).to(DEV, dtype)
+        gains = torch.from_numpy(g0).to(DEV, dtype)
+        sched = T.Schedule()
+        plan.step(Yt, uY, gains, sched, it)
+        torch.cuda.synchronize()
+        st = plan.query()
+        assert st["status"] == 0 and st["iter"] == it + 1
+        Yd = Y.astype(np.float64)
+        o, w, m = oracle.geometry(Yd, "fixed", 1, 0.75)
+        r = oracle.interp_rep(Yd, o, w, m, 5)
+        Fa = oracle.attr(Yd, inputs.CSR(P.row_ptr, P.col, P.val.astype(np.float64)))
+        alpha, mom = oracle.schedule(it)
+        Y1, u1, g1 = oracle.update(Yd, uY0, g0, Fa, r["F"], alpha, mom, 200.0)
+        assert rel(uY.cpu().numpy(), u1) < tol
+        assert rel(gains.cpu().numpy(), g1) < tol
+        assert rel(Yt.cpu().numpy(), Y1) < tol
+
+
+def test_run_matches_steps(T):
+    """tsne_run (graph replay, device iteration counter) against the same
+    iterations issued one tsne_step at a time."""
+    print("case: run vs steps", flush=True)
+    c1 = inputs.config_inputs("c1")
+    Y, P = c1["Y"], c1["P"]
+    n = Y.shape[0]
+    outs = []
+    for mode in ("steps", "run"):
+        plan = T.Plan(n, 2, torch.float64, p=5, interval_width=0.75, max_intervals=256,
+                      nnz=P.nnz, device=DEV)
+        plan.bind_P(torch.from_numpy(P.row_ptr).to(DEV), torch.from_numpy(P.col).to(DEV),
+                    torch.from_numpy(P.val).to(DEV, torch.float64))
+        Yt = torch.from_numpy(Y).to(DEV, torch.float64)
+        uY = torch.zeros_like(Yt)
+        gains = torch.ones_like(Yt)
+        sched = T.Schedule(ee_stop=3, mom_switch=4)
+        if mode == "steps":
+            for it in range(8):
+                plan.step(Yt, uY, gains, sched, it)
+        else:
+            plan.run(Yt, uY, gains, sched, 0, 8)
+        torch.cuda.synchronize()
+        st = plan.query()
+        assert st["status"] == 0 and st["iter"] == 8
+        outs.append(Yt.cpu().numpy())
+    assert rel(outs[1], outs[0]) < 1e-9
+
+
+def test_edge_two_points_and_coincident(T):
+    print("case: edges", flush=True)
+    Y = np.array([[0.3, -1.2], [2.1, 0.4]])
+    _, _, F, Z, st = gpu_rep(T, Y, torch.float64, p=5, policy="paper", min_int=50, max_int=64)
+    r2 = ((Y[0] - Y[1]) ** 2).sum()
+    # interpolation at 50 intervals on a 1.8-wide box is accurate to ~1e-9
+    assert abs(Z - 2 / (1 + r2)) / (2 / (1 + r2)) < 1e-7
+    np.testing.assert_allclose(F[0], (Y[0] - Y[1]) / (2 * (1 + r2)), rtol=1e-6)
+    Yc = np.full((777, 2), 3.25)
+    _, _, F, Z, st = gpu_rep(T, Yc, torch.float32, p=5, policy="paper", min_int=50, max_int=64)
+    assert st["status"] == 0
+    assert np.abs(F).max() < 1e-6 and abs(Z - 777 * 776) / (777 * 776) < 1e-3
+
+
+def test_status_capacity_and_nonfinite(T):
+    print("case: status", flush=True)
+    Y = inputs.mixture_embedding(1000, 2, 4, -40, 40, 1.0, seed=9)
+    n = 1000
+    plan = T.Plan(n, 2, torch.float32, p=3, policy="fixed", interval_width=1.0, max_intervals=16,
+                  device=DEV)
+    Yt = torch.from_numpy(Y).to(DEV)
+    F = torch.full_like(Yt, 7.0)
+    plan.repulsive(Yt, F)
+    torch.cuda.synchronize()
+    st = plan.query()
+    assert st["status"] == 4
+    assert torch.all(F == 7.0)             # nothing committed
+    assert plan.query()["status"] == 0     # cleared by the query
+    Y2 = Y.copy()
+    Y2[17, 1] = np.nan
+    plan2 = T.Plan(n, 2, torch.float32, p=3, policy="paper", min_intervals=20, max_intervals=128,
+                   device=DEV)
+    F2 = torch.full_like(Yt, 7.0)
+    plan2.repulsive(torch.from_numpy(Y2).to(DEV), F2)
+    torch.cuda.synchronize()
+    assert plan2.query()["status"] == 5
+    assert torch.all(F2 == 7.0)
