@@ -93,6 +93,17 @@ template <typename T> struct Dft<T, 5> {
     }
 };
 
+// floor(x / d) for 0 <= x < 2^24 and 0 < d < 2^15, with rd = 1/d in float:
+// the float estimate is within one of the quotient, one correction fixes it.
+__device__ __forceinline__ int fdiv(int x, int d, float rd)
+{
+    int q = (int)((float)x * rd);
+    const int r = x - q * d;
+    if (r < 0) q -= 1;
+    else if (r >= d) q += 1;
+    return q;
+}
+
 // One Stockham stage of radix R over G transforms of length M stored
 // back-to-back in buf; Ns = product of the radices of earlier stages.
 template <typename T, int R>
@@ -102,6 +113,7 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int M, int G, int Ns,
     const int Mr = M / R;
     const int nb = G * Mr;
     const int stw = M / (Ns * R);
+    const float rMr = 1.0f / (float)Mr, rNs = 1.0f / (float)Ns;
     const int nthr = blockDim.x;
     cplx<T> v[kMaxB][R];
     int dst[kMaxB];
@@ -110,16 +122,17 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int M, int G, int Ns,
         const int idx = threadIdx.x + b * nthr;
         dst[b] = -1;
         if (idx < nb) {
-            const int g = idx / Mr;
+            const int g = fdiv(idx, Mr, rMr);
             const int j = idx - g * Mr;
             const cplx<T>* src = buf + g * M;
-            const int k = j % Ns;
+            const int a = fdiv(j, Ns, rNs);
+            const int k = j - a * Ns;
 #pragma unroll
             for (int r = 0; r < R; ++r) v[b][r] = src[j + r * Mr];
 #pragma unroll
             for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[r * k * stw]);
             Dft<T, R>::run(v[b]);
-            dst[b] = g * M + (j / Ns) * Ns * R + k;
+            dst[b] = g * M + a * Ns * R + k;
         }
     }
     __syncthreads();
@@ -133,15 +146,16 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int M, int G, int Ns,
     __syncthreads();
 }
 
-// Forward transforms (exp(-2 pi i k n / M)) of G length-M sequences in LDS.
+// Forward transforms (exp(-2 pi i k n / M)) of G length-M sequences in LDS,
+// M and the radix stages being those of this iteration (Geom).
 template <typename T>
-__device__ void block_fft(cplx<T>* buf, int G, const Inst& I)
+__device__ void block_fft(cplx<T>* buf, int G, const Inst& I, const Geom& Gm)
 {
     const cplx<T>* tw = static_cast<const cplx<T>*>(I.tw);
-    const int M = I.M;
+    const int M = Gm.M;
     int Ns = 1;
-    for (int s = 0; s < I.nstages; ++s) {
-        const int R = I.radix[s];
+    for (int s = 0; s < Gm.nstages; ++s) {
+        const int R = Gm.radix[s];
         switch (R) {
         case 2: fft_stage<T, 2>(buf, M, G, Ns, tw); break;
         case 3: fft_stage<T, 3>(buf, M, G, Ns, tw); break;
@@ -178,7 +192,7 @@ __global__ __launch_bounds__(1024) void k_fft_rows(LaunchMap map)
     VB_BEGIN(map, K_FFT_ROWS)
     if (okay(I)) {
         const Geom& G = *I.geom;
-        const int n = G.n, n_int = G.n_int, M = I.M, n_cap = I.n_cap, tw_ = I.tile_w;
+        const int n = G.n, n_int = G.n_int, M = G.M, n_cap = I.n_cap, tw_ = I.tile_w;
         const int npairs = (n_cap + 1) / 2;
         const int ch = lb / npairs, j = lb - ch * npairs;
         const int ra = 2 * j, rb = 2 * j + 1;
@@ -196,10 +210,10 @@ __global__ __launch_bounds__(1024) void k_fft_rows(LaunchMap map)
                 buf[g] = {a, b};
             }
             __syncthreads();
-            block_fft<T>(buf, 1, I);
+            block_fft<T>(buf, 1, I, G);
             cplx<T>* X = static_cast<cplx<T>*>(I.X) + (int64_t)ch * I.ntiles * n_cap * tw_;
             const T hlf = (T)0.5;
-            for (int k = threadIdx.x; k < I.half; k += blockDim.x) {
+            for (int k = threadIdx.x; k < G.half; k += blockDim.x) {
                 const cplx<T> z = buf[k], zc = buf[k == 0 ? 0 : M - k];
                 const cplx<T> A = {(z.x + zc.x) * hlf, (z.y - zc.y) * hlf};
                 const cplx<T> B = {(z.y + zc.y) * hlf, (zc.x - z.x) * hlf};
@@ -221,10 +235,11 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
     VB_BEGIN(map, K_FFT_COLS)
     if (okay(I)) {
         const Geom& Gm = *I.geom;
-        const int n = Gm.n, M = I.M, n_cap = I.n_cap, tw_ = I.tile_w, half = I.half;
-        const int Gc = I.col_group;
-        const int ncg = (half + Gc - 1) / Gc;
+        const int n = Gm.n, M = Gm.M, n_cap = I.n_cap, tw_ = I.tile_w, half = Gm.half;
+        const int Gc = Gm.col_group;                   // columns per block this iteration
+        const int ncg = (I.half + I.col_group - 1) / I.col_group;   // blocks per potential
         const int pot = lb / ncg, cg = lb - pot * ncg;
+        if (cg * Gc < half) {
         int ch, kern;
         pot_of<S, FORM>(pot, ch, kern);
         const cplx<T>* X = static_cast<const cplx<T>*>(I.X) + (int64_t)ch * I.ntiles * n_cap * tw_;
@@ -239,7 +254,7 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
             buf[idx] = v;
         }
         __syncthreads();
-        block_fft<T>(buf, Gc, I);
+        block_fft<T>(buf, Gc, I, Gm);
         // multiply by the real kernel spectrum, conjugate for the inverse
         const T* sp = static_cast<const T*>(I.spec) + (int64_t)kern * half * half;
         for (int idx = threadIdx.x; idx < Gc * M; idx += blockDim.x) {
@@ -250,7 +265,7 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
             buf[idx] = {v.x * sv, -v.y * sv};
         }
         __syncthreads();
-        block_fft<T>(buf, Gc, I);
+        block_fft<T>(buf, Gc, I, Gm);
         cplx<T>* Xc = static_cast<cplx<T>*>(I.Xc) + (int64_t)pot * I.ntiles * n_cap * tw_;
         for (int idx = threadIdx.x; idx < Gc * M; idx += blockDim.x) {
             const int g = idx / M, r = idx - g * M;
@@ -261,6 +276,7 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
             }
         }
         __syncthreads();
+        }
     }
     VB_END
 }
@@ -274,7 +290,7 @@ __global__ __launch_bounds__(1024) void k_fft_irows(LaunchMap map)
     VB_BEGIN(map, K_FFT_IROWS)
     if (okay(I)) {
         const Geom& G = *I.geom;
-        const int n = G.n, M = I.M, n_cap = I.n_cap, tw_ = I.tile_w;
+        const int n = G.n, M = G.M, n_cap = I.n_cap, tw_ = I.tile_w;
         const int q = lb / n_cap, r = lb - q * n_cap;
         const int pa = 2 * q, pb = 2 * q + 1;
         if (r < n) {
@@ -293,7 +309,7 @@ __global__ __launch_bounds__(1024) void k_fft_irows(LaunchMap map)
                 buf[k] = {A.x - B.y, -(A.y + B.x)};
             }
             __syncthreads();
-            block_fft<T>(buf, 1, I);
+            block_fft<T>(buf, 1, I, G);
             T* Va = static_cast<T*>(I.V) + (int64_t)pa * n_cap * n_cap + (int64_t)r * n_cap;
             T* Vb = static_cast<T*>(I.V) + (int64_t)pb * n_cap * n_cap + (int64_t)r * n_cap;
             for (int g = threadIdx.x; g < n; g += blockDim.x) {
@@ -317,7 +333,7 @@ __global__ __launch_bounds__(1024) void k_fft_1d(LaunchMap map)
     VB_BEGIN(map, K_FFT_1D)
     if (okay(I)) {
         const Geom& G = *I.geom;
-        const int n = G.n, M = I.M, n_cap = I.n_cap, half = I.half;
+        const int n = G.n, M = G.M, n_cap = I.n_cap, half = G.half;
         const int pot = lb;
         int ch, kern;
         pot_of<1, FORM>(pot, ch, kern);
@@ -329,7 +345,7 @@ __global__ __launch_bounds__(1024) void k_fft_1d(LaunchMap map)
             buf[g] = {a, (T)0};
         }
         __syncthreads();
-        block_fft<T>(buf, 1, I);
+        block_fft<T>(buf, 1, I, G);
         const T* sp = static_cast<const T*>(I.spec) + (int64_t)kern * half;
         for (int k = threadIdx.x; k < M; k += blockDim.x) {
             const T sv = sp[k <= M - k ? k : M - k];
@@ -337,7 +353,7 @@ __global__ __launch_bounds__(1024) void k_fft_1d(LaunchMap map)
             buf[k] = {v.x * sv, -v.y * sv};
         }
         __syncthreads();
-        block_fft<T>(buf, 1, I);
+        block_fft<T>(buf, 1, I, G);
         T* Vp = static_cast<T*>(I.V) + (int64_t)pot * n_cap;
         for (int g = threadIdx.x; g < n; g += blockDim.x) Vp[g] = buf[g].x;
         __syncthreads();
@@ -345,7 +361,7 @@ __global__ __launch_bounds__(1024) void k_fft_1d(LaunchMap map)
     VB_END
 }
 
-// ---------------------------------------------------------------- kernel spectra (double)
+// ---------------------------------------------------------------- tables and kernel spectra
 
 __device__ __forceinline__ double kern_val(int kern, double r2)
 {
@@ -353,27 +369,58 @@ __device__ __forceinline__ double kern_val(int kern, double r2)
     return kern == 0 ? a : a * a;
 }
 
-// The spectra are rebuilt when the box kernel found a new node spacing (every
-// call under the paper policy, the first call under a fixed width).
-__device__ __forceinline__ bool spec_needed(const Inst& I, double& h)
+// The tables are rebuilt when the box kernel found a new node spacing or a
+// new circulant length (every call under the paper policy; under a fixed
+// width only when the ladder length changes).
+__device__ __forceinline__ bool spec_needed(const Inst& I)
 {
-    if (!okay(I)) return false;
-    h = I.geom->h;
-    return I.geom->spec_dirty != 0;
+    return okay(I) && I.geom->spec_dirty != 0;
+}
+
+// Twiddles exp(-2 pi i k / M) (element type), cos(2 pi k / M) (double) and
+// the kernel values K(h^2 (j1^2 + j0^2)) on the lag grid j <= M/2 (double).
+template <typename T, int S>
+__global__ __launch_bounds__(256) void k_spec0(LaunchMap map)
+{
+    VB_BEGIN(map, K_SPEC0)
+    if (spec_needed(I)) {
+        const Geom& G = *I.geom;
+        const int M = G.M, half = G.half;
+        const int64_t idx = (int64_t)lb * 256 + threadIdx.x;
+        if (idx < M) {
+            double sv, cv;
+            sincospi(2.0 * (double)idx / (double)M, &sv, &cv);
+            cplx<T>* tw = static_cast<cplx<T>*>(I.tw);
+            tw[idx] = {(T)cv, (T)(-sv)};
+            I.costab[idx] = cv;
+        }
+        const double h2 = G.h * G.h;
+        if (S == 2) {
+            if (idx < (int64_t)2 * half * half) {
+                const int kern = (int)(idx / ((int64_t)half * half));
+                const int rem = (int)(idx - (int64_t)kern * half * half);
+                const int j1 = rem / half, j0 = rem - j1 * half;
+                I.ktab[idx] = kern_val(kern, h2 * ((double)j1 * j1 + (double)j0 * j0));
+            }
+        } else if (idx < 2 * half) {
+            const int kern = (int)(idx / half), j = (int)(idx - (int64_t)kern * half);
+            I.ktab[idx] = kern_val(kern, h2 * (double)j * j);
+        }
+    }
+    VB_END
 }
 
 // First cosine pass.  s = 2: A[kern][j1][k0] = sum_{j0=0}^{M/2} wt(j0)
-// K(h^2 (j1^2 + j0^2)) cos(2 pi k0 j0 / M); s = 1: the whole spectrum
-// K^[kern][k] = sum_j wt(j) K(h^2 j^2) cos(2 pi k j / M) / M.
+// K(j1, j0) cos(2 pi k0 j0 / M); s = 1: the whole spectrum
+// K^[kern][k] = sum_j wt(j) K(j) cos(2 pi k j / M) / M.
 // wt = 1 at j = 0 and j = M/2, else 2 (the circulant folds j and M - j).
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_spec1(LaunchMap map)
 {
     VB_BEGIN(map, K_SPEC1)
-    double h;
-    if (spec_needed(I, h)) {
-        const int M = I.M, half = I.half, mh = M / 2;
-        const double h2 = h * h;
+    if (spec_needed(I)) {
+        const Geom& G = *I.geom;
+        const int M = G.M, half = G.half, mh = M / 2;
         const double* ct = I.costab;
         if (S == 2) {
             const int64_t idx = (int64_t)lb * 256 + threadIdx.x;
@@ -381,29 +428,29 @@ __global__ __launch_bounds__(256) void k_spec1(LaunchMap map)
                 const int kern = (int)(idx / ((int64_t)half * half));
                 const int rem = (int)(idx - (int64_t)kern * half * half);
                 const int j1 = rem / half, k0 = rem - j1 * half;
-                double acc = 0.0;
-                int ph = 0;
-                for (int j0 = 0; j0 <= mh; ++j0) {
-                    const double wt = (j0 == 0 || j0 == mh) ? 1.0 : 2.0;
-                    acc += wt * kern_val(kern, h2 * ((double)j1 * j1 + (double)j0 * j0)) * ct[ph];
+                const double* kt = I.ktab + ((int64_t)kern * half + j1) * half;
+                double acc = 0.5 * (kt[0] + kt[mh] * ct[(int)(((int64_t)k0 * mh) % M)]);
+                int ph = k0;
+                for (int j0 = 1; j0 < mh; ++j0) {
+                    acc += kt[j0] * ct[ph];
                     ph += k0;
                     if (ph >= M) ph -= M;
                 }
-                I.spec_tmp[idx] = acc;
+                I.spec_tmp[idx] = 2.0 * acc;
             }
         } else {
             const int idx = lb * 256 + threadIdx.x;
             if (idx < 2 * half) {
                 const int kern = idx / half, k = idx - kern * half;
-                double acc = 0.0;
-                int ph = 0;
-                for (int j = 0; j <= mh; ++j) {
-                    const double wt = (j == 0 || j == mh) ? 1.0 : 2.0;
-                    acc += wt * kern_val(kern, h2 * (double)j * j) * ct[ph];
+                const double* kt = I.ktab + (int64_t)kern * half;
+                double acc = 0.5 * (kt[0] + kt[mh] * ct[(int)(((int64_t)k * mh) % M)]);
+                int ph = k;
+                for (int j = 1; j < mh; ++j) {
+                    acc += kt[j] * ct[ph];
                     ph += k;
                     if (ph >= M) ph -= M;
                 }
-                static_cast<T*>(I.spec)[idx] = (T)(acc / M);
+                static_cast<T*>(I.spec)[idx] = (T)(2.0 * acc / M);
             }
         }
     }
@@ -416,9 +463,9 @@ template <typename T, int S>
 __global__ __launch_bounds__(256) void k_spec2(LaunchMap map)
 {
     VB_BEGIN(map, K_SPEC2)
-    double h;
-    if (S == 2 && spec_needed(I, h)) {
-        const int M = I.M, half = I.half, mh = M / 2;
+    if (S == 2 && spec_needed(I)) {
+        const Geom& G = *I.geom;
+        const int M = G.M, half = G.half, mh = M / 2;
         const int64_t idx = (int64_t)lb * 256 + threadIdx.x;
         if (idx < (int64_t)2 * half * half) {
             const int kern = (int)(idx / ((int64_t)half * half));
@@ -426,15 +473,14 @@ __global__ __launch_bounds__(256) void k_spec2(LaunchMap map)
             const int k0 = rem / half, k1 = rem - k0 * half;
             const double* A = I.spec_tmp + (int64_t)kern * half * half;
             const double* ct = I.costab;
-            double acc = 0.0;
-            int ph = 0;
-            for (int j1 = 0; j1 <= mh; ++j1) {
-                const double wt = (j1 == 0 || j1 == mh) ? 1.0 : 2.0;
-                acc += wt * A[(int64_t)j1 * half + k0] * ct[ph];
+            double acc = 0.5 * (A[k0] + A[(int64_t)mh * half + k0] * ct[(int)(((int64_t)k1 * mh) % M)]);
+            int ph = k1;
+            for (int j1 = 1; j1 < mh; ++j1) {
+                acc += A[(int64_t)j1 * half + k0] * ct[ph];
                 ph += k1;
                 if (ph >= M) ph -= M;
             }
-            static_cast<T*>(I.spec)[idx] = (T)(acc / ((double)M * (double)M));
+            static_cast<T*>(I.spec)[idx] = (T)(2.0 * acc / ((double)M * (double)M));
         }
     }
     VB_END
@@ -480,6 +526,7 @@ static hipError_t fft_go(int kind, const LaunchMap& map, const Launch& l, hipStr
             hipLaunchKernelGGL((k_fft_1d<T, P, FORM>), g, b, l.lds, st, map);
         }
         break;
+    case K_SPEC0: hipLaunchKernelGGL((k_spec0<T, S>), g, b, 0, st, map); break;
     case K_SPEC1: hipLaunchKernelGGL((k_spec1<T, S>), g, b, 0, st, map); break;
     case K_SPEC2: hipLaunchKernelGGL((k_spec2<T, S>), g, b, 0, st, map); break;
     default: return hipErrorInvalidValue;

@@ -19,46 +19,22 @@ template <typename T> __device__ __forceinline__ T ld(const void* p, int64_t i)
     return static_cast<const T*>(p)[i];
 }
 
-__device__ __forceinline__ double aload(const double* p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void astore(double* p, double v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Returns true in every thread of the block that finishes last among the
-// nblocks blocks sharing this ticket.  Writes made before the call by any of
-// those blocks are visible to the last block afterwards.
-__device__ __forceinline__ bool last_block(unsigned* ticket, unsigned nblocks, int* flag)
-{
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL,
-                                            __HIP_MEMORY_SCOPE_AGENT);
-        *flag = (t == nblocks - 1);
-    }
-    __syncthreads();
-    const bool last = *flag != 0;
-    if (last) __threadfence();
-    return last;
-}
-
 // Interval of a coordinate value and its local coordinate:
 // u = (y - o) / w, l = clamp(floor(u), 0, n_int - 1), t = u - l.
+// Evaluated in double for both element types: the input value is exact in
+// double, so the interval is the same in every kernel and t carries no error
+// from the box offset (FP32 t would lose |u| * 2^-24 absolute).
 template <typename T>
-__device__ __forceinline__ int locate(T y, T o, T w, int n_int, T& t)
+__device__ __forceinline__ int locate(T y, double o, double w, int n_int, T& t)
 {
 #pragma clang fp contract(off)
-    const T u = (y - o) / w;
-    const T f = floor(u);
+    const double u = ((double)y - o) / w;
+    const double f = floor(u);
     int c;
-    if (!(f >= (T)0)) c = 0;
-    else if (f > (T)(n_int - 1)) c = n_int - 1;
+    if (!(f >= 0.0)) c = 0;
+    else if (f > (double)(n_int - 1)) c = n_int - 1;
     else c = (int)f;
-    t = u - (T)c;
+    t = (T)(u - (double)c);
     return c;
 }
 
@@ -102,6 +78,7 @@ __global__ void k_set_args(Inst* inst, CallArgs a)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     if (a.set_ptrs) {
+        inst->counting = a.counting;
         inst->Yin = a.Yin;
         inst->Y = a.Y;
         inst->uY = a.uY;
@@ -128,16 +105,14 @@ hipError_t launch_set_args(Inst* inst, const CallArgs& a, hipStream_t st)
 
 // ---------------------------------------------------------------- a1: box geometry
 
-// Square box (Section 2.4) with per-dimension origin at the minimum; interval
-// count by the policy (paper: max(min, ceil(L)) as in Section 2.5; fixed:
-// constant width).  Also the mean (recentring) and the status checks.
+// Per-block partial min / max / sum of the coordinates (double) and a
+// non-finite flag.  The geometry kernel reduces them.
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_box(LaunchMap map)
 {
     __shared__ double sh[4][8];
-    __shared__ int flag;
     VB_BEGIN(map, K_BOX)
-    if (live(I)) {
+    if (live_pre(I)) {
         const T* Y = static_cast<const T*>(I.Yin);
         const int64_t n = I.n;
         const int nb = I.nb_box;
@@ -155,7 +130,6 @@ __global__ __launch_bounds__(256) void k_box(LaunchMap map)
                 sm[d] += v;
             }
         }
-        // wave then block reduction: slots [lo0 lo1 hi0 hi1 sm0 sm1 bad]
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
 #pragma unroll
@@ -178,51 +152,113 @@ __global__ __launch_bounds__(256) void k_box(LaunchMap map)
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            for (int w = 1; w < 4; ++w)
-                for (int d = 0; d < S; ++d) {
-                    sh[0][d] = fmin(sh[0][d], sh[w][d]);
-                    sh[0][2 + d] = fmax(sh[0][2 + d], sh[w][2 + d]);
-                    sh[0][4 + d] += sh[w][4 + d];
-                }
-            for (int w = 1; w < 4; ++w) sh[0][6] = fmax(sh[0][6], sh[w][6]);
-            for (int k = 0; k < 7; ++k) astore(&I.box_part[(int64_t)lb * 8 + k], sh[0][k]);
+            double* out = I.box_part + (int64_t)lb * 8;
+            for (int d = 0; d < S; ++d) {
+                out[d] = fmin(fmin(sh[0][d], sh[1][d]), fmin(sh[2][d], sh[3][d]));
+                out[2 + d] = fmax(fmax(sh[0][2 + d], sh[1][2 + d]), fmax(sh[2][2 + d], sh[3][2 + d]));
+                out[4 + d] = ((sh[0][4 + d] + sh[1][4 + d]) + sh[2][4 + d]) + sh[3][4 + d];
+            }
+            out[6] = fmax(fmax(sh[0][6], sh[1][6]), fmax(sh[2][6], sh[3][6]));
         }
-        if (last_block(&I.tickets[0], (unsigned)nb, &flag)) {
-            if (threadIdx.x == 0) {
-                double glo[2] = {INFINITY, INFINITY}, ghi[2] = {-INFINITY, -INFINITY};
-                double gsm[2] = {0.0, 0.0}, gbad = 0.0;
-                for (int b = 0; b < nb; ++b) {
-                    const double* pp = I.box_part + (int64_t)b * 8;
-                    for (int d = 0; d < S; ++d) {
-                        glo[d] = fmin(glo[d], aload(pp + d));
-                        ghi[d] = fmax(ghi[d], aload(pp + 2 + d));
-                        gsm[d] += aload(pp + 4 + d);
-                    }
-                    gbad = fmax(gbad, aload(pp + 6));
-                }
-                Geom& G = *I.geom;
-                int st = 0;
-                double L = 0.0;
-                for (int d = 0; d < S; ++d) {
-                    G.origin[d] = glo[d];
-                    if (ghi[d] - glo[d] > L) L = ghi[d] - glo[d];
-                    G.mean[d] = gsm[d] / (double)n;
-                }
-                if (gbad != 0.0) st = ST_NONFINITE;
-                if (L < 1e-6) L = 1e-6;
-                int m;
-                double w;
-                if (I.policy == 0) {
-                    m = (int)fmin(ceil(L), 2.0e9);
-                    if (m < I.min_int) m = I.min_int;
-                    w = L / m;
-                } else {
-                    w = I.interval_width;
-                    m = (int)fmin(ceil(L / w), 2.0e9);
-                    if (m < I.min_int) m = I.min_int;
-                }
-                if (st == 0 && m > I.max_int) st = ST_CAPACITY;
-                if (st != 0) m = I.max_int;   // keep sizes in range for the skipped kernels
+    }
+    VB_END
+}
+
+// Smallest even M >= lo whose prime factors are 2, 3 and 5.
+__device__ __forceinline__ int ladder(int lo)
+{
+    int M = lo + (lo & 1);
+    for (;; M += 2) {
+        int r = M;
+        while (r % 2 == 0) r /= 2;
+        while (r % 3 == 0) r /= 3;
+        while (r % 5 == 0) r /= 5;
+        if (r == 1) return M;
+    }
+}
+
+// One block per instance: reduce the box partials, decide the iteration
+// (status checks, iteration counter) and its geometry.  Square box (Section
+// 2.4) with the origin at the per-dimension minimum; interval count by the
+// policy (paper: max(min, ceil(L)) as in Section 2.5; fixed: constant width);
+// circulant length M from the 2-3-5 ladder with hysteresis, so the tables are
+// rebuilt only when the node count leaves [M/3, M/2].
+template <int S>
+__global__ __launch_bounds__(256) void k_geom(LaunchMap map)
+{
+    __shared__ double sh[4][8];
+    VB_BEGIN(map, K_GEOM)
+    Geom& G = *I.geom;
+    const bool run = live_pre(I);
+    if (run) {
+        const int nb = I.nb_box;
+        double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
+        double sm[2] = {0.0, 0.0}, bad = 0.0;
+        for (int b = threadIdx.x; b < nb; b += 256) {
+            const double* pp = I.box_part + (int64_t)b * 8;
+            for (int d = 0; d < S; ++d) {
+                lo[d] = fmin(lo[d], pp[d]);
+                hi[d] = fmax(hi[d], pp[2 + d]);
+                sm[d] += pp[4 + d];
+            }
+            bad = fmax(bad, pp[6]);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+            for (int d = 0; d < S; ++d) {
+                lo[d] = fmin(lo[d], __shfl_xor(lo[d], o, 64));
+                hi[d] = fmax(hi[d], __shfl_xor(hi[d], o, 64));
+                sm[d] += __shfl_xor(sm[d], o, 64);
+            }
+            bad = fmax(bad, __shfl_xor(bad, o, 64));
+        }
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        if (lane == 0) {
+            for (int d = 0; d < S; ++d) {
+                sh[wv][d] = lo[d];
+                sh[wv][2 + d] = hi[d];
+                sh[wv][4 + d] = sm[d];
+            }
+            sh[wv][6] = bad;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double glo[2], ghi[2], gsm[2];
+            for (int d = 0; d < S; ++d) {
+                glo[d] = fmin(fmin(sh[0][d], sh[1][d]), fmin(sh[2][d], sh[3][d]));
+                ghi[d] = fmax(fmax(sh[0][2 + d], sh[1][2 + d]), fmax(sh[2][2 + d], sh[3][2 + d]));
+                gsm[d] = ((sh[0][4 + d] + sh[1][4 + d]) + sh[2][4 + d]) + sh[3][4 + d];
+            }
+            const double gbad = fmax(fmax(sh[0][6], sh[1][6]), fmax(sh[2][6], sh[3][6]));
+            int st = 0;
+            double L = 0.0;
+            for (int d = 0; d < S; ++d) {
+                G.origin[d] = glo[d];
+                if (ghi[d] - glo[d] > L) L = ghi[d] - glo[d];
+                G.mean[d] = gsm[d] / (double)I.n;
+            }
+            if (gbad != 0.0) st = ST_NONFINITE;
+            if (L < 1e-6) L = 1e-6;
+            int m;
+            double w;
+            if (I.policy == 0) {
+                m = (int)fmin(ceil(L), 2.0e9);
+                if (m < I.min_int) m = I.min_int;
+                w = L / m;
+            } else {
+                w = I.interval_width;
+                m = (int)fmin(ceil(L / w), 2.0e9);
+                if (m < I.min_int) m = I.min_int;
+            }
+            if (st == 0 && m > I.max_int) st = ST_CAPACITY;
+            if (st != 0) {
+                *I.status = st;            // latched; the iteration is not committed
+                G.active = 0;
+            } else {
+                G.active = 1;
+                G.it = *I.iter;
+                if (I.counting) *I.iter = G.it + 1;
                 G.side = L;
                 G.w = w;
                 G.inv_w = 1.0 / w;
@@ -232,38 +268,81 @@ __global__ __launch_bounds__(256) void k_box(LaunchMap map)
                 G.n_cells = (S == 2) ? m * m : m;
                 for (int d = 0; d < S; ++d) G.centre[d] = G.origin[d] + 0.5 * m * w;
                 // power-of-two charge scale: |(y - centre) * qscale| < 1
-                const double halfside = 0.5 * m * w;
-                G.qscale = ldexp(1.0, -(ilogb(halfside) + 1));
-                G.spec_dirty = (G.h != G.spec_h) ? 1 : 0;
+                G.qscale = ldexp(1.0, -(ilogb(0.5 * m * w) + 1));
+                // circulant length with hysteresis
+                int M = G.M;
+                const int want = ladder(2 * G.n);
+                if (M < 2 * G.n || M > I.M || want * 3 < M * 2) M = want;
+                if (M > I.M) M = I.M;
+                if (M != G.M) {
+                    int r = M, k = 0, n2 = 0, n3 = 0, n5 = 0;
+                    while (r % 2 == 0) { r /= 2; ++n2; }
+                    while (r % 3 == 0) { r /= 3; ++n3; }
+                    while (r % 5 == 0) { r /= 5; ++n5; }
+                    for (int q = 0; q < n2 / 2; ++q) G.radix[k++] = 4;
+                    if (n2 & 1) G.radix[k++] = 2;
+                    for (int q = 0; q < n3; ++q) G.radix[k++] = 3;
+                    for (int q = 0; q < n5; ++q) G.radix[k++] = 5;
+                    G.nstages = k;
+                    G.M = M;
+                    G.half = M / 2 + 1;
+                    // columns per block: as many as the LDS holds (power of two)
+                    const int csz = 2 * ((I.tile_w == 16) ? 4 : 8);
+                    int g = I.tile_w;
+                    while (g > 1 && (int64_t)g * M * csz > I.col_lds) g >>= 1;
+                    G.col_group = g;
+                }
+                G.spec_dirty = (G.h != G.spec_h || G.M != G.spec_M) ? 1 : 0;
                 G.spec_h = G.h;
-                if (st != 0)
-                    __hip_atomic_store(I.status, st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&I.tickets[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                G.spec_M = G.M;
+                G.pbuf ^= 1;                   // this iteration's sorted order goes here
             }
         }
+    } else if (threadIdx.x == 0) {
+        G.active = 0;
     }
     VB_END
 }
 
 // ---------------------------------------------------------------- a2: binning
 
-// Cell key of each point and its rank among the points of that cell (the
+// Cell key of each point and its rank among the points of its cell (the
 // "for each interval" loops of Algorithm 1 become a counting sort by cell).
+// Points are visited in the previous iteration's sorted order, so neighbouring
+// lanes mostly share a cell: each run of equal keys in a wave takes its ranks
+// with one atomic.  key/rank are stored by visit position.
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_key(LaunchMap map)
 {
     VB_BEGIN(map, K_KEY)
     if (live(I)) {
-        const int64_t i = (int64_t)lb * 256 + threadIdx.x;
-        if (i < I.n) {
-            const Geom& G = *I.geom;
+        const Geom& G = *I.geom;
+        const int64_t pos = (int64_t)lb * 256 + threadIdx.x;
+        const int lane = threadIdx.x & 63;
+        const bool valid = pos < I.n;
+        int key = -1;
+        int i = 0;
+        if (valid) {
+            const int* prev = I.perm + (int64_t)(G.pbuf ^ 1) * I.n;
+            i = G.perm_valid ? prev[pos] : (int)pos;
             const T* Y = static_cast<const T*>(I.Yin);
-            const T w = (T)G.w;
             T t;
-            int key = locate<T>(Y[i * S], (T)G.origin[0], w, G.n_int, t);
-            if (S == 2) key += G.n_int * locate<T>(Y[i * S + 1], (T)G.origin[1], w, G.n_int, t);
-            I.key[i] = key;
-            I.rank[i] = atomicAdd(&I.counts[key], 1);
+            key = locate<T>(Y[(int64_t)i * S], G.origin[0], G.w, G.n_int, t);
+            if (S == 2) key += G.n_int * locate<T>(Y[(int64_t)i * S + 1], G.origin[1], G.w, G.n_int, t);
+        }
+        const int kprev = __shfl_up(key, 1, 64);
+        const bool head = (lane == 0) || (kprev != key);
+        const unsigned long long hm = __ballot(head);
+        const unsigned long long upto = (lane == 63) ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+        const int run_start = 63 - __clzll(hm & upto);
+        const unsigned long long above = (lane == 63) ? 0ull : (hm >> (lane + 1));
+        const int run_end = (above == 0ull) ? 63 : lane + __ffsll((long long)above) - 1;
+        int base = 0;
+        if (valid && head) base = atomicAdd(&I.counts[key], run_end - run_start + 1);
+        base = __shfl(base, run_start, 64);
+        if (valid) {
+            I.key[pos] = key;
+            I.rank[pos] = base + (lane - run_start);
         }
     }
     VB_END
@@ -381,20 +460,24 @@ __global__ __launch_bounds__(256) void k_scan_b(LaunchMap map)
     VB_END
 }
 
-// Scatter: sorted position of every point; sorted copy of Y.
+// Scatter: this iteration's sorted order and sorted copy of Y.
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_scatter(LaunchMap map)
 {
     VB_BEGIN(map, K_SCATTER)
     if (live(I)) {
-        const int64_t i = (int64_t)lb * 256 + threadIdx.x;
-        if (i < I.n) {
-            const int pos = I.cell_start[I.key[i]] + I.rank[i];
-            I.perm[pos] = (int)i;
+        const Geom& G = *I.geom;
+        const int64_t pos = (int64_t)lb * 256 + threadIdx.x;
+        if (pos < I.n) {
+            const int* prev = I.perm + (int64_t)(G.pbuf ^ 1) * I.n;
+            int* cur = I.perm + (int64_t)G.pbuf * I.n;
+            const int i = G.perm_valid ? prev[pos] : (int)pos;
+            const int np_ = I.cell_start[I.key[pos]] + I.rank[pos];
+            cur[np_] = i;
             const T* Y = static_cast<const T*>(I.Yin);
             T* sY = static_cast<T*>(I.sY);
 #pragma unroll
-            for (int d = 0; d < S; ++d) sY[(int64_t)pos * S + d] = Y[i * S + d];
+            for (int d = 0; d < S; ++d) sY[(int64_t)np_ * S + d] = Y[(int64_t)i * S + d];
         }
     }
     VB_END
@@ -432,27 +515,26 @@ __global__ __launch_bounds__(256) void k_spread(LaunchMap map)
             const int b = I.cell_start[c] + (t - fi) * I.kpts;
             const int e = min(b + I.kpts, I.cell_start[c + 1]);
             const T* sY = static_cast<const T*>(I.sY);
-            const T w = (T)G.w, qs = (T)G.qscale;
-            const T o0 = (T)G.origin[0], o1 = (T)G.origin[S - 1];
-            const T c0 = (T)G.centre[0], c1 = (T)G.centre[S - 1];
+            const double w = G.w, qs = G.qscale;
+            const double o0 = G.origin[0], o1 = G.origin[S - 1];
+            const double c0 = G.centre[0], c1 = G.centre[S - 1];
             for (int pos = b; pos < e; ++pos) {
                 T q[NC];
                 T tx, ty = (T)0;
                 const T yx = sY[(int64_t)pos * S];
                 locate<T>(yx, o0, w, n_int, tx);
+                // centred, power-of-two scaled charges, rounded once from double
+                const double qx = ((double)yx - c0) * qs;
+                double qy = 0.0;
                 q[0] = (T)1;
-                q[1] = (yx - c0) * qs;
-                T yy = (T)0;
+                q[1] = (T)qx;
                 if (S == 2) {
-                    yy = sY[(int64_t)pos * S + 1];
+                    const T yy = sY[(int64_t)pos * S + 1];
                     locate<T>(yy, o1, w, n_int, ty);
-                    q[2] = (yy - c1) * qs;
+                    qy = ((double)yy - c1) * qs;
+                    q[2] = (T)qy;
                 }
-                if (FORM == 1) {
-                    T r2 = q[1] * q[1];
-                    if (S == 2) r2 += q[2] * q[2];
-                    q[NC - 1] = r2;
-                }
+                if (FORM == 1) q[NC - 1] = (T)(qx * qx + qy * qy);
                 T Lx[P];
                 lagrange<T, P>(tx, Lx);
                 if (S == 2) {
@@ -589,7 +671,6 @@ __global__ __launch_bounds__(256) void k_gather(LaunchMap map)
 {
     constexpr int NP = S + 2;
     __shared__ double sh[8];
-    __shared__ int flag;
     VB_BEGIN(map, K_GATHER)
     if (live(I)) {
         const Geom& G = *I.geom;
@@ -599,13 +680,13 @@ __global__ __launch_bounds__(256) void k_gather(LaunchMap map)
             const int n_int = G.n_int, n_cap = I.n_cap;
             const T* sY = static_cast<const T*>(I.sY);
             const T* V = static_cast<const T*>(I.V);
-            const T w = (T)G.w, qs = (T)G.qscale;
+            const double w = G.w, qs = G.qscale;
             T yv[2], tl[2];
             int cl[2] = {0, 0};
 #pragma unroll
             for (int d = 0; d < S; ++d) {
                 yv[d] = sY[pos * S + d];
-                cl[d] = locate<T>(yv[d], (T)G.origin[d], w, n_int, tl[d]);
+                cl[d] = locate<T>(yv[d], G.origin[d], w, n_int, tl[d]);
             }
             T Lx[P], Ly[P];
             lagrange<T, P>(tl[0], Lx);
@@ -633,41 +714,54 @@ __global__ __launch_bounds__(256) void k_gather(LaunchMap map)
             }
             // potentials: phi[1] = K2*1, phi[2+d] = K2*(y'(d) qs); phi[0] = K1*1 (A)
             // or K2*(|y'|^2 qs^2) (B)
-            T yc[2];
-            T r2c = (T)0;
+            // assembly in double: the numerator y'(d) h4 - h_{1+d} cancels
+            double yc[2];
+            double r2c = 0.0;
 #pragma unroll
             for (int d = 0; d < S; ++d) {
-                yc[d] = yv[d] - (T)G.centre[d];
+                yc[d] = (double)yv[d] - G.centre[d];
                 r2c += yc[d] * yc[d];
             }
-            const T inv_qs = (T)1 / qs;
-            T h1;
+            const double inv_qs = 1.0 / qs;
+            double h1;
             if (FORM == 0) {
-                h1 = phi[0];
+                h1 = (double)phi[0];
             } else {
-                T dot = (T)0;
+                double dot = 0.0;
 #pragma unroll
-                for (int d = 0; d < S; ++d) dot += yc[d] * phi[2 + d];
-                h1 = ((T)1 + r2c) * phi[1] - (T)2 * dot * inv_qs + phi[0] * inv_qs * inv_qs;
+                for (int d = 0; d < S; ++d) dot += yc[d] * (double)phi[2 + d];
+                h1 = (1.0 + r2c) * (double)phi[1] - 2.0 * dot * inv_qs +
+                     (double)phi[0] * inv_qs * inv_qs;
             }
-            const int i = I.perm[pos];
+            const int i = I.perm[(int64_t)G.pbuf * I.n + pos];
             T* R = static_cast<T*>(I.R);
 #pragma unroll
-            for (int d = 0; d < S; ++d) R[(int64_t)i * S + d] = yc[d] * phi[1] - phi[2 + d] * inv_qs;
-            h1d = (double)h1;
+            for (int d = 0; d < S; ++d)
+                R[(int64_t)i * S + d] = (T)(yc[d] * (double)phi[1] - (double)phi[2 + d] * inv_qs);
+            h1d = h1;
         }
         const double bs = block_sum_d(h1d, sh);
-        if (threadIdx.x == 0) astore(&I.z_part[lb], bs);
-        if (last_block(&I.tickets[1], (unsigned)I.nb_gather, &flag)) {
-            double z = 0.0;
-            for (int b = threadIdx.x; b < I.nb_gather; b += 256) z += aload(&I.z_part[b]);
-            z = block_sum_d(z, sh);
-            if (threadIdx.x == 0) {
-                z -= (double)I.n;      // self pairs: K1(0) = 1 per point
-                I.geom->Z = z;
-                if (I.Zout) *I.Zout = z;
-                __hip_atomic_store(&I.tickets[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
+        if (threadIdx.x == 0) I.z_part[lb] = bs;
+    }
+    VB_END
+}
+
+// One block per instance: Z = sum_i h1_i - N (the self pairs, K1(0) = 1),
+// from the gather's block partials in a fixed order.  Also marks the sorted
+// order of this iteration as available to the next one.
+__global__ __launch_bounds__(256) void k_zsum(LaunchMap map)
+{
+    __shared__ double sh[8];
+    VB_BEGIN(map, K_ZSUM)
+    if (live(I)) {
+        double z = 0.0;
+        for (int b = threadIdx.x; b < I.nb_gather; b += 256) z += I.z_part[b];
+        z = block_sum_d(z, sh);
+        if (threadIdx.x == 0) {
+            z -= (double)I.n;
+            I.geom->Z = z;
+            I.geom->perm_valid = 1;
+            if (I.Zout) *I.Zout = z;
         }
     }
     VB_END
@@ -690,37 +784,61 @@ __global__ __launch_bounds__(256) void k_norm(LaunchMap map)
 
 // ---------------------------------------------------------------- a9: attraction
 
+template <typename T, int S> struct Vec;
+template <> struct Vec<float, 1> { typedef float t; };
+template <> struct Vec<float, 2> { typedef float2 t; };
+template <> struct Vec<double, 1> { typedef double t; };
+template <> struct Vec<double, 2> { typedef double2 t; };
+
+template <typename V> __device__ __forceinline__ double cx(const V& v) { return (double)v.x; }
+template <> __device__ __forceinline__ double cx<float>(const float& v) { return (double)v; }
+template <> __device__ __forceinline__ double cx<double>(const double& v) { return v; }
+
 // F_attr,i = sum_j p_ij (y_i - y_j) / (1 + |y_i - y_j|^2) over row i of the CSR
-// P (Section 3).  LPR lanes per row stride over the row's non-zeros; each
-// lane accumulates in double, then the lanes of the row are reduced.
-template <typename T, int S, int LPR>
+// P (Section 3).  LPR lanes per row; each lane takes U non-zeros per round and
+// issues all their loads (column, value, then the neighbours' positions as one
+// vector load each) before using them.  Terms in the element type, sums in
+// double, then a reduction over the row's lanes.
+template <typename T, int S, int LPR, bool GATED>
 __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
 {
-    VB_BEGIN(map, K_ATTR)
-    if (live(I)) {
+    constexpr int U = 4;
+    typedef typename Vec<T, S>::t V;
+    VB_BEGIN(map, GATED ? K_ATTR : K_ATTR_ALL)
+    if (!GATED || live(I)) {
         constexpr int RPB = 256 / LPR;
         const int64_t i = (int64_t)lb * RPB + threadIdx.x / LPR;
         const int sub = threadIdx.x % LPR;
         double f0 = 0.0, f1 = 0.0;
-        const T* Y = static_cast<const T*>(I.Yin);
+        const V* Y = static_cast<const V*>(I.Yin);
         if (i < I.n) {
             const T* val = static_cast<const T*>(I.val);
-            const T yi0 = Y[i * S];
-            const T yi1 = (S == 2) ? Y[i * S + 1] : (T)0;
+            const V yi = Y[i];
+            T yi0, yi1 = (T)0;
+            if constexpr (S == 2) { yi0 = yi.x; yi1 = yi.y; } else { yi0 = yi; }
             const int64_t e = I.row_ptr[i + 1];
-            for (int64_t k = I.row_ptr[i] + sub; k < e; k += LPR) {
-                const int64_t j = I.col[k];
-                const T p = val[k];
-                const T d0 = yi0 - Y[j * S];
-                T r2 = d0 * d0;
-                T d1 = (T)0;
-                if (S == 2) {
-                    d1 = yi1 - Y[j * S + 1];
-                    r2 += d1 * d1;
+            for (int64_t k0 = I.row_ptr[i] + sub; k0 < e; k0 += (int64_t)LPR * U) {
+                int jj[U];
+                T pp[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t k = k0 + (int64_t)u * LPR;
+                    const bool ok = k < e;
+                    jj[u] = ok ? I.col[k] : (int)i;
+                    pp[u] = ok ? val[k] : (T)0;
                 }
-                const T wgt = p / ((T)1 + r2);
-                f0 += (double)(wgt * d0);
-                if (S == 2) f1 += (double)(wgt * d1);
+                V yj[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) yj[u] = Y[jj[u]];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    T d0, d1 = (T)0;
+                    if constexpr (S == 2) { d0 = yi0 - yj[u].x; d1 = yi1 - yj[u].y; }
+                    else { d0 = yi0 - yj[u]; }
+                    const T wgt = pp[u] / ((T)1 + d0 * d0 + d1 * d1);
+                    f0 += (double)(wgt * d0);
+                    if (S == 2) f1 += (double)(wgt * d1);
+                }
             }
         }
 #pragma unroll
@@ -748,21 +866,19 @@ __device__ __forceinline__ void sched_at(const Sched& sc, int it, double& alpha,
 }
 
 // grad = 4 (alpha F_attr - F_rep); gains, momentum, step; recentring by the
-// mean of the Y the forces were computed on.  The last block advances the
-// device iteration counter.
+// mean of the Y the forces were computed on.  The schedule is indexed by the
+// iteration the geometry kernel assigned.
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_update(LaunchMap map)
 {
-    __shared__ int flag;
     VB_BEGIN(map, K_UPDATE)
     if (live(I)) {
-        const int it = *I.iter;
+        const Geom& G = *I.geom;
         const Sched& sc = *I.sched;
         double alpha, mom;
-        sched_at(sc, it, alpha, mom);
+        sched_at(sc, G.it, alpha, mom);
         const int64_t i = (int64_t)lb * 256 + threadIdx.x;
         if (i < I.n) {
-            const Geom& G = *I.geom;
             const T invz = (T)(1.0 / G.Z);
             T* Y = static_cast<T*>(I.Y);
             T* uY = static_cast<T*>(I.uY);
@@ -782,13 +898,6 @@ __global__ __launch_bounds__(256) void k_update(LaunchMap map)
                 uY[k] = un;
                 const T y = sc.recentre ? (Y[k] - (T)G.mean[d]) : Y[k];
                 Y[k] = y + un;
-            }
-        }
-        const unsigned nb = (unsigned)((I.n + 255) / 256);
-        if (last_block(&I.tickets[2], nb, &flag)) {
-            if (threadIdx.x == 0) {
-                *I.iter = it + 1;
-                __hip_atomic_store(&I.tickets[2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
     }
@@ -814,11 +923,20 @@ static hipError_t launch_pts(int kind, const Cfg& c, const LaunchMap& map, const
     case K_SPREAD: hipLaunchKernelGGL((k_spread<T, S, P, FORM>), g, b, 0, st, map); break;
     case K_FIX: hipLaunchKernelGGL((k_spread_fix<T, S, P, FORM>), g, b, 0, st, map); break;
     case K_GATHER: hipLaunchKernelGGL((k_gather<T, S, P, FORM>), g, b, 0, st, map); break;
+    case K_GEOM: hipLaunchKernelGGL((k_geom<S>), g, b, 0, st, map); break;
+    case K_ZSUM: hipLaunchKernelGGL(k_zsum, g, b, 0, st, map); break;
     case K_NORM: hipLaunchKernelGGL((k_norm<T, S>), g, b, 0, st, map); break;
     case K_ATTR:
-        if (c.lpr == 16) hipLaunchKernelGGL((k_attr<T, S, 16>), g, b, 0, st, map);
-        else if (c.lpr == 32) hipLaunchKernelGGL((k_attr<T, S, 32>), g, b, 0, st, map);
-        else hipLaunchKernelGGL((k_attr<T, S, 64>), g, b, 0, st, map);
+        if (c.lpr == 8) hipLaunchKernelGGL((k_attr<T, S, 8, true>), g, b, 0, st, map);
+        else if (c.lpr == 16) hipLaunchKernelGGL((k_attr<T, S, 16, true>), g, b, 0, st, map);
+        else if (c.lpr == 32) hipLaunchKernelGGL((k_attr<T, S, 32, true>), g, b, 0, st, map);
+        else hipLaunchKernelGGL((k_attr<T, S, 64, true>), g, b, 0, st, map);
+        break;
+    case K_ATTR_ALL:
+        if (c.lpr == 8) hipLaunchKernelGGL((k_attr<T, S, 8, false>), g, b, 0, st, map);
+        else if (c.lpr == 16) hipLaunchKernelGGL((k_attr<T, S, 16, false>), g, b, 0, st, map);
+        else if (c.lpr == 32) hipLaunchKernelGGL((k_attr<T, S, 32, false>), g, b, 0, st, map);
+        else hipLaunchKernelGGL((k_attr<T, S, 64, false>), g, b, 0, st, map);
         break;
     case K_UPDATE: hipLaunchKernelGGL((k_update<T, S>), g, b, 0, st, map); break;
     default: return hipErrorInvalidValue;
@@ -858,7 +976,7 @@ hipError_t launch_kind(int kind, const Cfg& c, const LaunchMap& map, const Launc
     if (l.grid <= 0) return hipSuccess;
     switch (kind) {
     case K_FFT_ROWS: case K_FFT_COLS: case K_FFT_IROWS: case K_FFT_1D:
-    case K_SPEC1: case K_SPEC2:
+    case K_SPEC0: case K_SPEC1: case K_SPEC2:
         return launch_fft_kind(kind, c, map, l, st);
     default:
         return c.dtype == 0 ? pts_s<float>(kind, c, map, l, st) : pts_s<double>(kind, c, map, l, st);

@@ -36,6 +36,7 @@ struct CallArgs {
     int iter_end;
     int set_sched;  // write *sched
     Sched sched;
+    int counting;   // geometry kernel advances the iteration counter
 };
 
 // Grid geometry of one launch.

@@ -72,7 +72,7 @@ struct Layout {
 enum Region {
     R_INST, R_PREFIX, R_GEOM, R_SCHED, R_SMALL, R_BOX, R_COUNTS, R_CSTART, R_ISTART, R_SCAN,
     R_ICELL, R_KEY, R_RANK, R_PERM, R_SY, R_CARRY, R_W, R_X, R_XC, R_V, R_SPEC, R_TW, R_COS,
-    R_SPECTMP, R_R, R_FA, R_ZPART, R_N
+    R_SPECTMP, R_KTAB, R_R, R_FA, R_ZPART, R_N
 };
 
 struct Derived {
@@ -98,8 +98,8 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     if (d->min_intervals < 1 || d->max_intervals < d->min_intervals) return TSNE_E_ARG;
     if (d->policy == TSNE_GRID_FIXED && !(d->interval_width > 0.0)) return TSNE_E_ARG;
     if (d->nnz < 0 || d->nnz > (int64_t)INT_MAX * 8) return TSNE_E_ARG;
-    if (d->lanes_per_row != 0 && d->lanes_per_row != 16 && d->lanes_per_row != 32 &&
-        d->lanes_per_row != 64)
+    if (d->lanes_per_row != 0 && d->lanes_per_row != 8 && d->lanes_per_row != 16 &&
+        d->lanes_per_row != 32 && d->lanes_per_row != 64)
         return TSNE_E_ARG;
     if (d->points_per_lane != 0 && (d->points_per_lane < 1 || d->points_per_lane > 64))
         return TSNE_E_ARG;
@@ -119,6 +119,9 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     o.half = o.M / 2 + 1;
     o.nstages = radix_plan(o.M, o.radix, &o.rmin);
     if (o.nstages < 0) return TSNE_E_UNSUPPORTED;
+    // the device picks a smaller ladder length when the box is smaller; any of
+    // them may have a radix-2 stage, so thread counts assume the smallest radix
+    o.rmin = 2;
     o.ncell_cap = (d->s == 2) ? o.max_int * o.max_int : o.max_int;
     o.kpts = d->points_per_lane ? d->points_per_lane : 8;
     o.lpr = d->lanes_per_row ? d->lanes_per_row : 32;
@@ -134,17 +137,15 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     o.row_threads = std::max(256, pow2_at_least(need_row));
     if (o.row_threads > 1024) return TSNE_E_UNSUPPORTED;
     o.row_lds = (size_t)o.M * csz;
-    o.col_group = 1;
-    for (int g = o.tile_w; g >= 1; g >>= 1) {
-        if ((size_t)g * o.M * csz <= 96 * 1024 && cdiv((int64_t)g * o.M, (int64_t)o.rmin * kMaxBfly) <= 1024) {
-            o.col_group = g;
-            break;
-        }
-    }
-    o.col_threads = std::max(256, pow2_at_least(cdiv((int64_t)o.col_group * o.M, (int64_t)o.rmin * kMaxBfly)));
+    // column kernel: LDS for as many columns as fit in 96 KB (at least one);
+    // each iteration packs G = (largest power of two) columns of its own M
+    o.col_lds = std::min<size_t>((size_t)o.tile_w * o.M * csz, 96 * 1024);
+    o.col_lds = std::max<size_t>(o.col_lds, (size_t)o.M * csz);
+    o.col_group = 1;                                   // columns per block at capacity
+    while (o.col_group < o.tile_w && (size_t)(2 * o.col_group) * o.M * csz <= o.col_lds) o.col_group *= 2;
+    o.col_threads = std::max(256, pow2_at_least(cdiv((int64_t)(o.col_lds / csz), (int64_t)o.rmin * kMaxBfly)));
     if (o.col_threads > 1024) return TSNE_E_UNSUPPORTED;
-    o.col_lds = (size_t)o.col_group * o.M * csz;
-    if (o.row_lds > 160 * 1024) return TSNE_E_UNSUPPORTED;
+    if (o.row_lds > 160 * 1024 || o.col_lds > 160 * 1024) return TSNE_E_UNSUPPORTED;
 
     o.nb_box = std::min(512, std::max(1, cdiv(n, 256 * 4)));
     o.nb_gather = cdiv(n, 256);
@@ -165,14 +166,19 @@ tsne_status derive(const tsne_desc* d, Derived& o)
         vb[K_FFT_IROWS] = cdiv(o.np, 2) * o.n_cap;
         vb[K_SPEC1] = cdiv((int64_t)2 * o.half * o.half, 256);
         vb[K_SPEC2] = vb[K_SPEC1];
+        vb[K_SPEC0] = cdiv(std::max<int64_t>(o.M, (int64_t)2 * o.half * o.half), 256);
     } else {
         vb[K_FFT_1D] = o.np;
         vb[K_SPEC1] = cdiv(2 * o.half, 256);
+        vb[K_SPEC0] = cdiv(std::max(o.M, 2 * o.half), 256);
     }
     vb[K_GATHER] = o.nb_gather;
     vb[K_NORM] = cdiv(n * d->s, 256);
     vb[K_ATTR] = d->nnz > 0 ? cdiv(n, 256 / o.lpr) : 0;
+    vb[K_ATTR_ALL] = vb[K_ATTR];
     vb[K_UPDATE] = cdiv(n, 256);
+    vb[K_GEOM] = 1;
+    vb[K_ZSUM] = 1;
 
     // workspace layout
     const int64_t grid = (d->s == 2) ? (int64_t)o.n_cap * o.n_cap : o.n_cap;
@@ -191,7 +197,7 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     sz[R_ICELL] = sizeof(int) * o.items_cap;
     sz[R_KEY] = sizeof(int) * n;
     sz[R_RANK] = sizeof(int) * n;
-    sz[R_PERM] = sizeof(int) * n;
+    sz[R_PERM] = sizeof(int) * 2 * n;
     sz[R_SY] = (size_t)o.tsz * n * d->s;
     sz[R_CARRY] = (size_t)o.tsz * 2 * o.nwaves * nn * o.nc;
     sz[R_W] = (size_t)o.tsz * o.nc * grid;
@@ -200,11 +206,13 @@ tsne_status derive(const tsne_desc* d, Derived& o)
         sz[R_XC] = (size_t)csz * o.np * o.ntiles * o.n_cap * o.tile_w;
         sz[R_SPEC] = (size_t)o.tsz * 2 * o.half * o.half;
         sz[R_SPECTMP] = sizeof(double) * 2 * (size_t)o.half * o.half;
+        sz[R_KTAB] = sizeof(double) * 2 * (size_t)o.half * o.half;
     } else {
         sz[R_X] = 0;
         sz[R_XC] = 0;
         sz[R_SPEC] = (size_t)o.tsz * 2 * o.half;
         sz[R_SPECTMP] = 0;
+        sz[R_KTAB] = sizeof(double) * 2 * (size_t)o.half;
     }
     sz[R_V] = (size_t)o.tsz * o.np * grid;
     sz[R_TW] = (size_t)csz * o.M;
@@ -232,6 +240,10 @@ Launch launch_of(int kind, const Derived& o, int vblocks)
 {
     Launch l{std::min(vblocks, kGridCap), 256, 0};
     switch (kind) {
+    case K_SPEC0: case K_SPEC1: case K_SPEC2:
+        // usually idle (tables unchanged): few blocks, each loops when there is work
+        l.grid = std::min(vblocks, 512);
+        break;
     case K_FFT_ROWS: case K_FFT_IROWS: case K_FFT_1D:
         l.block = o.row_threads;
         l.lds = o.row_lds;
@@ -260,11 +272,27 @@ struct tsne_plan {
     int* dprefix;
     Cfg cfg;
     bool P_bound;
-    bool spec_built;
     bool graph_ok;
     hipGraphExec_t gexec;
     hipGraph_t graph;
+    bool args_valid;        // last_args mirrors the device record's pointers
+    CallArgs last_args;
 };
+
+// Enqueue the per-call pointer update unless the device record already holds
+// exactly these pointers.
+static tsne_status set_ptrs(tsne_plan* pl, const CallArgs& a)
+{
+    if (pl->args_valid && a.Yin == pl->last_args.Yin && a.Y == pl->last_args.Y &&
+        a.uY == pl->last_args.uY && a.gains == pl->last_args.gains &&
+        a.Frep == pl->last_args.Frep && a.Zout == pl->last_args.Zout &&
+        a.Fattr == pl->last_args.Fattr && a.counting == pl->last_args.counting)
+        return TSNE_OK;
+    if (!hip_ok(launch_set_args(pl->dinst, a, pl->st))) return TSNE_E_HIP;
+    pl->last_args = a;
+    pl->args_valid = true;
+    return TSNE_OK;
+}
 
 static tsne_status enqueue(tsne_plan* pl, int kind)
 {
@@ -275,21 +303,23 @@ static tsne_status enqueue(tsne_plan* pl, int kind)
     return hip_ok(launch_kind(kind, pl->cfg, map, l, pl->st)) ? TSNE_OK : TSNE_E_HIP;
 }
 
+// Kernel order of one repulsion.  The table kernels (K_SPEC*) always run;
+// they return at once unless the box kernel found a new spacing or length.
+static const int kChain2[] = {K_BOX, K_GEOM, K_SPEC0, K_SPEC1, K_SPEC2, K_KEY, K_SCAN_A,
+                              K_SCAN_B, K_SCATTER, K_SPREAD, K_FIX, K_FFT_ROWS, K_FFT_COLS,
+                              K_FFT_IROWS, K_GATHER, K_ZSUM};
+static const int kChain1[] = {K_BOX, K_GEOM, K_SPEC0, K_SPEC1, K_KEY, K_SCAN_A, K_SCAN_B,
+                              K_SCATTER, K_SPREAD, K_FIX, K_FFT_1D, K_GATHER, K_ZSUM};
+
 static tsne_status enqueue_repulsion(tsne_plan* pl, bool normalise)
 {
-    static const int chain2[] = {K_BOX, K_SPEC1, K_SPEC2, K_KEY, K_SCAN_A, K_SCAN_B, K_SCATTER,
-                                 K_SPREAD, K_FIX, K_FFT_ROWS, K_FFT_COLS, K_FFT_IROWS, K_GATHER};
-    static const int chain1[] = {K_BOX, K_SPEC1, K_KEY, K_SCAN_A, K_SCAN_B, K_SCATTER,
-                                 K_SPREAD, K_FIX, K_FFT_1D, K_GATHER};
-    const int* ch = (pl->d.s == 2) ? chain2 : chain1;
-    const int nk = (pl->d.s == 2) ? (int)(sizeof(chain2) / sizeof(int)) : (int)(sizeof(chain1) / sizeof(int));
-    const bool spec = (pl->d.policy == TSNE_GRID_PAPER) || !pl->spec_built;
+    const int* ch = (pl->d.s == 2) ? kChain2 : kChain1;
+    const int nk = (pl->d.s == 2) ? (int)(sizeof(kChain2) / sizeof(int))
+                                  : (int)(sizeof(kChain1) / sizeof(int));
     for (int k = 0; k < nk; ++k) {
-        if ((ch[k] == K_SPEC1 || ch[k] == K_SPEC2) && !spec) continue;
         tsne_status s = enqueue(pl, ch[k]);
         if (s != TSNE_OK) return s;
     }
-    pl->spec_built = true;
     if (normalise) return enqueue(pl, K_NORM);
     return TSNE_OK;
 }
@@ -359,8 +389,8 @@ tsne_status tsne_plan_create(const tsne_desc* desc, void* workspace, size_t byte
     pl->ws = static_cast<char*>(workspace);
     pl->cfg = cfg_of(*desc, o);
     pl->P_bound = false;
-    pl->spec_built = false;
     pl->graph_ok = false;
+    pl->args_valid = false;
 
     char* b = pl->ws;
     const size_t* off = o.L.off;
@@ -384,10 +414,9 @@ tsne_status tsne_plan_create(const tsne_desc* desc, void* workspace, size_t byte
     h.kpts = o.kpts;
     h.lpr = o.lpr;
     h.col_group = o.col_group;
+    h.col_lds = (int)o.col_lds;
     h.tile_w = o.tile_w;
     h.ntiles = o.ntiles;
-    h.nstages = o.nstages;
-    for (int i = 0; i < o.nstages; ++i) h.radix[i] = o.radix[i];
     h.interval_width = desc->interval_width;
     h.iter_end = INT_MAX;
     h.geom = reinterpret_cast<Geom*>(b + off[R_GEOM]);
@@ -414,6 +443,7 @@ tsne_status tsne_plan_create(const tsne_desc* desc, void* workspace, size_t byte
     h.tw = b + off[R_TW];
     h.costab = reinterpret_cast<double*>(b + off[R_COS]);
     h.spec_tmp = reinterpret_cast<double*>(b + off[R_SPECTMP]);
+    h.ktab = reinterpret_cast<double*>(b + off[R_KTAB]);
     h.R = b + off[R_R];
     h.Fa_ws = b + off[R_FA];
     h.z_part = reinterpret_cast<double*>(b + off[R_ZPART]);
@@ -430,29 +460,9 @@ tsne_status tsne_plan_create(const tsne_desc* desc, void* workspace, size_t byte
         prefix[2 * k] = 0;
         prefix[2 * k + 1] = o.vb[k];
     }
-    std::vector<double> costab(o.M);
-    std::vector<char> tw((size_t)o.M * 2 * o.tsz);
-    const double two_pi = 6.283185307179586476925286766559;
-    for (int k = 0; k < o.M; ++k) {
-        const double a = two_pi * (double)k / (double)o.M;
-        const double c = std::cos(a), s = -std::sin(a);
-        costab[k] = c;
-        if (o.tsz == 4) {
-            float* t = reinterpret_cast<float*>(tw.data());
-            t[2 * k] = (float)c;
-            t[2 * k + 1] = (float)s;
-        } else {
-            double* t = reinterpret_cast<double*>(tw.data());
-            t[2 * k] = c;
-            t[2 * k + 1] = s;
-        }
-    }
     hipStream_t st = pl->st;
     bool ok = hip_ok(hipMemcpyAsync(pl->dinst, &h, sizeof(Inst), hipMemcpyHostToDevice, st)) &&
               hip_ok(hipMemcpyAsync(pl->dprefix, prefix.data(), prefix.size() * sizeof(int),
-                                    hipMemcpyHostToDevice, st)) &&
-              hip_ok(hipMemcpyAsync(h.tw, tw.data(), tw.size(), hipMemcpyHostToDevice, st)) &&
-              hip_ok(hipMemcpyAsync(h.costab, costab.data(), costab.size() * sizeof(double),
                                     hipMemcpyHostToDevice, st)) &&
               hip_ok(hipMemsetAsync(b + off[R_GEOM], 0, sizeof(Geom), st)) &&
               hip_ok(hipMemsetAsync(b + off[R_SCHED], 0, sizeof(Sched), st)) &&
@@ -517,7 +527,8 @@ tsne_status tsne_repulsive(tsne_plan* pl, const void* Y, void* F_rep, double* Z)
     a.Frep = F_rep;
     a.Zout = Z;
     a.Fattr = pl->h.Fa_ws;
-    if (!hip_ok(launch_set_args(pl->dinst, a, pl->st))) return TSNE_E_HIP;
+    tsne_status s = set_ptrs(pl, a);
+    if (s != TSNE_OK) return s;
     return enqueue_repulsion(pl, true);
 }
 
@@ -529,8 +540,9 @@ tsne_status tsne_attractive(tsne_plan* pl, const void* Y, void* F_attr)
     a.set_ptrs = 1;
     a.Yin = Y;
     a.Fattr = F_attr;
-    if (!hip_ok(launch_set_args(pl->dinst, a, pl->st))) return TSNE_E_HIP;
-    return enqueue(pl, K_ATTR);
+    tsne_status s = set_ptrs(pl, a);
+    if (s != TSNE_OK) return s;
+    return enqueue(pl, K_ATTR_ALL);
 }
 
 static tsne_status step_args(tsne_plan* pl, void* Y, void* uY, void* gains, const tsne_sched* sc,
@@ -547,7 +559,11 @@ static tsne_status step_args(tsne_plan* pl, void* Y, void* uY, void* gains, cons
     fill_sched(a.sched, sc);
     a.set_iter = 1;
     a.iter = iter;
-    return hip_ok(launch_set_args(pl->dinst, a, pl->st)) ? TSNE_OK : TSNE_E_HIP;
+    a.counting = 1;
+    if (!hip_ok(launch_set_args(pl->dinst, a, pl->st))) return TSNE_E_HIP;
+    pl->last_args = a;
+    pl->args_valid = true;
+    return TSNE_OK;
 }
 
 static tsne_status enqueue_iteration(tsne_plan* pl)
@@ -584,8 +600,8 @@ tsne_status tsne_run(tsne_plan* pl, void* Y, void* uY, void* gains, const tsne_s
     if (n_iter == 0) return TSNE_OK;
     tsne_status s = step_args(pl, Y, uY, gains, sc, iter0);
     if (s != TSNE_OK) return s;
-    // the first iteration runs eagerly (it builds the kernel spectra under the
-    // fixed policy); the rest replay a captured graph of one iteration
+    // the first iteration runs eagerly, the rest replay a captured graph of one
+    // iteration (the device iteration counter selects the schedule)
     s = enqueue_iteration(pl);
     if (s != TSNE_OK || n_iter == 1) return s;
     if (pl->st == nullptr) {
@@ -631,7 +647,7 @@ tsne_status tsne_query(tsne_plan* pl, tsne_stats* out)
     out->iter = small[1];
     out->n_int = g.n_int;
     out->n_nodes = g.n;
-    out->fft_len = pl->o.M;
+    out->fft_len = g.M;
     out->max_intervals = pl->d.max_intervals;
     out->origin[0] = g.origin[0];
     out->origin[1] = g.origin[1];
@@ -699,8 +715,6 @@ struct tsne_batch {
     Launch launch[K_NKINDS];
     Cfg cfg;
     bool dirty;
-    bool spec_pending;
-    bool any_paper;
     bool graph_ok;
     hipGraph_t graph;
     hipGraphExec_t gexec;
@@ -729,7 +743,6 @@ static tsne_status batch_refresh(tsne_batch* b)
         if (b->slots[i].used) b->live.push_back(i);
     const int nl = (int)b->live.size();
     b->prefix_host.assign((size_t)K_NKINDS * (nl + 1), 0);
-    b->any_paper = false;
     for (int k = 0; k < K_NKINDS; ++k) {
         b->launch[k] = Launch{0, 256, 0};
     }
@@ -737,7 +750,6 @@ static tsne_status batch_refresh(tsne_batch* b)
         tsne_plan* pl = b->slots[b->live[j]].plan;
         if (!hip_ok(hipMemcpyAsync(b->dtable + j, pl->dinst, sizeof(Inst), hipMemcpyDeviceToDevice, b->st)))
             return TSNE_E_HIP;
-        if (pl->d.policy == TSNE_GRID_PAPER) b->any_paper = true;
         for (int k = 0; k < K_NKINDS; ++k) {
             int* pre = b->prefix_host.data() + (size_t)k * (nl + 1);
             pre[j + 1] = pre[j] + pl->o.vb[k];
@@ -760,20 +772,15 @@ static tsne_status batch_refresh(tsne_batch* b)
     return TSNE_OK;
 }
 
-static tsne_status batch_enqueue_tick(tsne_batch* b, bool with_spec)
+static tsne_status batch_enqueue_tick(tsne_batch* b)
 {
     const int nl = (int)b->live.size();
     LaunchMap map{b->dtable, b->dprefix, nl};
-    static const int chain2[] = {K_BOX, K_SPEC1, K_SPEC2, K_KEY, K_SCAN_A, K_SCAN_B, K_SCATTER,
-                                 K_SPREAD, K_FIX, K_FFT_ROWS, K_FFT_COLS, K_FFT_IROWS, K_GATHER,
-                                 K_ATTR, K_UPDATE};
-    static const int chain1[] = {K_BOX, K_SPEC1, K_KEY, K_SCAN_A, K_SCAN_B, K_SCATTER, K_SPREAD,
-                                 K_FIX, K_FFT_1D, K_GATHER, K_ATTR, K_UPDATE};
-    const int* ch = (b->s == 2) ? chain2 : chain1;
-    const int nk = (b->s == 2) ? (int)(sizeof(chain2) / sizeof(int)) : (int)(sizeof(chain1) / sizeof(int));
-    for (int i = 0; i < nk; ++i) {
-        const int k = ch[i];
-        if ((k == K_SPEC1 || k == K_SPEC2) && !with_spec) continue;
+    const int* ch = (b->s == 2) ? kChain2 : kChain1;
+    const int nk = (b->s == 2) ? (int)(sizeof(kChain2) / sizeof(int))
+                               : (int)(sizeof(kChain1) / sizeof(int));
+    for (int i = 0; i <= nk + 1; ++i) {
+        const int k = (i < nk) ? ch[i] : (i == nk ? K_ATTR : K_UPDATE);
         if (b->launch[k].grid <= 0) continue;
         if (!hip_ok(launch_kind(k, b->cfg, map, b->launch[k], b->st))) return TSNE_E_HIP;
     }
@@ -812,8 +819,6 @@ tsne_status tsne_batch_create(int32_t max_slots, int32_t s, int32_t dtype, int32
     b->dprefix = reinterpret_cast<int*>(b->ws + batch_table_bytes(max_slots));
     b->slots.assign(max_slots, Slot{false, nullptr});
     b->dirty = true;
-    b->spec_pending = false;
-    b->any_paper = false;
     b->graph_ok = false;
     b->cfg = Cfg{dtype, s, p, form, 32};
     *out = b;
@@ -862,7 +867,6 @@ tsne_status tsne_batch_admit(tsne_batch* b, const tsne_desc* desc, void* plan_ws
     pl->h.iter_end = iter0 + n_iter;
     b->slots[free_id] = Slot{true, pl};
     b->dirty = true;
-    b->spec_pending = true;
     *slot = free_id;
     return TSNE_OK;
 }
@@ -876,24 +880,16 @@ tsne_status tsne_batch_tick(tsne_batch* b, int32_t n_ticks)
     }
     if (b->live.empty() || n_ticks == 0) return TSNE_OK;
     int t = 0;
-    if (b->spec_pending || b->st == nullptr) {
-        // first tick after an admission builds the new slots' spectra eagerly
-        tsne_status s = batch_enqueue_tick(b, true);
-        if (s != TSNE_OK) return s;
-        b->spec_pending = false;
-        ++t;
-        if (b->st == nullptr) {
-            for (; t < n_ticks; ++t) {
-                s = batch_enqueue_tick(b, b->any_paper);
-                if (s != TSNE_OK) return s;
-            }
-            return TSNE_OK;
+    if (b->st == nullptr) {
+        for (; t < n_ticks; ++t) {
+            tsne_status s = batch_enqueue_tick(b);
+            if (s != TSNE_OK) return s;
         }
+        return TSNE_OK;
     }
-    if (t >= n_ticks) return TSNE_OK;
     if (!b->graph_ok) {
         if (!hip_ok(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal))) return TSNE_E_HIP;
-        tsne_status cs = batch_enqueue_tick(b, b->any_paper);
+        tsne_status cs = batch_enqueue_tick(b);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(b->st, &g);
         if (cs != TSNE_OK || e != hipSuccess || !g) {

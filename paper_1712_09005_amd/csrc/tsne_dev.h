@@ -23,7 +23,7 @@ constexpr int kWave = 64;
 enum Kind : int {
     K_ARGS = 0, K_BOX, K_KEY, K_SCAN_A, K_SCAN_B, K_SCATTER, K_SPREAD, K_FIX,
     K_FFT_ROWS, K_FFT_COLS, K_FFT_IROWS, K_FFT_1D, K_GATHER, K_NORM, K_ATTR,
-    K_UPDATE, K_SPEC1, K_SPEC2, K_NKINDS
+    K_UPDATE, K_SPEC0, K_SPEC1, K_SPEC2, K_GEOM, K_ZSUM, K_ATTR_ALL, K_NKINDS
 };
 
 // Status bits latched on the device (values of tsne_status).
@@ -43,9 +43,18 @@ struct Geom {
     int n_int;         // intervals per dimension
     int n;             // nodes per dimension, n_int * p
     int n_cells;       // n_int^s
-    int spec_dirty;    // node spacing changed: spectra must be rebuilt
+    int active;        // this iteration runs (set by the geometry kernel)
+    int it;            // absolute index of this iteration
+    int pbuf;          // which permutation buffer holds this iteration's sorted order
+    int perm_valid;    // a sorted order from an earlier iteration exists
+    int spec_dirty;    // spacing or FFT length changed: tables must be rebuilt
     double spec_h;     // spacing the current spectra were built for
-    int pad[2];
+    int spec_M;        // FFT length the current tables were built for
+    int M;             // circulant length of this iteration (even, 2-3-5 smooth, >= 2n)
+    int half;          // M / 2 + 1
+    int nstages;
+    int radix[kMaxStages];
+    int col_group;     // FFT columns per block this iteration
 };
 
 struct Sched {
@@ -58,13 +67,13 @@ struct Inst {
     int64_t n;
     int64_t nnz;
     int s, p, form, nc, np, policy;
-    int min_int, max_int, n_cap, M, half;      // half = M/2 + 1
+    int min_int, max_int, n_cap, M, half;      // capacity: largest M, M/2 + 1
     int ncell_cap, items_cap, kpts, lpr;
     int col_group, tile_w, ntiles;              // FFT column kernel grouping
-    int nstages;
-    int radix[kMaxStages];
     double interval_width;
     int iter_end;                               // iterations stop at this index
+    int counting;                               // the geometry kernel advances *iter
+    int col_lds;                                // LDS bytes of the FFT column kernel
 
     // ---- caller buffers (set per call by k_set_args)
     const void* Yin;       // positions read by repulsion / attraction
@@ -92,7 +101,7 @@ struct Inst {
     int* item_cell;        // [items_cap]
     int* key;              // [n]
     int* rank;             // [n]
-    int* perm;             // [n] sorted position -> point
+    int* perm;             // [2][n] sorted position -> point (double buffered)
     void* sY;              // [n][s] sorted positions
     void* carry;           // [2 * nwaves][1 + p^s * nc] spread carries
     void* W;               // [nc][n_cap][n_cap] (s = 2) or [nc][n_cap]
@@ -100,9 +109,10 @@ struct Inst {
     void* Xc;              // [np][ntiles][n_cap][tile_w] complex (after columns)
     void* V;               // [np][n_cap][n_cap] or [np][n_cap]
     void* spec;            // [2][half][half] (s = 2) or [2][half], pre-scaled
-    void* tw;              // [M] complex roots exp(-2 pi i k / M)
+    void* tw;              // [M] complex roots exp(-2 pi i k / M) of this iteration's M
     double* costab;        // [M] cos(2 pi k / M) in double
-    double* spec_tmp;      // [half][half] first cosine pass (double)
+    double* spec_tmp;      // [2][half][half] first cosine pass (double)
+    double* ktab;          // [2][half][half] kernel values on the lag grid (double)
     void* R;               // [n][s] unnormalised repulsion numerators
     void* Fa_ws;           // [n][s] attraction (workspace copy for the step)
     double* z_part;        // [nb_gather]
@@ -130,13 +140,16 @@ __device__ __forceinline__ int find_inst(const int* __restrict__ pre, int ninst,
     return lo;
 }
 
-// The instance takes part in this iteration: no latched status and its
-// iteration counter has not reached iter_end.
-__device__ __forceinline__ bool live(const Inst& I)
+// Before the geometry kernel: no latched status and the iteration counter
+// has not reached iter_end.
+__device__ __forceinline__ bool live_pre(const Inst& I)
 {
-    return __hip_atomic_load(I.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
-           __hip_atomic_load(I.iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < I.iter_end;
+    return *I.status == 0 && *I.iter < I.iter_end;
 }
+
+// After the geometry kernel: this iteration runs (written once per iteration
+// by the geometry kernel; later kernels only read it).
+__device__ __forceinline__ bool live(const Inst& I) { return I.geom->active != 0; }
 
 // Iterate over this launch's virtual blocks of kernel kind K:
 //   VB_LOOP(map, K) { const Inst& I = ...; int lb = ...; ... }
