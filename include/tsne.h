@@ -89,8 +89,11 @@ typedef struct {
     int32_t max_intervals;   /* capacity: the largest N_int the plan holds */
     double interval_width;   /* w for TSNE_GRID_FIXED (> 0); ignored otherwise */
     int64_t nnz;             /* non-zeros of P; 0 if attraction is not used */
-    int32_t lanes_per_row;   /* CSR lanes per row: 0 (auto), 16, 32 or 64 */
-    int32_t points_per_lane; /* spreading points per lane: 0 (auto), 4..32 */
+    int32_t lanes_per_row;   /* CSR lanes per row: 0 (auto), 8, 16, 32 or 64 */
+    int32_t points_per_lane; /* spreading points per lane: 0 (auto), 1..64 */
+    int32_t attr_slabs;      /* column slabs of P for the attraction: 0 (auto: each
+                                slab's positions ~2 MB, so they stay in L2), 1..64 */
+    int32_t reserved;        /* must be 0 */
 } tsne_desc;
 
 /* Descent schedule, indexed by the absolute iteration it:
@@ -147,8 +150,10 @@ tsne_status tsne_plan_destroy(tsne_plan* plan);
 
 /* Bind the sparse symmetric P in CSR form (Section 3): row_ptr int64 [n+1]
  * (row_ptr[0] = 0, row_ptr[n] = desc.nnz), col int32 [nnz], val [nnz] of the
- * plan's dtype.  Preconditions (not checked on the device): symmetric, zero
- * diagonal, sum of values 1, columns in [0, n). */
+ * plan's dtype.  Checked on the host (synchronous; TSNE_E_ARG on failure):
+ * row_ptr monotone from 0 to nnz, columns in [0, n) and increasing within each
+ * row.  Not checked: symmetry, zero diagonal, sum of values 1.  Also builds the
+ * per-row slab split table in the workspace. */
 tsne_status tsne_bind_P(tsne_plan* plan, const int64_t* row_ptr,
                         const int32_t* col, const void* val);
 

@@ -382,8 +382,8 @@ __device__ __forceinline__ bool spec_needed(const Inst& I)
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_spec0(LaunchMap map)
 {
-    VB_BEGIN(map, K_SPEC0)
-    if (spec_needed(I)) {
+    VB_BEGIN_IF(map, K_SPEC0, spec_needed(I))
+    {
         const Geom& G = *I.geom;
         const int M = G.M, half = G.half;
         const int64_t idx = (int64_t)lb * 256 + threadIdx.x;
@@ -417,8 +417,8 @@ __global__ __launch_bounds__(256) void k_spec0(LaunchMap map)
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_spec1(LaunchMap map)
 {
-    VB_BEGIN(map, K_SPEC1)
-    if (spec_needed(I)) {
+    VB_BEGIN_IF(map, K_SPEC1, spec_needed(I))
+    {
         const Geom& G = *I.geom;
         const int M = G.M, half = G.half, mh = M / 2;
         const double* ct = I.costab;
@@ -462,8 +462,8 @@ __global__ __launch_bounds__(256) void k_spec1(LaunchMap map)
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_spec2(LaunchMap map)
 {
-    VB_BEGIN(map, K_SPEC2)
-    if (S == 2 && spec_needed(I)) {
+    VB_BEGIN_IF(map, K_SPEC2, S == 2 && spec_needed(I))
+    {
         const Geom& G = *I.geom;
         const int M = G.M, half = G.half, mh = M / 2;
         const int64_t idx = (int64_t)lb * 256 + threadIdx.x;

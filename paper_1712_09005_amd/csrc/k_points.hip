@@ -795,29 +795,37 @@ template <> __device__ __forceinline__ double cx<float>(const float& v) { return
 template <> __device__ __forceinline__ double cx<double>(const double& v) { return v; }
 
 // F_attr,i = sum_j p_ij (y_i - y_j) / (1 + |y_i - y_j|^2) over row i of the CSR
-// P (Section 3).  LPR lanes per row; each lane takes U non-zeros per round and
-// issues all their loads (column, value, then the neighbours' positions as one
-// vector load each) before using them.  Terms in the element type, sums in
-// double, then a reduction over the row's lanes.
+// P (Section 3).  The columns are split into slabs of slab_w points so that
+// the positions one slab gathers stay resident in every XCD's L2; virtual
+// blocks run slab-major, each row's slab range comes from the split table
+// (rows are column-sorted), and each slab writes a partial force.  LPR lanes
+// per row; each lane takes U non-zeros per round and issues all their loads
+// (column, value, then the neighbours' positions as one vector load each)
+// before using them.  Terms in the element type, sums in double.
 template <typename T, int S, int LPR, bool GATED>
 __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
 {
     constexpr int U = 4;
+    constexpr int RPB = 256 / LPR;
     typedef typename Vec<T, S>::t V;
-    VB_BEGIN(map, GATED ? K_ATTR : K_ATTR_ALL)
-    if (!GATED || live(I)) {
-        constexpr int RPB = 256 / LPR;
-        const int64_t i = (int64_t)lb * RPB + threadIdx.x / LPR;
+    VB_BEGIN_IF(map, GATED ? K_ATTR : K_ATTR_ALL, (!GATED || live(I)))
+    {
+        const int64_t n = I.n;
+        const int nrb = (int)((n + RPB - 1) / RPB);
+        const int slab = lb / nrb, rb = lb - slab * nrb;
+        const int64_t i = (int64_t)rb * RPB + threadIdx.x / LPR;
         const int sub = threadIdx.x % LPR;
         double f0 = 0.0, f1 = 0.0;
         const V* Y = static_cast<const V*>(I.Yin);
-        if (i < I.n) {
+        if (i < n) {
             const T* val = static_cast<const T*>(I.val);
             const V yi = Y[i];
             T yi0, yi1 = (T)0;
             if constexpr (S == 2) { yi0 = yi.x; yi1 = yi.y; } else { yi0 = yi; }
-            const int64_t e = I.row_ptr[i + 1];
-            for (int64_t k0 = I.row_ptr[i] + sub; k0 < e; k0 += (int64_t)LPR * U) {
+            const int64_t b = (slab == 0) ? I.row_ptr[i] : (int64_t)I.split[(int64_t)(slab - 1) * n + i];
+            const int64_t e = (slab == I.slabs - 1) ? I.row_ptr[i + 1]
+                                                     : (int64_t)I.split[(int64_t)slab * n + i];
+            for (int64_t k0 = b + sub; k0 < e; k0 += (int64_t)LPR * U) {
                 int jj[U];
                 T pp[U];
 #pragma unroll
@@ -846,10 +854,29 @@ __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
             f0 += __shfl_xor(f0, o, 64);
             if (S == 2) f1 += __shfl_xor(f1, o, 64);
         }
-        if (i < I.n && sub == 0) {
-            T* F = static_cast<T*>(I.Fattr);
+        if (i < n && sub == 0) {
+            T* F = (I.slabs == 1) ? static_cast<T*>(I.Fattr)
+                                  : static_cast<T*>(I.Fap) + (int64_t)slab * n * S;
             F[i * S] = (T)f0;
             if (S == 2) F[i * S + 1] = (T)f1;
+        }
+    }
+    VB_END
+}
+
+// Attraction entry point with slabs: F_attr = sum of the slab partials.
+template <typename T, int S>
+__global__ __launch_bounds__(256) void k_asum(LaunchMap map)
+{
+    VB_BEGIN(map, K_ASUM)
+    {
+        const int64_t k = (int64_t)lb * 256 + threadIdx.x;
+        const int64_t ns = I.n * S;
+        if (k < ns) {
+            const T* Fp = static_cast<const T*>(I.Fap);
+            double a = 0.0;
+            for (int sl = 0; sl < I.slabs; ++sl) a += (double)Fp[(int64_t)sl * ns + k];
+            static_cast<T*>(I.Fattr)[k] = (T)a;
         }
     }
     VB_END
@@ -884,11 +911,21 @@ __global__ __launch_bounds__(256) void k_update(LaunchMap map)
             T* uY = static_cast<T*>(I.uY);
             T* gains = static_cast<T*>(I.gains);
             const T* Fa = static_cast<const T*>(I.Fattr);
+            const T* Fp = static_cast<const T*>(I.Fap);
             const T* R = static_cast<const T*>(I.R);
+            const int64_t ns = I.n * S;
 #pragma unroll
             for (int d = 0; d < S; ++d) {
                 const int64_t k = i * S + d;
-                const T grad = (T)4 * ((T)alpha * Fa[k] - R[k] * invz);
+                T fa;
+                if (I.slabs == 1) {
+                    fa = Fa[k];
+                } else {
+                    double a = 0.0;
+                    for (int sl = 0; sl < I.slabs; ++sl) a += (double)Fp[(int64_t)sl * ns + k];
+                    fa = (T)a;
+                }
+                const T grad = (T)4 * ((T)alpha * fa - R[k] * invz);
                 const T u = uY[k];
                 T g = ((grad > (T)0) != (u > (T)0)) ? gains[k] + (T)sc.gain_inc
                                                     : gains[k] * (T)sc.gain_dec;
@@ -939,6 +976,7 @@ static hipError_t launch_pts(int kind, const Cfg& c, const LaunchMap& map, const
         else hipLaunchKernelGGL((k_attr<T, S, 64, false>), g, b, 0, st, map);
         break;
     case K_UPDATE: hipLaunchKernelGGL((k_update<T, S>), g, b, 0, st, map); break;
+    case K_ASUM: hipLaunchKernelGGL((k_asum<T, S>), g, b, 0, st, map); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -72,12 +72,13 @@ struct Layout {
 enum Region {
     R_INST, R_PREFIX, R_GEOM, R_SCHED, R_SMALL, R_BOX, R_COUNTS, R_CSTART, R_ISTART, R_SCAN,
     R_ICELL, R_KEY, R_RANK, R_PERM, R_SY, R_CARRY, R_W, R_X, R_XC, R_V, R_SPEC, R_TW, R_COS,
-    R_SPECTMP, R_KTAB, R_R, R_FA, R_ZPART, R_N
+    R_SPECTMP, R_KTAB, R_R, R_FA, R_FAP, R_SPLIT, R_ZPART, R_N
 };
 
 struct Derived {
     int s, p, nc, np, tsz, max_int, n_cap, M, half, ncell_cap, items_cap, kpts, lpr;
     int nstages, radix[kMaxStages], rmin;
+    int slabs, slab_w;
     int tile_w, ntiles, col_group;
     int nb_box, nb_gather, nb_scan, nwaves;
     int row_threads, col_threads;
@@ -103,6 +104,7 @@ tsne_status derive(const tsne_desc* d, Derived& o)
         return TSNE_E_ARG;
     if (d->points_per_lane != 0 && (d->points_per_lane < 1 || d->points_per_lane > 64))
         return TSNE_E_ARG;
+    if (d->attr_slabs < 0 || d->attr_slabs > 64 || d->reserved != 0) return TSNE_E_ARG;
 
     o.s = d->s;
     o.p = d->p;
@@ -125,6 +127,15 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     o.ncell_cap = (d->s == 2) ? o.max_int * o.max_int : o.max_int;
     o.kpts = d->points_per_lane ? d->points_per_lane : 8;
     o.lpr = d->lanes_per_row ? d->lanes_per_row : 32;
+    // column slabs: the positions one slab gathers (~2 MB) stay in each XCD's L2
+    {
+        const int64_t ybytes = d->n * d->s * ((d->dtype == TSNE_F32) ? 4 : 8);
+        int sl = d->attr_slabs ? d->attr_slabs : (int)std::min<int64_t>(64, std::max<int64_t>(1, (ybytes + (2 << 20) - 1) >> 21));
+        if (d->nnz >= ((int64_t)1 << 31) || d->nnz == 0) sl = 1;   // split offsets are int32
+        if (sl > d->n) sl = (int)d->n;
+        o.slabs = sl;
+        o.slab_w = (int)((d->n + sl - 1) / sl);
+    }
     const int64_t n = d->n;
     o.items_cap = cdiv(n, o.kpts) + (int)std::min<int64_t>(n, o.ncell_cap);
     o.nwaves = cdiv(o.items_cap, 64);
@@ -174,8 +185,9 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     }
     vb[K_GATHER] = o.nb_gather;
     vb[K_NORM] = cdiv(n * d->s, 256);
-    vb[K_ATTR] = d->nnz > 0 ? cdiv(n, 256 / o.lpr) : 0;
+    vb[K_ATTR] = d->nnz > 0 ? o.slabs * cdiv(n, 256 / o.lpr) : 0;
     vb[K_ATTR_ALL] = vb[K_ATTR];
+    vb[K_ASUM] = (d->nnz > 0 && o.slabs > 1) ? cdiv(n * d->s, 256) : 0;
     vb[K_UPDATE] = cdiv(n, 256);
     vb[K_GEOM] = 1;
     vb[K_ZSUM] = 1;
@@ -219,6 +231,8 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     sz[R_COS] = sizeof(double) * o.M;
     sz[R_R] = (size_t)o.tsz * n * d->s;
     sz[R_FA] = (size_t)o.tsz * n * d->s;
+    sz[R_FAP] = (o.slabs > 1) ? (size_t)o.tsz * n * d->s * o.slabs : 0;
+    sz[R_SPLIT] = (o.slabs > 1) ? sizeof(int) * (size_t)(o.slabs - 1) * n : 0;
     sz[R_ZPART] = sizeof(double) * o.nb_gather;
     size_t cur = 0;
     for (int r = 0; r < R_N; ++r) {
@@ -447,6 +461,10 @@ tsne_status tsne_plan_create(const tsne_desc* desc, void* workspace, size_t byte
     h.R = b + off[R_R];
     h.Fa_ws = b + off[R_FA];
     h.z_part = reinterpret_cast<double*>(b + off[R_ZPART]);
+    h.Fap = b + off[R_FAP];
+    h.split = reinterpret_cast<const int*>(b + off[R_SPLIT]);
+    h.slabs = o.slabs;
+    h.slab_w = o.slab_w;
     h.nb_box = o.nb_box;
     h.nb_gather = o.nb_gather;
     h.nb_scan = o.nb_scan;
@@ -507,6 +525,25 @@ tsne_status tsne_bind_P(tsne_plan* pl, const int64_t* row_ptr, const int32_t* co
             if (rp[i + 1] < rp[i]) return TSNE_E_ARG;
         for (int64_t k = 0; k < pl->d.nnz; ++k)
             if (cc[k] < 0 || cc[k] >= n) return TSNE_E_ARG;
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t k = rp[i] + 1; k < rp[i + 1]; ++k)
+                if (cc[k] <= cc[k - 1]) return TSNE_E_ARG;
+        // per-row start of each later column slab
+        const int S = pl->o.slabs;
+        if (S > 1) {
+            std::vector<int> split((size_t)(S - 1) * n);
+            for (int64_t i = 0; i < n; ++i) {
+                const int32_t* r0 = cc.data() + rp[i];
+                const int32_t* r1 = cc.data() + rp[i + 1];
+                for (int sl = 1; sl < S; ++sl) {
+                    const int32_t bound = (int32_t)std::min<int64_t>((int64_t)sl * pl->o.slab_w, n);
+                    split[(size_t)(sl - 1) * n + i] = (int)(std::lower_bound(r0, r1, bound) - cc.data());
+                }
+            }
+            if (!hip_ok(hipMemcpy(const_cast<int*>(pl->h.split), split.data(),
+                                  split.size() * sizeof(int), hipMemcpyHostToDevice)))
+                return TSNE_E_HIP;
+        }
     }
     CallArgs a = no_args();
     a.set_P = 1;
@@ -542,7 +579,9 @@ tsne_status tsne_attractive(tsne_plan* pl, const void* Y, void* F_attr)
     a.Fattr = F_attr;
     tsne_status s = set_ptrs(pl, a);
     if (s != TSNE_OK) return s;
-    return enqueue(pl, K_ATTR_ALL);
+    s = enqueue(pl, K_ATTR_ALL);
+    if (s != TSNE_OK) return s;
+    return enqueue(pl, K_ASUM);
 }
 
 static tsne_status step_args(tsne_plan* pl, void* Y, void* uY, void* gains, const tsne_sched* sc,

@@ -23,7 +23,7 @@ constexpr int kWave = 64;
 enum Kind : int {
     K_ARGS = 0, K_BOX, K_KEY, K_SCAN_A, K_SCAN_B, K_SCATTER, K_SPREAD, K_FIX,
     K_FFT_ROWS, K_FFT_COLS, K_FFT_IROWS, K_FFT_1D, K_GATHER, K_NORM, K_ATTR,
-    K_UPDATE, K_SPEC0, K_SPEC1, K_SPEC2, K_GEOM, K_ZSUM, K_ATTR_ALL, K_NKINDS
+    K_UPDATE, K_SPEC0, K_SPEC1, K_SPEC2, K_GEOM, K_ZSUM, K_ATTR_ALL, K_ASUM, K_NKINDS
 };
 
 // Status bits latched on the device (values of tsne_status).
@@ -115,6 +115,10 @@ struct Inst {
     double* ktab;          // [2][half][half] kernel values on the lag grid (double)
     void* R;               // [n][s] unnormalised repulsion numerators
     void* Fa_ws;           // [n][s] attraction (workspace copy for the step)
+    void* Fap;             // [slabs][n][s] attraction partials per column slab
+    const int* split;      // [slabs - 1][n] first non-zero of each later slab per row
+    int slabs;             // column slabs of P (1: no split)
+    int slab_w;            // points per column slab
     double* z_part;        // [nb_gather]
     int nb_box, nb_gather, nb_scan, nwaves;
 };
@@ -165,6 +169,26 @@ __device__ __forceinline__ bool live(const Inst& I) { return I.geom->active != 0
 #define VB_END \
         }      \
     }
+
+// Like VB_BEGIN, but skips virtual blocks whose instance fails COND; COND is
+// evaluated once per instance change (not per virtual block), which keeps
+// launches that are usually idle cheap.
+#define VB_BEGIN_IF(map, KIND, COND)                                           \
+    {                                                                          \
+        const int* __pre = (map).prefix + (KIND) * ((map).ninst + 1);          \
+        const int __total = __pre[(map).ninst];                                \
+        int __last = -1;                                                       \
+        bool __ok = false;                                                     \
+        for (int __vb = blockIdx.x; __vb < __total; __vb += gridDim.x) {       \
+            const int inst_id = find_inst(__pre, (map).ninst, __vb);           \
+            const Inst& I = (map).insts[inst_id];                              \
+            if (inst_id != __last) {                                           \
+                __last = inst_id;                                              \
+                __ok = (COND);                                                 \
+            }                                                                  \
+            if (!__ok) continue;                                               \
+            const int lb = __vb - __pre[inst_id];                              \
+            (void)lb;
 
 template <typename T> __device__ __forceinline__ T wave_sum(T v)
 {
