@@ -104,63 +104,76 @@ __device__ __forceinline__ int fdiv(int x, int d, float rd)
     return q;
 }
 
-// One Stockham stage of radix R over G transforms of length M stored
-// back-to-back in buf; Ns = product of the radices of earlier stages.
+// One Stockham stage of radix R over G transforms of length M stored at
+// stride PM (padded indices) in buf; Ns = product of the radices of earlier
+// stages.  Butterfly j = a Ns + k reads x[j + r M/R], multiplies by the
+// twiddles w^(r k M/(Ns R)) (this stage's table, R-1 values per k), applies
+// the length-R DFT and writes to a Ns R + k + r Ns.
 template <typename T, int R>
-__device__ __forceinline__ void fft_stage(cplx<T>* buf, int M, int G, int Ns,
-                                          const cplx<T>* __restrict__ tw)
+__device__ __forceinline__ void fft_stage(cplx<T>* buf, int M, int PM, int G, int Ns,
+                                          const cplx<T>* __restrict__ tws)
 {
     const int Mr = M / R;
     const int nb = G * Mr;
-    const int stw = M / (Ns * R);
     const float rMr = 1.0f / (float)Mr, rNs = 1.0f / (float)Ns;
     const int nthr = blockDim.x;
+    const int nbt = (nb + nthr - 1) / nthr;
     cplx<T> v[kMaxB][R];
-    int dst[kMaxB];
+    int dst[kMaxB], dbase[kMaxB];
 #pragma unroll
     for (int b = 0; b < kMaxB; ++b) {
+        if (b >= nbt) break;
         const int idx = threadIdx.x + b * nthr;
         dst[b] = -1;
+        dbase[b] = 0;
         if (idx < nb) {
             const int g = fdiv(idx, Mr, rMr);
             const int j = idx - g * Mr;
-            const cplx<T>* src = buf + g * M;
+            const cplx<T>* src = buf + g * PM;
             const int a = fdiv(j, Ns, rNs);
             const int k = j - a * Ns;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[b][r] = src[j + r * Mr];
+            for (int r = 0; r < R; ++r) v[b][r] = src[lds_pad(j + r * Mr)];
+            if (Ns > 1) {
+                const cplx<T>* t = tws + k * (R - 1);
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[r * k * stw]);
+                for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], t[r - 1]);
+            }
             Dft<T, R>::run(v[b]);
-            dst[b] = g * M + a * Ns * R + k;
+            dbase[b] = g * PM;
+            dst[b] = a * Ns * R + k;
         }
     }
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < kMaxB; ++b) {
+        if (b >= nbt) break;
         if (dst[b] >= 0) {
+            cplx<T>* out = buf + dbase[b];
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[dst[b] + r * Ns] = v[b][r];
+            for (int r = 0; r < R; ++r) out[lds_pad(dst[b] + r * Ns)] = v[b][r];
         }
     }
     __syncthreads();
 }
 
-// Forward transforms (exp(-2 pi i k n / M)) of G length-M sequences in LDS,
-// M and the radix stages being those of this iteration (Geom).
+// Forward transforms (exp(-2 pi i k n / M)) of G length-M sequences in LDS
+// (padded layout, transform g at g * lds_stride(M)), M and the radix stages
+// being those of this iteration (Geom).
 template <typename T>
 __device__ void block_fft(cplx<T>* buf, int G, const Inst& I, const Geom& Gm)
 {
     const cplx<T>* tw = static_cast<const cplx<T>*>(I.tw);
-    const int M = Gm.M;
+    const int M = Gm.M, PM = lds_stride(M);
     int Ns = 1;
     for (int s = 0; s < Gm.nstages; ++s) {
         const int R = Gm.radix[s];
+        const cplx<T>* tws = tw + Gm.tw_off[s];
         switch (R) {
-        case 2: fft_stage<T, 2>(buf, M, G, Ns, tw); break;
-        case 3: fft_stage<T, 3>(buf, M, G, Ns, tw); break;
-        case 4: fft_stage<T, 4>(buf, M, G, Ns, tw); break;
-        default: fft_stage<T, 5>(buf, M, G, Ns, tw); break;
+        case 2: fft_stage<T, 2>(buf, M, PM, G, Ns, tws); break;
+        case 3: fft_stage<T, 3>(buf, M, PM, G, Ns, tws); break;
+        case 4: fft_stage<T, 4>(buf, M, PM, G, Ns, tws); break;
+        default: fft_stage<T, 5>(buf, M, PM, G, Ns, tws); break;
         }
         Ns *= R;
     }
@@ -207,14 +220,14 @@ __global__ __launch_bounds__(1024) void k_fft_rows(LaunchMap map)
                     if (occupied(cs, cya * n_int + cx)) a = W[(int64_t)ra * n_cap + g];
                     if (rb < n && occupied(cs, cyb * n_int + cx)) b = W[(int64_t)rb * n_cap + g];
                 }
-                buf[g] = {a, b};
+                buf[lds_pad(g)] = {a, b};
             }
             __syncthreads();
             block_fft<T>(buf, 1, I, G);
             cplx<T>* X = static_cast<cplx<T>*>(I.X) + (int64_t)ch * I.ntiles * n_cap * tw_;
             const T hlf = (T)0.5;
             for (int k = threadIdx.x; k < G.half; k += blockDim.x) {
-                const cplx<T> z = buf[k], zc = buf[k == 0 ? 0 : M - k];
+                const cplx<T> z = buf[lds_pad(k)], zc = buf[lds_pad(k == 0 ? 0 : M - k)];
                 const cplx<T> A = {(z.x + zc.x) * hlf, (z.y - zc.y) * hlf};
                 const cplx<T> B = {(z.y + zc.y) * hlf, (zc.x - z.x) * hlf};
                 const int tile = k / tw_, kk = k - tile * tw_;
@@ -243,15 +256,16 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
         int ch, kern;
         pot_of<S, FORM>(pot, ch, kern);
         const cplx<T>* X = static_cast<const cplx<T>*>(I.X) + (int64_t)ch * I.ntiles * n_cap * tw_;
+        const int PM = lds_stride(M);
         for (int idx = threadIdx.x; idx < Gc * M; idx += blockDim.x) {
-            const int g = idx / M, r = idx - g * M;
+            const int r = idx / Gc, g = idx - r * Gc;     // consecutive threads: columns of a row
             const int k0 = cg * Gc + g;
             cplx<T> v = {(T)0, (T)0};
             if (k0 < half && r < n) {
                 const int tile = k0 / tw_;
                 v = X[((int64_t)tile * n_cap + r) * tw_ + (k0 - tile * tw_)];
             }
-            buf[idx] = v;
+            buf[g * PM + lds_pad(r)] = v;
         }
         __syncthreads();
         block_fft<T>(buf, Gc, I, Gm);
@@ -261,18 +275,19 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
             const int g = idx / M, k1 = idx - g * M;
             const int k0 = cg * Gc + g;
             const T sv = (k0 < half) ? sp[(int64_t)k0 * half + (k1 <= M - k1 ? k1 : M - k1)] : (T)0;
-            const cplx<T> v = buf[idx];
-            buf[idx] = {v.x * sv, -v.y * sv};
+            const int li = g * PM + lds_pad(k1);
+            const cplx<T> v = buf[li];
+            buf[li] = {v.x * sv, -v.y * sv};
         }
         __syncthreads();
         block_fft<T>(buf, Gc, I, Gm);
         cplx<T>* Xc = static_cast<cplx<T>*>(I.Xc) + (int64_t)pot * I.ntiles * n_cap * tw_;
-        for (int idx = threadIdx.x; idx < Gc * M; idx += blockDim.x) {
-            const int g = idx / M, r = idx - g * M;
+        for (int idx = threadIdx.x; idx < Gc * n; idx += blockDim.x) {
+            const int r = idx / Gc, g = idx - r * Gc;
             const int k0 = cg * Gc + g;
-            if (k0 < half && r < n) {
+            if (k0 < half) {
                 const int tile = k0 / tw_;
-                Xc[((int64_t)tile * n_cap + r) * tw_ + (k0 - tile * tw_)] = cconj(buf[idx]);
+                Xc[((int64_t)tile * n_cap + r) * tw_ + (k0 - tile * tw_)] = cconj(buf[g * PM + lds_pad(r)]);
             }
         }
         __syncthreads();
@@ -306,14 +321,14 @@ __global__ __launch_bounds__(1024) void k_fft_irows(LaunchMap map)
                 cplx<T> B = (pb < NP) ? Xb[off] : cplx<T>{(T)0, (T)0};
                 if (up) { A = cconj(A); B = cconj(B); }
                 // Z = A + i B, stored conjugated (inverse by forward transform)
-                buf[k] = {A.x - B.y, -(A.y + B.x)};
+                buf[lds_pad(k)] = {A.x - B.y, -(A.y + B.x)};
             }
             __syncthreads();
             block_fft<T>(buf, 1, I, G);
             T* Va = static_cast<T*>(I.V) + (int64_t)pa * n_cap * n_cap + (int64_t)r * n_cap;
             T* Vb = static_cast<T*>(I.V) + (int64_t)pb * n_cap * n_cap + (int64_t)r * n_cap;
             for (int g = threadIdx.x; g < n; g += blockDim.x) {
-                const cplx<T> z = buf[g];       // conj of the inverse
+                const cplx<T> z = buf[lds_pad(g)];   // conj of the inverse
                 Va[g] = z.x;
                 if (pb < NP) Vb[g] = -z.y;
             }
@@ -342,20 +357,20 @@ __global__ __launch_bounds__(1024) void k_fft_1d(LaunchMap map)
         for (int g = threadIdx.x; g < M; g += blockDim.x) {
             T a = (T)0;
             if (g < n && occupied(cs, g / P)) a = W[g];
-            buf[g] = {a, (T)0};
+            buf[lds_pad(g)] = {a, (T)0};
         }
         __syncthreads();
         block_fft<T>(buf, 1, I, G);
         const T* sp = static_cast<const T*>(I.spec) + (int64_t)kern * half;
         for (int k = threadIdx.x; k < M; k += blockDim.x) {
             const T sv = sp[k <= M - k ? k : M - k];
-            const cplx<T> v = buf[k];
-            buf[k] = {v.x * sv, -v.y * sv};
+            const cplx<T> v = buf[lds_pad(k)];
+            buf[lds_pad(k)] = {v.x * sv, -v.y * sv};
         }
         __syncthreads();
         block_fft<T>(buf, 1, I, G);
         T* Vp = static_cast<T*>(I.V) + (int64_t)pot * n_cap;
-        for (int g = threadIdx.x; g < n; g += blockDim.x) Vp[g] = buf[g].x;
+        for (int g = threadIdx.x; g < n; g += blockDim.x) Vp[g] = buf[lds_pad(g)].x;
         __syncthreads();
     }
     VB_END
@@ -390,9 +405,22 @@ __global__ __launch_bounds__(256) void k_spec0(LaunchMap map)
         if (idx < M) {
             double sv, cv;
             sincospi(2.0 * (double)idx / (double)M, &sv, &cv);
+            I.costab[idx] = cv;
+        }
+        if (idx < M - 1) {
+            // stage tables: stage s holds w^(r k M/(Ns R)) at [k (R-1) + r - 1]
+            int st = 0;
+            while (st + 1 < G.nstages && G.tw_off[st + 1] <= idx) ++st;
+            int ns = 1;
+            for (int q = 0; q < st; ++q) ns *= G.radix[q];
+            const int R = G.radix[st];
+            const int e = (int)idx - G.tw_off[st];
+            const int k = e / (R - 1), r = e - k * (R - 1) + 1;
+            const int64_t ang = (int64_t)r * k * (M / (ns * R));
+            double sv, cv;
+            sincospi(2.0 * (double)ang / (double)M, &sv, &cv);
             cplx<T>* tw = static_cast<cplx<T>*>(I.tw);
             tw[idx] = {(T)cv, (T)(-sv)};
-            I.costab[idx] = cv;
         }
         const double h2 = G.h * G.h;
         if (S == 2) {

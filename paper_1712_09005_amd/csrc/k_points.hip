@@ -286,10 +286,16 @@ __global__ __launch_bounds__(256) void k_geom(LaunchMap map)
                     G.nstages = k;
                     G.M = M;
                     G.half = M / 2 + 1;
+                    int off = 0, ns = 1;
+                    for (int q = 0; q < k; ++q) {
+                        G.tw_off[q] = off;
+                        off += ns * (G.radix[q] - 1);
+                        ns *= G.radix[q];
+                    }
                     // columns per block: as many as the LDS holds (power of two)
                     const int csz = 2 * ((I.tile_w == 16) ? 4 : 8);
                     int g = I.tile_w;
-                    while (g > 1 && (int64_t)g * M * csz > I.col_lds) g >>= 1;
+                    while (g > 1 && (int64_t)g * lds_stride(M) * csz > I.col_lds) g >>= 1;
                     G.col_group = g;
                 }
                 G.spec_dirty = (G.h != G.spec_h || G.M != G.spec_M) ? 1 : 0;
@@ -794,18 +800,21 @@ template <typename V> __device__ __forceinline__ double cx(const V& v) { return 
 template <> __device__ __forceinline__ double cx<float>(const float& v) { return (double)v; }
 template <> __device__ __forceinline__ double cx<double>(const double& v) { return v; }
 
+// 1 / x: the hardware reciprocal (1 ulp) for float, IEEE division for double.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 // F_attr,i = sum_j p_ij (y_i - y_j) / (1 + |y_i - y_j|^2) over row i of the CSR
-// P (Section 3).  The columns are split into slabs of slab_w points so that
-// the positions one slab gathers stay resident in every XCD's L2; virtual
-// blocks run slab-major, each row's slab range comes from the split table
-// (rows are column-sorted), and each slab writes a partial force.  LPR lanes
-// per row; each lane takes U non-zeros per round and issues all their loads
-// (column, value, then the neighbours' positions as one vector load each)
-// before using them.  Terms in the element type, sums in double.
-template <typename T, int S, int LPR, bool GATED>
+// P (Section 3).  LPR lanes per row; each lane takes U non-zeros per round and
+// issues all their loads (column, value, then the neighbours' positions as one
+// vector load each) before using them, so LPR * U should cover a typical row.
+// Each lane sums its few terms in the element type; the row's lanes are
+// reduced in double.  Optionally the columns are split into slabs (virtual
+// blocks run slab-major, each row's slab range from the split table) and each
+// slab writes a partial force.
+template <typename T, int S, int LPR, int U, bool GATED>
 __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
 {
-    constexpr int U = 4;
     constexpr int RPB = 256 / LPR;
     typedef typename Vec<T, S>::t V;
     VB_BEGIN_IF(map, GATED ? K_ATTR : K_ATTR_ALL, (!GATED || live(I)))
@@ -813,12 +822,13 @@ __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
         const int64_t n = I.n;
         const int nrb = (int)((n + RPB - 1) / RPB);
         const int slab = lb / nrb, rb = lb - slab * nrb;
-        const int64_t i = (int64_t)rb * RPB + threadIdx.x / LPR;
-        const int sub = threadIdx.x % LPR;
-        double f0 = 0.0, f1 = 0.0;
+        const int i = rb * RPB + (int)threadIdx.x / LPR;
+        const int sub = (int)threadIdx.x % LPR;
+        T a0 = (T)0, a1 = (T)0;
         const V* Y = static_cast<const V*>(I.Yin);
         if (i < n) {
             const T* val = static_cast<const T*>(I.val);
+            const int32_t* col = I.col;
             const V yi = Y[i];
             T yi0, yi1 = (T)0;
             if constexpr (S == 2) { yi0 = yi.x; yi1 = yi.y; } else { yi0 = yi; }
@@ -832,7 +842,7 @@ __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
                 for (int u = 0; u < U; ++u) {
                     const int64_t k = k0 + (int64_t)u * LPR;
                     const bool ok = k < e;
-                    jj[u] = ok ? I.col[k] : (int)i;
+                    jj[u] = ok ? col[k] : i;
                     pp[u] = ok ? val[k] : (T)0;
                 }
                 V yj[U];
@@ -843,12 +853,13 @@ __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
                     T d0, d1 = (T)0;
                     if constexpr (S == 2) { d0 = yi0 - yj[u].x; d1 = yi1 - yj[u].y; }
                     else { d0 = yi0 - yj[u]; }
-                    const T wgt = pp[u] / ((T)1 + d0 * d0 + d1 * d1);
-                    f0 += (double)(wgt * d0);
-                    if (S == 2) f1 += (double)(wgt * d1);
+                    const T wgt = pp[u] * recip((T)1 + d0 * d0 + d1 * d1);
+                    a0 += wgt * d0;
+                    if (S == 2) a1 += wgt * d1;
                 }
             }
         }
+        double f0 = (double)a0, f1 = (double)a1;
 #pragma unroll
         for (int o = LPR / 2; o > 0; o >>= 1) {
             f0 += __shfl_xor(f0, o, 64);
@@ -857,8 +868,8 @@ __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
         if (i < n && sub == 0) {
             T* F = (I.slabs == 1) ? static_cast<T*>(I.Fattr)
                                   : static_cast<T*>(I.Fap) + (int64_t)slab * n * S;
-            F[i * S] = (T)f0;
-            if (S == 2) F[i * S + 1] = (T)f1;
+            F[(int64_t)i * S] = (T)f0;
+            if (S == 2) F[(int64_t)i * S + 1] = (T)f1;
         }
     }
     VB_END
@@ -964,16 +975,16 @@ static hipError_t launch_pts(int kind, const Cfg& c, const LaunchMap& map, const
     case K_ZSUM: hipLaunchKernelGGL(k_zsum, g, b, 0, st, map); break;
     case K_NORM: hipLaunchKernelGGL((k_norm<T, S>), g, b, 0, st, map); break;
     case K_ATTR:
-        if (c.lpr == 8) hipLaunchKernelGGL((k_attr<T, S, 8, true>), g, b, 0, st, map);
-        else if (c.lpr == 16) hipLaunchKernelGGL((k_attr<T, S, 16, true>), g, b, 0, st, map);
-        else if (c.lpr == 32) hipLaunchKernelGGL((k_attr<T, S, 32, true>), g, b, 0, st, map);
-        else hipLaunchKernelGGL((k_attr<T, S, 64, true>), g, b, 0, st, map);
+        if (c.lpr == 8) hipLaunchKernelGGL((k_attr<T, S, 8, 4, true>), g, b, 0, st, map);
+        else if (c.lpr == 16) hipLaunchKernelGGL((k_attr<T, S, 16, 3, true>), g, b, 0, st, map);
+        else if (c.lpr == 32) hipLaunchKernelGGL((k_attr<T, S, 32, 3, true>), g, b, 0, st, map);
+        else hipLaunchKernelGGL((k_attr<T, S, 64, 2, true>), g, b, 0, st, map);
         break;
     case K_ATTR_ALL:
-        if (c.lpr == 8) hipLaunchKernelGGL((k_attr<T, S, 8, false>), g, b, 0, st, map);
-        else if (c.lpr == 16) hipLaunchKernelGGL((k_attr<T, S, 16, false>), g, b, 0, st, map);
-        else if (c.lpr == 32) hipLaunchKernelGGL((k_attr<T, S, 32, false>), g, b, 0, st, map);
-        else hipLaunchKernelGGL((k_attr<T, S, 64, false>), g, b, 0, st, map);
+        if (c.lpr == 8) hipLaunchKernelGGL((k_attr<T, S, 8, 4, false>), g, b, 0, st, map);
+        else if (c.lpr == 16) hipLaunchKernelGGL((k_attr<T, S, 16, 3, false>), g, b, 0, st, map);
+        else if (c.lpr == 32) hipLaunchKernelGGL((k_attr<T, S, 32, 3, false>), g, b, 0, st, map);
+        else hipLaunchKernelGGL((k_attr<T, S, 64, 2, false>), g, b, 0, st, map);
         break;
     case K_UPDATE: hipLaunchKernelGGL((k_update<T, S>), g, b, 0, st, map); break;
     case K_ASUM: hipLaunchKernelGGL((k_asum<T, S>), g, b, 0, st, map); break;

@@ -130,7 +130,8 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     // column slabs: the positions one slab gathers (~2 MB) stay in each XCD's L2
     {
         const int64_t ybytes = d->n * d->s * ((d->dtype == TSNE_F32) ? 4 : 8);
-        int sl = d->attr_slabs ? d->attr_slabs : (int)std::min<int64_t>(64, std::max<int64_t>(1, (ybytes + (2 << 20) - 1) >> 21));
+        (void)ybytes;
+        int sl = d->attr_slabs ? d->attr_slabs : 1;   // measured: slabs do not pay on gfx950
         if (d->nnz >= ((int64_t)1 << 31) || d->nnz == 0) sl = 1;   // split offsets are int32
         if (sl > d->n) sl = (int)d->n;
         o.slabs = sl;
@@ -147,13 +148,14 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     const int need_row = cdiv(o.M, (int64_t)o.rmin * kMaxBfly);
     o.row_threads = std::max(256, pow2_at_least(need_row));
     if (o.row_threads > 1024) return TSNE_E_UNSUPPORTED;
-    o.row_lds = (size_t)o.M * csz;
+    o.row_lds = (size_t)lds_stride(o.M) * csz;
     // column kernel: LDS for as many columns as fit in 96 KB (at least one);
     // each iteration packs G = (largest power of two) columns of its own M
-    o.col_lds = std::min<size_t>((size_t)o.tile_w * o.M * csz, 96 * 1024);
-    o.col_lds = std::max<size_t>(o.col_lds, (size_t)o.M * csz);
+    const size_t pm = (size_t)lds_stride(o.M) * csz;   // one padded transform
+    o.col_lds = std::min<size_t>((size_t)o.tile_w * pm, 96 * 1024);
+    o.col_lds = std::max<size_t>(o.col_lds, pm);
     o.col_group = 1;                                   // columns per block at capacity
-    while (o.col_group < o.tile_w && (size_t)(2 * o.col_group) * o.M * csz <= o.col_lds) o.col_group *= 2;
+    while (o.col_group < o.tile_w && (size_t)(2 * o.col_group) * pm <= o.col_lds) o.col_group *= 2;
     o.col_threads = std::max(256, pow2_at_least(cdiv((int64_t)(o.col_lds / csz), (int64_t)o.rmin * kMaxBfly)));
     if (o.col_threads > 1024) return TSNE_E_UNSUPPORTED;
     if (o.row_lds > 160 * 1024 || o.col_lds > 160 * 1024) return TSNE_E_UNSUPPORTED;

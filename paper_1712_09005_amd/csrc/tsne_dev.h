@@ -54,8 +54,14 @@ struct Geom {
     int half;          // M / 2 + 1
     int nstages;
     int radix[kMaxStages];
+    int tw_off[kMaxStages];   // offset of each stage's twiddle table in tw
     int col_group;     // FFT columns per block this iteration
 };
+
+// LDS index of element i of a transform: one pad slot per 16 complex values
+// keeps the strided Stockham writes of the early stages off shared banks.
+__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int lds_stride(int M) { return M + (M >> 4) + 1; }
 
 struct Sched {
     double eta, mom0, mom1, ee_alpha, le_alpha, gain_inc, gain_dec, gain_min;
@@ -109,7 +115,7 @@ struct Inst {
     void* Xc;              // [np][ntiles][n_cap][tile_w] complex (after columns)
     void* V;               // [np][n_cap][n_cap] or [np][n_cap]
     void* spec;            // [2][half][half] (s = 2) or [2][half], pre-scaled
-    void* tw;              // [M] complex roots exp(-2 pi i k / M) of this iteration's M
+    void* tw;              // [M] stage twiddle tables of this iteration's M (complex)
     double* costab;        // [M] cos(2 pi k / M) in double
     double* spec_tmp;      // [2][half][half] first cosine pass (double)
     double* ktab;          // [2][half][half] kernel values on the lag grid (double)
