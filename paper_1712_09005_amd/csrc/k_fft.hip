@@ -20,7 +20,7 @@
 
 namespace tsne {
 
-constexpr int kMaxB = 8;   // butterflies per thread per stage (host-enforced)
+constexpr int kMaxB = 4;   // butterflies per thread per stage (host-enforced)
 
 template <typename T>
 __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b)
@@ -161,7 +161,7 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int M, int PM, int G, in
 // (padded layout, transform g at g * lds_stride(M)), M and the radix stages
 // being those of this iteration (Geom).
 template <typename T>
-__device__ void block_fft(cplx<T>* buf, int G, const Inst& I, const Geom& Gm)
+__device__ __forceinline__ void block_fft(cplx<T>* buf, int G, const Inst& I, const Geom& Gm)
 {
     const cplx<T>* tw = static_cast<const cplx<T>*>(I.tw);
     const int M = Gm.M, PM = lds_stride(M);

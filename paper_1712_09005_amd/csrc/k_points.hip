@@ -164,13 +164,13 @@ __global__ __launch_bounds__(256) void k_box(LaunchMap map)
     VB_END
 }
 
-// Smallest even M >= lo whose prime factors are 2, 3 and 5.
+// Smallest M >= lo of the form 4^a 3^b 5^c with a >= 1 (radix-4, 3 and 5
+// stages only).
 __device__ __forceinline__ int ladder(int lo)
 {
-    int M = lo + (lo & 1);
-    for (;; M += 2) {
+    for (int M = (lo + 3) & ~3;; M += 4) {
         int r = M;
-        while (r % 2 == 0) r /= 2;
+        while (r % 4 == 0) r /= 4;
         while (r % 3 == 0) r /= 3;
         while (r % 5 == 0) r /= 5;
         if (r == 1) return M;
@@ -275,12 +275,11 @@ __global__ __launch_bounds__(256) void k_geom(LaunchMap map)
                 if (M < 2 * G.n || M > I.M || want * 3 < M * 2) M = want;
                 if (M > I.M) M = I.M;
                 if (M != G.M) {
-                    int r = M, k = 0, n2 = 0, n3 = 0, n5 = 0;
-                    while (r % 2 == 0) { r /= 2; ++n2; }
+                    int r = M, k = 0, n4 = 0, n3 = 0, n5 = 0;
+                    while (r % 4 == 0) { r /= 4; ++n4; }
                     while (r % 3 == 0) { r /= 3; ++n3; }
                     while (r % 5 == 0) { r /= 5; ++n5; }
-                    for (int q = 0; q < n2 / 2; ++q) G.radix[k++] = 4;
-                    if (n2 & 1) G.radix[k++] = 2;
+                    for (int q = 0; q < n4; ++q) G.radix[k++] = 4;
                     for (int q = 0; q < n3; ++q) G.radix[k++] = 3;
                     for (int q = 0; q < n5; ++q) G.radix[k++] = 5;
                     G.nstages = k;

@@ -19,35 +19,35 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxM = 16384;
-constexpr int kMaxBfly = 8;          // must match the kernels' per-thread butterfly bound
+constexpr int kMaxBfly = 4;          // must match the kernels' per-thread butterfly bound
 constexpr int kGridCap = 4096;       // virtual blocks are looped over beyond this
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
-// Smallest even M >= lo whose prime factors are 2, 3, 5.
+// Smallest M >= lo of the form 4^a 3^b 5^c, a >= 1: every stage is radix 4, 3
+// or 5 (the device picks its per-iteration length from the same ladder).
 int fft_len(int lo)
 {
-    for (int m = std::max(lo, 2); m <= kMaxM; ++m) {
-        if (m & 1) continue;
+    for (int m = std::max((lo + 3) & ~3, 4); m <= kMaxM; m += 4) {
         int r = m;
-        for (int f : {2, 3, 5})
+        while (r % 4 == 0) r /= 4;
+        for (int f : {3, 5})
             while (r % f == 0) r /= f;
         if (r == 1) return m;
     }
     return -1;
 }
 
-// Radix stages: 4s, then a 2 if needed, then 3s, then 5s.
+// Radix stages: 4s, then 3s, then 5s.
 int radix_plan(int M, int* radix, int* rmin)
 {
-    int r = M, n2 = 0, n3 = 0, n5 = 0, k = 0;
-    while (r % 2 == 0) { r /= 2; ++n2; }
+    int r = M, n4 = 0, n3 = 0, n5 = 0, k = 0;
+    while (r % 4 == 0) { r /= 4; ++n4; }
     while (r % 3 == 0) { r /= 3; ++n3; }
     while (r % 5 == 0) { r /= 5; ++n5; }
     if (r != 1) return -1;
-    for (int i = 0; i < n2 / 2; ++i) radix[k++] = 4;
-    if (n2 & 1) radix[k++] = 2;
+    for (int i = 0; i < n4; ++i) radix[k++] = 4;
     for (int i = 0; i < n3; ++i) radix[k++] = 3;
     for (int i = 0; i < n5; ++i) radix[k++] = 5;
     if (k > kMaxStages) return -1;
@@ -121,9 +121,9 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     o.half = o.M / 2 + 1;
     o.nstages = radix_plan(o.M, o.radix, &o.rmin);
     if (o.nstages < 0) return TSNE_E_UNSUPPORTED;
-    // the device picks a smaller ladder length when the box is smaller; any of
-    // them may have a radix-2 stage, so thread counts assume the smallest radix
-    o.rmin = 2;
+    // the device picks a smaller ladder length when the box is smaller; every
+    // ladder length has radix 3, 4 or 5 stages only
+    o.rmin = 3;
     o.ncell_cap = (d->s == 2) ? o.max_int * o.max_int : o.max_int;
     o.kpts = d->points_per_lane ? d->points_per_lane : 8;
     o.lpr = d->lanes_per_row ? d->lanes_per_row : 32;
@@ -157,8 +157,8 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     o.col_group = 1;                                   // columns per block at capacity
     while (o.col_group < o.tile_w && (size_t)(2 * o.col_group) * pm <= o.col_lds) o.col_group *= 2;
     o.col_threads = std::max(256, pow2_at_least(cdiv((int64_t)(o.col_lds / csz), (int64_t)o.rmin * kMaxBfly)));
-    if (o.col_threads > 1024) return TSNE_E_UNSUPPORTED;
-    if (o.row_lds > 160 * 1024 || o.col_lds > 160 * 1024) return TSNE_E_UNSUPPORTED;
+    if (o.row_lds > 160 * 1024) return TSNE_E_UNSUPPORTED;
+    if (d->s == 2 && (o.col_threads > 1024 || o.col_lds > 160 * 1024)) return TSNE_E_UNSUPPORTED;
 
     o.nb_box = std::min(512, std::max(1, cdiv(n, 256 * 4)));
     o.nb_gather = cdiv(n, 256);
@@ -257,8 +257,9 @@ Launch launch_of(int kind, const Derived& o, int vblocks)
     Launch l{std::min(vblocks, kGridCap), 256, 0};
     switch (kind) {
     case K_SPEC0: case K_SPEC1: case K_SPEC2:
-        // usually idle (tables unchanged): few blocks, each loops when there is work
-        l.grid = std::min(vblocks, 512);
+        // usually idle (tables unchanged): a bounded grid, each block loops when
+        // there is work and checks once when there is none
+        l.grid = std::min(vblocks, 2048);
         break;
     case K_FFT_ROWS: case K_FFT_IROWS: case K_FFT_1D:
         l.block = o.row_threads;
