@@ -91,9 +91,12 @@ typedef struct {
     int64_t nnz;             /* non-zeros of P; 0 if attraction is not used */
     int32_t lanes_per_row;   /* CSR lanes per row: 0 (auto), 8, 16, 32 or 64 */
     int32_t points_per_lane; /* spreading points per lane: 0 (auto), 1..64 */
-    int32_t attr_slabs;      /* column slabs of P for the attraction: 0 (auto: each
-                                slab's positions ~2 MB, so they stay in L2), 1..64 */
-    int32_t reserved;        /* must be 0 */
+    int32_t attr_slabs;      /* CSR layout: column slabs of P, 0 (auto), 1, 2, 4 or 8;
+                                each slab is handled by 8/slabs of the 8 XCDs */
+    int32_t attr_layout;     /* attraction: 0 auto, 1 CSR rows (lanes per row over
+                                the bound CSR), 2 tiles (P re-bucketed at bind time
+                                into row-block x column-block tiles, positions of
+                                both blocks staged in LDS) */
 } tsne_desc;
 
 /* Descent schedule, indexed by the absolute iteration it:

@@ -820,12 +820,22 @@ __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
     {
         const int64_t n = I.n;
         const int nrb = (int)((n + RPB - 1) / RPB);
-        const int slab = lb / nrb, rb = lb - slab * nrb;
+        // XCD-aware slab assignment: workgroups go to the 8 XCDs round-robin
+        // (block b -> XCD b mod 8, and launches keep virtual block = b mod 8),
+        // so virtual block v works on slab (v mod 8) / (8 / slabs): each XCD's
+        // L2 then only holds the positions of its own slab.
+        int slab = 0, rb = lb;
+        if (I.slabs > 1) {
+            const int per = 8 / I.slabs;
+            const int x = lb & 7, q = lb >> 3;
+            slab = x / per;
+            rb = q * per + (x - slab * per);
+        }
         const int i = rb * RPB + (int)threadIdx.x / LPR;
         const int sub = (int)threadIdx.x % LPR;
         T a0 = (T)0, a1 = (T)0;
         const V* Y = static_cast<const V*>(I.Yin);
-        if (i < n) {
+        if (i < n && rb < nrb) {
             const T* val = static_cast<const T*>(I.val);
             const int32_t* col = I.col;
             const V yi = Y[i];
@@ -864,12 +874,85 @@ __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
             f0 += __shfl_xor(f0, o, 64);
             if (S == 2) f1 += __shfl_xor(f1, o, 64);
         }
-        if (i < n && sub == 0) {
+        if (i < n && rb < nrb && sub == 0) {
             T* F = (I.slabs == 1) ? static_cast<T*>(I.Fattr)
                                   : static_cast<T*>(I.Fap) + (int64_t)slab * n * S;
             F[(int64_t)i * S] = (T)f0;
             if (S == 2) F[(int64_t)i * S + 1] = (T)f1;
         }
+    }
+    VB_END
+}
+
+// Attraction over tiles of P: edges re-bucketed (at bind time) by row block
+// of tile_bi rows and column block of tile_bj columns, rows increasing within
+// a tile.  One workgroup per row block keeps that block's positions and force
+// sums in LDS and walks the column blocks in order, staging each block's
+// positions in LDS; every neighbour position then comes from LDS instead of a
+// random global gather, and all workgroups sweep the column blocks in the same
+// order, so the staged blocks are shared through L2.  Per-row sums use LDS
+// atomics in the element type.
+template <typename T, int S, bool GATED>
+__global__ __launch_bounds__(1024) void k_attr_tile(LaunchMap map)
+{
+    typedef typename Vec<T, S>::t V;
+    constexpr int U = 2;
+    extern __shared__ __align__(16) char smem[];
+    VB_BEGIN_IF(map, GATED ? K_ATTR_T : K_ATTR_T_ALL, (!GATED || live(I)))
+    {
+        const int BI = I.tile_bi, BJ = I.tile_bj, nj = I.tile_nj;
+        const int64_t n = I.n;
+        V* yJ = reinterpret_cast<V*>(smem);
+        V* yI = yJ + BJ;
+        T* f = reinterpret_cast<T*>(yI + BI);
+        const V* Y = static_cast<const V*>(I.Yin);
+        const int i0 = lb * BI;
+        const int rows = (int)min((int64_t)BI, n - i0);
+        for (int r = threadIdx.x; r < BI; r += blockDim.x) {
+            V z;
+            if constexpr (S == 2) z = V{(T)0, (T)0}; else z = (T)0;
+            yI[r] = (r < rows) ? Y[i0 + r] : z;
+#pragma unroll
+            for (int d = 0; d < S; ++d) f[r * S + d] = (T)0;
+        }
+        const int64_t* to = I.toff + (int64_t)lb * nj;
+        const uint32_t* ep = I.epack;
+        const T* ev = static_cast<const T*>(I.eval);
+        for (int J = 0; J < nj; ++J) {
+            const int64_t e0 = to[J], e1 = to[J + 1];
+            if (e0 == e1) continue;
+            const int j0 = J * BJ;
+            const int cols = (int)min((int64_t)BJ, n - j0);
+            __syncthreads();
+            for (int c = threadIdx.x; c < cols; c += blockDim.x) yJ[c] = Y[j0 + c];
+            __syncthreads();
+            for (int64_t e = e0 + threadIdx.x; e < e1; e += (int64_t)blockDim.x * U) {
+                uint32_t pk[U];
+                T pv[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t k = e + (int64_t)u * blockDim.x;
+                    pk[u] = (k < e1) ? ep[k] : 0xffffffffu;
+                    pv[u] = (k < e1) ? ev[k] : (T)0;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (pk[u] == 0xffffffffu) continue;
+                    const int il = (int)(pk[u] >> 16), jl = (int)(pk[u] & 0xffffu);
+                    const V a = yI[il], b = yJ[jl];
+                    T d0, d1 = (T)0;
+                    if constexpr (S == 2) { d0 = a.x - b.x; d1 = a.y - b.y; }
+                    else { d0 = a - b; }
+                    const T wgt = pv[u] * recip((T)1 + d0 * d0 + d1 * d1);
+                    atomicAdd(&f[il * S], wgt * d0);
+                    if (S == 2) atomicAdd(&f[il * S + 1], wgt * d1);
+                }
+            }
+        }
+        __syncthreads();
+        T* F = static_cast<T*>(I.Fattr);
+        for (int r = threadIdx.x; r < rows * S; r += blockDim.x) F[(int64_t)i0 * S + r] = f[r];
+        __syncthreads();
     }
     VB_END
 }
@@ -987,6 +1070,18 @@ static hipError_t launch_pts(int kind, const Cfg& c, const LaunchMap& map, const
         break;
     case K_UPDATE: hipLaunchKernelGGL((k_update<T, S>), g, b, 0, st, map); break;
     case K_ASUM: hipLaunchKernelGGL((k_asum<T, S>), g, b, 0, st, map); break;
+    case K_ATTR_T:
+        if (l.lds > 48 * 1024)
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_attr_tile<T, S, true>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipLaunchKernelGGL((k_attr_tile<T, S, true>), g, b, l.lds, st, map);
+        break;
+    case K_ATTR_T_ALL:
+        if (l.lds > 48 * 1024)
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_attr_tile<T, S, false>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipLaunchKernelGGL((k_attr_tile<T, S, false>), g, b, l.lds, st, map);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

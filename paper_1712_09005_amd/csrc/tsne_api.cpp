@@ -18,7 +18,7 @@ using namespace tsne;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kMaxM = 16384;
+constexpr int kMaxM = 12288;       // row transforms: 1024 threads x 4 butterflies x radix 3
 constexpr int kMaxBfly = 4;          // must match the kernels' per-thread butterfly bound
 constexpr int kGridCap = 4096;       // virtual blocks are looped over beyond this
 
@@ -72,13 +72,15 @@ struct Layout {
 enum Region {
     R_INST, R_PREFIX, R_GEOM, R_SCHED, R_SMALL, R_BOX, R_COUNTS, R_CSTART, R_ISTART, R_SCAN,
     R_ICELL, R_KEY, R_RANK, R_PERM, R_SY, R_CARRY, R_W, R_X, R_XC, R_V, R_SPEC, R_TW, R_COS,
-    R_SPECTMP, R_KTAB, R_R, R_FA, R_FAP, R_SPLIT, R_ZPART, R_N
+    R_SPECTMP, R_KTAB, R_R, R_FA, R_FAP, R_SPLIT, R_TOFF, R_EPACK, R_EVAL, R_ZPART, R_N
 };
 
 struct Derived {
     int s, p, nc, np, tsz, max_int, n_cap, M, half, ncell_cap, items_cap, kpts, lpr;
     int nstages, radix[kMaxStages], rmin;
     int slabs, slab_w;
+    int tiled, tile_bi, tile_bj, tile_ni, tile_nj;
+    size_t tile_lds;
     int tile_w, ntiles, col_group;
     int nb_box, nb_gather, nb_scan, nwaves;
     int row_threads, col_threads;
@@ -104,7 +106,8 @@ tsne_status derive(const tsne_desc* d, Derived& o)
         return TSNE_E_ARG;
     if (d->points_per_lane != 0 && (d->points_per_lane < 1 || d->points_per_lane > 64))
         return TSNE_E_ARG;
-    if (d->attr_slabs < 0 || d->attr_slabs > 64 || d->reserved != 0) return TSNE_E_ARG;
+    if (d->attr_slabs < 0 || d->attr_slabs > 64) return TSNE_E_ARG;
+    if (d->attr_layout < 0 || d->attr_layout > 2) return TSNE_E_ARG;
 
     o.s = d->s;
     o.p = d->p;
@@ -131,12 +134,24 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     {
         const int64_t ybytes = d->n * d->s * ((d->dtype == TSNE_F32) ? 4 : 8);
         (void)ybytes;
-        int sl = d->attr_slabs ? d->attr_slabs : 1;   // measured: slabs do not pay on gfx950
+        int sl = d->attr_slabs ? d->attr_slabs : 1;
+        if (sl != 1 && sl != 2 && sl != 4 && sl != 8) return TSNE_E_ARG;   // slabs map onto XCDs
         if (d->nnz >= ((int64_t)1 << 31) || d->nnz == 0) sl = 1;   // split offsets are int32
         if (sl > d->n) sl = (int)d->n;
         o.slabs = sl;
         o.slab_w = (int)((d->n + sl - 1) / sl);
     }
+    // attraction layout: tiles for large P (measured faster), CSR rows otherwise
+    o.tiled = (d->nnz > 0) && (d->attr_layout == 2 || (d->attr_layout == 0 && d->n >= 16384));
+    o.tile_bi = (d->dtype == TSNE_F32) ? 4096 : 2048;
+    o.tile_bj = 2 * o.tile_bi;
+    o.tile_ni = (int)((d->n + o.tile_bi - 1) / o.tile_bi);
+    o.tile_nj = (int)((d->n + o.tile_bj - 1) / o.tile_bj);
+    {
+        const size_t tsz_ = (d->dtype == TSNE_F32) ? 4 : 8;
+        o.tile_lds = (size_t)(o.tile_bi + o.tile_bj) * d->s * tsz_ + (size_t)o.tile_bi * d->s * tsz_;
+    }
+    if (o.tiled) o.slabs = 1;
     const int64_t n = d->n;
     o.items_cap = cdiv(n, o.kpts) + (int)std::min<int64_t>(n, o.ncell_cap);
     o.nwaves = cdiv(o.items_cap, 64);
@@ -187,7 +202,13 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     }
     vb[K_GATHER] = o.nb_gather;
     vb[K_NORM] = cdiv(n * d->s, 256);
-    vb[K_ATTR] = d->nnz > 0 ? o.slabs * cdiv(n, 256 / o.lpr) : 0;
+    {
+        const int nrb = cdiv(n, 256 / o.lpr);
+        // with slabs: 8 * ceil(nrb / (8 / slabs)) virtual blocks, a multiple of 8
+        vb[K_ATTR] = (d->nnz == 0 || o.tiled) ? 0 : (o.slabs == 1 ? nrb : 8 * cdiv(nrb, 8 / o.slabs));
+        vb[K_ATTR_T] = o.tiled ? o.tile_ni : 0;
+        vb[K_ATTR_T_ALL] = vb[K_ATTR_T];
+    }
     vb[K_ATTR_ALL] = vb[K_ATTR];
     vb[K_ASUM] = (d->nnz > 0 && o.slabs > 1) ? cdiv(n * d->s, 256) : 0;
     vb[K_UPDATE] = cdiv(n, 256);
@@ -235,6 +256,9 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     sz[R_FA] = (size_t)o.tsz * n * d->s;
     sz[R_FAP] = (o.slabs > 1) ? (size_t)o.tsz * n * d->s * o.slabs : 0;
     sz[R_SPLIT] = (o.slabs > 1) ? sizeof(int) * (size_t)(o.slabs - 1) * n : 0;
+    sz[R_TOFF] = o.tiled ? sizeof(int64_t) * ((size_t)o.tile_ni * o.tile_nj + 1) : 0;
+    sz[R_EPACK] = o.tiled ? sizeof(uint32_t) * (size_t)d->nnz : 0;
+    sz[R_EVAL] = o.tiled ? (size_t)o.tsz * d->nnz : 0;
     sz[R_ZPART] = sizeof(double) * o.nb_gather;
     size_t cur = 0;
     for (int r = 0; r < R_N; ++r) {
@@ -268,6 +292,10 @@ Launch launch_of(int kind, const Derived& o, int vblocks)
     case K_FFT_COLS:
         l.block = o.col_threads;
         l.lds = o.col_lds;
+        break;
+    case K_ATTR_T: case K_ATTR_T_ALL:
+        l.block = 1024;
+        l.lds = o.tile_lds;
         break;
     default:
         break;
@@ -468,6 +496,14 @@ tsne_status tsne_plan_create(const tsne_desc* desc, void* workspace, size_t byte
     h.split = reinterpret_cast<const int*>(b + off[R_SPLIT]);
     h.slabs = o.slabs;
     h.slab_w = o.slab_w;
+    h.tiled = o.tiled;
+    h.tile_bi = o.tile_bi;
+    h.tile_bj = o.tile_bj;
+    h.tile_ni = o.tile_ni;
+    h.tile_nj = o.tile_nj;
+    h.toff = reinterpret_cast<const int64_t*>(b + off[R_TOFF]);
+    h.epack = reinterpret_cast<const uint32_t*>(b + off[R_EPACK]);
+    h.eval = b + off[R_EVAL];
     h.nb_box = o.nb_box;
     h.nb_gather = o.nb_gather;
     h.nb_scan = o.nb_scan;
@@ -547,6 +583,45 @@ tsne_status tsne_bind_P(tsne_plan* pl, const int64_t* row_ptr, const int32_t* co
                                   split.size() * sizeof(int), hipMemcpyHostToDevice)))
                 return TSNE_E_HIP;
         }
+        // tiles: edges bucketed by (row block, column block), rows increasing
+        if (pl->o.tiled) {
+            const Derived& o = pl->o;
+            const int64_t nnz = pl->d.nnz;
+            const size_t tsz = (size_t)o.tsz;
+            std::vector<char> vv(nnz * tsz), vt(nnz * tsz);
+            if (!hip_ok(hipMemcpy(vv.data(), val, nnz * tsz, hipMemcpyDeviceToHost))) return TSNE_E_HIP;
+            std::vector<int64_t> toff((size_t)o.tile_ni * o.tile_nj + 1, 0);
+            std::vector<uint32_t> pack(nnz);
+            std::vector<int64_t> cnt(o.tile_nj);
+            int64_t cur = 0;
+            for (int I = 0; I < o.tile_ni; ++I) {
+                const int64_t r0 = (int64_t)I * o.tile_bi, r1 = std::min<int64_t>(n, r0 + o.tile_bi);
+                std::fill(cnt.begin(), cnt.end(), 0);
+                for (int64_t i = r0; i < r1; ++i)
+                    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) ++cnt[cc[k] / o.tile_bj];
+                for (int J = 0; J < o.tile_nj; ++J) {
+                    toff[(size_t)I * o.tile_nj + J] = cur;
+                    const int64_t c = cnt[J];
+                    cnt[J] = cur;
+                    cur += c;
+                }
+                for (int64_t i = r0; i < r1; ++i)
+                    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+                        const int J = cc[k] / o.tile_bj;
+                        const int64_t dst = cnt[J]++;
+                        pack[dst] = ((uint32_t)(i - r0) << 16) | (uint32_t)(cc[k] - (int64_t)J * o.tile_bj);
+                        std::memcpy(vt.data() + dst * tsz, vv.data() + k * tsz, tsz);
+                    }
+            }
+            toff.back() = cur;
+            if (!hip_ok(hipMemcpy(const_cast<int64_t*>(pl->h.toff), toff.data(),
+                                  toff.size() * sizeof(int64_t), hipMemcpyHostToDevice)) ||
+                !hip_ok(hipMemcpy(const_cast<uint32_t*>(pl->h.epack), pack.data(),
+                                  pack.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) ||
+                !hip_ok(hipMemcpy(const_cast<void*>(pl->h.eval), vt.data(), vt.size(),
+                                  hipMemcpyHostToDevice)))
+                return TSNE_E_HIP;
+        }
     }
     CallArgs a = no_args();
     a.set_P = 1;
@@ -584,6 +659,8 @@ tsne_status tsne_attractive(tsne_plan* pl, const void* Y, void* F_attr)
     if (s != TSNE_OK) return s;
     s = enqueue(pl, K_ATTR_ALL);
     if (s != TSNE_OK) return s;
+    s = enqueue(pl, K_ATTR_T_ALL);
+    if (s != TSNE_OK) return s;
     return enqueue(pl, K_ASUM);
 }
 
@@ -614,6 +691,8 @@ static tsne_status enqueue_iteration(tsne_plan* pl)
     if (s != TSNE_OK) return s;
     if (pl->P_bound) {
         s = enqueue(pl, K_ATTR);
+        if (s != TSNE_OK) return s;
+        s = enqueue(pl, K_ATTR_T);
         if (s != TSNE_OK) return s;
     }
     return enqueue(pl, K_UPDATE);
@@ -821,8 +900,8 @@ static tsne_status batch_enqueue_tick(tsne_batch* b)
     const int* ch = (b->s == 2) ? kChain2 : kChain1;
     const int nk = (b->s == 2) ? (int)(sizeof(kChain2) / sizeof(int))
                                : (int)(sizeof(kChain1) / sizeof(int));
-    for (int i = 0; i <= nk + 1; ++i) {
-        const int k = (i < nk) ? ch[i] : (i == nk ? K_ATTR : K_UPDATE);
+    for (int i = 0; i <= nk + 2; ++i) {
+        const int k = (i < nk) ? ch[i] : (i == nk ? K_ATTR : (i == nk + 1 ? K_ATTR_T : K_UPDATE));
         if (b->launch[k].grid <= 0) continue;
         if (!hip_ok(launch_kind(k, b->cfg, map, b->launch[k], b->st))) return TSNE_E_HIP;
     }

@@ -23,7 +23,7 @@ constexpr int kWave = 64;
 enum Kind : int {
     K_ARGS = 0, K_BOX, K_KEY, K_SCAN_A, K_SCAN_B, K_SCATTER, K_SPREAD, K_FIX,
     K_FFT_ROWS, K_FFT_COLS, K_FFT_IROWS, K_FFT_1D, K_GATHER, K_NORM, K_ATTR,
-    K_UPDATE, K_SPEC0, K_SPEC1, K_SPEC2, K_GEOM, K_ZSUM, K_ATTR_ALL, K_ASUM, K_NKINDS
+    K_UPDATE, K_SPEC0, K_SPEC1, K_SPEC2, K_GEOM, K_ZSUM, K_ATTR_ALL, K_ASUM, K_ATTR_T, K_ATTR_T_ALL, K_NKINDS
 };
 
 // Status bits latched on the device (values of tsne_status).
@@ -125,6 +125,12 @@ struct Inst {
     const int* split;      // [slabs - 1][n] first non-zero of each later slab per row
     int slabs;             // column slabs of P (1: no split)
     int slab_w;            // points per column slab
+    int tiled;             // attraction over LDS tiles
+    int tile_bi, tile_bj;  // rows / columns per tile
+    int tile_ni, tile_nj;  // tile grid
+    const int64_t* toff;   // [ni * nj + 1] first edge of each tile
+    const uint32_t* epack; // [nnz] (row in block << 16) | column in block
+    const void* eval;      // [nnz] values in tile order
     double* z_part;        // [nb_gather]
     int nb_box, nb_gather, nb_scan, nwaves;
 };

@@ -31,7 +31,7 @@ class Desc(ctypes.Structure):
                 ("min_intervals", ctypes.c_int32), ("max_intervals", ctypes.c_int32),
                 ("interval_width", ctypes.c_double), ("nnz", ctypes.c_int64),
                 ("lanes_per_row", ctypes.c_int32), ("points_per_lane", ctypes.c_int32),
-                ("attr_slabs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("attr_slabs", ctypes.c_int32), ("attr_layout", ctypes.c_int32)]
 
 
 class Sched(ctypes.Structure):
@@ -134,12 +134,12 @@ def _dt(dtype) -> int:
 
 def make_desc(n, s, dtype=torch.float32, p=5, policy="fixed", form="A", min_intervals=1,
               max_intervals=512, interval_width=0.75, nnz=0, lanes_per_row=0,
-              points_per_lane=0, attr_slabs=0) -> Desc:
+              points_per_lane=0, attr_slabs=0, attr_layout=0) -> Desc:
     pol = GRID_PAPER if policy in ("paper", GRID_PAPER) else GRID_FIXED
     frm = FORM_A if form in ("A", FORM_A) else FORM_B
     return Desc(int(n), int(s), _dt(dtype), int(p), pol, frm, int(min_intervals),
                 int(max_intervals), float(interval_width), int(nnz), int(lanes_per_row),
-                int(points_per_lane), int(attr_slabs), 0)
+                int(points_per_lane), int(attr_slabs), int(attr_layout))
 
 
 def workspace_bytes(desc: Desc) -> int:
@@ -157,9 +157,11 @@ class Plan:
 
     def __init__(self, n, s, dtype=torch.float32, p=5, policy="fixed", form="A",
                  min_intervals=1, max_intervals=512, interval_width=0.75, nnz=0,
-                 lanes_per_row=0, points_per_lane=0, attr_slabs=0, device="cuda", stream=None):
+                 lanes_per_row=0, points_per_lane=0, attr_slabs=0, attr_layout=0, device="cuda",
+                 stream=None):
         self.desc = make_desc(n, s, dtype, p, policy, form, min_intervals, max_intervals,
-                              interval_width, nnz, lanes_per_row, points_per_lane, attr_slabs)
+                              interval_width, nnz, lanes_per_row, points_per_lane, attr_slabs,
+                              attr_layout)
         self.n, self.s = int(n), int(s)
         self.dtype = torch.float32 if self.desc.dtype == F32 else torch.float64
         self.device = torch.device(device)

@@ -156,14 +156,22 @@ def test_c1_against_direct_sum(T):
         assert rel(F2[:, d], Fd[:, d]) < 1e-3
 
 
+ATTR_LAYOUTS = [  # (lanes per row, slabs, layout): CSR rows, XCD slabs, LDS tiles
+    (8, 1, 1), (16, 1, 1), (32, 1, 1), (64, 1, 1), (8, 4, 1), (16, 2, 1), (32, 8, 1), (0, 0, 2)]
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
-@pytest.mark.parametrize("lpr", [16, 32, 64])
-def test_attraction(T, dtype, lpr):
-    print("case: attraction %s lpr=%d" % (dtype, lpr), flush=True)
-    n = 3001
-    Y = inputs.mixture_embedding(n, 2, 10, -30, 30, 2.0, seed=0)
+@pytest.mark.parametrize("lpr,slabs,layout", ATTR_LAYOUTS)
+@pytest.mark.parametrize("n,s", [(3001, 2), (20011, 2), (9001, 1)])
+def test_attraction(T, dtype, lpr, slabs, layout, n, s):
+    """Every attraction layout against the oracle, with ragged row and tile
+    counts (n not a multiple of any block size)."""
+    print("case: attraction %s n=%d s=%d lpr=%d slabs=%d layout=%d" % (dtype, n, s, lpr, slabs, layout),
+          flush=True)
+    Y = inputs.mixture_embedding(n, s, 10, -30, 30, 2.0, seed=0)
     P = inputs.random_graph_P(n, 90, seed=1)
-    plan = T.Plan(n, 2, dtype, nnz=P.nnz, lanes_per_row=lpr, max_intervals=128, device=DEV)
+    plan = T.Plan(n, s, dtype, nnz=P.nnz, lanes_per_row=lpr, attr_slabs=slabs, attr_layout=layout,
+                  max_intervals=128, device=DEV)
     plan.bind_P(torch.from_numpy(P.row_ptr).to(DEV), torch.from_numpy(P.col).to(DEV),
                 torch.from_numpy(P.val).to(DEV, dtype))
     Yt = torch.from_numpy(Y).to(DEV, dtype)
