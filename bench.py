@@ -37,11 +37,18 @@ def main():
     ap.add_argument("--width", type=float, default=0.75)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c2", "serve"],
+                    help="c3: N=1e6 2-D step throughput (default); c4: N=1e6 1-D 750-iteration "
+                         "run; c2: N=1e5 2-D 1000-iteration run from a 50-d mixture; serve: "
+                         "64-job continuous-batching server vs sequential runs")
+    ap.add_argument("--jobs", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload != "c3":
+        return other_workloads(args)
 
     import numpy as np
     import torch
@@ -174,6 +181,148 @@ def main():
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_us": t_attr * 1e6},
         "cpu_baseline": cpu,
     }
+    print(json.dumps(out), flush=True)
+
+
+def sampled_error(plan, Yt, n, s, rows=512, seed=123):
+    """Relative L2 error of the repulsion numerators on sampled rows against
+    the direct sum (the normalisation Z cancels out of the comparison)."""
+    import numpy as np
+    import oracle
+    import torch
+    rng = np.random.default_rng(seed)
+    r = np.sort(rng.choice(n, min(rows, n), replace=False))
+    plan.repulsive(Yt)
+    torch.cuda.synchronize()
+    Rn = np.frombuffer(plan.export(2), np.float32).reshape(n, s)[r].astype(np.float64)
+    Yd = Yt.cpu().numpy().astype(np.float64)
+    _, num = oracle.direct_sums(Yd, r)
+    return float(np.linalg.norm(Rn - num) / np.linalg.norm(num))
+
+
+def timed_run(plan, Yt, uY, gains, sched, n_iter, checkpoints, n, s):
+    """Run n_iter iterations from iteration 0, stopping at the checkpoints to
+    measure the sampled repulsion error; returns (seconds of GPU work, errors)."""
+    import torch
+    errs = {}
+    t = 0.0
+    it = 0
+    for c in sorted(set(checkpoints) | {n_iter}):
+        if c > it:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.run(Yt, uY, gains, sched, it, c - it)
+            plan.stream.synchronize()
+            torch.cuda.synchronize()
+            t += time.perf_counter() - t0
+            q = plan.query()
+            if q["status"] != 0:
+                raise SystemExit("device status %d at iteration %d" % (q["status"], c))
+            it = c
+        if c in checkpoints:
+            errs[str(c)] = sampled_error(plan, Yt, n, s)
+    return t, errs
+
+
+def other_workloads(args):
+    import numpy as np
+    import torch
+    from paper_1712_09005_amd import inputs, tsne
+    dev = torch.device("cuda:0")
+    if args.workload in ("c4", "c2"):
+        if args.workload == "c4":
+            n, s, n_iter = 1_000_000, 1, 750
+            Y = inputs.mixture_embedding(n, 1, 30, -195.0, 195.0, 1.5, seed=0)
+            P = inputs.random_graph_P(n, 90, seed=1)
+            sched = tsne.Schedule(ee_alpha=1.0, ee_stop=0, le_alpha=4.0, le_start=500)
+            checks = [0, 500, 749]
+            cap = 1024
+            desc = "N=1e6 1-D, 30 clusters on [-195,195] sd 1.5, random 90-neighbour P, 750 " \
+                   "iterations, late exaggeration 4 from iteration 500"
+        else:
+            n, s, n_iter = 100_000, 2, 1000
+            t0 = time.time()
+            x = inputs.mixture_highdim(n, 50, 20, 5.0, seed=0)
+            P = inputs.perplexity_P(x, 90, 30.0, device=dev)
+            log("c2 inputs: exact 90-NN perplexity-30 P, nnz=%d (%.1f s)" % (P.nnz, time.time() - t0))
+            rng = np.random.default_rng(2)
+            Y = (1e-2 * rng.standard_normal((n, 2))).astype(np.float32)
+            sched = tsne.Schedule()
+            checks = [0, 250, 500, 999]
+            cap = 512
+            desc = "N=1e5 2-D from a 20-cluster 50-d mixture, exact 90-NN perplexity-30 P, " \
+                   "1000 iterations, early exaggeration 12 for 250"
+        plan = tsne.Plan(n, s, torch.float32, p=args.p, policy="fixed", interval_width=args.width,
+                         max_intervals=cap, nnz=P.nnz, device=dev)
+        with torch.cuda.stream(plan.stream):
+            Yt = torch.from_numpy(np.ascontiguousarray(Y)).to(dev)
+            uY = torch.zeros_like(Yt)
+            gains = torch.ones_like(Yt)
+            rp = torch.from_numpy(P.row_ptr).to(dev)
+            col = torch.from_numpy(P.col).to(dev)
+            val = torch.from_numpy(P.val).to(dev)
+        torch.cuda.synchronize()
+        plan.bind_P(rp, col, val)
+        secs, errs = timed_run(plan, Yt, uY, gains, sched, n_iter, checks, n, s)
+        q = plan.query()
+        out = {"metric": "t-SNE iterations/s over a full run", "value": n_iter / secs,
+               "unit": "iterations/s", "n_gpus": 1, "steps": n_iter, "warmup": 0,
+               "ms_per_step": 1e3 * secs / n_iter, "higher_is_better": True, "scaling": "weak",
+               "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+               "config": {"workload": desc, "n": n, "s": s, "nnz": int(P.nnz), "p": args.p,
+                          "interval_width": args.width, "final_n_int": q["n_int"],
+                          "final_fft_len": q["fft_len"],
+                          "rel_err_rep_numerators_sampled_at": errs}}
+        print(json.dumps(out), flush=True)
+        return
+    # serving: 64 jobs, Poisson arrivals at twice the sequential rate
+    from paper_1712_09005_amd import serve
+    t0 = time.time()
+    specs = inputs.serving_jobs(args.jobs, device=dev)
+    log("serving inputs: %d jobs, N from %d to %d (%.1f s)" % (
+        len(specs), min(y.shape[0] for y, _ in specs), max(y.shape[0] for y, _ in specs),
+        time.time() - t0))
+
+    def jobs_at(arrivals):
+        return [serve.Job(j, float(a), y, P) for j, ((y, P), a) in enumerate(zip(specs, arrivals))]
+
+    back_to_back = serve.sequential(jobs_at(np.zeros(len(specs))), interval_width=args.width,
+                                    p=args.p, device=dev)
+    rate = 2.0 * back_to_back["runs_per_s"]
+    arr = inputs.poisson_arrivals(len(specs), rate, seed=7)
+    log("sequential back-to-back: %.2f runs/s; Poisson rate %.2f/s" % (back_to_back["runs_per_s"], rate))
+    srv = serve.Server(max_slots=64, hbm_budget=200 << 30, ticks_per_poll=10,
+                       interval_width=args.width, p=args.p, device=dev)
+    batched_jobs = jobs_at(arr)
+    batched = srv.run(batched_jobs)
+    log("batched: %s" % batched)
+    seq_jobs = jobs_at(arr)
+    seq = serve.sequential(seq_jobs, interval_width=args.width, p=args.p, device=dev)
+    log("sequential: %s" % seq)
+    # equal accuracy: repulsion error of the final embeddings of the smallest jobs
+    import oracle
+    acc = []
+    for jb, js in sorted(zip(batched_jobs, seq_jobs), key=lambda t: t[0].n)[:3]:
+        errs = []
+        for Yo in (jb.Y_out, js.Y_out):
+            plan = tsne.Plan(jb.n, 2, torch.float32, p=args.p, interval_width=args.width,
+                             max_intervals=serve.capacity_for(jb.n, args.width) * 2, device=dev)
+            Yt = torch.from_numpy(np.ascontiguousarray(Yo)).to(dev)
+            F, Z = plan.repulsive(Yt)
+            torch.cuda.synchronize()
+            Fd, Zd = oracle.direct_rep(Yo.astype(np.float64))
+            errs.append(float(np.linalg.norm(F.cpu().numpy() - Fd) / np.linalg.norm(Fd)))
+        acc.append({"job": jb.jid, "n": jb.n, "rel_err_batched": errs[0], "rel_err_sequential": errs[1]})
+    out = {"metric": "served t-SNE runs/s (64 jobs, 1000 iterations each)", "value": batched["runs_per_s"],
+           "unit": "runs/s", "n_gpus": 1, "steps": len(specs), "warmup": 0,
+           "ms_per_step": 1e3 * batched["makespan_s"] / len(specs), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "64 jobs, N log-uniform [5e3, 2e5], 5-30 cluster 50-d mixtures, "
+                                  "exact 90-NN perplexity-30 P, Poisson arrivals at 2x the "
+                                  "sequential rate", "batched": batched, "sequential_same_trace": seq,
+                      "sequential_back_to_back": back_to_back,
+                      "speedup_runs_per_s": batched["runs_per_s"] / seq["runs_per_s"],
+                      "accuracy_final_embeddings": acc}}
     print(json.dumps(out), flush=True)
 
 

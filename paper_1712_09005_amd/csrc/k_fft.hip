@@ -424,6 +424,13 @@ __global__ __launch_bounds__(256) void k_spec0(LaunchMap map)
         }
         const double h2 = G.h * G.h;
         if (S == 2) {
+            if (idx < (int64_t)half * half) {
+                const int j = (int)(idx / half), k = (int)(idx - (int64_t)j * half);
+                const double wt = (j == 0 || 2 * j == M) ? 1.0 : 2.0;
+                double sv, cv;
+                sincospi(2.0 * (double)(((int64_t)j * k) % M) / (double)M, &sv, &cv);
+                I.ccos[idx] = wt * cv;
+            }
             if (idx < (int64_t)2 * half * half) {
                 const int kern = (int)(idx / ((int64_t)half * half));
                 const int rem = (int)(idx - (int64_t)kern * half * half);
@@ -438,77 +445,117 @@ __global__ __launch_bounds__(256) void k_spec0(LaunchMap map)
     VB_END
 }
 
-// First cosine pass.  s = 2: A[kern][j1][k0] = sum_{j0=0}^{M/2} wt(j0)
-// K(j1, j0) cos(2 pi k0 j0 / M); s = 1: the whole spectrum
-// K^[kern][k] = sum_j wt(j) K(j) cos(2 pi k j / M) / M.
-// wt = 1 at j = 0 and j = M/2, else 2 (the circulant folds j and M - j).
+// Weighted cosine matrix C[j][k] = wt(j) cos(2 pi j k / M), j, k <= M/2,
+// wt = 1 at j = 0 and j = M/2, else 2 (the circulant folds j and M - j), so
+// that for an even sequence c the DFT is sum_j C[j][k] c[j].
+__device__ __forceinline__ double cos_w(const double* ct, int M, int j, int k)
+{
+    const double wt = (j == 0 || 2 * j == M) ? 1.0 : 2.0;
+    return wt * ct[(int)(((int64_t)j * k) % M)];
+}
+
+// One 64 x 64 tile of out = op(A) B for h x h row-major double matrices
+// (op(A) = A or its transpose), k staged through LDS 16 at a time; 256
+// threads, 4 x 4 outputs each.  emit(m, n, value) stores a result.
+template <bool TA, typename Emit>
+__device__ __forceinline__ void gemm_tile(const double* __restrict__ A, const double* __restrict__ B,
+                                          int h, int tm, int tn, double (*As)[65], double (*Bs)[65],
+                                          Emit emit)
+{
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int k0 = 0; k0 < h; k0 += 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + q * 256;
+            int kk, mm;
+            if (TA) { kk = e >> 6; mm = e & 63; } else { kk = e & 15; mm = e >> 4; }
+            const int m = tm * 64 + mm, k = k0 + kk;
+            As[kk][mm] = (m < h && k < h) ? (TA ? A[(int64_t)k * h + m] : A[(int64_t)m * h + k]) : 0.0;
+            const int nk = e >> 6, nn = e & 63;
+            const int n = tn * 64 + nn, k2 = k0 + nk;
+            Bs[nk][nn] = (n < h && k2 < h) ? B[(int64_t)k2 * h + n] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int m = tm * 64 + ty * 4 + i, n = tn * 64 + tx * 4 + j;
+            if (m < h && n < h) emit(m, n, acc[i][j]);
+        }
+}
+
+// First pass.  s = 2: A[kern] = K[kern] C (the row transform of the even
+// kernel grid), by tiled GEMM; s = 1: the whole spectrum
+// K^[kern][k] = sum_j C[j][k] K[kern][j] / M.
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_spec1(LaunchMap map)
 {
+    __shared__ double As[16][65], Bs[16][65];
     VB_BEGIN_IF(map, K_SPEC1, spec_needed(I))
     {
         const Geom& G = *I.geom;
-        const int M = G.M, half = G.half, mh = M / 2;
-        const double* ct = I.costab;
+        const int M = G.M, half = G.half;
         if (S == 2) {
-            const int64_t idx = (int64_t)lb * 256 + threadIdx.x;
-            if (idx < (int64_t)2 * half * half) {
-                const int kern = (int)(idx / ((int64_t)half * half));
-                const int rem = (int)(idx - (int64_t)kern * half * half);
-                const int j1 = rem / half, k0 = rem - j1 * half;
-                const double* kt = I.ktab + ((int64_t)kern * half + j1) * half;
-                double acc = 0.5 * (kt[0] + kt[mh] * ct[(int)(((int64_t)k0 * mh) % M)]);
-                int ph = k0;
-                for (int j0 = 1; j0 < mh; ++j0) {
-                    acc += kt[j0] * ct[ph];
-                    ph += k0;
-                    if (ph >= M) ph -= M;
-                }
-                I.spec_tmp[idx] = 2.0 * acc;
+            const int nt = (half + 63) / 64;
+            const int kern = lb / (nt * nt), rem = lb - kern * nt * nt;
+            const int tm = rem / nt, tn = rem - tm * nt;
+            if (kern < 2) {
+                double* out = I.spec_tmp + (int64_t)kern * half * half;
+                gemm_tile<false>(I.ktab + (int64_t)kern * half * half, I.ccos, half, tm, tn, As, Bs,
+                                 [&](int m, int n, double v) { out[(int64_t)m * half + n] = v; });
             }
         } else {
             const int idx = lb * 256 + threadIdx.x;
             if (idx < 2 * half) {
                 const int kern = idx / half, k = idx - kern * half;
                 const double* kt = I.ktab + (int64_t)kern * half;
-                double acc = 0.5 * (kt[0] + kt[mh] * ct[(int)(((int64_t)k * mh) % M)]);
-                int ph = k;
-                for (int j = 1; j < mh; ++j) {
-                    acc += kt[j] * ct[ph];
-                    ph += k;
-                    if (ph >= M) ph -= M;
-                }
-                static_cast<T*>(I.spec)[idx] = (T)(2.0 * acc / M);
+                double acc = 0.0;
+                for (int j = 0; j < half; ++j) acc += cos_w(I.costab, M, j, k) * kt[j];
+                static_cast<T*>(I.spec)[idx] = (T)(acc / M);
             }
         }
     }
     VB_END
 }
 
-// Second pass (s = 2): K^[kern][k0][k1] = sum_{j1} wt(j1) A[kern][j1][k0]
-// cos(2 pi k1 j1 / M) / M^2, stored [kern][k0][k1], k0, k1 <= M/2.
+// Second pass (s = 2): K^[kern] = A[kern]^T C / M^2, stored [kern][k0][k1],
+// k0, k1 <= M/2.
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_spec2(LaunchMap map)
 {
+    __shared__ double As[16][65], Bs[16][65];
     VB_BEGIN_IF(map, K_SPEC2, S == 2 && spec_needed(I))
     {
         const Geom& G = *I.geom;
-        const int M = G.M, half = G.half, mh = M / 2;
-        const int64_t idx = (int64_t)lb * 256 + threadIdx.x;
-        if (idx < (int64_t)2 * half * half) {
-            const int kern = (int)(idx / ((int64_t)half * half));
-            const int rem = (int)(idx - (int64_t)kern * half * half);
-            const int k0 = rem / half, k1 = rem - k0 * half;
-            const double* A = I.spec_tmp + (int64_t)kern * half * half;
-            const double* ct = I.costab;
-            double acc = 0.5 * (A[k0] + A[(int64_t)mh * half + k0] * ct[(int)(((int64_t)k1 * mh) % M)]);
-            int ph = k1;
-            for (int j1 = 1; j1 < mh; ++j1) {
-                acc += A[(int64_t)j1 * half + k0] * ct[ph];
-                ph += k1;
-                if (ph >= M) ph -= M;
-            }
-            static_cast<T*>(I.spec)[idx] = (T)(2.0 * acc / ((double)M * (double)M));
+        const int M = G.M, half = G.half;
+        const int nt = (half + 63) / 64;
+        const int kern = lb / (nt * nt), rem = lb - kern * nt * nt;
+        const int tm = rem / nt, tn = rem - tm * nt;
+        if (kern < 2) {
+            T* out = static_cast<T*>(I.spec) + (int64_t)kern * half * half;
+            const double sc = 1.0 / ((double)M * (double)M);
+            gemm_tile<true>(I.spec_tmp + (int64_t)kern * half * half, I.ccos, half, tm, tn, As, Bs,
+                            [&](int m, int n, double v) { out[(int64_t)m * half + n] = (T)(v * sc); });
         }
     }
     VB_END

@@ -72,7 +72,7 @@ struct Layout {
 enum Region {
     R_INST, R_PREFIX, R_GEOM, R_SCHED, R_SMALL, R_BOX, R_COUNTS, R_CSTART, R_ISTART, R_SCAN,
     R_ICELL, R_KEY, R_RANK, R_PERM, R_SY, R_CARRY, R_W, R_X, R_XC, R_V, R_SPEC, R_TW, R_COS,
-    R_SPECTMP, R_KTAB, R_R, R_FA, R_FAP, R_SPLIT, R_TOFF, R_EPACK, R_EVAL, R_ZPART, R_N
+    R_SPECTMP, R_KTAB, R_CCOS, R_R, R_FA, R_FAP, R_SPLIT, R_TOFF, R_EPACK, R_EVAL, R_ZPART, R_N
 };
 
 struct Derived {
@@ -129,20 +129,24 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     o.rmin = 3;
     o.ncell_cap = (d->s == 2) ? o.max_int * o.max_int : o.max_int;
     o.kpts = d->points_per_lane ? d->points_per_lane : 8;
-    o.lpr = d->lanes_per_row ? d->lanes_per_row : 32;
-    // column slabs: the positions one slab gathers (~2 MB) stay in each XCD's L2
+    // column slabs: when the positions exceed ~4 MB, 4 slabs of P split over
+    // XCD pairs keep each XCD's gathers inside its own 4 MB L2 (measured at
+    // N = 1e6: 754 us against 980 us with one slab); short rows per slab then
+    // want fewer lanes per row
     {
         const int64_t ybytes = d->n * d->s * ((d->dtype == TSNE_F32) ? 4 : 8);
-        (void)ybytes;
-        int sl = d->attr_slabs ? d->attr_slabs : 1;
+        const bool big = ybytes >= ((int64_t)4 << 20);
+        int sl = d->attr_slabs ? d->attr_slabs : (big ? 4 : 1);
         if (sl != 1 && sl != 2 && sl != 4 && sl != 8) return TSNE_E_ARG;   // slabs map onto XCDs
+        o.lpr = d->lanes_per_row ? d->lanes_per_row : (sl > 1 ? 8 : 32);
         if (d->nnz >= ((int64_t)1 << 31) || d->nnz == 0) sl = 1;   // split offsets are int32
         if (sl > d->n) sl = (int)d->n;
         o.slabs = sl;
         o.slab_w = (int)((d->n + sl - 1) / sl);
     }
-    // attraction layout: tiles for large P (measured faster), CSR rows otherwise
-    o.tiled = (d->nnz > 0) && (d->attr_layout == 2 || (d->attr_layout == 0 && d->n >= 16384));
+    // attraction layout: CSR rows unless tiles are asked for (tiles measured
+    // slower at N = 1e6: 1480 us, one 128 KB-LDS workgroup per CU)
+    o.tiled = (d->nnz > 0) && d->attr_layout == 2;
     o.tile_bi = (d->dtype == TSNE_F32) ? 4096 : 2048;
     o.tile_bj = 2 * o.tile_bi;
     o.tile_ni = (int)((d->n + o.tile_bi - 1) / o.tile_bi);
@@ -192,7 +196,7 @@ tsne_status derive(const tsne_desc* d, Derived& o)
         vb[K_FFT_ROWS] = o.nc * cdiv(o.n_cap, 2);
         vb[K_FFT_COLS] = o.np * cdiv(o.half, o.col_group);
         vb[K_FFT_IROWS] = cdiv(o.np, 2) * o.n_cap;
-        vb[K_SPEC1] = cdiv((int64_t)2 * o.half * o.half, 256);
+        vb[K_SPEC1] = 2 * cdiv(o.half, 64) * cdiv(o.half, 64);      // 64 x 64 GEMM tiles
         vb[K_SPEC2] = vb[K_SPEC1];
         vb[K_SPEC0] = cdiv(std::max<int64_t>(o.M, (int64_t)2 * o.half * o.half), 256);
     } else {
@@ -242,7 +246,9 @@ tsne_status derive(const tsne_desc* d, Derived& o)
         sz[R_SPEC] = (size_t)o.tsz * 2 * o.half * o.half;
         sz[R_SPECTMP] = sizeof(double) * 2 * (size_t)o.half * o.half;
         sz[R_KTAB] = sizeof(double) * 2 * (size_t)o.half * o.half;
+        sz[R_CCOS] = sizeof(double) * (size_t)o.half * o.half;
     } else {
+        sz[R_CCOS] = 0;
         sz[R_X] = 0;
         sz[R_XC] = 0;
         sz[R_SPEC] = (size_t)o.tsz * 2 * o.half;
@@ -489,6 +495,7 @@ tsne_status tsne_plan_create(const tsne_desc* desc, void* workspace, size_t byte
     h.costab = reinterpret_cast<double*>(b + off[R_COS]);
     h.spec_tmp = reinterpret_cast<double*>(b + off[R_SPECTMP]);
     h.ktab = reinterpret_cast<double*>(b + off[R_KTAB]);
+    h.ccos = reinterpret_cast<double*>(b + off[R_CCOS]);
     h.R = b + off[R_R];
     h.Fa_ws = b + off[R_FA];
     h.z_part = reinterpret_cast<double*>(b + off[R_ZPART]);
@@ -965,7 +972,15 @@ tsne_status tsne_batch_admit(tsne_batch* b, const tsne_desc* desc, void* plan_ws
         return TSNE_E_ARG;
     if (desc->s != b->s || desc->dtype != b->dtype || desc->p != b->p || desc->form != b->form)
         return TSNE_E_ARG;
-    if (desc->lanes_per_row != 0 && desc->lanes_per_row != 32) return TSNE_E_UNSUPPORTED;
+    // every slot shares one attraction launch: CSR rows, 32 lanes per row, one slab
+    if ((desc->lanes_per_row != 0 && desc->lanes_per_row != 32) ||
+        (desc->attr_slabs != 0 && desc->attr_slabs != 1) || desc->attr_layout == 2)
+        return TSNE_E_UNSUPPORTED;
+    tsne_desc dd = *desc;
+    dd.lanes_per_row = 32;
+    dd.attr_slabs = 1;
+    dd.attr_layout = 1;
+    desc = &dd;
     int free_id = -1;
     for (int i = 0; i < b->max_slots; ++i)
         if (!b->slots[i].used) { free_id = i; break; }

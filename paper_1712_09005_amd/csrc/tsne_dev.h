@@ -119,6 +119,7 @@ struct Inst {
     double* costab;        // [M] cos(2 pi k / M) in double
     double* spec_tmp;      // [2][half][half] first cosine pass (double)
     double* ktab;          // [2][half][half] kernel values on the lag grid (double)
+    double* ccos;          // [half][half] weighted cosine matrix (double)
     void* R;               // [n][s] unnormalised repulsion numerators
     void* Fa_ws;           // [n][s] attraction (workspace copy for the step)
     void* Fap;             // [slabs][n][s] attraction partials per column slab

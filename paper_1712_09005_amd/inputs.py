@@ -137,6 +137,10 @@ def perplexity_P(x: np.ndarray, k: int = 90, perplexity: float = 30.0,
     gradient path takes P as given."""
     n = x.shape[0]
     idx, d2 = _knn(x, k, device=device)
+    if device is not None:
+        pc = _calibrate_torch(d2, perplexity, device)
+        rows = np.repeat(np.arange(n, dtype=np.int64), k)
+        return _csr_from_edges(n, rows, idx.ravel(), pc.ravel())
     target = np.log(perplexity)
     beta = np.ones(n)
     lo = np.full(n, -np.inf)
@@ -158,6 +162,56 @@ def perplexity_P(x: np.ndarray, k: int = 90, perplexity: float = 30.0,
     pc = e / e.sum(1, keepdims=True)
     rows = np.repeat(np.arange(n, dtype=np.int64), k)
     return _csr_from_edges(n, rows, idx.ravel(), pc.ravel())
+
+
+def _calibrate_torch(d2: np.ndarray, perplexity: float, device) -> np.ndarray:
+    """The bisection of perplexity_P on a torch device (same steps, float64)."""
+    import torch
+    d = torch.as_tensor(d2, dtype=torch.float64, device=device)
+    d = d - d[:, :1]
+    n = d.shape[0]
+    target = float(np.log(perplexity))
+    beta = torch.ones(n, dtype=torch.float64, device=device)
+    lo = torch.full((n,), -np.inf, dtype=torch.float64, device=device)
+    hi = torch.full((n,), np.inf, dtype=torch.float64, device=device)
+    for _ in range(200):
+        e = torch.exp(-d * beta[:, None])
+        z = e.sum(1)
+        h = torch.log(z) + beta * (d * e).sum(1) / z
+        diff = h - target
+        if bool((diff.abs() < 1e-10).all()):
+            break
+        up = diff > 0
+        lo = torch.where(up, beta, lo)
+        hi = torch.where(up, hi, beta)
+        beta = torch.where(up, torch.where(torch.isinf(hi), beta * 2, (beta + hi) / 2),
+                           torch.where(torch.isinf(lo), beta / 2, (beta + lo) / 2))
+    e = torch.exp(-d * beta[:, None])
+    return (e / e.sum(1, keepdim=True)).cpu().numpy()
+
+
+def serving_jobs(n_jobs: int = 64, k: int = 90, perplexity: float = 30.0, device=None,
+                 n_min: int = 5_000, n_max: int = 200_000):
+    """The serving workload: job j uses seed 100 + j; N log-uniform in
+    [n_min, n_max], K ~ U{5..30} unit-variance clusters in 50-d with centres
+    N(0, 25 I), P from exact k-NN at the given perplexity, Y0 ~ N(0, 1e-4 I).
+    Returns a list of (Y0 float32 [N, 2], P)."""
+    out = []
+    for j in range(n_jobs):
+        rng = np.random.default_rng(100 + j)
+        n = int(round(np.exp(rng.uniform(np.log(n_min), np.log(n_max)))))
+        kc = int(rng.integers(5, 31))
+        x = mixture_highdim(n, 50, kc, 5.0, seed=100 + j)
+        P = perplexity_P(x, k, perplexity, device=device)
+        y = (1e-2 * rng.standard_normal((n, 2))).astype(np.float32)
+        out.append((np.ascontiguousarray(y), P))
+    return out
+
+
+def poisson_arrivals(n: int, rate: float, seed: int = 7) -> np.ndarray:
+    """Arrival times (seconds) of a Poisson process with the given rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
 
 
 def config_inputs(name: str, small: bool = False, device=None):

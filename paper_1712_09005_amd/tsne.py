@@ -205,6 +205,10 @@ class Plan:
     def bind_P(self, row_ptr, col, val):
         if row_ptr.dtype != torch.int64 or col.dtype != torch.int32 or val.dtype != self.dtype:
             raise ValueError("P must be (int64 row_ptr, int32 col, %s val)" % self.dtype)
+        if tuple(row_ptr.shape) != (self.n + 1,) or col.dim() != 1 or \
+                tuple(val.shape) != tuple(col.shape) or col.numel() != self.desc.nnz:
+            raise ValueError("P must have row_ptr [n+1] and col, val [nnz] with nnz = %d"
+                             % self.desc.nnz)
         for t in (row_ptr, col, val):
             if t.device != self.device or not t.is_contiguous():
                 raise ValueError("P arrays must be contiguous on the plan's device")
@@ -304,18 +308,27 @@ class Batch:
     def footprint(n, nnz, s=2, dtype=torch.float32, p=5, policy="fixed", max_intervals=512,
                   interval_width=0.75, min_intervals=1):
         """Device bytes a job holds: plan workspace plus Y, uY, gains and P."""
-        d = make_desc(n, s, dtype, p, policy, "A", min_intervals, max_intervals, interval_width, nnz)
+        d = make_desc(n, s, dtype, p, policy, "A", min_intervals, max_intervals, interval_width, nnz,
+                      lanes_per_row=32, attr_slabs=1, attr_layout=1)
         tsz = 4 if d.dtype == F32 else 8
         return workspace_bytes(d) + 3 * n * s * tsz + 8 * (n + 1) + (4 + tsz) * nnz
 
     def admit(self, Y, P, sched: Schedule, it0, n_it, policy="fixed", min_intervals=1,
-              max_intervals=512, interval_width=0.75):
-        """Admit a job: Y (host or device), P = (row_ptr, col, val) arrays.
-        Returns the slot; the job's tensors stay alive in ``self.jobs``."""
+              max_intervals=512, interval_width=0.75, uY=None, gains=None):
+        """Admit a job: Y (host or device), P = (row_ptr, col, val) arrays,
+        optionally the uY and gains of a job being resumed.  Returns the slot;
+        the job's tensors stay alive in ``self.jobs``."""
         n = Y.shape[0]
         row_ptr, col, val = P
+        if len(Y.shape) != 2 or Y.shape[1] != self.s:
+            raise ValueError("Y must be [n, %d]" % self.s)
+        if tuple(row_ptr.shape) != (n + 1,) or len(col.shape) != 1 or \
+                tuple(val.shape) != tuple(col.shape):
+            raise ValueError("P must have row_ptr [n+1] and col, val [nnz]")
+        # every slot shares one attraction launch: CSR rows, 32 lanes, one slab
         d = make_desc(n, self.s, self.dtype, self.p, policy, self.form, min_intervals,
-                      max_intervals, interval_width, int(col.shape[0]))
+                      max_intervals, interval_width, int(col.shape[0]), lanes_per_row=32,
+                      attr_slabs=1, attr_layout=1)
         nbytes = workspace_bytes(d)
         if nbytes == 0:
             raise TsneError(1, "tsne_workspace_bytes")
@@ -326,8 +339,10 @@ class Batch:
                 rp=torch.as_tensor(row_ptr, dtype=torch.int64).to(self.device).contiguous(),
                 col=torch.as_tensor(col, dtype=torch.int32).to(self.device).contiguous(),
                 val=torch.as_tensor(val, dtype=self.dtype).to(self.device).contiguous())
-            job["uY"] = torch.zeros_like(job["Y"])
-            job["gains"] = torch.ones_like(job["Y"])
+            job["uY"] = torch.zeros_like(job["Y"]) if uY is None else \
+                torch.as_tensor(uY, dtype=self.dtype).to(self.device).contiguous()
+            job["gains"] = torch.ones_like(job["Y"]) if gains is None else \
+                torch.as_tensor(gains, dtype=self.dtype).to(self.device).contiguous()
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
         slot = ctypes.c_int32(-1)
         sc = sched.c()
