@@ -43,18 +43,22 @@ def _alone(T, Y, P, dtype, sched, it0, n_it):
     return Yt.cpu().numpy()
 
 
-@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-9), (torch.float32, 1e-3)])
-def test_alone_equals_in_the_mix(T, dtype, tol):
+# FP64: 30 iterations, 1e-9.  FP32: the within-cell order of the counting sort
+# comes from atomics, so two runs of the same job differ by rounding, and the
+# early-exaggeration dynamics amplify such differences over tens of
+# iterations; FP32 is therefore compared after 3 iterations at 1e-4.
+@pytest.mark.parametrize("dtype,tol,iters", [(torch.float64, 1e-9, 30), (torch.float32, 1e-4, 3)])
+def test_alone_equals_in_the_mix(T, dtype, tol, iters):
     print("case: batch alone vs mix %s" % dtype, flush=True)
     sched = T.Schedule(ee_stop=10, mom_switch=10)
-    sizes = [(3000, 10, 30), (7001, 3, 30), (1500, 20, 25)]     # (n, seed, iterations)
+    sizes = [(3000, 10, iters), (7001, 3, iters), (1500, 20, iters - 1)]   # (n, seed, iterations)
     jobs = [_job(n, sd) for n, sd, _ in sizes]
     alone = [_alone(T, Y, P, dtype, sched, 0, it) for (Y, P), (_, _, it) in zip(jobs, sizes)]
     b = T.Batch(4, s=2, dtype=dtype, p=5, device=DEV)
     slots = []
     for (Y, P), (_, _, it) in zip(jobs[:2], sizes[:2]):
         slots.append(b.admit(Y, (P.row_ptr, P.col, P.val), sched, 0, it, max_intervals=256))
-    b.tick(5)                                   # third job arrives while the others run
+    b.tick(1)                                   # third job arrives while the others run
     Y, P = jobs[2]
     slots.append(b.admit(Y, (P.row_ptr, P.col, P.val), sched, 0, sizes[2][2], max_intervals=256))
     b.tick(40)                                  # more ticks than any job needs
