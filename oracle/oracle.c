@@ -26,8 +26,10 @@
  *     attractive/repulsive split in Section 1.1, so that the gradient is
  *     4 (alpha F_attr - F_rep); eq. (frep) and the Appendix print the
  *     opposite sign;
- *   - nodes of interval l sit at origin + (l p + m + 1/2) h, m = 0..p-1, the
- *     affine image of eq. (equinodes) on the box;
+ *   - the square box (Section 2.4) of side N_int w is centred on each
+ *     dimension's mid-range; nodes of interval l sit at
+ *     origin + (l p + m + 1/2) h, m = 0..p-1, the affine image of eq.
+ *     (equinodes) on the box;
  *   - a point belongs to interval floor((y - origin)/w), clamped to
  *     [0, N_int - 1];
  *   - Z = sum_i h1_i - N K1(0): the grid sums include the self pair, whose
@@ -146,9 +148,11 @@ void oracle_attr(int64_t n, int s, const double* Y, const int64_t* row_ptr,
 /* 2.5 or a fixed interval width)                                            */
 /* ------------------------------------------------------------------------ */
 
-/* Per-dimension origin = min_i y_i(d); side L = max_d (max - min), floored at
- * 1e-6.  PAPER: N_int = max(min_intervals, ceil(L)), w = L / N_int.
- * FIXED: w = interval_width, N_int = max(min_intervals, ceil(L / w)).
+/* Side L = max_d (max - min), floored at 1e-6.  PAPER: N_int =
+ * max(min_intervals, ceil(L)), w = L / N_int.  FIXED: w = interval_width,
+ * N_int = max(min_intervals, ceil(L / w)).  The square box of side N_int w is
+ * centred on the mid-range of each dimension: origin(d) = (min + max)/2 -
+ * N_int w / 2 (for the widest dimension under PAPER this is its minimum).
  * Y holds the float32 inputs widened to double. */
 void oracle_geometry(int64_t n, int s, const double* Y, int policy,
                      int min_intervals, double interval_width,
@@ -163,10 +167,8 @@ void oracle_geometry(int64_t n, int s, const double* Y, int policy,
             if (v > hi[d]) hi[d] = v;
         }
     double L = 0.0;
-    for (int d = 0; d < s; ++d) {
-        origin[d] = lo[d];
+    for (int d = 0; d < s; ++d)
         if (hi[d] - lo[d] > L) L = hi[d] - lo[d];
-    }
     if (L < 1e-6) L = 1e-6;
     int m;
     if (policy == ORACLE_POLICY_PAPER) {
@@ -179,6 +181,7 @@ void oracle_geometry(int64_t n, int s, const double* Y, int policy,
         *w_int = interval_width;
     }
     *n_int = m;
+    for (int d = 0; d < s; ++d) origin[d] = 0.5 * (lo[d] + hi[d]) - 0.5 * m * (*w_int);
 }
 
 /* ------------------------------------------------------------------------ */

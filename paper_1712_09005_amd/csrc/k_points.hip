@@ -179,7 +179,9 @@ __device__ __forceinline__ int ladder(int lo)
 
 // One block per instance: reduce the box partials, decide the iteration
 // (status checks, iteration counter) and its geometry.  Square box (Section
-// 2.4) with the origin at the per-dimension minimum; interval count by the
+// 2.4) of side n_int * w centred on each dimension's mid-range (for the
+// widest dimension under the paper policy the origin is its minimum, and a
+// narrower dimension keeps its points inside the node hull); interval count by the
 // policy (paper: max(min, ceil(L)) as in Section 2.5; fixed: constant width);
 // circulant length M from the 2-3-5 ladder with hysteresis, so the tables are
 // rebuilt only when the node count leaves [M/3, M/2].
@@ -234,7 +236,6 @@ __global__ __launch_bounds__(256) void k_geom(LaunchMap map)
             int st = 0;
             double L = 0.0;
             for (int d = 0; d < S; ++d) {
-                G.origin[d] = glo[d];
                 if (ghi[d] - glo[d] > L) L = ghi[d] - glo[d];
                 G.mean[d] = gsm[d] / (double)I.n;
             }
@@ -266,7 +267,13 @@ __global__ __launch_bounds__(256) void k_geom(LaunchMap map)
                 G.n_int = m;
                 G.n = m * I.p;
                 G.n_cells = (S == 2) ? m * m : m;
-                for (int d = 0; d < S; ++d) G.centre[d] = G.origin[d] + 0.5 * m * w;
+                // explicit roundings (no contraction) so the origin is the
+                // correctly rounded value of mid - (m/2) w
+                const double half_side = __dmul_rn(0.5 * m, w);
+                for (int d = 0; d < S; ++d) {
+                    G.origin[d] = __dsub_rn(__dmul_rn(0.5, __dadd_rn(glo[d], ghi[d])), half_side);
+                    G.centre[d] = __dadd_rn(G.origin[d], half_side);
+                }
                 // power-of-two charge scale: |(y - centre) * qscale| < 1
                 G.qscale = ldexp(1.0, -(ilogb(0.5 * m * w) + 1));
                 // circulant length with hysteresis

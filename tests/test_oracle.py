@@ -105,17 +105,24 @@ def test_direct_invariants(cloud):
 # --------------------------------------------------------------------------
 
 def test_geometry_policies():
-    Y = np.array([[1.0, -2.0], [38.2, 3.0], [5.0, 10.0]])        # width 37.2 in x
-    o, w, m = oracle.geometry(Y, "paper", 50)
-    np.testing.assert_array_equal(o, [1.0, -2.0])
-    assert m == 50 and w == pytest.approx(37.2 / 50, rel=1e-15)
+    """Square box of side N_int w centred on each dimension's mid-range."""
+    Y = np.array([[1.0, -2.0], [38.2, 3.0], [5.0, 10.0]])        # widths 37.2 (x), 12 (y)
     o, w, m = oracle.geometry(Y, "paper", 20)
     assert m == 38 and w == pytest.approx(37.2 / 38, rel=1e-15)
+    np.testing.assert_allclose(o, [1.0, 4.0 - 18.6], rtol=0, atol=1e-13)   # x: its minimum
+    o, w, m = oracle.geometry(Y, "paper", 50)
+    assert m == 50 and w == pytest.approx(37.2 / 50, rel=1e-15)
+    np.testing.assert_allclose(o, [1.0, 4.0 - 18.6], rtol=0, atol=1e-13)
     o, w, m = oracle.geometry(Y, "fixed", 1, 0.75)
     assert m == 50 and w == 0.75                               # ceil(49.6)
+    np.testing.assert_allclose(o, [19.6 - 18.75, 4.0 - 18.75], rtol=0, atol=1e-13)
     Yc = np.zeros((5, 2))                                      # coincident points
     o, w, m = oracle.geometry(Yc, "paper", 50)
     assert m == 50 and w == pytest.approx(1e-6 / 50)
+    np.testing.assert_allclose(o, [-0.5e-6, -0.5e-6], rtol=1e-9)
+    Yt = np.array([[0.01], [0.03]])                            # narrower than one interval
+    o, w, m = oracle.geometry(Yt, "fixed", 1, 0.75)
+    assert m == 1 and o[0] == pytest.approx(0.02 - 0.375)
 
 
 # --------------------------------------------------------------------------
