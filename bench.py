@@ -3,15 +3,19 @@
 
 Workload: N = 1,000,000 points in 2-D drawn from 50 Gaussian clusters (centres
 uniform in [-95, 95]^2, sd 2) with a random 90-neighbour P (about 9e7
-non-zeros), FP32, p = 5 Lagrange nodes per interval of width 0.75.  A step is
+non-zeros), FP32, p = 5 Lagrange nodes per interval; the interval width and
+the launch knobs come from the autotuner (accuracy target 1e-3).  A step is
 one full iteration: box, binning, spreading, FFT convolution, gather and Z,
 attraction and the descent update, replayed from a captured HIP graph.
 
 Prints one JSON line: iterations/s, the roofline of the dominant kernel (the
-CSR attraction, timed with HIP events on the plan's stream) and the CPU
-oracle timed on a bounded sample of the same workload.
+CSR attraction, timed with HIP events on the plan's stream; its measured HBM
+traffic comes from the committed counter summary when that summary was taken
+on the same kernel source and launch knobs) and the CPU oracle timed on a
+bounded sample of the same workload.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -21,6 +25,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_attr_traffic_n1e6_2d.txt")
+ATTR_SOURCE = os.path.join(ROOT, "paper_1712_09005_amd", "csrc", "k_points.hip")
+
+
+def measured_traffic(knobs):
+    """HBM bytes per attraction launch from the counter summary (FETCH_SIZE
+    and WRITE_SIZE, scaled by a plain copy of known size), or None if the
+    summary is missing or was taken on another kernel source or knobs."""
+    try:
+        fields = {}
+        with open(TRAFFIC_SUMMARY) as f:
+            for line in f:
+                if ":" in line and not line.startswith(" "):
+                    k, v = line.split(":", 1)
+                    fields[k.strip()] = v.strip()
+        with open(ATTR_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+        if fields.get("source_sha256") != sha:
+            return None
+        want = "lanes_per_row=%d attr_slabs=%d attr_layout=%d" % (
+            knobs.get("lanes_per_row", 0), knobs.get("attr_slabs", 0), knobs.get("attr_layout", 0))
+        if fields.get("knobs") != want:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -34,7 +64,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--p", type=int, default=5)
-    ap.add_argument("--width", type=float, default=0.75)
+    ap.add_argument("--width", type=float, default=None,
+                    help="interval width (default: autotuned for the 2-D step benchmark, "
+                         "0.75 for the other 2-D workloads, 0.5 in 1-D)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="2-D step benchmark: skip the autotuner (default knobs, width 0.75)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c2", "serve"],
@@ -42,12 +76,17 @@ def main():
                          "run; c2: N=1e5 2-D 1000-iteration run from a 50-d mixture; serve: "
                          "64-job continuous-batching server vs sequential runs")
     ap.add_argument("--jobs", type=int, default=64)
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="after the benchmark, copy a 512 MiB buffer three times (a plain copy "
+                         "kernel of known size that scales HBM counters under a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.workload != "c3":
+        if args.width is None:
+            args.width = 0.5 if args.workload == "c4" else 0.75
         return other_workloads(args)
 
     import numpy as np
@@ -62,8 +101,26 @@ def main():
     log("inputs: n=%d nnz=%d (%.1f s)" % (n, P.nnz, time.time() - t0))
 
     max_int = 512
+    knobs = {}
+    tuned = None
+    if not args.no_tune:
+        # autotuner: interval width for the accuracy target, then launch knobs
+        from paper_1712_09005_amd import autotune
+        t0 = time.time()
+        if args.width is None:
+            tw = autotune.tune_width(Y, target=1e-3, safety=2.0, p=args.p, device=dev, log=log)
+            args.width = tw["interval_width"]
+        ta = autotune.tune_attraction(Y, P, p=args.p, device=dev, log=log)
+        tsp = autotune.tune_spread(Y, p=args.p, interval_width=args.width, max_intervals=max_int,
+                                   device=dev, log=log)
+        knobs = dict(lanes_per_row=ta["lanes_per_row"], attr_slabs=ta["attr_slabs"],
+                     attr_layout=ta["attr_layout"], points_per_lane=tsp["points_per_lane"])
+        tuned = dict(knobs, interval_width=args.width, seconds=round(time.time() - t0, 1))
+        log("autotuned: %s" % tuned)
+    if args.width is None:
+        args.width = 0.75
     plan = tsne.Plan(n, s, torch.float32, p=args.p, policy="fixed", interval_width=args.width,
-                     max_intervals=max_int, nnz=P.nnz, device=dev)
+                     max_intervals=max_int, nnz=P.nnz, device=dev, **knobs)
     st_ = plan.stream
     with torch.cuda.stream(st_):
         Yt = torch.from_numpy(Y).to(dev)
@@ -174,14 +231,29 @@ def main():
                                "random 90-neighbour P",
                    "n": n, "s": s, "nnz": int(P.nnz), "p": args.p, "interval_width": args.width,
                    "n_int": q["n_int"], "fft_len": q["fft_len"], "form": "A",
+                   "autotuned": tuned,
                    "rel_err_rep_numerators_sampled": rel_err},
         "roofline": {"bound": "hbm", "kernel": "k_attr (CSR attraction)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(knobs),
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_us": t_attr * 1e6},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    if args.copy_ref:
+        copy_reference()
+
+
+def copy_reference(nbytes=512 << 20, reps=3):
+    """Device-to-device copies of ``nbytes`` (reads and writes nbytes each)."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copy reference: %d x %d bytes" % (reps, nbytes))
 
 
 def sampled_error(plan, Yt, n, s, rows=512, seed=123):
@@ -286,18 +358,25 @@ def other_workloads(args):
     def jobs_at(arrivals):
         return [serve.Job(j, float(a), y, P) for j, ((y, P), a) in enumerate(zip(specs, arrivals))]
 
+    # autotuner: lanes per row of the shared attraction launch, over a sample of jobs
+    lanes = 32
+    if not args.no_tune:
+        from paper_1712_09005_amd import autotune
+        lanes = autotune.tune_batch_lanes(specs[::8], p=args.p, device=dev, log=log)["lanes_per_row"]
+        log("autotuned lanes per row: %d" % lanes)
     back_to_back = serve.sequential(jobs_at(np.zeros(len(specs))), interval_width=args.width,
-                                    p=args.p, device=dev)
+                                    p=args.p, lanes_per_row=lanes, device=dev)
     rate = 2.0 * back_to_back["runs_per_s"]
     arr = inputs.poisson_arrivals(len(specs), rate, seed=7)
     log("sequential back-to-back: %.2f runs/s; Poisson rate %.2f/s" % (back_to_back["runs_per_s"], rate))
     srv = serve.Server(max_slots=64, hbm_budget=200 << 30, ticks_per_poll=10,
-                       interval_width=args.width, p=args.p, device=dev)
+                       interval_width=args.width, p=args.p, lanes_per_row=lanes, device=dev)
     batched_jobs = jobs_at(arr)
     batched = srv.run(batched_jobs)
     log("batched: %s" % batched)
     seq_jobs = jobs_at(arr)
-    seq = serve.sequential(seq_jobs, interval_width=args.width, p=args.p, device=dev)
+    seq = serve.sequential(seq_jobs, interval_width=args.width, p=args.p, lanes_per_row=lanes,
+                           device=dev)
     log("sequential: %s" % seq)
     # equal accuracy: repulsion error of the final embeddings of the smallest jobs
     import oracle
@@ -320,7 +399,7 @@ def other_workloads(args):
            "config": {"workload": "64 jobs, N log-uniform [5e3, 2e5], 5-30 cluster 50-d mixtures, "
                                   "exact 90-NN perplexity-30 P, Poisson arrivals at 2x the "
                                   "sequential rate", "batched": batched, "sequential_same_trace": seq,
-                      "sequential_back_to_back": back_to_back,
+                      "sequential_back_to_back": back_to_back, "lanes_per_row": lanes,
                       "speedup_runs_per_s": batched["runs_per_s"] / seq["runs_per_s"],
                       "accuracy_final_embeddings": acc}}
     print(json.dumps(out), flush=True)

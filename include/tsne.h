@@ -60,15 +60,18 @@ typedef enum {
 
 typedef enum { TSNE_F32 = 0, TSNE_F64 = 1 } tsne_dtype;
 
-/* Box / interval policy.  In both the box is square with side
- * L = max_d (max_i y_i(d) - min_i y_i(d)) (Section 2.4), origin at the
- * per-dimension minimum, and the nodes of interval l at
- * origin + (l p + m + 1/2) w/p, m = 0..p-1 (eq. (equinodes) mapped onto the box).
+/* Box / interval policy.  With L = max_d (max_i y_i(d) - min_i y_i(d)) the
+ * box is the square (Section 2.4) of side N_int w centred on the mid-range
+ * (max + min)/2 of each dimension, and the nodes of interval l sit at
+ * origin + (l p + m + 1/2) w/p, m = 0..p-1 (eq. (equinodes) mapped onto the
+ * box).  A point y falls in interval clamp(floor((y - origin)/w), 0, N_int-1).
  *   TSNE_GRID_PAPER: N_int = max(min_intervals, ceil(L)), w = L / N_int
  *                    (the interval count of the experiments of Section 2.5);
  *   TSNE_GRID_FIXED: w = interval_width, N_int = max(min_intervals, ceil(L/w)).
- * Under FIXED the node spacing never changes, so the kernel spectra are
- * computed once per plan; under PAPER they are recomputed at every call. */
+ * L is floored at 1e-6.  The FFT length M (a 4^a 3^b 5^c number >= 2 N_int p)
+ * is chosen on the device every call, with hysteresis; the FP64 kernel spectra
+ * are rebuilt whenever M or the node spacing w/p changes: under FIXED only
+ * when M changes, under PAPER at nearly every call. */
 typedef enum { TSNE_GRID_PAPER = 0, TSNE_GRID_FIXED = 1 } tsne_grid_policy;
 
 /* Which s+2 kernel sums are formed (Section 2 and the Appendix).
@@ -209,9 +212,12 @@ typedef struct tsne_batch tsne_batch;
 /* Workspace for the batch's own tables (bytes). */
 size_t tsne_batch_workspace_bytes(int32_t max_slots);
 
+/* lanes_per_row: CSR lanes per row of the shared attraction launch (0 = 32,
+ * else 8, 16, 32 or 64); admitted descriptors must leave it 0 or match.  The
+ * attraction of a batch always uses the CSR layout with one column slab. */
 tsne_status tsne_batch_create(int32_t max_slots, int32_t s, int32_t dtype, int32_t p,
-                              int32_t form, void* workspace, size_t bytes,
-                              void* stream, tsne_batch** out);
+                              int32_t form, int32_t lanes_per_row, void* workspace,
+                              size_t bytes, void* stream, tsne_batch** out);
 tsne_status tsne_batch_destroy(tsne_batch* batch);
 
 /* Admit a job into a free slot.  The job runs iterations [iter0, iter0+n_iter)

@@ -250,9 +250,21 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
         const Geom& Gm = *I.geom;
         const int n = Gm.n, M = Gm.M, n_cap = I.n_cap, tw_ = I.tile_w, half = Gm.half;
         const int Gc = Gm.col_group;                   // columns per block this iteration
-        const int ncg = (I.half + I.col_group - 1) / I.col_group;   // blocks per potential
-        const int pot = lb / ncg, cg = lb - pot * ncg;
-        if (cg * Gc < half) {
+        const int G = tw_ / Gc;                        // blocks per tile of X
+        const int ncg = ((half + tw_ - 1) / tw_) * G;  // blocks per potential this iteration
+        // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin, so
+        // transposing each run of 8 x G virtual blocks puts the G blocks that
+        // share one tile (and so every cache line of it) on the same XCD,
+        // one after another.  A bijection on whole runs; the tail is as is.
+        const int vtotal = (S + 2) * I.ntiles * (tw_ / I.col_group);
+        const int run = 8 * G;
+        int L = lb;
+        if (lb < (vtotal / run) * run) {
+            const int r = lb % run;
+            L = lb - r + (r & 7) * G + (r >> 3);
+        }
+        const int pot = L / ncg, cg = L - pot * ncg;
+        if (pot < S + 2 && cg * Gc < half) {
         int ch, kern;
         pot_of<S, FORM>(pot, ch, kern);
         const cplx<T>* X = static_cast<const cplx<T>*>(I.X) + (int64_t)ch * I.ntiles * n_cap * tw_;

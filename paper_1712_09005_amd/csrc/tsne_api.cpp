@@ -194,7 +194,8 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     vb[K_FIX] = cdiv(o.ncell_cap, 256);
     if (d->s == 2) {
         vb[K_FFT_ROWS] = o.nc * cdiv(o.n_cap, 2);
-        vb[K_FFT_COLS] = o.np * cdiv(o.half, o.col_group);
+        // whole tiles of tile_w / col_group groups each, per potential
+        vb[K_FFT_COLS] = o.np * o.ntiles * (o.tile_w / o.col_group);
         vb[K_FFT_IROWS] = cdiv(o.np, 2) * o.n_cap;
         vb[K_SPEC1] = 2 * cdiv(o.half, 64) * cdiv(o.half, 64);      // 64 x 64 GEMM tiles
         vb[K_SPEC2] = vb[K_SPEC1];
@@ -924,12 +925,16 @@ size_t tsne_batch_workspace_bytes(int32_t max_slots)
 }
 
 tsne_status tsne_batch_create(int32_t max_slots, int32_t s, int32_t dtype, int32_t p, int32_t form,
-                              void* workspace, size_t bytes, void* stream, tsne_batch** out)
+                              int32_t lanes_per_row, void* workspace, size_t bytes, void* stream,
+                              tsne_batch** out)
 {
     if (!out) return TSNE_E_ARG;
     *out = nullptr;
     if (max_slots < 1 || max_slots > 4096 || (s != 1 && s != 2) || (dtype != 0 && dtype != 1) ||
         (form != 0 && form != 1))
+        return TSNE_E_ARG;
+    if (lanes_per_row == 0) lanes_per_row = 32;
+    if (lanes_per_row != 8 && lanes_per_row != 16 && lanes_per_row != 32 && lanes_per_row != 64)
         return TSNE_E_ARG;
     if (p < 2 || p > kMaxP) return TSNE_E_UNSUPPORTED;
     if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || bytes < tsne_batch_workspace_bytes(max_slots))
@@ -948,7 +953,7 @@ tsne_status tsne_batch_create(int32_t max_slots, int32_t s, int32_t dtype, int32
     b->slots.assign(max_slots, Slot{false, nullptr});
     b->dirty = true;
     b->graph_ok = false;
-    b->cfg = Cfg{dtype, s, p, form, 32};
+    b->cfg = Cfg{dtype, s, p, form, lanes_per_row};
     *out = b;
     return TSNE_OK;
 }
@@ -972,12 +977,12 @@ tsne_status tsne_batch_admit(tsne_batch* b, const tsne_desc* desc, void* plan_ws
         return TSNE_E_ARG;
     if (desc->s != b->s || desc->dtype != b->dtype || desc->p != b->p || desc->form != b->form)
         return TSNE_E_ARG;
-    // every slot shares one attraction launch: CSR rows, 32 lanes per row, one slab
-    if ((desc->lanes_per_row != 0 && desc->lanes_per_row != 32) ||
+    // every slot shares one attraction launch: CSR rows, the batch's lanes per row, one slab
+    if ((desc->lanes_per_row != 0 && desc->lanes_per_row != b->cfg.lpr) ||
         (desc->attr_slabs != 0 && desc->attr_slabs != 1) || desc->attr_layout == 2)
         return TSNE_E_UNSUPPORTED;
     tsne_desc dd = *desc;
-    dd.lanes_per_row = 32;
+    dd.lanes_per_row = b->cfg.lpr;
     dd.attr_slabs = 1;
     dd.attr_layout = 1;
     desc = &dd;

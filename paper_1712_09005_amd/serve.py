@@ -67,9 +67,10 @@ def summarize(jobs, makespan: float) -> dict:
 
 class Server:
     def __init__(self, max_slots: int = 64, hbm_budget: int = 200 << 30, ticks_per_poll: int = 10,
-                 interval_width: float = 0.75, p: int = 5, device="cuda"):
+                 interval_width: float = 0.75, p: int = 5, lanes_per_row: int = 32, device="cuda"):
         self.device = torch.device(device)
-        self.batch = tsne.Batch(max_slots, s=2, dtype=torch.float32, p=p, device=self.device)
+        self.batch = tsne.Batch(max_slots, s=2, dtype=torch.float32, p=p,
+                                lanes_per_row=lanes_per_row, device=self.device)
         self.max_slots = max_slots
         self.budget = hbm_budget
         self.k = ticks_per_poll
@@ -135,7 +136,8 @@ class Server:
         return summarize(done, time.perf_counter() - t0)
 
 
-def sequential(jobs, interval_width: float = 0.75, p: int = 5, device="cuda", log=None) -> dict:
+def sequential(jobs, interval_width: float = 0.75, p: int = 5, lanes_per_row: int = 32,
+               device="cuda", log=None) -> dict:
     """The same trace served one job at a time with the unbatched path."""
     dev = torch.device(device)
     t0 = time.perf_counter()
@@ -156,7 +158,8 @@ def sequential(jobs, interval_width: float = 0.75, p: int = 5, device="cuda", lo
         while True:
             plan = tsne.Plan(job.n, 2, torch.float32, p=p, policy="fixed",
                              interval_width=interval_width, max_intervals=cap, nnz=job.P.nnz,
-                             lanes_per_row=32, attr_slabs=1, attr_layout=1, device=dev)
+                             lanes_per_row=lanes_per_row, attr_slabs=1, attr_layout=1,
+                             device=dev)
             plan.bind_P(rp, col, val)
             plan.run(Y, uY, gains, job.sched, it, job.n_iter - it)
             st = plan.query()

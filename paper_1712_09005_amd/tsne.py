@@ -98,7 +98,7 @@ def lib():
             "tsne_debug_export": ([P, i32, P, P], i32),
             "tsne_status_str": ([i32], ctypes.c_char_p),
             "tsne_batch_workspace_bytes": ([i32], ctypes.c_size_t),
-            "tsne_batch_create": ([i32, i32, i32, i32, i32, P, ctypes.c_size_t, P, P], i32),
+            "tsne_batch_create": ([i32, i32, i32, i32, i32, i32, P, ctypes.c_size_t, P, P], i32),
             "tsne_batch_destroy": ([P], i32),
             "tsne_batch_admit": ([P, P, P, ctypes.c_size_t, P, P, P, P, P, P, P, i32, i32, P], i32),
             "tsne_batch_tick": ([P, i32], i32),
@@ -276,9 +276,10 @@ class Plan:
 class Batch:
     """Independent embeddings sharing every launch (tsne_batch_*)."""
 
-    def __init__(self, max_slots, s=2, dtype=torch.float32, p=5, form="A", device="cuda",
-                 stream=None):
+    def __init__(self, max_slots, s=2, dtype=torch.float32, p=5, form="A", lanes_per_row=32,
+                 device="cuda", stream=None):
         self.device = torch.device(device)
+        self.lanes_per_row = int(lanes_per_row)
         self.dtype = torch.float32 if _dt(dtype) == F32 else torch.float64
         self.s, self.p = int(s), int(p)
         self.form = FORM_A if form in ("A", FORM_A) else FORM_B
@@ -290,7 +291,8 @@ class Batch:
             self.ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
         self._h = ctypes.c_void_p()
         _check(lib().tsne_batch_create(int(max_slots), self.s, _dt(self.dtype), self.p, self.form,
-                                       _ptr(self.ws), nb, ctypes.c_void_p(self.stream.cuda_stream),
+                                       self.lanes_per_row, _ptr(self.ws), nb,
+                                       ctypes.c_void_p(self.stream.cuda_stream),
                                        ctypes.byref(self._h)), "tsne_batch_create")
         self.jobs = {}
 
@@ -314,7 +316,7 @@ class Batch:
         return workspace_bytes(d) + 3 * n * s * tsz + 8 * (n + 1) + (4 + tsz) * nnz
 
     def admit(self, Y, P, sched: Schedule, it0, n_it, policy="fixed", min_intervals=1,
-              max_intervals=512, interval_width=0.75, uY=None, gains=None):
+              max_intervals=512, interval_width=0.75, uY=None, gains=None, points_per_lane=0):
         """Admit a job: Y (host or device), P = (row_ptr, col, val) arrays,
         optionally the uY and gains of a job being resumed.  Returns the slot;
         the job's tensors stay alive in ``self.jobs``."""
@@ -325,9 +327,10 @@ class Batch:
         if tuple(row_ptr.shape) != (n + 1,) or len(col.shape) != 1 or \
                 tuple(val.shape) != tuple(col.shape):
             raise ValueError("P must have row_ptr [n+1] and col, val [nnz]")
-        # every slot shares one attraction launch: CSR rows, 32 lanes, one slab
+        # every slot shares one attraction launch: CSR rows, one slab
         d = make_desc(n, self.s, self.dtype, self.p, policy, self.form, min_intervals,
-                      max_intervals, interval_width, int(col.shape[0]), lanes_per_row=32,
+                      max_intervals, interval_width, int(col.shape[0]),
+                      lanes_per_row=self.lanes_per_row, points_per_lane=points_per_lane,
                       attr_slabs=1, attr_layout=1)
         nbytes = workspace_bytes(d)
         if nbytes == 0:
