@@ -100,7 +100,7 @@ def main():
     P = inputs.random_graph_P(n, 90, seed=1)
     log("inputs: n=%d nnz=%d (%.1f s)" % (n, P.nnz, time.time() - t0))
 
-    max_int = 512
+    max_int = 512                     # grid capacity (intervals per dimension)
     knobs = {}
     tuned = None
     if not args.no_tune:
@@ -110,6 +110,9 @@ def main():
         if args.width is None:
             tw = autotune.tune_width(Y, target=1e-3, safety=2.0, p=args.p, device=dev, log=log)
             args.width = tw["interval_width"]
+    if args.width is None:
+        args.width = 0.75
+    if not args.no_tune:
         ta = autotune.tune_attraction(Y, P, p=args.p, device=dev, log=log)
         tsp = autotune.tune_spread(Y, p=args.p, interval_width=args.width, max_intervals=max_int,
                                    device=dev, log=log)
@@ -117,8 +120,6 @@ def main():
                      attr_layout=ta["attr_layout"], points_per_lane=tsp["points_per_lane"])
         tuned = dict(knobs, interval_width=args.width, seconds=round(time.time() - t0, 1))
         log("autotuned: %s" % tuned)
-    if args.width is None:
-        args.width = 0.75
     plan = tsne.Plan(n, s, torch.float32, p=args.p, policy="fixed", interval_width=args.width,
                      max_intervals=max_int, nnz=P.nnz, device=dev, **knobs)
     st_ = plan.stream
@@ -156,16 +157,24 @@ def main():
     ips = K / elapsed
     log("timed: %d iterations in %.4f s -> %.1f it/s" % (K, elapsed, ips))
 
-    # dominant kernel: CSR attraction, HIP events on the plan's stream
+    # dominant kernel: the attraction step (k_attr, plus k_asum summing the
+    # column-slab partials when slabs > 1), timed with HIP events on the
+    # plan's stream over R back-to-back calls through the C ABI
+    import ctypes
     R = 50
     with torch.cuda.stream(st_):
         Fa = torch.empty_like(Yt)
     plan.attractive(Yt, Fa)
+    st_.synchronize()
+    fn = tsne.lib().tsne_attractive
+    yp, fp = ctypes.c_void_p(Yt.data_ptr()), ctypes.c_void_p(Fa.data_ptr())
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record(st_)
     for _ in range(R):
-        plan.attractive(Yt, Fa)
+        rc = fn(plan._h, yp, fp)
+        if rc != 0:
+            raise SystemExit("tsne_attractive failed with status %d" % rc)
     ev1.record(st_)
     ev1.synchronize()
     t_attr = ev0.elapsed_time(ev1) / 1e3 / R
@@ -230,10 +239,12 @@ def main():
         "config": {"workload": "N=1e6 2-D, 50-cluster Gaussian mixture on [-95,95]^2 sd 2, "
                                "random 90-neighbour P",
                    "n": n, "s": s, "nnz": int(P.nnz), "p": args.p, "interval_width": args.width,
-                   "n_int": q["n_int"], "fft_len": q["fft_len"], "form": "A",
+                   "n_int": q["n_int"], "fft_len": q["fft_len"], "max_intervals": max_int,
+                   "form": "A",
                    "autotuned": tuned,
                    "rel_err_rep_numerators_sampled": rel_err},
-        "roofline": {"bound": "hbm", "kernel": "k_attr (CSR attraction)",
+        "roofline": {"bound": "hbm", "kernel": "attraction step: k_attr (+ k_asum when "
+                                               "attr_slabs > 1)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(knobs),
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_us": t_attr * 1e6},

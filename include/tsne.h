@@ -92,7 +92,7 @@ typedef struct {
     int32_t max_intervals;   /* capacity: the largest N_int the plan holds */
     double interval_width;   /* w for TSNE_GRID_FIXED (> 0); ignored otherwise */
     int64_t nnz;             /* non-zeros of P; 0 if attraction is not used */
-    int32_t lanes_per_row;   /* CSR lanes per row: 0 (auto), 8, 16, 32 or 64 */
+    int32_t lanes_per_row;   /* CSR lanes per row: 0 (auto), 4, 8, 16, 32 or 64 */
     int32_t points_per_lane; /* spreading points per lane: 0 (auto), 1..64 */
     int32_t attr_slabs;      /* CSR layout: column slabs of P, 0 (auto), 1, 2, 4 or 8;
                                 each slab is handled by 8/slabs of the 8 XCDs */
@@ -213,7 +213,7 @@ typedef struct tsne_batch tsne_batch;
 size_t tsne_batch_workspace_bytes(int32_t max_slots);
 
 /* lanes_per_row: CSR lanes per row of the shared attraction launch (0 = 32,
- * else 8, 16, 32 or 64); admitted descriptors must leave it 0 or match.  The
+ * else 4, 8, 16, 32 or 64); admitted descriptors must leave it 0 or match.  The
  * attraction of a batch always uses the CSR layout with one column slab. */
 tsne_status tsne_batch_create(int32_t max_slots, int32_t s, int32_t dtype, int32_t p,
                               int32_t form, int32_t lanes_per_row, void* workspace,

@@ -33,7 +33,7 @@ import torch
 from . import tsne
 
 WIDTHS = (1.5, 1.25, 1.0, 0.9, 0.8, 0.75, 0.7, 0.6, 0.5, 0.4, 0.3)
-CSR_KNOBS = [(lpr, sl, 1) for lpr in (8, 16, 32, 64) for sl in (1, 2, 4, 8)] + [(0, 0, 2)]
+CSR_KNOBS = [(lpr, sl, 1) for lpr in (4, 8, 16, 32, 64) for sl in (1, 2, 4, 8)] + [(0, 0, 2)]
 KPTS = (4, 8, 16)
 
 

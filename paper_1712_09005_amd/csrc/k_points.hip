@@ -1064,13 +1064,15 @@ static hipError_t launch_pts(int kind, const Cfg& c, const LaunchMap& map, const
     case K_ZSUM: hipLaunchKernelGGL(k_zsum, g, b, 0, st, map); break;
     case K_NORM: hipLaunchKernelGGL((k_norm<T, S>), g, b, 0, st, map); break;
     case K_ATTR:
-        if (c.lpr == 8) hipLaunchKernelGGL((k_attr<T, S, 8, 4, true>), g, b, 0, st, map);
+        if (c.lpr == 4) hipLaunchKernelGGL((k_attr<T, S, 4, 6, true>), g, b, 0, st, map);
+        else if (c.lpr == 8) hipLaunchKernelGGL((k_attr<T, S, 8, 4, true>), g, b, 0, st, map);
         else if (c.lpr == 16) hipLaunchKernelGGL((k_attr<T, S, 16, 3, true>), g, b, 0, st, map);
         else if (c.lpr == 32) hipLaunchKernelGGL((k_attr<T, S, 32, 3, true>), g, b, 0, st, map);
         else hipLaunchKernelGGL((k_attr<T, S, 64, 2, true>), g, b, 0, st, map);
         break;
     case K_ATTR_ALL:
-        if (c.lpr == 8) hipLaunchKernelGGL((k_attr<T, S, 8, 4, false>), g, b, 0, st, map);
+        if (c.lpr == 4) hipLaunchKernelGGL((k_attr<T, S, 4, 6, false>), g, b, 0, st, map);
+        else if (c.lpr == 8) hipLaunchKernelGGL((k_attr<T, S, 8, 4, false>), g, b, 0, st, map);
         else if (c.lpr == 16) hipLaunchKernelGGL((k_attr<T, S, 16, 3, false>), g, b, 0, st, map);
         else if (c.lpr == 32) hipLaunchKernelGGL((k_attr<T, S, 32, 3, false>), g, b, 0, st, map);
         else hipLaunchKernelGGL((k_attr<T, S, 64, 2, false>), g, b, 0, st, map);

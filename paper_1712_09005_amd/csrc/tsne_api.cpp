@@ -101,7 +101,7 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     if (d->min_intervals < 1 || d->max_intervals < d->min_intervals) return TSNE_E_ARG;
     if (d->policy == TSNE_GRID_FIXED && !(d->interval_width > 0.0)) return TSNE_E_ARG;
     if (d->nnz < 0 || d->nnz > (int64_t)INT_MAX * 8) return TSNE_E_ARG;
-    if (d->lanes_per_row != 0 && d->lanes_per_row != 8 && d->lanes_per_row != 16 &&
+    if (d->lanes_per_row != 0 && d->lanes_per_row != 4 && d->lanes_per_row != 8 && d->lanes_per_row != 16 &&
         d->lanes_per_row != 32 && d->lanes_per_row != 64)
         return TSNE_E_ARG;
     if (d->points_per_lane != 0 && (d->points_per_lane < 1 || d->points_per_lane > 64))
@@ -168,11 +168,11 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     o.row_threads = std::max(256, pow2_at_least(need_row));
     if (o.row_threads > 1024) return TSNE_E_UNSUPPORTED;
     o.row_lds = (size_t)lds_stride(o.M) * csz;
-    // column kernel: LDS for as many columns as fit in 96 KB (at least one);
-    // each iteration packs G = (largest power of two) columns of its own M
+    // column kernel: LDS for one column at capacity, so several workgroups
+    // share a CU and hide each other's barriers and loads; each iteration
+    // packs G = (largest power of two) columns of its own M into that space
     const size_t pm = (size_t)lds_stride(o.M) * csz;   // one padded transform
-    o.col_lds = std::min<size_t>((size_t)o.tile_w * pm, 96 * 1024);
-    o.col_lds = std::max<size_t>(o.col_lds, pm);
+    o.col_lds = pm;
     o.col_group = 1;                                   // columns per block at capacity
     while (o.col_group < o.tile_w && (size_t)(2 * o.col_group) * pm <= o.col_lds) o.col_group *= 2;
     o.col_threads = std::max(256, pow2_at_least(cdiv((int64_t)(o.col_lds / csz), (int64_t)o.rmin * kMaxBfly)));
@@ -934,7 +934,8 @@ tsne_status tsne_batch_create(int32_t max_slots, int32_t s, int32_t dtype, int32
         (form != 0 && form != 1))
         return TSNE_E_ARG;
     if (lanes_per_row == 0) lanes_per_row = 32;
-    if (lanes_per_row != 8 && lanes_per_row != 16 && lanes_per_row != 32 && lanes_per_row != 64)
+    if (lanes_per_row != 4 && lanes_per_row != 8 && lanes_per_row != 16 && lanes_per_row != 32 &&
+        lanes_per_row != 64)
         return TSNE_E_ARG;
     if (p < 2 || p > kMaxP) return TSNE_E_UNSUPPORTED;
     if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || bytes < tsne_batch_workspace_bytes(max_slots))

@@ -157,7 +157,8 @@ def test_c1_against_direct_sum(T):
 
 
 ATTR_LAYOUTS = [  # (lanes per row, slabs, layout): CSR rows, XCD slabs, LDS tiles
-    (8, 1, 1), (16, 1, 1), (32, 1, 1), (64, 1, 1), (8, 4, 1), (16, 2, 1), (32, 8, 1), (0, 0, 2)]
+    (4, 1, 1), (8, 1, 1), (16, 1, 1), (32, 1, 1), (64, 1, 1), (4, 4, 1), (8, 4, 1), (16, 2, 1),
+    (32, 8, 1), (0, 0, 2)]
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
