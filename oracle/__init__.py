@@ -55,6 +55,7 @@ def _load():
             "oracle_direct_sums": [i64, i32, P, i32, P, i64, P, P],
             "oracle_direct_rep": [i64, i32, P, i32, P, P],
             "oracle_attr": [i64, i32, P, P, P, P, P],
+            "oracle_kl": [i64, i32, P, P, P, P, f64],
             "oracle_geometry": [i64, i32, P, i32, i32, f64, P, P, P],
             "oracle_lagrange": [i32, f64, P],
             "oracle_grid_conv": [i32, i32, f64, i32, i32, P, P],
@@ -70,6 +71,7 @@ def _load():
             fn = getattr(_lib, name)
             fn.argtypes = args
             fn.restype = ctypes.c_int if name.startswith("oracle_interp") else None
+        _lib.oracle_kl.restype = f64
     return _lib
 
 
@@ -125,6 +127,19 @@ def attr(Y, P):
     F = np.empty((n, s))
     _load().oracle_attr(n, s, _ptr(Y), _ptr(rp), _ptr(col), _ptr(val), _ptr(F))
     return F
+
+
+def kl(Y, P, Z=None):
+    """KL(P || Q) over the non-zeros of P with q_ij = K1(y_i, y_j) / Z
+    (Section 1.1).  Z defaults to the direct sum over ordered pairs."""
+    Y = _f64(Y)
+    n, s = Y.shape
+    if Z is None:
+        Z = direct_rep(Y)[1]
+    rp = np.ascontiguousarray(P.row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(P.col, dtype=np.int32)
+    val = _f64(P.val)
+    return float(_load().oracle_kl(n, s, _ptr(Y), _ptr(rp), _ptr(col), _ptr(val), float(Z)))
 
 
 # ---------------------------------------------------------------- geometry

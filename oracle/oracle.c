@@ -143,6 +143,28 @@ void oracle_attr(int64_t n, int s, const double* Y, const int64_t* row_ptr,
     }
 }
 
+/* Kullback-Leibler divergence of Section 1.1, written out from its
+ * definition: C = sum over the non-zeros p_ij of P of p_ij log(p_ij / q_ij),
+ * with q_ij = K1(y_i, y_j) / Z and K1 = 1 / (1 + |y_i - y_j|^2).  Z is an
+ * argument: the direct sum over ordered pairs i != j (oracle_direct_rep) or
+ * the interpolated one of oracle_interp_rep.  Zero entries contribute 0. */
+double oracle_kl(int64_t n, int s, const double* Y, const int64_t* row_ptr,
+                 const int32_t* col, const double* val, double Z)
+{
+    double acc = 0.0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : acc)
+    for (int64_t i = 0; i < n; ++i) {
+        const double* yi = Y + i * s;
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            const double p = val[k];
+            if (p <= 0.0) continue;
+            const double q = (1.0 / (1.0 + sqdist(s, yi, Y + (int64_t)col[k] * s))) / Z;
+            acc += p * log(p / q);
+        }
+    }
+    return acc;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Box geometry (the square box of Section 2.4; interval count of Section    */
 /* 2.5 or a fixed interval width)                                            */

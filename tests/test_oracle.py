@@ -405,3 +405,40 @@ def test_perplexity_P_rows():
     import scipy.sparse as sp
     A = sp.csr_matrix((P.val, P.col, P.row_ptr), shape=(600, 600))
     assert abs(A - A.T).max() < 1e-9
+
+
+# --------------------------------------------------------------------------
+# Kullback-Leibler divergence (Section 1.1)
+# --------------------------------------------------------------------------
+
+def test_kl_hand_computed_and_two_points():
+    g = _golden("three_points_1d.json")
+    Y = np.array(g["Y"])[:, None]
+    P = inputs.CSR(np.array(g["P_row_ptr"]), np.array(g["P_col"], np.int32), np.array(g["P_val"]))
+    assert oracle.kl(Y, P) == pytest.approx(g["KL"], rel=1e-14)
+    # N = 2 with p12 = p21 = 1/2: q12 = q21 = 1/2 at any distance, so C = 0
+    P2 = inputs.CSR(np.array([0, 1, 2]), np.array([1, 0], np.int32), np.array([0.5, 0.5]))
+    for d in (0.1, 3.0, 40.0):
+        assert abs(oracle.kl(np.array([[0.0, 0.0], [d, -d]]), P2)) < 1e-15
+
+
+def test_kl_zero_when_p_equals_q_and_positive_otherwise():
+    """Gibbs' inequality: C >= 0 with equality exactly when P = Q; P built
+    from the embedding's own Q over every ordered pair gives 0."""
+    rng = np.random.default_rng(31)
+    Y = rng.normal(size=(9, 2)) * 2.0
+    n = Y.shape[0]
+    d2 = ((Y[:, None, :] - Y[None, :, :]) ** 2).sum(-1)
+    K = 1.0 / (1.0 + d2)
+    np.fill_diagonal(K, 0.0)
+    Q = K / K.sum()
+    rows, cols = np.nonzero(Q)
+    P = inputs.CSR(np.searchsorted(rows, np.arange(n + 1)).astype(np.int64),
+                   cols.astype(np.int32), Q[rows, cols])
+    assert abs(oracle.kl(Y, P)) < 1e-14
+    # any other P: strictly positive; a translated copy gives the same value
+    Pr = inputs.random_graph_P(n, 4, seed=3)
+    Pd = inputs.CSR(Pr.row_ptr, Pr.col, Pr.val.astype(np.float64))
+    c = oracle.kl(Y, Pd)
+    assert c > 0.0
+    assert oracle.kl(Y + np.array([5.0, -2.0]), Pd) == pytest.approx(c, rel=1e-12)
