@@ -182,6 +182,22 @@ def main():
     achieved = alg_bytes / t_attr / 1e9
     log("attraction: %.1f us per launch, %.1f GB/s algorithmic" % (t_attr * 1e6, achieved))
 
+    # KL divergence at the final Y: the repulsion chain for Z plus one pass
+    # over P (not part of a step), timed the same way
+    with torch.cuda.stream(st_):
+        klv = torch.empty(1, dtype=torch.float64, device=dev)
+    fnk = tsne.lib().tsne_kl_divergence
+    kp = ctypes.c_void_p(klv.data_ptr())
+    if fnk(plan._h, yp, kp) != 0:
+        raise SystemExit("tsne_kl_divergence failed")
+    ev0.record(st_)
+    for _ in range(20):
+        fnk(plan._h, yp, kp)
+    ev1.record(st_)
+    ev1.synchronize()
+    kl_info = {"value": float(klv.item()), "ms_per_call": ev0.elapsed_time(ev1) / 20}
+    log("KL divergence %.6f, %.3f ms per call" % (kl_info["value"], kl_info["ms_per_call"]))
+
     # accuracy on sampled rows against the direct sum (repulsion numerators)
     rel_err = None
     cpu = None
@@ -241,7 +257,7 @@ def main():
                    "n": n, "s": s, "nnz": int(P.nnz), "p": args.p, "interval_width": args.width,
                    "n_int": q["n_int"], "fft_len": q["fft_len"], "max_intervals": max_int,
                    "form": "A",
-                   "autotuned": tuned,
+                   "autotuned": tuned, "kl_divergence": kl_info,
                    "rel_err_rep_numerators_sampled": rel_err},
         "roofline": {"bound": "hbm", "kernel": "attraction step: k_attr (+ k_asum when "
                                                "attr_slabs > 1)",

@@ -183,6 +183,15 @@ tsne_status tsne_step(tsne_plan* plan, void* Y, void* uY, void* gains,
 tsne_status tsne_run(tsne_plan* plan, void* Y, void* uY, void* gains,
                      const tsne_sched* sched, int32_t iter0, int32_t n_iter);
 
+/* Kullback-Leibler divergence C = KL(P || Q) of Section 1.1 at Y, with
+ * q_ij = K1(y_i, y_j) / Z: the repulsion's interpolated Z (Section 2) and one
+ * pass over the bound P, C = sum p log(p (1 + |y_i - y_j|^2)) + (sum p) log Z.
+ * Y [n, s] device; *kl one device double, written when the enqueued work
+ * completes.  Needs a bound P (TSNE_E_STATE otherwise); Y, uY, gains and the
+ * iteration counter are not touched.  The logarithms run in the element type,
+ * the sums in FP64. */
+tsne_status tsne_kl_divergence(tsne_plan* plan, const void* Y, double* kl);
+
 /* Synchronise the plan's stream, fill *out (host) and clear the latched
  * device status. */
 tsne_status tsne_query(tsne_plan* plan, tsne_stats* out);

@@ -25,6 +25,7 @@ struct CallArgs {
     void* Frep;
     double* Zout;
     void* Fattr;
+    double* KLout;
     const int64_t* row_ptr;
     const int32_t* col;
     const void* val;

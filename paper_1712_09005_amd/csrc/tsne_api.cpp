@@ -72,7 +72,7 @@ struct Layout {
 enum Region {
     R_INST, R_PREFIX, R_GEOM, R_SCHED, R_SMALL, R_BOX, R_COUNTS, R_CSTART, R_ISTART, R_SCAN,
     R_ICELL, R_KEY, R_RANK, R_PERM, R_SY, R_CARRY, R_W, R_X, R_XC, R_V, R_SPEC, R_TW, R_COS,
-    R_SPECTMP, R_KTAB, R_CCOS, R_R, R_FA, R_FAP, R_SPLIT, R_TOFF, R_EPACK, R_EVAL, R_ZPART, R_N
+    R_SPECTMP, R_KTAB, R_CCOS, R_R, R_FA, R_FAP, R_SPLIT, R_TOFF, R_EPACK, R_EVAL, R_ZPART, R_KLPART, R_N
 };
 
 struct Derived {
@@ -82,7 +82,7 @@ struct Derived {
     int tiled, tile_bi, tile_bj, tile_ni, tile_nj;
     size_t tile_lds;
     int tile_w, ntiles, col_group;
-    int nb_box, nb_gather, nb_scan, nwaves;
+    int nb_box, nb_gather, nb_scan, nwaves, nb_kl;
     int row_threads, col_threads;
     size_t row_lds, col_lds;
     int vb[K_NKINDS];
@@ -181,6 +181,7 @@ tsne_status derive(const tsne_desc* d, Derived& o)
 
     o.nb_box = std::min(512, std::max(1, cdiv(n, 256 * 4)));
     o.nb_gather = cdiv(n, 256);
+    o.nb_kl = (int)std::min<int64_t>(2048, cdiv(n, 8));
     o.nb_scan = cdiv(o.ncell_cap, 1024);
 
     int* vb = o.vb;
@@ -219,6 +220,8 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     vb[K_UPDATE] = cdiv(n, 256);
     vb[K_GEOM] = 1;
     vb[K_ZSUM] = 1;
+    vb[K_KL] = (d->nnz > 0) ? o.nb_kl : 0;
+    vb[K_KLSUM] = (d->nnz > 0) ? 1 : 0;
 
     // workspace layout
     const int64_t grid = (d->s == 2) ? (int64_t)o.n_cap * o.n_cap : o.n_cap;
@@ -267,6 +270,7 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     sz[R_EPACK] = o.tiled ? sizeof(uint32_t) * (size_t)d->nnz : 0;
     sz[R_EVAL] = o.tiled ? (size_t)o.tsz * d->nnz : 0;
     sz[R_ZPART] = sizeof(double) * o.nb_gather;
+    sz[R_KLPART] = (d->nnz > 0) ? sizeof(double) * 2 * o.nb_kl : 0;
     size_t cur = 0;
     for (int r = 0; r < R_N; ++r) {
         o.L.off[r] = cur;
@@ -338,7 +342,8 @@ static tsne_status set_ptrs(tsne_plan* pl, const CallArgs& a)
     if (pl->args_valid && a.Yin == pl->last_args.Yin && a.Y == pl->last_args.Y &&
         a.uY == pl->last_args.uY && a.gains == pl->last_args.gains &&
         a.Frep == pl->last_args.Frep && a.Zout == pl->last_args.Zout &&
-        a.Fattr == pl->last_args.Fattr && a.counting == pl->last_args.counting)
+        a.Fattr == pl->last_args.Fattr && a.KLout == pl->last_args.KLout &&
+        a.counting == pl->last_args.counting)
         return TSNE_OK;
     if (!hip_ok(launch_set_args(pl->dinst, a, pl->st))) return TSNE_E_HIP;
     pl->last_args = a;
@@ -500,6 +505,9 @@ tsne_status tsne_plan_create(const tsne_desc* desc, void* workspace, size_t byte
     h.R = b + off[R_R];
     h.Fa_ws = b + off[R_FA];
     h.z_part = reinterpret_cast<double*>(b + off[R_ZPART]);
+    h.kl_part = reinterpret_cast<double*>(b + off[R_KLPART]);
+    h.KLout = nullptr;
+    h.nb_kl = o.nb_kl;
     h.Fap = b + off[R_FAP];
     h.split = reinterpret_cast<const int*>(b + off[R_SPLIT]);
     h.slabs = o.slabs;
@@ -670,6 +678,24 @@ tsne_status tsne_attractive(tsne_plan* pl, const void* Y, void* F_attr)
     s = enqueue(pl, K_ATTR_T_ALL);
     if (s != TSNE_OK) return s;
     return enqueue(pl, K_ASUM);
+}
+
+tsne_status tsne_kl_divergence(tsne_plan* pl, const void* Y, double* kl)
+{
+    if (!pl || !Y || !kl) return TSNE_E_ARG;
+    if (!pl->P_bound) return TSNE_E_STATE;
+    CallArgs a = no_args();
+    a.set_ptrs = 1;
+    a.Yin = Y;
+    a.Fattr = pl->h.Fa_ws;
+    a.KLout = kl;
+    tsne_status s = set_ptrs(pl, a);
+    if (s != TSNE_OK) return s;
+    s = enqueue_repulsion(pl, false);
+    if (s != TSNE_OK) return s;
+    s = enqueue(pl, K_KL);
+    if (s != TSNE_OK) return s;
+    return enqueue(pl, K_KLSUM);
 }
 
 static tsne_status step_args(tsne_plan* pl, void* Y, void* uY, void* gains, const tsne_sched* sc,

@@ -23,7 +23,8 @@ constexpr int kWave = 64;
 enum Kind : int {
     K_ARGS = 0, K_BOX, K_KEY, K_SCAN_A, K_SCAN_B, K_SCATTER, K_SPREAD, K_FIX,
     K_FFT_ROWS, K_FFT_COLS, K_FFT_IROWS, K_FFT_1D, K_GATHER, K_NORM, K_ATTR,
-    K_UPDATE, K_SPEC0, K_SPEC1, K_SPEC2, K_GEOM, K_ZSUM, K_ATTR_ALL, K_ASUM, K_ATTR_T, K_ATTR_T_ALL, K_NKINDS
+    K_UPDATE, K_SPEC0, K_SPEC1, K_SPEC2, K_GEOM, K_ZSUM, K_ATTR_ALL, K_ASUM, K_ATTR_T, K_ATTR_T_ALL,
+    K_KL, K_KLSUM, K_NKINDS
 };
 
 // Status bits latched on the device (values of tsne_status).
@@ -133,7 +134,9 @@ struct Inst {
     const uint32_t* epack; // [nnz] (row in block << 16) | column in block
     const void* eval;      // [nnz] values in tile order
     double* z_part;        // [nb_gather]
-    int nb_box, nb_gather, nb_scan, nwaves;
+    double* kl_part;       // [nb_kl][2] divergence partials (sum p log(p/K1), sum p)
+    double* KLout;         // caller's divergence output (device, may be null)
+    int nb_box, nb_gather, nb_scan, nwaves, nb_kl;
 };
 
 // Launch table: first virtual block of each instance per kernel kind.

@@ -92,6 +92,7 @@ def lib():
             "tsne_bind_P": ([P, P, P, P], i32),
             "tsne_repulsive": ([P, P, P, P], i32),
             "tsne_attractive": ([P, P, P], i32),
+            "tsne_kl_divergence": ([P, P, P], i32),
             "tsne_step": ([P, P, P, P, P, i32], i32),
             "tsne_run": ([P, P, P, P, P, i32, i32], i32),
             "tsne_query": ([P, P], i32),
@@ -237,6 +238,17 @@ class Plan:
         _check(lib().tsne_attractive(self._h, _ptr(Y), _ptr(F)), "tsne_attractive")
         self._leave()
         return F
+
+    def kl_divergence(self, Y, out=None):
+        """KL(P || Q) at Y as a one-element float64 device tensor."""
+        self._vec(Y, "Y")
+        with torch.cuda.stream(self.stream):
+            if out is None:
+                out = torch.empty(1, dtype=torch.float64, device=self.device)
+        self._enter()
+        _check(lib().tsne_kl_divergence(self._h, _ptr(Y), _ptr(out)), "tsne_kl_divergence")
+        self._leave()
+        return out
 
     def step(self, Y, uY, gains, sched: Schedule, it: int):
         for t, nm in ((Y, "Y"), (uY, "uY"), (gains, "gains")):
