@@ -892,74 +892,116 @@ __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
     VB_END
 }
 
-// Attraction over tiles of P: edges re-bucketed (at bind time) by row block
-// of tile_bi rows and column block of tile_bj columns, rows increasing within
-// a tile.  One workgroup per row block keeps that block's positions and force
-// sums in LDS and walks the column blocks in order, staging each block's
-// positions in LDS; every neighbour position then comes from LDS instead of a
-// random global gather, and all workgroups sweep the column blocks in the same
-// order, so the staged blocks are shared through L2.  Per-row sums use LDS
-// atomics in the element type.
+// Attraction over tiles of P: edges re-bucketed (at bind time) by row block of
+// tile_bi rows and column block of tile_bj columns, rows increasing within a
+// tile.  One 1024-thread workgroup per row block keeps that block's positions
+// and force sums in LDS and sweeps the column blocks in order.  The sweep is
+// software-pipelined two steps deep: the positions of column block J+2 and
+// the first edges of tile J+2 are requested while tile J is processed from LDS,
+// and block J+1 (requested a step earlier) is stored to the other half of a
+// double-buffered LDS area at the end of the step; each step costs one
+// barrier.  Every neighbour position comes from LDS instead of a random global
+// gather; per-row sums use LDS atomics in the element type.
+template <typename T, int S>
+struct TileEdges {
+    static constexpr int UE = 4;   // edges per thread carried between steps
+    uint32_t k[UE];
+    T v[UE];
+};
+
 template <typename T, int S, bool GATED>
 __global__ __launch_bounds__(1024) void k_attr_tile(LaunchMap map)
 {
     typedef typename Vec<T, S>::t V;
-    constexpr int U = 2;
+    constexpr int NT = 1024;       // threads (the launch uses exactly this)
+    constexpr int UE = TileEdges<T, S>::UE;
+    constexpr int PJ = 4;          // positions per thread per column block (tile_bj <= 4096)
+    constexpr uint32_t kNone = 0xffffffffu;
     extern __shared__ __align__(16) char smem[];
     VB_BEGIN_IF(map, GATED ? K_ATTR_T : K_ATTR_T_ALL, (!GATED || live(I)))
     {
         const int BI = I.tile_bi, BJ = I.tile_bj, nj = I.tile_nj;
         const int64_t n = I.n;
-        V* yJ = reinterpret_cast<V*>(smem);
-        V* yI = yJ + BJ;
+        const int tid = (int)threadIdx.x;
+        V* yI = reinterpret_cast<V*>(smem);
         T* f = reinterpret_cast<T*>(yI + BI);
+        V* yJbuf = reinterpret_cast<V*>(f + (int64_t)BI * S);
         const V* Y = static_cast<const V*>(I.Yin);
+        V zero;
+        if constexpr (S == 2) zero = V{(T)0, (T)0}; else zero = (T)0;
         const int i0 = lb * BI;
         const int rows = (int)min((int64_t)BI, n - i0);
-        for (int r = threadIdx.x; r < BI; r += blockDim.x) {
-            V z;
-            if constexpr (S == 2) z = V{(T)0, (T)0}; else z = (T)0;
-            yI[r] = (r < rows) ? Y[i0 + r] : z;
+        for (int r = tid; r < BI; r += NT) {
+            yI[r] = (r < rows) ? Y[i0 + r] : zero;
 #pragma unroll
             for (int d = 0; d < S; ++d) f[r * S + d] = (T)0;
         }
         const int64_t* to = I.toff + (int64_t)lb * nj;
         const uint32_t* ep = I.epack;
         const T* ev = static_cast<const T*>(I.eval);
-        for (int J = 0; J < nj; ++J) {
-            const int64_t e0 = to[J], e1 = to[J + 1];
-            if (e0 == e1) continue;
-            const int j0 = J * BJ;
-            const int cols = (int)min((int64_t)BJ, n - j0);
-            __syncthreads();
-            for (int c = threadIdx.x; c < cols; c += blockDim.x) yJ[c] = Y[j0 + c];
-            __syncthreads();
-            for (int64_t e = e0 + threadIdx.x; e < e1; e += (int64_t)blockDim.x * U) {
-                uint32_t pk[U];
-                T pv[U];
+        auto load_pos = [&](int J, V (&pos)[PJ]) {
+            const int64_t j0 = (int64_t)J * BJ;
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int64_t k = e + (int64_t)u * blockDim.x;
-                    pk[u] = (k < e1) ? ep[k] : 0xffffffffu;
-                    pv[u] = (k < e1) ? ev[k] : (T)0;
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    if (pk[u] == 0xffffffffu) continue;
-                    const int il = (int)(pk[u] >> 16), jl = (int)(pk[u] & 0xffffu);
-                    const V a = yI[il], b = yJ[jl];
-                    T d0, d1 = (T)0;
-                    if constexpr (S == 2) { d0 = a.x - b.x; d1 = a.y - b.y; }
-                    else { d0 = a - b; }
-                    const T wgt = pv[u] * recip((T)1 + d0 * d0 + d1 * d1);
-                    atomicAdd(&f[il * S], wgt * d0);
-                    if (S == 2) atomicAdd(&f[il * S + 1], wgt * d1);
-                }
+            for (int q = 0; q < PJ; ++q) {
+                const int c = tid + q * NT;
+                pos[q] = (c < BJ && j0 + c < n) ? Y[j0 + c] : zero;
             }
+        };
+        auto store_pos = [&](int J, const V (&pos)[PJ]) {
+            V* b = yJbuf + (J & 1) * BJ;
+#pragma unroll
+            for (int q = 0; q < PJ; ++q) {
+                const int c = tid + q * NT;
+                if (c < BJ) b[c] = pos[q];
+            }
+        };
+        auto load_edges = [&](int J, TileEdges<T, S>& e) {
+            const int64_t e0 = to[J], e1 = to[J + 1];
+#pragma unroll
+            for (int u = 0; u < UE; ++u) {
+                const int64_t k = e0 + tid + (int64_t)u * NT;
+                e.k[u] = (k < e1) ? ep[k] : kNone;
+                e.v[u] = (k < e1) ? ev[k] : (T)0;
+            }
+        };
+        auto edge = [&](uint32_t pk, T pv, const V* yJ) {
+            const int il = (int)(pk >> 16), jl = (int)(pk & 0xffffu);
+            const V a = yI[il], b = yJ[jl];
+            T d0, d1 = (T)0;
+            if constexpr (S == 2) { d0 = a.x - b.x; d1 = a.y - b.y; }
+            else { d0 = a - b; }
+            const T wgt = pv * recip((T)1 + d0 * d0 + d1 * d1);
+            atomicAdd(&f[il * S], wgt * d0);
+            if (S == 2) atomicAdd(&f[il * S + 1], wgt * d1);
+        };
+        V posA[PJ], posB[PJ];
+        TileEdges<T, S> eA, eB, cur;
+        // prologue: block 0 staged; block 1 and the edges of tiles 0 and 1 requested
+        load_pos(0, posA);
+        store_pos(0, posA);
+        if (nj > 1) load_pos(1, posA);
+        load_edges(0, eA);
+        if (nj > 1) load_edges(1, eB);
+        for (int J = 0; J < nj; ++J) {
+            __syncthreads();   // block J staged, yI / f ready, the other buffer free
+            if (J + 2 < nj) load_pos(J + 2, posB);
+            cur = eA;
+            eA = eB;
+            if (J + 2 < nj) load_edges(J + 2, eB);
+            const V* yJ = yJbuf + (J & 1) * BJ;
+#pragma unroll
+            for (int u = 0; u < UE; ++u)
+                if (cur.k[u] != kNone) edge(cur.k[u], cur.v[u], yJ);
+            // a tile with more than NT * UE edges: the rest directly
+            const int64_t e1 = to[J + 1];
+            for (int64_t k = to[J] + (int64_t)NT * UE + tid; k < e1; k += NT) edge(ep[k], ev[k], yJ);
+            if (J + 1 < nj) store_pos(J + 1, posA);
+#pragma unroll
+            for (int q = 0; q < PJ; ++q) posA[q] = posB[q];
         }
         __syncthreads();
         T* F = static_cast<T*>(I.Fattr);
-        for (int r = threadIdx.x; r < rows * S; r += blockDim.x) F[(int64_t)i0 * S + r] = f[r];
+        for (int r = tid; r < rows * S; r += NT) F[(int64_t)i0 * S + r] = f[r];
         __syncthreads();
     }
     VB_END

@@ -144,16 +144,18 @@ tsne_status derive(const tsne_desc* d, Derived& o)
         o.slabs = sl;
         o.slab_w = (int)((d->n + sl - 1) / sl);
     }
-    // attraction layout: CSR rows unless tiles are asked for (tiles measured
-    // slower at N = 1e6: 1480 us, one 128 KB-LDS workgroup per CU)
+    // attraction layout: CSR rows unless tiles are asked for.  Tiles: square
+    // blocks of 4096 (FP32) or 2048 (FP64) points; LDS holds the row block's
+    // positions and sums and two column blocks (128 KB in 2-D); the kernel
+    // stages at most 4 positions per thread per column block (4096 / 1024).
     o.tiled = (d->nnz > 0) && d->attr_layout == 2;
     o.tile_bi = (d->dtype == TSNE_F32) ? 4096 : 2048;
-    o.tile_bj = 2 * o.tile_bi;
+    o.tile_bj = o.tile_bi;
     o.tile_ni = (int)((d->n + o.tile_bi - 1) / o.tile_bi);
     o.tile_nj = (int)((d->n + o.tile_bj - 1) / o.tile_bj);
     {
         const size_t tsz_ = (d->dtype == TSNE_F32) ? 4 : 8;
-        o.tile_lds = (size_t)(o.tile_bi + o.tile_bj) * d->s * tsz_ + (size_t)o.tile_bi * d->s * tsz_;
+        o.tile_lds = (size_t)(2 * o.tile_bi + 2 * o.tile_bj) * d->s * tsz_;
     }
     if (o.tiled) o.slabs = 1;
     const int64_t n = d->n;
