@@ -76,6 +76,9 @@ def main():
                          "run; c2: N=1e5 2-D 1000-iteration run from a 50-d mixture; serve: "
                          "64-job continuous-batching server vs sequential runs")
     ap.add_argument("--jobs", type=int, default=64)
+    ap.add_argument("--slots", type=str, default="64",
+                    help="serving: batch slots (jobs live at once); a comma list runs the "
+                         "batched server once per value and reports each")
     ap.add_argument("--copy-ref", action="store_true",
                     help="after the benchmark, copy a 512 MiB buffer three times (a plain copy "
                          "kernel of known size that scales HBM counters under a profiler)")
@@ -396,11 +399,16 @@ def other_workloads(args):
     rate = 2.0 * back_to_back["runs_per_s"]
     arr = inputs.poisson_arrivals(len(specs), rate, seed=7)
     log("sequential back-to-back: %.2f runs/s; Poisson rate %.2f/s" % (back_to_back["runs_per_s"], rate))
-    srv = serve.Server(max_slots=64, hbm_budget=200 << 30, ticks_per_poll=10,
-                       interval_width=args.width, p=args.p, lanes_per_row=lanes, device=dev)
-    batched_jobs = jobs_at(arr)
-    batched = srv.run(batched_jobs)
-    log("batched: %s" % batched)
+    slot_list = [int(x) for x in args.slots.split(",")]
+    runs = {}
+    for k in slot_list:
+        srv = serve.Server(max_slots=k, hbm_budget=200 << 30, ticks_per_poll=10,
+                           interval_width=args.width, p=args.p, lanes_per_row=lanes, device=dev)
+        jobs_k = jobs_at(arr)
+        runs[k] = (srv.run(jobs_k), jobs_k)
+        log("batched, %d slots: %s" % (k, runs[k][0]))
+        del srv
+    batched, batched_jobs = runs[slot_list[0]]
     seq_jobs = jobs_at(arr)
     seq = serve.sequential(seq_jobs, interval_width=args.width, p=args.p, lanes_per_row=lanes,
                            device=dev)
@@ -427,6 +435,8 @@ def other_workloads(args):
                                   "exact 90-NN perplexity-30 P, Poisson arrivals at 2x the "
                                   "sequential rate", "batched": batched, "sequential_same_trace": seq,
                       "sequential_back_to_back": back_to_back, "lanes_per_row": lanes,
+                      "slots": slot_list[0],
+                      "batched_by_slots": {str(k): v[0] for k, v in runs.items()},
                       "speedup_runs_per_s": batched["runs_per_s"] / seq["runs_per_s"],
                       "accuracy_final_embeddings": acc}}
     print(json.dumps(out), flush=True)
