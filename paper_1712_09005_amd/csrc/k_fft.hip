@@ -114,22 +114,22 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int M, int PM, int G, in
                                           const cplx<T>* __restrict__ tws)
 {
     const int Mr = M / R;
-    const int nb = G * Mr;
-    const float rMr = 1.0f / (float)Mr, rNs = 1.0f / (float)Ns;
-    const int nthr = blockDim.x;
-    const int nbt = (nb + nthr - 1) / nthr;
+    const float rNs = 1.0f / (float)Ns;
+    // the threads split evenly over the G transforms (G and the block size are
+    // powers of two), so a thread's transform is fixed for the whole stage
+    const int tpc = (int)blockDim.x / G;
+    const int g = (int)threadIdx.x >> (__ffs(tpc) - 1);
+    const int jt = (int)threadIdx.x - g * tpc;
+    const int nbt = (Mr + tpc - 1) / tpc;
+    const cplx<T>* src = buf + g * PM;
     cplx<T> v[kMaxB][R];
-    int dst[kMaxB], dbase[kMaxB];
+    int dst[kMaxB];
 #pragma unroll
     for (int b = 0; b < kMaxB; ++b) {
         if (b >= nbt) break;
-        const int idx = threadIdx.x + b * nthr;
+        const int j = jt + b * tpc;
         dst[b] = -1;
-        dbase[b] = 0;
-        if (idx < nb) {
-            const int g = fdiv(idx, Mr, rMr);
-            const int j = idx - g * Mr;
-            const cplx<T>* src = buf + g * PM;
+        if (j < Mr) {
             const int a = fdiv(j, Ns, rNs);
             const int k = j - a * Ns;
 #pragma unroll
@@ -140,16 +140,15 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int M, int PM, int G, in
                 for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], t[r - 1]);
             }
             Dft<T, R>::run(v[b]);
-            dbase[b] = g * PM;
             dst[b] = a * Ns * R + k;
         }
     }
     __syncthreads();
+    cplx<T>* out = buf + g * PM;
 #pragma unroll
     for (int b = 0; b < kMaxB; ++b) {
         if (b >= nbt) break;
         if (dst[b] >= 0) {
-            cplx<T>* out = buf + dbase[b];
 #pragma unroll
             for (int r = 0; r < R; ++r) out[lds_pad(dst[b] + r * Ns)] = v[b][r];
         }
