@@ -225,11 +225,12 @@ __global__ __launch_bounds__(1024) void k_fft_rows(LaunchMap map)
             block_fft<T>(buf, 1, I, G);
             cplx<T>* X = static_cast<cplx<T>*>(I.X) + (int64_t)ch * I.ntiles * n_cap * tw_;
             const T hlf = (T)0.5;
+            const int ltw = __ffs(tw_) - 1;                // tile_w is a power of two
             for (int k = threadIdx.x; k < G.half; k += blockDim.x) {
                 const cplx<T> z = buf[lds_pad(k)], zc = buf[lds_pad(k == 0 ? 0 : M - k)];
                 const cplx<T> A = {(z.x + zc.x) * hlf, (z.y - zc.y) * hlf};
                 const cplx<T> B = {(z.y + zc.y) * hlf, (zc.x - z.x) * hlf};
-                const int tile = k / tw_, kk = k - tile * tw_;
+                const int tile = k >> ltw, kk = k & (tw_ - 1);
                 X[((int64_t)tile * n_cap + ra) * tw_ + kk] = A;
                 if (rb < n) X[((int64_t)tile * n_cap + rb) * tw_ + kk] = B;
             }
@@ -268,38 +269,42 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
         pot_of<S, FORM>(pot, ch, kern);
         const cplx<T>* X = static_cast<const cplx<T>*>(I.X) + (int64_t)ch * I.ntiles * n_cap * tw_;
         const int PM = lds_stride(M);
-        for (int idx = threadIdx.x; idx < Gc * M; idx += blockDim.x) {
-            const int r = idx / Gc, g = idx - r * Gc;     // consecutive threads: columns of a row
-            const int k0 = cg * Gc + g;
+        // the Gc columns of a block lie in one tile (Gc divides tile_w, both
+        // powers of two): element (r, g) of the block is at tile row r, slot kk0 + g
+        const int lgc = __ffs(Gc) - 1;
+        const int k00 = cg * Gc;
+        const int tile = k00 >> (__ffs(tw_) - 1);
+        const int64_t t0 = (int64_t)tile * n_cap * tw_ + (k00 - tile * tw_);
+        for (int idx = threadIdx.x; idx < (M << lgc); idx += blockDim.x) {
+            const int r = idx >> lgc, g = idx & (Gc - 1);   // consecutive threads: columns of a row
             cplx<T> v = {(T)0, (T)0};
-            if (k0 < half && r < n) {
-                const int tile = k0 / tw_;
-                v = X[((int64_t)tile * n_cap + r) * tw_ + (k0 - tile * tw_)];
-            }
+            if (k00 + g < half && r < n) v = X[t0 + (int64_t)r * tw_ + g];
             buf[g * PM + lds_pad(r)] = v;
         }
         __syncthreads();
         block_fft<T>(buf, Gc, I, Gm);
-        // multiply by the real kernel spectrum, conjugate for the inverse
-        const T* sp = static_cast<const T*>(I.spec) + (int64_t)kern * half * half;
-        for (int idx = threadIdx.x; idx < Gc * M; idx += blockDim.x) {
-            const int g = idx / M, k1 = idx - g * M;
-            const int k0 = cg * Gc + g;
-            const T sv = (k0 < half) ? sp[(int64_t)k0 * half + (k1 <= M - k1 ? k1 : M - k1)] : (T)0;
-            const int li = g * PM + lds_pad(k1);
-            const cplx<T> v = buf[li];
-            buf[li] = {v.x * sv, -v.y * sv};
+        // multiply by the real kernel spectrum, conjugate for the inverse; the
+        // threads split evenly over the block's columns
+        {
+            const int tpc = (int)blockDim.x >> lgc;
+            const int g = (int)threadIdx.x >> (__ffs(tpc) - 1);
+            const int jt = (int)threadIdx.x - g * tpc;
+            const int k0 = k00 + g;
+            const T* sp = static_cast<const T*>(I.spec) + (int64_t)kern * half * half + (int64_t)k0 * half;
+            cplx<T>* col = buf + g * PM;
+            for (int k1 = jt; k1 < M; k1 += tpc) {
+                const T sv = (k0 < half) ? sp[k1 <= M - k1 ? k1 : M - k1] : (T)0;
+                const int li = lds_pad(k1);
+                const cplx<T> v = col[li];
+                col[li] = {v.x * sv, -v.y * sv};
+            }
         }
         __syncthreads();
         block_fft<T>(buf, Gc, I, Gm);
         cplx<T>* Xc = static_cast<cplx<T>*>(I.Xc) + (int64_t)pot * I.ntiles * n_cap * tw_;
-        for (int idx = threadIdx.x; idx < Gc * n; idx += blockDim.x) {
-            const int r = idx / Gc, g = idx - r * Gc;
-            const int k0 = cg * Gc + g;
-            if (k0 < half) {
-                const int tile = k0 / tw_;
-                Xc[((int64_t)tile * n_cap + r) * tw_ + (k0 - tile * tw_)] = cconj(buf[g * PM + lds_pad(r)]);
-            }
+        for (int idx = threadIdx.x; idx < (n << lgc); idx += blockDim.x) {
+            const int r = idx >> lgc, g = idx & (Gc - 1);
+            if (k00 + g < half) Xc[t0 + (int64_t)r * tw_ + g] = cconj(buf[g * PM + lds_pad(r)]);
         }
         __syncthreads();
         }
@@ -323,11 +328,12 @@ __global__ __launch_bounds__(1024) void k_fft_irows(LaunchMap map)
             const cplx<T>* Xa = static_cast<const cplx<T>*>(I.Xc) + (int64_t)pa * I.ntiles * n_cap * tw_;
             const cplx<T>* Xb = static_cast<const cplx<T>*>(I.Xc) + (int64_t)pb * I.ntiles * n_cap * tw_;
             const int mh = M / 2;
+            const int ltw = __ffs(tw_) - 1;                // tile_w is a power of two
             for (int k = threadIdx.x; k < M; k += blockDim.x) {
                 const bool up = k > mh;
                 const int kk = up ? M - k : k;
-                const int tile = kk / tw_;
-                const int64_t off = ((int64_t)tile * n_cap + r) * tw_ + (kk - tile * tw_);
+                const int tile = kk >> ltw;
+                const int64_t off = ((int64_t)tile * n_cap + r) * tw_ + (kk & (tw_ - 1));
                 cplx<T> A = Xa[off];
                 cplx<T> B = (pb < NP) ? Xb[off] : cplx<T>{(T)0, (T)0};
                 if (up) { A = cconj(A); B = cconj(B); }

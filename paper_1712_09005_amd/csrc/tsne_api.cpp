@@ -294,9 +294,9 @@ Launch launch_of(int kind, const Derived& o, int vblocks)
     Launch l{std::min(vblocks, kGridCap), 256, 0};
     switch (kind) {
     case K_SPEC0: case K_SPEC1: case K_SPEC2:
-        // usually idle (tables unchanged): a bounded grid, each block loops when
-        // there is work and checks once when there is none
-        l.grid = std::min(vblocks, 2048);
+        // usually idle (tables unchanged): one block per CU, each block loops
+        // when there is work and checks once when there is none
+        l.grid = std::min(vblocks, 256);
         break;
     case K_FFT_ROWS: case K_FFT_IROWS: case K_FFT_1D:
         l.block = o.row_threads;
