@@ -26,7 +26,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_attr_traffic_n1e6_2d.txt")
-ATTR_SOURCE = os.path.join(ROOT, "paper_1712_09005_amd", "csrc", "k_points.hip")
+ATTR_SOURCES = [os.path.join(ROOT, "paper_1712_09005_amd", "csrc", f)
+                for f in ("k_points.hip", "tsne_dev.h", "launch.h")]
 
 
 def measured_traffic(knobs):
@@ -40,8 +41,11 @@ def measured_traffic(knobs):
                 if ":" in line and not line.startswith(" "):
                     k, v = line.split(":", 1)
                     fields[k.strip()] = v.strip()
-        with open(ATTR_SOURCE, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        h = hashlib.sha256()
+        for path in ATTR_SOURCES:
+            with open(path, "rb") as f:
+                h.update(f.read())
+        sha = h.hexdigest()
         if fields.get("source_sha256") != sha:
             return None
         want = "lanes_per_row=%d attr_slabs=%d attr_layout=%d" % (
@@ -76,7 +80,7 @@ def main():
                          "run; c2: N=1e5 2-D 1000-iteration run from a 50-d mixture; serve: "
                          "64-job continuous-batching server vs sequential runs")
     ap.add_argument("--jobs", type=int, default=64)
-    ap.add_argument("--slots", type=str, default="64",
+    ap.add_argument("--slots", type=str, default="8",
                     help="serving: batch slots (jobs live at once); a comma list runs the "
                          "batched server once per value and reports each")
     ap.add_argument("--copy-ref", action="store_true",

@@ -414,7 +414,7 @@ __device__ __forceinline__ bool spec_needed(const Inst& I)
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_spec0(LaunchMap map)
 {
-    VB_BEGIN_IF(map, K_SPEC0, spec_needed(I))
+    VB_BEGIN_IF_SKIP(map, K_SPEC0, spec_needed(I))
     {
         const Geom& G = *I.geom;
         const int M = G.M, half = G.half;
@@ -528,7 +528,7 @@ template <typename T, int S>
 __global__ __launch_bounds__(256) void k_spec1(LaunchMap map)
 {
     __shared__ double As[16][65], Bs[16][65];
-    VB_BEGIN_IF(map, K_SPEC1, spec_needed(I))
+    VB_BEGIN_IF_SKIP(map, K_SPEC1, spec_needed(I))
     {
         const Geom& G = *I.geom;
         const int M = G.M, half = G.half;
@@ -561,7 +561,7 @@ template <typename T, int S>
 __global__ __launch_bounds__(256) void k_spec2(LaunchMap map)
 {
     __shared__ double As[16][65], Bs[16][65];
-    VB_BEGIN_IF(map, K_SPEC2, S == 2 && spec_needed(I))
+    VB_BEGIN_IF_SKIP(map, K_SPEC2, S == 2 && spec_needed(I))
     {
         const Geom& G = *I.geom;
         const int M = G.M, half = G.half;

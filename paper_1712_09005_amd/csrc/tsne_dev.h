@@ -59,10 +59,13 @@ struct Geom {
     int col_group;     // FFT columns per block this iteration
 };
 
-// LDS index of element i of a transform: one pad slot per 16 complex values
-// keeps the strided Stockham writes of the early stages off shared banks.
-__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
-__host__ __device__ constexpr int lds_stride(int M) { return M + (M >> 4) + 1; }
+// LDS index of element i of a transform and the stride between the
+// transforms of one block.  Unpadded: measured faster at the lengths in use
+// (a pad slot per 8, 16 or 32 values cost more index arithmetic than the bank
+// conflicts of the early strided Stockham writes); the odd stride keeps the
+// transforms of a block on different banks.
+__host__ __device__ constexpr int lds_pad(int i) { return i; }
+__host__ __device__ constexpr int lds_stride(int M) { return M + 1; }
 
 struct Sched {
     double eta, mom0, mom1, ee_alpha, le_alpha, gain_inc, gain_dec, gain_min;
@@ -203,6 +206,30 @@ __device__ __forceinline__ bool live(const Inst& I) { return I.geom->active != 0
                 __ok = (COND);                                                 \
             }                                                                  \
             if (!__ok) continue;                                               \
+            const int lb = __vb - __pre[inst_id];                              \
+            (void)lb;
+
+// Like VB_BEGIN_IF, but a failing instance is stepped over in one jump, for
+// launches with many virtual blocks per instance that are usually idle.
+#define VB_BEGIN_IF_SKIP(map, KIND, COND)                                      \
+    {                                                                          \
+        const int* __pre = (map).prefix + (KIND) * ((map).ninst + 1);          \
+        const int __total = __pre[(map).ninst];                                \
+        int __last = -1;                                                       \
+        bool __ok = false;                                                     \
+        for (int __vb = blockIdx.x; __vb < __total; __vb += gridDim.x) {       \
+            const int inst_id = find_inst(__pre, (map).ninst, __vb);           \
+            const Inst& I = (map).insts[inst_id];                              \
+            if (inst_id != __last) {                                           \
+                __last = inst_id;                                              \
+                __ok = (COND);                                                 \
+            }                                                                  \
+            if (!__ok) {                                                       \
+                const int __end = __pre[inst_id + 1];                          \
+                const int __k = (__end - __vb + (int)gridDim.x - 1) / (int)gridDim.x; \
+                __vb += (__k - 1) * (int)gridDim.x;                            \
+                continue;                                                      \
+            }                                                                  \
             const int lb = __vb - __pre[inst_id];                              \
             (void)lb;
 

@@ -66,7 +66,7 @@ def summarize(jobs, makespan: float) -> dict:
 
 
 class Server:
-    def __init__(self, max_slots: int = 64, hbm_budget: int = 200 << 30, ticks_per_poll: int = 10,
+    def __init__(self, max_slots: int = 8, hbm_budget: int = 200 << 30, ticks_per_poll: int = 10,
                  interval_width: float = 0.75, p: int = 5, lanes_per_row: int = 32, device="cuda"):
         self.device = torch.device(device)
         self.batch = tsne.Batch(max_slots, s=2, dtype=torch.float32, p=p,
