@@ -67,7 +67,9 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=1_000_000)
-    ap.add_argument("--p", type=int, default=5)
+    ap.add_argument("--p", type=int, default=None,
+                    help="Lagrange nodes per interval (default: autotuned with the width for "
+                         "the 2-D step benchmark, else 5)")
     ap.add_argument("--width", type=float, default=None,
                     help="interval width (default: autotuned for the 2-D step benchmark, "
                          "0.75 for the other 2-D workloads, 0.5 in 1-D)")
@@ -92,6 +94,8 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.workload != "c3":
+        if args.p is None:
+            args.p = 5
         if args.width is None:
             args.width = 0.5 if args.workload == "c4" else 0.75
         return other_workloads(args)
@@ -114,9 +118,15 @@ def main():
         # autotuner: interval width for the accuracy target, then launch knobs
         from paper_1712_09005_amd import autotune
         t0 = time.time()
-        if args.width is None:
-            tw = autotune.tune_width(Y, target=1e-3, safety=2.0, p=args.p, device=dev, log=log)
+        if args.width is None and args.p is None:
+            ti = autotune.tune_interp(Y, target=1e-3, safety=2.5, max_intervals=max_int,
+                                      device=dev, log=log)
+            args.p, args.width = ti["p"], ti["interval_width"]
+        elif args.width is None:
+            tw = autotune.tune_width(Y, target=1e-3, safety=2.5, p=args.p, device=dev, log=log)
             args.width = tw["interval_width"]
+    if args.p is None:
+        args.p = 5
     if args.width is None:
         args.width = 0.75
     if not args.no_tune:
@@ -125,7 +135,7 @@ def main():
                                    device=dev, log=log)
         knobs = dict(lanes_per_row=ta["lanes_per_row"], attr_slabs=ta["attr_slabs"],
                      attr_layout=ta["attr_layout"], points_per_lane=tsp["points_per_lane"])
-        tuned = dict(knobs, interval_width=args.width, seconds=round(time.time() - t0, 1))
+        tuned = dict(knobs, p=args.p, interval_width=args.width, seconds=round(time.time() - t0, 1))
         log("autotuned: %s" % tuned)
     plan = tsne.Plan(n, s, torch.float32, p=args.p, policy="fixed", interval_width=args.width,
                      max_intervals=max_int, nnz=P.nnz, device=dev, **knobs)

@@ -32,7 +32,8 @@ import torch
 
 from . import tsne
 
-WIDTHS = (1.5, 1.25, 1.0, 0.9, 0.8, 0.75, 0.7, 0.6, 0.5, 0.4, 0.3)
+WIDTHS = (1.6, 1.5, 1.4, 1.3, 1.2, 1.1, 1.0, 0.95, 0.9, 0.85, 0.8, 0.75, 0.7, 0.65, 0.6,
+          0.55, 0.5, 0.45, 0.4, 0.35, 0.3)
 CSR_KNOBS = [(lpr, sl, 1) for lpr in (4, 8, 16, 32, 64) for sl in (1, 2, 4, 8)] + [(0, 0, 2)]
 KPTS = (4, 8, 16)
 
@@ -227,6 +228,55 @@ def tune_width(Y, target=1e-3, safety=2.0, p=5, device="cuda:0", widths=WIDTHS,
     if chosen is None:
         raise RuntimeError("no width on the ladder meets the target %g" % target)
     out = {"interval_width": chosen[0], "estimate": chosen[1], "table": table}
+    _store(cache, key, out)
+    return out
+
+
+def tune_interp(Y, target=1e-3, safety=2.5, ps=(4, 5, 6), max_intervals=512, device="cuda:0",
+                reps=10, cache="default", log=None) -> dict:
+    """Nodes per interval p and interval width together: for each p the
+    widest width meeting the accuracy target (tune_width), then the pair
+    whose FP32 repulsion at this Y is fastest.  Returns {"p",
+    "interval_width", "estimate", "seconds", "table"}."""
+    cache = default_cache() if cache == "default" else cache
+    dev = torch.device(device)
+    n, s = Y.shape
+    L = float(np.max(Y.max(0) - Y.min(0)))
+    key = _key("interp", dev, n, 0, s, torch.float32, 0,
+               "|L%d|t%g|k%g|p%s" % (_bucket(int(L)), target, safety, "-".join(map(str, ps))))
+    hit = _load(cache).get(key)
+    if hit is not None:
+        return hit
+    Yt = torch.as_tensor(np.ascontiguousarray(Y)).to(dev, torch.float32)
+    table = []
+    best = None
+    for p in ps:
+        try:
+            tw = tune_width(Y, target=target, safety=safety, p=p, device=dev, cache=cache, log=log)
+        except RuntimeError:
+            continue
+        w = tw["interval_width"]
+        if L / w + 1 > max_intervals:
+            continue
+        plan = tsne.Plan(n, s, torch.float32, p=p, interval_width=w, max_intervals=max_intervals,
+                         device=dev)
+        with torch.cuda.stream(plan.stream):
+            F = torch.empty_like(Yt)
+            Z = torch.empty(1, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t = time_launches(lambda: plan.repulsive(Yt, F, Z), plan.stream, reps)
+        if plan.query()["status"] != 0:
+            continue
+        table.append([p, w, tw["estimate"], t])
+        if log:
+            log("  p=%d width %.3g (estimate %.2e): repulsion %.1f us" % (p, w, tw["estimate"], t * 1e6))
+        if best is None or t < best[3]:
+            best = (p, w, tw["estimate"], t)
+        del plan
+    if best is None:
+        raise RuntimeError("no (p, width) meets the target %g" % target)
+    out = {"p": best[0], "interval_width": best[1], "estimate": best[2], "seconds": best[3],
+           "table": table}
     _store(cache, key, out)
     return out
 

@@ -96,3 +96,23 @@ def test_spread_and_batch_lanes(A, tmp_path):
              inputs.random_graph_P(n, 90, seed=n)) for n in (5000, 12000)]
     b = A.tune_batch_lanes(jobs, device=DEV, reps=3, cache=str(tmp_path / "b.json"))
     assert b["lanes_per_row"] in (16, 32, 64)
+
+
+def test_interp_choice_meets_target(A, tmp_path):
+    """Joint choice of nodes per interval and width: the chosen pair meets the
+    accuracy target against the direct sum."""
+    print("case: tune_interp", flush=True)
+    n = 3000
+    Y = inputs.mixture_embedding(n, 2, 8, -25, 25, 2.0, seed=23).astype(np.float64)
+    r = A.tune_interp(Y, target=1e-3, safety=2.5, max_intervals=128, device=DEV, reps=3,
+                      cache=str(tmp_path / "i.json"))
+    assert r["p"] in (4, 5, 6) and len(r["table"]) >= 1
+    from paper_1712_09005_amd import tsne
+    plan = tsne.Plan(n, 2, torch.float32, p=r["p"], interval_width=r["interval_width"],
+                     max_intervals=128, device=DEV)
+    F, _ = plan.repulsive(torch.from_numpy(Y.astype(np.float32)).to(DEV))
+    Fd, _ = oracle.direct_rep(Y)
+    e = rel(F.cpu().numpy(), Fd)
+    print("  chose p=%d w=%.2f, FP32 error vs direct %.2e (table %s)" % (r["p"], r["interval_width"], e,
+                                                                       r["table"]))
+    assert e < 1e-3
