@@ -56,6 +56,9 @@ def _load():
             "oracle_direct_rep": [i64, i32, P, i32, P, P],
             "oracle_attr": [i64, i32, P, P, P, P, P],
             "oracle_kl": [i64, i32, P, P, P, P, f64],
+            "oracle_knn": [i64, i32, P, i32, P, P],
+            "oracle_perplexity": [i64, i32, P, f64, P, P],
+            "oracle_symmetrize": [i64, i32, P, P, P, P, P],
             "oracle_geometry": [i64, i32, P, i32, i32, f64, P, P, P],
             "oracle_lagrange": [i32, f64, P],
             "oracle_grid_conv": [i32, i32, f64, i32, i32, P, P],
@@ -72,6 +75,7 @@ def _load():
             fn.argtypes = args
             fn.restype = ctypes.c_int if name.startswith("oracle_interp") else None
         _lib.oracle_kl.restype = f64
+        _lib.oracle_symmetrize.restype = i64
     return _lib
 
 
@@ -140,6 +144,44 @@ def kl(Y, P, Z=None):
     col = np.ascontiguousarray(P.col, dtype=np.int32)
     val = _f64(P.val)
     return float(_load().oracle_kl(n, s, _ptr(Y), _ptr(rp), _ptr(col), _ptr(val), float(Z)))
+
+
+# ---------------------------------------------------------------- affinities
+def knn(X, k):
+    """Exact k nearest neighbours (self excluded, ties by index): (idx int32
+    [n, k], squared distances [n, k]) in ascending order."""
+    X = _f64(X)
+    n, dim = X.shape
+    if not 0 < k < n:
+        raise ValueError("need 0 < k < n")
+    idx = np.empty((n, k), np.int32)
+    d2 = np.empty((n, k))
+    _load().oracle_knn(n, dim, _ptr(X), int(k), _ptr(idx), _ptr(d2))
+    return idx, d2
+
+
+def perplexity(dist2, perp):
+    """Conditional affinities [n, k] and bandwidths beta [n] by bisection to
+    the target perplexity (Section 1.1)."""
+    d2 = _f64(dist2)
+    n, k = d2.shape
+    p = np.empty((n, k))
+    beta = np.empty(n)
+    _load().oracle_perplexity(n, k, _ptr(d2), float(perp), _ptr(beta), _ptr(p))
+    return p, beta
+
+
+def symmetrize(idx, p):
+    """Joint P = (P_cond + P_cond^T) / (2N) as CSR (row_ptr int64, col int32,
+    val float64), columns ascending in each row."""
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    p = _f64(p)
+    n, k = idx.shape
+    rp = np.empty(n + 1, np.int64)
+    col = np.empty(2 * n * k, np.int32)
+    val = np.empty(2 * n * k)
+    nnz = _load().oracle_symmetrize(n, k, _ptr(idx), _ptr(p), _ptr(rp), _ptr(col), _ptr(val))
+    return rp, col[:nnz].copy(), val[:nnz].copy()
 
 
 # ---------------------------------------------------------------- geometry

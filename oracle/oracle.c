@@ -550,3 +550,146 @@ void oracle_update(int64_t n, int s, double* Y, double* uY, double* gains,
             Y[k] = (Y[k] - mean[d]) + uY[k];
         }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Input affinities (Section 1.1, restricted to the k nearest neighbours as  */
+/* in Section 3)                                                             */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { double d; int32_t j; } knn_pair;
+
+static int knn_cmp(const void* a, const void* b)
+{
+    const knn_pair* x = (const knn_pair*)a;
+    const knn_pair* y = (const knn_pair*)b;
+    if (x->d < y->d) return -1;
+    if (x->d > y->d) return 1;
+    return (x->j > y->j) - (x->j < y->j);
+}
+
+/* Exact k nearest neighbours of every row of X [n, dim] (squared Euclidean
+ * distance summed over the coordinate differences, the point itself
+ * excluded), by computing every distance and sorting; equal distances are
+ * ordered by index.  idx [n, k], dist2 [n, k], ascending.  Needs k < n. */
+void oracle_knn(int64_t n, int dim, const double* X, int k, int32_t* idx, double* dist2)
+{
+#pragma omp parallel
+    {
+        knn_pair* buf = (knn_pair*)malloc(sizeof(knn_pair) * (size_t)n);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t m = 0;
+            for (int64_t j = 0; j < n; ++j) {
+                if (j == i) continue;
+                double acc = 0.0;
+                for (int c = 0; c < dim; ++c) {
+                    const double t = X[i * dim + c] - X[j * dim + c];
+                    acc += t * t;
+                }
+                buf[m].d = acc;
+                buf[m].j = (int32_t)j;
+                ++m;
+            }
+            qsort(buf, (size_t)m, sizeof(knn_pair), knn_cmp);
+            for (int t = 0; t < k; ++t) {
+                idx[i * k + t] = buf[t].j;
+                dist2[i * k + t] = buf[t].d;
+            }
+        }
+        free(buf);
+    }
+}
+
+/* Conditional affinities of every row from its k squared neighbour
+ * distances (ascending): p_{j|i} = exp(-beta_i d_ij) / sum_l exp(-beta_i d_il),
+ * beta_i = 1 / (2 sigma_i^2), with beta_i found by bisection so that the
+ * perplexity exp(H_i), H_i = -sum_j p_{j|i} ln p_{j|i}, equals the target.
+ * Steps: distances are shifted by the row minimum (the p do not change);
+ * H = ln S + beta sum_j d'_j w_j / S with w_j = exp(-beta d'_j), S = sum w_j;
+ * start at beta = 1 with no bounds; while |H - ln(perplexity)| >= 1e-10 and
+ * fewer than 200 steps: if H is too high, the lower bound becomes beta and
+ * beta doubles (no upper bound yet) or moves to the midpoint; otherwise the
+ * upper bound becomes beta and beta halves (no lower bound) or moves to the
+ * midpoint.  beta_out [n] (may be NULL), p [n, k]. */
+void oracle_perplexity(int64_t n, int k, const double* dist2, double perplexity,
+                       double* beta_out, double* p)
+{
+    const double target = log(perplexity);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        const double* d = dist2 + i * k;
+        double dmin = d[0];
+        for (int t = 1; t < k; ++t) if (d[t] < dmin) dmin = d[t];
+        double beta = 1.0, lo = -INFINITY, hi = INFINITY;
+        for (int it = 0; it < 200; ++it) {
+            double S = 0.0, SD = 0.0;
+            for (int t = 0; t < k; ++t) {
+                const double w = exp(-beta * (d[t] - dmin));
+                S += w;
+                SD += (d[t] - dmin) * w;
+            }
+            const double H = log(S) + beta * SD / S;
+            const double diff = H - target;
+            if (fabs(diff) < 1e-10) break;
+            if (diff > 0.0) {
+                lo = beta;
+                beta = isinf(hi) ? beta * 2.0 : 0.5 * (beta + hi);
+            } else {
+                hi = beta;
+                beta = isinf(lo) ? beta * 0.5 : 0.5 * (beta + lo);
+            }
+        }
+        double S = 0.0;
+        for (int t = 0; t < k; ++t) S += exp(-beta * (d[t] - dmin));
+        for (int t = 0; t < k; ++t) p[i * k + t] = exp(-beta * (d[t] - dmin)) / S;
+        if (beta_out) beta_out[i] = beta;
+    }
+}
+
+typedef struct { int64_t r; int32_t c; double v; } coo_entry;
+
+static int coo_cmp(const void* a, const void* b)
+{
+    const coo_entry* x = (const coo_entry*)a;
+    const coo_entry* y = (const coo_entry*)b;
+    if (x->r != y->r) return (x->r > y->r) - (x->r < y->r);
+    return (x->c > y->c) - (x->c < y->c);
+}
+
+/* Symmetric joint affinities p_ij = (p_{j|i} + p_{i|j}) / (2N) from the
+ * conditional rows (idx [n, k], p [n, k]), as CSR with columns ascending in
+ * each row: every (i, j, p_{j|i}) is counted in row i and in row j, equal
+ * (row, column) pairs are summed.  row_ptr [n+1]; col, val hold nnz <= 2nk
+ * entries.  Returns nnz. */
+int64_t oracle_symmetrize(int64_t n, int k, const int32_t* idx, const double* p,
+                          int64_t* row_ptr, int32_t* col, double* val)
+{
+    const int64_t m = 2 * n * (int64_t)k;
+    coo_entry* e = (coo_entry*)malloc(sizeof(coo_entry) * (size_t)m);
+    for (int64_t i = 0; i < n; ++i)
+        for (int t = 0; t < k; ++t) {
+            const int64_t q = i * k + t;
+            e[2 * q].r = i;
+            e[2 * q].c = idx[q];
+            e[2 * q].v = p[q];
+            e[2 * q + 1].r = idx[q];
+            e[2 * q + 1].c = (int32_t)i;
+            e[2 * q + 1].v = p[q];
+        }
+    qsort(e, (size_t)m, sizeof(coo_entry), coo_cmp);
+    int64_t nnz = 0;
+    for (int64_t r = 0; r <= n; ++r) row_ptr[r] = 0;
+    for (int64_t a = 0; a < m;) {
+        int64_t b = a;
+        double v = 0.0;
+        while (b < m && e[b].r == e[a].r && e[b].c == e[a].c) v += e[b++].v;
+        col[nnz] = e[a].c;
+        val[nnz] = v / (2.0 * (double)n);
+        row_ptr[e[a].r + 1] += 1;
+        ++nnz;
+        a = b;
+    }
+    for (int64_t r = 0; r < n; ++r) row_ptr[r + 1] += row_ptr[r];
+    free(e);
+    return nnz;
+}

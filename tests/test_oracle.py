@@ -442,3 +442,80 @@ def test_kl_zero_when_p_equals_q_and_positive_otherwise():
     c = oracle.kl(Y, Pd)
     assert c > 0.0
     assert oracle.kl(Y + np.array([5.0, -2.0]), Pd) == pytest.approx(c, rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Input affinities (Section 1.1 over the k nearest neighbours of Section 3)
+# --------------------------------------------------------------------------
+
+def test_knn_hand_computed_and_ties():
+    X = np.array([[0.0], [1.0], [3.0], [7.0], [8.0]])
+    idx, d2 = oracle.knn(X, 2)
+    np.testing.assert_array_equal(idx, [[1, 2], [0, 2], [1, 0], [4, 2], [3, 2]])
+    np.testing.assert_array_equal(d2, [[1, 9], [1, 4], [4, 9], [1, 16], [1, 25]])
+    # equal distances are ordered by index
+    idx, d2 = oracle.knn(np.array([[0.0, 0.0], [1.0, 0.0], [-1.0, 0.0], [0.0, 5.0]]), 2)
+    np.testing.assert_array_equal(idx[0], [1, 2])
+    np.testing.assert_array_equal(d2[0], [1, 1])
+
+
+def test_knn_invariances():
+    """Translation and orthogonal maps keep the neighbours and distances;
+    relabelling the points relabels the neighbours."""
+    rng = np.random.default_rng(41)
+    X = rng.normal(size=(120, 6))
+    idx, d2 = oracle.knn(X, 7)
+    Q, _ = np.linalg.qr(rng.normal(size=(6, 6)))
+    idx2, d22 = oracle.knn(X @ Q.T + 3.0, 7)
+    np.testing.assert_array_equal(idx2, idx)
+    np.testing.assert_allclose(d22, d2, rtol=1e-10)
+    perm = rng.permutation(120)
+    inv = np.argsort(perm)
+    idx3, d23 = oracle.knn(X[perm], 7)
+    np.testing.assert_array_equal(perm[idx3], idx[perm])
+    np.testing.assert_allclose(d23, d2[perm], rtol=1e-12)
+
+
+def test_perplexity_rows():
+    """Every row sums to 1, decreases with distance and has entropy ln(perp);
+    equal distances give the uniform row; two neighbours have the closed
+    form p1 = 1 / (1 + exp(-beta (d2 - d1)))."""
+    rng = np.random.default_rng(42)
+    d2 = np.sort(rng.uniform(0.5, 30.0, size=(200, 15)), axis=1)
+    p, beta = oracle.perplexity(d2, 5.0)
+    np.testing.assert_allclose(p.sum(1), 1.0, rtol=1e-12)
+    assert np.all(np.diff(p, axis=1) <= 0)
+    H = -(p * np.log(p)).sum(1)
+    np.testing.assert_allclose(H, np.log(5.0), atol=1e-9)
+    pu, _ = oracle.perplexity(np.full((3, 8), 4.0), 8.0)
+    np.testing.assert_allclose(pu, 1.0 / 8.0, rtol=1e-12)
+    p2, b2 = oracle.perplexity(np.array([[1.0, 3.0]]), 1.5)
+    np.testing.assert_allclose(p2[0, 0], 1.0 / (1.0 + np.exp(-b2[0] * 2.0)), rtol=1e-12)
+
+
+def test_symmetrize_hand_computed_and_structure():
+    # n = 3, k = 1: 0 -> 1, 1 -> 0, 2 -> 1, all with p = 1:
+    # P01 = P10 = (1 + 1) / 6, P12 = P21 = 1 / 6
+    rp, col, val = oracle.symmetrize(np.array([[1], [0], [1]]), np.ones((3, 1)))
+    np.testing.assert_array_equal(rp, [0, 1, 3, 4])
+    np.testing.assert_array_equal(col, [1, 0, 2, 1])
+    np.testing.assert_allclose(val, [1 / 3, 1 / 3, 1 / 6, 1 / 6], rtol=1e-15)
+    # random rows: symmetric, sums to 1, row i holds out(i) union in(i), sorted
+    rng = np.random.default_rng(43)
+    n, k = 60, 5
+    idx = np.array([rng.choice(np.delete(np.arange(n), i), k, replace=False) for i in range(n)],
+                   dtype=np.int32)
+    p = rng.uniform(0.1, 1.0, size=(n, k))
+    p /= p.sum(1, keepdims=True)
+    rp, col, val = oracle.symmetrize(idx, p)
+    assert val.sum() == pytest.approx(1.0, rel=1e-12)
+    pairs = {}
+    for i in range(n):
+        cs = col[rp[i]:rp[i + 1]]
+        assert np.all(np.diff(cs) > 0)
+        want = set(idx[i]) | {j for j in range(n) if i in idx[j]}
+        assert set(cs) == want
+        for c, v in zip(cs, val[rp[i]:rp[i + 1]]):
+            pairs[(i, c)] = v
+    for (i, j), v in pairs.items():
+        assert pairs[(j, i)] == pytest.approx(v, rel=1e-15)
