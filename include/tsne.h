@@ -208,6 +208,46 @@ tsne_status tsne_debug_export(tsne_plan* plan, int32_t what, void* dst_host,
 const char* tsne_status_str(tsne_status status);
 
 /* ---------------------------------------------------------------------- */
+/* Input affinities (Section 1.1) over the k nearest neighbours (Section 3) */
+/* ---------------------------------------------------------------------- */
+
+/* Exact k nearest neighbours of every row of X [n, dim] (row-major FP32,
+ * device): squared Euclidean distances accumulated in FP32 over the
+ * coordinate differences, the point itself excluded, equal distances ordered
+ * by index.  idx [n, k] int32 and dist2 [n, k] FP32 (device, caller-owned)
+ * receive each row's neighbours in ascending distance.  1 <= k < n,
+ * k <= 256 (TSNE_E_UNSUPPORTED above); n < 2^31.  Enqueued on stream; no
+ * workspace. */
+tsne_status tsne_knn(const float* X, int64_t n, int32_t dim, int32_t k, int32_t* idx, float* dist2,
+                     void* stream);
+
+/* Conditional affinities p_{j|i} = exp(-beta_i d_ij) / sum_l exp(-beta_i d_il)
+ * over the k neighbour distances of each row (dist2 [n, k] FP32, device), with
+ * beta_i = 1 / (2 sigma_i^2) found by bisection in FP64 so that the
+ * perplexity exp(-sum p ln p) equals the target: distances shifted by the row
+ * minimum, doubling or halving beta until the target is bracketed, then
+ * halving the bracket, until the entropy is within 1e-10 of ln(perplexity)
+ * or after 200 steps.  p [n, k] FP32 (device); beta [n] FP64 (device, may be
+ * NULL).  k <= 128. */
+tsne_status tsne_perplexity(const float* dist2, int64_t n, int32_t k, double perplexity, float* p,
+                            double* beta, void* stream);
+
+/* Workspace bytes of tsne_symmetrize (0 for invalid sizes). */
+size_t tsne_symmetrize_workspace_bytes(int64_t n, int32_t k);
+
+/* Joint affinities p_ij = (p_{j|i} + p_{i|j}) / (2N) (Section 1.1) from the
+ * conditional rows idx [n, k], p [n, k] (device) as CSR for tsne_bind_P:
+ * row_ptr [n+1] int64, col [<= 2nk] int32 ascending within each row, val
+ * [<= 2nk] FP32 (device, caller-owned; nnz = row_ptr[n]).  Equal (row,
+ * column) pairs are summed.  A row longer than 16384 entries (a point in
+ * more than 16384 - k neighbour lists) is left empty and sets *status
+ * (device int, may be NULL) to 1; otherwise *status is 0.  workspace: 256-byte
+ * aligned, tsne_symmetrize_workspace_bytes(n, k) bytes. */
+tsne_status tsne_symmetrize(const int32_t* idx, const float* p, int64_t n, int32_t k, void* workspace,
+                            size_t bytes, void* stream, int64_t* row_ptr, int32_t* col, float* val,
+                            int* status);
+
+/* ---------------------------------------------------------------------- */
 /* Batching: independent embeddings of uneven n sharing every launch.      */
 /* ---------------------------------------------------------------------- */
 

@@ -57,6 +57,7 @@ def _load():
             "oracle_attr": [i64, i32, P, P, P, P, P],
             "oracle_kl": [i64, i32, P, P, P, P, f64],
             "oracle_knn": [i64, i32, P, i32, P, P],
+            "oracle_knn_rows": [i64, i32, P, i32, P, i64, P, P],
             "oracle_perplexity": [i64, i32, P, f64, P, P],
             "oracle_symmetrize": [i64, i32, P, P, P, P, P],
             "oracle_geometry": [i64, i32, P, i32, i32, f64, P, P, P],
@@ -157,6 +158,17 @@ def knn(X, k):
     idx = np.empty((n, k), np.int32)
     d2 = np.empty((n, k))
     _load().oracle_knn(n, dim, _ptr(X), int(k), _ptr(idx), _ptr(d2))
+    return idx, d2
+
+
+def knn_rows(X, rows, k):
+    """knn for the listed rows only: (idx int32 [r, k], dist2 [r, k])."""
+    X = _f64(X)
+    n, dim = X.shape
+    r = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+    idx = np.empty((r.shape[0], k), np.int32)
+    d2 = np.empty((r.shape[0], k))
+    _load().oracle_knn_rows(n, dim, _ptr(X), int(k), _ptr(r), r.shape[0], _ptr(idx), _ptr(d2))
     return idx, d2
 
 

@@ -600,6 +600,39 @@ void oracle_knn(int64_t n, int dim, const double* X, int k, int32_t* idx, double
     }
 }
 
+/* oracle_knn for the listed rows only (rows [nr] of X [n, dim]): idx [nr, k],
+ * dist2 [nr, k]. */
+void oracle_knn_rows(int64_t n, int dim, const double* X, int k, const int64_t* rows, int64_t nr,
+                     int32_t* idx, double* dist2)
+{
+#pragma omp parallel
+    {
+        knn_pair* buf = (knn_pair*)malloc(sizeof(knn_pair) * (size_t)n);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t r = 0; r < nr; ++r) {
+            const int64_t i = rows[r];
+            int64_t m = 0;
+            for (int64_t j = 0; j < n; ++j) {
+                if (j == i) continue;
+                double acc = 0.0;
+                for (int c = 0; c < dim; ++c) {
+                    const double t = X[i * dim + c] - X[j * dim + c];
+                    acc += t * t;
+                }
+                buf[m].d = acc;
+                buf[m].j = (int32_t)j;
+                ++m;
+            }
+            qsort(buf, (size_t)m, sizeof(knn_pair), knn_cmp);
+            for (int t = 0; t < k; ++t) {
+                idx[r * k + t] = buf[t].j;
+                dist2[r * k + t] = buf[t].d;
+            }
+        }
+        free(buf);
+    }
+}
+
 /* Conditional affinities of every row from its k squared neighbour
  * distances (ascending): p_{j|i} = exp(-beta_i d_ij) / sum_l exp(-beta_i d_il),
  * beta_i = 1 / (2 sigma_i^2), with beta_i found by bisection so that the

@@ -93,6 +93,10 @@ def lib():
             "tsne_repulsive": ([P, P, P, P], i32),
             "tsne_attractive": ([P, P, P], i32),
             "tsne_kl_divergence": ([P, P, P], i32),
+            "tsne_knn": ([P, i64, i32, i32, P, P, P], i32),
+            "tsne_perplexity": ([P, i64, i32, ctypes.c_double, P, P, P], i32),
+            "tsne_symmetrize_workspace_bytes": ([i64, i32], ctypes.c_size_t),
+            "tsne_symmetrize": ([P, P, i64, i32, P, ctypes.c_size_t, P, P, P, P, P], i32),
             "tsne_step": ([P, P, P, P, P, i32], i32),
             "tsne_run": ([P, P, P, P, P, i32, i32], i32),
             "tsne_query": ([P, P], i32),
@@ -283,6 +287,72 @@ class Plan:
         buf = (ctypes.c_char * nb.value)()
         _check(lib().tsne_debug_export(self._h, int(what), buf, ctypes.byref(nb)), "export")
         return bytes(buf)
+
+
+def _stream_ptr(stream):
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def knn(X, k, stream=None):
+    """Exact k nearest neighbours of the rows of X (contiguous FP32 [n, dim]
+    on a GPU): (idx int32 [n, k], dist2 float32 [n, k]) in ascending order."""
+    if X.dtype != torch.float32 or X.dim() != 2 or not X.is_cuda or not X.is_contiguous():
+        raise ValueError("X must be a contiguous float32 [n, dim] GPU tensor")
+    n, dim = X.shape
+    st = stream if stream is not None else torch.cuda.current_stream(X.device)
+    with torch.cuda.stream(st):
+        idx = torch.empty((n, k), dtype=torch.int32, device=X.device)
+        d2 = torch.empty((n, k), dtype=torch.float32, device=X.device)
+    _check(lib().tsne_knn(_ptr(X), n, dim, int(k), _ptr(idx), _ptr(d2), _stream_ptr(st)), "tsne_knn")
+    return idx, d2
+
+
+def perplexity(dist2, perp, stream=None, want_beta=False):
+    """Conditional affinities [n, k] (float32) by bisection to the perplexity."""
+    if dist2.dtype != torch.float32 or dist2.dim() != 2 or not dist2.is_contiguous():
+        raise ValueError("dist2 must be a contiguous float32 [n, k] GPU tensor")
+    n, k = dist2.shape
+    st = stream if stream is not None else torch.cuda.current_stream(dist2.device)
+    with torch.cuda.stream(st):
+        p = torch.empty_like(dist2)
+        beta = torch.empty(n, dtype=torch.float64, device=dist2.device) if want_beta else None
+    _check(lib().tsne_perplexity(_ptr(dist2), n, k, float(perp), _ptr(p), _ptr(beta),
+                                 _stream_ptr(st)), "tsne_perplexity")
+    return (p, beta) if want_beta else p
+
+
+def symmetrize(idx, p, stream=None):
+    """Joint CSR P from conditional rows: (row_ptr int64 [n+1], col int32
+    [nnz], val float32 [nnz]) on the GPU."""
+    if idx.dtype != torch.int32 or p.dtype != torch.float32 or idx.shape != p.shape or \
+            not idx.is_contiguous() or not p.is_contiguous():
+        raise ValueError("idx int32 and p float32 of one shape [n, k], contiguous")
+    n, k = idx.shape
+    dev = idx.device
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    nb = int(lib().tsne_symmetrize_workspace_bytes(n, k))
+    if nb == 0:
+        raise TsneError(1, "tsne_symmetrize_workspace_bytes")
+    with torch.cuda.stream(st):
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        rp = torch.empty(n + 1, dtype=torch.int64, device=dev)
+        col = torch.empty(2 * n * k, dtype=torch.int32, device=dev)
+        val = torch.empty(2 * n * k, dtype=torch.float32, device=dev)
+        status = torch.zeros(1, dtype=torch.int32, device=dev)
+    _check(lib().tsne_symmetrize(_ptr(idx), _ptr(p), n, k, _ptr(ws), nb, _stream_ptr(st), _ptr(rp),
+                                 _ptr(col), _ptr(val), _ptr(status)), "tsne_symmetrize")
+    st.synchronize()
+    if int(status.item()) != 0:
+        raise TsneError(2, "tsne_symmetrize: a row exceeds 16384 entries")
+    nnz = int(rp[n].item())
+    return rp, col[:nnz].clone(), val[:nnz].clone()
+
+
+def affinities(X, k=90, perp=30.0, stream=None):
+    """Joint P (CSR on the GPU) from the points X: kNN, perplexity, symmetrise."""
+    idx, d2 = knn(X, k, stream)
+    p = perplexity(d2, perp, stream)
+    return symmetrize(idx, p, stream)
 
 
 class Batch:

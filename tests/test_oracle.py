@@ -519,3 +519,12 @@ def test_symmetrize_hand_computed_and_structure():
             pairs[(i, c)] = v
     for (i, j), v in pairs.items():
         assert pairs[(j, i)] == pytest.approx(v, rel=1e-15)
+
+
+def test_knn_rows_matches_full():
+    X = np.random.default_rng(44).normal(size=(300, 9))
+    idx, d2 = oracle.knn(X, 11)
+    rows = np.array([0, 17, 299, 150])
+    ir, dr = oracle.knn_rows(X, rows, 11)
+    np.testing.assert_array_equal(ir, idx[rows])
+    np.testing.assert_array_equal(dr, d2[rows])
