@@ -353,14 +353,22 @@ def other_workloads(args):
             sched = tsne.Schedule(ee_alpha=1.0, ee_stop=0, le_alpha=4.0, le_start=500)
             checks = [0, 500, 749]
             cap = 1024
+            extra = {}
             desc = "N=1e6 1-D, 30 clusters on [-195,195] sd 1.5, random 90-neighbour P, 750 " \
                    "iterations, late exaggeration 4 from iteration 500"
         else:
             n, s, n_iter = 100_000, 2, 1000
-            t0 = time.time()
             x = inputs.mixture_highdim(n, 50, 20, 5.0, seed=0)
-            P = inputs.perplexity_P(x, 90, 30.0, device=dev)
-            log("c2 inputs: exact 90-NN perplexity-30 P, nnz=%d (%.1f s)" % (P.nnz, time.time() - t0))
+            # affinities on the device: exact 90-NN, perplexity 30, symmetrised
+            Xt = torch.from_numpy(x).to(dev)
+            torch.cuda.synchronize()
+            ta0 = time.perf_counter()
+            rp_d, col_d, val_d = tsne.affinities(Xt, 90, 30.0)
+            torch.cuda.synchronize()
+            t_aff = time.perf_counter() - ta0
+            P = inputs.CSR(rp_d.cpu().numpy(), col_d.cpu().numpy(), val_d.cpu().numpy())
+            log("c2 inputs: exact 90-NN perplexity-30 P on the device in %.1f ms, nnz=%d"
+                % (1e3 * t_aff, P.nnz))
             rng = np.random.default_rng(2)
             Y = (1e-2 * rng.standard_normal((n, 2))).astype(np.float32)
             sched = tsne.Schedule()
@@ -368,6 +376,7 @@ def other_workloads(args):
             cap = 512
             desc = "N=1e5 2-D from a 20-cluster 50-d mixture, exact 90-NN perplexity-30 P, " \
                    "1000 iterations, early exaggeration 12 for 250"
+            extra = {"affinities_ms": 1e3 * t_aff}
         plan = tsne.Plan(n, s, torch.float32, p=args.p, policy="fixed", interval_width=args.width,
                          max_intervals=cap, nnz=P.nnz, device=dev)
         with torch.cuda.stream(plan.stream):
@@ -388,16 +397,27 @@ def other_workloads(args):
                "config": {"workload": desc, "n": n, "s": s, "nnz": int(P.nnz), "p": args.p,
                           "interval_width": args.width, "final_n_int": q["n_int"],
                           "final_fft_len": q["fft_len"],
-                          "rel_err_rep_numerators_sampled_at": errs}}
+                          "rel_err_rep_numerators_sampled_at": errs, **extra}}
         print(json.dumps(out), flush=True)
         return
     # serving: 64 jobs, Poisson arrivals at twice the sequential rate
     from paper_1712_09005_amd import serve
     t0 = time.time()
-    specs = inputs.serving_jobs(args.jobs, device=dev)
-    log("serving inputs: %d jobs, N from %d to %d (%.1f s)" % (
+    raw = inputs.serving_jobs(args.jobs)
+    specs = []
+    t_aff = 0.0
+    for y, x in raw:                       # affinities on the device, before the clock
+        Xt = torch.from_numpy(x).to(dev)
+        torch.cuda.synchronize()
+        ta0 = time.perf_counter()
+        rp_d, col_d, val_d = tsne.affinities(Xt, 90, 30.0)
+        torch.cuda.synchronize()
+        t_aff += time.perf_counter() - ta0
+        specs.append((y, inputs.CSR(rp_d.cpu().numpy(), col_d.cpu().numpy(), val_d.cpu().numpy())))
+    del raw
+    log("serving inputs: %d jobs, N from %d to %d (%.1f s; device affinities %.2f s in all)" % (
         len(specs), min(y.shape[0] for y, _ in specs), max(y.shape[0] for y, _ in specs),
-        time.time() - t0))
+        time.time() - t0, t_aff))
 
     def jobs_at(arrivals):
         return [serve.Job(j, float(a), y, P) for j, ((y, P), a) in enumerate(zip(specs, arrivals))]

@@ -410,8 +410,11 @@ __device__ __forceinline__ int wave_incl_scan(int v)
 
 __global__ __launch_bounds__(256) void k_scan_b(LaunchMap map)
 {
+    constexpr int kSerialItems = 16;     // cells with more items are filled by the whole block
     __shared__ int sh[2][4];
     __shared__ int off[2];
+    __shared__ int nbig;
+    __shared__ int big[1024][3];         // (cell, first item, items)
     VB_BEGIN(map, K_SCAN_B)
     if (live(I)) {
         const int ncell = I.geom->n_cells;
@@ -433,6 +436,7 @@ __global__ __launch_bounds__(256) void k_scan_b(LaunchMap map)
                 off[0] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
                 off[1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
             }
+            if (threadIdx.x == 0) nbig = 0;
             __syncthreads();
             const int base = lb * 1024 + threadIdx.x * 4;
             int cv[4], iv[4], c = 0, it = 0;
@@ -458,7 +462,14 @@ __global__ __launch_bounds__(256) void k_scan_b(LaunchMap map)
                 if (e < ncell) {
                     I.cell_start[e] = pc;
                     I.item_start[e] = pi;
-                    for (int q = 0; q < iv[k]; ++q) I.item_cell[pi + q] = e;
+                    if (iv[k] <= kSerialItems) {
+                        for (int q = 0; q < iv[k]; ++q) I.item_cell[pi + q] = e;
+                    } else {
+                        const int b = atomicAdd(&nbig, 1);   // at most one per cell of the tile
+                        big[b][0] = e;
+                        big[b][1] = pi;
+                        big[b][2] = iv[k];
+                    }
                     I.counts[e] = 0;          // ready for the next iteration
                     if (e == ncell - 1) {
                         I.cell_start[ncell] = pc + cv[k];
@@ -468,6 +479,14 @@ __global__ __launch_bounds__(256) void k_scan_b(LaunchMap map)
                 pc += cv[k];
                 pi += iv[k];
             }
+            // cells with many items (a small box holding many points): the
+            // whole block writes their item -> cell entries
+            __syncthreads();
+            for (int b = 0; b < nbig; ++b) {
+                const int e = big[b][0], p0 = big[b][1], m = big[b][2];
+                for (int q = threadIdx.x; q < m; q += 256) I.item_cell[p0 + q] = e;
+            }
+            __syncthreads();
         }
     }
     VB_END
@@ -630,13 +649,25 @@ __global__ __launch_bounds__(256) void k_spread_fix(LaunchMap map)
 {
     constexpr int NC = Shape<S, FORM>::NC;
     constexpr int NN = (S == 2) ? P * P : P;
+    constexpr int kSerialWaves = 16;     // cells spanning more waves are summed by the block
+    constexpr int NV = NN * NC;
+    constexpr int NG = 256 / NV;         // wave groups summed in parallel per value (>= 1)
+    __shared__ int nbig;
+    __shared__ int bigc[256];
+    __shared__ float part[NG > 0 ? NG : 1][NV];
+    __shared__ double partd[NG > 0 ? NG : 1][NV];
+    static_assert(NG >= 1, "carry vector longer than a block");
     VB_BEGIN(map, K_FIX)
     if (live(I)) {
         const Geom& G = *I.geom;
         const int c = lb * 256 + threadIdx.x;
+        if (threadIdx.x == 0) nbig = 0;
+        __syncthreads();
         if (c < G.n_cells) {
             const int fi = I.item_start[c], li = I.item_start[c + 1] - 1;
-            if (li >= fi && (fi >> 6) != (li >> 6)) {
+            if (li >= fi && (li >> 6) - (fi >> 6) > kSerialWaves) {
+                bigc[atomicAdd(&nbig, 1)] = c;
+            } else if (li >= fi && (fi >> 6) != (li >> 6)) {
                 const int w0 = fi >> 6, w1 = li >> 6;
                 const T* cr = static_cast<const T*>(I.carry);
                 T acc[NN * NC];
@@ -668,6 +699,42 @@ __global__ __launch_bounds__(256) void k_spread_fix(LaunchMap map)
                     }
                 }
             }
+        }
+        __syncthreads();
+        // cells spanning many waves: thread (g, v) sums value v over the waves
+        // w0 + 1 + g, w0 + 1 + g + NG, ...; the NG partial sums and the first
+        // wave's carry are then added in a fixed order (deterministic)
+        const T* cr = static_cast<const T*>(I.carry);
+        for (int b = 0; b < nbig; ++b) {
+            const int cb = bigc[b];
+            const int fi = I.item_start[cb], li = I.item_start[cb + 1] - 1;
+            const int w0 = fi >> 6, w1 = li >> 6;
+            const int g = threadIdx.x / NV, v = threadIdx.x - g * NV;
+            if (g < NG) {
+                T a = (T)0;
+                for (int wv = w0 + 1 + g; wv <= w1; wv += NG) a += cr[(int64_t)wv * 2 * NV + v];
+                if constexpr (sizeof(T) == 4) part[g][v] = a; else partd[g][v] = (double)a;
+            }
+            __syncthreads();
+            if (threadIdx.x < NV) {
+                const int vv = threadIdx.x;
+                T a = cr[((int64_t)w0 * 2 + ((fi & 63) == 0 ? 0 : 1)) * NV + vv];
+                for (int gg = 0; gg < NG; ++gg) {
+                    if constexpr (sizeof(T) == 4) a += (T)part[gg][vv]; else a += (T)partd[gg][vv];
+                }
+                T* W = static_cast<T*>(I.W);
+                const int n_int = G.n_int, n_cap = I.n_cap;
+                const int cx = cb % n_int;
+                const int cy = (S == 2) ? cb / n_int : 0;
+                const int qq = vv % NC, mm = vv / NC;
+                if (S == 2) {
+                    const int m1 = mm / P, m0 = mm - m1 * P;
+                    W[((int64_t)qq * n_cap + cy * P + m1) * n_cap + cx * P + m0] = a;
+                } else {
+                    W[(int64_t)qq * n_cap + cx * P + mm] = a;
+                }
+            }
+            __syncthreads();
         }
     }
     VB_END

@@ -1,9 +1,10 @@
 """Seeded synthetic inputs for the t-SNE gradient path.
 
-This module builds *inputs only*: embeddings Y, the sparse joint-probability
-matrix P in CSR form, and high-dimensional point clouds for the perplexity
-workloads.  It holds none of the gradient arithmetic (no kernels, no
-interpolation, no forces), so both the GPU library's tests and the CPU oracle
+This module builds *inputs only*: embeddings Y, a random-graph P in CSR form,
+and high-dimensional point clouds X for the perplexity workloads (their
+affinities are computed from X by the library, or by the oracle in tests).
+It holds none of the method's arithmetic (no neighbours, bandwidths,
+interpolation or forces), so both the GPU library's tests and the CPU oracle
 can be fed from it without sharing any of the method's code.
 
 Every generator uses ``numpy.random.default_rng(seed)`` (PCG64).  Mixture
@@ -21,7 +22,7 @@ import numpy as np
 
 __all__ = [
     "CSR", "mixture_embedding", "random_graph_P", "mixture_highdim",
-    "perplexity_P", "config_inputs",
+    "serving_jobs", "poisson_arrivals", "config_inputs",
 ]
 
 
@@ -93,118 +94,20 @@ def mixture_highdim(n: int, d: int, n_clusters: int, centre_sd: float,
     return np.ascontiguousarray(x.astype(np.float32))
 
 
-def _knn(x: np.ndarray, k: int, chunk: int = 1024, device=None):
-    """Exact k nearest neighbours (excluding self) by brute force.
-    Returns (idx int64 [n,k], sqdist float64 [n,k]).  With ``device`` set to a
-    torch device the distance blocks are formed there (input tooling only)."""
-    n = x.shape[0]
-    if device is not None:
-        import torch
-        xt = torch.as_tensor(x, device=device, dtype=torch.float32)
-        sq = (xt * xt).sum(1)
-        idx_out = np.empty((n, k), np.int64)
-        d_out = np.empty((n, k), np.float64)
-        for a in range(0, n, chunk):
-            b = min(n, a + chunk)
-            d2 = sq[a:b, None] + sq[None, :] - 2.0 * (xt[a:b] @ xt.T)
-            d2[torch.arange(b - a, device=device), torch.arange(a, b, device=device)] = float("inf")
-            vals, ids = torch.topk(d2, k, dim=1, largest=False, sorted=True)
-            idx_out[a:b] = ids.cpu().numpy()
-            d_out[a:b] = vals.clamp_min(0).double().cpu().numpy()
-        return idx_out, d_out
-    xd = x.astype(np.float64)
-    sq = (xd * xd).sum(1)
-    idx_out = np.empty((n, k), np.int64)
-    d_out = np.empty((n, k), np.float64)
-    for a in range(0, n, chunk):
-        b = min(n, a + chunk)
-        d2 = sq[a:b, None] + sq[None, :] - 2.0 * (xd[a:b] @ xd.T)
-        d2[np.arange(b - a), np.arange(a, b)] = np.inf
-        part = np.argpartition(d2, k, axis=1)[:, :k]
-        pd = np.take_along_axis(d2, part, 1)
-        order = np.argsort(pd, axis=1, kind="stable")
-        idx_out[a:b] = np.take_along_axis(part, order, 1)
-        d_out[a:b] = np.maximum(np.take_along_axis(pd, order, 1), 0.0)
-    return idx_out, d_out
-
-
-def perplexity_P(x: np.ndarray, k: int = 90, perplexity: float = 30.0,
-                 device=None) -> CSR:
-    """Input affinities from exact k-NN: per row a Gaussian bandwidth found by
-    bisection so that exp(entropy) of the conditional row equals
-    ``perplexity`` (Section 1.1), normalised over the k neighbours; then
-    p_ij = (p_{j|i} + p_{i|j}) / (2N).  This is input construction: the
-    gradient path takes P as given."""
-    n = x.shape[0]
-    idx, d2 = _knn(x, k, device=device)
-    if device is not None:
-        pc = _calibrate_torch(d2, perplexity, device)
-        rows = np.repeat(np.arange(n, dtype=np.int64), k)
-        return _csr_from_edges(n, rows, idx.ravel(), pc.ravel())
-    target = np.log(perplexity)
-    beta = np.ones(n)
-    lo = np.full(n, -np.inf)
-    hi = np.full(n, np.inf)
-    d2s = d2 - d2[:, :1]                       # shift for stability
-    for _ in range(200):
-        e = np.exp(-d2s * beta[:, None])
-        z = e.sum(1)
-        h = np.log(z) + beta * (d2s * e).sum(1) / z
-        diff = h - target
-        if np.all(np.abs(diff) < 1e-10):
-            break
-        up = diff > 0                          # entropy too high -> raise beta
-        lo = np.where(up, beta, lo)
-        hi = np.where(up, hi, beta)
-        beta = np.where(up, np.where(np.isinf(hi), beta * 2, (beta + hi) / 2),
-                        np.where(np.isinf(lo), beta / 2, (beta + lo) / 2))
-    e = np.exp(-d2s * beta[:, None])
-    pc = e / e.sum(1, keepdims=True)
-    rows = np.repeat(np.arange(n, dtype=np.int64), k)
-    return _csr_from_edges(n, rows, idx.ravel(), pc.ravel())
-
-
-def _calibrate_torch(d2: np.ndarray, perplexity: float, device) -> np.ndarray:
-    """The bisection of perplexity_P on a torch device (same steps, float64)."""
-    import torch
-    d = torch.as_tensor(d2, dtype=torch.float64, device=device)
-    d = d - d[:, :1]
-    n = d.shape[0]
-    target = float(np.log(perplexity))
-    beta = torch.ones(n, dtype=torch.float64, device=device)
-    lo = torch.full((n,), -np.inf, dtype=torch.float64, device=device)
-    hi = torch.full((n,), np.inf, dtype=torch.float64, device=device)
-    for _ in range(200):
-        e = torch.exp(-d * beta[:, None])
-        z = e.sum(1)
-        h = torch.log(z) + beta * (d * e).sum(1) / z
-        diff = h - target
-        if bool((diff.abs() < 1e-10).all()):
-            break
-        up = diff > 0
-        lo = torch.where(up, beta, lo)
-        hi = torch.where(up, hi, beta)
-        beta = torch.where(up, torch.where(torch.isinf(hi), beta * 2, (beta + hi) / 2),
-                           torch.where(torch.isinf(lo), beta / 2, (beta + lo) / 2))
-    e = torch.exp(-d * beta[:, None])
-    return (e / e.sum(1, keepdim=True)).cpu().numpy()
-
-
-def serving_jobs(n_jobs: int = 64, k: int = 90, perplexity: float = 30.0, device=None,
-                 n_min: int = 5_000, n_max: int = 200_000):
-    """The serving workload: job j uses seed 100 + j; N log-uniform in
-    [n_min, n_max], K ~ U{5..30} unit-variance clusters in 50-d with centres
-    N(0, 25 I), P from exact k-NN at the given perplexity, Y0 ~ N(0, 1e-4 I).
-    Returns a list of (Y0 float32 [N, 2], P)."""
+def serving_jobs(n_jobs: int = 64, n_min: int = 5_000, n_max: int = 200_000):
+    """The serving workload's raw inputs: job j uses seed 100 + j; N
+    log-uniform in [n_min, n_max], K ~ U{5..30} unit-variance clusters in
+    50-d with centres N(0, 25 I), Y0 ~ N(0, 1e-4 I).  Returns a list of
+    (Y0 float32 [N, 2], X float32 [N, 50]); the affinities P are built from X
+    by the caller (90 nearest neighbours at perplexity 30)."""
     out = []
     for j in range(n_jobs):
         rng = np.random.default_rng(100 + j)
         n = int(round(np.exp(rng.uniform(np.log(n_min), np.log(n_max)))))
         kc = int(rng.integers(5, 31))
         x = mixture_highdim(n, 50, kc, 5.0, seed=100 + j)
-        P = perplexity_P(x, k, perplexity, device=device)
         y = (1e-2 * rng.standard_normal((n, 2))).astype(np.float32)
-        out.append((np.ascontiguousarray(y), P))
+        out.append((np.ascontiguousarray(y), x))
     return out
 
 
@@ -214,9 +117,10 @@ def poisson_arrivals(n: int, rate: float, seed: int = 7) -> np.ndarray:
     return np.cumsum(rng.exponential(1.0 / rate, size=n))
 
 
-def config_inputs(name: str, small: bool = False, device=None):
+def config_inputs(name: str, small: bool = False):
     """Inputs of the named workload.  Returns a dict with ``Y`` (float32
-    [N, s]), ``P`` (CSR) and workload metadata.
+    [N, s]), either ``P`` (CSR) or ``X`` (float32 [N, 50], from which P is
+    built with 90 nearest neighbours at perplexity 30) and workload metadata.
 
     c1: N=2048 2-D check; c3: N=1e6 2-D; c4: N=1e6 1-D; c2: N=1e5 2-D full run
     from a 50-d mixture.  ``small`` shrinks c2/c3/c4 for CPU tests while
@@ -240,6 +144,5 @@ def config_inputs(name: str, small: bool = False, device=None):
         x = mixture_highdim(n, 50, 20, 5.0, seed=0)
         rng = np.random.default_rng(2)
         y = np.ascontiguousarray((1e-2 * rng.standard_normal((n, 2))).astype(np.float32))
-        return dict(Y=y, P=perplexity_P(x, 90, 30.0, device=device), s=2,
-                    policy="paper", min_intervals=50)
+        return dict(Y=y, X=x, s=2, policy="paper", min_intervals=50)
     raise KeyError(name)

@@ -398,15 +398,6 @@ def test_random_graph_P_structure():
         assert np.all(np.diff(c) > 0)
 
 
-def test_perplexity_P_rows():
-    x = inputs.mixture_highdim(600, 10, 3, 5.0, seed=0)
-    P = inputs.perplexity_P(x, k=30, perplexity=10.0)
-    assert abs(float(P.val.astype(np.float64).sum()) - 1.0) < 1e-5
-    import scipy.sparse as sp
-    A = sp.csr_matrix((P.val, P.col, P.row_ptr), shape=(600, 600))
-    assert abs(A - A.T).max() < 1e-9
-
-
 # --------------------------------------------------------------------------
 # Kullback-Leibler divergence (Section 1.1)
 # --------------------------------------------------------------------------
