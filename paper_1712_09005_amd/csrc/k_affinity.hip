@@ -33,22 +33,23 @@ __device__ __forceinline__ bool pair_less(float da, int ia, float db, int ib)
     return da < db || (da == db && ia < ib);
 }
 
-// Block-wide bitonic sort of the buffers of the flagged queries (CAP entries
-// each, empty slots holding (+inf, INT_MAX)).
+// Block-wide bitonic sort of the buffers of the flagged queries (CAPv
+// entries each, empty slots holding (+inf, INT_MAX)).
+template <int QBv, int CAPv>
 __device__ void sort_buffers(float* bd, int* bi, const int* flag)
 {
-    constexpr int PAIRS = QB * CAP / 2;
-    for (int size = 2; size <= CAP; size <<= 1) {
+    constexpr int PAIRS = QBv * CAPv / 2;
+    for (int size = 2; size <= CAPv; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             for (int e = threadIdx.x; e < PAIRS; e += blockDim.x) {
-                const int q = e / (CAP / 2);
+                const int q = e / (CAPv / 2);
                 if (!flag[q]) continue;
-                const int r = e - q * (CAP / 2);
+                const int r = e - q * (CAPv / 2);
                 const int i = 2 * r - (r & (stride - 1));
                 const int j = i + stride;
                 const bool up = (i & size) == 0;
-                float* d = bd + q * CAP;
-                int* x = bi + q * CAP;
+                float* d = bd + q * CAPv;
+                int* x = bi + q * CAPv;
                 const float di = d[i], dj = d[j];
                 const int xi = x[i], xj = x[j];
                 if (pair_less(dj, xj, di, xi) == up) {
@@ -61,23 +62,82 @@ __device__ void sort_buffers(float* bd, int* bi, const int* flag)
     }
 }
 
-// Sort the flagged buffers, keep the k best, reset the rest to empty and
-// take the k-th distance as the new admission threshold.
-__device__ void compact(float* bd, int* bi, int* cnt, float* thr, int* flag, int k)
+// Sort the flagged buffers, keep the kk best, reset the rest to empty and
+// take the kk-th distance as the new admission threshold.
+template <int QBv, int CAPv>
+__device__ void compact(float* bd, int* bi, int* cnt, float* thr, int* flag, int kk)
 {
-    sort_buffers(bd, bi, flag);
-    for (int e = threadIdx.x; e < QB * CAP; e += blockDim.x) {
-        const int q = e / CAP, s = e - q * CAP;
-        if (!flag[q] || s < k) continue;
+    sort_buffers<QBv, CAPv>(bd, bi, flag);
+    for (int e = threadIdx.x; e < QBv * CAPv; e += blockDim.x) {
+        const int q = e / CAPv, s = e - q * CAPv;
+        if (!flag[q] || s < kk) continue;
         bd[e] = INFINITY;
         bi[e] = INT_MAX;
     }
     __syncthreads();
-    if (threadIdx.x < QB && flag[threadIdx.x]) {
-        const int q = threadIdx.x;
-        cnt[q] = min(cnt[q], k);
-        thr[q] = (cnt[q] == k) ? bd[q * CAP + k - 1] : INFINITY;
+    for (int q = threadIdx.x; q < QBv; q += blockDim.x) {
+        if (!flag[q]) continue;
+        cnt[q] = min(cnt[q], kk);
+        thr[q] = (cnt[q] == kk) ? bd[q * CAPv + kk - 1] : INFINITY;
         flag[q] = 0;
+    }
+    __syncthreads();
+}
+
+// Wave-synchronous step of a sort: the wave's LDS writes are complete and
+// visible to its other lanes before it goes on (no block barrier).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Bitonic sort of one query's CAPv-entry buffer by one wave.
+template <int CAPv>
+__device__ void wave_sort(float* d, int* x)
+{
+    const int lane = threadIdx.x & 63;
+    for (int size = 2; size <= CAPv; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int r = lane; r < CAPv / 2; r += 64) {
+                const int i = 2 * r - (r & (stride - 1));
+                const int j = i + stride;
+                const bool up = (i & size) == 0;
+                const float di = d[i], dj = d[j];
+                const int xi = x[i], xj = x[j];
+                if (pair_less(dj, xj, di, xi) == up) {
+                    d[i] = dj; d[j] = di;
+                    x[i] = xj; x[j] = xi;
+                }
+            }
+            wave_sync();
+        }
+    }
+}
+
+// Like compact, with each flagged query's buffer sorted by one wave (the
+// block's waves take the flagged queries in turn): two block barriers per
+// call instead of one per sorting step.
+template <int QBv, int CAPv>
+__device__ void compact_waves(float* bd, int* bi, int* cnt, float* thr, int* flag, int kk)
+{
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    for (int q = threadIdx.x >> 6; q < QBv; q += nw) {
+        if (!flag[q]) continue;
+        float* d = bd + q * CAPv;
+        int* x = bi + q * CAPv;
+        wave_sort<CAPv>(d, x);
+        for (int s = kk + lane; s < CAPv; s += 64) {
+            d[s] = INFINITY;
+            x[s] = INT_MAX;
+        }
+        wave_sync();
+        if (lane == 0) {
+            cnt[q] = min(cnt[q], kk);
+            thr[q] = (cnt[q] == kk) ? d[kk - 1] : INFINITY;
+            flag[q] = 0;
+        }
     }
     __syncthreads();
 }
@@ -148,7 +208,7 @@ __global__ __launch_bounds__(256) void k_knn(const float* __restrict__ X, int64_
         }
         __syncthreads();
         for (int q = 0; q < QB; ++q) any |= flag[q];
-        if (any) compact(bd, bi, cnt, thr, flag, k);
+        if (any) compact_waves<QB, CAP>(bd, bi, cnt, thr, flag, k);
     }
     // the buffers now hold the k nearest in order
     for (int e = threadIdx.x; e < QB * k; e += blockDim.x) {
@@ -156,6 +216,142 @@ __global__ __launch_bounds__(256) void k_knn(const float* __restrict__ X, int64_
         if (q0 + q < n) {
             idx[(q0 + q) * k + t] = bi[q * CAP + t];
             dist2[(q0 + q) * k + t] = bd[q * CAP + t];
+        }
+    }
+}
+
+// Exact kNN with the dot products on the matrix cores: a 64-query x
+// 64-candidate tile per step, each wave one 16-query row of four 16 x 16
+// FP32 MFMA tiles (v_mfma_f32_16x16x4f32, K = 4 coordinates per instruction;
+// lane l holds A[l % 16][l / 16], B[l / 16][l % 16] and D[4 (l / 16) + r][l % 16]).
+// Squared distances |q|^2 + |c|^2 - 2 q.c select the k + 8 best per query
+// through the same LDS candidate buffer; those are then recomputed exactly
+// over the coordinate differences and re-sorted, so the k returned are
+// ordered by their exact FP32 distance (ties by index).  dim <= 56.
+constexpr int MQB = 64, MCB = 64, MCAP = 256, MKMAX = MCAP - MCB, MDMAX = 56, MKX = 8;
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_knn_mfma(const float* __restrict__ X, int64_t n, int dim, int k,
+                                                  int32_t* __restrict__ idx, float* __restrict__ dist2)
+{
+    __shared__ float xqT[MDMAX][MQB];
+    __shared__ float xcT[MDMAX][MCB + 1];
+    __shared__ float qn[MQB], cn[MCB];
+    __shared__ float bd[MQB * MCAP];
+    __shared__ int bi[MQB * MCAP];
+    __shared__ int cnt[MQB], flag[MQB];
+    __shared__ float thr[MQB];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int dim4 = (dim + 3) & ~3;
+    const int kx = k + MKX;
+    const int64_t q0 = (int64_t)blockIdx.x * MQB;
+    for (int e = tid; e < MQB * dim4; e += 256) {
+        const int q = e / dim4, dd = e - q * dim4;
+        xqT[dd][q] = (q0 + q < n && dd < dim) ? X[(q0 + q) * dim + dd] : 0.0f;
+    }
+    for (int e = tid; e < MQB * MCAP; e += 256) {
+        bd[e] = INFINITY;
+        bi[e] = INT_MAX;
+    }
+    for (int e = tid; e < MDMAX * (MCB + 1); e += 256) (&xcT[0][0])[e] = 0.0f;   // padding dims stay 0
+    const float rdim = 1.0f / (float)dim;
+    constexpr int SJ = (MCB * MDMAX + 255) / 256;     // staged values per thread
+    __syncthreads();
+    if (tid < MQB) {
+        float a = 0.0f;
+        for (int dd = 0; dd < dim4; ++dd) a = fmaf(xqT[dd][tid], xqT[dd][tid], a);
+        qn[tid] = a;
+        cnt[tid] = 0;
+        flag[tid] = 0;
+        thr[tid] = INFINITY;
+    }
+    const int li = lane & 15, lk = lane >> 4;
+    for (int64_t c0 = 0; c0 < n; c0 += MCB) {
+        // the chunk is one contiguous run of X: all loads first (coalesced,
+        // in flight together), then the transposed LDS stores
+        const int64_t base = c0 * dim;
+        const int lim = (int)min((int64_t)MCB, n - c0) * dim, tot = MCB * dim;
+        float tmp[SJ];
+#pragma unroll
+        for (int j = 0; j < SJ; ++j) {
+            const int e = tid + 256 * j;
+            tmp[j] = (e < lim) ? X[base + e] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < SJ; ++j) {
+            const int e = tid + 256 * j;
+            if (e < tot) {
+                int c = (int)((float)e * rdim);
+                int dd = e - c * dim;
+                if (dd < 0) { --c; dd += dim; } else if (dd >= dim) { ++c; dd -= dim; }
+                xcT[dd][c] = tmp[j];
+            }
+        }
+        __syncthreads();
+        if (tid < MCB) {
+            float a = 0.0f;
+            for (int dd = 0; dd < dim4; ++dd) a = fmaf(xcT[dd][tid], xcT[dd][tid], a);
+            cn[tid] = a;
+        }
+        v4f acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int kk = 0; kk < dim4; kk += 4) {
+            const float a = xqT[kk + lk][16 * w + li];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xcT[kk + lk][16 * t + li], acc[t], 0, 0, 0);
+        }
+        __syncthreads();                   // cn ready
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int qi = 16 * w + 4 * lk + r, cj = 16 * t + li;
+                const int64_t cg = c0 + cj;
+                const float d = fmaxf(qn[qi] + cn[cj] - 2.0f * acc[t][r], 0.0f);
+                if (cg < n && q0 + qi < n && cg != q0 + qi && d < thr[qi]) {
+                    const int s = atomicAdd(&cnt[qi], 1);
+                    bd[qi * MCAP + s] = d;
+                    bi[qi * MCAP + s] = (int)cg;
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < MQB) flag[tid] = (cnt[tid] > MKMAX) ? 1 : 0;
+        __syncthreads();
+        int any = 0;
+        for (int q = 0; q < MQB; ++q) any |= flag[q];
+        if (any) compact_waves<MQB, MCAP>(bd, bi, cnt, thr, flag, kx);
+    }
+    __syncthreads();
+    if (tid < MQB) flag[tid] = 1;
+    __syncthreads();
+    compact_waves<MQB, MCAP>(bd, bi, cnt, thr, flag, kx);
+    // exact distances of the kept candidates, then the final order
+    for (int e = tid; e < MQB * kx; e += 256) {
+        const int q = e / kx, t = e - q * kx;
+        if (q0 + q >= n || t >= cnt[q]) continue;
+        const int64_t c = bi[q * MCAP + t];
+        const float* xa = X + (q0 + q) * dim;
+        const float* xb = X + c * dim;
+        float a = 0.0f;
+        for (int dd = 0; dd < dim; ++dd) {
+            const float u = xa[dd] - xb[dd];
+            a = fmaf(u, u, a);
+        }
+        bd[q * MCAP + t] = a;
+    }
+    __syncthreads();
+    if (tid < MQB) flag[tid] = 1;
+    __syncthreads();
+    sort_buffers<MQB, MCAP>(bd, bi, flag);
+    for (int e = tid; e < MQB * k; e += 256) {
+        const int q = e / k, t = e - q * k;
+        if (q0 + q < n) {
+            idx[(q0 + q) * k + t] = bi[q * MCAP + t];
+            dist2[(q0 + q) * k + t] = bd[q * MCAP + t];
         }
     }
 }
@@ -475,8 +671,14 @@ tsne_status tsne_knn(const float* X, int64_t n, int32_t dim, int32_t k, int32_t*
         return TSNE_E_ARG;
     if (k > KMAX) return TSNE_E_UNSUPPORTED;
     const hipStream_t st = static_cast<hipStream_t>(stream);
-    const int64_t nb = (n + QB - 1) / QB;
-    hipLaunchKernelGGL(k_knn, dim3((unsigned)nb), dim3(CB), 0, st, X, n, (int)dim, (int)k, idx, dist2);
+    if (dim <= MDMAX && k + MKX <= MKMAX && k + MKX < n) {
+        const int64_t nb = (n + MQB - 1) / MQB;
+        hipLaunchKernelGGL(k_knn_mfma, dim3((unsigned)nb), dim3(256), 0, st, X, n, (int)dim, (int)k, idx,
+                           dist2);
+    } else {
+        const int64_t nb = (n + QB - 1) / QB;
+        hipLaunchKernelGGL(k_knn, dim3((unsigned)nb), dim3(CB), 0, st, X, n, (int)dim, (int)k, idx, dist2);
+    }
     return hipGetLastError() == hipSuccess ? TSNE_OK : TSNE_E_HIP;
 }
 
