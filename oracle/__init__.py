@@ -26,7 +26,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 KERNEL_TSNE, KERNEL_POLY = 0, 1
-FORM_A, FORM_B = 0, 1
+FORM_A, FORM_B, FORM_V = 0, 1, 2
 POLICY_PAPER, POLICY_FIXED = 0, 1
 
 _lib = None
@@ -218,7 +218,8 @@ def lagrange(p, t):
 
 
 def grid_conv(W, h, kernel, kind=KERNEL_TSNE):
-    """Step 2 directly on a 1-D [ng] or 2-D [ng, ng] (index [g1, g0]) grid."""
+    """Step 2 directly on a 1-D [ng] or 2-D [ng, ng] (index [g1, g0]) grid.
+    kernel: 1 = K1, 2 = K2, 3 / 4 = the odd kernels z_0 K2, z_1 K2."""
     W = _f64(W)
     s = W.ndim
     ng = W.shape[0]
@@ -236,13 +237,14 @@ def interp_rep(Y, origin, w_int, n_int, p=3, form=FORM_A, kind=KERNEL_TSNE,
     o = _f64(origin)
     ng = n_int * p
     tn = ng ** s
-    nc = s + 1 if form == FORM_A else s + 2
+    nc = s + 1 if form == FORM_A else (s + 2 if form == FORM_B else 1)
+    npot = s + 1 if form == FORM_V else s + 2
     F = np.empty((n, s))
     Z = ctypes.c_double()
-    phi = np.empty((n, s + 2))
+    phi = np.empty((n, npot))
     h1 = np.empty(n)
     W = np.empty((nc, tn)) if want_grids else None
-    V = np.empty((s + 2, tn)) if want_grids else None
+    V = np.empty((npot, tn)) if want_grids else None
     rc = _load().oracle_interp_rep(n, s, _ptr(Y), _ptr(o), float(w_int), int(n_int), int(p),
                                    int(form), int(kind), _ptr(F), ctypes.addressof(Z),
                                    _ptr(W), _ptr(V), _ptr(phi), _ptr(h1))
@@ -252,7 +254,7 @@ def interp_rep(Y, origin, w_int, n_int, p=3, form=FORM_A, kind=KERNEL_TSNE,
     if want_grids:
         shape = (ng,) if s == 1 else (ng, ng)
         out["W"] = W.reshape((nc,) + shape)
-        out["V"] = V.reshape((s + 2,) + shape)
+        out["V"] = V.reshape((npot,) + shape)
     return out
 
 
@@ -260,7 +262,7 @@ def interp_spread(Y, origin, w_int, n_int, p=3, form=FORM_A):
     Y = _f64(Y)
     n, s = Y.shape
     ng = n_int * p
-    nc = s + 1 if form == FORM_A else s + 2
+    nc = s + 1 if form == FORM_A else (s + 2 if form == FORM_B else 1)
     W = np.empty((nc, ng ** s))
     rc = _load().oracle_interp_spread(n, s, _ptr(Y), _ptr(_f64(origin)), float(w_int),
                                       int(n_int), int(p), int(form), _ptr(W))
@@ -270,11 +272,12 @@ def interp_spread(Y, origin, w_int, n_int, p=3, form=FORM_A):
 
 
 def interp_rows(Y, origin, w_int, n_int, rows, W, p=3, form=FORM_A, kind=KERNEL_TSNE):
-    """phi [len(rows), s+2] at the listed points, node values by direct sums."""
+    """phi [len(rows), P] at the listed points (P = s+2, or s+1 for form V),
+    node values by direct sums."""
     Y = _f64(Y)
     n, s = Y.shape
     r = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
-    phi = np.empty((r.shape[0], s + 2))
+    phi = np.empty((r.shape[0], s + 1 if form == FORM_V else s + 2))
     rc = _load().oracle_interp_rows(n, s, _ptr(Y), _ptr(_f64(origin)), float(w_int),
                                     int(n_int), int(p), int(form), int(kind), _ptr(_f64(W)),
                                     _ptr(r), r.shape[0], _ptr(phi))
@@ -294,6 +297,8 @@ def assemble_rows(Y, origin, w_int, n_int, phi, form=FORM_A):
     Y = _f64(Y)
     s = Y.shape[1]
     yc = Y - centre(origin, w_int, n_int)
+    if form == FORM_V:
+        return phi[:, 0].copy(), phi[:, 1:1 + s].copy()
     if form == FORM_A:
         h1 = phi[:, 0].copy()
     else:

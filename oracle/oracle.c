@@ -51,7 +51,7 @@ enum { ORACLE_KERNEL_TSNE = 0, ORACLE_KERNEL_POLY = 1 };
 /* Charge sets: FORM_A follows the Appendix (K1 with charge 1, K2 with charges
  * 1 and y(d)); FORM_B uses K2 with charges 1, y(d) and |y|^2, and gets the K1
  * sum from K1 = (1 + r^2) K2. */
-enum { ORACLE_FORM_A = 0, ORACLE_FORM_B = 1 };
+enum { ORACLE_FORM_A = 0, ORACLE_FORM_B = 1, ORACLE_FORM_V = 2 };
 enum { ORACLE_POLICY_PAPER = 0, ORACLE_POLICY_FIXED = 1 };
 
 static double kern1(int kind, double r2)
@@ -240,10 +240,12 @@ static void locate(double y, double o, double w, int n_int, int* cell, double* t
 
 /* Step 2 directly (eq. (equikereval2)): on a grid with ng nodes per dimension
  * and spacing h,
- *   V[g] = sum_{g'} K(h^2 |g - g'|^2) W[g'],
- * where kernel selects K1 (1) or K2 (2).  2-D grids are indexed g1*ng + g0.
- * The kernel values are taken from a table over the lag (|g0-g0'|, |g1-g1'|),
- * which is the translation invariance that makes the matrix Toeplitz. */
+ *   V[g] = sum_{g'} K(h (g - g')) W[g'],
+ * where kernel selects K1 (1), K2 (2), or the odd vector kernels
+ * G_d(z) = z_d K2(|z|^2) along dimension 0 (3) or 1 (4).  2-D grids are
+ * indexed g1*ng + g0.  The kernel values come from a table over the lag
+ * (|g0-g0'|, |g1-g1'|), with the sign of the lag along d for G_d: the
+ * translation invariance that makes the matrix Toeplitz. */
 void oracle_grid_conv(int s, int ng, double h, int kind, int kernel,
                       const double* W, double* V)
 {
@@ -252,13 +254,19 @@ void oracle_grid_conv(int s, int ng, double h, int kind, int kernel,
     for (int64_t a = 0; a < tn; ++a) {
         double dx = (double)(a % ng), dy = (s == 1) ? 0.0 : (double)(a / ng);
         double r2 = h * h * (dx * dx + dy * dy);
-        T[a] = (kernel == 1) ? kern1(kind, r2) : kern2(kind, r2);
+        if (kernel == 1) T[a] = kern1(kind, r2);
+        else if (kernel == 2) T[a] = kern2(kind, r2);
+        else if (kernel == 3) T[a] = h * dx * kern2(kind, r2);
+        else T[a] = h * dy * kern2(kind, r2);
     }
     if (s == 1) {
 #pragma omp parallel for schedule(static)
         for (int g = 0; g < ng; ++g) {
             double acc = 0.0;
-            for (int q = 0; q < ng; ++q) acc += T[abs(g - q)] * W[q];
+            for (int q = 0; q < ng; ++q) {
+                const double sg = (kernel == 3) ? (double)((g > q) - (g < q)) : 1.0;
+                acc += sg * T[abs(g - q)] * W[q];
+            }
             V[g] = acc;
         }
     } else {
@@ -269,7 +277,11 @@ void oracle_grid_conv(int s, int ng, double h, int kind, int kernel,
             for (int q1 = 0; q1 < ng; ++q1) {
                 const double* Trow = T + (int64_t)abs(g1 - q1) * ng;
                 const double* Wrow = W + (int64_t)q1 * ng;
-                for (int q0 = 0; q0 < ng; ++q0) acc += Trow[abs(g0 - q0)] * Wrow[q0];
+                const double s1 = (kernel == 4) ? (double)((g1 > q1) - (g1 < q1)) : 1.0;
+                for (int q0 = 0; q0 < ng; ++q0) {
+                    const double s0 = (kernel == 3) ? (double)((g0 > q0) - (g0 < q0)) : 1.0;
+                    acc += s0 * s1 * Trow[abs(g0 - q0)] * Wrow[q0];
+                }
             }
             V[g] = acc;
         }
@@ -285,6 +297,10 @@ void oracle_grid_conv(int s, int ng, double h, int kind, int kernel,
  *   pot[0] = K1 * 1 (form A)  or  K2 * |y'|^2 (form B)
  *   pot[1] = K2 * 1
  *   pot[2+d] = K2 * y'(d)
+ * Form V (the vector-kernel variant, not in the paper): the single charge 1
+ * and s + 1 potentials pot[0] = K1 * 1, pot[1+d] = G_d * 1 with the odd
+ * kernels G_d(z) = z_d K2(|z|^2), so pot[1+d] at y_i is the numerator
+ * sum_j (y_i(d) - y_j(d)) K2 itself, with no cancellation.
  * Step 1 spreads each charge onto the nodes of its point's interval (square),
  * Step 2 is oracle_grid_conv, Step 3 interpolates back (Section 2.2,
  * Algorithm 1; tensor-product nodes for s = 2, Section 2.4).  Assembly
@@ -292,10 +308,12 @@ void oracle_grid_conv(int s, int ng, double h, int kind, int kernel,
  * h1 = (1 + |y'|^2) pot[1] - 2 y'.pot[2..] + pot[0] (form B);
  * Z = sum_i h1_i - N K1(0); F_i(d) = (y'_i(d) pot[1]_i - pot[2+d]_i) / Z.
  *
+ * Form V: h1 = pot[0], F_i(d) = pot[1+d]_i / Z.
+ *
  * Outputs: F [n*s], Z; optional (may be NULL): Wout [C][ng^s] charge grids
- * (C = s+1 form A, s+2 form B, charge order 1, y'(0..s-1), |y'|^2),
- * Vout [s+2][ng^s] potential grids, phi [n][s+2] potentials at the points,
- * h1 [n].  Returns 0, or -1 on bad arguments. */
+ * (C = s+1 form A, s+2 form B, 1 form V; charge order 1, y'(0..s-1), |y'|^2),
+ * Vout [P][ng^s] potential grids (P = s+2, or s+1 form V), phi [n][P]
+ * potentials at the points, h1 [n].  Returns 0, or -1 on bad arguments. */
 int oracle_interp_rep(int64_t n, int s, const double* Y, const double* origin,
                       double w, int n_int, int p, int form, int kind,
                       double* F, double* Z, double* Wout, double* Vout,
@@ -304,8 +322,8 @@ int oracle_interp_rep(int64_t n, int s, const double* Y, const double* origin,
     if (s < 1 || s > 2 || p < 1 || n_int < 1 || n < 1) return -1;
     int ng = n_int * p;
     int64_t tn = (s == 1) ? ng : (int64_t)ng * ng;
-    int nc = (form == ORACLE_FORM_A) ? s + 1 : s + 2;
-    int np = s + 2;
+    int nc = (form == ORACLE_FORM_A) ? s + 1 : (form == ORACLE_FORM_B) ? s + 2 : 1;
+    int np = (form == ORACLE_FORM_V) ? s + 1 : s + 2;
     double h = w / p;
     double centre[2];
     for (int d = 0; d < s; ++d) centre[d] = origin[d] + 0.5 * n_int * w;
@@ -321,7 +339,7 @@ int oracle_interp_rep(int64_t n, int s, const double* Y, const double* origin,
             locate(Y[i * s + d], origin[d], w, n_int, &cells[i * s + d], &t);
             oracle_lagrange(p, t, wts + (i * s + d) * p);
             double yc = Y[i * s + d] - centre[d];
-            q[i * nc + 1 + d] = yc;
+            if (form != ORACLE_FORM_V) q[i * nc + 1 + d] = yc;
             r2c += yc * yc;
         }
         if (form == ORACLE_FORM_B) q[i * nc + 1 + s] = r2c;
@@ -351,10 +369,15 @@ int oracle_interp_rep(int64_t n, int s, const double* Y, const double* origin,
     /* Step 2: v = K~ w for every (kernel, charge) pair */
     double* V = (double*)malloc((size_t)np * tn * sizeof(double));
     int pk[5], pc[5];
-    if (form == ORACLE_FORM_A) { pk[0] = 1; pc[0] = 0; }
-    else                       { pk[0] = 2; pc[0] = s + 1; }
-    pk[1] = 2; pc[1] = 0;
-    for (int d = 0; d < s; ++d) { pk[2 + d] = 2; pc[2 + d] = 1 + d; }
+    if (form == ORACLE_FORM_V) {
+        pk[0] = 1; pc[0] = 0;
+        for (int d = 0; d < s; ++d) { pk[1 + d] = 3 + d; pc[1 + d] = 0; }
+    } else {
+        if (form == ORACLE_FORM_A) { pk[0] = 1; pc[0] = 0; }
+        else                       { pk[0] = 2; pc[0] = s + 1; }
+        pk[1] = 2; pc[1] = 0;
+        for (int d = 0; d < s; ++d) { pk[2 + d] = 2; pc[2 + d] = 1 + d; }
+    }
     for (int k = 0; k < np; ++k)
         oracle_grid_conv(s, ng, h, kind, pk[k], W + (int64_t)pc[k] * tn, V + (int64_t)k * tn);
 
@@ -385,7 +408,7 @@ int oracle_interp_rep(int64_t n, int s, const double* Y, const double* origin,
     for (int64_t i = 0; i < n; ++i) {
         const double* f = ph + i * np;
         double a;
-        if (form == ORACLE_FORM_A) {
+        if (form == ORACLE_FORM_A || form == ORACLE_FORM_V) {
             a = f[0];
         } else {
             double r2c = q[i * nc + 1 + s], dot = 0.0;
@@ -398,7 +421,9 @@ int oracle_interp_rep(int64_t n, int s, const double* Y, const double* origin,
     z -= (double)n * kern1(kind, 0.0);
     for (int64_t i = 0; i < n; ++i)
         for (int d = 0; d < s; ++d)
-            F[i * s + d] = (q[i * nc + 1 + d] * ph[i * np + 1] - ph[i * np + 2 + d]) / z;
+            F[i * s + d] = (form == ORACLE_FORM_V)
+                               ? ph[i * np + 1 + d] / z
+                               : (q[i * nc + 1 + d] * ph[i * np + 1] - ph[i * np + 2 + d]) / z;
     *Z = z;
 
     if (Wout) memcpy(Wout, W, (size_t)nc * tn * sizeof(double));
@@ -416,7 +441,7 @@ int oracle_interp_spread(int64_t n, int s, const double* Y, const double* origin
     if (s < 1 || s > 2 || p < 1 || n_int < 1) return -1;
     int ng = n_int * p;
     int64_t tn = (s == 1) ? ng : (int64_t)ng * ng;
-    int nc = (form == ORACLE_FORM_A) ? s + 1 : s + 2;
+    int nc = (form == ORACLE_FORM_A) ? s + 1 : (form == ORACLE_FORM_B) ? s + 2 : 1;
     double centre[2], L0[16], L1[16];
     for (int d = 0; d < s; ++d) centre[d] = origin[d] + 0.5 * n_int * w;
     memset(Wout, 0, (size_t)nc * tn * sizeof(double));
@@ -461,20 +486,28 @@ int oracle_interp_rows(int64_t n, int s, const double* Y, const double* origin,
     if (s < 1 || s > 2 || p < 1 || n_int < 1) return -1;
     int ng = n_int * p;
     int64_t tn = (s == 1) ? ng : (int64_t)ng * ng;
-    int np = s + 2;
+    int np = (form == ORACLE_FORM_V) ? s + 1 : s + 2;
     double h = w / p;
     int pk[5], pc[5];
-    if (form == ORACLE_FORM_A) { pk[0] = 1; pc[0] = 0; }
-    else                       { pk[0] = 2; pc[0] = s + 1; }
-    pk[1] = 2; pc[1] = 0;
-    for (int d = 0; d < s; ++d) { pk[2 + d] = 2; pc[2 + d] = 1 + d; }
-    /* kernel values by lag (|dg0|, |dg1|), as in oracle_grid_conv */
-    double* T = (double*)malloc((size_t)2 * tn * sizeof(double));
+    if (form == ORACLE_FORM_V) {
+        pk[0] = 1; pc[0] = 0;
+        for (int d = 0; d < s; ++d) { pk[1 + d] = 3 + d; pc[1 + d] = 0; }
+    } else {
+        if (form == ORACLE_FORM_A) { pk[0] = 1; pc[0] = 0; }
+        else                       { pk[0] = 2; pc[0] = s + 1; }
+        pk[1] = 2; pc[1] = 0;
+        for (int d = 0; d < s; ++d) { pk[2 + d] = 2; pc[2 + d] = 1 + d; }
+    }
+    /* kernel values by lag (|dg0|, |dg1|), as in oracle_grid_conv: K1, K2,
+     * then |z_0| K2 and |z_1| K2 (the odd kernels without their sign) */
+    double* T = (double*)malloc((size_t)4 * tn * sizeof(double));
     for (int64_t a = 0; a < tn; ++a) {
         double dx = (double)(a % ng), dy = (s == 1) ? 0.0 : (double)(a / ng);
         double r2 = h * h * (dx * dx + dy * dy);
         T[a] = kern1(kind, r2);
         T[tn + a] = kern2(kind, r2);
+        T[2 * tn + a] = h * dx * kern2(kind, r2);
+        T[3 * tn + a] = h * dy * kern2(kind, r2);
     }
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t r = 0; r < nrows; ++r) {
@@ -496,13 +529,17 @@ int oracle_interp_rows(int64_t n, int s, const double* Y, const double* origin,
                 for (int m0 = 0; m0 < p; ++m0) {
                     int g0 = c0 * p + m0, g1 = (s == 2) ? c1 * p + m1 : 0;
                     /* node value by the direct sum over all nodes */
-                    const double* Tk = T + (pk[k] == 1 ? 0 : tn);
+                    const double* Tk = T + (int64_t)(pk[k] - 1) * tn;
                     const double* Wc = W + (int64_t)pc[k] * tn;
                     double v = 0.0;
                     for (int q1 = 0; q1 < ((s == 2) ? ng : 1); ++q1) {
                         const double* Trow = Tk + (int64_t)abs(g1 - q1) * ng;
                         const double* Wrow = Wc + (int64_t)q1 * ng;
-                        for (int q0 = 0; q0 < ng; ++q0) v += Trow[abs(g0 - q0)] * Wrow[q0];
+                        const double s1 = (pk[k] == 4) ? (double)((g1 > q1) - (g1 < q1)) : 1.0;
+                        for (int q0 = 0; q0 < ng; ++q0) {
+                            const double s0 = (pk[k] == 3) ? (double)((g0 > q0) - (g0 < q0)) : 1.0;
+                            v += s0 * s1 * Trow[abs(g0 - q0)] * Wrow[q0];
+                        }
                     }
                     acc += L0[m0] * L1[m1] * v;
                 }

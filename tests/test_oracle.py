@@ -173,6 +173,32 @@ def test_grid_conv_vs_numpy_fft(s, ng, kernel):
     np.testing.assert_allclose(V, Vf, atol=1e-12 * np.abs(Vf).max())
 
 
+@pytest.mark.parametrize("s,ng,kernel", [(1, 37, 3), (2, 12, 3), (2, 9, 4), (2, 10, 4)])
+def test_grid_conv_odd_kernels_vs_numpy_fft(s, ng, kernel):
+    """The odd kernels G_d(z) = z_d K2(|z|^2) (vector-kernel form): the
+    product with the signed-lag Toeplitz matrix equals the circulant
+    convolution whose kernel holds the signed lag j (j < M/2) or j - M
+    (j > M/2), by numpy's FFT.  A wrong sign or a transposed axis fails."""
+    rng = np.random.default_rng(s * 10 + ng + kernel)
+    h = 0.29
+    W = rng.standard_normal((ng,) * s)
+    V = oracle.grid_conv(W, h, kernel)
+    M = 2 * ng
+    j = np.arange(M)
+    js = np.where(j < M // 2, j, j - M).astype(float)
+    js[M // 2] = 0.0                                   # lag M/2 never reaches the first ng outputs
+    if s == 1:
+        K = h * js / (1.0 + h * h * js ** 2) ** 2
+    else:
+        a, b = js[:, None], js[None, :]                # [g1 lag, g0 lag]
+        K2 = 1.0 / (1.0 + h * h * (a ** 2 + b ** 2)) ** 2
+        K = h * (b if kernel == 3 else a) * K2
+    ax = tuple(range(s))
+    Vf = np.real(np.fft.ifftn(np.fft.fftn(W, (M,) * s, axes=ax) * np.fft.fftn(K, axes=ax), axes=ax))
+    Vf = Vf[tuple(slice(0, ng) for _ in range(s))]
+    np.testing.assert_allclose(V, Vf, atol=1e-12 * np.abs(Vf).max())
+
+
 # --------------------------------------------------------------------------
 # Interpolation scheme (Sections 2.1-2.4, Appendix)
 # --------------------------------------------------------------------------
@@ -238,6 +264,45 @@ def test_interp_matches_pairwise_interpolant(s, nint, p):
         assert np.all(np.abs(r["phi"][:, k] - exact) <= eps * np.abs(q).sum() * (1 + 1e-9) + 1e-13)
 
 
+def _brute_interp_vec(Y, o, w, nint, p, fn):
+    """sum_j K_p(y_i, y_j) for a kernel fn of the component differences
+    (dx) or (dx, dy), interpolated pair by pair as in _brute_phi."""
+    n, s = Y.shape
+    h = w / p
+    cells = np.clip(np.floor((Y - o) / w), 0, nint - 1).astype(int)
+    t = (Y - o) / w - cells
+    Ls = [[_vander_lagrange(p, t[i, d]) for d in range(s)] for i in range(n)]
+    node = [[o[d] + (cells[i, d] * p + np.arange(p) + 0.5) * h for d in range(s)] for i in range(n)]
+    out = np.zeros(n)
+    for i in range(n):
+        for j in range(n):
+            if s == 1:
+                out[i] += Ls[i][0] @ fn(node[i][0][:, None] - node[j][0][None, :]) @ Ls[j][0]
+            else:
+                a = node[i][0][:, None, None, None] - node[j][0][None, None, :, None]
+                b = node[i][1][None, :, None, None] - node[j][1][None, None, None, :]
+                out[i] += np.einsum("abcd,a,b,c,d->", fn(a, b), Ls[i][0], Ls[i][1], Ls[j][0], Ls[j][1])
+    return out
+
+
+@pytest.mark.parametrize("s,nint,p", [(1, 5, 3), (2, 3, 3), (2, 2, 4)])
+def test_interp_form_v_matches_pairwise_interpolant(s, nint, p):
+    """Form V's numerators are the pairwise sums of the interpolated odd
+    kernels z_d K2(|z|^2), z = y_i - y_j (brute force on a tiny input)."""
+    rng = np.random.default_rng(17 + s)
+    n = 30 if s == 1 else 20
+    Y = rng.uniform(1.0, 1.0 + 0.9 * nint, size=(n, s))
+    o, w, m = oracle.geometry(Y, "paper", nint)
+    r = oracle.interp_rep(Y, o, w, m, p, oracle.FORM_V)
+    if s == 1:
+        fns = [lambda a: a / (1.0 + a * a) ** 2]
+    else:
+        fns = [lambda a, b: a / (1.0 + a * a + b * b) ** 2, lambda a, b: b / (1.0 + a * a + b * b) ** 2]
+    for d, fn in enumerate(fns):
+        np.testing.assert_allclose(r["phi"][:, 1 + d], _brute_interp_vec(Y, o, w, m, p, fn),
+                                   rtol=1e-10, atol=1e-12)
+
+
 @pytest.mark.parametrize("s", [1, 2])
 def test_interp_single_interval_is_textbook_lagrange(s):
     """N_int = 1 is the single-interval three-step scheme of Section 2.1: with
@@ -284,6 +349,28 @@ def test_interp_exact_for_polynomial_kernels(s, form, p):
     assert _rel(r["F"], F) < 1e-10
 
 
+@pytest.mark.parametrize("s", [1, 2])
+def test_interp_form_v_polynomial_exactness(s):
+    """Vector-kernel form with the polynomial kernels: z_d K2 has degree 3
+    in z_d, K1 degree 4.  With p = 4 the numerators are reproduced to
+    rounding and h1 is not; with p = 5 both are (Section 2.1)."""
+    rng = np.random.default_rng(40 + s)
+    n = 300 if s == 1 else 150
+    Y = rng.uniform(-3.0, 4.0, size=(n, s))
+    o, w, m = oracle.geometry(Y, "paper", 7)
+    h1d, numd = oracle.direct_sums(Y, kind=oracle.KERNEL_POLY)
+    h1d = h1d + 2.0                  # h1 from the grid holds the self pair, K1(0) = 2 here
+    r4 = oracle.interp_rep(Y, o, w, m, 4, oracle.FORM_V, oracle.KERNEL_POLY)
+    assert _rel(r4["phi"][:, 1:], numd) < 1e-10
+    assert _rel(r4["h1"], h1d) > 1e-8
+    r5 = oracle.interp_rep(Y, o, w, m, 5, oracle.FORM_V, oracle.KERNEL_POLY)
+    assert _rel(r5["phi"][:, 1:], numd) < 1e-10
+    assert _rel(r5["h1"], h1d) < 1e-11
+    F, Z = oracle.direct_rep(Y, oracle.KERNEL_POLY)
+    assert r5["Z"] == pytest.approx(Z, rel=1e-11)
+    assert _rel(r5["F"], F) < 1e-10
+
+
 def test_interp_not_exact_for_polynomial_form_a_p3():
     """Counter-check of the previous test: form A with p = 3 cannot reproduce
     the degree-4 K1, so the same comparison must fail."""
@@ -310,16 +397,20 @@ def test_interp_third_order_convergence():
 
 
 def test_interp_forms_agree_and_sum_to_zero(cloud):
-    """Forms A and B approximate the same forces; the interpolated kernel is
-    symmetric (same nodes for sources and targets), so forces still sum to zero."""
+    """Forms A, B and V approximate the same forces; the interpolated kernel is
+    symmetric (same nodes for sources and targets; antisymmetric for the odd
+    kernels of form V), so forces still sum to zero.  Form A and form V share
+    the K1 potential, so their Z agree to rounding."""
     Y, _ = cloud
     o, w, m = oracle.geometry(Y, "paper", 20)
     ra = oracle.interp_rep(Y, o, w, m, 3, oracle.FORM_A)
     rb = oracle.interp_rep(Y, o, w, m, 3, oracle.FORM_B)
+    rv = oracle.interp_rep(Y, o, w, m, 3, oracle.FORM_V)
     F, Z = oracle.direct_rep(Y)
-    assert _rel(ra["F"], F) < 5e-2 and _rel(rb["F"], F) < 5e-2
+    assert _rel(ra["F"], F) < 5e-2 and _rel(rb["F"], F) < 5e-2 and _rel(rv["F"], F) < 5e-2
     assert abs(ra["Z"] - Z) / Z < 5e-3
-    for r in (ra, rb):
+    assert rv["Z"] == pytest.approx(ra["Z"], rel=1e-13)
+    for r in (ra, rb, rv):
         assert np.abs(r["F"].sum(0)).max() < 1e-10 * np.abs(r["F"]).sum()
 
 
@@ -346,7 +437,7 @@ def test_interp_coincident_points():
 def test_interp_rows_matches_full():
     Y = inputs.mixture_embedding(300, 2, 3, -6, 6, 1.0, seed=8).astype(np.float64)
     o, w, m = oracle.geometry(Y, "fixed", 1, 0.75)
-    for form in (oracle.FORM_A, oracle.FORM_B):
+    for form in (oracle.FORM_A, oracle.FORM_B, oracle.FORM_V):
         r = oracle.interp_rep(Y, o, w, m, 5, form, want_grids=True)
         W = oracle.interp_spread(Y, o, w, m, 5, form)
         np.testing.assert_allclose(W, r["W"].reshape(W.shape), rtol=0, atol=1e-12)
