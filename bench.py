@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_attr_traffic_n1e6_2d.txt")
 ATTR_SOURCES = [os.path.join(ROOT, "paper_1712_09005_amd", "csrc", f)
-                for f in ("k_points.hip", "tsne_dev.h", "launch.h")]
+                for f in ("k_attr.hip", "tsne_dev.h", "launch.h")]
 
 
 def measured_traffic(knobs):
@@ -75,6 +75,8 @@ def main():
                          "0.75 for the other 2-D workloads, 0.5 in 1-D)")
     ap.add_argument("--no-tune", action="store_true",
                     help="2-D step benchmark: skip the autotuner (default knobs, width 0.75)")
+    ap.add_argument("--form", default=None, choices=["A", "B", "V"],
+                    help="charge/kernel form of the repulsion (default: autotuned between A and V)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c2", "serve"],
@@ -119,12 +121,17 @@ def main():
         from paper_1712_09005_amd import autotune
         t0 = time.time()
         if args.width is None and args.p is None:
+            forms = (args.form,) if args.form else ("A", "V")
             ti = autotune.tune_interp(Y, target=1e-3, safety=2.5, max_intervals=max_int,
-                                      device=dev, log=log)
-            args.p, args.width = ti["p"], ti["interval_width"]
+                                      device=dev, log=log, forms=forms)
+            args.form, args.p, args.width = ti["form"], ti["p"], ti["interval_width"]
         elif args.width is None:
-            tw = autotune.tune_width(Y, target=1e-3, safety=2.5, p=args.p, device=dev, log=log)
+            args.form = args.form or "A"
+            tw = autotune.tune_width(Y, target=1e-3, safety=2.5, p=args.p, device=dev, log=log,
+                                     form=args.form)
             args.width = tw["interval_width"]
+    if args.form is None:
+        args.form = "A"
     if args.p is None:
         args.p = 5
     if args.width is None:
@@ -132,13 +139,14 @@ def main():
     if not args.no_tune:
         ta = autotune.tune_attraction(Y, P, p=args.p, device=dev, log=log)
         tsp = autotune.tune_spread(Y, p=args.p, interval_width=args.width, max_intervals=max_int,
-                                   device=dev, log=log)
+                                   device=dev, log=log, form=args.form)
         knobs = dict(lanes_per_row=ta["lanes_per_row"], attr_slabs=ta["attr_slabs"],
                      attr_layout=ta["attr_layout"], points_per_lane=tsp["points_per_lane"])
-        tuned = dict(knobs, p=args.p, interval_width=args.width, seconds=round(time.time() - t0, 1))
+        tuned = dict(knobs, form=args.form, p=args.p, interval_width=args.width,
+                     seconds=round(time.time() - t0, 1))
         log("autotuned: %s" % tuned)
     plan = tsne.Plan(n, s, torch.float32, p=args.p, policy="fixed", interval_width=args.width,
-                     max_intervals=max_int, nnz=P.nnz, device=dev, **knobs)
+                     form=args.form, max_intervals=max_int, nnz=P.nnz, device=dev, **knobs)
     st_ = plan.stream
     with torch.cuda.stream(st_):
         Yt = torch.from_numpy(Y).to(dev)
@@ -273,7 +281,7 @@ def main():
                                "random 90-neighbour P",
                    "n": n, "s": s, "nnz": int(P.nnz), "p": args.p, "interval_width": args.width,
                    "n_int": q["n_int"], "fft_len": q["fft_len"], "max_intervals": max_int,
-                   "form": "A",
+                   "form": args.form,
                    "autotuned": tuned, "kl_divergence": kl_info,
                    "rel_err_rep_numerators_sampled": rel_err},
         "roofline": {"bound": "hbm", "kernel": "attraction step: k_attr (+ k_asum when "

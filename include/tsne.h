@@ -74,12 +74,16 @@ typedef enum { TSNE_F32 = 0, TSNE_F64 = 1 } tsne_dtype;
  * when M changes, under PAPER at nearly every call. */
 typedef enum { TSNE_GRID_PAPER = 0, TSNE_GRID_FIXED = 1 } tsne_grid_policy;
 
-/* Which s+2 kernel sums are formed (Section 2 and the Appendix).
+/* Which kernel sums are formed (Section 2 and the Appendix).
  *   TSNE_FORM_A: K1 with charge 1; K2 with charges 1 and y(d) (the Appendix);
  *   TSNE_FORM_B: K2 with charges 1, y(d) and |y|^2; the K1 sum follows from
  *                K1 = (1 + r^2) K2.
+ *   TSNE_FORM_V: not in the paper; the same interpolation with the single
+ *                charge 1 against K1 and the s odd kernels z_d K2(|z|^2),
+ *                whose sums are the numerators of eq. (frep) themselves:
+ *                one spread grid, s + 1 potentials and no cancellation.
  * Charges are centred at the box centre. */
-typedef enum { TSNE_FORM_A = 0, TSNE_FORM_B = 1 } tsne_form;
+typedef enum { TSNE_FORM_A = 0, TSNE_FORM_B = 1, TSNE_FORM_V = 2 } tsne_form;
 
 typedef struct {
     int64_t n;               /* number of points, >= 2 (< 2^31) */

@@ -136,14 +136,19 @@ def tune_attraction(Y, P, dtype=torch.float32, p=5, device="cuda:0", candidates=
     return out
 
 
+def _fkey(form):
+    return "" if form in ("A", tsne.FORM_A) else "|f%s" % form
+
+
 def tune_spread(Y, dtype=torch.float32, p=5, interval_width=0.75, max_intervals=512,
-                device="cuda:0", candidates=KPTS, reps=15, cache="default", log=None) -> dict:
+                device="cuda:0", candidates=KPTS, reps=15, cache="default", log=None,
+                form="A") -> dict:
     """Fastest points_per_lane for the spreading kernel, timed over the whole
-    repulsion (a1-a8) at this Y.  Returns {"points_per_lane", "seconds", "table"}."""
+    repulsion (box to gather) at this Y.  Returns {"points_per_lane", "seconds", "table"}."""
     cache = default_cache() if cache == "default" else cache
     dev = torch.device(device)
     n, s = Y.shape
-    key = _key("spread", dev, n, 0, s, dtype, p, "|w%g" % interval_width)
+    key = _key("spread", dev, n, 0, s, dtype, p, "|w%g" % interval_width + _fkey(form))
     hit = _load(cache).get(key)
     if hit is not None:
         return hit
@@ -151,7 +156,7 @@ def tune_spread(Y, dtype=torch.float32, p=5, interval_width=0.75, max_intervals=
     table = []
     best = None
     for k in candidates:
-        plan = tsne.Plan(n, s, dtype, p=p, interval_width=interval_width,
+        plan = tsne.Plan(n, s, dtype, p=p, interval_width=interval_width, form=form,
                          max_intervals=max_intervals, points_per_lane=k, device=dev)
         with torch.cuda.stream(plan.stream):
             F = torch.empty_like(Yt)
@@ -172,7 +177,7 @@ def tune_spread(Y, dtype=torch.float32, p=5, interval_width=0.75, max_intervals=
 
 
 def estimate_error(Y, interval_width, dtype=torch.float32, p=5, device="cuda:0",
-                   max_intervals=4096) -> float:
+                   max_intervals=4096, form="A") -> float:
     """Estimated relative L2 error of F_rep at ``interval_width``: the
     difference to the same computation at half the width (in FP64, so that
     FP32 rounding does not mask the interpolation error)."""
@@ -186,7 +191,7 @@ def estimate_error(Y, interval_width, dtype=torch.float32, p=5, device="cuda:0",
         if need > max_intervals:
             raise ValueError("box of side %.3g needs %d intervals at width %g" % (L, need, w))
         plan = tsne.Plan(n, s, torch.float64, p=p, interval_width=w, max_intervals=need,
-                         device=dev)
+                         form=form, device=dev)
         F, _ = plan.repulsive(Yt)
         torch.cuda.synchronize()
         if plan.query()["status"] != 0:
@@ -198,7 +203,7 @@ def estimate_error(Y, interval_width, dtype=torch.float32, p=5, device="cuda:0",
 
 
 def tune_width(Y, target=1e-3, safety=2.0, p=5, device="cuda:0", widths=WIDTHS,
-               cache="default", log=None) -> dict:
+               cache="default", log=None, form="A") -> dict:
     """Largest width on the ladder with safety * estimated error <= target.
     Returns {"interval_width", "estimate", "table"}."""
     cache = default_cache() if cache == "default" else cache
@@ -206,7 +211,7 @@ def tune_width(Y, target=1e-3, safety=2.0, p=5, device="cuda:0", widths=WIDTHS,
     n, s = Y.shape
     L = float(np.max(Y.max(0) - Y.min(0)))
     key = _key("width", dev, n, 0, s, torch.float64, p,
-               "|L%d|t%g|k%g" % (_bucket(int(L)), target, safety))
+               "|L%d|t%g|k%g" % (_bucket(int(L)), target, safety) + _fkey(form))
     hit = _load(cache).get(key)
     if hit is not None:
         return hit
@@ -214,7 +219,7 @@ def tune_width(Y, target=1e-3, safety=2.0, p=5, device="cuda:0", widths=WIDTHS,
     chosen = None
     for w in sorted(widths, reverse=True):
         try:
-            e = estimate_error(Y, w, p=p, device=dev)
+            e = estimate_error(Y, w, p=p, device=dev, form=form)
         except (ValueError, tsne.TsneError) as ex:   # the half-width grid no longer fits
             if log:
                 log("  width %.3g: not evaluated (%s)" % (w, ex))
@@ -233,33 +238,35 @@ def tune_width(Y, target=1e-3, safety=2.0, p=5, device="cuda:0", widths=WIDTHS,
 
 
 def tune_interp(Y, target=1e-3, safety=2.5, ps=(4, 5, 6), max_intervals=512, device="cuda:0",
-                reps=10, cache="default", log=None) -> dict:
-    """Nodes per interval p and interval width together: for each p the
-    widest width meeting the accuracy target (tune_width), then the pair
-    whose FP32 repulsion at this Y is fastest.  Returns {"p",
-    "interval_width", "estimate", "seconds", "table"}."""
+                reps=10, cache="default", log=None, forms=("A",)) -> dict:
+    """Form, nodes per interval p and interval width together: for each
+    (form, p) the widest width meeting the accuracy target (tune_width), then
+    the choice whose FP32 repulsion at this Y is fastest.  Returns {"form",
+    "p", "interval_width", "estimate", "seconds", "table"}."""
     cache = default_cache() if cache == "default" else cache
     dev = torch.device(device)
     n, s = Y.shape
     L = float(np.max(Y.max(0) - Y.min(0)))
     key = _key("interp", dev, n, 0, s, torch.float32, 0,
-               "|L%d|t%g|k%g|p%s" % (_bucket(int(L)), target, safety, "-".join(map(str, ps))))
+               "|L%d|t%g|k%g|p%s" % (_bucket(int(L)), target, safety, "-".join(map(str, ps)))
+               + ("" if tuple(forms) == ("A",) else "|f" + "".join(forms)))
     hit = _load(cache).get(key)
     if hit is not None:
         return hit
     Yt = torch.as_tensor(np.ascontiguousarray(Y)).to(dev, torch.float32)
     table = []
     best = None
-    for p in ps:
+    for form, p in [(f, p) for f in forms for p in ps]:
         try:
-            tw = tune_width(Y, target=target, safety=safety, p=p, device=dev, cache=cache, log=log)
+            tw = tune_width(Y, target=target, safety=safety, p=p, device=dev, cache=cache, log=log,
+                            form=form)
         except RuntimeError:
             continue
         w = tw["interval_width"]
         if L / w + 1 > max_intervals:
             continue
         plan = tsne.Plan(n, s, torch.float32, p=p, interval_width=w, max_intervals=max_intervals,
-                         device=dev)
+                         form=form, device=dev)
         with torch.cuda.stream(plan.stream):
             F = torch.empty_like(Yt)
             Z = torch.empty(1, dtype=torch.float64, device=dev)
@@ -267,16 +274,17 @@ def tune_interp(Y, target=1e-3, safety=2.5, ps=(4, 5, 6), max_intervals=512, dev
         t = time_launches(lambda: plan.repulsive(Yt, F, Z), plan.stream, reps)
         if plan.query()["status"] != 0:
             continue
-        table.append([p, w, tw["estimate"], t])
+        table.append([form, p, w, tw["estimate"], t])
         if log:
-            log("  p=%d width %.3g (estimate %.2e): repulsion %.1f us" % (p, w, tw["estimate"], t * 1e6))
-        if best is None or t < best[3]:
-            best = (p, w, tw["estimate"], t)
+            log("  form %s p=%d width %.3g (estimate %.2e): repulsion %.1f us"
+                % (form, p, w, tw["estimate"], t * 1e6))
+        if best is None or t < best[4]:
+            best = (form, p, w, tw["estimate"], t)
         del plan
     if best is None:
-        raise RuntimeError("no (p, width) meets the target %g" % target)
-    out = {"p": best[0], "interval_width": best[1], "estimate": best[2], "seconds": best[3],
-           "table": table}
+        raise RuntimeError("no (form, p, width) meets the target %g" % target)
+    out = {"form": best[0], "p": best[1], "interval_width": best[2], "estimate": best[3],
+           "seconds": best[4], "table": table}
     _store(cache, key, out)
     return out
 

@@ -185,14 +185,22 @@ __device__ __forceinline__ bool occupied(const int* __restrict__ cs, int c)
     return cs[c + 1] > cs[c];
 }
 
-// Charge index and kernel (0: K1, 1: K2) of potential pot.
+// Charge index and kernel spectrum of potential pot.  Forms A and B: kern 0
+// is K1, 1 is K2 (real spectra).  Form V (one charge): kern 0 is K1, 1 + d
+// the odd kernel z_d K2 along dimension d, whose spectrum is -i times a real
+// table (odd along d, even along the other dimension).
 template <int S, int FORM>
 __device__ __forceinline__ void pot_of(int pot, int& ch, int& kern)
 {
+    if (FORM == 2) { ch = 0; kern = pot; return; }
     if (pot == 0) { ch = (FORM == 0) ? 0 : S + 1; kern = (FORM == 0) ? 0 : 1; }
     else if (pot == 1) { ch = 0; kern = 1; }
     else { ch = pot - 1; kern = 1; }
 }
+
+template <int S, int FORM> struct Pots {
+    static constexpr int NP = (FORM == 2) ? S + 1 : S + 2;
+};
 
 // ---------------------------------------------------------------- 2-D passes
 
@@ -256,7 +264,8 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
         // transposing each run of 8 x G virtual blocks puts the G blocks that
         // share one tile (and so every cache line of it) on the same XCD,
         // one after another.  A bijection on whole runs; the tail is as is.
-        const int vtotal = (S + 2) * I.ntiles * (tw_ / I.col_group);
+        constexpr int NP = Pots<S, FORM>::NP;
+        const int vtotal = NP * I.ntiles * (tw_ / I.col_group);
         const int run = 8 * G;
         int L = lb;
         if (lb < (vtotal / run) * run) {
@@ -264,7 +273,7 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
             L = lb - r + (r & 7) * G + (r >> 3);
         }
         const int pot = L / ncg, cg = L - pot * ncg;
-        if (pot < S + 2 && cg * Gc < half) {
+        if (pot < NP && cg * Gc < half) {
         int ch, kern;
         pot_of<S, FORM>(pot, ch, kern);
         const cplx<T>* X = static_cast<const cplx<T>*>(I.X) + (int64_t)ch * I.ntiles * n_cap * tw_;
@@ -292,11 +301,23 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
             const int k0 = k00 + g;
             const T* sp = static_cast<const T*>(I.spec) + (int64_t)kern * half * half + (int64_t)k0 * half;
             cplx<T>* col = buf + g * PM;
-            for (int k1 = jt; k1 < M; k1 += tpc) {
-                const T sv = (k0 < half) ? sp[k1 <= M - k1 ? k1 : M - k1] : (T)0;
-                const int li = lds_pad(k1);
-                const cplx<T> v = col[li];
-                col[li] = {v.x * sv, -v.y * sv};
+            if (FORM == 2 && kern > 0) {
+                // times -i b, b odd in k1 for the kernel odd along dimension 1
+                for (int k1 = jt; k1 < M; k1 += tpc) {
+                    const bool up = k1 > M - k1;
+                    T sv = (k0 < half) ? sp[up ? M - k1 : k1] : (T)0;
+                    if (kern == 2 && up) sv = -sv;
+                    const int li = lds_pad(k1);
+                    const cplx<T> v = col[li];
+                    col[li] = {v.y * sv, v.x * sv};
+                }
+            } else {
+                for (int k1 = jt; k1 < M; k1 += tpc) {
+                    const T sv = (k0 < half) ? sp[k1 <= M - k1 ? k1 : M - k1] : (T)0;
+                    const int li = lds_pad(k1);
+                    const cplx<T> v = col[li];
+                    col[li] = {v.x * sv, -v.y * sv};
+                }
             }
         }
         __syncthreads();
@@ -312,10 +333,9 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
     VB_END
 }
 
-template <typename T, int S>
+template <typename T, int S, int NP>
 __global__ __launch_bounds__(1024) void k_fft_irows(LaunchMap map)
 {
-    constexpr int NP = S + 2;
     extern __shared__ __align__(16) char smem[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
     VB_BEGIN(map, K_FFT_IROWS)
@@ -380,9 +400,15 @@ __global__ __launch_bounds__(1024) void k_fft_1d(LaunchMap map)
         block_fft<T>(buf, 1, I, G);
         const T* sp = static_cast<const T*>(I.spec) + (int64_t)kern * half;
         for (int k = threadIdx.x; k < M; k += blockDim.x) {
-            const T sv = sp[k <= M - k ? k : M - k];
+            const bool up = k > M - k;
             const cplx<T> v = buf[lds_pad(k)];
-            buf[lds_pad(k)] = {v.x * sv, -v.y * sv};
+            if (FORM == 2 && kern > 0) {             // times -i b, b odd in k
+                const T sv = up ? -sp[M - k] : sp[k];
+                buf[lds_pad(k)] = {v.y * sv, v.x * sv};
+            } else {
+                const T sv = sp[up ? M - k : k];
+                buf[lds_pad(k)] = {v.x * sv, -v.y * sv};
+            }
         }
         __syncthreads();
         block_fft<T>(buf, 1, I, G);
@@ -401,6 +427,15 @@ __device__ __forceinline__ double kern_val(int kern, double r2)
     return kern == 0 ? a : a * a;
 }
 
+// Table kern of the lag grid: K1 (0); K2 (1), or for form V the odd kernel
+// z_0 K2 at the non-negative lag z_0 = h j0 (its sign is restored by the
+// sine transform).
+__device__ __forceinline__ double ktab_val(int form, int kern, double h, int j0, double r2)
+{
+    const double v = kern_val(kern, r2);
+    return (form == 2 && kern == 1) ? h * (double)j0 * v : v;
+}
+
 // The tables are rebuilt when the box kernel found a new node spacing or a
 // new circulant length (every call under the paper policy; under a fixed
 // width only when the ladder length changes).
@@ -409,8 +444,9 @@ __device__ __forceinline__ bool spec_needed(const Inst& I)
     return okay(I) && I.geom->spec_dirty != 0;
 }
 
-// Twiddles exp(-2 pi i k / M) (element type), cos(2 pi k / M) (double) and
-// the kernel values K(h^2 (j1^2 + j0^2)) on the lag grid j <= M/2 (double).
+// Twiddles exp(-2 pi i k / M) (element type), cos and sin(2 pi k / M)
+// (double) and the kernel values K(h^2 (j1^2 + j0^2)) on the lag grid
+// j <= M/2 (double).
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_spec0(LaunchMap map)
 {
@@ -423,6 +459,7 @@ __global__ __launch_bounds__(256) void k_spec0(LaunchMap map)
             double sv, cv;
             sincospi(2.0 * (double)idx / (double)M, &sv, &cv);
             I.costab[idx] = cv;
+            I.costab[M + idx] = sv;
         }
         if (idx < M - 1) {
             // stage tables: stage s holds w^(r k M/(Ns R)) at [k (R-1) + r - 1]
@@ -447,16 +484,19 @@ __global__ __launch_bounds__(256) void k_spec0(LaunchMap map)
                 double sv, cv;
                 sincospi(2.0 * (double)(((int64_t)j * k) % M) / (double)M, &sv, &cv);
                 I.ccos[idx] = wt * cv;
+                // form V: the sine matrix 2 sin(2 pi j k / M), zero at j = 0, M/2
+                if (I.form == 2)
+                    I.ccos[(int64_t)half * half + idx] = (j == 0 || 2 * j == M) ? 0.0 : 2.0 * sv;
             }
             if (idx < (int64_t)2 * half * half) {
                 const int kern = (int)(idx / ((int64_t)half * half));
                 const int rem = (int)(idx - (int64_t)kern * half * half);
                 const int j1 = rem / half, j0 = rem - j1 * half;
-                I.ktab[idx] = kern_val(kern, h2 * ((double)j1 * j1 + (double)j0 * j0));
+                I.ktab[idx] = ktab_val(I.form, kern, G.h, j0, h2 * ((double)j1 * j1 + (double)j0 * j0));
             }
         } else if (idx < 2 * half) {
             const int kern = (int)(idx / half), j = (int)(idx - (int64_t)kern * half);
-            I.ktab[idx] = kern_val(kern, h2 * (double)j * j);
+            I.ktab[idx] = ktab_val(I.form, kern, G.h, j, h2 * (double)j * j);
         }
     }
     VB_END
@@ -469,6 +509,14 @@ __device__ __forceinline__ double cos_w(const double* ct, int M, int j, int k)
 {
     const double wt = (j == 0 || 2 * j == M) ? 1.0 : 2.0;
     return wt * ct[(int)(((int64_t)j * k) % M)];
+}
+
+// Sine counterpart for an odd sequence s (s[M - j] = -s[j]): the DFT is
+// -i sum_j S[j][k] s[j] with S[j][k] = 2 sin(2 pi j k / M), zero at j = 0, M/2.
+__device__ __forceinline__ double sin_w(const double* st, int M, int j, int k)
+{
+    if (j == 0 || 2 * j == M) return 0.0;
+    return 2.0 * st[(int)(((int64_t)j * k) % M)];
 }
 
 // One 64 x 64 tile of out = op(A) B for h x h row-major double matrices
@@ -523,7 +571,8 @@ __device__ __forceinline__ void gemm_tile(const double* __restrict__ A, const do
 
 // First pass.  s = 2: A[kern] = K[kern] C (the row transform of the even
 // kernel grid), by tiled GEMM; s = 1: the whole spectrum
-// K^[kern][k] = sum_j C[j][k] K[kern][j] / M.
+// K^[kern][k] = sum_j C[j][k] K[kern][j] / M.  Form V's odd table (kern 1)
+// takes the sine matrix in place of C.
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_spec1(LaunchMap map)
 {
@@ -538,7 +587,8 @@ __global__ __launch_bounds__(256) void k_spec1(LaunchMap map)
             const int tm = rem / nt, tn = rem - tm * nt;
             if (kern < 2) {
                 double* out = I.spec_tmp + (int64_t)kern * half * half;
-                gemm_tile<false>(I.ktab + (int64_t)kern * half * half, I.ccos, half, tm, tn, As, Bs,
+                const double* cm = I.ccos + ((I.form == 2 && kern == 1) ? (int64_t)half * half : 0);
+                gemm_tile<false>(I.ktab + (int64_t)kern * half * half, cm, half, tm, tn, As, Bs,
                                  [&](int m, int n, double v) { out[(int64_t)m * half + n] = v; });
             }
         } else {
@@ -547,7 +597,10 @@ __global__ __launch_bounds__(256) void k_spec1(LaunchMap map)
                 const int kern = idx / half, k = idx - kern * half;
                 const double* kt = I.ktab + (int64_t)kern * half;
                 double acc = 0.0;
-                for (int j = 0; j < half; ++j) acc += cos_w(I.costab, M, j, k) * kt[j];
+                if (I.form == 2 && kern == 1)
+                    for (int j = 0; j < half; ++j) acc += sin_w(I.costab + M, M, j, k) * kt[j];
+                else
+                    for (int j = 0; j < half; ++j) acc += cos_w(I.costab, M, j, k) * kt[j];
                 static_cast<T*>(I.spec)[idx] = (T)(acc / M);
             }
         }
@@ -556,7 +609,9 @@ __global__ __launch_bounds__(256) void k_spec1(LaunchMap map)
 }
 
 // Second pass (s = 2): K^[kern] = A[kern]^T C / M^2, stored [kern][k0][k1],
-// k0, k1 <= M/2.
+// k0, k1 <= M/2.  Form V also stores the transpose of the odd table as
+// table 2: the kernel odd along dimension 1 is the same function with the
+// axes swapped.
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_spec2(LaunchMap map)
 {
@@ -570,9 +625,13 @@ __global__ __launch_bounds__(256) void k_spec2(LaunchMap map)
         const int tm = rem / nt, tn = rem - tm * nt;
         if (kern < 2) {
             T* out = static_cast<T*>(I.spec) + (int64_t)kern * half * half;
+            T* outT = (I.form == 2 && kern == 1) ? out + (int64_t)half * half : nullptr;
             const double sc = 1.0 / ((double)M * (double)M);
             gemm_tile<true>(I.spec_tmp + (int64_t)kern * half * half, I.ccos, half, tm, tn, As, Bs,
-                            [&](int m, int n, double v) { out[(int64_t)m * half + n] = (T)(v * sc); });
+                            [&](int m, int n, double v) {
+                                out[(int64_t)m * half + n] = (T)(v * sc);
+                                if (outT) outT[(int64_t)n * half + m] = (T)(v * sc);
+                            });
         }
     }
     VB_END
@@ -608,8 +667,9 @@ static hipError_t fft_go(int kind, const LaunchMap& map, const Launch& l, hipStr
         break;
     case K_FFT_IROWS:
         if (S == 2) {
-            allow_lds(k_fft_irows<T, S>, l.lds);
-            hipLaunchKernelGGL((k_fft_irows<T, S>), g, b, l.lds, st, map);
+            constexpr int NP = Pots<S, FORM>::NP;
+            allow_lds(k_fft_irows<T, S, NP>, l.lds);
+            hipLaunchKernelGGL((k_fft_irows<T, S, NP>), g, b, l.lds, st, map);
         }
         break;
     case K_FFT_1D:
@@ -629,7 +689,12 @@ static hipError_t fft_go(int kind, const LaunchMap& map, const Launch& l, hipStr
 template <typename T, int S, int P>
 static hipError_t fft_form(int kind, const Cfg& c, const LaunchMap& m, const Launch& l, hipStream_t st)
 {
-    return c.form == 0 ? fft_go<T, S, P, 0>(kind, m, l, st) : fft_go<T, S, P, 1>(kind, m, l, st);
+    switch (c.form) {
+    case 0: return fft_go<T, S, P, 0>(kind, m, l, st);
+    case 1: return fft_go<T, S, P, 1>(kind, m, l, st);
+    case 2: return fft_go<T, S, P, 2>(kind, m, l, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T, int S>

@@ -1,8 +1,8 @@
 // Point-side kernels of one t-SNE gradient iteration on gfx950:
 //   box geometry, binning by cell (counting sort), charge spreading (Step 1 of
 //   Algorithm 1), interpolation back to the points and the Z reduction
-//   (Step 3 and the Appendix assembly), sparse attraction (Section 3) and the
-//   descent update.
+//   (Step 3 and the Appendix assembly) and the descent update.  The sparse
+//   attraction and the divergence are in k_attr.hip.
 //
 // Every kernel walks the virtual blocks of its kind over all instances of the
 // launch (VB_BEGIN/VB_END), so one launch serves a single plan or a batch.
@@ -67,9 +67,12 @@ __device__ __forceinline__ void lagrange(T t, T (&L)[P])
     }
 }
 
+// Charges and potentials per form: A {1, y'(d)} -> K1*1, K2*1, K2*y'(d);
+// B adds |y'|^2 and takes K2*|y'|^2 in place of K1*1; V (vector kernels)
+// has the one charge 1 -> K1*1 and (z_d K2)*1 for each dimension d.
 template <int S, int FORM> struct Shape {
-    static constexpr int NC = (FORM == 0) ? S + 1 : S + 2;   // charges
-    static constexpr int NP = S + 2;                          // potentials
+    static constexpr int NC = (FORM == 0) ? S + 1 : (FORM == 1) ? S + 2 : 1;
+    static constexpr int NP = (FORM == 2) ? S + 1 : S + 2;
 };
 
 // ---------------------------------------------------------------- per-call arguments
@@ -104,7 +107,7 @@ hipError_t launch_set_args(Inst* inst, const CallArgs& a, hipStream_t st)
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- a1: box geometry
+// ---------------------------------------------------------------- box geometry
 
 // Per-block partial min / max / sum of the coordinates (double) and a
 // non-finite flag.  The geometry kernel reduces them.
@@ -317,7 +320,7 @@ __global__ __launch_bounds__(256) void k_geom(LaunchMap map)
     VB_END
 }
 
-// ---------------------------------------------------------------- a2: binning
+// ---------------------------------------------------------------- binning
 
 // Cell key of each point and its rank among the points of its cell (the
 // "for each interval" loops of Algorithm 1 become a counting sort by cell).
@@ -515,7 +518,7 @@ __global__ __launch_bounds__(256) void k_scatter(LaunchMap map)
     VB_END
 }
 
-// ---------------------------------------------------------------- a3: spreading (Step 1)
+// ---------------------------------------------------------------- spreading (Step 1)
 
 // One thread per item (up to kpts consecutive sorted points of one cell):
 // w_{m,c} += L_m(y_i) q_c(i) accumulated in registers, then a segmented
@@ -559,12 +562,12 @@ __global__ __launch_bounds__(256) void k_spread(LaunchMap map)
                 const double qx = ((double)yx - c0) * qs;
                 double qy = 0.0;
                 q[0] = (T)1;
-                q[1] = (T)qx;
+                if (NC > 1) q[1 % NC] = (T)qx;
                 if (S == 2) {
                     const T yy = sY[(int64_t)pos * S + 1];
                     locate<T>(yy, o1, w, n_int, ty);
                     qy = ((double)yy - c1) * qs;
-                    q[2] = (T)qy;
+                    if (NC > 2) q[2 % NC] = (T)qy;
                 }
                 if (FORM == 1) q[NC - 1] = (T)(qx * qx + qy * qy);
                 T Lx[P];
@@ -740,16 +743,17 @@ __global__ __launch_bounds__(256) void k_spread_fix(LaunchMap map)
     VB_END
 }
 
-// ---------------------------------------------------------------- a8: gather (Step 3) + Z
+// ---------------------------------------------------------------- gather (Step 3) + Z
 
 // phi_k(y_i) = sum_m L_m(y_i) V_k[node m of i's cell], then the Appendix
-// assembly: h1 (the K1 sum), numerators y'(d) h4 - h_{1+d}.  One thread per
+// assembly: h1 (the K1 sum), numerators y'(d) h4 - h_{1+d} (form V: the
+// numerators are the odd-kernel potentials themselves).  One thread per
 // sorted position (neighbouring threads share their cell's nodes); results go
 // to the point's own index.  Z = sum_i h1_i - N, reduced in double.
 template <typename T, int S, int P, int FORM>
 __global__ __launch_bounds__(256) void k_gather(LaunchMap map)
 {
-    constexpr int NP = S + 2;
+    constexpr int NP = Shape<S, FORM>::NP;
     __shared__ double sh[8];
     VB_BEGIN(map, K_GATHER)
     if (live(I)) {
@@ -793,7 +797,7 @@ __global__ __launch_bounds__(256) void k_gather(LaunchMap map)
                 phi[k] = a;
             }
             // potentials: phi[1] = K2*1, phi[2+d] = K2*(y'(d) qs); phi[0] = K1*1 (A)
-            // or K2*(|y'|^2 qs^2) (B)
+            // or K2*(|y'|^2 qs^2) (B); form V: phi[0] = K1*1, phi[1+d] = (z_d K2)*1
             // assembly in double: the numerator y'(d) h4 - h_{1+d} cancels
             double yc[2];
             double r2c = 0.0;
@@ -804,12 +808,12 @@ __global__ __launch_bounds__(256) void k_gather(LaunchMap map)
             }
             const double inv_qs = 1.0 / qs;
             double h1;
-            if (FORM == 0) {
+            if (FORM == 0 || FORM == 2) {
                 h1 = (double)phi[0];
             } else {
                 double dot = 0.0;
 #pragma unroll
-                for (int d = 0; d < S; ++d) dot += yc[d] * (double)phi[2 + d];
+                for (int d = 0; d < S; ++d) dot += yc[d] * (double)phi[(2 + d) % NP];
                 h1 = (1.0 + r2c) * (double)phi[1] - 2.0 * dot * inv_qs +
                      (double)phi[0] * inv_qs * inv_qs;
             }
@@ -817,7 +821,8 @@ __global__ __launch_bounds__(256) void k_gather(LaunchMap map)
             T* R = static_cast<T*>(I.R);
 #pragma unroll
             for (int d = 0; d < S; ++d)
-                R[(int64_t)i * S + d] = (T)(yc[d] * (double)phi[1] - (double)phi[2 + d] * inv_qs);
+                R[(int64_t)i * S + d] = (FORM == 2) ? phi[1 + d]
+                                                    : (T)(yc[d] * (double)phi[1] - (double)phi[(2 + d) % NP] * inv_qs);
             h1d = h1;
         }
         const double bs = block_sum_d(h1d, sh);
@@ -862,305 +867,7 @@ __global__ __launch_bounds__(256) void k_norm(LaunchMap map)
     VB_END
 }
 
-// ---------------------------------------------------------------- a9: attraction
-
-template <typename T, int S> struct Vec;
-template <> struct Vec<float, 1> { typedef float t; };
-template <> struct Vec<float, 2> { typedef float2 t; };
-template <> struct Vec<double, 1> { typedef double t; };
-template <> struct Vec<double, 2> { typedef double2 t; };
-
-template <typename V> __device__ __forceinline__ double cx(const V& v) { return (double)v.x; }
-template <> __device__ __forceinline__ double cx<float>(const float& v) { return (double)v; }
-template <> __device__ __forceinline__ double cx<double>(const double& v) { return v; }
-
-// 1 / x: the hardware reciprocal (1 ulp) for float, IEEE division for double.
-__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
-
-// F_attr,i = sum_j p_ij (y_i - y_j) / (1 + |y_i - y_j|^2) over row i of the CSR
-// P (Section 3).  LPR lanes per row; each lane takes U non-zeros per round and
-// issues all their loads (column, value, then the neighbours' positions as one
-// vector load each) before using them, so LPR * U should cover a typical row.
-// Each lane sums its few terms in the element type; the row's lanes are
-// reduced in double.  Optionally the columns are split into slabs (virtual
-// blocks run slab-major, each row's slab range from the split table) and each
-// slab writes a partial force.
-template <typename T, int S, int LPR, int U, bool GATED>
-__global__ __launch_bounds__(256) void k_attr(LaunchMap map)
-{
-    constexpr int RPB = 256 / LPR;
-    typedef typename Vec<T, S>::t V;
-    VB_BEGIN_IF(map, GATED ? K_ATTR : K_ATTR_ALL, (!GATED || live(I)))
-    {
-        const int64_t n = I.n;
-        const int nrb = (int)((n + RPB - 1) / RPB);
-        // XCD-aware slab assignment: workgroups go to the 8 XCDs round-robin
-        // (block b -> XCD b mod 8, and launches keep virtual block = b mod 8),
-        // so virtual block v works on slab (v mod 8) / (8 / slabs): each XCD's
-        // L2 then only holds the positions of its own slab.
-        int slab = 0, rb = lb;
-        if (I.slabs > 1) {
-            const int per = 8 / I.slabs;
-            const int x = lb & 7, q = lb >> 3;
-            slab = x / per;
-            rb = q * per + (x - slab * per);
-        }
-        const int i = rb * RPB + (int)threadIdx.x / LPR;
-        const int sub = (int)threadIdx.x % LPR;
-        T a0 = (T)0, a1 = (T)0;
-        const V* Y = static_cast<const V*>(I.Yin);
-        if (i < n && rb < nrb) {
-            const T* val = static_cast<const T*>(I.val);
-            const int32_t* col = I.col;
-            const V yi = Y[i];
-            T yi0, yi1 = (T)0;
-            if constexpr (S == 2) { yi0 = yi.x; yi1 = yi.y; } else { yi0 = yi; }
-            const int64_t b = (slab == 0) ? I.row_ptr[i] : (int64_t)I.split[(int64_t)(slab - 1) * n + i];
-            const int64_t e = (slab == I.slabs - 1) ? I.row_ptr[i + 1]
-                                                     : (int64_t)I.split[(int64_t)slab * n + i];
-            for (int64_t k0 = b + sub; k0 < e; k0 += (int64_t)LPR * U) {
-                int jj[U];
-                T pp[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int64_t k = k0 + (int64_t)u * LPR;
-                    const bool ok = k < e;
-                    jj[u] = ok ? col[k] : i;
-                    pp[u] = ok ? val[k] : (T)0;
-                }
-                V yj[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) yj[u] = Y[jj[u]];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    T d0, d1 = (T)0;
-                    if constexpr (S == 2) { d0 = yi0 - yj[u].x; d1 = yi1 - yj[u].y; }
-                    else { d0 = yi0 - yj[u]; }
-                    const T wgt = pp[u] * recip((T)1 + d0 * d0 + d1 * d1);
-                    a0 += wgt * d0;
-                    if (S == 2) a1 += wgt * d1;
-                }
-            }
-        }
-        double f0 = (double)a0, f1 = (double)a1;
-#pragma unroll
-        for (int o = LPR / 2; o > 0; o >>= 1) {
-            f0 += __shfl_xor(f0, o, 64);
-            if (S == 2) f1 += __shfl_xor(f1, o, 64);
-        }
-        if (i < n && rb < nrb && sub == 0) {
-            T* F = (I.slabs == 1) ? static_cast<T*>(I.Fattr)
-                                  : static_cast<T*>(I.Fap) + (int64_t)slab * n * S;
-            F[(int64_t)i * S] = (T)f0;
-            if (S == 2) F[(int64_t)i * S + 1] = (T)f1;
-        }
-    }
-    VB_END
-}
-
-// Attraction over tiles of P: edges re-bucketed (at bind time) by row block of
-// tile_bi rows and column block of tile_bj columns, rows increasing within a
-// tile.  One 1024-thread workgroup per row block keeps that block's positions
-// and force sums in LDS and sweeps the column blocks in order.  The sweep is
-// software-pipelined two steps deep: the positions of column block J+2 and
-// the first edges of tile J+2 are requested while tile J is processed from LDS,
-// and block J+1 (requested a step earlier) is stored to the other half of a
-// double-buffered LDS area at the end of the step; each step costs one
-// barrier.  Every neighbour position comes from LDS instead of a random global
-// gather; per-row sums use LDS atomics in the element type.
-template <typename T, int S>
-struct TileEdges {
-    static constexpr int UE = 4;   // edges per thread carried between steps
-    uint32_t k[UE];
-    T v[UE];
-};
-
-template <typename T, int S, bool GATED>
-__global__ __launch_bounds__(1024) void k_attr_tile(LaunchMap map)
-{
-    typedef typename Vec<T, S>::t V;
-    constexpr int NT = 1024;       // threads (the launch uses exactly this)
-    constexpr int UE = TileEdges<T, S>::UE;
-    constexpr int PJ = 4;          // positions per thread per column block (tile_bj <= 4096)
-    constexpr uint32_t kNone = 0xffffffffu;
-    extern __shared__ __align__(16) char smem[];
-    VB_BEGIN_IF(map, GATED ? K_ATTR_T : K_ATTR_T_ALL, (!GATED || live(I)))
-    {
-        const int BI = I.tile_bi, BJ = I.tile_bj, nj = I.tile_nj;
-        const int64_t n = I.n;
-        const int tid = (int)threadIdx.x;
-        V* yI = reinterpret_cast<V*>(smem);
-        T* f = reinterpret_cast<T*>(yI + BI);
-        V* yJbuf = reinterpret_cast<V*>(f + (int64_t)BI * S);
-        const V* Y = static_cast<const V*>(I.Yin);
-        V zero;
-        if constexpr (S == 2) zero = V{(T)0, (T)0}; else zero = (T)0;
-        const int i0 = lb * BI;
-        const int rows = (int)min((int64_t)BI, n - i0);
-        for (int r = tid; r < BI; r += NT) {
-            yI[r] = (r < rows) ? Y[i0 + r] : zero;
-#pragma unroll
-            for (int d = 0; d < S; ++d) f[r * S + d] = (T)0;
-        }
-        const int64_t* to = I.toff + (int64_t)lb * nj;
-        const uint32_t* ep = I.epack;
-        const T* ev = static_cast<const T*>(I.eval);
-        auto load_pos = [&](int J, V (&pos)[PJ]) {
-            const int64_t j0 = (int64_t)J * BJ;
-#pragma unroll
-            for (int q = 0; q < PJ; ++q) {
-                const int c = tid + q * NT;
-                pos[q] = (c < BJ && j0 + c < n) ? Y[j0 + c] : zero;
-            }
-        };
-        auto store_pos = [&](int J, const V (&pos)[PJ]) {
-            V* b = yJbuf + (J & 1) * BJ;
-#pragma unroll
-            for (int q = 0; q < PJ; ++q) {
-                const int c = tid + q * NT;
-                if (c < BJ) b[c] = pos[q];
-            }
-        };
-        auto load_edges = [&](int J, TileEdges<T, S>& e) {
-            const int64_t e0 = to[J], e1 = to[J + 1];
-#pragma unroll
-            for (int u = 0; u < UE; ++u) {
-                const int64_t k = e0 + tid + (int64_t)u * NT;
-                e.k[u] = (k < e1) ? ep[k] : kNone;
-                e.v[u] = (k < e1) ? ev[k] : (T)0;
-            }
-        };
-        auto edge = [&](uint32_t pk, T pv, const V* yJ) {
-            const int il = (int)(pk >> 16), jl = (int)(pk & 0xffffu);
-            const V a = yI[il], b = yJ[jl];
-            T d0, d1 = (T)0;
-            if constexpr (S == 2) { d0 = a.x - b.x; d1 = a.y - b.y; }
-            else { d0 = a - b; }
-            const T wgt = pv * recip((T)1 + d0 * d0 + d1 * d1);
-            atomicAdd(&f[il * S], wgt * d0);
-            if (S == 2) atomicAdd(&f[il * S + 1], wgt * d1);
-        };
-        V posA[PJ], posB[PJ];
-        TileEdges<T, S> eA, eB, cur;
-        // prologue: block 0 staged; block 1 and the edges of tiles 0 and 1 requested
-        load_pos(0, posA);
-        store_pos(0, posA);
-        if (nj > 1) load_pos(1, posA);
-        load_edges(0, eA);
-        if (nj > 1) load_edges(1, eB);
-        for (int J = 0; J < nj; ++J) {
-            __syncthreads();   // block J staged, yI / f ready, the other buffer free
-            if (J + 2 < nj) load_pos(J + 2, posB);
-            cur = eA;
-            eA = eB;
-            if (J + 2 < nj) load_edges(J + 2, eB);
-            const V* yJ = yJbuf + (J & 1) * BJ;
-#pragma unroll
-            for (int u = 0; u < UE; ++u)
-                if (cur.k[u] != kNone) edge(cur.k[u], cur.v[u], yJ);
-            // a tile with more than NT * UE edges: the rest directly
-            const int64_t e1 = to[J + 1];
-            for (int64_t k = to[J] + (int64_t)NT * UE + tid; k < e1; k += NT) edge(ep[k], ev[k], yJ);
-            if (J + 1 < nj) store_pos(J + 1, posA);
-#pragma unroll
-            for (int q = 0; q < PJ; ++q) posA[q] = posB[q];
-        }
-        __syncthreads();
-        T* F = static_cast<T*>(I.Fattr);
-        for (int r = tid; r < rows * S; r += NT) F[(int64_t)i0 * S + r] = f[r];
-        __syncthreads();
-    }
-    VB_END
-}
-
-// Attraction entry point with slabs: F_attr = sum of the slab partials.
-template <typename T, int S>
-__global__ __launch_bounds__(256) void k_asum(LaunchMap map)
-{
-    VB_BEGIN(map, K_ASUM)
-    {
-        const int64_t k = (int64_t)lb * 256 + threadIdx.x;
-        const int64_t ns = I.n * S;
-        if (k < ns) {
-            const T* Fp = static_cast<const T*>(I.Fap);
-            double a = 0.0;
-            for (int sl = 0; sl < I.slabs; ++sl) a += (double)Fp[(int64_t)sl * ns + k];
-            static_cast<T*>(I.Fattr)[k] = (T)a;
-        }
-    }
-    VB_END
-}
-
-// ---------------------------------------------------------------- KL divergence
-
-// Kullback-Leibler divergence of Section 1.1 from one pass over P:
-// C = sum p_ij log(p_ij / q_ij) with q_ij = K1_ij / Z, split as
-// sum p log(p (1 + |y_i - y_j|^2)) + (sum p) log Z.  32 lanes per row, the
-// logarithm in the element type, FP64 sums; each virtual block strides over
-// rows and leaves its two partial sums, which k_klsum adds in a fixed order
-// with the Z of the same call.
-template <typename T, int S>
-__global__ __launch_bounds__(256) void k_kl(LaunchMap map)
-{
-    constexpr int LPR = 32, RPB = 256 / LPR;
-    typedef typename Vec<T, S>::t V;
-    __shared__ double sh[8];
-    VB_BEGIN(map, K_KL)
-    if (live(I)) {
-        const int64_t n = I.n;
-        const int sub = (int)threadIdx.x % LPR;
-        const V* Y = static_cast<const V*>(I.Yin);
-        const T* val = static_cast<const T*>(I.val);
-        double a = 0.0, ps = 0.0;
-        for (int64_t i = (int64_t)lb * RPB + (int)threadIdx.x / LPR; i < n;
-             i += (int64_t)I.nb_kl * RPB) {
-            const V yi = Y[i];
-            const int64_t e = I.row_ptr[i + 1];
-            for (int64_t k = I.row_ptr[i] + sub; k < e; k += LPR) {
-                const T pk = val[k];
-                if (!(pk > (T)0)) continue;
-                const V yj = Y[I.col[k]];
-                T d2;
-                if constexpr (S == 2) {
-                    const T d0 = yi.x - yj.x, d1 = yi.y - yj.y;
-                    d2 = d0 * d0 + d1 * d1;
-                } else {
-                    const T d0 = yi - yj;
-                    d2 = d0 * d0;
-                }
-                a += (double)pk * (double)log(pk * ((T)1 + d2));
-                ps += (double)pk;
-            }
-        }
-        a = block_sum_d(a, sh);
-        ps = block_sum_d(ps, sh);
-        if (threadIdx.x == 0) {
-            I.kl_part[2 * lb] = a;
-            I.kl_part[2 * lb + 1] = ps;
-        }
-    }
-    VB_END
-}
-
-__global__ __launch_bounds__(256) void k_klsum(LaunchMap map)
-{
-    __shared__ double sh[8];
-    VB_BEGIN(map, K_KLSUM)
-    if (live(I)) {
-        double a = 0.0, ps = 0.0;
-        for (int b = threadIdx.x; b < I.nb_kl; b += 256) {
-            a += I.kl_part[2 * b];
-            ps += I.kl_part[2 * b + 1];
-        }
-        a = block_sum_d(a, sh);
-        ps = block_sum_d(ps, sh);
-        if (threadIdx.x == 0 && I.KLout) *I.KLout = a + ps * log(I.geom->Z);
-    }
-    VB_END
-}
-
-// ---------------------------------------------------------------- a10: update
+// ---------------------------------------------------------------- update
 
 __device__ __forceinline__ void sched_at(const Sched& sc, int it, double& alpha, double& mom)
 {
@@ -1223,6 +930,8 @@ __global__ __launch_bounds__(256) void k_update(LaunchMap map)
 
 hipError_t launch_fft_kind(int kind, const Cfg& c, const LaunchMap& map, const Launch& l,
                            hipStream_t st);
+hipError_t launch_attr_kind(int kind, const Cfg& c, const LaunchMap& map, const Launch& l,
+                            hipStream_t st);
 
 template <typename T, int S, int P, int FORM>
 static hipError_t launch_pts(int kind, const Cfg& c, const LaunchMap& map, const Launch& l,
@@ -1241,36 +950,7 @@ static hipError_t launch_pts(int kind, const Cfg& c, const LaunchMap& map, const
     case K_GEOM: hipLaunchKernelGGL((k_geom<S>), g, b, 0, st, map); break;
     case K_ZSUM: hipLaunchKernelGGL(k_zsum, g, b, 0, st, map); break;
     case K_NORM: hipLaunchKernelGGL((k_norm<T, S>), g, b, 0, st, map); break;
-    case K_ATTR:
-        if (c.lpr == 4) hipLaunchKernelGGL((k_attr<T, S, 4, 6, true>), g, b, 0, st, map);
-        else if (c.lpr == 8) hipLaunchKernelGGL((k_attr<T, S, 8, 4, true>), g, b, 0, st, map);
-        else if (c.lpr == 16) hipLaunchKernelGGL((k_attr<T, S, 16, 3, true>), g, b, 0, st, map);
-        else if (c.lpr == 32) hipLaunchKernelGGL((k_attr<T, S, 32, 3, true>), g, b, 0, st, map);
-        else hipLaunchKernelGGL((k_attr<T, S, 64, 2, true>), g, b, 0, st, map);
-        break;
-    case K_ATTR_ALL:
-        if (c.lpr == 4) hipLaunchKernelGGL((k_attr<T, S, 4, 6, false>), g, b, 0, st, map);
-        else if (c.lpr == 8) hipLaunchKernelGGL((k_attr<T, S, 8, 4, false>), g, b, 0, st, map);
-        else if (c.lpr == 16) hipLaunchKernelGGL((k_attr<T, S, 16, 3, false>), g, b, 0, st, map);
-        else if (c.lpr == 32) hipLaunchKernelGGL((k_attr<T, S, 32, 3, false>), g, b, 0, st, map);
-        else hipLaunchKernelGGL((k_attr<T, S, 64, 2, false>), g, b, 0, st, map);
-        break;
     case K_UPDATE: hipLaunchKernelGGL((k_update<T, S>), g, b, 0, st, map); break;
-    case K_ASUM: hipLaunchKernelGGL((k_asum<T, S>), g, b, 0, st, map); break;
-    case K_KL: hipLaunchKernelGGL((k_kl<T, S>), g, b, 0, st, map); break;
-    case K_KLSUM: hipLaunchKernelGGL(k_klsum, g, b, 0, st, map); break;
-    case K_ATTR_T:
-        if (l.lds > 48 * 1024)
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_attr_tile<T, S, true>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        hipLaunchKernelGGL((k_attr_tile<T, S, true>), g, b, l.lds, st, map);
-        break;
-    case K_ATTR_T_ALL:
-        if (l.lds > 48 * 1024)
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_attr_tile<T, S, false>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        hipLaunchKernelGGL((k_attr_tile<T, S, false>), g, b, l.lds, st, map);
-        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1279,8 +959,12 @@ static hipError_t launch_pts(int kind, const Cfg& c, const LaunchMap& map, const
 template <typename T, int S, int P>
 static hipError_t pts_form(int kind, const Cfg& c, const LaunchMap& m, const Launch& l, hipStream_t st)
 {
-    return c.form == 0 ? launch_pts<T, S, P, 0>(kind, c, m, l, st)
-                       : launch_pts<T, S, P, 1>(kind, c, m, l, st);
+    switch (c.form) {
+    case 0: return launch_pts<T, S, P, 0>(kind, c, m, l, st);
+    case 1: return launch_pts<T, S, P, 1>(kind, c, m, l, st);
+    case 2: return launch_pts<T, S, P, 2>(kind, c, m, l, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T, int S>
@@ -1310,6 +994,9 @@ hipError_t launch_kind(int kind, const Cfg& c, const LaunchMap& map, const Launc
     case K_FFT_ROWS: case K_FFT_COLS: case K_FFT_IROWS: case K_FFT_1D:
     case K_SPEC0: case K_SPEC1: case K_SPEC2:
         return launch_fft_kind(kind, c, map, l, st);
+    case K_ATTR: case K_ATTR_ALL: case K_ATTR_T: case K_ATTR_T_ALL: case K_ASUM:
+    case K_KL: case K_KLSUM:
+        return launch_attr_kind(kind, c, map, l, st);
     default:
         return c.dtype == 0 ? pts_s<float>(kind, c, map, l, st) : pts_s<double>(kind, c, map, l, st);
     }

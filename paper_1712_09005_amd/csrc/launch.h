@@ -13,7 +13,7 @@ struct Cfg {
     int dtype;   // 0 float, 1 double
     int s;       // 1, 2
     int p;       // 2..6
-    int form;    // 0 A, 1 B
+    int form;    // 0 A, 1 B, 2 V
     int lpr;     // CSR lanes per row
 };
 

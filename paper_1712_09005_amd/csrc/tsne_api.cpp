@@ -97,7 +97,7 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     if (d->dtype != TSNE_F32 && d->dtype != TSNE_F64) return TSNE_E_ARG;
     if (d->p < 2 || d->p > kMaxP) return TSNE_E_UNSUPPORTED;
     if (d->policy != TSNE_GRID_PAPER && d->policy != TSNE_GRID_FIXED) return TSNE_E_ARG;
-    if (d->form != TSNE_FORM_A && d->form != TSNE_FORM_B) return TSNE_E_ARG;
+    if (d->form != TSNE_FORM_A && d->form != TSNE_FORM_B && d->form != TSNE_FORM_V) return TSNE_E_ARG;
     if (d->min_intervals < 1 || d->max_intervals < d->min_intervals) return TSNE_E_ARG;
     if (d->policy == TSNE_GRID_FIXED && !(d->interval_width > 0.0)) return TSNE_E_ARG;
     if (d->nnz < 0 || d->nnz > (int64_t)INT_MAX * 8) return TSNE_E_ARG;
@@ -111,8 +111,8 @@ tsne_status derive(const tsne_desc* d, Derived& o)
 
     o.s = d->s;
     o.p = d->p;
-    o.nc = (d->form == TSNE_FORM_A) ? d->s + 1 : d->s + 2;
-    o.np = d->s + 2;
+    o.nc = (d->form == TSNE_FORM_A) ? d->s + 1 : (d->form == TSNE_FORM_B) ? d->s + 2 : 1;
+    o.np = (d->form == TSNE_FORM_V) ? d->s + 1 : d->s + 2;
     o.tsz = (d->dtype == TSNE_F32) ? 4 : 8;
     o.max_int = d->max_intervals;
     const int64_t ncap64 = (int64_t)d->max_intervals * d->p;
@@ -249,10 +249,12 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     if (d->s == 2) {
         sz[R_X] = (size_t)csz * o.nc * o.ntiles * o.n_cap * o.tile_w;
         sz[R_XC] = (size_t)csz * o.np * o.ntiles * o.n_cap * o.tile_w;
-        sz[R_SPEC] = (size_t)o.tsz * 2 * o.half * o.half;
+        // form V: a third spectrum (the transposed odd table) and the sine matrix
+        const size_t vf = (d->form == TSNE_FORM_V) ? 1 : 0;
+        sz[R_SPEC] = (size_t)o.tsz * (2 + vf) * o.half * o.half;
         sz[R_SPECTMP] = sizeof(double) * 2 * (size_t)o.half * o.half;
         sz[R_KTAB] = sizeof(double) * 2 * (size_t)o.half * o.half;
-        sz[R_CCOS] = sizeof(double) * (size_t)o.half * o.half;
+        sz[R_CCOS] = sizeof(double) * (1 + vf) * (size_t)o.half * o.half;
     } else {
         sz[R_CCOS] = 0;
         sz[R_X] = 0;
@@ -263,7 +265,7 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     }
     sz[R_V] = (size_t)o.tsz * o.np * grid;
     sz[R_TW] = (size_t)csz * o.M;
-    sz[R_COS] = sizeof(double) * o.M;
+    sz[R_COS] = sizeof(double) * 2 * o.M;               // cos, then sin
     sz[R_R] = (size_t)o.tsz * n * d->s;
     sz[R_FA] = (size_t)o.tsz * n * d->s;
     sz[R_FAP] = (o.slabs > 1) ? (size_t)o.tsz * n * d->s * o.slabs : 0;
@@ -959,7 +961,7 @@ tsne_status tsne_batch_create(int32_t max_slots, int32_t s, int32_t dtype, int32
     if (!out) return TSNE_E_ARG;
     *out = nullptr;
     if (max_slots < 1 || max_slots > 4096 || (s != 1 && s != 2) || (dtype != 0 && dtype != 1) ||
-        (form != 0 && form != 1))
+        (form != 0 && form != 1 && form != 2))
         return TSNE_E_ARG;
     if (lanes_per_row == 0) lanes_per_row = 32;
     if (lanes_per_row != 4 && lanes_per_row != 8 && lanes_per_row != 16 && lanes_per_row != 32 &&

@@ -18,7 +18,15 @@ LIB_PATH = os.path.join(_HERE, "libtsne_mi355x.so")
 
 F32, F64 = 0, 1
 GRID_PAPER, GRID_FIXED = 0, 1
-FORM_A, FORM_B = 0, 1
+FORM_A, FORM_B, FORM_V = 0, 1, 2
+_FORMS = {"A": FORM_A, "B": FORM_B, "V": FORM_V, FORM_A: FORM_A, FORM_B: FORM_B, FORM_V: FORM_V}
+
+
+def form_code(form):
+    """Form name ("A", "B", "V") or code to the tsne_form code."""
+    if form not in _FORMS:
+        raise ValueError("form must be one of A, B, V")
+    return _FORMS[form]
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported configuration",
           3: "workspace", 4: "capacity exceeded", 5: "non-finite coordinate",
@@ -141,7 +149,7 @@ def make_desc(n, s, dtype=torch.float32, p=5, policy="fixed", form="A", min_inte
               max_intervals=512, interval_width=0.75, nnz=0, lanes_per_row=0,
               points_per_lane=0, attr_slabs=0, attr_layout=0) -> Desc:
     pol = GRID_PAPER if policy in ("paper", GRID_PAPER) else GRID_FIXED
-    frm = FORM_A if form in ("A", FORM_A) else FORM_B
+    frm = form_code(form)
     return Desc(int(n), int(s), _dt(dtype), int(p), pol, frm, int(min_intervals),
                 int(max_intervals), float(interval_width), int(nnz), int(lanes_per_row),
                 int(points_per_lane), int(attr_slabs), int(attr_layout))
@@ -364,7 +372,7 @@ class Batch:
         self.lanes_per_row = int(lanes_per_row)
         self.dtype = torch.float32 if _dt(dtype) == F32 else torch.float64
         self.s, self.p = int(s), int(p)
-        self.form = FORM_A if form in ("A", FORM_A) else FORM_B
+        self.form = form_code(form)
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         nb = int(lib().tsne_batch_workspace_bytes(int(max_slots)))
         if nb == 0:

@@ -105,14 +105,14 @@ def test_interp_choice_meets_target(A, tmp_path):
     n = 3000
     Y = inputs.mixture_embedding(n, 2, 8, -25, 25, 2.0, seed=23).astype(np.float64)
     r = A.tune_interp(Y, target=1e-3, safety=2.5, max_intervals=128, device=DEV, reps=3,
-                      cache=str(tmp_path / "i.json"))
-    assert r["p"] in (4, 5, 6) and len(r["table"]) >= 1
+                      cache=str(tmp_path / "i.json"), forms=("A", "V"))
+    assert r["p"] in (4, 5, 6) and r["form"] in ("A", "V") and len(r["table"]) >= 2
     from paper_1712_09005_amd import tsne
     plan = tsne.Plan(n, 2, torch.float32, p=r["p"], interval_width=r["interval_width"],
-                     max_intervals=128, device=DEV)
+                     max_intervals=128, form=r["form"], device=DEV)
     F, _ = plan.repulsive(torch.from_numpy(Y.astype(np.float32)).to(DEV))
     Fd, _ = oracle.direct_rep(Y)
     e = rel(F.cpu().numpy(), Fd)
-    print("  chose p=%d w=%.2f, FP32 error vs direct %.2e (table %s)" % (r["p"], r["interval_width"], e,
-                                                                       r["table"]))
+    print("  chose form %s p=%d w=%.2f, FP32 error vs direct %.2e (table %s)"
+          % (r["form"], r["p"], r["interval_width"], e, r["table"]))
     assert e < 1e-3

@@ -59,8 +59,8 @@ def gpu_rep(T, Y, dtype=torch.float32, p=5, policy="fixed", w=0.75, min_int=1, m
 def oracle_rep(Y, p, policy, w, min_int, form="A"):
     Yd = np.asarray(Y, np.float64)
     o, ww, m = oracle.geometry(Yd, policy, min_int, w)
-    r = oracle.interp_rep(Yd, o, ww, m, p, oracle.FORM_A if form == "A" else oracle.FORM_B,
-                          want_grids=True)
+    code = {"A": oracle.FORM_A, "B": oracle.FORM_B, "V": oracle.FORM_V}[form]
+    r = oracle.interp_rep(Yd, o, ww, m, p, code, want_grids=True)
     return (o, ww, m), r
 
 
@@ -114,8 +114,50 @@ def test_grids_match_oracle(T, dtype):
     np.testing.assert_array_equal(np.diff(cs), counts)
 
 
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-9), (torch.float32, 1e-4)])
+@pytest.mark.parametrize("n", [2048, 3001])
+def test_repulsion_form_v_2d(T, dtype, tol, n):
+    """Vector-kernel form against the oracle's form V on the same geometry."""
+    print("case: repulsion form V 2-D n=%d %s" % (n, dtype), flush=True)
+    Y = inputs.mixture_embedding(n, 2, 10, -30, 30, 2.0, seed=1)
+    _, _, F, Z, st = gpu_rep(T, Y, dtype, p=5, policy="fixed", w=0.75, max_int=128, form="V")
+    assert st["status"] == 0, st
+    (o, w, m), r = oracle_rep(Y, 5, "fixed", 0.75, 1, "V")
+    assert st["n_int"] == m
+    e = rel(F, r["F"])
+    ez = abs(Z - r["Z"]) / r["Z"]
+    print("  rel err F %.3e  Z %.3e" % (e, ez))
+    assert e < tol and ez < tol
+    for d in range(2):
+        assert rel(F[:, d], r["F"][:, d]) < tol
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_grids_form_v_match_oracle(T, dtype):
+    """Form V: the one charge grid and the K1 and odd-kernel potential grids
+    (no charge scaling: the charge is 1)."""
+    print("case: grids form V %s" % dtype, flush=True)
+    n = 2500
+    Y = inputs.mixture_embedding(n, 2, 6, -12, 12, 1.5, seed=5)
+    plan, _, F, Z, st = gpu_rep(T, Y, dtype, p=4, policy="paper", min_int=20, max_int=64, form="V")
+    (o, w, m), r = oracle_rep(Y, 4, "paper", 1.0, 20, "V")
+    assert st["n_int"] == m
+    ng, ncap = m * 4, 64 * 4
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    Wg = np.frombuffer(plan.export(0), npdt).reshape(1, ncap, ncap)[:, :ng, :ng]
+    Vg = np.frombuffer(plan.export(1), npdt).reshape(3, ncap, ncap)[:, :ng, :ng]
+    Yd = Y.astype(np.float64)
+    cells = np.clip(np.floor((Yd - o) / w), 0, m - 1).astype(int)
+    occ = np.zeros((m, m), bool)
+    occ[cells[:, 1], cells[:, 0]] = True
+    mask = np.kron(occ, np.ones((4, 4), bool))
+    assert rel(Wg[0][mask], r["W"][0][mask]) < (1e-10 if dtype == torch.float64 else 1e-5)
+    for k in range(3):
+        assert rel(Vg[k], r["V"][k]) < (1e-9 if dtype == torch.float64 else 2e-5), k
+
+
 @pytest.mark.parametrize("p", [3, 4, 5])
-@pytest.mark.parametrize("form", ["A", "B"])
+@pytest.mark.parametrize("form", ["A", "B", "V"])
 def test_repulsion_p_and_form(T, p, form):
     print("case: p=%d form %s" % (p, form), flush=True)
     Y = inputs.mixture_embedding(1500, 2, 5, -10, 10, 1.0, seed=2)
@@ -126,7 +168,7 @@ def test_repulsion_p_and_form(T, p, form):
 
 
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-9), (torch.float32, 1e-4)])
-@pytest.mark.parametrize("form", ["A", "B"])
+@pytest.mark.parametrize("form", ["A", "B", "V"])
 def test_repulsion_1d(T, dtype, tol, form):
     print("case: 1-D %s %s" % (dtype, form), flush=True)
     Y = inputs.mixture_embedding(4000, 1, 12, -60, 60, 1.5, seed=0)
