@@ -114,10 +114,11 @@ def test_grids_match_oracle(T, dtype):
     np.testing.assert_array_equal(np.diff(cs), counts)
 
 
-@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-9), (torch.float32, 1e-4)])
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-9), (torch.float32, 1e-5)])
 @pytest.mark.parametrize("n", [2048, 3001])
 def test_repulsion_form_v_2d(T, dtype, tol, n):
-    """Vector-kernel form against the oracle's form V on the same geometry."""
+    """Vector-kernel form against the oracle's form V on the same geometry.
+    No cancellation in the numerators, so FP32 is held to 1e-5."""
     print("case: repulsion form V 2-D n=%d %s" % (n, dtype), flush=True)
     Y = inputs.mixture_embedding(n, 2, 10, -30, 30, 2.0, seed=1)
     _, _, F, Z, st = gpu_rep(T, Y, dtype, p=5, policy="fixed", w=0.75, max_int=128, form="V")
