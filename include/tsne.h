@@ -67,7 +67,10 @@ typedef enum { TSNE_F32 = 0, TSNE_F64 = 1 } tsne_dtype;
  * box).  A point y falls in interval clamp(floor((y - origin)/w), 0, N_int-1).
  *   TSNE_GRID_PAPER: N_int = max(min_intervals, ceil(L)), w = L / N_int
  *                    (the interval count of the experiments of Section 2.5);
- *   TSNE_GRID_FIXED: w = interval_width, N_int = max(min_intervals, ceil(L/w)).
+ *   TSNE_GRID_FIXED: w = interval_width, N_int = ceil(L/w); a box narrower than
+ *                    min_intervals * interval_width gets N_int = min_intervals
+ *                    and w = L / N_int (no interval wider than L / min_intervals,
+ *                    as under the interval count of Section 2.5).
  * L is floored at 1e-6.  The FFT length M (a 4^a 3^b 5^c number >= 2 N_int p)
  * is chosen on the device every call, with hysteresis; the FP64 kernel spectra
  * are rebuilt whenever M or the node spacing w/p changes: under FIXED only

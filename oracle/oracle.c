@@ -171,8 +171,10 @@ double oracle_kl(int64_t n, int s, const double* Y, const int64_t* row_ptr,
 /* ------------------------------------------------------------------------ */
 
 /* Side L = max_d (max - min), floored at 1e-6.  PAPER: N_int =
- * max(min_intervals, ceil(L)), w = L / N_int.  FIXED: w = interval_width,
- * N_int = max(min_intervals, ceil(L / w)).  The square box of side N_int w is
+ * max(min_intervals, ceil(L)), w = L / N_int.  FIXED: w = interval_width and
+ * N_int = ceil(L / w), unless that gives fewer than min_intervals intervals;
+ * then N_int = min_intervals and w = L / N_int, so that, as under the
+ * interval count of Section 2.5, no interval is wider than L / min_intervals.  The square box of side N_int w is
  * centred on the mid-range of each dimension: origin(d) = (min + max)/2 -
  * N_int w / 2 (for the widest dimension under PAPER this is its minimum).
  * Y holds the float32 inputs widened to double. */
@@ -196,6 +198,9 @@ void oracle_geometry(int64_t n, int s, const double* Y, int policy,
     if (policy == ORACLE_POLICY_PAPER) {
         m = (int)ceil(L);
         if (m < min_intervals) m = min_intervals;
+        *w_int = L / m;
+    } else if (L < interval_width * min_intervals) {
+        m = min_intervals;
         *w_int = L / m;
     } else {
         m = (int)ceil(L / interval_width);

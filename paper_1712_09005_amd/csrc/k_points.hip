@@ -251,6 +251,11 @@ __global__ __launch_bounds__(256) void k_geom(LaunchMap map)
                 m = (int)fmin(ceil(L), 2.0e9);
                 if (m < I.min_int) m = I.min_int;
                 w = L / m;
+            } else if (L < I.interval_width * I.min_int) {
+                // a box narrower than min_int intervals: shrink the intervals
+                // to L / min_int, as the paper's interval count does
+                m = I.min_int;
+                w = L / m;
             } else {
                 w = I.interval_width;
                 m = (int)fmin(ceil(L / w), 2.0e9);

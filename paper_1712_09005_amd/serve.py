@@ -67,10 +67,12 @@ def summarize(jobs, makespan: float) -> dict:
 
 class Server:
     def __init__(self, max_slots: int = 8, hbm_budget: int = 200 << 30, ticks_per_poll: int = 10,
-                 interval_width: float = 0.75, p: int = 5, lanes_per_row: int = 32, device="cuda"):
+                 interval_width: float = 0.75, p: int = 5, lanes_per_row: int = 32, device="cuda",
+                 form="A"):
         self.device = torch.device(device)
-        self.batch = tsne.Batch(max_slots, s=2, dtype=torch.float32, p=p,
+        self.batch = tsne.Batch(max_slots, s=2, dtype=torch.float32, p=p, form=form,
                                 lanes_per_row=lanes_per_row, device=self.device)
+        self.form = form
         self.max_slots = max_slots
         self.budget = hbm_budget
         self.k = ticks_per_poll
@@ -79,7 +81,7 @@ class Server:
 
     def footprint(self, job: Job, cap: int) -> int:
         return tsne.Batch.footprint(job.n, job.P.nnz, s=2, p=self.p, max_intervals=cap,
-                                    interval_width=self.w)
+                                    interval_width=self.w, form=self.form)
 
     def run(self, jobs, log=None) -> dict:
         pending = deque(sorted(jobs, key=lambda j: j.arrival))
@@ -137,7 +139,7 @@ class Server:
 
 
 def sequential(jobs, interval_width: float = 0.75, p: int = 5, lanes_per_row: int = 32,
-               device="cuda", log=None) -> dict:
+               device="cuda", log=None, form="A") -> dict:
     """The same trace served one job at a time with the unbatched path."""
     dev = torch.device(device)
     t0 = time.perf_counter()
@@ -156,7 +158,7 @@ def sequential(jobs, interval_width: float = 0.75, p: int = 5, lanes_per_row: in
         col = torch.from_numpy(job.P.col).to(dev)
         val = torch.from_numpy(job.P.val).to(dev)
         while True:
-            plan = tsne.Plan(job.n, 2, torch.float32, p=p, policy="fixed",
+            plan = tsne.Plan(job.n, 2, torch.float32, p=p, policy="fixed", form=form,
                              interval_width=interval_width, max_intervals=cap, nnz=job.P.nnz,
                              lanes_per_row=lanes_per_row, attr_slabs=1, attr_layout=1,
                              device=dev)

@@ -398,9 +398,9 @@ class Batch:
 
     @staticmethod
     def footprint(n, nnz, s=2, dtype=torch.float32, p=5, policy="fixed", max_intervals=512,
-                  interval_width=0.75, min_intervals=1):
+                  interval_width=0.75, min_intervals=1, form="A"):
         """Device bytes a job holds: plan workspace plus Y, uY, gains and P."""
-        d = make_desc(n, s, dtype, p, policy, "A", min_intervals, max_intervals, interval_width, nnz,
+        d = make_desc(n, s, dtype, p, policy, form, min_intervals, max_intervals, interval_width, nnz,
                       lanes_per_row=32, attr_slabs=1, attr_layout=1)
         tsz = 4 if d.dtype == F32 else 8
         return workspace_bytes(d) + 3 * n * s * tsz + 8 * (n + 1) + (4 + tsz) * nnz

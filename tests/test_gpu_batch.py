@@ -28,9 +28,9 @@ def _job(n, seed):
     return Y, P
 
 
-def _alone(T, Y, P, dtype, sched, it0, n_it):
+def _alone(T, Y, P, dtype, sched, it0, n_it, form="A"):
     n = Y.shape[0]
-    plan = T.Plan(n, 2, dtype, p=5, policy="fixed", interval_width=0.75, max_intervals=256,
+    plan = T.Plan(n, 2, dtype, p=5, policy="fixed", interval_width=0.75, max_intervals=256, form=form,
                   nnz=P.nnz, lanes_per_row=32, attr_slabs=1, attr_layout=1, device=DEV)
     plan.bind_P(torch.from_numpy(P.row_ptr).to(DEV), torch.from_numpy(P.col).to(DEV),
                 torch.from_numpy(P.val).to(DEV, dtype))
@@ -48,13 +48,14 @@ def _alone(T, Y, P, dtype, sched, it0, n_it):
 # early-exaggeration dynamics amplify such differences over tens of
 # iterations; FP32 is therefore compared after 3 iterations at 1e-4.
 @pytest.mark.parametrize("dtype,tol,iters", [(torch.float64, 1e-9, 30), (torch.float32, 1e-4, 3)])
-def test_alone_equals_in_the_mix(T, dtype, tol, iters):
-    print("case: batch alone vs mix %s" % dtype, flush=True)
+@pytest.mark.parametrize("form", ["A", "V"])
+def test_alone_equals_in_the_mix(T, dtype, tol, iters, form):
+    print("case: batch alone vs mix %s form %s" % (dtype, form), flush=True)
     sched = T.Schedule(ee_stop=10, mom_switch=10)
     sizes = [(3000, 10, iters), (7001, 3, iters), (1500, 20, iters - 1)]   # (n, seed, iterations)
     jobs = [_job(n, sd) for n, sd, _ in sizes]
-    alone = [_alone(T, Y, P, dtype, sched, 0, it) for (Y, P), (_, _, it) in zip(jobs, sizes)]
-    b = T.Batch(4, s=2, dtype=dtype, p=5, device=DEV)
+    alone = [_alone(T, Y, P, dtype, sched, 0, it, form) for (Y, P), (_, _, it) in zip(jobs, sizes)]
+    b = T.Batch(4, s=2, dtype=dtype, p=5, form=form, device=DEV)
     slots = []
     for (Y, P), (_, _, it) in zip(jobs[:2], sizes[:2]):
         slots.append(b.admit(Y, (P.row_ptr, P.col, P.val), sched, 0, it, max_intervals=256))
@@ -77,7 +78,7 @@ def test_alone_equals_in_the_mix(T, dtype, tol, iters):
     b.tick(12)
     done, st = b.poll(sl)
     assert done == 12 and st == 0
-    ref = _alone(T, Y, P, dtype, sched, 0, 12)
+    ref = _alone(T, Y, P, dtype, sched, 0, 12, form)
     Yb = b.retire(sl)["Y"].cpu().numpy()
     assert np.linalg.norm(Yb - ref) / np.linalg.norm(ref) < tol
 

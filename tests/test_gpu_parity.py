@@ -133,6 +133,28 @@ def test_repulsion_form_v_2d(T, dtype, tol, n):
         assert rel(F[:, d], r["F"][:, d]) < tol
 
 
+@pytest.mark.parametrize("form", ["A", "V"])
+@pytest.mark.parametrize("min_int", [1, 6])
+def test_small_box_fixed_policy(T, form, min_int):
+    """A box narrower than min_int intervals of the fixed width (the start of
+    a run from a tiny random embedding): the intervals shrink to L / min_int
+    on the device exactly as in the oracle, and the forces meet the accuracy
+    target against the direct sum in both forms."""
+    print("case: small box form %s min_int %d" % (form, min_int), flush=True)
+    rng = np.random.default_rng(12)
+    Y = (1e-2 * rng.standard_normal((3000, 2))).astype(np.float32)
+    _, _, F, Z, st = gpu_rep(T, Y, torch.float32, p=5, policy="fixed", w=0.75, min_int=min_int,
+                             max_int=64, form=form)
+    assert st["status"] == 0
+    (o, w, m), r = oracle_rep(Y, 5, "fixed", 0.75, min_int, form)
+    assert st["n_int"] == m == min_int and st["w_int"] == w < 0.75
+    np.testing.assert_array_equal(st["origin"], o)
+    Fd, Zd = oracle.direct_rep(Y.astype(np.float64))
+    e = rel(F, Fd)
+    print("  vs direct %.2e, vs interpolation oracle %.2e" % (e, rel(F, r["F"])))
+    assert e < 1e-3 and abs(Z - Zd) / Zd < 1e-3
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_grids_form_v_match_oracle(T, dtype):
     """Form V: the one charge grid and the K1 and odd-kernel potential grids

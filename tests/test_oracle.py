@@ -122,7 +122,13 @@ def test_geometry_policies():
     np.testing.assert_allclose(o, [-0.5e-6, -0.5e-6], rtol=1e-9)
     Yt = np.array([[0.01], [0.03]])                            # narrower than one interval
     o, w, m = oracle.geometry(Yt, "fixed", 1, 0.75)
-    assert m == 1 and o[0] == pytest.approx(0.02 - 0.375)
+    assert m == 1 and w == pytest.approx(0.02, rel=1e-14)      # the interval shrinks to the box
+    assert o[0] == pytest.approx(0.01, rel=1e-14)
+    o, w, m = oracle.geometry(Y, "fixed", 60, 0.75)            # 60 x 0.75 > 37.2: w = L / 60
+    assert m == 60 and w == pytest.approx(37.2 / 60, rel=1e-15)
+    np.testing.assert_allclose(o, [1.0, 4.0 - 18.6], rtol=0, atol=1e-13)
+    o, w, m = oracle.geometry(Y, "fixed", 40, 0.75)            # 40 x 0.75 < 37.2: w fixed
+    assert m == 50 and w == 0.75
 
 
 # --------------------------------------------------------------------------
