@@ -248,21 +248,22 @@ def test_attraction(T, dtype, lpr, slabs, layout, n, s):
 
 
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-9), (torch.float32, 1e-4)])
-def test_step_vs_oracle(T, dtype, tol):
+@pytest.mark.parametrize("form", ["A", "V"])
+def test_step_vs_oracle(T, dtype, tol, form):
     """One full iteration (repulsion, attraction, update) against the oracle
     composed step by step, in the early-exaggeration phase and after it."""
     n = 2048
     c1 = inputs.config_inputs("c1")
     Y, P = c1["Y"], c1["P"]
     plan = T.Plan(n, 2, dtype, p=5, policy="fixed", interval_width=0.75, max_intervals=128,
-                  nnz=P.nnz, device=DEV)
+                  form=form, nnz=P.nnz, device=DEV)
     plan.bind_P(torch.from_numpy(P.row_ptr).to(DEV), torch.from_numpy(P.col).to(DEV),
                 torch.from_numpy(P.val).to(DEV, dtype))
     rng = np.random.default_rng(3)
     uY0 = rng.standard_normal((n, 2)) * 0.1
     g0 = 1.0 + rng.uniform(0, 0.5, (n, 2))
     for it in (0, 300):
-        print("case: step it=%d %s" % (it, dtype), flush=True)
+        print("case: step it=%d %s form %s" % (it, dtype, form), flush=True)
         Yt = torch.from_numpy(Y).to(DEV, dtype)
         uY = torch.from_numpy(uY0).to(DEV, dtype)
         gains = torch.from_numpy(g0).to(DEV, dtype)
@@ -273,7 +274,7 @@ def test_step_vs_oracle(T, dtype, tol):
         assert st["status"] == 0 and st["iter"] == it + 1
         Yd = Y.astype(np.float64)
         o, w, m = oracle.geometry(Yd, "fixed", 1, 0.75)
-        r = oracle.interp_rep(Yd, o, w, m, 5)
+        r = oracle.interp_rep(Yd, o, w, m, 5, oracle.FORM_A if form == "A" else oracle.FORM_V)
         Fa = oracle.attr(Yd, inputs.CSR(P.row_ptr, P.col, P.val.astype(np.float64)))
         alpha, mom = oracle.schedule(it)
         Y1, u1, g1 = oracle.update(Yd, uY0, g0, Fa, r["F"], alpha, mom, 200.0)
@@ -282,17 +283,18 @@ def test_step_vs_oracle(T, dtype, tol):
         assert rel(Yt.cpu().numpy(), Y1) < tol
 
 
-def test_run_matches_steps(T):
+@pytest.mark.parametrize("form", ["A", "V"])
+def test_run_matches_steps(T, form):
     """tsne_run (graph replay, device iteration counter) against the same
     iterations issued one tsne_step at a time."""
-    print("case: run vs steps", flush=True)
+    print("case: run vs steps form %s" % form, flush=True)
     c1 = inputs.config_inputs("c1")
     Y, P = c1["Y"], c1["P"]
     n = Y.shape[0]
     outs = []
     for mode in ("steps", "run"):
         plan = T.Plan(n, 2, torch.float64, p=5, interval_width=0.75, max_intervals=256,
-                      nnz=P.nnz, device=DEV)
+                      form=form, nnz=P.nnz, device=DEV)
         plan.bind_P(torch.from_numpy(P.row_ptr).to(DEV), torch.from_numpy(P.col).to(DEV),
                     torch.from_numpy(P.val).to(DEV, torch.float64))
         Yt = torch.from_numpy(Y).to(DEV, torch.float64)
