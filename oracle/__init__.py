@@ -60,13 +60,13 @@ def _load():
             "oracle_knn_rows": [i64, i32, P, i32, P, i64, P, P],
             "oracle_perplexity": [i64, i32, P, f64, P, P],
             "oracle_symmetrize": [i64, i32, P, P, P, P, P],
-            "oracle_geometry": [i64, i32, P, i32, i32, f64, P, P, P],
+            "oracle_geometry": [i64, i32, P, i32, i32, f64, i32, P, P, P],
             "oracle_lagrange": [i32, f64, P],
-            "oracle_grid_conv": [i32, i32, f64, i32, i32, P, P],
-            "oracle_interp_rep": [i64, i32, P, P, f64, i32, i32, i32, i32,
+            "oracle_grid_conv": [i32, P, f64, i32, i32, P, P],
+            "oracle_interp_rep": [i64, i32, P, P, f64, P, i32, i32, i32,
                                   P, P, P, P, P, P],
-            "oracle_interp_spread": [i64, i32, P, P, f64, i32, i32, i32, P],
-            "oracle_interp_rows": [i64, i32, P, P, f64, i32, i32, i32, i32,
+            "oracle_interp_spread": [i64, i32, P, P, f64, P, i32, i32, P],
+            "oracle_interp_rows": [i64, i32, P, P, f64, P, i32, i32, i32,
                                    P, P, i64, P],
             "oracle_update": [i64, i32, P, P, P, P, P, f64, f64, f64, f64,
                               f64, f64, i32],
@@ -197,17 +197,28 @@ def symmetrize(idx, p):
 
 
 # ---------------------------------------------------------------- geometry
-def geometry(Y, policy, min_intervals=1, interval_width=1.0):
-    """(origin [s], w_int, N_int) of the box policy."""
+def geometry(Y, policy, min_intervals=1, interval_width=1.0, rect=False):
+    """(origin [s], w_int, N_int) of the box policy; N_int is an int for the
+    square box, or a tuple of per-axis counts with ``rect``."""
     Y = _f64(Y)
     n, s = Y.shape
     o = np.empty(s)
     w = ctypes.c_double()
-    m = ctypes.c_int()
+    m = np.zeros(s, dtype=np.int32)
     pol = POLICY_PAPER if policy in ("paper", POLICY_PAPER) else POLICY_FIXED
     _load().oracle_geometry(n, s, _ptr(Y), pol, int(min_intervals), float(interval_width),
-                            _ptr(o), ctypes.addressof(w), ctypes.addressof(m))
-    return o, w.value, m.value
+                            int(bool(rect)), _ptr(o), ctypes.addressof(w), _ptr(m))
+    return o, w.value, (tuple(int(x) for x in m) if rect else int(m[0]))
+
+
+def _axes(n_int, s):
+    """Per-axis interval counts as an int32 array of length s."""
+    a = np.atleast_1d(np.asarray(n_int, dtype=np.int32))
+    if a.shape[0] == 1:
+        a = np.repeat(a, s)
+    if a.shape[0] != s:
+        raise ValueError("n_int must be one count or one per axis")
+    return np.ascontiguousarray(a)
 
 
 # ---------------------------------------------------------------- interpolation
@@ -218,25 +229,27 @@ def lagrange(p, t):
 
 
 def grid_conv(W, h, kernel, kind=KERNEL_TSNE):
-    """Step 2 directly on a 1-D [ng] or 2-D [ng, ng] (index [g1, g0]) grid.
+    """Step 2 directly on a 1-D [ng] or 2-D [ng1, ng0] (index [g1, g0]) grid.
     kernel: 1 = K1, 2 = K2, 3 / 4 = the odd kernels z_0 K2, z_1 K2."""
     W = _f64(W)
     s = W.ndim
-    ng = W.shape[0]
+    ngv = np.array(W.shape[::-1], dtype=np.int32)         # [ng0(, ng1)]
     V = np.empty_like(W)
-    _load().oracle_grid_conv(s, ng, float(h), kind, int(kernel), _ptr(W), _ptr(V))
+    _load().oracle_grid_conv(s, _ptr(ngv), float(h), kind, int(kernel), _ptr(W), _ptr(V))
     return V
 
 
 def interp_rep(Y, origin, w_int, n_int, p=3, form=FORM_A, kind=KERNEL_TSNE,
                want_grids=False):
-    """Interpolation scheme with direct Step 2.  Returns a dict with F [N, s],
-    Z, phi [N, s+2], h1 [N] and (``want_grids``) W [C, ng(, ng)], V [s+2, ...]."""
+    """Interpolation scheme with direct Step 2.  n_int: one interval count
+    (square box) or one per axis.  Returns a dict with F [N, s], Z,
+    phi [N, P], h1 [N] and (``want_grids``) W [C, (ng1,) ng0], V [P, ...]."""
     Y = _f64(Y)
     n, s = Y.shape
     o = _f64(origin)
-    ng = n_int * p
-    tn = ng ** s
+    ax = _axes(n_int, s)
+    shape = tuple(int(x) * p for x in ax[::-1])           # (ng1,) ng0
+    tn = int(np.prod(shape))
     nc = s + 1 if form == FORM_A else (s + 2 if form == FORM_B else 1)
     npot = s + 1 if form == FORM_V else s + 2
     F = np.empty((n, s))
@@ -245,14 +258,13 @@ def interp_rep(Y, origin, w_int, n_int, p=3, form=FORM_A, kind=KERNEL_TSNE,
     h1 = np.empty(n)
     W = np.empty((nc, tn)) if want_grids else None
     V = np.empty((npot, tn)) if want_grids else None
-    rc = _load().oracle_interp_rep(n, s, _ptr(Y), _ptr(o), float(w_int), int(n_int), int(p),
+    rc = _load().oracle_interp_rep(n, s, _ptr(Y), _ptr(o), float(w_int), _ptr(ax), int(p),
                                    int(form), int(kind), _ptr(F), ctypes.addressof(Z),
                                    _ptr(W), _ptr(V), _ptr(phi), _ptr(h1))
     if rc != 0:
         raise ValueError("oracle_interp_rep: bad arguments")
     out = dict(F=F, Z=Z.value, phi=phi, h1=h1)
     if want_grids:
-        shape = (ng,) if s == 1 else (ng, ng)
         out["W"] = W.reshape((nc,) + shape)
         out["V"] = V.reshape((npot,) + shape)
     return out
@@ -261,11 +273,11 @@ def interp_rep(Y, origin, w_int, n_int, p=3, form=FORM_A, kind=KERNEL_TSNE,
 def interp_spread(Y, origin, w_int, n_int, p=3, form=FORM_A):
     Y = _f64(Y)
     n, s = Y.shape
-    ng = n_int * p
+    ax = _axes(n_int, s)
     nc = s + 1 if form == FORM_A else (s + 2 if form == FORM_B else 1)
-    W = np.empty((nc, ng ** s))
+    W = np.empty((nc, int(np.prod(ax * p))))
     rc = _load().oracle_interp_spread(n, s, _ptr(Y), _ptr(_f64(origin)), float(w_int),
-                                      int(n_int), int(p), int(form), _ptr(W))
+                                      _ptr(ax), int(p), int(form), _ptr(W))
     if rc != 0:
         raise ValueError("oracle_interp_spread: bad arguments")
     return W
@@ -279,7 +291,7 @@ def interp_rows(Y, origin, w_int, n_int, rows, W, p=3, form=FORM_A, kind=KERNEL_
     r = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
     phi = np.empty((r.shape[0], s + 1 if form == FORM_V else s + 2))
     rc = _load().oracle_interp_rows(n, s, _ptr(Y), _ptr(_f64(origin)), float(w_int),
-                                    int(n_int), int(p), int(form), int(kind), _ptr(_f64(W)),
+                                    _ptr(_axes(n_int, s)), int(p), int(form), int(kind), _ptr(_f64(W)),
                                     _ptr(r), r.shape[0], _ptr(phi))
     if rc != 0:
         raise ValueError("oracle_interp_rows: bad arguments")
@@ -287,8 +299,9 @@ def interp_rows(Y, origin, w_int, n_int, rows, W, p=3, form=FORM_A, kind=KERNEL_
 
 
 def centre(origin, w_int, n_int):
-    """Box centre used to centre the charges."""
-    return _f64(origin) + 0.5 * n_int * w_int
+    """Box centre used to centre the charges (n_int: one count or per axis)."""
+    o = _f64(origin)
+    return o + 0.5 * _axes(n_int, o.shape[0]).astype(np.float64) * w_int
 
 
 def assemble_rows(Y, origin, w_int, n_int, phi, form=FORM_A):

@@ -174,12 +174,16 @@ double oracle_kl(int64_t n, int s, const double* Y, const int64_t* row_ptr,
  * max(min_intervals, ceil(L)), w = L / N_int.  FIXED: w = interval_width and
  * N_int = ceil(L / w), unless that gives fewer than min_intervals intervals;
  * then N_int = min_intervals and w = L / N_int, so that, as under the
- * interval count of Section 2.5, no interval is wider than L / min_intervals.  The square box of side N_int w is
+ * interval count of Section 2.5, no interval is wider than L / min_intervals.
+ * Every axis gets that N_int (the square box of Section 2.4), or with rect
+ * set (s = 2) each narrower axis d gets its own count
+ * min(N_int, max(min_intervals, ceil(L_d / w))) at the same w, so the box is
+ * a rectangle of equal spacing; n_int[d] receives the per-axis counts.  The square box of side N_int w is
  * centred on the mid-range of each dimension: origin(d) = (min + max)/2 -
  * N_int w / 2 (for the widest dimension under PAPER this is its minimum).
  * Y holds the float32 inputs widened to double. */
 void oracle_geometry(int64_t n, int s, const double* Y, int policy,
-                     int min_intervals, double interval_width,
+                     int min_intervals, double interval_width, int rect,
                      double* origin, double* w_int, int* n_int)
 {
     double lo[3], hi[3];
@@ -207,8 +211,17 @@ void oracle_geometry(int64_t n, int s, const double* Y, int policy,
         if (m < min_intervals) m = min_intervals;
         *w_int = interval_width;
     }
-    *n_int = m;
-    for (int d = 0; d < s; ++d) origin[d] = 0.5 * (lo[d] + hi[d]) - 0.5 * m * (*w_int);
+    for (int d = 0; d < s; ++d) {
+        int md = m;
+        double Ld = hi[d] - lo[d];
+        if (rect && s == 2 && Ld < L) {
+            md = (int)ceil(Ld / *w_int);
+            if (md < min_intervals) md = min_intervals;
+            if (md > m) md = m;
+        }
+        n_int[d] = md;
+        origin[d] = 0.5 * (lo[d] + hi[d]) - 0.5 * md * (*w_int);
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -243,18 +256,19 @@ static void locate(double y, double o, double w, int n_int, int* cell, double* t
     *t = u - (double)c;
 }
 
-/* Step 2 directly (eq. (equikereval2)): on a grid with ng nodes per dimension
- * and spacing h,
+/* Step 2 directly (eq. (equikereval2)): on a grid with ngv[d] nodes along
+ * dimension d and spacing h,
  *   V[g] = sum_{g'} K(h (g - g')) W[g'],
  * where kernel selects K1 (1), K2 (2), or the odd vector kernels
  * G_d(z) = z_d K2(|z|^2) along dimension 0 (3) or 1 (4).  2-D grids are
- * indexed g1*ng + g0.  The kernel values come from a table over the lag
+ * indexed g1*ng0 + g0.  The kernel values come from a table over the lag
  * (|g0-g0'|, |g1-g1'|), with the sign of the lag along d for G_d: the
  * translation invariance that makes the matrix Toeplitz. */
-void oracle_grid_conv(int s, int ng, double h, int kind, int kernel,
+void oracle_grid_conv(int s, const int* ngv, double h, int kind, int kernel,
                       const double* W, double* V)
 {
-    int64_t tn = (s == 1) ? ng : (int64_t)ng * ng;
+    const int ng = ngv[0], ng1 = (s == 2) ? ngv[1] : 1;
+    int64_t tn = (int64_t)ng * ng1;
     double* T = (double*)malloc((size_t)tn * sizeof(double));
     for (int64_t a = 0; a < tn; ++a) {
         double dx = (double)(a % ng), dy = (s == 1) ? 0.0 : (double)(a / ng);
@@ -279,7 +293,7 @@ void oracle_grid_conv(int s, int ng, double h, int kind, int kernel,
         for (int64_t g = 0; g < tn; ++g) {
             int g0 = (int)(g % ng), g1 = (int)(g / ng);
             double acc = 0.0;
-            for (int q1 = 0; q1 < ng; ++q1) {
+            for (int q1 = 0; q1 < ng1; ++q1) {
                 const double* Trow = T + (int64_t)abs(g1 - q1) * ng;
                 const double* Wrow = W + (int64_t)q1 * ng;
                 const double s1 = (kernel == 4) ? (double)((g1 > q1) - (g1 < q1)) : 1.0;
@@ -295,7 +309,8 @@ void oracle_grid_conv(int s, int ng, double h, int kind, int kernel,
 }
 
 /* The interpolation-based repulsion for s = 1 or 2 with the given box
- * (origin[s], interval width w, N_int intervals, p nodes per interval).
+ * (origin[s], interval width w, n_int[d] intervals along dimension d, p
+ * nodes per interval).
  *
  * Charges (centred at the box centre c): form A {1, y'(d)}, form B
  * {1, y'(d), |y'|^2}; y' = y - c.  Potentials (s + 2 of them):
@@ -320,18 +335,21 @@ void oracle_grid_conv(int s, int ng, double h, int kind, int kernel,
  * Vout [P][ng^s] potential grids (P = s+2, or s+1 form V), phi [n][P]
  * potentials at the points, h1 [n].  Returns 0, or -1 on bad arguments. */
 int oracle_interp_rep(int64_t n, int s, const double* Y, const double* origin,
-                      double w, int n_int, int p, int form, int kind,
+                      double w, const int* n_int, int p, int form, int kind,
                       double* F, double* Z, double* Wout, double* Vout,
                       double* phi, double* h1out)
 {
-    if (s < 1 || s > 2 || p < 1 || n_int < 1 || n < 1) return -1;
-    int ng = n_int * p;
-    int64_t tn = (s == 1) ? ng : (int64_t)ng * ng;
+    if (s < 1 || s > 2 || p < 1 || n < 1) return -1;
+    for (int d = 0; d < s; ++d)
+        if (n_int[d] < 1) return -1;
+    int ng = n_int[0] * p;
+    int ngv[2] = {ng, (s == 2) ? n_int[1] * p : 1};
+    int64_t tn = (int64_t)ngv[0] * ngv[1];
     int nc = (form == ORACLE_FORM_A) ? s + 1 : (form == ORACLE_FORM_B) ? s + 2 : 1;
     int np = (form == ORACLE_FORM_V) ? s + 1 : s + 2;
     double h = w / p;
     double centre[2];
-    for (int d = 0; d < s; ++d) centre[d] = origin[d] + 0.5 * n_int * w;
+    for (int d = 0; d < s; ++d) centre[d] = origin[d] + 0.5 * n_int[d] * w;
 
     int* cells = (int*)malloc((size_t)n * s * sizeof(int));
     double* wts = (double*)malloc((size_t)n * s * p * sizeof(double));
@@ -341,7 +359,7 @@ int oracle_interp_rep(int64_t n, int s, const double* Y, const double* origin,
         q[i * nc + 0] = 1.0;
         for (int d = 0; d < s; ++d) {
             double t;
-            locate(Y[i * s + d], origin[d], w, n_int, &cells[i * s + d], &t);
+            locate(Y[i * s + d], origin[d], w, n_int[d], &cells[i * s + d], &t);
             oracle_lagrange(p, t, wts + (i * s + d) * p);
             double yc = Y[i * s + d] - centre[d];
             if (form != ORACLE_FORM_V) q[i * nc + 1 + d] = yc;
@@ -384,7 +402,7 @@ int oracle_interp_rep(int64_t n, int s, const double* Y, const double* origin,
         for (int d = 0; d < s; ++d) { pk[2 + d] = 2; pc[2 + d] = 1 + d; }
     }
     for (int k = 0; k < np; ++k)
-        oracle_grid_conv(s, ng, h, kind, pk[k], W + (int64_t)pc[k] * tn, V + (int64_t)k * tn);
+        oracle_grid_conv(s, ngv, h, kind, pk[k], W + (int64_t)pc[k] * tn, V + (int64_t)k * tn);
 
     /* Step 3: phi(y_i) = sum_m L_m(y_i) v_{m,l} */
     double* ph = (double*)calloc((size_t)n * np, sizeof(double));
@@ -441,22 +459,24 @@ int oracle_interp_rep(int64_t n, int s, const double* Y, const double* origin,
 
 /* Step 1 alone: the charge grids W [C][ng^s] of oracle_interp_rep. */
 int oracle_interp_spread(int64_t n, int s, const double* Y, const double* origin,
-                         double w, int n_int, int p, int form, double* Wout)
+                         double w, const int* n_int, int p, int form, double* Wout)
 {
-    if (s < 1 || s > 2 || p < 1 || n_int < 1) return -1;
-    int ng = n_int * p;
-    int64_t tn = (s == 1) ? ng : (int64_t)ng * ng;
+    if (s < 1 || s > 2 || p < 1) return -1;
+    for (int d = 0; d < s; ++d)
+        if (n_int[d] < 1) return -1;
+    int ng = n_int[0] * p;
+    int64_t tn = (int64_t)ng * ((s == 2) ? n_int[1] * p : 1);
     int nc = (form == ORACLE_FORM_A) ? s + 1 : (form == ORACLE_FORM_B) ? s + 2 : 1;
     double centre[2], L0[16], L1[16];
-    for (int d = 0; d < s; ++d) centre[d] = origin[d] + 0.5 * n_int * w;
+    for (int d = 0; d < s; ++d) centre[d] = origin[d] + 0.5 * n_int[d] * w;
     memset(Wout, 0, (size_t)nc * tn * sizeof(double));
     for (int64_t i = 0; i < n; ++i) {
         int c0 = 0, c1 = 0;
         double t0, t1 = 0.0, qv[4], r2c = 0.0;
-        locate(Y[i * s], origin[0], w, n_int, &c0, &t0);
+        locate(Y[i * s], origin[0], w, n_int[0], &c0, &t0);
         oracle_lagrange(p, t0, L0);
         if (s == 2) {
-            locate(Y[i * s + 1], origin[1], w, n_int, &c1, &t1);
+            locate(Y[i * s + 1], origin[1], w, n_int[1], &c1, &t1);
             oracle_lagrange(p, t1, L1);
         } else {
             L1[0] = 1.0;
@@ -483,14 +503,17 @@ int oracle_interp_spread(int64_t n, int s, const double* Y, const double* origin
  * over every node.  Needs the complete charge grids W (oracle_interp_spread).
  * Outputs phi [nrows][s+2] in the potential order of oracle_interp_rep. */
 int oracle_interp_rows(int64_t n, int s, const double* Y, const double* origin,
-                       double w, int n_int, int p, int form, int kind,
+                       double w, const int* n_int, int p, int form, int kind,
                        const double* W, const int64_t* rows, int64_t nrows,
                        double* phi)
 {
     (void)n;
-    if (s < 1 || s > 2 || p < 1 || n_int < 1) return -1;
-    int ng = n_int * p;
-    int64_t tn = (s == 1) ? ng : (int64_t)ng * ng;
+    if (s < 1 || s > 2 || p < 1) return -1;
+    for (int d = 0; d < s; ++d)
+        if (n_int[d] < 1) return -1;
+    int ng = n_int[0] * p;
+    int ng1 = (s == 2) ? n_int[1] * p : 1;
+    int64_t tn = (int64_t)ng * ng1;
     int np = (form == ORACLE_FORM_V) ? s + 1 : s + 2;
     double h = w / p;
     int pk[5], pc[5];
@@ -519,10 +542,10 @@ int oracle_interp_rows(int64_t n, int s, const double* Y, const double* origin,
         int64_t i = rows[r];
         int c0 = 0, c1 = 0;
         double t0, t1 = 0.0, L0[16], L1[16];
-        locate(Y[i * s], origin[0], w, n_int, &c0, &t0);
+        locate(Y[i * s], origin[0], w, n_int[0], &c0, &t0);
         oracle_lagrange(p, t0, L0);
         if (s == 2) {
-            locate(Y[i * s + 1], origin[1], w, n_int, &c1, &t1);
+            locate(Y[i * s + 1], origin[1], w, n_int[1], &c1, &t1);
             oracle_lagrange(p, t1, L1);
         } else {
             L1[0] = 1.0;
@@ -537,7 +560,7 @@ int oracle_interp_rows(int64_t n, int s, const double* Y, const double* origin,
                     const double* Tk = T + (int64_t)(pk[k] - 1) * tn;
                     const double* Wc = W + (int64_t)pc[k] * tn;
                     double v = 0.0;
-                    for (int q1 = 0; q1 < ((s == 2) ? ng : 1); ++q1) {
+                    for (int q1 = 0; q1 < ng1; ++q1) {
                         const double* Trow = Tk + (int64_t)abs(g1 - q1) * ng;
                         const double* Wrow = Wc + (int64_t)q1 * ng;
                         const double s1 = (pk[k] == 4) ? (double)((g1 > q1) - (g1 < q1)) : 1.0;

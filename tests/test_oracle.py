@@ -131,6 +131,27 @@ def test_geometry_policies():
     assert m == 50 and w == 0.75
 
 
+def test_geometry_rect_per_axis_counts():
+    """Rectangular box: the widest axis keeps the square box's count and
+    width, each narrower axis gets min(N, max(N_min, ceil(L_d / w))) intervals
+    of the same width, centred on its mid-range."""
+    Y = np.array([[1.0, -2.0], [38.2, 3.0], [5.0, 10.0]])        # widths 37.2 (x), 12 (y)
+    o, w, m = oracle.geometry(Y, "fixed", 1, 0.75, rect=True)
+    assert m == (50, 16) and w == 0.75                          # 12 / 0.75 = 16 exactly
+    np.testing.assert_allclose(o, [19.6 - 18.75, -2.0], rtol=0, atol=1e-13)
+    o, w, m = oracle.geometry(Y, "paper", 20, rect=True)
+    assert m == (38, 20) and w == pytest.approx(37.2 / 38, rel=1e-15)   # N_min holds per axis
+    np.testing.assert_allclose(o, [1.0, 4.0 - 10 * 37.2 / 38], rtol=0, atol=1e-13)
+    Yt = Y[:, ::-1].copy()                                      # the wide axis second
+    o2, w2, m2 = oracle.geometry(Yt, "fixed", 1, 0.75, rect=True)
+    assert m2 == (16, 50) and w2 == 0.75
+    Ys = np.array([[0.0, 0.0], [10.0, 10.0], [3.0, 7.0]])       # equal widths: the square box
+    o3, w3, m3 = oracle.geometry(Ys, "fixed", 1, 0.75, rect=True)
+    o4, w4, m4 = oracle.geometry(Ys, "fixed", 1, 0.75)
+    assert m3 == (m4, m4) and w3 == w4
+    np.testing.assert_array_equal(o3, o4)
+
+
 # --------------------------------------------------------------------------
 # Lagrange basis (Section 2.1) on the nodes of eq. (equinodes)
 # --------------------------------------------------------------------------
@@ -179,6 +200,28 @@ def test_grid_conv_vs_numpy_fft(s, ng, kernel):
     np.testing.assert_allclose(V, Vf, atol=1e-12 * np.abs(Vf).max())
 
 
+@pytest.mark.parametrize("ng0,ng1,kernel", [(12, 7, 1), (9, 14, 2), (11, 6, 3), (8, 13, 4)])
+def test_grid_conv_rect_vs_numpy_fft(ng0, ng1, kernel):
+    """A rectangular grid (ng1 rows of ng0 nodes): the Toeplitz product equals
+    the 2 ng1 x 2 ng0 circulant convolution by numpy's FFT, for the even and
+    the odd kernels (a swapped axis or a wrong extent fails)."""
+    rng = np.random.default_rng(ng0 * 31 + ng1 + kernel)
+    h = 0.41
+    W = rng.standard_normal((ng1, ng0))
+    V = oracle.grid_conv(W, h, kernel)
+    M0, M1 = 2 * ng0, 2 * ng1
+    def signed(M):
+        j = np.arange(M)
+        js = np.where(j < M // 2, j, j - M).astype(float)
+        js[M // 2] = 0.0
+        return js
+    a, b = signed(M1)[:, None], signed(M0)[None, :]             # [g1 lag, g0 lag]
+    K1 = 1.0 / (1.0 + h * h * (a ** 2 + b ** 2))
+    K = {1: K1, 2: K1 ** 2, 3: h * b * K1 ** 2, 4: h * a * K1 ** 2}[kernel]
+    Vf = np.real(np.fft.ifft2(np.fft.fft2(W, (M1, M0)) * np.fft.fft2(K)))[:ng1, :ng0]
+    np.testing.assert_allclose(V, Vf, atol=1e-12 * np.abs(Vf).max())
+
+
 @pytest.mark.parametrize("s,ng,kernel", [(1, 37, 3), (2, 12, 3), (2, 9, 4), (2, 10, 4)])
 def test_grid_conv_odd_kernels_vs_numpy_fft(s, ng, kernel):
     """The odd kernels G_d(z) = z_d K2(|z|^2) (vector-kernel form): the
@@ -222,7 +265,7 @@ def _brute_phi(Y, o, w, nint, p, kind_fn):
     interpolant of Section 2.1/2.4, built pair by pair."""
     n, s = Y.shape
     h = w / p
-    cells = np.clip(np.floor((Y - o) / w), 0, nint - 1).astype(int)
+    cells = np.clip(np.floor((Y - o) / w), 0, np.asarray(nint) - 1).astype(int)
     t = (Y - o) / w - cells
     Ls = [[_vander_lagrange(p, t[i, d]) for d in range(s)] for i in range(n)]
     node = [[o[d] + (cells[i, d] * p + np.arange(p) + 0.5) * h for d in range(s)] for i in range(n)]
@@ -375,6 +418,49 @@ def test_interp_form_v_polynomial_exactness(s):
     F, Z = oracle.direct_rep(Y, oracle.KERNEL_POLY)
     assert r5["Z"] == pytest.approx(Z, rel=1e-11)
     assert _rel(r5["F"], F) < 1e-10
+
+
+@pytest.mark.parametrize("form,p", [(oracle.FORM_B, 3), (oracle.FORM_A, 5), (oracle.FORM_V, 5)])
+def test_interp_rect_exact_for_polynomial_kernels(form, p):
+    """Rectangular box (per-axis interval counts, equal spacing): with the
+    polynomial kernels the three steps still reproduce the direct sums to
+    rounding, so the per-axis grids, centres and lags are consistent."""
+    rng = np.random.default_rng(70 + p + form)
+    Y = np.column_stack([rng.uniform(-3.0, 9.0, 160), rng.uniform(2.0, 5.5, 160)])
+    o, w, m = oracle.geometry(Y, "fixed", 1, 0.8, rect=True)
+    assert m[0] == 15 and m[1] == 5                                 # 12 / 0.8, ceil(3.5 / 0.8)
+    r = oracle.interp_rep(Y, o, w, m, p, form, oracle.KERNEL_POLY, want_grids=True)
+    assert r["W"].shape[1:] == (5 * p, 15 * p)
+    F, Z = oracle.direct_rep(Y, oracle.KERNEL_POLY)
+    assert r["Z"] == pytest.approx(Z, rel=1e-11)
+    assert _rel(r["F"], F) < 1e-10
+
+
+def test_interp_rect_pairwise_interpolant_and_agreement():
+    """Rectangular box: the three steps equal the brute-force pairwise sum
+    with the interpolated kernel on per-axis cells; rect and square boxes
+    give the same forces to the interpolation error; forces sum to zero."""
+    rng = np.random.default_rng(81)
+    Y = np.column_stack([rng.uniform(0.0, 2.6, 24), rng.uniform(0.0, 0.8, 24)])
+    o, w, m = oracle.geometry(Y, "fixed", 1, 0.9, rect=True)
+    assert m == (3, 1)
+    r = oracle.interp_rep(Y, o, w, m, 4, oracle.FORM_A)
+    Kp1, Kp2 = _brute_phi(Y, o, w, m, 4, TSNE)
+    yc = Y - oracle.centre(o, w, m)
+    phi_b = np.column_stack([Kp1.sum(1), Kp2.sum(1)] + [Kp2 @ yc[:, d] for d in range(2)])
+    np.testing.assert_allclose(r["phi"], phi_b, rtol=1e-11, atol=1e-12)
+    Yc = inputs.mixture_embedding(800, 2, 4, -10, 10, 1.0, seed=3).astype(np.float64)
+    Yc[:, 1] *= 0.3                                              # a flat cloud
+    F, Z = oracle.direct_rep(Yc)
+    for form in (oracle.FORM_A, oracle.FORM_V):
+        o, w, m = oracle.geometry(Yc, "fixed", 1, 0.5, rect=True)
+        assert m[1] < m[0]
+        rr = oracle.interp_rep(Yc, o, w, m, 5, form)
+        o2, w2, m2 = oracle.geometry(Yc, "fixed", 1, 0.5)
+        rs = oracle.interp_rep(Yc, o2, w2, m2, 5, form)
+        assert _rel(rr["F"], F) < 1e-3 and _rel(rs["F"], F) < 1e-3
+        assert abs(rr["Z"] - Z) / Z < 1e-4
+        assert np.abs(rr["F"].sum(0)).max() < 1e-10 * np.abs(rr["F"]).sum()
 
 
 def test_interp_not_exact_for_polynomial_form_a_p3():
