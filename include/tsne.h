@@ -107,6 +107,12 @@ typedef struct {
                                 the bound CSR), 2 tiles (P re-bucketed at bind time
                                 into row-block x column-block tiles, positions of
                                 both blocks staged in LDS) */
+    int32_t rect;            /* box shape (s = 2): 0 the square box of Section 2.4;
+                                1 a rectangle of equal spacing: the widest axis
+                                keeps the policy's N_int and w, a narrower axis d
+                                gets min(N_int, max(min_intervals, ceil(L_d / w)))
+                                intervals, and each axis its own FFT length.
+                                Ignored for s = 1. */
 } tsne_desc;
 
 /* Descent schedule, indexed by the absolute iteration it:
@@ -143,6 +149,9 @@ typedef struct {
     double w_int;            /* interval width of the last iteration */
     double box_side;         /* L of the last iteration */
     double Z;                /* normalisation of the last repulsion */
+    int32_t n_int_y;         /* second axis (s = 2): N_int, nodes and FFT length; */
+    int32_t n_nodes_y;       /* equal to the first axis' for the square box */
+    int32_t fft_len_y;
 } tsne_stats;
 
 typedef struct tsne_plan tsne_plan;

@@ -158,16 +158,21 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int M, int PM, int G, in
 
 // Forward transforms (exp(-2 pi i k n / M)) of G length-M sequences in LDS
 // (padded layout, transform g at g * lds_stride(M)), M and the radix stages
-// being those of this iteration (Geom).
+// being those of this iteration's first axis (Geom), or of its second axis
+// with yaxis set.
 template <typename T>
-__device__ __forceinline__ void block_fft(cplx<T>* buf, int G, const Inst& I, const Geom& Gm)
+__device__ __forceinline__ void block_fft(cplx<T>* buf, int G, const Inst& I, const Geom& Gm,
+                                          bool yaxis = false)
 {
-    const cplx<T>* tw = static_cast<const cplx<T>*>(I.tw);
-    const int M = Gm.M, PM = lds_stride(M);
+    const cplx<T>* tw = static_cast<const cplx<T>*>(yaxis ? I.twy : I.tw);
+    const int M = yaxis ? Gm.My : Gm.M, PM = lds_stride(M);
+    const int nst = yaxis ? Gm.nstages_y : Gm.nstages;
+    const int* radix = yaxis ? Gm.radix_y : Gm.radix;
+    const int* tw_off = yaxis ? Gm.tw_off_y : Gm.tw_off;
     int Ns = 1;
-    for (int s = 0; s < Gm.nstages; ++s) {
-        const int R = Gm.radix[s];
-        const cplx<T>* tws = tw + Gm.tw_off[s];
+    for (int s = 0; s < nst; ++s) {
+        const int R = radix[s];
+        const cplx<T>* tws = tw + tw_off[s];
         switch (R) {
         case 2: fft_stage<T, 2>(buf, M, PM, G, Ns, tws); break;
         case 3: fft_stage<T, 3>(buf, M, PM, G, Ns, tws); break;
@@ -212,11 +217,11 @@ __global__ __launch_bounds__(1024) void k_fft_rows(LaunchMap map)
     VB_BEGIN(map, K_FFT_ROWS)
     if (okay(I)) {
         const Geom& G = *I.geom;
-        const int n = G.n, n_int = G.n_int, M = G.M, n_cap = I.n_cap, tw_ = I.tile_w;
+        const int n = G.n, ny = G.n_y, n_int = G.n_int, M = G.M, n_cap = I.n_cap, tw_ = I.tile_w;
         const int npairs = (n_cap + 1) / 2;
         const int ch = lb / npairs, j = lb - ch * npairs;
         const int ra = 2 * j, rb = 2 * j + 1;
-        if (ra < n) {
+        if (ra < ny) {
             const T* W = static_cast<const T*>(I.W) + (int64_t)ch * n_cap * n_cap;
             const int* cs = I.cell_start;
             const int cya = ra / P, cyb = rb / P;
@@ -225,7 +230,7 @@ __global__ __launch_bounds__(1024) void k_fft_rows(LaunchMap map)
                 if (g < n) {
                     const int cx = g / P;
                     if (occupied(cs, cya * n_int + cx)) a = W[(int64_t)ra * n_cap + g];
-                    if (rb < n && occupied(cs, cyb * n_int + cx)) b = W[(int64_t)rb * n_cap + g];
+                    if (rb < ny && occupied(cs, cyb * n_int + cx)) b = W[(int64_t)rb * n_cap + g];
                 }
                 buf[lds_pad(g)] = {a, b};
             }
@@ -240,7 +245,7 @@ __global__ __launch_bounds__(1024) void k_fft_rows(LaunchMap map)
                 const cplx<T> B = {(z.y + zc.y) * hlf, (zc.x - z.x) * hlf};
                 const int tile = k >> ltw, kk = k & (tw_ - 1);
                 X[((int64_t)tile * n_cap + ra) * tw_ + kk] = A;
-                if (rb < n) X[((int64_t)tile * n_cap + rb) * tw_ + kk] = B;
+                if (rb < ny) X[((int64_t)tile * n_cap + rb) * tw_ + kk] = B;
             }
             __syncthreads();
         }
@@ -256,7 +261,11 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
     VB_BEGIN(map, K_FFT_COLS)
     if (okay(I)) {
         const Geom& Gm = *I.geom;
-        const int n = Gm.n, M = Gm.M, n_cap = I.n_cap, tw_ = I.tile_w, half = Gm.half;
+        // columns: the half spectrum of the first axis; each column is a
+        // transform of length My over the n_y node rows of the second axis
+        const int n = Gm.n_y, M = Gm.My, n_cap = I.n_cap, tw_ = I.tile_w, half = Gm.half;
+        const int half_y = Gm.half_y;
+        const int64_t kslot = (int64_t)I.half * I.half; // one spectrum table
         const int Gc = Gm.col_group;                   // columns per block this iteration
         const int G = tw_ / Gc;                        // blocks per tile of X
         const int ncg = ((half + tw_ - 1) / tw_) * G;  // blocks per potential this iteration
@@ -291,7 +300,7 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
             buf[g * PM + lds_pad(r)] = v;
         }
         __syncthreads();
-        block_fft<T>(buf, Gc, I, Gm);
+        block_fft<T>(buf, Gc, I, Gm, true);
         // multiply by the real kernel spectrum, conjugate for the inverse; the
         // threads split evenly over the block's columns
         {
@@ -299,7 +308,7 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
             const int g = (int)threadIdx.x >> (__ffs(tpc) - 1);
             const int jt = (int)threadIdx.x - g * tpc;
             const int k0 = k00 + g;
-            const T* sp = static_cast<const T*>(I.spec) + (int64_t)kern * half * half + (int64_t)k0 * half;
+            const T* sp = static_cast<const T*>(I.spec) + (int64_t)kern * kslot + (int64_t)k0 * half_y;
             cplx<T>* col = buf + g * PM;
             if (FORM == 2 && kern > 0) {
                 // times -i b, b odd in k1 for the kernel odd along dimension 1
@@ -321,7 +330,7 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
             }
         }
         __syncthreads();
-        block_fft<T>(buf, Gc, I, Gm);
+        block_fft<T>(buf, Gc, I, Gm, true);
         cplx<T>* Xc = static_cast<cplx<T>*>(I.Xc) + (int64_t)pot * I.ntiles * n_cap * tw_;
         for (int idx = threadIdx.x; idx < (n << lgc); idx += blockDim.x) {
             const int r = idx >> lgc, g = idx & (Gc - 1);
@@ -344,7 +353,7 @@ __global__ __launch_bounds__(1024) void k_fft_irows(LaunchMap map)
         const int n = G.n, M = G.M, n_cap = I.n_cap, tw_ = I.tile_w;
         const int q = lb / n_cap, r = lb - q * n_cap;
         const int pa = 2 * q, pb = 2 * q + 1;
-        if (r < n) {
+        if (r < G.n_y) {
             const cplx<T>* Xa = static_cast<const cplx<T>*>(I.Xc) + (int64_t)pa * I.ntiles * n_cap * tw_;
             const cplx<T>* Xb = static_cast<const cplx<T>*>(I.Xc) + (int64_t)pb * I.ntiles * n_cap * tw_;
             const int mh = M / 2;
@@ -427,13 +436,16 @@ __device__ __forceinline__ double kern_val(int kern, double r2)
     return kern == 0 ? a : a * a;
 }
 
-// Table kern of the lag grid: K1 (0); K2 (1), or for form V the odd kernel
-// z_0 K2 at the non-negative lag z_0 = h j0 (its sign is restored by the
-// sine transform).
-__device__ __forceinline__ double ktab_val(int form, int kern, double h, int j0, double r2)
+// Value of table kern on the lag grid (j0, j1) with r2 = h^2 (j0^2 + j1^2):
+// K1 (0); K2 (1); for form V, table 1 is the odd kernel along dimension 0,
+// z_0 K2 at the non-negative lag z_0 = h j0, and table 2 the one along
+// dimension 1 (their signs are restored by the sine transforms).
+__device__ __forceinline__ double ktab_val(int form, int kern, double h, int j0, int j1, double r2)
 {
-    const double v = kern_val(kern, r2);
-    return (form == 2 && kern == 1) ? h * (double)j0 * v : v;
+    if (kern == 0) return kern_val(0, r2);
+    const double v = kern_val(1, r2);
+    if (form != 2) return v;
+    return h * (double)(kern == 1 ? j0 : j1) * v;
 }
 
 // The tables are rebuilt when the box kernel found a new node spacing or a
@@ -444,9 +456,43 @@ __device__ __forceinline__ bool spec_needed(const Inst& I)
     return okay(I) && I.geom->spec_dirty != 0;
 }
 
-// Twiddles exp(-2 pi i k / M) (element type), cos and sin(2 pi k / M)
-// (double) and the kernel values K(h^2 (j1^2 + j0^2)) on the lag grid
-// j <= M/2 (double).
+// Stage twiddle tables of one axis: stage s holds w^(r k M/(Ns R)) at
+// tw_off[s] + k (R-1) + r - 1, w = exp(-2 pi i / M); idx < M - 1.
+template <typename T>
+__device__ __forceinline__ void stage_twiddle(int64_t idx, int M, int nstages, const int* radix,
+                                              const int* tw_off, void* twv)
+{
+    int st = 0;
+    while (st + 1 < nstages && tw_off[st + 1] <= idx) ++st;
+    int ns = 1;
+    for (int q = 0; q < st; ++q) ns *= radix[q];
+    const int R = radix[st];
+    const int e = (int)idx - tw_off[st];
+    const int k = e / (R - 1), r = e - k * (R - 1) + 1;
+    const int64_t ang = (int64_t)r * k * (M / (ns * R));
+    double sv, cv;
+    sincospi(2.0 * (double)ang / (double)M, &sv, &cv);
+    static_cast<cplx<T>*>(twv)[idx] = {(T)cv, (T)(-sv)};
+}
+
+// Entry (j, k) of the weighted cosine matrix wt(j) cos(2 pi j k / M) (wt = 1
+// at j = 0 and j = M/2, else 2: the circulant folds j and M - j), or of the
+// sine matrix 2 sin(2 pi j k / M) (zero at j = 0, M/2), j, k <= M/2.
+__device__ __forceinline__ void cs_entry(int M, int j, int k, double& c, double& sn)
+{
+    double sv, cv;
+    sincospi(2.0 * (double)(((int64_t)j * k) % M) / (double)M, &sv, &cv);
+    const bool edge = (j == 0 || 2 * j == M);
+    c = (edge ? 1.0 : 2.0) * cv;
+    sn = edge ? 0.0 : 2.0 * sv;
+}
+
+// Number of kernel tables: K1 and K2, or K1 and the s odd kernels (form V).
+__device__ __forceinline__ int n_tables(const Inst& I) { return I.form == 2 ? I.s + 1 : 2; }
+
+// Twiddles exp(-2 pi i k / M) of each axis (element type), the cos and sin
+// tables (s = 1) or the weighted cosine and sine matrices of each axis
+// (s = 2), and the kernel values on the lag grid j <= M/2 (double).
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_spec0(LaunchMap map)
 {
@@ -455,48 +501,47 @@ __global__ __launch_bounds__(256) void k_spec0(LaunchMap map)
         const Geom& G = *I.geom;
         const int M = G.M, half = G.half;
         const int64_t idx = (int64_t)lb * 256 + threadIdx.x;
-        if (idx < M) {
-            double sv, cv;
-            sincospi(2.0 * (double)idx / (double)M, &sv, &cv);
-            I.costab[idx] = cv;
-            I.costab[M + idx] = sv;
-        }
-        if (idx < M - 1) {
-            // stage tables: stage s holds w^(r k M/(Ns R)) at [k (R-1) + r - 1]
-            int st = 0;
-            while (st + 1 < G.nstages && G.tw_off[st + 1] <= idx) ++st;
-            int ns = 1;
-            for (int q = 0; q < st; ++q) ns *= G.radix[q];
-            const int R = G.radix[st];
-            const int e = (int)idx - G.tw_off[st];
-            const int k = e / (R - 1), r = e - k * (R - 1) + 1;
-            const int64_t ang = (int64_t)r * k * (M / (ns * R));
-            double sv, cv;
-            sincospi(2.0 * (double)ang / (double)M, &sv, &cv);
-            cplx<T>* tw = static_cast<cplx<T>*>(I.tw);
-            tw[idx] = {(T)cv, (T)(-sv)};
-        }
         const double h2 = G.h * G.h;
+        if (idx < M - 1) stage_twiddle<T>(idx, M, G.nstages, G.radix, G.tw_off, I.tw);
         if (S == 2) {
+            const int My = G.My, hy = G.half_y;
+            const int64_t slot = (int64_t)I.half * I.half;
+            if (idx < My - 1) stage_twiddle<T>(idx, My, G.nstages_y, G.radix_y, G.tw_off_y, I.twy);
+            // cosine (and form V sine) matrices: x at slots 0 and 2, y at 1 and 3
             if (idx < (int64_t)half * half) {
                 const int j = (int)(idx / half), k = (int)(idx - (int64_t)j * half);
-                const double wt = (j == 0 || 2 * j == M) ? 1.0 : 2.0;
-                double sv, cv;
-                sincospi(2.0 * (double)(((int64_t)j * k) % M) / (double)M, &sv, &cv);
-                I.ccos[idx] = wt * cv;
-                // form V: the sine matrix 2 sin(2 pi j k / M), zero at j = 0, M/2
-                if (I.form == 2)
-                    I.ccos[(int64_t)half * half + idx] = (j == 0 || 2 * j == M) ? 0.0 : 2.0 * sv;
+                double c, sn;
+                cs_entry(M, j, k, c, sn);
+                I.ccos[idx] = c;
+                if (I.form == 2) I.ccos[2 * slot + idx] = sn;
             }
-            if (idx < (int64_t)2 * half * half) {
-                const int kern = (int)(idx / ((int64_t)half * half));
-                const int rem = (int)(idx - (int64_t)kern * half * half);
+            if (idx < (int64_t)hy * hy) {
+                const int j = (int)(idx / hy), k = (int)(idx - (int64_t)j * hy);
+                double c, sn;
+                cs_entry(My, j, k, c, sn);
+                I.ccos[slot + idx] = c;
+                if (I.form == 2) I.ccos[3 * slot + idx] = sn;
+            }
+            // kernel tables [kern][j1 < half_y][j0 < half]
+            const int64_t per = (int64_t)hy * half;
+            if (idx < n_tables(I) * per) {
+                const int kern = (int)(idx / per);
+                const int rem = (int)(idx - (int64_t)kern * per);
                 const int j1 = rem / half, j0 = rem - j1 * half;
-                I.ktab[idx] = ktab_val(I.form, kern, G.h, j0, h2 * ((double)j1 * j1 + (double)j0 * j0));
+                I.ktab[kern * slot + rem] =
+                    ktab_val(I.form, kern, G.h, j0, j1, h2 * ((double)j1 * j1 + (double)j0 * j0));
             }
-        } else if (idx < 2 * half) {
-            const int kern = (int)(idx / half), j = (int)(idx - (int64_t)kern * half);
-            I.ktab[idx] = ktab_val(I.form, kern, G.h, j, h2 * (double)j * j);
+        } else {
+            if (idx < M) {
+                double sv, cv;
+                sincospi(2.0 * (double)idx / (double)M, &sv, &cv);
+                I.costab[idx] = cv;
+                I.costab[I.M + idx] = sv;
+            }
+            if (idx < 2 * half) {
+                const int kern = (int)(idx / half), j = (int)(idx - (int64_t)kern * half);
+                I.ktab[idx] = ktab_val(I.form, kern, G.h, j, 0, h2 * (double)j * j);
+            }
         }
     }
     VB_END
@@ -519,13 +564,15 @@ __device__ __forceinline__ double sin_w(const double* st, int M, int j, int k)
     return 2.0 * st[(int)(((int64_t)j * k) % M)];
 }
 
-// One 64 x 64 tile of out = op(A) B for h x h row-major double matrices
-// (op(A) = A or its transpose), k staged through LDS 16 at a time; 256
-// threads, 4 x 4 outputs each.  emit(m, n, value) stores a result.
+// One 64 x 64 tile of out = op(A) B, op(A) [m x k] and B [k x n] row-major
+// double matrices with leading dimensions lda and ldb (op(A) = A, or the
+// transpose of a [k x m] A), k staged through LDS 16 at a time; 256 threads,
+// 4 x 4 outputs each.  emit(m, n, value) stores a result.
 template <bool TA, typename Emit>
-__device__ __forceinline__ void gemm_tile(const double* __restrict__ A, const double* __restrict__ B,
-                                          int h, int tm, int tn, double (*As)[65], double (*Bs)[65],
-                                          Emit emit)
+__device__ __forceinline__ void gemm_tile(const double* __restrict__ A, int lda,
+                                          const double* __restrict__ B, int ldb,
+                                          int mdim, int kdim, int ndim, int tm, int tn,
+                                          double (*As)[65], double (*Bs)[65], Emit emit)
 {
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     double acc[4][4];
@@ -533,17 +580,18 @@ __device__ __forceinline__ void gemm_tile(const double* __restrict__ A, const do
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-    for (int k0 = 0; k0 < h; k0 += 16) {
+    for (int k0 = 0; k0 < kdim; k0 += 16) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int e = tid + q * 256;
             int kk, mm;
             if (TA) { kk = e >> 6; mm = e & 63; } else { kk = e & 15; mm = e >> 4; }
             const int m = tm * 64 + mm, k = k0 + kk;
-            As[kk][mm] = (m < h && k < h) ? (TA ? A[(int64_t)k * h + m] : A[(int64_t)m * h + k]) : 0.0;
+            As[kk][mm] = (m < mdim && k < kdim) ? (TA ? A[(int64_t)k * lda + m] : A[(int64_t)m * lda + k])
+                                                : 0.0;
             const int nk = e >> 6, nn = e & 63;
             const int n = tn * 64 + nn, k2 = k0 + nk;
-            Bs[nk][nn] = (n < h && k2 < h) ? B[(int64_t)k2 * h + n] : 0.0;
+            Bs[nk][nn] = (n < ndim && k2 < kdim) ? B[(int64_t)k2 * ldb + n] : 0.0;
         }
         __syncthreads();
 #pragma unroll
@@ -565,14 +613,15 @@ __device__ __forceinline__ void gemm_tile(const double* __restrict__ A, const do
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int m = tm * 64 + ty * 4 + i, n = tn * 64 + tx * 4 + j;
-            if (m < h && n < h) emit(m, n, acc[i][j]);
+            if (m < mdim && n < ndim) emit(m, n, acc[i][j]);
         }
 }
 
-// First pass.  s = 2: A[kern] = K[kern] C (the row transform of the even
-// kernel grid), by tiled GEMM; s = 1: the whole spectrum
-// K^[kern][k] = sum_j C[j][k] K[kern][j] / M.  Form V's odd table (kern 1)
-// takes the sine matrix in place of C.
+// First pass.  s = 2: A[kern] = K[kern] Cx, the transform along dimension 0
+// of the kernel grid (K[kern] is [half_y][half_x]; the sine matrix in place
+// of Cx for the odd kernel along dimension 0), by tiled GEMM; s = 1: the
+// whole spectrum K^[kern][k] = sum_j C[j][k] K[kern][j] / M (sine sums for
+// form V's odd kernel).
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_spec1(LaunchMap map)
 {
@@ -582,13 +631,14 @@ __global__ __launch_bounds__(256) void k_spec1(LaunchMap map)
         const Geom& G = *I.geom;
         const int M = G.M, half = G.half;
         if (S == 2) {
-            const int nt = (half + 63) / 64;
+            const int nt = (I.half + 63) / 64;         // tile grid of the capacity
             const int kern = lb / (nt * nt), rem = lb - kern * nt * nt;
             const int tm = rem / nt, tn = rem - tm * nt;
-            if (kern < 2) {
-                double* out = I.spec_tmp + (int64_t)kern * half * half;
-                const double* cm = I.ccos + ((I.form == 2 && kern == 1) ? (int64_t)half * half : 0);
-                gemm_tile<false>(I.ktab + (int64_t)kern * half * half, cm, half, tm, tn, As, Bs,
+            const int64_t slot = (int64_t)I.half * I.half;
+            if (kern < n_tables(I)) {
+                double* out = I.spec_tmp + kern * slot;
+                const double* bx = I.ccos + ((I.form == 2 && kern == 1) ? 2 * slot : 0);
+                gemm_tile<false>(I.ktab + kern * slot, half, bx, half, G.half_y, half, half, tm, tn, As, Bs,
                                  [&](int m, int n, double v) { out[(int64_t)m * half + n] = v; });
             }
         } else {
@@ -598,7 +648,7 @@ __global__ __launch_bounds__(256) void k_spec1(LaunchMap map)
                 const double* kt = I.ktab + (int64_t)kern * half;
                 double acc = 0.0;
                 if (I.form == 2 && kern == 1)
-                    for (int j = 0; j < half; ++j) acc += sin_w(I.costab + M, M, j, k) * kt[j];
+                    for (int j = 0; j < half; ++j) acc += sin_w(I.costab + I.M, M, j, k) * kt[j];
                 else
                     for (int j = 0; j < half; ++j) acc += cos_w(I.costab, M, j, k) * kt[j];
                 static_cast<T*>(I.spec)[idx] = (T)(acc / M);
@@ -608,10 +658,9 @@ __global__ __launch_bounds__(256) void k_spec1(LaunchMap map)
     VB_END
 }
 
-// Second pass (s = 2): K^[kern] = A[kern]^T C / M^2, stored [kern][k0][k1],
-// k0, k1 <= M/2.  Form V also stores the transpose of the odd table as
-// table 2: the kernel odd along dimension 1 is the same function with the
-// axes swapped.
+// Second pass (s = 2): K^[kern] = A[kern]^T Cy / (M My), the transform along
+// dimension 1 (the sine matrix of y for form V's odd kernel along dimension
+// 1), stored [kern][k0 < half_x][k1 < half_y] in the element type.
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_spec2(LaunchMap map)
 {
@@ -619,19 +668,17 @@ __global__ __launch_bounds__(256) void k_spec2(LaunchMap map)
     VB_BEGIN_IF_SKIP(map, K_SPEC2, S == 2 && spec_needed(I))
     {
         const Geom& G = *I.geom;
-        const int M = G.M, half = G.half;
-        const int nt = (half + 63) / 64;
+        const int M = G.M, half = G.half, hy = G.half_y;
+        const int nt = (I.half + 63) / 64;
         const int kern = lb / (nt * nt), rem = lb - kern * nt * nt;
         const int tm = rem / nt, tn = rem - tm * nt;
-        if (kern < 2) {
-            T* out = static_cast<T*>(I.spec) + (int64_t)kern * half * half;
-            T* outT = (I.form == 2 && kern == 1) ? out + (int64_t)half * half : nullptr;
-            const double sc = 1.0 / ((double)M * (double)M);
-            gemm_tile<true>(I.spec_tmp + (int64_t)kern * half * half, I.ccos, half, tm, tn, As, Bs,
-                            [&](int m, int n, double v) {
-                                out[(int64_t)m * half + n] = (T)(v * sc);
-                                if (outT) outT[(int64_t)n * half + m] = (T)(v * sc);
-                            });
+        const int64_t slot = (int64_t)I.half * I.half;
+        if (kern < n_tables(I)) {
+            T* out = static_cast<T*>(I.spec) + kern * slot;
+            const double* by = I.ccos + ((I.form == 2 && kern == 2) ? 3 * slot : slot);
+            const double sc = 1.0 / ((double)M * (double)G.My);
+            gemm_tile<true>(I.spec_tmp + kern * slot, half, by, hy, half, hy, hy, tm, tn, As, Bs,
+                            [&](int m, int n, double v) { out[(int64_t)m * hy + n] = (T)(v * sc); });
         }
     }
     VB_END

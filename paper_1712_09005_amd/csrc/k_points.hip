@@ -188,7 +188,39 @@ __device__ __forceinline__ int ladder(int lo)
 // narrower dimension keeps its points inside the node hull); interval count by the
 // policy (paper: max(min, ceil(L)) as in Section 2.5; fixed: constant width);
 // circulant length M from the 2-3-5 ladder with hysteresis, so the tables are
-// rebuilt only when the node count leaves [M/3, M/2].
+// rebuilt only when the node count leaves [M/3, M/2].  With rect set, a
+// narrower second dimension gets its own interval count and FFT length at the
+// same spacing.
+
+// Circulant length of one axis with hysteresis, and its radix plan when it
+// changes.  Returns true if M changed.
+__device__ __forceinline__ bool axis_plan(int nodes, int Mcap, int& Mref, int& half, int& nstages,
+                                          int* radix, int* tw_off)
+{
+    int M = Mref;
+    const int want = ladder(2 * nodes);
+    if (M < 2 * nodes || M > Mcap || want * 3 < M * 2) M = want;
+    if (M > Mcap) M = Mcap;
+    if (M == Mref) return false;
+    int r = M, k = 0, n4 = 0, n3 = 0, n5 = 0;
+    while (r % 4 == 0) { r /= 4; ++n4; }
+    while (r % 3 == 0) { r /= 3; ++n3; }
+    while (r % 5 == 0) { r /= 5; ++n5; }
+    for (int q = 0; q < n4; ++q) radix[k++] = 4;
+    for (int q = 0; q < n3; ++q) radix[k++] = 3;
+    for (int q = 0; q < n5; ++q) radix[k++] = 5;
+    nstages = k;
+    Mref = M;
+    half = M / 2 + 1;
+    int off = 0, ns = 1;
+    for (int q = 0; q < k; ++q) {
+        tw_off[q] = off;
+        off += ns * (radix[q] - 1);
+        ns *= radix[q];
+    }
+    return true;
+}
+
 template <int S>
 __global__ __launch_bounds__(256) void k_geom(LaunchMap map)
 {
@@ -273,49 +305,46 @@ __global__ __launch_bounds__(256) void k_geom(LaunchMap map)
                 G.w = w;
                 G.inv_w = 1.0 / w;
                 G.h = w / I.p;
-                G.n_int = m;
-                G.n = m * I.p;
-                G.n_cells = (S == 2) ? m * m : m;
+                // per-axis interval counts: the square box, or a rectangle of
+                // the same spacing whose narrower axes get their own counts
+                int ma[2] = {m, m};
+                for (int d = 0; d < S; ++d) {
+                    const double Ld = ghi[d] - glo[d];
+                    if (I.rect && S == 2 && Ld < L) {
+                        int md = (int)ceil(Ld / w);
+                        if (md < I.min_int) md = I.min_int;
+                        if (md > m) md = m;
+                        ma[d] = md;
+                    }
+                }
+                G.n_int = ma[0];
+                G.n = ma[0] * I.p;
+                G.n_int_y = (S == 2) ? ma[1] : 1;
+                G.n_y = (S == 2) ? ma[1] * I.p : 1;
+                G.n_cells = (S == 2) ? ma[0] * ma[1] : ma[0];
                 // explicit roundings (no contraction) so the origin is the
                 // correctly rounded value of mid - (m/2) w
-                const double half_side = __dmul_rn(0.5 * m, w);
                 for (int d = 0; d < S; ++d) {
+                    const double half_side = __dmul_rn(0.5 * ma[d], w);
                     G.origin[d] = __dsub_rn(__dmul_rn(0.5, __dadd_rn(glo[d], ghi[d])), half_side);
                     G.centre[d] = __dadd_rn(G.origin[d], half_side);
                 }
                 // power-of-two charge scale: |(y - centre) * qscale| < 1
                 G.qscale = ldexp(1.0, -(ilogb(0.5 * m * w) + 1));
-                // circulant length with hysteresis
-                int M = G.M;
-                const int want = ladder(2 * G.n);
-                if (M < 2 * G.n || M > I.M || want * 3 < M * 2) M = want;
-                if (M > I.M) M = I.M;
-                if (M != G.M) {
-                    int r = M, k = 0, n4 = 0, n3 = 0, n5 = 0;
-                    while (r % 4 == 0) { r /= 4; ++n4; }
-                    while (r % 3 == 0) { r /= 3; ++n3; }
-                    while (r % 5 == 0) { r /= 5; ++n5; }
-                    for (int q = 0; q < n4; ++q) G.radix[k++] = 4;
-                    for (int q = 0; q < n3; ++q) G.radix[k++] = 3;
-                    for (int q = 0; q < n5; ++q) G.radix[k++] = 5;
-                    G.nstages = k;
-                    G.M = M;
-                    G.half = M / 2 + 1;
-                    int off = 0, ns = 1;
-                    for (int q = 0; q < k; ++q) {
-                        G.tw_off[q] = off;
-                        off += ns * (G.radix[q] - 1);
-                        ns *= G.radix[q];
-                    }
+                // circulant lengths with hysteresis, per axis
+                axis_plan(G.n, I.M, G.M, G.half, G.nstages, G.radix, G.tw_off);
+                if (S == 2 &&
+                    axis_plan(G.n_y, I.M, G.My, G.half_y, G.nstages_y, G.radix_y, G.tw_off_y)) {
                     // columns per block: as many as the LDS holds (power of two)
                     const int csz = 2 * ((I.tile_w == 16) ? 4 : 8);
                     int g = I.tile_w;
-                    while (g > 1 && (int64_t)g * lds_stride(M) * csz > I.col_lds) g >>= 1;
+                    while (g > 1 && (int64_t)g * lds_stride(G.My) * csz > I.col_lds) g >>= 1;
                     G.col_group = g;
                 }
-                G.spec_dirty = (G.h != G.spec_h || G.M != G.spec_M) ? 1 : 0;
+                G.spec_dirty = (G.h != G.spec_h || G.M != G.spec_M || (S == 2 && G.My != G.spec_My)) ? 1 : 0;
                 G.spec_h = G.h;
                 G.spec_M = G.M;
+                G.spec_My = G.My;
                 G.pbuf ^= 1;                   // this iteration's sorted order goes here
             }
         }
@@ -349,7 +378,7 @@ __global__ __launch_bounds__(256) void k_key(LaunchMap map)
             const T* Y = static_cast<const T*>(I.Yin);
             T t;
             key = locate<T>(Y[(int64_t)i * S], G.origin[0], G.w, G.n_int, t);
-            if (S == 2) key += G.n_int * locate<T>(Y[(int64_t)i * S + 1], G.origin[1], G.w, G.n_int, t);
+            if (S == 2) key += G.n_int * locate<T>(Y[(int64_t)i * S + 1], G.origin[1], G.w, G.n_int_y, t);
         }
         const int kprev = __shfl_up(key, 1, 64);
         const bool head = (lane == 0) || (kprev != key);
@@ -570,7 +599,7 @@ __global__ __launch_bounds__(256) void k_spread(LaunchMap map)
                 if (NC > 1) q[1 % NC] = (T)qx;
                 if (S == 2) {
                     const T yy = sY[(int64_t)pos * S + 1];
-                    locate<T>(yy, o1, w, n_int, ty);
+                    locate<T>(yy, o1, w, G.n_int_y, ty);
                     qy = ((double)yy - c1) * qs;
                     if (NC > 2) q[2 % NC] = (T)qy;
                 }
@@ -775,7 +804,7 @@ __global__ __launch_bounds__(256) void k_gather(LaunchMap map)
 #pragma unroll
             for (int d = 0; d < S; ++d) {
                 yv[d] = sY[pos * S + d];
-                cl[d] = locate<T>(yv[d], G.origin[d], w, n_int, tl[d]);
+                cl[d] = locate<T>(yv[d], G.origin[d], w, d == 0 ? n_int : G.n_int_y, tl[d]);
             }
             T Lx[P], Ly[P];
             lagrange<T, P>(tl[0], Lx);

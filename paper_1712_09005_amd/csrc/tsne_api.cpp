@@ -71,7 +71,7 @@ struct Layout {
 
 enum Region {
     R_INST, R_PREFIX, R_GEOM, R_SCHED, R_SMALL, R_BOX, R_COUNTS, R_CSTART, R_ISTART, R_SCAN,
-    R_ICELL, R_KEY, R_RANK, R_PERM, R_SY, R_CARRY, R_W, R_X, R_XC, R_V, R_SPEC, R_TW, R_COS,
+    R_ICELL, R_KEY, R_RANK, R_PERM, R_SY, R_CARRY, R_W, R_X, R_XC, R_V, R_SPEC, R_TW, R_TWY, R_COS,
     R_SPECTMP, R_KTAB, R_CCOS, R_R, R_FA, R_FAP, R_SPLIT, R_TOFF, R_EPACK, R_EVAL, R_ZPART, R_KLPART, R_N
 };
 
@@ -108,6 +108,7 @@ tsne_status derive(const tsne_desc* d, Derived& o)
         return TSNE_E_ARG;
     if (d->attr_slabs < 0 || d->attr_slabs > 64) return TSNE_E_ARG;
     if (d->attr_layout < 0 || d->attr_layout > 2) return TSNE_E_ARG;
+    if (d->rect != 0 && d->rect != 1) return TSNE_E_ARG;
 
     o.s = d->s;
     o.p = d->p;
@@ -200,9 +201,11 @@ tsne_status derive(const tsne_desc* d, Derived& o)
         // whole tiles of tile_w / col_group groups each, per potential
         vb[K_FFT_COLS] = o.np * o.ntiles * (o.tile_w / o.col_group);
         vb[K_FFT_IROWS] = cdiv(o.np, 2) * o.n_cap;
-        vb[K_SPEC1] = 2 * cdiv(o.half, 64) * cdiv(o.half, 64);      // 64 x 64 GEMM tiles
+        // kernel tables: K1 and K2, or K1 and the two odd kernels (form V)
+        const int ntab = (d->form == TSNE_FORM_V) ? 3 : 2;
+        vb[K_SPEC1] = ntab * cdiv(o.half, 64) * cdiv(o.half, 64);   // 64 x 64 GEMM tiles
         vb[K_SPEC2] = vb[K_SPEC1];
-        vb[K_SPEC0] = cdiv(std::max<int64_t>(o.M, (int64_t)2 * o.half * o.half), 256);
+        vb[K_SPEC0] = cdiv(std::max<int64_t>(o.M, (int64_t)ntab * o.half * o.half), 256);
     } else {
         vb[K_FFT_1D] = o.np;
         vb[K_SPEC1] = cdiv(2 * o.half, 256);
@@ -249,12 +252,15 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     if (d->s == 2) {
         sz[R_X] = (size_t)csz * o.nc * o.ntiles * o.n_cap * o.tile_w;
         sz[R_XC] = (size_t)csz * o.np * o.ntiles * o.n_cap * o.tile_w;
-        // form V: a third spectrum (the transposed odd table) and the sine matrix
+        // one [half][half] slot per kernel table (form V: a third, the odd
+        // kernel along dimension 1); cosine matrices of both axes, and for
+        // form V their sine matrices
         const size_t vf = (d->form == TSNE_FORM_V) ? 1 : 0;
-        sz[R_SPEC] = (size_t)o.tsz * (2 + vf) * o.half * o.half;
-        sz[R_SPECTMP] = sizeof(double) * 2 * (size_t)o.half * o.half;
-        sz[R_KTAB] = sizeof(double) * 2 * (size_t)o.half * o.half;
-        sz[R_CCOS] = sizeof(double) * (1 + vf) * (size_t)o.half * o.half;
+        const size_t slot = (size_t)o.half * o.half;
+        sz[R_SPEC] = (size_t)o.tsz * (2 + vf) * slot;
+        sz[R_SPECTMP] = sizeof(double) * (2 + vf) * slot;
+        sz[R_KTAB] = sizeof(double) * (2 + vf) * slot;
+        sz[R_CCOS] = sizeof(double) * (2 + 2 * vf) * slot;
     } else {
         sz[R_CCOS] = 0;
         sz[R_X] = 0;
@@ -265,6 +271,7 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     }
     sz[R_V] = (size_t)o.tsz * o.np * grid;
     sz[R_TW] = (size_t)csz * o.M;
+    sz[R_TWY] = (d->s == 2) ? (size_t)csz * o.M : 0;
     sz[R_COS] = sizeof(double) * 2 * o.M;               // cos, then sin
     sz[R_R] = (size_t)o.tsz * n * d->s;
     sz[R_FA] = (size_t)o.tsz * n * d->s;
@@ -462,6 +469,7 @@ tsne_status tsne_plan_create(const tsne_desc* desc, void* workspace, size_t byte
     h.s = desc->s;
     h.p = desc->p;
     h.form = desc->form;
+    h.rect = (desc->s == 2) ? desc->rect : 0;
     h.nc = o.nc;
     h.np = o.np;
     h.policy = desc->policy;
@@ -502,6 +510,7 @@ tsne_status tsne_plan_create(const tsne_desc* desc, void* workspace, size_t byte
     h.V = b + off[R_V];
     h.spec = b + off[R_SPEC];
     h.tw = b + off[R_TW];
+    h.twy = b + off[R_TWY];
     h.costab = reinterpret_cast<double*>(b + off[R_COS]);
     h.spec_tmp = reinterpret_cast<double*>(b + off[R_SPECTMP]);
     h.ktab = reinterpret_cast<double*>(b + off[R_KTAB]);
@@ -813,6 +822,9 @@ tsne_status tsne_query(tsne_plan* pl, tsne_stats* out)
     out->w_int = g.w;
     out->box_side = g.side;
     out->Z = g.Z;
+    out->n_int_y = (pl->d.s == 2) ? g.n_int_y : 1;
+    out->n_nodes_y = (pl->d.s == 2) ? g.n_y : 1;
+    out->fft_len_y = (pl->d.s == 2) ? g.My : 0;
     return TSNE_OK;
 }
 

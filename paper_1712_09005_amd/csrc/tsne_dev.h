@@ -50,13 +50,22 @@ struct Geom {
     int perm_valid;    // a sorted order from an earlier iteration exists
     int spec_dirty;    // spacing or FFT length changed: tables must be rebuilt
     double spec_h;     // spacing the current spectra were built for
-    int spec_M;        // FFT length the current tables were built for
+    int spec_M;        // FFT lengths the current tables were built for
+    int spec_My;
+    // first axis (x, dimension 0): rows of the grid
     int M;             // circulant length of this iteration (even, 2-3-5 smooth, >= 2n)
     int half;          // M / 2 + 1
     int nstages;
     int radix[kMaxStages];
     int tw_off[kMaxStages];   // offset of each stage's twiddle table in tw
-    int col_group;     // FFT columns per block this iteration
+    // second axis (y, dimension 1; s = 2): columns of the grid.  Equal to the
+    // first axis' values for the square box.
+    int n_int_y;       // intervals along y
+    int n_y;           // nodes along y
+    int My, half_y, nstages_y;
+    int radix_y[kMaxStages];
+    int tw_off_y[kMaxStages];  // offsets in twy
+    int col_group;     // FFT columns per block this iteration (for My)
 };
 
 // LDS index of element i of a transform and the stride between the
@@ -76,7 +85,7 @@ struct Inst {
     // ---- configuration (fixed for the plan)
     int64_t n;
     int64_t nnz;
-    int s, p, form, nc, np, policy;
+    int s, p, form, nc, np, policy, rect;
     int min_int, max_int, n_cap, M, half;      // capacity: largest M, M/2 + 1
     int ncell_cap, items_cap, kpts, lpr;
     int col_group, tile_w, ntiles;              // FFT column kernel grouping
@@ -118,12 +127,16 @@ struct Inst {
     void* X;               // [nc][ntiles][n_cap][tile_w] complex (row spectra)
     void* Xc;              // [np][ntiles][n_cap][tile_w] complex (after columns)
     void* V;               // [np][n_cap][n_cap] or [np][n_cap]
-    void* spec;            // [2][half][half] (s = 2) or [2][half], pre-scaled
+    void* spec;            // s = 2: [K][half_x][half_y] in slots of the capacity's
+                           // half^2; s = 1: [2][half]; pre-scaled
     void* tw;              // [M] stage twiddle tables of this iteration's M (complex)
-    double* costab;        // [M] cos(2 pi k / M) in double
-    double* spec_tmp;      // [2][half][half] first cosine pass (double)
-    double* ktab;          // [2][half][half] kernel values on the lag grid (double)
-    double* ccos;          // [half][half] weighted cosine matrix (double)
+    void* twy;             // [M] the same for the second axis' length My
+    double* costab;        // [2][M] cos and sin(2 pi k / M) in double (s = 1)
+    // s = 2 tables, each in a [half][half] slot of the capacity's half:
+    double* spec_tmp;      // [K][..] first transform pass (double)
+    double* ktab;          // [K][..] kernel values on the lag grid [j1][j0] (double)
+    double* ccos;          // [2 or 4][..] weighted cosine matrices of x and y, then
+                           // (form V) the sine matrices of x and y (double)
     void* R;               // [n][s] unnormalised repulsion numerators
     void* Fa_ws;           // [n][s] attraction (workspace copy for the step)
     void* Fap;             // [slabs][n][s] attraction partials per column slab

@@ -39,7 +39,8 @@ class Desc(ctypes.Structure):
                 ("min_intervals", ctypes.c_int32), ("max_intervals", ctypes.c_int32),
                 ("interval_width", ctypes.c_double), ("nnz", ctypes.c_int64),
                 ("lanes_per_row", ctypes.c_int32), ("points_per_lane", ctypes.c_int32),
-                ("attr_slabs", ctypes.c_int32), ("attr_layout", ctypes.c_int32)]
+                ("attr_slabs", ctypes.c_int32), ("attr_layout", ctypes.c_int32),
+                ("rect", ctypes.c_int32)]
 
 
 class Sched(ctypes.Structure):
@@ -55,7 +56,9 @@ class Stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("n_int", ctypes.c_int32), ("n_nodes", ctypes.c_int32),
                 ("fft_len", ctypes.c_int32), ("iter", ctypes.c_int32),
                 ("max_intervals", ctypes.c_int32), ("origin", ctypes.c_double * 2),
-                ("w_int", ctypes.c_double), ("box_side", ctypes.c_double), ("Z", ctypes.c_double)]
+                ("w_int", ctypes.c_double), ("box_side", ctypes.c_double), ("Z", ctypes.c_double),
+                ("n_int_y", ctypes.c_int32), ("n_nodes_y", ctypes.c_int32),
+                ("fft_len_y", ctypes.c_int32)]
 
 
 @dataclass
@@ -147,12 +150,12 @@ def _dt(dtype) -> int:
 
 def make_desc(n, s, dtype=torch.float32, p=5, policy="fixed", form="A", min_intervals=1,
               max_intervals=512, interval_width=0.75, nnz=0, lanes_per_row=0,
-              points_per_lane=0, attr_slabs=0, attr_layout=0) -> Desc:
+              points_per_lane=0, attr_slabs=0, attr_layout=0, rect=False) -> Desc:
     pol = GRID_PAPER if policy in ("paper", GRID_PAPER) else GRID_FIXED
     frm = form_code(form)
     return Desc(int(n), int(s), _dt(dtype), int(p), pol, frm, int(min_intervals),
                 int(max_intervals), float(interval_width), int(nnz), int(lanes_per_row),
-                int(points_per_lane), int(attr_slabs), int(attr_layout))
+                int(points_per_lane), int(attr_slabs), int(attr_layout), int(bool(rect)))
 
 
 def workspace_bytes(desc: Desc) -> int:
@@ -171,10 +174,10 @@ class Plan:
     def __init__(self, n, s, dtype=torch.float32, p=5, policy="fixed", form="A",
                  min_intervals=1, max_intervals=512, interval_width=0.75, nnz=0,
                  lanes_per_row=0, points_per_lane=0, attr_slabs=0, attr_layout=0, device="cuda",
-                 stream=None):
+                 stream=None, rect=False):
         self.desc = make_desc(n, s, dtype, p, policy, form, min_intervals, max_intervals,
                               interval_width, nnz, lanes_per_row, points_per_lane, attr_slabs,
-                              attr_layout)
+                              attr_layout, rect)
         self.n, self.s = int(n), int(s)
         self.dtype = torch.float32 if self.desc.dtype == F32 else torch.float64
         self.device = torch.device(device)
@@ -286,7 +289,8 @@ class Plan:
         return dict(status=st.status, n_int=st.n_int, n_nodes=st.n_nodes, fft_len=st.fft_len,
                     iter=st.iter, max_intervals=st.max_intervals,
                     origin=(st.origin[0], st.origin[1]), w_int=st.w_int,
-                    box_side=st.box_side, Z=st.Z)
+                    box_side=st.box_side, Z=st.Z, n_int_y=st.n_int_y, n_nodes_y=st.n_nodes_y,
+                    fft_len_y=st.fft_len_y)
 
     def export(self, what: int):
         """Internal array of the last iteration as a flat host buffer (bytes)."""

@@ -133,6 +133,67 @@ def test_repulsion_form_v_2d(T, dtype, tol, n):
         assert rel(F[:, d], r["F"][:, d]) < tol
 
 
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-9), (torch.float32, None)])
+@pytest.mark.parametrize("form", ["A", "B", "V"])
+@pytest.mark.parametrize("wide", [0, 1])
+def test_rect_box_vs_oracle(T, dtype, tol, form, wide):
+    """Rectangular box (per-axis interval counts and FFT lengths at equal
+    spacing) on a flat cloud, wide along x or along y: geometry exactly as
+    the oracle's, forces and Z against the oracle's rectangular scheme."""
+    print("case: rect box %s form %s wide axis %d" % (dtype, form, wide), flush=True)
+    Y = inputs.mixture_embedding(3001, 2, 8, -30, 30, 1.5, seed=4)
+    Y[:, 1 - wide] *= 0.25                                     # the other axis a quarter as wide
+    n = Y.shape[0]
+    plan = T.Plan(n, 2, dtype, p=5, policy="fixed", interval_width=0.75, max_intervals=128,
+                  form=form, rect=True, device=DEV)
+    Yt = torch.from_numpy(np.ascontiguousarray(Y)).to(DEV, dtype)
+    F, Z = plan.repulsive(Yt)
+    torch.cuda.synchronize()
+    st = plan.query()
+    assert st["status"] == 0, st
+    Yd = Y.astype(np.float64)
+    o, w, m = oracle.geometry(Yd, "fixed", 1, 0.75, rect=True)
+    assert (st["n_int"], st["n_int_y"]) == m and st["w_int"] == w
+    np.testing.assert_array_equal(st["origin"], o)
+    narrow = st["fft_len_y"] if wide == 0 else st["fft_len"]
+    wide_len = st["fft_len"] if wide == 0 else st["fft_len_y"]
+    assert narrow < wide_len
+    code = {"A": oracle.FORM_A, "B": oracle.FORM_B, "V": oracle.FORM_V}[form]
+    r = oracle.interp_rep(Yd, o, w, m, 5, code)
+    F = F.cpu().numpy().astype(np.float64)
+    e, ez = rel(F, r["F"]), abs(float(Z.item()) - r["Z"]) / r["Z"]
+    print("  n_int %s, FFT %d x %d: rel err F %.2e Z %.2e" % (m, st["fft_len"], st["fft_len_y"], e, ez))
+    if tol is None:
+        tol = 1e-5 if form == "V" else 1e-4
+    assert e < tol and ez < tol
+    Fd, _ = oracle.direct_rep(Yd)
+    assert rel(F, Fd) < 1e-3
+
+
+def test_rect_on_square_box_is_the_square_path(T):
+    """With equal extents on both axes the rectangular box is the square box:
+    same geometry and FFT lengths, and the same forces up to the summation
+    order inside a cell (the counting sort ranks points with atomics, so two
+    runs of either path differ at rounding level; FP64 here)."""
+    print("case: rect on a square box", flush=True)
+    Y = inputs.mixture_embedding(2000, 2, 6, -20, 20, 1.5, seed=8)
+    Y[0] = [Y[:, 0].min(), Y[:, 1].min()]
+    side = np.ptp(Y, axis=0).max()
+    Y[1] = Y[0] + side                                          # both axes exactly `side` wide
+    outs = []
+    for rect in (False, True):
+        plan = T.Plan(Y.shape[0], 2, torch.float64, p=5, interval_width=0.75, max_intervals=128,
+                      form="V", rect=rect, device=DEV)
+        F, Z = plan.repulsive(torch.from_numpy(np.ascontiguousarray(Y)).to(DEV, torch.float64))
+        torch.cuda.synchronize()
+        st = plan.query()
+        assert st["n_int"] == st["n_int_y"] and st["fft_len"] == st["fft_len_y"]
+        outs.append((F.cpu().numpy(), float(Z.item()), st))
+    assert outs[0][2]["n_int"] == outs[1][2]["n_int"] and outs[0][2]["origin"] == outs[1][2]["origin"]
+    assert rel(outs[1][0], outs[0][0]) < 1e-13
+    assert abs(outs[1][1] - outs[0][1]) < 1e-13 * outs[0][1]
+
+
 @pytest.mark.parametrize("form", ["A", "V"])
 @pytest.mark.parametrize("min_int", [1, 6])
 def test_small_box_fixed_policy(T, form, min_int):
