@@ -31,8 +31,9 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 // Each lane sums its few terms in the element type; the row's lanes are
 // reduced in double.  Optionally the columns are split into slabs (virtual
 // blocks run slab-major, each row's slab range from the split table) and each
-// slab writes a partial force.
-template <typename T, int S, int LPR, int U, bool GATED>
+// slab writes a partial force.  PK: the (column, value) pairs come packed in
+// one 8-byte array (FP32), one load per non-zero.
+template <typename T, int S, int LPR, int U, bool GATED, bool PK>
 __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
 {
     constexpr int RPB = 256 / LPR;
@@ -72,8 +73,14 @@ __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
                 for (int u = 0; u < U; ++u) {
                     const int64_t k = k0 + (int64_t)u * LPR;
                     const bool ok = k < e;
-                    jj[u] = ok ? col[k] : i;
-                    pp[u] = ok ? val[k] : (T)0;
+                    if constexpr (PK) {
+                        const uint2 q = ok ? static_cast<const uint2*>(I.cv)[k] : make_uint2((unsigned)i, 0u);
+                        jj[u] = (int)q.x;
+                        pp[u] = (T)__uint_as_float(q.y);
+                    } else {
+                        jj[u] = ok ? col[k] : i;
+                        pp[u] = ok ? val[k] : (T)0;
+                    }
                 }
                 V yj[U];
 #pragma unroll
@@ -312,21 +319,22 @@ template <typename T, int S>
 static hipError_t launch_attr(int kind, const Cfg& c, const LaunchMap& map, const Launch& l,
                               hipStream_t st)
 {
+    constexpr bool PK = sizeof(T) == 4;   // FP32 plans bind P packed (the CSR layout)
     dim3 g(l.grid), b(l.block);
     switch (kind) {
     case K_ATTR:
-        if (c.lpr == 4) hipLaunchKernelGGL((k_attr<T, S, 4, 6, true>), g, b, 0, st, map);
-        else if (c.lpr == 8) hipLaunchKernelGGL((k_attr<T, S, 8, 4, true>), g, b, 0, st, map);
-        else if (c.lpr == 16) hipLaunchKernelGGL((k_attr<T, S, 16, 3, true>), g, b, 0, st, map);
-        else if (c.lpr == 32) hipLaunchKernelGGL((k_attr<T, S, 32, 3, true>), g, b, 0, st, map);
-        else hipLaunchKernelGGL((k_attr<T, S, 64, 2, true>), g, b, 0, st, map);
+        if (c.lpr == 4) hipLaunchKernelGGL((k_attr<T, S, 4, 6, true, PK>), g, b, 0, st, map);
+        else if (c.lpr == 8) hipLaunchKernelGGL((k_attr<T, S, 8, 4, true, PK>), g, b, 0, st, map);
+        else if (c.lpr == 16) hipLaunchKernelGGL((k_attr<T, S, 16, 3, true, PK>), g, b, 0, st, map);
+        else if (c.lpr == 32) hipLaunchKernelGGL((k_attr<T, S, 32, 3, true, PK>), g, b, 0, st, map);
+        else hipLaunchKernelGGL((k_attr<T, S, 64, 2, true, PK>), g, b, 0, st, map);
         break;
     case K_ATTR_ALL:
-        if (c.lpr == 4) hipLaunchKernelGGL((k_attr<T, S, 4, 6, false>), g, b, 0, st, map);
-        else if (c.lpr == 8) hipLaunchKernelGGL((k_attr<T, S, 8, 4, false>), g, b, 0, st, map);
-        else if (c.lpr == 16) hipLaunchKernelGGL((k_attr<T, S, 16, 3, false>), g, b, 0, st, map);
-        else if (c.lpr == 32) hipLaunchKernelGGL((k_attr<T, S, 32, 3, false>), g, b, 0, st, map);
-        else hipLaunchKernelGGL((k_attr<T, S, 64, 2, false>), g, b, 0, st, map);
+        if (c.lpr == 4) hipLaunchKernelGGL((k_attr<T, S, 4, 6, false, PK>), g, b, 0, st, map);
+        else if (c.lpr == 8) hipLaunchKernelGGL((k_attr<T, S, 8, 4, false, PK>), g, b, 0, st, map);
+        else if (c.lpr == 16) hipLaunchKernelGGL((k_attr<T, S, 16, 3, false, PK>), g, b, 0, st, map);
+        else if (c.lpr == 32) hipLaunchKernelGGL((k_attr<T, S, 32, 3, false, PK>), g, b, 0, st, map);
+        else hipLaunchKernelGGL((k_attr<T, S, 64, 2, false, PK>), g, b, 0, st, map);
         break;
     case K_ASUM: hipLaunchKernelGGL((k_asum<T, S>), g, b, 0, st, map); break;
     case K_KL: hipLaunchKernelGGL((k_kl<T, S>), g, b, 0, st, map); break;

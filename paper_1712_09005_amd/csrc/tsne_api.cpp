@@ -71,7 +71,7 @@ struct Layout {
 
 enum Region {
     R_INST, R_PREFIX, R_GEOM, R_SCHED, R_SMALL, R_BOX, R_COUNTS, R_CSTART, R_ISTART, R_SCAN,
-    R_ICELL, R_KEY, R_RANK, R_PERM, R_SY, R_CARRY, R_W, R_X, R_XC, R_V, R_SPEC, R_TW, R_TWY, R_COS,
+    R_ICELL, R_KEY, R_RANK, R_PERM, R_SY, R_CARRY, R_W, R_X, R_XC, R_V, R_SPEC, R_TW, R_TWY, R_COS, R_CV,
     R_SPECTMP, R_KTAB, R_CCOS, R_R, R_FA, R_FAP, R_SPLIT, R_TOFF, R_EPACK, R_EVAL, R_ZPART, R_KLPART, R_N
 };
 
@@ -278,6 +278,9 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     sz[R_FAP] = (o.slabs > 1) ? (size_t)o.tsz * n * d->s * o.slabs : 0;
     sz[R_SPLIT] = (o.slabs > 1) ? sizeof(int) * (size_t)(o.slabs - 1) * n : 0;
     sz[R_TOFF] = o.tiled ? sizeof(int64_t) * ((size_t)o.tile_ni * o.tile_nj + 1) : 0;
+    // FP32 CSR rows: column and value of each non-zero packed into 8 bytes, so
+    // the attraction streams one vector load per non-zero instead of two
+    sz[R_CV] = (d->dtype == TSNE_F32 && !o.tiled && d->nnz > 0) ? (size_t)8 * d->nnz : 0;
     sz[R_EPACK] = o.tiled ? sizeof(uint32_t) * (size_t)d->nnz : 0;
     sz[R_EVAL] = o.tiled ? (size_t)o.tsz * d->nnz : 0;
     sz[R_ZPART] = sizeof(double) * o.nb_gather;
@@ -531,6 +534,7 @@ tsne_status tsne_plan_create(const tsne_desc* desc, void* workspace, size_t byte
     h.tile_ni = o.tile_ni;
     h.tile_nj = o.tile_nj;
     h.toff = reinterpret_cast<const int64_t*>(b + off[R_TOFF]);
+    h.cv = (off[R_CV + 1] > off[R_CV]) ? (const void*)(b + off[R_CV]) : nullptr;
     h.epack = reinterpret_cast<const uint32_t*>(b + off[R_EPACK]);
     h.eval = b + off[R_EVAL];
     h.nb_box = o.nb_box;
@@ -648,6 +652,21 @@ tsne_status tsne_bind_P(tsne_plan* pl, const int64_t* row_ptr, const int32_t* co
                 !hip_ok(hipMemcpy(const_cast<uint32_t*>(pl->h.epack), pack.data(),
                                   pack.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) ||
                 !hip_ok(hipMemcpy(const_cast<void*>(pl->h.eval), vt.data(), vt.size(),
+                                  hipMemcpyHostToDevice)))
+                return TSNE_E_HIP;
+        }
+        // FP32 CSR: (column, value) pairs in one array
+        if (pl->h.cv) {
+            const int64_t nnz = pl->d.nnz;
+            std::vector<uint32_t> cvh(2 * (size_t)nnz);
+            std::vector<float> vf(nnz);
+            if (!hip_ok(hipMemcpy(vf.data(), val, sizeof(float) * nnz, hipMemcpyDeviceToHost)))
+                return TSNE_E_HIP;
+            for (int64_t k = 0; k < nnz; ++k) {
+                cvh[2 * k] = (uint32_t)cc[k];
+                std::memcpy(&cvh[2 * k + 1], &vf[k], sizeof(float));
+            }
+            if (!hip_ok(hipMemcpy(const_cast<void*>(pl->h.cv), cvh.data(), cvh.size() * sizeof(uint32_t),
                                   hipMemcpyHostToDevice)))
                 return TSNE_E_HIP;
         }

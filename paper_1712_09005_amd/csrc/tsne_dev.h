@@ -105,6 +105,7 @@ struct Inst {
     const int64_t* row_ptr;
     const int32_t* col;
     const void* val;
+    const void* cv;        // FP32 CSR: [nnz] (column, value bits) pairs packed at bind time
 
     // ---- workspace regions
     Geom* geom;
