@@ -313,6 +313,26 @@ __global__ __launch_bounds__(256) void k_klsum(LaunchMap map)
     VB_END
 }
 
+// ---------------------------------------------------------------- packing
+
+// (column, value bits) pairs of an FP32 CSR, for the packed attraction.
+__global__ __launch_bounds__(256) void k_pack_cv(const int32_t* __restrict__ col,
+                                                 const float* __restrict__ val, uint2* __restrict__ cv,
+                                                 int64_t nnz)
+{
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * 256)
+        cv[k] = make_uint2((unsigned)col[k], __float_as_uint(val[k]));
+}
+
+hipError_t launch_pack_cv(const int32_t* col, const float* val, void* cv, int64_t nnz, hipStream_t st)
+{
+    if (nnz <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((nnz + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_pack_cv, dim3((unsigned)blocks), dim3(256), 0, st, col, val,
+                       static_cast<uint2*>(cv), nnz);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- dispatch
 
 template <typename T, int S>

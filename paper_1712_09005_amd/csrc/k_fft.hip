@@ -164,7 +164,7 @@ template <typename T>
 __device__ __forceinline__ void block_fft(cplx<T>* buf, int G, const Inst& I, const Geom& Gm,
                                           bool yaxis = false)
 {
-    const cplx<T>* tw = static_cast<const cplx<T>*>(yaxis ? I.twy : I.tw);
+    const cplx<T>* tw = static_cast<const cplx<T>*>((yaxis && Gm.My != Gm.M) ? I.twy : I.tw);
     const int M = yaxis ? Gm.My : Gm.M, PM = lds_stride(M);
     const int nst = yaxis ? Gm.nstages_y : Gm.nstages;
     const int* radix = yaxis ? Gm.radix_y : Gm.radix;
@@ -506,7 +506,8 @@ __global__ __launch_bounds__(256) void k_spec0(LaunchMap map)
         if (S == 2) {
             const int My = G.My, hy = G.half_y;
             const int64_t slot = (int64_t)I.half * I.half;
-            if (idx < My - 1) stage_twiddle<T>(idx, My, G.nstages_y, G.radix_y, G.tw_off_y, I.twy);
+            const bool same = (My == M);       // the second axis reuses the first's tables
+            if (!same && idx < My - 1) stage_twiddle<T>(idx, My, G.nstages_y, G.radix_y, G.tw_off_y, I.twy);
             // cosine (and form V sine) matrices: x at slots 0 and 2, y at 1 and 3
             if (idx < (int64_t)half * half) {
                 const int j = (int)(idx / half), k = (int)(idx - (int64_t)j * half);
@@ -515,7 +516,7 @@ __global__ __launch_bounds__(256) void k_spec0(LaunchMap map)
                 I.ccos[idx] = c;
                 if (I.form == 2) I.ccos[2 * slot + idx] = sn;
             }
-            if (idx < (int64_t)hy * hy) {
+            if (!same && idx < (int64_t)hy * hy) {
                 const int j = (int)(idx / hy), k = (int)(idx - (int64_t)j * hy);
                 double c, sn;
                 cs_entry(My, j, k, c, sn);
@@ -631,9 +632,11 @@ __global__ __launch_bounds__(256) void k_spec1(LaunchMap map)
         const Geom& G = *I.geom;
         const int M = G.M, half = G.half;
         if (S == 2) {
-            const int nt = (I.half + 63) / 64;         // tile grid of the capacity
-            const int kern = lb / (nt * nt), rem = lb - kern * nt * nt;
-            const int tm = rem / nt, tn = rem - tm * nt;
+            // tiles of this iteration's [half_y x half] products (the launch
+            // covers the capacity's; the rest exit at once)
+            const int ntm = (G.half_y + 63) / 64, ntn = (half + 63) / 64;
+            const int kern = lb / (ntm * ntn), rem = lb - kern * ntm * ntn;
+            const int tm = rem / ntn, tn = rem - tm * ntn;
             const int64_t slot = (int64_t)I.half * I.half;
             if (kern < n_tables(I)) {
                 double* out = I.spec_tmp + kern * slot;
@@ -669,13 +672,15 @@ __global__ __launch_bounds__(256) void k_spec2(LaunchMap map)
     {
         const Geom& G = *I.geom;
         const int M = G.M, half = G.half, hy = G.half_y;
-        const int nt = (I.half + 63) / 64;
-        const int kern = lb / (nt * nt), rem = lb - kern * nt * nt;
-        const int tm = rem / nt, tn = rem - tm * nt;
+        const int ntm = (half + 63) / 64, ntn = (hy + 63) / 64;   // this iteration's tiles
+        const int kern = lb / (ntm * ntn), rem = lb - kern * ntm * ntn;
+        const int tm = rem / ntn, tn = rem - tm * ntn;
         const int64_t slot = (int64_t)I.half * I.half;
         if (kern < n_tables(I)) {
             T* out = static_cast<T*>(I.spec) + kern * slot;
-            const double* by = I.ccos + ((I.form == 2 && kern == 2) ? 3 * slot : slot);
+            // the second axis' matrices; the first axis' when the lengths agree
+            const int64_t ys = (G.My == M) ? 0 : slot;
+            const double* by = I.ccos + ((I.form == 2 && kern == 2) ? 2 * slot + ys : ys);
             const double sc = 1.0 / ((double)M * (double)G.My);
             gemm_tile<true>(I.spec_tmp + kern * slot, half, by, hy, half, hy, hy, tm, tn, As, Bs,
                             [&](int m, int n, double v) { out[(int64_t)m * hy + n] = (T)(v * sc); });

@@ -48,6 +48,7 @@ struct Launch {
 };
 
 hipError_t launch_set_args(Inst* inst, const CallArgs& a, hipStream_t st);
+hipError_t launch_pack_cv(const int32_t* col, const float* val, void* cv, int64_t nnz, hipStream_t st);
 hipError_t launch_kind(int kind, const Cfg& c, const LaunchMap& map, const Launch& l,
                        hipStream_t st);
 

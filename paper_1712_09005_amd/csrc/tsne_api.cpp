@@ -655,21 +655,11 @@ tsne_status tsne_bind_P(tsne_plan* pl, const int64_t* row_ptr, const int32_t* co
                                   hipMemcpyHostToDevice)))
                 return TSNE_E_HIP;
         }
-        // FP32 CSR: (column, value) pairs in one array
-        if (pl->h.cv) {
-            const int64_t nnz = pl->d.nnz;
-            std::vector<uint32_t> cvh(2 * (size_t)nnz);
-            std::vector<float> vf(nnz);
-            if (!hip_ok(hipMemcpy(vf.data(), val, sizeof(float) * nnz, hipMemcpyDeviceToHost)))
-                return TSNE_E_HIP;
-            for (int64_t k = 0; k < nnz; ++k) {
-                cvh[2 * k] = (uint32_t)cc[k];
-                std::memcpy(&cvh[2 * k + 1], &vf[k], sizeof(float));
-            }
-            if (!hip_ok(hipMemcpy(const_cast<void*>(pl->h.cv), cvh.data(), cvh.size() * sizeof(uint32_t),
-                                  hipMemcpyHostToDevice)))
-                return TSNE_E_HIP;
-        }
+        // FP32 CSR: (column, value) pairs in one array, packed on the device
+        if (pl->h.cv &&
+            !hip_ok(launch_pack_cv(col, static_cast<const float*>(val), const_cast<void*>(pl->h.cv),
+                                   pl->d.nnz, pl->st)))
+            return TSNE_E_HIP;
     }
     CallArgs a = no_args();
     a.set_P = 1;
