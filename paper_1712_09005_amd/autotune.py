@@ -78,20 +78,23 @@ def _store(cache, key, value):
     os.replace(tmp, cache)
 
 
-def time_launches(fn, stream, reps=15, warm=2) -> float:
-    """Median seconds of ``fn()`` over ``reps`` launches, by HIP events
-    recorded on ``stream`` (the stream the library enqueues on)."""
+def time_launches(fn, stream, reps=15, warm=2, inner=5) -> float:
+    """Seconds per ``fn()``: the median over ``reps`` groups of ``inner``
+    back-to-back calls, each group bracketed by HIP events recorded on
+    ``stream`` (the stream the library enqueues on).  Grouping hides the host
+    time between calls, which a single bracketed call would count."""
     for _ in range(warm):
         fn()
     ts = []
-    for _ in range(reps):
+    for _ in range(max(1, reps // inner + 2)):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        fn()
+        for _ in range(inner):
+            fn()
         e1.record(stream)
         e1.synchronize()
-        ts.append(e0.elapsed_time(e1) / 1e3)
+        ts.append(e0.elapsed_time(e1) / 1e3 / inner)
     return statistics.median(ts)
 
 

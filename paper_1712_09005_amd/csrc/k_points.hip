@@ -198,6 +198,10 @@ __device__ __forceinline__ bool axis_plan(int nodes, int Mcap, int& Mref, int& h
                                           int* radix, int* tw_off)
 {
     int M = Mref;
+    // keep M while 2n <= M <= 3n: the ladder length for 2n is then at least
+    // 2M/3, so the hysteresis test below would keep it (and the ladder
+    // search, a few microseconds on one lane, is skipped)
+    if (M >= 2 * nodes && M <= Mcap && M <= 3 * nodes) return false;
     const int want = ladder(2 * nodes);
     if (M < 2 * nodes || M > Mcap || want * 3 < M * 2) M = want;
     if (M > Mcap) M = Mcap;
