@@ -32,7 +32,7 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 // reduced in double.  Optionally the columns are split into slabs (virtual
 // blocks run slab-major, each row's slab range from the split table) and each
 // slab writes a partial force.  PK: the (column, value) pairs come packed in
-// one 8-byte array (FP32), one load per non-zero.
+// one 8-byte array (FP32), loaded two at a time.
 template <typename T, int S, int LPR, int U, bool GATED, bool PK>
 __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
 {
@@ -66,6 +66,40 @@ __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
             const int64_t b = (slab == 0) ? I.row_ptr[i] : (int64_t)I.split[(int64_t)(slab - 1) * n + i];
             const int64_t e = (slab == I.slabs - 1) ? I.row_ptr[i + 1]
                                                      : (int64_t)I.split[(int64_t)slab * n + i];
+            if constexpr (PK) {
+                // two (column, value) pairs per 16-byte load: lane `sub` takes
+                // the aligned pair couples q0 + v LPR, each covering entries
+                // 2q and 2q + 1 (entries outside [b, e) are masked)
+                constexpr int UH = (U + 1) / 2;
+                const uint4* cv4 = static_cast<const uint4*>(I.cv);
+                for (int64_t q0 = (b >> 1) + sub; 2 * q0 < e; q0 += (int64_t)LPR * UH) {
+                    int jj[2 * UH];
+                    T pp[2 * UH];
+#pragma unroll
+                    for (int v = 0; v < UH; ++v) {
+                        const int64_t q = q0 + (int64_t)v * LPR;
+                        const bool any = 2 * q < e;
+                        const uint4 w = any ? cv4[q] : make_uint4((unsigned)i, 0u, (unsigned)i, 0u);
+                        const bool ok0 = any && 2 * q >= b, ok1 = 2 * q + 1 < e;
+                        jj[2 * v] = ok0 ? (int)w.x : i;
+                        pp[2 * v] = ok0 ? (T)__uint_as_float(w.y) : (T)0;
+                        jj[2 * v + 1] = ok1 ? (int)w.z : i;
+                        pp[2 * v + 1] = ok1 ? (T)__uint_as_float(w.w) : (T)0;
+                    }
+                    V yj[2 * UH];
+#pragma unroll
+                    for (int u = 0; u < 2 * UH; ++u) yj[u] = Y[jj[u]];
+#pragma unroll
+                    for (int u = 0; u < 2 * UH; ++u) {
+                        T d0, d1 = (T)0;
+                        if constexpr (S == 2) { d0 = yi0 - yj[u].x; d1 = yi1 - yj[u].y; }
+                        else { d0 = yi0 - yj[u]; }
+                        const T wgt = pp[u] * recip((T)1 + d0 * d0 + d1 * d1);
+                        a0 += wgt * d0;
+                        if (S == 2) a1 += wgt * d1;
+                    }
+                }
+            } else {
             for (int64_t k0 = b + sub; k0 < e; k0 += (int64_t)LPR * U) {
                 int jj[U];
                 T pp[U];
@@ -73,14 +107,8 @@ __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
                 for (int u = 0; u < U; ++u) {
                     const int64_t k = k0 + (int64_t)u * LPR;
                     const bool ok = k < e;
-                    if constexpr (PK) {
-                        const uint2 q = ok ? static_cast<const uint2*>(I.cv)[k] : make_uint2((unsigned)i, 0u);
-                        jj[u] = (int)q.x;
-                        pp[u] = (T)__uint_as_float(q.y);
-                    } else {
-                        jj[u] = ok ? col[k] : i;
-                        pp[u] = ok ? val[k] : (T)0;
-                    }
+                    jj[u] = ok ? col[k] : i;
+                    pp[u] = ok ? val[k] : (T)0;
                 }
                 V yj[U];
 #pragma unroll
@@ -94,6 +122,7 @@ __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
                     a0 += wgt * d0;
                     if (S == 2) a1 += wgt * d1;
                 }
+            }
             }
         }
         double f0 = (double)a0, f1 = (double)a1;

@@ -280,7 +280,8 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     sz[R_TOFF] = o.tiled ? sizeof(int64_t) * ((size_t)o.tile_ni * o.tile_nj + 1) : 0;
     // FP32 CSR rows: column and value of each non-zero packed into 8 bytes, so
     // the attraction streams one vector load per non-zero instead of two
-    sz[R_CV] = (d->dtype == TSNE_F32 && !o.tiled && d->nnz > 0) ? (size_t)8 * d->nnz : 0;
+    // (one spare pair: the kernel reads pairs two at a time, 16-byte aligned)
+    sz[R_CV] = (d->dtype == TSNE_F32 && !o.tiled && d->nnz > 0) ? (size_t)8 * (d->nnz + 1) : 0;
     sz[R_EPACK] = o.tiled ? sizeof(uint32_t) * (size_t)d->nnz : 0;
     sz[R_EVAL] = o.tiled ? (size_t)o.tsz * d->nnz : 0;
     sz[R_ZPART] = sizeof(double) * o.nb_gather;
