@@ -32,14 +32,33 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 // reduced in double.  Optionally the columns are split into slabs (virtual
 // blocks run slab-major, each row's slab range from the split table) and each
 // slab writes a partial force.  PK: the (column, value) pairs come packed in
-// one 8-byte array (FP32), loaded two at a time.
-template <typename T, int S, int LPR, int U, bool GATED, bool PK>
+// one 8-byte array (FP32), loaded two at a time.  KL: the same pass computes
+// the Kullback-Leibler sums of Section 1.1 instead, sum p log(p (1 + d^2))
+// and sum p over the block's edges (log in the element type, FP64 sums),
+// left as the virtual block's two partials for k_klsum.
+template <typename T, int S, int LPR, int U, bool GATED, bool PK, bool KL = false>
 __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
 {
     constexpr int RPB = 256 / LPR;
     typedef typename Vec<T, S>::t V;
+    __shared__ double klsh[8];
     VB_BEGIN_IF(map, GATED ? K_ATTR : K_ATTR_ALL, (!GATED || live(I)))
     {
+        double kla = 0.0, klp = 0.0;
+        // one edge's contribution: the force term, or the divergence terms
+        auto edge = [&](T pk, T d0, T d1, T& a0, T& a1) {
+            const T q = (T)1 + d0 * d0 + d1 * d1;
+            if constexpr (KL) {
+                if (pk > (T)0) {
+                    kla += (double)pk * (double)log(pk * q);
+                    klp += (double)pk;
+                }
+            } else {
+                const T wgt = pk * recip(q);
+                a0 += wgt * d0;
+                if (S == 2) a1 += wgt * d1;
+            }
+        };
         const int64_t n = I.n;
         const int nrb = (int)((n + RPB - 1) / RPB);
         // XCD-aware slab assignment: workgroups go to the 8 XCDs round-robin
@@ -94,9 +113,7 @@ __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
                         T d0, d1 = (T)0;
                         if constexpr (S == 2) { d0 = yi0 - yj[u].x; d1 = yi1 - yj[u].y; }
                         else { d0 = yi0 - yj[u]; }
-                        const T wgt = pp[u] * recip((T)1 + d0 * d0 + d1 * d1);
-                        a0 += wgt * d0;
-                        if (S == 2) a1 += wgt * d1;
+                        edge(pp[u], d0, d1, a0, a1);
                     }
                 }
             } else {
@@ -118,12 +135,19 @@ __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
                     T d0, d1 = (T)0;
                     if constexpr (S == 2) { d0 = yi0 - yj[u].x; d1 = yi1 - yj[u].y; }
                     else { d0 = yi0 - yj[u]; }
-                    const T wgt = pp[u] * recip((T)1 + d0 * d0 + d1 * d1);
-                    a0 += wgt * d0;
-                    if (S == 2) a1 += wgt * d1;
+                    edge(pp[u], d0, d1, a0, a1);
                 }
             }
             }
+        }
+        if constexpr (KL) {
+            kla = block_sum_d(kla, klsh);
+            klp = block_sum_d(klp, klsh);
+            if (threadIdx.x == 0) {
+                I.kl_part[2 * lb] = kla;
+                I.kl_part[2 * lb + 1] = klp;
+            }
+            continue;
         }
         double f0 = (double)a0, f1 = (double)a1;
 #pragma unroll
@@ -386,6 +410,13 @@ static hipError_t launch_attr(int kind, const Cfg& c, const LaunchMap& map, cons
         else hipLaunchKernelGGL((k_attr<T, S, 64, 2, false, PK>), g, b, 0, st, map);
         break;
     case K_ASUM: hipLaunchKernelGGL((k_asum<T, S>), g, b, 0, st, map); break;
+    case K_KL_ATTR:
+        if (c.lpr == 4) hipLaunchKernelGGL((k_attr<T, S, 4, 6, true, PK, true>), g, b, 0, st, map);
+        else if (c.lpr == 8) hipLaunchKernelGGL((k_attr<T, S, 8, 4, true, PK, true>), g, b, 0, st, map);
+        else if (c.lpr == 16) hipLaunchKernelGGL((k_attr<T, S, 16, 3, true, PK, true>), g, b, 0, st, map);
+        else if (c.lpr == 32) hipLaunchKernelGGL((k_attr<T, S, 32, 3, true, PK, true>), g, b, 0, st, map);
+        else hipLaunchKernelGGL((k_attr<T, S, 64, 2, true, PK, true>), g, b, 0, st, map);
+        break;
     case K_KL: hipLaunchKernelGGL((k_kl<T, S>), g, b, 0, st, map); break;
     case K_KLSUM: hipLaunchKernelGGL(k_klsum, g, b, 0, st, map); break;
     case K_ATTR_T:

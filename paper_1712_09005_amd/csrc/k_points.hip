@@ -1032,7 +1032,7 @@ hipError_t launch_kind(int kind, const Cfg& c, const LaunchMap& map, const Launc
     case K_FFT_ROWS: case K_FFT_COLS: case K_FFT_IROWS: case K_FFT_1D:
     case K_SPEC0: case K_SPEC1: case K_SPEC2:
         return launch_fft_kind(kind, c, map, l, st);
-    case K_ATTR: case K_ATTR_ALL: case K_ATTR_T: case K_ATTR_T_ALL: case K_ASUM:
+    case K_ATTR: case K_ATTR_ALL: case K_ATTR_T: case K_ATTR_T_ALL: case K_ASUM: case K_KL_ATTR:
     case K_KL: case K_KLSUM:
         return launch_attr_kind(kind, c, map, l, st);
     default:

@@ -225,7 +225,11 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     vb[K_UPDATE] = cdiv(n, 256);
     vb[K_GEOM] = 1;
     vb[K_ZSUM] = 1;
-    vb[K_KL] = (d->nnz > 0) ? o.nb_kl : 0;
+    // the divergence runs as a mode of the CSR attraction pass (same virtual
+    // blocks, one partial each), or over rows for the tiled layout
+    vb[K_KL_ATTR] = vb[K_ATTR];
+    if (vb[K_KL_ATTR] > 0) o.nb_kl = vb[K_KL_ATTR];
+    vb[K_KL] = (d->nnz > 0 && vb[K_KL_ATTR] == 0) ? o.nb_kl : 0;
     vb[K_KLSUM] = (d->nnz > 0) ? 1 : 0;
 
     // workspace layout
@@ -716,7 +720,7 @@ tsne_status tsne_kl_divergence(tsne_plan* pl, const void* Y, double* kl)
     if (s != TSNE_OK) return s;
     s = enqueue_repulsion(pl, false);
     if (s != TSNE_OK) return s;
-    s = enqueue(pl, K_KL);
+    s = enqueue(pl, pl->o.vb[K_KL_ATTR] > 0 ? K_KL_ATTR : K_KL);
     if (s != TSNE_OK) return s;
     return enqueue(pl, K_KLSUM);
 }

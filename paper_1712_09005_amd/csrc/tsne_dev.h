@@ -24,7 +24,7 @@ enum Kind : int {
     K_ARGS = 0, K_BOX, K_KEY, K_SCAN_A, K_SCAN_B, K_SCATTER, K_SPREAD, K_FIX,
     K_FFT_ROWS, K_FFT_COLS, K_FFT_IROWS, K_FFT_1D, K_GATHER, K_NORM, K_ATTR,
     K_UPDATE, K_SPEC0, K_SPEC1, K_SPEC2, K_GEOM, K_ZSUM, K_ATTR_ALL, K_ASUM, K_ATTR_T, K_ATTR_T_ALL,
-    K_KL, K_KLSUM, K_NKINDS
+    K_KL, K_KLSUM, K_KL_ATTR, K_NKINDS
 };
 
 // Status bits latched on the device (values of tsne_status).
