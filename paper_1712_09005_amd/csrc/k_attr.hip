@@ -396,14 +396,14 @@ static hipError_t launch_attr(int kind, const Cfg& c, const LaunchMap& map, cons
     dim3 g(l.grid), b(l.block);
     switch (kind) {
     case K_ATTR:
-        if (c.lpr == 4) hipLaunchKernelGGL((k_attr<T, S, 4, 6, true, PK>), g, b, 0, st, map);
+        if (c.lpr == 4) hipLaunchKernelGGL((k_attr<T, S, 4, 10, true, PK>), g, b, 0, st, map);
         else if (c.lpr == 8) hipLaunchKernelGGL((k_attr<T, S, 8, 4, true, PK>), g, b, 0, st, map);
         else if (c.lpr == 16) hipLaunchKernelGGL((k_attr<T, S, 16, 3, true, PK>), g, b, 0, st, map);
         else if (c.lpr == 32) hipLaunchKernelGGL((k_attr<T, S, 32, 3, true, PK>), g, b, 0, st, map);
         else hipLaunchKernelGGL((k_attr<T, S, 64, 2, true, PK>), g, b, 0, st, map);
         break;
     case K_ATTR_ALL:
-        if (c.lpr == 4) hipLaunchKernelGGL((k_attr<T, S, 4, 6, false, PK>), g, b, 0, st, map);
+        if (c.lpr == 4) hipLaunchKernelGGL((k_attr<T, S, 4, 10, false, PK>), g, b, 0, st, map);
         else if (c.lpr == 8) hipLaunchKernelGGL((k_attr<T, S, 8, 4, false, PK>), g, b, 0, st, map);
         else if (c.lpr == 16) hipLaunchKernelGGL((k_attr<T, S, 16, 3, false, PK>), g, b, 0, st, map);
         else if (c.lpr == 32) hipLaunchKernelGGL((k_attr<T, S, 32, 3, false, PK>), g, b, 0, st, map);
@@ -411,7 +411,7 @@ static hipError_t launch_attr(int kind, const Cfg& c, const LaunchMap& map, cons
         break;
     case K_ASUM: hipLaunchKernelGGL((k_asum<T, S>), g, b, 0, st, map); break;
     case K_KL_ATTR:
-        if (c.lpr == 4) hipLaunchKernelGGL((k_attr<T, S, 4, 6, true, PK, true>), g, b, 0, st, map);
+        if (c.lpr == 4) hipLaunchKernelGGL((k_attr<T, S, 4, 10, true, PK, true>), g, b, 0, st, map);
         else if (c.lpr == 8) hipLaunchKernelGGL((k_attr<T, S, 8, 4, true, PK, true>), g, b, 0, st, map);
         else if (c.lpr == 16) hipLaunchKernelGGL((k_attr<T, S, 16, 3, true, PK, true>), g, b, 0, st, map);
         else if (c.lpr == 32) hipLaunchKernelGGL((k_attr<T, S, 32, 3, true, PK, true>), g, b, 0, st, map);
