@@ -34,17 +34,19 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 // slab writes a partial force.  PK: the (column, value) pairs come packed in
 // one 8-byte array (FP32), loaded two at a time.  KL: the same pass computes
 // the Kullback-Leibler sums of Section 1.1 instead, sum p log(p (1 + d^2))
-// and sum p over the block's edges (log in the element type, FP64 sums),
-// left as the virtual block's two partials for k_klsum.
+// and sum p over the edges of all the block's virtual blocks (log in the
+// element type, FP64 sums), left as the block's two partials for k_klsum.
 template <typename T, int S, int LPR, int U, bool GATED, bool PK, bool KL = false>
 __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
 {
     constexpr int RPB = 256 / LPR;
     typedef typename Vec<T, S>::t V;
     __shared__ double klsh[8];
+    double kla = 0.0, klp = 0.0;
+    double* klout = nullptr;
     VB_BEGIN_IF(map, GATED ? K_ATTR : K_ATTR_ALL, (!GATED || live(I)))
     {
-        double kla = 0.0, klp = 0.0;
+        if (KL) klout = I.kl_part;
         // one edge's contribution: the force term, or the divergence terms
         auto edge = [&](T pk, T d0, T d1, T& a0, T& a1) {
             const T q = (T)1 + d0 * d0 + d1 * d1;
@@ -140,15 +142,7 @@ __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
             }
             }
         }
-        if constexpr (KL) {
-            kla = block_sum_d(kla, klsh);
-            klp = block_sum_d(klp, klsh);
-            if (threadIdx.x == 0) {
-                I.kl_part[2 * lb] = kla;
-                I.kl_part[2 * lb + 1] = klp;
-            }
-            continue;
-        }
+        if constexpr (KL) continue;
         double f0 = (double)a0, f1 = (double)a1;
 #pragma unroll
         for (int o = LPR / 2; o > 0; o >>= 1) {
@@ -163,6 +157,16 @@ __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
         }
     }
     VB_END
+    if constexpr (KL) {
+        // a single-instance launch: the block's partials (klout is this
+        // instance's array once the block has run a virtual block)
+        kla = block_sum_d(kla, klsh);
+        klp = block_sum_d(klp, klsh);
+        if (threadIdx.x == 0 && klout) {
+            klout[2 * blockIdx.x] = kla;
+            klout[2 * blockIdx.x + 1] = klp;
+        }
+    }
 }
 
 // Attraction over tiles of P: edges re-bucketed (at bind time) by row block of

@@ -228,7 +228,7 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     // the divergence runs as a mode of the CSR attraction pass (same virtual
     // blocks, one partial each), or over rows for the tiled layout
     vb[K_KL_ATTR] = vb[K_ATTR];
-    if (vb[K_KL_ATTR] > 0) o.nb_kl = vb[K_KL_ATTR];
+    if (vb[K_KL_ATTR] > 0) o.nb_kl = std::min(vb[K_KL_ATTR], kGridCap);   // one partial per block
     vb[K_KL] = (d->nnz > 0 && vb[K_KL_ATTR] == 0) ? o.nb_kl : 0;
     vb[K_KLSUM] = (d->nnz > 0) ? 1 : 0;
 
