@@ -292,7 +292,7 @@ def tune_interp(Y, target=1e-3, safety=2.5, ps=(4, 5, 6), max_intervals=512, dev
     return out
 
 
-def tune_batch_lanes(jobs, p=5, device="cuda:0", candidates=(16, 32, 64), reps=10,
+def tune_batch_lanes(jobs, p=5, device="cuda:0", candidates=(4, 8, 16, 32, 64), reps=10,
                      cache="default", log=None) -> dict:
     """Lanes per row for a batch's shared attraction launch: the candidate with
     the least summed attraction time over a sample of jobs [(Y, P), ...]."""

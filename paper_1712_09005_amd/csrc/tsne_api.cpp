@@ -132,14 +132,14 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     o.kpts = d->points_per_lane ? d->points_per_lane : 8;
     // column slabs: when the positions exceed ~4 MB, 4 slabs of P split over
     // XCD pairs keep each XCD's gathers inside its own 4 MB L2 (measured at
-    // N = 1e6: 754 us against 980 us with one slab); short rows per slab then
+    // N = 1e6: 573 us against 906 us with one slab); short rows per slab then
     // want fewer lanes per row
     {
         const int64_t ybytes = d->n * d->s * ((d->dtype == TSNE_F32) ? 4 : 8);
         const bool big = ybytes >= ((int64_t)4 << 20);
         int sl = d->attr_slabs ? d->attr_slabs : (big ? 4 : 1);
         if (sl != 1 && sl != 2 && sl != 4 && sl != 8) return TSNE_E_ARG;   // slabs map onto XCDs
-        o.lpr = d->lanes_per_row ? d->lanes_per_row : (sl > 1 ? 8 : 32);
+        o.lpr = d->lanes_per_row ? d->lanes_per_row : (sl > 1 ? 4 : 32);
         if (d->nnz >= ((int64_t)1 << 31) || d->nnz == 0) sl = 1;   // split offsets are int32
         if (sl > d->n) sl = (int)d->n;
         o.slabs = sl;

@@ -95,7 +95,7 @@ def test_spread_and_batch_lanes(A, tmp_path):
     jobs = [(inputs.mixture_embedding(n, 2, 5, -10, 10, 1.0, seed=n),
              inputs.random_graph_P(n, 90, seed=n)) for n in (5000, 12000)]
     b = A.tune_batch_lanes(jobs, device=DEV, reps=3, cache=str(tmp_path / "b.json"))
-    assert b["lanes_per_row"] in (16, 32, 64)
+    assert b["lanes_per_row"] in (4, 8, 16, 32, 64)
 
 
 def test_interp_choice_meets_target(A, tmp_path):
