@@ -175,7 +175,11 @@ tsne_status tsne_plan_destroy(tsne_plan* plan);
  * plan's dtype.  Checked on the host (synchronous; TSNE_E_ARG on failure):
  * row_ptr monotone from 0 to nnz, columns in [0, n) and increasing within each
  * row.  Not checked: symmetry, zero diagonal, sum of values 1.  Also builds the
- * per-row slab split table in the workspace. */
+ * per-row slab split table in the workspace, and for FP32 plans with the CSR
+ * layout copies (column, value) pairs into the workspace (enqueued on the
+ * plan's stream): the attraction and the divergence then read the copy, so
+ * a change to P's values takes effect at the next bind.  The arrays stay
+ * borrowed (the tiled layout and FP64 plans read them directly). */
 tsne_status tsne_bind_P(tsne_plan* plan, const int64_t* row_ptr,
                         const int32_t* col, const void* val);
 
