@@ -500,6 +500,18 @@ __global__ __launch_bounds__(256) void k_spec0(LaunchMap map)
     {
         const Geom& G = *I.geom;
         const int M = G.M, half = G.half;
+        // the launch covers the capacity's tables: past this iteration's,
+        // step over the rest of the instance's virtual blocks in one jump
+        // (the loop variables of VB_BEGIN_IF_SKIP)
+        const int64_t hyw = G.half_y;
+        const int64_t work = (S == 2) ? std::max(std::max<int64_t>(std::max(M, G.My), (int64_t)half * half),
+                                                 std::max(hyw * hyw, (int64_t)n_tables(I) * hyw * half))
+                                      : std::max<int64_t>(M, 2 * (int64_t)half);
+        if ((int64_t)lb * 256 >= work) {
+            const int end = __pre[inst_id + 1];
+            __vb += ((end - __vb + (int)gridDim.x - 1) / (int)gridDim.x - 1) * (int)gridDim.x;
+            continue;
+        }
         const int64_t idx = (int64_t)lb * 256 + threadIdx.x;
         const double h2 = G.h * G.h;
         if (idx < M - 1) stage_twiddle<T>(idx, M, G.nstages, G.radix, G.tw_off, I.tw);
