@@ -280,6 +280,13 @@ def test_c1_against_direct_sum(T):
     assert abs(Z2 - Zd) / Zd < 1e-4
     for d in range(2):
         assert rel(F2[:, d], Fd[:, d]) < 1e-3
+    # FP64 mode and the vector-kernel form at the default settings, per component
+    for dt, form in ((torch.float64, "A"), (torch.float32, "V"), (torch.float64, "V")):
+        _, _, F3, Z3, _ = gpu_rep(T, Y, dt, p=5, policy="fixed", w=0.75, max_int=128, form=form)
+        print("  %s form %s: %.3e (Z %.2e)" % (dt, form, rel(F3, Fd), abs(Z3 - Zd) / Zd))
+        assert abs(Z3 - Zd) / Zd < 1e-4
+        for d in range(2):
+            assert rel(F3[:, d], Fd[:, d]) < 1e-3
 
 
 ATTR_LAYOUTS = [  # (lanes per row, slabs, layout): CSR rows, XCD slabs, LDS tiles
