@@ -11,7 +11,8 @@
 //   cols:  for each potential, tiles of columns: forward transform, multiply
 //          by the (real, even) kernel spectrum, inverse transform, keep the n
 //          node rows;
-//   irows: two potentials packed per complex inverse transform, keep n nodes.
+//   irows: two potentials packed per complex inverse transform (an odd last
+//          potential packs two of its rows), keep n nodes.
 // The kernel spectra are built in double by direct cosine sums (the circulant
 // of an even kernel has a real, even spectrum) and stored pre-scaled by 1/M^s.
 #include <math.h>
@@ -352,8 +353,17 @@ __global__ __launch_bounds__(1024) void k_fft_irows(LaunchMap map)
         const Geom& G = *I.geom;
         const int n = G.n, M = G.M, n_cap = I.n_cap, tw_ = I.tile_w;
         const int q = lb / n_cap, r = lb - q * n_cap;
-        const int pa = 2 * q, pb = 2 * q + 1;
-        if (r < G.n_y) {
+        // two real outputs per complex transform: row r of potentials 2q and
+        // 2q + 1, or, for an odd last potential, its rows 2r' and 2r' + 1
+        int pa = 2 * q, pb = 2 * q + 1, ra = r, rb = r;
+        bool has_b = pb < NP;
+        if (!has_b) {
+            pb = pa;
+            ra = 2 * r;
+            rb = 2 * r + 1;
+            has_b = rb < G.n_y;
+        }
+        if (ra < G.n_y) {
             const cplx<T>* Xa = static_cast<const cplx<T>*>(I.Xc) + (int64_t)pa * I.ntiles * n_cap * tw_;
             const cplx<T>* Xb = static_cast<const cplx<T>*>(I.Xc) + (int64_t)pb * I.ntiles * n_cap * tw_;
             const int mh = M / 2;
@@ -362,21 +372,21 @@ __global__ __launch_bounds__(1024) void k_fft_irows(LaunchMap map)
                 const bool up = k > mh;
                 const int kk = up ? M - k : k;
                 const int tile = kk >> ltw;
-                const int64_t off = ((int64_t)tile * n_cap + r) * tw_ + (kk & (tw_ - 1));
-                cplx<T> A = Xa[off];
-                cplx<T> B = (pb < NP) ? Xb[off] : cplx<T>{(T)0, (T)0};
+                const int64_t off = (int64_t)tile * n_cap * tw_ + (kk & (tw_ - 1));
+                cplx<T> A = Xa[off + (int64_t)ra * tw_];
+                cplx<T> B = has_b ? Xb[off + (int64_t)rb * tw_] : cplx<T>{(T)0, (T)0};
                 if (up) { A = cconj(A); B = cconj(B); }
                 // Z = A + i B, stored conjugated (inverse by forward transform)
                 buf[lds_pad(k)] = {A.x - B.y, -(A.y + B.x)};
             }
             __syncthreads();
             block_fft<T>(buf, 1, I, G);
-            T* Va = static_cast<T*>(I.V) + (int64_t)pa * n_cap * n_cap + (int64_t)r * n_cap;
-            T* Vb = static_cast<T*>(I.V) + (int64_t)pb * n_cap * n_cap + (int64_t)r * n_cap;
+            T* Va = static_cast<T*>(I.V) + (int64_t)pa * n_cap * n_cap + (int64_t)ra * n_cap;
+            T* Vb = static_cast<T*>(I.V) + (int64_t)pb * n_cap * n_cap + (int64_t)rb * n_cap;
             for (int g = threadIdx.x; g < n; g += blockDim.x) {
                 const cplx<T> z = buf[lds_pad(g)];   // conj of the inverse
                 Va[g] = z.x;
-                if (pb < NP) Vb[g] = -z.y;
+                if (has_b) Vb[g] = -z.y;
             }
             __syncthreads();
         }
