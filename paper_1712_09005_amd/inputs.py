@@ -23,6 +23,7 @@ import numpy as np
 __all__ = [
     "CSR", "mixture_embedding", "random_graph_P", "mixture_highdim",
     "serving_jobs", "poisson_arrivals", "config_inputs",
+    "low_rank_factors", "pca_matrix", "pca_omega",
 ]
 
 
@@ -146,3 +147,42 @@ def config_inputs(name: str, small: bool = False):
         y = np.ascontiguousarray((1e-2 * rng.standard_normal((n, 2))).astype(np.float32))
         return dict(Y=y, X=x, s=2, policy="paper", min_intervals=50)
     raise KeyError(name)
+
+
+def low_rank_factors(m: int, n: int, rank: int, seed: int, s_max: float = 1.0,
+                     s_min: float = 1e-2):
+    """Planted factors of a rank-`rank` matrix A = U0 diag(s) V0^T with
+    exactly these singular values: U0 (m x rank) and V0 (n x rank) have
+    orthonormal columns, cosine vectors of distinct random frequencies,
+    sqrt(2/len) cos(pi f (2i + 1) / (2 len)), with random row signs and a
+    random row order; s decreases geometrically from s_max to s_min.
+    (Section 6.3 measures on a random rank-50 matrix of doubles.)"""
+    rng = np.random.default_rng(seed)
+
+    def basis(length: int) -> np.ndarray:
+        f = rng.choice(np.arange(1, length), size=rank, replace=False).astype(np.float64)
+        i = np.arange(length, dtype=np.float64)[:, None]
+        B = np.sqrt(2.0 / length) * np.cos(np.pi * f[None, :] * (2.0 * i + 1.0) / (2.0 * length))
+        B *= rng.choice(np.array([-1.0, 1.0]), size=(length, 1))
+        return np.ascontiguousarray(B[rng.permutation(length)])
+
+    U0 = basis(m)
+    V0 = basis(n)
+    s = s_max * (s_min / s_max) ** (np.arange(rank, dtype=np.float64) / max(rank - 1, 1))
+    return U0, s, V0
+
+
+def pca_matrix(m: int, n: int, rank: int, seed: int, noise: float = 0.0, **kw):
+    """A = U0 diag(s) V0^T (+ noise * standard normal entries), m x n FP64,
+    with the planted factors of low_rank_factors."""
+    U0, s, V0 = low_rank_factors(m, n, rank, seed, **kw)
+    A = (U0 * s) @ V0.T
+    if noise > 0.0:
+        A += noise * np.random.default_rng(seed + 1).standard_normal((m, n))
+    return np.ascontiguousarray(A), U0, s, V0
+
+
+def pca_omega(n: int, l: int, seed: int) -> np.ndarray:
+    """The random n x l matrix of the first step of Algorithm 2 (Section 6):
+    entries uniform on [-1, 1)."""
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, size=(n, l))
