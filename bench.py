@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (vector and matrix)
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_attr_traffic_n1e6_2d.txt")
 ATTR_SOURCES = [os.path.join(ROOT, "paper_1712_09005_amd", "csrc", f)
                 for f in ("k_attr.hip", "tsne_dev.h", "launch.h")]
@@ -78,6 +79,9 @@ def main():
     ap.add_argument("--form", default=None, choices=["A", "B", "V"],
                     help="charge/kernel form of the repulsion (default: autotuned between A and V)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-pca", action="store_true", help="skip the randomised-PCA workload")
+    ap.add_argument("--pca-m", type=int, default=1_000_000)
+    ap.add_argument("--pca-n", type=int, default=30_000)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c2", "serve"],
                     help="c3: N=1e6 2-D step throughput (default); c4: N=1e6 1-D 750-iteration "
@@ -232,6 +236,8 @@ def main():
     kl_info = {"value": float(klv.item()), "ms_per_call": ev0.elapsed_time(ev1) / 20}
     log("KL divergence %.6f, %.3f ms per call" % (kl_info["value"], kl_info["ms_per_call"]))
 
+    pca_info = None if args.no_pca else pca_leg(args, dev)
+
     # accuracy on sampled rows against the direct sum (repulsion numerators)
     rel_err = None
     cpu = None
@@ -291,7 +297,7 @@ def main():
                    "n": n, "s": s, "nnz": int(P.nnz), "p": args.p, "interval_width": args.width,
                    "n_int": q["n_int"], "fft_len": q["fft_len"], "max_intervals": max_int,
                    "form": args.form,
-                   "autotuned": tuned, "kl_divergence": kl_info,
+                   "autotuned": tuned, "kl_divergence": kl_info, "pca": pca_info,
                    "rel_err_rep_numerators_sampled": rel_err},
         "roofline": {"bound": "hbm", "kernel": "attraction step: k_attr (+ k_asum when "
                                                "attr_slabs > 1)",
@@ -303,6 +309,62 @@ def main():
     print(json.dumps(out), flush=True)
     if args.copy_ref:
         copy_reference()
+
+
+def pca_leg(args, dev, rank=50, k=50, l=52, its=2, reps=2):
+    """Randomised PCA (Section 6, Algorithm 2) of a planted rank-50 FP64
+    matrix, by default the section's 1,000,000 x 30,000 (240 GB, resident in
+    HBM): seconds per call, FP64 rate of its big products, error of the
+    singular values against the planted ones, and the oracle's time on a
+    row sample of the same matrix."""
+    import numpy as np
+    import torch
+    from paper_1712_09005_amd import inputs, pca
+    m, n = args.pca_m, args.pca_n
+    info = {"workload": "%d x %d FP64, planted rank %d (cosine factors, singular values 1 .. 1e-2), "
+                        "A in HBM" % (m, n, rank), "m": m, "n": n, "k": k, "l": l, "its": its}
+    try:
+        torch.cuda.empty_cache()
+        U0, s0, V0 = inputs.low_rank_factors(m, n, rank, seed=30)
+        A = (torch.from_numpy(U0).to(dev) * torch.from_numpy(s0).to(dev)) @ \
+            torch.from_numpy(V0).to(dev).T.contiguous()
+        om = inputs.pca_omega(n, l, seed=31)
+        U, s, V = pca.oocpca(A, om, k=k, its=its)     # warm-up (workspace, code objects)
+        torch.cuda.synchronize()
+        st_ = torch.cuda.current_stream()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(st_)
+        for _ in range(reps):
+            U, s, V = pca.oocpca(A, om, k=k, its=its)
+        ev1.record(st_)
+        ev1.synchronize()
+        sec = ev0.elapsed_time(ev1) / 1e3 / reps
+        gemms = 2 * its + 2
+        flops = gemms * 2.0 * m * n * l
+        info.update({"seconds_per_call": sec, "passes_over_A": its + 2, "big_products": gemms,
+                     "tflops": flops / sec / 1e12, "fp64_peak_tflops": FP64_PEAK_TFLOPS,
+                     "frac": flops / sec / 1e12 / FP64_PEAK_TFLOPS,
+                     "max_rel_err_sigma": float(np.max(np.abs(s.cpu().numpy() - s0) / s0))})
+        log("pca %d x %d: %.3f s per call, %.1f TFLOP/s FP64" % (m, n, sec, flops / sec / 1e12))
+        del A, U, s, V
+        torch.cuda.empty_cache()
+        if not args.no_cpu:
+            from oracle import pca as opca
+            ms = 20_000
+            Us = U0[:ms]
+            As = (Us * s0) @ V0.T
+            t0 = time.perf_counter()
+            opca.oocpca(As, om, k=k, its=its, b=4096)
+            tc = time.perf_counter() - t0
+            info["cpu_oracle"] = {"seconds_scaled": tc * m / ms, "sample_rows": ms,
+                                  "sample_seconds": tc, "kind": "oracle",
+                                  "note": "the first %d rows of the same matrix; time scaled by m / rows" % ms}
+            log("pca oracle on %d rows: %.2f s" % (ms, tc))
+    except (RuntimeError, MemoryError) as e:
+        info["error"] = str(e)[:200]
+        torch.cuda.empty_cache()
+    return info
 
 
 def copy_reference(nbytes=512 << 20, reps=3):

@@ -120,6 +120,8 @@ def lib():
             "tsne_batch_tick": ([P, i32], i32),
             "tsne_batch_poll": ([P, i32, P, P], i32),
             "tsne_batch_retire": ([P, i32], i32),
+            "tsne_pca_workspace_bytes": ([P], ctypes.c_size_t),
+            "tsne_pca": ([P, P, P, P, P, P, P, ctypes.c_size_t, P], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)

@@ -1,4 +1,4 @@
-"""The C-ABI library loads and exports every entry point include/tsne.h
+"""The C-ABI library loads and exports every entry point that include/*.h
 declares; host-side argument checks work without a GPU (no compute calls)."""
 import ctypes
 import os
@@ -7,7 +7,8 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "tsne.h")
+HEADERS = sorted(os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+                 if f.endswith(".h"))
 
 
 @pytest.fixture(scope="module")
@@ -20,7 +21,7 @@ def L():
 
 
 def declared():
-    src = open(HEADER).read()
+    src = "".join(open(h).read() for h in HEADERS)
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(tsne_\w+)\s*\(", src)))
 
@@ -28,7 +29,7 @@ def declared():
 def test_header_declares_the_boundary():
     names = declared()
     for must in ("tsne_plan_create", "tsne_repulsive", "tsne_attractive", "tsne_step",
-                 "tsne_run", "tsne_batch_tick"):
+                 "tsne_run", "tsne_batch_tick", "tsne_pca", "tsne_pca_workspace_bytes"):
         assert must in names
 
 
@@ -72,3 +73,26 @@ def test_fft_length_ladder(L):
     assert large > small
     # a circulant longer than the supported 12288 is refused
     assert tsne.workspace_bytes(tsne.make_desc(5000, 1, p=6, max_intervals=1100)) == 0
+
+
+def test_pca_workspace_and_argument_checks(L):
+    from paper_1712_09005_amd import pca
+    d = pca.make_desc(1_000_000, 30_000, k=50, l=52, its=2)
+    nb = L.tsne_pca_workspace_bytes(ctypes.byref(d))
+    # X, X2 (n x l), Y, Q (m x l), l x l matrices and the partial sums (8 n x l)
+    assert 2 * 1_000_000 * 52 * 8 + 10 * 30_000 * 52 * 8 < nb < \
+        2 * 1_000_000 * 52 * 8 + 10 * 30_000 * 52 * 8 + (1 << 20)
+    host = pca.make_desc(1_000_000, 30_000, k=50, l=52, its=2, a_host=True, b=1000)
+    assert L.tsne_pca_workspace_bytes(ctypes.byref(host)) == nb + 1000 * 30_000 * 8
+    for kw in (dict(k=0), dict(k=53), dict(l=30_000), dict(its=-1)):
+        args = dict(k=50, l=52, its=2)
+        args.update(kw)
+        assert L.tsne_pca_workspace_bytes(ctypes.byref(pca.make_desc(1000, 30_000, **args))) == 0
+    big = pca.make_desc(1000, 1000, k=50, l=65, its=2)
+    assert L.tsne_pca_workspace_bytes(ctypes.byref(big)) == 0
+    z = ctypes.c_void_p(4096)
+    assert L.tsne_pca(ctypes.byref(big), z, z, z, z, z, z, 1 << 40, None) == 2
+    assert L.tsne_pca(ctypes.byref(d), z, z, z, z, z, None, 0, None) == 3
+    assert L.tsne_pca(ctypes.byref(d), z, z, z, z, z, ctypes.c_void_p(4096 + 64), 1 << 40, None) == 3
+    bad = pca.make_desc(10, 10, k=5, l=12, its=1)
+    assert L.tsne_pca(ctypes.byref(bad), z, z, z, z, z, z, 1 << 40, None) == 1
