@@ -349,6 +349,24 @@ def pca_leg(args, dev, rank=50, k=50, l=52, its=2, reps=2):
         log("pca %d x %d: %.3f s per call, %.1f TFLOP/s FP64" % (m, n, sec, flops / sec / 1e12))
         del A, U, s, V
         torch.cuda.empty_cache()
+        # out of core: a tenth of the rows in pinned host memory, streamed to
+        # the device in 16,384-row blocks once per pass
+        mh = m // 10
+        Ah = torch.empty((mh, n), dtype=torch.float64, pin_memory=True)
+        Ah.copy_(torch.from_numpy((U0[:mh] * s0) @ V0.T))
+        An = Ah.numpy()
+        pca.oocpca(An, om, k=k, its=its)
+        t0 = time.perf_counter()
+        pca.oocpca(An, om, k=k, its=its)
+        torch.cuda.synchronize()
+        th = time.perf_counter() - t0
+        info["host_streamed"] = {"m": mh, "b": 16384, "seconds_per_call": th, "passes_over_A": its + 2,
+                                 "stream_GBps": (its + 2) * mh * n * 8 / th / 1e9,
+                                 "note": "A in pinned host memory, copied to the device in b-row "
+                                         "blocks; wall time of one call"}
+        log("pca out of core, %d rows: %.3f s per call, %.1f GB/s streamed" %
+            (mh, th, (its + 2) * mh * n * 8 / th / 1e9))
+        del Ah, An
         if not args.no_cpu:
             from oracle import pca as opca
             ms = 20_000

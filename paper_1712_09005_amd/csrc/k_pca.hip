@@ -1,10 +1,9 @@
 // Randomised PCA of Section 6 (Algorithm 2) on gfx950, FP64.
 //
-// The big matrix A enters only through two skinny products, each an
-// LDS-tiled FP64 kernel (the chip's FP64 vector rate equals its FP64 matrix
-// rate, so plain FMAs with 4 x 4 register tiles are used):
-//   k_mm   C (rows x nc) = M (rows x K, row-major) S (K x nc)     A X, Z W
-//   k_mmt  C (p x l)    (+)= M^T T, M rows x p, T rows x l         A^T T, Z^T Z
+// The big matrix A enters only through two skinny products on the FP64
+// matrix cores:
+//   k_mm_mfma   C (rows x nc) = M (rows x K, row-major) S (K x nc)   A X, Z W
+//   k_mmt_mfma  C (p x l)    (+)= M^T T, M rows x p, T rows x l       A^T T, Z^T Z
 // and the small l x l eigenproblems run in one workgroup (cyclic Jacobi).
 // The host side walks A in b-row blocks (copied from host memory when A is
 // there), so each power iteration reads every block once.
@@ -19,130 +18,22 @@
 
 namespace pca {
 
-constexpr int TILE = 64;      // rows (k_mm) or columns (k_mmt) per workgroup, and the max l
+constexpr int TILE = 64;      // output tile edge (rows or columns) per workgroup, and the max l
 constexpr int KC = 32;        // reduction chunk staged in LDS
 constexpr int GSPLIT = 256;   // row splits of a Gram product
 constexpr int MSPLIT = 8;     // most row splits of an A^T T product (partials of n x l each)
 constexpr double kDrop = 1e-12;
 
-// C[r][c] = sum_k M[r][k] S[k][c] for r < rows, c < nc (nc <= 64).  Thread
-// (tr, tc) of the 16 x 16 grid owns rows tr + 16 i and columns tc + 16 j.
-__global__ __launch_bounds__(256) void k_mm(const double* __restrict__ M, int64_t ldm, int64_t rows,
-                                            int64_t K, const double* __restrict__ S, int64_t lds,
-                                            int nc, double* __restrict__ C, int64_t ldc)
-{
-    __shared__ double sm[TILE][KC + 1];
-    __shared__ double ss[KC][TILE];
-    const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
-    const int64_t r0 = (int64_t)blockIdx.x * TILE;
-    double acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-    for (int64_t k0 = 0; k0 < K; k0 += KC) {
-#pragma unroll
-        for (int q = 0; q < TILE * KC / 256; ++q) {
-            const int e = tid + 256 * q, rr = e / KC, kk = e % KC;
-            const int64_t r = r0 + rr, k = k0 + kk;
-            sm[rr][kk] = (r < rows && k < K) ? M[r * ldm + k] : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < KC * TILE / 256; ++q) {
-            const int e = tid + 256 * q, kk = e / TILE, c = e % TILE;
-            const int64_t k = k0 + kk;
-            ss[kk][c] = (k < K && c < nc) ? S[k * lds + c] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll 8
-        for (int kk = 0; kk < KC; ++kk) {
-            double a[4], b[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = sm[tr + 16 * i][kk];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = ss[kk][tc + 16 * j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int64_t r = r0 + tr + 16 * i;
-        if (r >= rows) continue;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int c = tc + 16 * j;
-            if (c < nc) C[r * ldc + c] = acc[i][j];
-        }
-    }
-}
-
-// C[c][j] (+)= sum_r M[r][c] T[r][j] for c < p, j < l, over the rows of this
-// workgroup's split (blockIdx.y; split s writes C + s * split_stride).
-// Thread (tp, tj) owns columns tp + 16 i and tj + 16 j of the output tile.
-__global__ __launch_bounds__(256) void k_mmt(const double* __restrict__ M, int64_t ldm, int64_t rows,
-                                             int64_t p, const double* __restrict__ T, int64_t ldt, int l,
-                                             double* __restrict__ C, int64_t ldc, int accumulate,
-                                             int64_t rows_per_split, int64_t split_stride)
-{
-    __shared__ double sm[KC][TILE + 1];
-    __shared__ double st[KC][TILE];
-    const int tid = threadIdx.x, tp = tid >> 4, tj = tid & 15;
-    const int64_t c0 = (int64_t)blockIdx.x * TILE;
-    const int64_t rb = (int64_t)blockIdx.y * rows_per_split;
-    const int64_t re = std::min(rows, rb + rows_per_split);
-    double acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-    for (int64_t r0 = rb; r0 < re; r0 += KC) {
-#pragma unroll
-        for (int q = 0; q < KC * TILE / 256; ++q) {
-            const int e = tid + 256 * q, rr = e / TILE, cc = e % TILE;
-            const int64_t r = r0 + rr, c = c0 + cc;
-            sm[rr][cc] = (r < re && c < p) ? M[r * ldm + c] : 0.0;
-            st[rr][cc] = (r < re && cc < l) ? T[r * ldt + cc] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll 8
-        for (int rr = 0; rr < KC; ++rr) {
-            double a[4], b[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = sm[rr][tp + 16 * i];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = st[rr][tj + 16 * j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-        }
-        __syncthreads();
-    }
-    double* Cs = C + (int64_t)blockIdx.y * split_stride;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int64_t c = c0 + tp + 16 * i;
-        if (c >= p) continue;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int jj = tj + 16 * j;
-            if (jj < l) {
-                double* o = Cs + c * ldc + jj;
-                *o = accumulate ? *o + acc[i][j] : acc[i][j];
-            }
-        }
-    }
-}
-
-// The same two products on the FP64 matrix cores (v_mfma_f64_16x16x4f64:
-// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
-// D[4 v + l / 16][l % 16] in its v-th accumulator).  Each of the four waves
-// owns a 16-row strip of the 64 x 64 output tile as four 16 x 16 blocks; the
-// staging through LDS is the same as above.
+// The two products on the FP64 matrix cores (v_mfma_f64_16x16x4f64: lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
+// D[4 v + l / 16][l % 16] in its v-th accumulator).  A workgroup computes a
+// 64 x 64 output tile; each of its four waves owns a 16-row strip of it as
+// four 16 x 16 blocks.  Operands are staged through LDS in chunks of KC
+// along the reduction:
+//   k_mm_mfma   C[r][c] = sum_k M[r][k] S[k][c], r < rows, c < nc <= 64;
+//   k_mmt_mfma  C[c][j] (+)= sum_r M[r][c] T[r][j], c < p, j < l, over the
+//               rows of the workgroup's split (blockIdx.y; split s writes
+//               C + s * split_stride).
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int SMP = KC + 4;     // LDS row pitch of the 64 x 32 tile
 constexpr int SSP = TILE + 16;  // LDS row pitch of the 32 x 64 tile
@@ -433,7 +324,7 @@ struct Runner {
     {
         if (rows <= 0) return;
         const dim3 g((unsigned)((rows + TILE - 1) / TILE));
-        hipLaunchKernelGGL(k_mm, g, dim3(256), 0, st, M, ldm, rows, K, S, lds, nc, C, ldc);
+        hipLaunchKernelGGL(k_mm_mfma, g, dim3(256), 0, st, M, ldm, rows, K, S, lds, nc, C, ldc);
         launched();
     }
     // C (+)= M^T T with C p x l.  When the column tiles alone leave the chip
@@ -446,7 +337,7 @@ struct Runner {
         const int64_t tiles = (p + TILE - 1) / TILE;
         int64_t splits = std::min<int64_t>({(int64_t)MSPLIT, (2048 + tiles - 1) / tiles, rows / 4096});
         if (splits < 2) {
-            hipLaunchKernelGGL(k_mmt, dim3((unsigned)tiles, 1), dim3(256), 0, st, M, ldm, rows, p, T, ldt,
+            hipLaunchKernelGGL(k_mmt_mfma, dim3((unsigned)tiles, 1), dim3(256), 0, st, M, ldm, rows, p, T, ldt,
                                d->l, C, (int64_t)d->l, accumulate, rows, (int64_t)0);
             launched();
             return;
@@ -455,7 +346,7 @@ struct Runner {
         per = ((per + KC - 1) / KC) * KC;
         splits = (rows + per - 1) / per;
         const int64_t cnt = p * d->l;
-        hipLaunchKernelGGL(k_mmt, dim3((unsigned)tiles, (unsigned)splits), dim3(256), 0, st, M, ldm, rows, p, T,
+        hipLaunchKernelGGL(k_mmt_mfma, dim3((unsigned)tiles, (unsigned)splits), dim3(256), 0, st, M, ldm, rows, p, T,
                            ldt, d->l, w.part, (int64_t)d->l, 0, per, cnt);
         launched();
         hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, w.part,
@@ -469,7 +360,7 @@ struct Runner {
         int64_t per = (rows + GSPLIT - 1) / GSPLIT;
         per = ((per + KC - 1) / KC) * KC;
         const int splits = (int)((rows + per - 1) / per);
-        hipLaunchKernelGGL(k_mmt, dim3(1, splits), dim3(256), 0, st, Z, (int64_t)l, rows, (int64_t)l, Z,
+        hipLaunchKernelGGL(k_mmt_mfma, dim3(1, splits), dim3(256), 0, st, Z, (int64_t)l, rows, (int64_t)l, Z,
                            (int64_t)l, l, w.part, (int64_t)l, 0, per, (int64_t)l * l);
         launched();
         const int64_t cnt = (int64_t)l * l;
