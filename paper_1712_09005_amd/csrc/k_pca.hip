@@ -49,20 +49,37 @@ __global__ __launch_bounds__(256) void k_mm_mfma(const double* __restrict__ M, i
     dbl4 acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
-    for (int64_t k0 = 0; k0 < K; k0 += KC) {
+    // the next chunk is loaded into registers while the current one is multiplied
+    constexpr int QA = TILE * KC / 256, QS = KC * TILE / 256;
+    double ra[QA], rs[QS];
+    auto fetch = [&](int64_t k0) {
 #pragma unroll
-        for (int q = 0; q < TILE * KC / 256; ++q) {
+        for (int q = 0; q < QA; ++q) {
             const int e = tid + 256 * q, rr = e / KC, kk = e % KC;
             const int64_t r = r0 + rr, k = k0 + kk;
-            sm[rr * SMP + kk] = (r < rows && k < K) ? M[r * ldm + k] : 0.0;
+            ra[q] = (r < rows && k < K) ? M[r * ldm + k] : 0.0;
         }
 #pragma unroll
-        for (int q = 0; q < KC * TILE / 256; ++q) {
+        for (int q = 0; q < QS; ++q) {
             const int e = tid + 256 * q, kk = e / TILE, c = e % TILE;
             const int64_t k = k0 + kk;
-            ss[kk * SSP + c] = (k < K && c < nc) ? S[k * lds + c] : 0.0;
+            rs[q] = (k < K && c < nc) ? S[k * lds + c] : 0.0;
+        }
+    };
+    fetch(0);
+    for (int64_t k0 = 0; k0 < K; k0 += KC) {
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int e = tid + 256 * q;
+            sm[(e / KC) * SMP + e % KC] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < QS; ++q) {
+            const int e = tid + 256 * q;
+            ss[(e / TILE) * SSP + e % TILE] = rs[q];
         }
         __syncthreads();
+        if (k0 + KC < K) fetch(k0 + KC);
 #pragma unroll
         for (int kk = 0; kk < KC; kk += 4) {
             const double a = sm[(wv * 16 + li) * SMP + kk + lk];
@@ -98,15 +115,28 @@ __global__ __launch_bounds__(256) void k_mmt_mfma(const double* __restrict__ M, 
     dbl4 acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
-    for (int64_t r0 = rb; r0 < re; r0 += KC) {
+    // the next chunk is loaded into registers while the current one is multiplied
+    constexpr int Q = KC * TILE / 256;
+    double rm[Q], rt[Q];
+    auto fetch = [&](int64_t r0) {
 #pragma unroll
-        for (int q = 0; q < KC * TILE / 256; ++q) {
+        for (int q = 0; q < Q; ++q) {
             const int e = tid + 256 * q, rr = e / TILE, cc = e % TILE;
             const int64_t r = r0 + rr, c = c0 + cc;
-            sm[rr * SSP + cc] = (r < re && c < p) ? M[r * ldm + c] : 0.0;
-            st[rr * SSP + cc] = (r < re && cc < l) ? T[r * ldt + cc] : 0.0;
+            rm[q] = (r < re && c < p) ? M[r * ldm + c] : 0.0;
+            rt[q] = (r < re && cc < l) ? T[r * ldt + cc] : 0.0;
+        }
+    };
+    if (rb < re) fetch(rb);
+    for (int64_t r0 = rb; r0 < re; r0 += KC) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int e = tid + 256 * q;
+            sm[(e / TILE) * SSP + e % TILE] = rm[q];
+            st[(e / TILE) * SSP + e % TILE] = rt[q];
         }
         __syncthreads();
+        if (r0 + KC < re) fetch(r0 + KC);
 #pragma unroll
         for (int kk = 0; kk < KC; kk += 4) {
             const double a = sm[(kk + lk) * SSP + wv * 16 + li];
