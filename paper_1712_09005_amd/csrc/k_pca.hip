@@ -34,11 +34,14 @@ constexpr double kDrop = 1e-12;
 //   k_mmt_mfma  C[c][j] (+)= sum_r M[r][c] T[r][j], c < p, j < l, over the
 //               rows of the workgroup's split (blockIdx.y; split s writes
 //               C + s * split_stride).
+// Both kernels are held to three waves per SIMD (three workgroups per CU,
+// 39 or 41 KB of LDS each): the accumulators then live in VGPRs and the
+// occupancy hides more of the global latency than the default two waves.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int SMP = KC + 4;     // LDS row pitch of the 64 x 32 tile
 constexpr int SSP = TILE + 16;  // LDS row pitch of the 32 x 64 tile
 
-__global__ __launch_bounds__(256) void k_mm_mfma(const double* __restrict__ M, int64_t ldm, int64_t rows,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_mm_mfma(const double* __restrict__ M, int64_t ldm, int64_t rows,
                                                  int64_t K, const double* __restrict__ S, int64_t lds,
                                                  int nc, double* __restrict__ C, int64_t ldc)
 {
@@ -101,7 +104,7 @@ __global__ __launch_bounds__(256) void k_mm_mfma(const double* __restrict__ M, i
     }
 }
 
-__global__ __launch_bounds__(256) void k_mmt_mfma(const double* __restrict__ M, int64_t ldm, int64_t rows,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_mmt_mfma(const double* __restrict__ M, int64_t ldm, int64_t rows,
                                                   int64_t p, const double* __restrict__ T, int64_t ldt, int l,
                                                   double* __restrict__ C, int64_t ldc, int accumulate,
                                                   int64_t rows_per_split, int64_t split_stride)
