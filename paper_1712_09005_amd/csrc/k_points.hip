@@ -358,6 +358,46 @@ __global__ __launch_bounds__(256) void k_geom(LaunchMap map)
     VB_END
 }
 
+// One point's S coordinates, moved with one vector access when S = 2 (the
+// [N, S] arrays are 8- or 16-byte aligned per point).
+template <typename T, int S> struct Pt {
+    T v[S];
+    __device__ __forceinline__ static Pt load(const T* a, int64_t i)
+    {
+        Pt p;
+#pragma unroll
+        for (int d = 0; d < S; ++d) p.v[d] = a[i * S + d];
+        return p;
+    }
+    __device__ __forceinline__ void store(T* a, int64_t i) const
+    {
+#pragma unroll
+        for (int d = 0; d < S; ++d) a[i * S + d] = v[d];
+    }
+};
+template <typename T> struct Pt2Vec;
+template <> struct Pt2Vec<float> { typedef float2 t; };
+template <> struct Pt2Vec<double> { typedef double2 t; };
+template <typename T> struct Pt<T, 2> {
+    typedef typename Pt2Vec<T>::t V;
+    T v[2];
+    __device__ __forceinline__ static Pt load(const T* a, int64_t i)
+    {
+        const V q = reinterpret_cast<const V*>(a)[i];
+        Pt p;
+        p.v[0] = q.x;
+        p.v[1] = q.y;
+        return p;
+    }
+    __device__ __forceinline__ void store(T* a, int64_t i) const
+    {
+        V q;
+        q.x = v[0];
+        q.y = v[1];
+        reinterpret_cast<V*>(a)[i] = q;
+    }
+};
+
 // ---------------------------------------------------------------- binning
 
 // Cell key of each point and its rank among the points of its cell (the
@@ -547,10 +587,7 @@ __global__ __launch_bounds__(256) void k_scatter(LaunchMap map)
             const int i = G.perm_valid ? prev[pos] : (int)pos;
             const int np_ = I.cell_start[I.key[pos]] + I.rank[pos];
             cur[np_] = i;
-            const T* Y = static_cast<const T*>(I.Yin);
-            T* sY = static_cast<T*>(I.sY);
-#pragma unroll
-            for (int d = 0; d < S; ++d) sY[(int64_t)np_ * S + d] = Y[(int64_t)i * S + d];
+            Pt<T, S>::load(static_cast<const T*>(I.Yin), i).store(static_cast<T*>(I.sY), np_);
         }
     }
     VB_END
@@ -937,28 +974,42 @@ __global__ __launch_bounds__(256) void k_update(LaunchMap map)
             const T* Fp = static_cast<const T*>(I.Fap);
             const T* R = static_cast<const T*>(I.R);
             const int64_t ns = I.n * S;
+            // the point's S components are loaded and stored as one vector
+            // per array (8 or 16 bytes in 2-D)
+            Pt<T, S> fa, r, u, g, y;
+            if (I.slabs == 1) {
+                fa = Pt<T, S>::load(Fa, i);
+            } else {
+                double a[S];
+#pragma unroll
+                for (int d = 0; d < S; ++d) a[d] = 0.0;
+                for (int sl = 0; sl < I.slabs; ++sl) {
+                    const Pt<T, S> q = Pt<T, S>::load(Fp + (int64_t)sl * ns, i);
+#pragma unroll
+                    for (int d = 0; d < S; ++d) a[d] += (double)q.v[d];
+                }
+#pragma unroll
+                for (int d = 0; d < S; ++d) fa.v[d] = (T)a[d];
+            }
+            r = Pt<T, S>::load(R, i);
+            u = Pt<T, S>::load(uY, i);
+            g = Pt<T, S>::load(gains, i);
+            y = Pt<T, S>::load(Y, i);
 #pragma unroll
             for (int d = 0; d < S; ++d) {
-                const int64_t k = i * S + d;
-                T fa;
-                if (I.slabs == 1) {
-                    fa = Fa[k];
-                } else {
-                    double a = 0.0;
-                    for (int sl = 0; sl < I.slabs; ++sl) a += (double)Fp[(int64_t)sl * ns + k];
-                    fa = (T)a;
-                }
-                const T grad = (T)4 * ((T)alpha * fa - R[k] * invz);
-                const T u = uY[k];
-                T g = ((grad > (T)0) != (u > (T)0)) ? gains[k] + (T)sc.gain_inc
-                                                    : gains[k] * (T)sc.gain_dec;
-                if (g < (T)sc.gain_min) g = (T)sc.gain_min;
-                gains[k] = g;
-                const T un = (T)mom * u - (T)sc.eta * g * grad;
-                uY[k] = un;
-                const T y = sc.recentre ? (Y[k] - (T)G.mean[d]) : Y[k];
-                Y[k] = y + un;
+                const T grad = (T)4 * ((T)alpha * fa.v[d] - r.v[d] * invz);
+                T gd = ((grad > (T)0) != (u.v[d] > (T)0)) ? g.v[d] + (T)sc.gain_inc
+                                                          : g.v[d] * (T)sc.gain_dec;
+                if (gd < (T)sc.gain_min) gd = (T)sc.gain_min;
+                g.v[d] = gd;
+                const T un = (T)mom * u.v[d] - (T)sc.eta * gd * grad;
+                u.v[d] = un;
+                const T yd = sc.recentre ? (y.v[d] - (T)G.mean[d]) : y.v[d];
+                y.v[d] = yd + un;
             }
+            g.store(gains, i);
+            u.store(uY, i);
+            y.store(Y, i);
         }
     }
     VB_END

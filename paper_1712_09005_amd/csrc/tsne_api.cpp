@@ -759,6 +759,14 @@ static tsne_status enqueue_iteration(tsne_plan* pl)
     return enqueue(pl, K_UPDATE);
 }
 
+// Per-point arrays are accessed one point at a time as a vector (s
+// elements), so each must be aligned to a whole point.
+static bool point_aligned(const tsne_desc& d, const void* p)
+{
+    const uintptr_t a = (uintptr_t)d.s * ((d.dtype == TSNE_F32) ? 4 : 8);
+    return p && ((uintptr_t)p % a) == 0;
+}
+
 static bool sched_ok(const tsne_sched* sc)
 {
     return sc && std::isfinite(sc->eta) && std::isfinite(sc->mom0) && std::isfinite(sc->mom1) &&
@@ -768,6 +776,7 @@ static bool sched_ok(const tsne_sched* sc)
 tsne_status tsne_step(tsne_plan* pl, void* Y, void* uY, void* gains, const tsne_sched* sc, int32_t iter)
 {
     if (!pl || !Y || !uY || !gains || !sched_ok(sc) || iter < 0) return TSNE_E_ARG;
+    if (!point_aligned(pl->d, Y) || !point_aligned(pl->d, uY) || !point_aligned(pl->d, gains)) return TSNE_E_ARG;
     if (pl->d.nnz > 0 && !pl->P_bound) return TSNE_E_STATE;
     tsne_status s = step_args(pl, Y, uY, gains, sc, iter);
     if (s != TSNE_OK) return s;
@@ -778,6 +787,7 @@ tsne_status tsne_run(tsne_plan* pl, void* Y, void* uY, void* gains, const tsne_s
                      int32_t iter0, int32_t n_iter)
 {
     if (!pl || !Y || !uY || !gains || !sched_ok(sc) || iter0 < 0 || n_iter < 0) return TSNE_E_ARG;
+    if (!point_aligned(pl->d, Y) || !point_aligned(pl->d, uY) || !point_aligned(pl->d, gains)) return TSNE_E_ARG;
     if (pl->d.nnz > 0 && !pl->P_bound) return TSNE_E_STATE;
     if (n_iter == 0) return TSNE_OK;
     tsne_status s = step_args(pl, Y, uY, gains, sc, iter0);
@@ -1034,6 +1044,7 @@ tsne_status tsne_batch_admit(tsne_batch* b, const tsne_desc* desc, void* plan_ws
         return TSNE_E_ARG;
     if (desc->s != b->s || desc->dtype != b->dtype || desc->p != b->p || desc->form != b->form)
         return TSNE_E_ARG;
+    if (!point_aligned(*desc, Y) || !point_aligned(*desc, uY) || !point_aligned(*desc, gains)) return TSNE_E_ARG;
     // every slot shares one attraction launch: CSR rows, the batch's lanes per row, one slab
     if ((desc->lanes_per_row != 0 && desc->lanes_per_row != b->cfg.lpr) ||
         (desc->attr_slabs != 0 && desc->attr_slabs != 1) || desc->attr_layout == 2)

@@ -418,3 +418,25 @@ def test_status_capacity_and_nonfinite(T):
     torch.cuda.synchronize()
     assert plan2.query()["status"] == 5
     assert torch.all(F2 == 7.0)
+
+
+def test_misaligned_point_arrays_rejected(T):
+    # per-point arrays move as one vector per point: a pointer that is not
+    # aligned to a whole point is refused on the host, before any launch
+    print("case: misaligned point arrays", flush=True)
+    import ctypes
+    n = 1000
+    plan = T.Plan(n, 2, torch.float32, p=3, max_intervals=64, device=DEV)
+    buf = torch.zeros(2 * n + 2, dtype=torch.float32, device=DEV)
+    good, bad = buf[:2 * n], buf[1:2 * n + 1]
+    sc = T.Schedule().c()
+    L = T.lib()
+    P = ctypes.c_void_p
+    assert L.tsne_step(plan._h, P(bad.data_ptr()), P(good.data_ptr()), P(good.data_ptr()),
+                       ctypes.byref(sc), 0) == 1
+    assert L.tsne_run(plan._h, P(good.data_ptr()), P(bad.data_ptr()), P(good.data_ptr()),
+                      ctypes.byref(sc), 0, 3) == 1
+    assert L.tsne_step(plan._h, P(good.data_ptr()), P(good.data_ptr()), P(bad.data_ptr()),
+                       ctypes.byref(sc), 0) == 1
+    torch.cuda.synchronize()
+    assert torch.all(buf == 0)
