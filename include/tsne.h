@@ -26,9 +26,9 @@
  *     vectors (F_rep, F_attr, uY, gains) share that layout.  The element type
  *     is float (TSNE_F32) or double (TSNE_F64) as set in the descriptor.
  *     Each such array is aligned to a whole point (s times the element size),
- *     since kernels move a point's coordinates as one vector; tsne_step,
- *     tsne_run and tsne_batch_admit return TSNE_E_ARG for Y, uY or gains
- *     that are not.
+ *     since kernels move a point's coordinates as one vector; every entry
+ *     point that takes Y (and tsne_step, tsne_run, tsne_batch_admit for uY
+ *     and gains) returns TSNE_E_ARG for one that is not.
  *   - F_rep follows the sign of the attractive/repulsive split of Section 1.1:
  *     F_rep,i = sum_{j != i} (y_i - y_j) / (1 + |y_i - y_j|^2)^2 / Z, pointing
  *     away from the other points; Z = sum_{k != l} 1/(1 + |y_k - y_l|^2).

@@ -419,10 +419,10 @@ __global__ __launch_bounds__(256) void k_key(LaunchMap map)
         if (valid) {
             const int* prev = I.perm + (int64_t)(G.pbuf ^ 1) * I.n;
             i = G.perm_valid ? prev[pos] : (int)pos;
-            const T* Y = static_cast<const T*>(I.Yin);
+            const Pt<T, S> y = Pt<T, S>::load(static_cast<const T*>(I.Yin), i);
             T t;
-            key = locate<T>(Y[(int64_t)i * S], G.origin[0], G.w, G.n_int, t);
-            if (S == 2) key += G.n_int * locate<T>(Y[(int64_t)i * S + 1], G.origin[1], G.w, G.n_int_y, t);
+            key = locate<T>(y.v[0], G.origin[0], G.w, G.n_int, t);
+            if (S == 2) key += G.n_int * locate<T>(y.v[S - 1], G.origin[1], G.w, G.n_int_y, t);
         }
         const int kprev = __shfl_up(key, 1, 64);
         const bool head = (lane == 0) || (kprev != key);
@@ -631,7 +631,8 @@ __global__ __launch_bounds__(256) void k_spread(LaunchMap map)
             for (int pos = b; pos < e; ++pos) {
                 T q[NC];
                 T tx, ty = (T)0;
-                const T yx = sY[(int64_t)pos * S];
+                const Pt<T, S> yp = Pt<T, S>::load(sY, pos);
+                const T yx = yp.v[0];
                 locate<T>(yx, o0, w, n_int, tx);
                 // centred, power-of-two scaled charges, rounded once from double
                 const double qx = ((double)yx - c0) * qs;
@@ -639,7 +640,7 @@ __global__ __launch_bounds__(256) void k_spread(LaunchMap map)
                 q[0] = (T)1;
                 if (NC > 1) q[1 % NC] = (T)qx;
                 if (S == 2) {
-                    const T yy = sY[(int64_t)pos * S + 1];
+                    const T yy = yp.v[S - 1];
                     locate<T>(yy, o1, w, G.n_int_y, ty);
                     qy = ((double)yy - c1) * qs;
                     if (NC > 2) q[2 % NC] = (T)qy;
@@ -842,9 +843,10 @@ __global__ __launch_bounds__(256) void k_gather(LaunchMap map)
             const double w = G.w, qs = G.qscale;
             T yv[2], tl[2];
             int cl[2] = {0, 0};
+            const Pt<T, S> yp = Pt<T, S>::load(sY, pos);
 #pragma unroll
             for (int d = 0; d < S; ++d) {
-                yv[d] = sY[pos * S + d];
+                yv[d] = yp.v[d];
                 cl[d] = locate<T>(yv[d], G.origin[d], w, d == 0 ? n_int : G.n_int_y, tl[d]);
             }
             T Lx[P], Ly[P];
@@ -893,11 +895,12 @@ __global__ __launch_bounds__(256) void k_gather(LaunchMap map)
                      (double)phi[0] * inv_qs * inv_qs;
             }
             const int i = I.perm[(int64_t)G.pbuf * I.n + pos];
-            T* R = static_cast<T*>(I.R);
+            Pt<T, S> rv;
 #pragma unroll
             for (int d = 0; d < S; ++d)
-                R[(int64_t)i * S + d] = (FORM == 2) ? phi[1 + d]
-                                                    : (T)(yc[d] * (double)phi[1] - (double)phi[(2 + d) % NP] * inv_qs);
+                rv.v[d] = (FORM == 2) ? phi[1 + d]
+                                      : (T)(yc[d] * (double)phi[1] - (double)phi[(2 + d) % NP] * inv_qs);
+            rv.store(static_cast<T*>(I.R), i);
             h1d = h1;
         }
         const double bs = block_sum_d(h1d, sh);

@@ -676,9 +676,17 @@ tsne_status tsne_bind_P(tsne_plan* pl, const int64_t* row_ptr, const int32_t* co
     return TSNE_OK;
 }
 
+// Per-point arrays are accessed one point at a time as a vector (s
+// elements), so each must be aligned to a whole point.
+static bool point_aligned(const tsne_desc& d, const void* p)
+{
+    const uintptr_t a = (uintptr_t)d.s * ((d.dtype == TSNE_F32) ? 4 : 8);
+    return p && ((uintptr_t)p % a) == 0;
+}
+
 tsne_status tsne_repulsive(tsne_plan* pl, const void* Y, void* F_rep, double* Z)
 {
-    if (!pl || !Y || !F_rep) return TSNE_E_ARG;
+    if (!pl || !Y || !F_rep || !point_aligned(pl->d, Y)) return TSNE_E_ARG;
     CallArgs a = no_args();
     a.set_ptrs = 1;
     a.Yin = Y;
@@ -692,7 +700,7 @@ tsne_status tsne_repulsive(tsne_plan* pl, const void* Y, void* F_rep, double* Z)
 
 tsne_status tsne_attractive(tsne_plan* pl, const void* Y, void* F_attr)
 {
-    if (!pl || !Y || !F_attr) return TSNE_E_ARG;
+    if (!pl || !Y || !F_attr || !point_aligned(pl->d, Y)) return TSNE_E_ARG;
     if (!pl->P_bound) return TSNE_E_STATE;
     CallArgs a = no_args();
     a.set_ptrs = 1;
@@ -709,7 +717,7 @@ tsne_status tsne_attractive(tsne_plan* pl, const void* Y, void* F_attr)
 
 tsne_status tsne_kl_divergence(tsne_plan* pl, const void* Y, double* kl)
 {
-    if (!pl || !Y || !kl) return TSNE_E_ARG;
+    if (!pl || !Y || !kl || !point_aligned(pl->d, Y)) return TSNE_E_ARG;
     if (!pl->P_bound) return TSNE_E_STATE;
     CallArgs a = no_args();
     a.set_ptrs = 1;
@@ -757,14 +765,6 @@ static tsne_status enqueue_iteration(tsne_plan* pl)
         if (s != TSNE_OK) return s;
     }
     return enqueue(pl, K_UPDATE);
-}
-
-// Per-point arrays are accessed one point at a time as a vector (s
-// elements), so each must be aligned to a whole point.
-static bool point_aligned(const tsne_desc& d, const void* p)
-{
-    const uintptr_t a = (uintptr_t)d.s * ((d.dtype == TSNE_F32) ? 4 : 8);
-    return p && ((uintptr_t)p % a) == 0;
 }
 
 static bool sched_ok(const tsne_sched* sc)

@@ -438,5 +438,6 @@ def test_misaligned_point_arrays_rejected(T):
                       ctypes.byref(sc), 0, 3) == 1
     assert L.tsne_step(plan._h, P(good.data_ptr()), P(good.data_ptr()), P(bad.data_ptr()),
                        ctypes.byref(sc), 0) == 1
+    assert L.tsne_repulsive(plan._h, P(bad.data_ptr()), P(good.data_ptr()), None) == 1
     torch.cuda.synchronize()
     assert torch.all(buf == 0)
