@@ -561,11 +561,12 @@ __global__ __launch_bounds__(256) void k_scan_b(LaunchMap map)
                 pi += iv[k];
             }
             // cells with many items (a small box holding many points): the
-            // whole block writes their item -> cell entries
+            // block's four waves take them in turn, each wave's lanes writing
+            // one cell's item -> cell entries
             __syncthreads();
-            for (int b = 0; b < nbig; ++b) {
+            for (int b = wv; b < nbig; b += 4) {
                 const int e = big[b][0], p0 = big[b][1], m = big[b][2];
-                for (int q = threadIdx.x; q < m; q += 256) I.item_cell[p0 + q] = e;
+                for (int q = lane; q < m; q += 64) I.item_cell[p0 + q] = e;
             }
             __syncthreads();
         }
