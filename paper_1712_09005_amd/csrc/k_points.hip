@@ -107,6 +107,46 @@ hipError_t launch_set_args(Inst* inst, const CallArgs& a, hipStream_t st)
     return hipGetLastError();
 }
 
+// One point's S coordinates, moved with one vector access when S = 2 (the
+// [N, S] arrays are 8- or 16-byte aligned per point).
+template <typename T, int S> struct Pt {
+    T v[S];
+    __device__ __forceinline__ static Pt load(const T* a, int64_t i)
+    {
+        Pt p;
+#pragma unroll
+        for (int d = 0; d < S; ++d) p.v[d] = a[i * S + d];
+        return p;
+    }
+    __device__ __forceinline__ void store(T* a, int64_t i) const
+    {
+#pragma unroll
+        for (int d = 0; d < S; ++d) a[i * S + d] = v[d];
+    }
+};
+template <typename T> struct Pt2Vec;
+template <> struct Pt2Vec<float> { typedef float2 t; };
+template <> struct Pt2Vec<double> { typedef double2 t; };
+template <typename T> struct Pt<T, 2> {
+    typedef typename Pt2Vec<T>::t V;
+    T v[2];
+    __device__ __forceinline__ static Pt load(const T* a, int64_t i)
+    {
+        const V q = reinterpret_cast<const V*>(a)[i];
+        Pt p;
+        p.v[0] = q.x;
+        p.v[1] = q.y;
+        return p;
+    }
+    __device__ __forceinline__ void store(T* a, int64_t i) const
+    {
+        V q;
+        q.x = v[0];
+        q.y = v[1];
+        reinterpret_cast<V*>(a)[i] = q;
+    }
+};
+
 // ---------------------------------------------------------------- box geometry
 
 // Per-block partial min / max / sum of the coordinates (double) and a
@@ -125,9 +165,10 @@ __global__ __launch_bounds__(256) void k_box(LaunchMap map)
 #pragma unroll
         for (int d = 0; d < S; ++d) { lo[d] = INFINITY; hi[d] = -INFINITY; sm[d] = 0.0; }
         for (int64_t i = (int64_t)lb * 256 + threadIdx.x; i < n; i += (int64_t)nb * 256) {
+            const Pt<T, S> y = Pt<T, S>::load(Y, i);
 #pragma unroll
             for (int d = 0; d < S; ++d) {
-                const double v = (double)Y[i * S + d];
+                const double v = (double)y.v[d];
                 if (!isfinite(v)) bad = 1.0;
                 lo[d] = fmin(lo[d], v);
                 hi[d] = fmax(hi[d], v);
@@ -357,46 +398,6 @@ __global__ __launch_bounds__(256) void k_geom(LaunchMap map)
     }
     VB_END
 }
-
-// One point's S coordinates, moved with one vector access when S = 2 (the
-// [N, S] arrays are 8- or 16-byte aligned per point).
-template <typename T, int S> struct Pt {
-    T v[S];
-    __device__ __forceinline__ static Pt load(const T* a, int64_t i)
-    {
-        Pt p;
-#pragma unroll
-        for (int d = 0; d < S; ++d) p.v[d] = a[i * S + d];
-        return p;
-    }
-    __device__ __forceinline__ void store(T* a, int64_t i) const
-    {
-#pragma unroll
-        for (int d = 0; d < S; ++d) a[i * S + d] = v[d];
-    }
-};
-template <typename T> struct Pt2Vec;
-template <> struct Pt2Vec<float> { typedef float2 t; };
-template <> struct Pt2Vec<double> { typedef double2 t; };
-template <typename T> struct Pt<T, 2> {
-    typedef typename Pt2Vec<T>::t V;
-    T v[2];
-    __device__ __forceinline__ static Pt load(const T* a, int64_t i)
-    {
-        const V q = reinterpret_cast<const V*>(a)[i];
-        Pt p;
-        p.v[0] = q.x;
-        p.v[1] = q.y;
-        return p;
-    }
-    __device__ __forceinline__ void store(T* a, int64_t i) const
-    {
-        V q;
-        q.x = v[0];
-        q.y = v[1];
-        reinterpret_cast<V*>(a)[i] = q;
-    }
-};
 
 // ---------------------------------------------------------------- binning
 
