@@ -919,9 +919,20 @@ __global__ __launch_bounds__(256) void k_zsum(LaunchMap map)
     __shared__ double sh[8];
     VB_BEGIN(map, K_ZSUM)
     if (live(I)) {
-        double z = 0.0;
-        for (int b = threadIdx.x; b < I.nb_gather; b += 256) z += I.z_part[b];
-        z = block_sum_d(z, sh);
+        // four independent partial sums per thread, so their loads are in
+        // flight together (a fixed order: the result is reproducible)
+        const double* zp = I.z_part;
+        const int nb = I.nb_gather;
+        double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
+        int b = threadIdx.x;
+        for (; b + 768 < nb; b += 1024) {
+            z0 += zp[b];
+            z1 += zp[b + 256];
+            z2 += zp[b + 512];
+            z3 += zp[b + 768];
+        }
+        for (; b < nb; b += 256) z0 += zp[b];
+        double z = block_sum_d((z0 + z1) + (z2 + z3), sh);
         if (threadIdx.x == 0) {
             z -= (double)I.n;
             I.geom->Z = z;
