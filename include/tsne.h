@@ -231,6 +231,35 @@ tsne_status tsne_debug_export(tsne_plan* plan, int32_t what, void* dst_host,
 
 const char* tsne_status_str(tsne_status status);
 
+/* Size of the device scratch array behind tsne_repulsive_static (bytes). */
+#define TSNE_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* Repulsion without any device allocation, for callers that cannot allocate
+ * device memory or hand over a workspace: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Computes exactly what
+ * tsne_plan_create + tsne_repulsive + tsne_plan_destroy compute for desc (same
+ * kernels; desc->nnz and the attraction fields are ignored), with the plan's
+ * workspace in a fixed device array of TSNE_STATIC_SCRATCH_BYTES (128 MiB)
+ * that the library holds on each GPU it runs on until the process ends, and
+ * its host record in static storage.  That covers, for example, FP32 n <= 1e6
+ * with max_intervals <= 128, or FP64 n <= 2e5 with max_intervals <= 128.
+ *   desc   host; validated as for tsne_plan_create (TSNE_E_ARG,
+ *          TSNE_E_UNSUPPORTED); TSNE_E_WORKSPACE when
+ *          tsne_workspace_bytes(desc with nnz = 0) exceeds the scratch size.
+ *   Y      device [n, s], F_rep device [n, s] (written), both point-aligned
+ *          (TSNE_E_ARG otherwise); Z device double (written) or NULL.
+ *   stream hipStream_t or NULL.
+ * Every call re-initialises the scratch of the current device (geometry,
+ * counters, kernel spectra; the initialisation synchronises the stream), so
+ * no state carries over from an earlier call.  Calls on one GPU share that
+ * GPU's scratch: calls that overlap on one device (two host threads, or two
+ * streams whose work is still in flight) race and give undefined results.
+ * Device conditions (TSNE_E_CAPACITY, TSNE_E_NONFINITE) latched by a call
+ * leave F_rep and Z unwritten; they are not reported (there is no plan to
+ * query), so a caller that needs them uses tsne_repulsive. */
+tsne_status tsne_repulsive_static(const tsne_desc* desc, const void* Y, void* F_rep, double* Z,
+                                  void* stream);
+
 /* ---------------------------------------------------------------------- */
 /* Input affinities (Section 1.1) over the k nearest neighbours (Section 3) */
 /* ---------------------------------------------------------------------- */

@@ -423,52 +423,22 @@ static void fill_sched(Sched& s, const tsne_sched* c)
     s.recentre = c->recentre;
 }
 
-extern "C" {
-
-size_t tsne_workspace_bytes(const tsne_desc* desc)
+// Lay a plan over its workspace: the host image of the device record, the
+// launch prefix table, and the device state that must start at zero (the
+// geometry record, the schedule, status and counters, the cell counts).
+// Allocates nothing; synchronises the stream before returning.
+static tsne_status plan_init(tsne_plan* pl, const tsne_desc* desc, const Derived& o, char* b,
+                             hipStream_t st)
 {
-    Derived o;
-    if (derive(desc, o) != TSNE_OK) return 0;
-    return o.L.total;
-}
-
-const char* tsne_status_str(tsne_status s)
-{
-    switch (s) {
-    case TSNE_OK: return "ok";
-    case TSNE_E_ARG: return "invalid argument";
-    case TSNE_E_UNSUPPORTED: return "unsupported configuration";
-    case TSNE_E_WORKSPACE: return "workspace missing, misaligned or too small";
-    case TSNE_E_CAPACITY: return "box needs more intervals than max_intervals";
-    case TSNE_E_NONFINITE: return "non-finite coordinate in Y";
-    case TSNE_E_HIP: return "HIP runtime error";
-    case TSNE_E_STATE: return "call not valid in this plan state";
-    }
-    return "unknown status";
-}
-
-tsne_status tsne_plan_create(const tsne_desc* desc, void* workspace, size_t bytes, void* stream,
-                             tsne_plan** out)
-{
-    if (!out) return TSNE_E_ARG;
-    *out = nullptr;
-    Derived o;
-    tsne_status rs = derive(desc, o);
-    if (rs != TSNE_OK) return rs;
-    if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || bytes < o.L.total) return TSNE_E_WORKSPACE;
-
-    tsne_plan* pl = new (std::nothrow) tsne_plan();
-    if (!pl) return TSNE_E_HIP;
     pl->d = *desc;
     pl->o = o;
-    pl->st = static_cast<hipStream_t>(stream);
-    pl->ws = static_cast<char*>(workspace);
+    pl->st = st;
+    pl->ws = b;
     pl->cfg = cfg_of(*desc, o);
     pl->P_bound = false;
     pl->graph_ok = false;
     pl->args_valid = false;
 
-    char* b = pl->ws;
     const size_t* off = o.L.off;
     Inst& h = pl->h;
     std::memset(&h, 0, sizeof(h));
@@ -549,24 +519,62 @@ tsne_status tsne_plan_create(const tsne_desc* desc, void* workspace, size_t byte
     pl->dinst = reinterpret_cast<Inst*>(b + off[R_INST]);
     pl->dprefix = reinterpret_cast<int*>(b + off[R_PREFIX]);
 
-    // host images of the tables
-    std::vector<int> prefix(K_NKINDS * 2);
+    // host image of the launch prefix table (one instance)
+    int prefix[K_NKINDS * 2];
     for (int k = 0; k < K_NKINDS; ++k) {
         prefix[2 * k] = 0;
         prefix[2 * k + 1] = o.vb[k];
     }
-    hipStream_t st = pl->st;
-    bool ok = hip_ok(hipMemcpyAsync(pl->dinst, &h, sizeof(Inst), hipMemcpyHostToDevice, st)) &&
-              hip_ok(hipMemcpyAsync(pl->dprefix, prefix.data(), prefix.size() * sizeof(int),
-                                    hipMemcpyHostToDevice, st)) &&
-              hip_ok(hipMemsetAsync(b + off[R_GEOM], 0, sizeof(Geom), st)) &&
-              hip_ok(hipMemsetAsync(b + off[R_SCHED], 0, sizeof(Sched), st)) &&
-              hip_ok(hipMemsetAsync(b + off[R_SMALL], 0, 64, st)) &&
-              hip_ok(hipMemsetAsync(h.counts, 0, sizeof(int) * o.ncell_cap, st)) &&
-              hip_ok(hipStreamSynchronize(st));
-    if (!ok) {
+    const bool ok = hip_ok(hipMemcpyAsync(pl->dinst, &h, sizeof(Inst), hipMemcpyHostToDevice, st)) &&
+                    hip_ok(hipMemcpyAsync(pl->dprefix, prefix, sizeof(prefix), hipMemcpyHostToDevice, st)) &&
+                    hip_ok(hipMemsetAsync(b + off[R_GEOM], 0, sizeof(Geom), st)) &&
+                    hip_ok(hipMemsetAsync(b + off[R_SCHED], 0, sizeof(Sched), st)) &&
+                    hip_ok(hipMemsetAsync(b + off[R_SMALL], 0, 64, st)) &&
+                    hip_ok(hipMemsetAsync(h.counts, 0, sizeof(int) * o.ncell_cap, st)) &&
+                    hip_ok(hipStreamSynchronize(st));
+    return ok ? TSNE_OK : TSNE_E_HIP;
+}
+
+extern "C" {
+
+size_t tsne_workspace_bytes(const tsne_desc* desc)
+{
+    Derived o;
+    if (derive(desc, o) != TSNE_OK) return 0;
+    return o.L.total;
+}
+
+const char* tsne_status_str(tsne_status s)
+{
+    switch (s) {
+    case TSNE_OK: return "ok";
+    case TSNE_E_ARG: return "invalid argument";
+    case TSNE_E_UNSUPPORTED: return "unsupported configuration";
+    case TSNE_E_WORKSPACE: return "workspace missing, misaligned or too small";
+    case TSNE_E_CAPACITY: return "box needs more intervals than max_intervals";
+    case TSNE_E_NONFINITE: return "non-finite coordinate in Y";
+    case TSNE_E_HIP: return "HIP runtime error";
+    case TSNE_E_STATE: return "call not valid in this plan state";
+    }
+    return "unknown status";
+}
+
+tsne_status tsne_plan_create(const tsne_desc* desc, void* workspace, size_t bytes, void* stream,
+                             tsne_plan** out)
+{
+    if (!out) return TSNE_E_ARG;
+    *out = nullptr;
+    Derived o;
+    tsne_status rs = derive(desc, o);
+    if (rs != TSNE_OK) return rs;
+    if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || bytes < o.L.total) return TSNE_E_WORKSPACE;
+
+    tsne_plan* pl = new (std::nothrow) tsne_plan();
+    if (!pl) return TSNE_E_HIP;
+    rs = plan_init(pl, desc, o, static_cast<char*>(workspace), static_cast<hipStream_t>(stream));
+    if (rs != TSNE_OK) {
         delete pl;
-        return TSNE_E_HIP;
+        return rs;
     }
     *out = pl;
     return TSNE_OK;
@@ -883,6 +891,52 @@ tsne_status tsne_debug_export(tsne_plan* pl, int32_t what, void* dst, size_t* by
         return TSNE_E_HIP;
     *bytes = nb;
     return TSNE_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- repulsion without allocation
+
+// Scratch of tsne_repulsive_static: one plan workspace of at most
+// TSNE_STATIC_SCRATCH_BYTES in a file-scope device array, one copy per GPU
+// (each device holds it until the process ends).  Host code never passes the
+// array's name to a kernel or a copy: the name is a host-side stand-in, so its
+// device address is looked up once per device and kept in g_scratch.
+namespace {
+constexpr size_t kScratchBytes = (size_t)TSNE_STATIC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+static_assert(kScratchBytes % kAlign == 0, "scratch size must keep the workspace alignment");
+}  // namespace
+
+static __device__ __align__(256) char scratch[kScratchBytes];
+static char* g_scratch[kMaxDevices];            // device address of scratch, per device
+static tsne_plan g_static_plan[kMaxDevices];    // the plan laid over it, per device
+
+extern "C" {
+
+tsne_status tsne_repulsive_static(const tsne_desc* desc, const void* Y, void* F_rep, double* Z,
+                                  void* stream)
+{
+    if (!desc || !Y || !F_rep) return TSNE_E_ARG;
+    tsne_desc d = *desc;
+    d.nnz = 0;                       // the repulsion does not read P
+    Derived o;
+    tsne_status rs = derive(&d, o);
+    if (rs != TSNE_OK) return rs;
+    if (!point_aligned(d, Y) || !point_aligned(d, F_rep)) return TSNE_E_ARG;
+    if (o.L.total > kScratchBytes) return TSNE_E_WORKSPACE;
+    int dev = -1;
+    if (!hip_ok(hipGetDevice(&dev))) return TSNE_E_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return TSNE_E_UNSUPPORTED;
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        if (!hip_ok(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) || !p) return TSNE_E_HIP;
+        g_scratch[dev] = static_cast<char*>(p);
+    }
+    tsne_plan* pl = &g_static_plan[dev];
+    rs = plan_init(pl, &d, o, g_scratch[dev], static_cast<hipStream_t>(stream));
+    if (rs != TSNE_OK) return rs;
+    return tsne_repulsive(pl, Y, F_rep, Z);
 }
 
 }  // extern "C"

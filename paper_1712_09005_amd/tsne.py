@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtsne_mi355x.so")
 
 F32, F64 = 0, 1
+STATIC_SCRATCH_BYTES = 128 << 20     # TSNE_STATIC_SCRATCH_BYTES of include/tsne.h
 GRID_PAPER, GRID_FIXED = 0, 1
 FORM_A, FORM_B, FORM_V = 0, 1, 2
 _FORMS = {"A": FORM_A, "B": FORM_B, "V": FORM_V, FORM_A: FORM_A, FORM_B: FORM_B, FORM_V: FORM_V}
@@ -102,6 +103,7 @@ def lib():
             "tsne_plan_destroy": ([P], i32),
             "tsne_bind_P": ([P, P, P, P], i32),
             "tsne_repulsive": ([P, P, P, P], i32),
+            "tsne_repulsive_static": ([P, P, P, P, P], i32),
             "tsne_attractive": ([P, P, P], i32),
             "tsne_kl_divergence": ([P, P, P], i32),
             "tsne_knn": ([P, i64, i32, i32, P, P, P], i32),
@@ -301,6 +303,25 @@ class Plan:
         buf = (ctypes.c_char * nb.value)()
         _check(lib().tsne_debug_export(self._h, int(what), buf, ctypes.byref(nb)), "export")
         return bytes(buf)
+
+
+def repulsive_static(Y, desc: Desc, F=None, Z=None, stream=None):
+    """tsne_repulsive_static: the repulsion of desc at Y with the plan's
+    workspace in the library's fixed device scratch (nothing is allocated by
+    the call; F and Z may be passed in).  Returns (F_rep, Z)."""
+    n, s = int(desc.n), int(desc.s)
+    dt = torch.float32 if desc.dtype == F32 else torch.float64
+    if Y.dtype != dt or not Y.is_cuda or not Y.is_contiguous() or Y.numel() != n * s:
+        raise ValueError("Y must be a contiguous %s GPU tensor with n*s elements" % dt)
+    st = stream if stream is not None else torch.cuda.current_stream(Y.device)
+    with torch.cuda.stream(st):
+        if F is None:
+            F = torch.empty_like(Y)
+        if Z is None:
+            Z = torch.empty(1, dtype=torch.float64, device=Y.device)
+    _check(lib().tsne_repulsive_static(ctypes.byref(desc), _ptr(Y), _ptr(F), _ptr(Z),
+                                       ctypes.c_void_p(st.cuda_stream)), "tsne_repulsive_static")
+    return F, Z
 
 
 def _stream_ptr(stream):

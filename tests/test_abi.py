@@ -96,3 +96,21 @@ def test_pca_workspace_and_argument_checks(L):
     assert L.tsne_pca(ctypes.byref(d), z, z, z, z, z, ctypes.c_void_p(4096 + 64), 1 << 40, None) == 3
     bad = pca.make_desc(10, 10, k=5, l=12, its=1)
     assert L.tsne_pca(ctypes.byref(bad), z, z, z, z, z, z, 1 << 40, None) == 1
+
+
+def test_static_repulsion_argument_checks(L):
+    """tsne_repulsive_static validates its descriptor and the scratch size on
+    the host, before any device work."""
+    from paper_1712_09005_amd import tsne
+    z = ctypes.c_void_p(4096)
+    assert L.tsne_repulsive_static(None, z, z, None, None) == 1
+    assert L.tsne_repulsive_static(ctypes.byref(tsne.make_desc(100, 3)), z, z, None, None) == 1
+    assert L.tsne_repulsive_static(ctypes.byref(tsne.make_desc(100, 2, p=9)), z, z, None, None) == 2
+    # a plan larger than the scratch array is refused with TSNE_E_WORKSPACE
+    big = tsne.make_desc(1_000_000, 2, p=5, max_intervals=512)
+    assert tsne.workspace_bytes(big) > tsne.STATIC_SCRATCH_BYTES
+    assert L.tsne_repulsive_static(ctypes.byref(big), z, z, None, None) == 3
+    # misaligned Y (FP32 2-D points are 8 bytes)
+    small = tsne.make_desc(1000, 2, p=5, max_intervals=64)
+    assert tsne.workspace_bytes(small) <= tsne.STATIC_SCRATCH_BYTES
+    assert L.tsne_repulsive_static(ctypes.byref(small), ctypes.c_void_p(4100), z, None, None) == 1
