@@ -68,6 +68,7 @@ def _load():
             "oracle_interp_spread": [i64, i32, P, P, f64, P, i32, i32, P],
             "oracle_interp_rows": [i64, i32, P, P, f64, P, i32, i32, i32,
                                    P, P, i64, P],
+            "oracle_interp_gather": [i64, i32, P, P, f64, P, i32, i32, P, P],
             "oracle_update": [i64, i32, P, P, P, P, P, f64, f64, f64, f64,
                               f64, f64, i32],
         }
@@ -296,6 +297,110 @@ def interp_rows(Y, origin, w_int, n_int, rows, W, p=3, form=FORM_A, kind=KERNEL_
     if rc != 0:
         raise ValueError("oracle_interp_rows: bad arguments")
     return phi
+
+
+def _kernel_fn(kind, kernel):
+    """Kernel of Step 2 as a function of the lag vector (z_0(, z_1)) in Y units:
+    1 = K1, 2 = K2, 3 / 4 = the odd kernels z_0 K2, z_1 K2 (the pair of
+    Section 2, eq. (kers); KERNEL_POLY is the polynomial test family)."""
+    def k(z):
+        r2 = sum(c * c for c in z)
+        if kind == KERNEL_TSNE:
+            k1 = 1.0 / (1.0 + r2)
+            k2 = k1 * k1
+        else:
+            k2 = 2.0 + r2 / 8.0
+            k1 = (1.0 + r2) * k2
+        if kernel == 1:
+            return k1
+        if kernel == 2:
+            return k2
+        return z[kernel - 3] * k2
+    return k
+
+
+def grid_conv_fft(W, h, kernel, kind=KERNEL_TSNE):
+    """Step 2 (eq. (equikereval2)) as a circulant convolution by FFT (Section
+    2.2): the Toeplitz kernel matrix of an ng-node axis is embedded in a
+    circulant of length 2 ng per axis, lag j at index j mod 2 ng (the lag ng
+    is never used by an ng-node grid and is set to zero), and applied with
+    numpy's FFT in FP64.  Same grid layout and kernels as ``grid_conv``, which
+    it must reproduce to rounding."""
+    W = _f64(W)
+    shape = W.shape                                       # (ng1,) ng0
+    Lx = tuple(2 * g for g in shape)
+    # lag of each circulant index along each axis: j for j < ng, j - 2 ng above
+    lags = []
+    for g, L in zip(shape, Lx):
+        j = np.arange(L)
+        lag = np.where(j < g, j, j - L).astype(np.float64)
+        lag[g] = 0.0
+        lags.append(lag)
+    grids = np.meshgrid(*lags, indexing="ij")             # axis order (g1,) g0
+    z = [h * grids[-1]] + ([h * grids[0]] if W.ndim == 2 else [])   # (z_0, z_1)
+    T = np.asarray(_kernel_fn(kind, kernel)(z), dtype=np.float64)
+    if T.ndim == 0:
+        T = np.full(Lx, float(T))
+    # the unused lag ng of each axis carries no kernel value
+    for ax, g in enumerate(shape):
+        idx = [slice(None)] * W.ndim
+        idx[ax] = g
+        T[tuple(idx)] = 0.0
+    Wp = np.zeros(Lx)
+    Wp[tuple(slice(0, g) for g in shape)] = W
+    axes = tuple(range(W.ndim))
+    V = np.fft.irfftn(np.fft.rfftn(Wp, axes=axes) * np.fft.rfftn(T, axes=axes), s=Lx, axes=axes)
+    return np.ascontiguousarray(V[tuple(slice(0, g) for g in shape)])
+
+
+def interp_gather(Y, origin, w_int, n_int, V, p=3):
+    """Step 3 alone: phi [N, P] at every point from the potential grids
+    V [P, (ng1,) ng0] (``interp_rep(want_grids=True)['V']`` layout)."""
+    Y = _f64(Y)
+    n, s = Y.shape
+    V = _f64(V)
+    npot = V.shape[0]
+    phi = np.empty((n, npot))
+    rc = _load().oracle_interp_gather(n, s, _ptr(Y), _ptr(_f64(origin)), float(w_int),
+                                      _ptr(_axes(n_int, s)), int(p), int(npot),
+                                      _ptr(np.ascontiguousarray(V.reshape(npot, -1))), _ptr(phi))
+    if rc != 0:
+        raise ValueError("oracle_interp_gather: bad arguments")
+    return phi
+
+
+def _pots(form, s):
+    """(kernel, charge) of each potential, in the order of interp_rep."""
+    if form == FORM_V:
+        return [(1, 0)] + [(3 + d, 0) for d in range(s)]
+    first = (1, 0) if form == FORM_A else (2, s + 1)
+    return [first, (2, 0)] + [(2, 1 + d) for d in range(s)]
+
+
+def interp_rep_fft(Y, origin, w_int, n_int, p=3, form=FORM_A, kind=KERNEL_TSNE,
+                   want_grids=False):
+    """``interp_rep`` with Step 2 by FFT (``grid_conv_fft``) instead of the
+    direct double sum, for grids too large for the direct sum (N = 1e6 boxes):
+    Step 1 ``interp_spread``, Step 2 ``grid_conv_fft`` per potential, Step 3
+    ``interp_gather``, the Appendix assembly (``assemble_rows``), Z = sum h1
+    - N K1(0) and F = numerator / Z.  Same outputs as ``interp_rep``."""
+    Y = _f64(Y)
+    n, s = Y.shape
+    ax = _axes(n_int, s)
+    shape = tuple(int(x) * p for x in ax[::-1])
+    Wf = interp_spread(Y, origin, w_int, ax, p, form)
+    W = Wf.reshape((Wf.shape[0],) + shape)
+    h = w_int / p
+    V = np.stack([grid_conv_fft(W[c], h, k, kind) for k, c in _pots(form, s)])
+    phi = interp_gather(Y, origin, w_int, ax, V, p)
+    h1, num = assemble_rows(Y, origin, w_int, ax, phi, form)
+    k10 = 1.0 if kind == KERNEL_TSNE else 2.0
+    Z = float(h1.sum() - n * k10)
+    out = dict(F=num / Z, Z=Z, phi=phi, h1=h1)
+    if want_grids:
+        out["W"] = W
+        out["V"] = V
+    return out
 
 
 def centre(origin, w_int, n_int):

@@ -498,6 +498,45 @@ int oracle_interp_spread(int64_t n, int s, const double* Y, const double* origin
     return 0;
 }
 
+/* Step 3 alone: phi [n][np] at every point from given potential grids
+ * V [np][ng^s] (grid layout of oracle_interp_rep), phi_k(y_i) =
+ * sum_m L_m(y_i) V_k[node m of the interval of y_i] (Section 2.2, Step 3;
+ * tensor-product nodes for s = 2, Section 2.4). */
+int oracle_interp_gather(int64_t n, int s, const double* Y, const double* origin,
+                         double w, const int* n_int, int p, int np, const double* V,
+                         double* phi)
+{
+    if (s < 1 || s > 2 || p < 1 || np < 1) return -1;
+    for (int d = 0; d < s; ++d)
+        if (n_int[d] < 1) return -1;
+    const int ng = n_int[0] * p;
+    const int64_t tn = (int64_t)ng * ((s == 2) ? n_int[1] * p : 1);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        int c0 = 0, c1 = 0;
+        double t0, t1 = 0.0, L0[16], L1[16];
+        locate(Y[i * s], origin[0], w, n_int[0], &c0, &t0);
+        oracle_lagrange(p, t0, L0);
+        if (s == 2) {
+            locate(Y[i * s + 1], origin[1], w, n_int[1], &c1, &t1);
+            oracle_lagrange(p, t1, L1);
+        } else {
+            L1[0] = 1.0;
+        }
+        const int p1 = (s == 2) ? p : 1;
+        for (int k = 0; k < np; ++k) {
+            double acc = 0.0;
+            for (int m1 = 0; m1 < p1; ++m1)
+                for (int m0 = 0; m0 < p; ++m0) {
+                    const int64_t g = (int64_t)(c1 * p + m1) * ((s == 2) ? ng : 0) + c0 * p + m0;
+                    acc += L0[m0] * L1[m1] * V[(int64_t)k * tn + g];
+                }
+            phi[i * np + k] = acc;
+        }
+    }
+    return 0;
+}
+
 /* Per-point interpolated sums for a few listed rows, computing V only at the
  * nodes those rows read: each node value is the full direct sum of Step 2
  * over every node.  Needs the complete charge grids W (oracle_interp_spread).

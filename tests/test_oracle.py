@@ -541,6 +541,58 @@ def test_interp_rows_matches_full():
         np.testing.assert_allclose(h1, r["h1"][rows], rtol=1e-11)
 
 
+@pytest.mark.parametrize("shape", [(37,), (12, 12), (7, 12), (13, 8)])
+@pytest.mark.parametrize("kernel", [1, 2, 3, 4])
+@pytest.mark.parametrize("kind", [oracle.KERNEL_TSNE, oracle.KERNEL_POLY])
+def test_grid_conv_fft_equals_direct(shape, kernel, kind):
+    """Step 2 by FFT (the oracle's route for full-size grids) reproduces the
+    direct Toeplitz product of ``grid_conv`` (itself pinned against circulant
+    convolutions above) for every kernel, square and rectangular grids, both
+    axis orders; an off-by-one lag, a missing sign or a swapped axis fails."""
+    if kernel == 4 and len(shape) == 1:
+        pytest.skip("no second axis")
+    rng = np.random.default_rng(sum(shape) * 7 + kernel + 3 * kind)
+    W = rng.standard_normal(shape)
+    h = 0.31
+    V = oracle.grid_conv(W, h, kernel, kind)
+    Vf = oracle.grid_conv_fft(W, h, kernel, kind)
+    np.testing.assert_allclose(Vf, V, rtol=0, atol=1e-12 * np.abs(V).max())
+
+
+def test_interp_gather_matches_interp_rep():
+    """Step 3 alone from the potential grids reproduces the potentials of the
+    full scheme at every point (square and rectangular boxes, 1-D and 2-D)."""
+    for s, rect in ((1, False), (2, False), (2, True)):
+        Y = inputs.mixture_embedding(400, s, 3, -6, 6, 1.0, seed=11 + s).astype(np.float64)
+        if rect:
+            Y[:, 1] *= 0.3
+        o, w, m = oracle.geometry(Y, "fixed", 1, 0.6, rect=rect)
+        for form in (oracle.FORM_A, oracle.FORM_B, oracle.FORM_V):
+            r = oracle.interp_rep(Y, o, w, m, 4, form, want_grids=True)
+            phi = oracle.interp_gather(Y, o, w, m, r["V"], 4)
+            np.testing.assert_allclose(phi, r["phi"], rtol=1e-13, atol=1e-13 * np.abs(r["phi"]).max())
+
+
+@pytest.mark.parametrize("s,rect", [(1, False), (2, False), (2, True)])
+@pytest.mark.parametrize("form", [oracle.FORM_A, oracle.FORM_B, oracle.FORM_V])
+def test_interp_rep_fft_matches_direct_step2(s, rect, form):
+    """The interpolation scheme with Step 2 by FFT equals the scheme with the
+    direct Step 2 (forces, Z and h1), and both sit within the interpolation
+    error of the direct O(N^2) sum."""
+    Y = inputs.mixture_embedding(700, s, 4, -8, 8, 1.2, seed=21 + s).astype(np.float64)
+    if rect:
+        Y[:, 1] *= 0.25
+    o, w, m = oracle.geometry(Y, "fixed", 1, 0.5, rect=rect)
+    a = oracle.interp_rep(Y, o, w, m, 5, form)
+    b = oracle.interp_rep_fft(Y, o, w, m, 5, form)
+    np.testing.assert_allclose(b["F"], a["F"], rtol=0, atol=1e-11 * np.abs(a["F"]).max())
+    assert abs(b["Z"] - a["Z"]) <= 1e-12 * a["Z"]
+    # form B forms h1 from cancelling K2 sums, so FFT rounding is amplified there
+    np.testing.assert_allclose(b["h1"], a["h1"], rtol=1e-10)
+    F, Z = oracle.direct_rep(Y)
+    assert _rel(b["F"], F) < 1e-3 and abs(b["Z"] - Z) < 1e-4 * Z
+
+
 # --------------------------------------------------------------------------
 # Update (gradient of Section 1.1 with exaggeration, Section 1.2 / Section 4)
 # --------------------------------------------------------------------------
