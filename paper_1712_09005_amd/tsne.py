@@ -272,7 +272,7 @@ class Plan:
     def step(self, Y, uY, gains, sched: Schedule, it: int):
         for t, nm in ((Y, "Y"), (uY, "uY"), (gains, "gains")):
             self._vec(t, nm)
-        sc = sched.c()
+        sc = (sched if sched is not None else Schedule()).c()
         self._enter()
         _check(lib().tsne_step(self._h, _ptr(Y), _ptr(uY), _ptr(gains), ctypes.byref(sc), int(it)),
                "tsne_step")
@@ -281,7 +281,7 @@ class Plan:
     def run(self, Y, uY, gains, sched: Schedule, it0: int, n_it: int):
         for t, nm in ((Y, "Y"), (uY, "uY"), (gains, "gains")):
             self._vec(t, nm)
-        sc = sched.c()
+        sc = (sched if sched is not None else Schedule()).c()
         self._enter()
         _check(lib().tsne_run(self._h, _ptr(Y), _ptr(uY), _ptr(gains), ctypes.byref(sc),
                               int(it0), int(n_it)), "tsne_run")
@@ -465,7 +465,7 @@ class Batch:
                 torch.as_tensor(gains, dtype=self.dtype).to(self.device).contiguous()
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
         slot = ctypes.c_int32(-1)
-        sc = sched.c()
+        sc = (sched if sched is not None else Schedule()).c()
         _check(lib().tsne_batch_admit(self._h, ctypes.byref(d), _ptr(job["ws"]), nbytes,
                                       _ptr(job["Y"]), _ptr(job["uY"]), _ptr(job["gains"]),
                                       _ptr(job["rp"]), _ptr(job["col"]), _ptr(job["val"]),
