@@ -59,7 +59,9 @@ typedef enum {
     TSNE_E_CAPACITY = 4,     /* the box needs more intervals than max_intervals */
     TSNE_E_NONFINITE = 5,    /* a coordinate of Y is NaN or infinite */
     TSNE_E_HIP = 6,          /* a HIP runtime call failed */
-    TSNE_E_STATE = 7         /* call not valid in the plan's state (e.g. no P bound) */
+    TSNE_E_STATE = 7,        /* call not valid in the plan's state (e.g. no P bound) */
+    TSNE_E_INTERNAL = 8      /* the binning's look-back did not complete (latched on the
+                                device; the iteration's results are invalid) */
 } tsne_status;
 
 typedef enum { TSNE_F32 = 0, TSNE_F64 = 1 } tsne_dtype;
@@ -117,6 +119,11 @@ typedef struct {
                                 gets min(N_int, max(min_intervals, ceil(L_d / w)))
                                 intervals, and each axis its own FFT length.
                                 Ignored for s = 1. */
+    int32_t keep_h1;         /* 1: keep each point's K1 sum h1_i = sum_j K1(y_i, y_j)
+                                (self pair included, so Z = sum_i h1_i - n) of the
+                                last repulsion, FP64 in point order, for
+                                tsne_debug_export(what = 5); the workspace grows by
+                                8 n bytes.  0: not kept. */
 } tsne_desc;
 
 /* Descent schedule, indexed by the absolute iteration it:
@@ -224,8 +231,11 @@ tsne_status tsne_query(tsne_plan* plan, tsne_stats* out);
  * inspection; synchronises).  what: 0 = charge grids W [C][n_cap][n_cap] (s=2)
  * or [C][n_cap] (s=1), 1 = potential grids V [s+2][...] same layout,
  * 2 = unnormalised repulsion numerators [n, s], 3 = cell start offsets
- * [N_int^s + 1] (int32).  *bytes is the size copied (or needed if dst_host
- * is NULL). */
+ * [N_int^s + 1] (int32), 4 = the sorted order [n] (int32: point at each
+ * sorted position; points by cell, x interval + N_int * y interval, and by
+ * index within a cell), 5 = h1 [n] (double, point order; TSNE_E_STATE unless
+ * the plan was created with keep_h1).  *bytes is the size copied (or needed
+ * if dst_host is NULL). */
 tsne_status tsne_debug_export(tsne_plan* plan, int32_t what, void* dst_host,
                               size_t* bytes);
 

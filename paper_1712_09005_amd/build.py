@@ -13,7 +13,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtsne_mi355x.so")
-SOURCES = ["k_points.hip", "k_attr.hip", "k_fft.hip", "k_affinity.hip", "k_pca.hip", "tsne_api.cpp"]
+SOURCES = ["k_points.hip", "k_sort.hip", "k_attr.hip", "k_fft.hip", "k_affinity.hip", "k_pca.hip",
+           "tsne_api.cpp"]
 ARCH = os.environ.get("TSNE_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

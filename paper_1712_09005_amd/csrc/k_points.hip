@@ -6,37 +6,11 @@
 //
 // Every kernel walks the virtual blocks of its kind over all instances of the
 // launch (VB_BEGIN/VB_END), so one launch serves a single plan or a batch.
-#include <math.h>
-
-#include "launch.h"
+#include "k_common.h"
 
 namespace tsne {
 
 // ---------------------------------------------------------------- helpers
-
-template <typename T> __device__ __forceinline__ T ld(const void* p, int64_t i)
-{
-    return static_cast<const T*>(p)[i];
-}
-
-// Interval of a coordinate value and its local coordinate:
-// u = (y - o) / w, l = clamp(floor(u), 0, n_int - 1), t = u - l.
-// Evaluated in double for both element types: the input value is exact in
-// double, so the interval is the same in every kernel and t carries no error
-// from the box offset (FP32 t would lose |u| * 2^-24 absolute).
-template <typename T>
-__device__ __forceinline__ int locate(T y, double o, double w, int n_int, T& t)
-{
-#pragma clang fp contract(off)
-    const double u = ((double)y - o) / w;
-    const double f = floor(u);
-    int c;
-    if (!(f >= 0.0)) c = 0;
-    else if (f > (double)(n_int - 1)) c = n_int - 1;
-    else c = (int)f;
-    t = (T)(u - (double)c);
-    return c;
-}
 
 // 1 / prod_{k != m} (m - k), the denominator of the Lagrange basis on nodes
 // m + 1/2 (in units of the node spacing).
@@ -106,46 +80,6 @@ hipError_t launch_set_args(Inst* inst, const CallArgs& a, hipStream_t st)
     hipLaunchKernelGGL(k_set_args, dim3(1), dim3(64), 0, st, inst, a);
     return hipGetLastError();
 }
-
-// One point's S coordinates, moved with one vector access when S = 2 (the
-// [N, S] arrays are 8- or 16-byte aligned per point).
-template <typename T, int S> struct Pt {
-    T v[S];
-    __device__ __forceinline__ static Pt load(const T* a, int64_t i)
-    {
-        Pt p;
-#pragma unroll
-        for (int d = 0; d < S; ++d) p.v[d] = a[i * S + d];
-        return p;
-    }
-    __device__ __forceinline__ void store(T* a, int64_t i) const
-    {
-#pragma unroll
-        for (int d = 0; d < S; ++d) a[i * S + d] = v[d];
-    }
-};
-template <typename T> struct Pt2Vec;
-template <> struct Pt2Vec<float> { typedef float2 t; };
-template <> struct Pt2Vec<double> { typedef double2 t; };
-template <typename T> struct Pt<T, 2> {
-    typedef typename Pt2Vec<T>::t V;
-    T v[2];
-    __device__ __forceinline__ static Pt load(const T* a, int64_t i)
-    {
-        const V q = reinterpret_cast<const V*>(a)[i];
-        Pt p;
-        p.v[0] = q.x;
-        p.v[1] = q.y;
-        return p;
-    }
-    __device__ __forceinline__ void store(T* a, int64_t i) const
-    {
-        V q;
-        q.x = v[0];
-        q.y = v[1];
-        reinterpret_cast<V*>(a)[i] = q;
-    }
-};
 
 // ---------------------------------------------------------------- box geometry
 
@@ -274,6 +208,8 @@ __global__ __launch_bounds__(256) void k_geom(LaunchMap map)
     Geom& G = *I.geom;
     const bool run = live_pre(I);
     if (run) {
+        // digit counts of this iteration's radix passes start from zero
+        for (int k = threadIdx.x; k < I.npass * kDigitBins; k += 256) I.ghist[k] = 0u;
         const int nb = I.nb_box;
         double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
         double sm[2] = {0.0, 0.0}, bad = 0.0;
@@ -390,207 +326,17 @@ __global__ __launch_bounds__(256) void k_geom(LaunchMap map)
                 G.spec_h = G.h;
                 G.spec_M = G.M;
                 G.spec_My = G.My;
-                G.pbuf ^= 1;                   // this iteration's sorted order goes here
+                // radix sort of this iteration: digit width for the cell count,
+                // a new epoch for its look-back words, tile tickets from zero
+                const int nc1 = G.n_cells - 1;
+                const int bits = (nc1 > 0) ? 32 - __clz(nc1) : 1;
+                G.sort_bits = (bits + I.npass - 1) / I.npass;
+                G.sort_epoch += 1u;
+                for (int q = 0; q < I.npass; ++q) I.tickets[q] = 0u;
             }
         }
     } else if (threadIdx.x == 0) {
         G.active = 0;
-    }
-    VB_END
-}
-
-// ---------------------------------------------------------------- binning
-
-// Cell key of each point and its rank among the points of its cell (the
-// "for each interval" loops of Algorithm 1 become a counting sort by cell).
-// Points are visited in the previous iteration's sorted order, so neighbouring
-// lanes mostly share a cell: each run of equal keys in a wave takes its ranks
-// with one atomic.  key/rank are stored by visit position.
-template <typename T, int S>
-__global__ __launch_bounds__(256) void k_key(LaunchMap map)
-{
-    VB_BEGIN(map, K_KEY)
-    if (live(I)) {
-        const Geom& G = *I.geom;
-        const int64_t pos = (int64_t)lb * 256 + threadIdx.x;
-        const int lane = threadIdx.x & 63;
-        const bool valid = pos < I.n;
-        int key = -1;
-        int i = 0;
-        if (valid) {
-            const int* prev = I.perm + (int64_t)(G.pbuf ^ 1) * I.n;
-            i = G.perm_valid ? prev[pos] : (int)pos;
-            const Pt<T, S> y = Pt<T, S>::load(static_cast<const T*>(I.Yin), i);
-            T t;
-            key = locate<T>(y.v[0], G.origin[0], G.w, G.n_int, t);
-            if (S == 2) key += G.n_int * locate<T>(y.v[S - 1], G.origin[1], G.w, G.n_int_y, t);
-        }
-        const int kprev = __shfl_up(key, 1, 64);
-        const bool head = (lane == 0) || (kprev != key);
-        const unsigned long long hm = __ballot(head);
-        const unsigned long long upto = (lane == 63) ? ~0ull : ((1ull << (lane + 1)) - 1ull);
-        const int run_start = 63 - __clzll(hm & upto);
-        const unsigned long long above = (lane == 63) ? 0ull : (hm >> (lane + 1));
-        const int run_end = (above == 0ull) ? 63 : lane + __ffsll((long long)above) - 1;
-        int base = 0;
-        if (valid && head) base = atomicAdd(&I.counts[key], run_end - run_start + 1);
-        base = __shfl(base, run_start, 64);
-        if (valid) {
-            I.key[pos] = key;
-            I.rank[pos] = base + (lane - run_start);
-        }
-    }
-    VB_END
-}
-
-// Exclusive scans of the per-cell point counts and item counts (items are
-// runs of at most kpts points of one cell), tile sums first.
-__device__ __forceinline__ int items_of(int count, int kpts) { return (count + kpts - 1) / kpts; }
-
-__global__ __launch_bounds__(256) void k_scan_a(LaunchMap map)
-{
-    __shared__ int sh[2][4];
-    VB_BEGIN(map, K_SCAN_A)
-    if (live(I)) {
-        const int ncell = I.geom->n_cells;
-        const int base = lb * 1024 + threadIdx.x * 4;
-        int c = 0, it = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int e = base + k;
-            if (e < ncell) {
-                const int v = I.counts[e];
-                c += v;
-                it += items_of(v, I.kpts);
-            }
-        }
-        c = wave_sum(c);
-        it = wave_sum(it);
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        __syncthreads();
-        if (lane == 0) { sh[0][wv] = c; sh[1][wv] = it; }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            I.scan_part[2 * lb] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
-            I.scan_part[2 * lb + 1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
-        }
-    }
-    VB_END
-}
-
-// Inclusive wave scan of an int.
-__device__ __forceinline__ int wave_incl_scan(int v)
-{
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int u = __shfl_up(v, o, 64);
-        if (lane >= o) v += u;
-    }
-    return v;
-}
-
-__global__ __launch_bounds__(256) void k_scan_b(LaunchMap map)
-{
-    constexpr int kSerialItems = 16;     // cells with more items are filled by the whole block
-    __shared__ int sh[2][4];
-    __shared__ int off[2];
-    __shared__ int nbig;
-    __shared__ int big[1024][3];         // (cell, first item, items)
-    VB_BEGIN(map, K_SCAN_B)
-    if (live(I)) {
-        const int ncell = I.geom->n_cells;
-        const int ntile = (ncell + 1023) / 1024;
-        if (lb < ntile) {
-            // offset of this tile: sum of earlier tile sums
-            int oc = 0, oi = 0;
-            for (int k = threadIdx.x; k < lb; k += 256) {
-                oc += I.scan_part[2 * k];
-                oi += I.scan_part[2 * k + 1];
-            }
-            oc = wave_sum(oc);
-            oi = wave_sum(oi);
-            const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-            __syncthreads();
-            if (lane == 0) { sh[0][wv] = oc; sh[1][wv] = oi; }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                off[0] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
-                off[1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
-            }
-            if (threadIdx.x == 0) nbig = 0;
-            __syncthreads();
-            const int base = lb * 1024 + threadIdx.x * 4;
-            int cv[4], iv[4], c = 0, it = 0;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int e = base + k;
-                cv[k] = (e < ncell) ? I.counts[e] : 0;
-                iv[k] = items_of(cv[k], I.kpts);
-                c += cv[k];
-                it += iv[k];
-            }
-            int ic = wave_incl_scan(c), ii = wave_incl_scan(it);
-            __syncthreads();
-            if (lane == 63) { sh[0][wv] = ic; sh[1][wv] = ii; }
-            __syncthreads();
-            int pc = off[0], pi = off[1];
-            for (int w = 0; w < wv; ++w) { pc += sh[0][w]; pi += sh[1][w]; }
-            pc += ic - c;
-            pi += ii - it;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int e = base + k;
-                if (e < ncell) {
-                    I.cell_start[e] = pc;
-                    I.item_start[e] = pi;
-                    if (iv[k] <= kSerialItems) {
-                        for (int q = 0; q < iv[k]; ++q) I.item_cell[pi + q] = e;
-                    } else {
-                        const int b = atomicAdd(&nbig, 1);   // at most one per cell of the tile
-                        big[b][0] = e;
-                        big[b][1] = pi;
-                        big[b][2] = iv[k];
-                    }
-                    I.counts[e] = 0;          // ready for the next iteration
-                    if (e == ncell - 1) {
-                        I.cell_start[ncell] = pc + cv[k];
-                        I.item_start[ncell] = pi + iv[k];
-                    }
-                }
-                pc += cv[k];
-                pi += iv[k];
-            }
-            // cells with many items (a small box holding many points): the
-            // block's four waves take them in turn, each wave's lanes writing
-            // one cell's item -> cell entries
-            __syncthreads();
-            for (int b = wv; b < nbig; b += 4) {
-                const int e = big[b][0], p0 = big[b][1], m = big[b][2];
-                for (int q = lane; q < m; q += 64) I.item_cell[p0 + q] = e;
-            }
-            __syncthreads();
-        }
-    }
-    VB_END
-}
-
-// Scatter: this iteration's sorted order and sorted copy of Y.
-template <typename T, int S>
-__global__ __launch_bounds__(256) void k_scatter(LaunchMap map)
-{
-    VB_BEGIN(map, K_SCATTER)
-    if (live(I)) {
-        const Geom& G = *I.geom;
-        const int64_t pos = (int64_t)lb * 256 + threadIdx.x;
-        if (pos < I.n) {
-            const int* prev = I.perm + (int64_t)(G.pbuf ^ 1) * I.n;
-            int* cur = I.perm + (int64_t)G.pbuf * I.n;
-            const int i = G.perm_valid ? prev[pos] : (int)pos;
-            const int np_ = I.cell_start[I.key[pos]] + I.rank[pos];
-            cur[np_] = i;
-            Pt<T, S>::load(static_cast<const T*>(I.Yin), i).store(static_cast<T*>(I.sY), np_);
-        }
     }
     VB_END
 }
@@ -896,13 +642,14 @@ __global__ __launch_bounds__(256) void k_gather(LaunchMap map)
                 h1 = (1.0 + r2c) * (double)phi[1] - 2.0 * dot * inv_qs +
                      (double)phi[0] * inv_qs * inv_qs;
             }
-            const int i = I.perm[(int64_t)G.pbuf * I.n + pos];
+            const int i = I.perm[pos];
             Pt<T, S> rv;
 #pragma unroll
             for (int d = 0; d < S; ++d)
                 rv.v[d] = (FORM == 2) ? phi[1 + d]
                                       : (T)(yc[d] * (double)phi[1] - (double)phi[(2 + d) % NP] * inv_qs);
             rv.store(static_cast<T*>(I.R), i);
+            if (I.h1keep) I.h1keep[i] = h1;
             h1d = h1;
         }
         const double bs = block_sum_d(h1d, sh);
@@ -912,8 +659,7 @@ __global__ __launch_bounds__(256) void k_gather(LaunchMap map)
 }
 
 // One block per instance: Z = sum_i h1_i - N (the self pairs, K1(0) = 1),
-// from the gather's block partials in a fixed order.  Also marks the sorted
-// order of this iteration as available to the next one.
+// from the gather's block partials in a fixed order.
 __global__ __launch_bounds__(256) void k_zsum(LaunchMap map)
 {
     __shared__ double sh[8];
@@ -936,7 +682,6 @@ __global__ __launch_bounds__(256) void k_zsum(LaunchMap map)
         if (threadIdx.x == 0) {
             z -= (double)I.n;
             I.geom->Z = z;
-            I.geom->perm_valid = 1;
             if (I.Zout) *I.Zout = z;
         }
     }
@@ -1037,6 +782,8 @@ hipError_t launch_fft_kind(int kind, const Cfg& c, const LaunchMap& map, const L
                            hipStream_t st);
 hipError_t launch_attr_kind(int kind, const Cfg& c, const LaunchMap& map, const Launch& l,
                             hipStream_t st);
+hipError_t launch_sort_kind(int kind, const Cfg& c, const LaunchMap& map, const Launch& l,
+                            hipStream_t st);
 
 template <typename T, int S, int P, int FORM>
 static hipError_t launch_pts(int kind, const Cfg& c, const LaunchMap& map, const Launch& l,
@@ -1045,10 +792,6 @@ static hipError_t launch_pts(int kind, const Cfg& c, const LaunchMap& map, const
     dim3 g(l.grid), b(l.block);
     switch (kind) {
     case K_BOX: hipLaunchKernelGGL((k_box<T, S>), g, b, 0, st, map); break;
-    case K_KEY: hipLaunchKernelGGL((k_key<T, S>), g, b, 0, st, map); break;
-    case K_SCAN_A: hipLaunchKernelGGL(k_scan_a, g, b, 0, st, map); break;
-    case K_SCAN_B: hipLaunchKernelGGL(k_scan_b, g, b, 0, st, map); break;
-    case K_SCATTER: hipLaunchKernelGGL((k_scatter<T, S>), g, b, 0, st, map); break;
     case K_SPREAD: hipLaunchKernelGGL((k_spread<T, S, P, FORM>), g, b, 0, st, map); break;
     case K_FIX: hipLaunchKernelGGL((k_spread_fix<T, S, P, FORM>), g, b, 0, st, map); break;
     case K_GATHER: hipLaunchKernelGGL((k_gather<T, S, P, FORM>), g, b, 0, st, map); break;
@@ -1102,6 +845,8 @@ hipError_t launch_kind(int kind, const Cfg& c, const LaunchMap& map, const Launc
     case K_ATTR: case K_ATTR_ALL: case K_ATTR_T: case K_ATTR_T_ALL: case K_ASUM: case K_KL_ATTR:
     case K_KL: case K_KLSUM:
         return launch_attr_kind(kind, c, map, l, st);
+    case K_KEY: case K_SORT0: case K_SORT1: case K_SORT2: case K_BOUNDS: case K_SCAN_A: case K_SCAN_B:
+        return launch_sort_kind(kind, c, map, l, st);
     default:
         return c.dtype == 0 ? pts_s<float>(kind, c, map, l, st) : pts_s<double>(kind, c, map, l, st);
     }

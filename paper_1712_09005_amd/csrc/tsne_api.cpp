@@ -70,13 +70,15 @@ struct Layout {
 };
 
 enum Region {
-    R_INST, R_PREFIX, R_GEOM, R_SCHED, R_SMALL, R_BOX, R_COUNTS, R_CSTART, R_ISTART, R_SCAN,
-    R_ICELL, R_KEY, R_RANK, R_PERM, R_SY, R_CARRY, R_W, R_X, R_XC, R_V, R_SPEC, R_TW, R_TWY, R_COS, R_CV,
-    R_SPECTMP, R_KTAB, R_CCOS, R_R, R_FA, R_FAP, R_SPLIT, R_TOFF, R_EPACK, R_EVAL, R_ZPART, R_KLPART, R_N
+    R_INST, R_PREFIX, R_GEOM, R_SCHED, R_SMALL, R_BOX, R_CSTART, R_ISTART, R_SCAN,
+    R_ICELL, R_KEY, R_KV, R_SKEY, R_GHIST, R_LOOK, R_PERM, R_SY, R_CARRY, R_W, R_X, R_XC, R_V, R_SPEC,
+    R_TW, R_TWY, R_COS, R_CV, R_SPECTMP, R_KTAB, R_CCOS, R_R, R_FA, R_FAP, R_SPLIT, R_TOFF, R_EPACK,
+    R_EVAL, R_ZPART, R_KLPART, R_H1, R_N
 };
 
 struct Derived {
     int s, p, nc, np, tsz, max_int, n_cap, M, half, ncell_cap, items_cap, kpts, lpr;
+    int npass, ntiles_sort;
     int nstages, radix[kMaxStages], rmin;
     int slabs, slab_w;
     int tiled, tile_bi, tile_bj, tile_ni, tile_nj;
@@ -109,6 +111,7 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     if (d->attr_slabs < 0 || d->attr_slabs > 64) return TSNE_E_ARG;
     if (d->attr_layout < 0 || d->attr_layout > 2) return TSNE_E_ARG;
     if (d->rect != 0 && d->rect != 1) return TSNE_E_ARG;
+    if (d->keep_h1 != 0 && d->keep_h1 != 1) return TSNE_E_ARG;
 
     o.s = d->s;
     o.p = d->p;
@@ -129,6 +132,14 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     // ladder length has radix 3, 4 or 5 stages only
     o.rmin = 3;
     o.ncell_cap = (d->s == 2) ? o.max_int * o.max_int : o.max_int;
+    // radix passes of the binning: enough digits of at most kDigitBitsMax bits
+    // for the largest cell index of the capacity
+    {
+        int bits = 1;
+        while (bits < 31 && ((int64_t)1 << bits) < (int64_t)o.ncell_cap) ++bits;
+        o.npass = (bits + kDigitBitsMax - 1) / kDigitBitsMax;
+        if (o.npass > kMaxSortPass) return TSNE_E_UNSUPPORTED;
+    }
     o.kpts = d->points_per_lane ? d->points_per_lane : 8;
     // column slabs: when the positions exceed ~4 MB, 4 slabs of P split over
     // XCD pairs keep each XCD's gathers inside its own 4 MB L2 (measured at
@@ -186,14 +197,18 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     o.nb_gather = cdiv(n, 256);
     o.nb_kl = (int)std::min<int64_t>(2048, cdiv(n, 8));
     o.nb_scan = cdiv(o.ncell_cap, 1024);
+    o.ntiles_sort = cdiv(n, kSortTile);
 
     int* vb = o.vb;
     for (int k = 0; k < K_NKINDS; ++k) vb[k] = 0;
     vb[K_BOX] = o.nb_box;
-    vb[K_KEY] = cdiv(n, 256);
+    vb[K_KEY] = cdiv(n, kKeyTile);
+    vb[K_SORT0] = o.ntiles_sort;
+    vb[K_SORT1] = (o.npass > 1) ? o.ntiles_sort : 0;
+    vb[K_SORT2] = (o.npass > 2) ? o.ntiles_sort : 0;
+    vb[K_BOUNDS] = cdiv(n + 1, 256);
     vb[K_SCAN_A] = o.nb_scan;
     vb[K_SCAN_B] = o.nb_scan;
-    vb[K_SCATTER] = cdiv(n, 256);
     vb[K_SPREAD] = cdiv(o.items_cap, 256);
     vb[K_FIX] = cdiv(o.ncell_cap, 256);
     if (d->s == 2) {
@@ -242,14 +257,16 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     sz[R_SCHED] = sizeof(Sched);
     sz[R_SMALL] = 64;                                   // status, iter, tickets[8]
     sz[R_BOX] = sizeof(double) * 8 * o.nb_box;
-    sz[R_COUNTS] = sizeof(int) * o.ncell_cap;
     sz[R_CSTART] = sizeof(int) * (o.ncell_cap + 1);
     sz[R_ISTART] = sizeof(int) * (o.ncell_cap + 1);
-    sz[R_SCAN] = sizeof(int) * 2 * o.nb_scan;
+    sz[R_SCAN] = sizeof(int) * o.nb_scan;
     sz[R_ICELL] = sizeof(int) * o.items_cap;
     sz[R_KEY] = sizeof(int) * n;
-    sz[R_RANK] = sizeof(int) * n;
-    sz[R_PERM] = sizeof(int) * 2 * n;
+    sz[R_KV] = (o.npass > 1) ? sizeof(uint32_t) * 2 * 2 * (size_t)n : 0;
+    sz[R_SKEY] = sizeof(uint32_t) * n;
+    sz[R_GHIST] = sizeof(uint32_t) * kMaxSortPass * kDigitBins;
+    sz[R_LOOK] = sizeof(uint64_t) * (size_t)o.npass * o.ntiles_sort * kDigitBins;
+    sz[R_PERM] = sizeof(int) * n;
     sz[R_SY] = (size_t)o.tsz * n * d->s;
     sz[R_CARRY] = (size_t)o.tsz * 2 * o.nwaves * nn * o.nc;
     sz[R_W] = (size_t)o.tsz * o.nc * grid;
@@ -290,6 +307,7 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     sz[R_EVAL] = o.tiled ? (size_t)o.tsz * d->nnz : 0;
     sz[R_ZPART] = sizeof(double) * o.nb_gather;
     sz[R_KLPART] = (d->nnz > 0) ? sizeof(double) * 2 * o.nb_kl : 0;
+    sz[R_H1] = d->keep_h1 ? sizeof(double) * n : 0;
     size_t cur = 0;
     for (int r = 0; r < R_N; ++r) {
         o.L.off[r] = cur;
@@ -381,11 +399,12 @@ static tsne_status enqueue(tsne_plan* pl, int kind)
 
 // Kernel order of one repulsion.  The table kernels (K_SPEC*) always run;
 // they return at once unless the box kernel found a new spacing or length.
-static const int kChain2[] = {K_BOX, K_GEOM, K_SPEC0, K_SPEC1, K_SPEC2, K_KEY, K_SCAN_A,
-                              K_SCAN_B, K_SCATTER, K_SPREAD, K_FIX, K_FFT_ROWS, K_FFT_COLS,
-                              K_FFT_IROWS, K_GATHER, K_ZSUM};
-static const int kChain1[] = {K_BOX, K_GEOM, K_SPEC0, K_SPEC1, K_KEY, K_SCAN_A, K_SCAN_B,
-                              K_SCATTER, K_SPREAD, K_FIX, K_FFT_1D, K_GATHER, K_ZSUM};
+static const int kChain2[] = {K_BOX, K_GEOM, K_SPEC0, K_SPEC1, K_SPEC2, K_KEY, K_SORT0, K_SORT1,
+                              K_SORT2, K_BOUNDS, K_SCAN_A, K_SCAN_B, K_SPREAD, K_FIX, K_FFT_ROWS,
+                              K_FFT_COLS, K_FFT_IROWS, K_GATHER, K_ZSUM};
+static const int kChain1[] = {K_BOX, K_GEOM, K_SPEC0, K_SPEC1, K_KEY, K_SORT0, K_SORT1, K_SORT2,
+                              K_BOUNDS, K_SCAN_A, K_SCAN_B, K_SPREAD, K_FIX, K_FFT_1D, K_GATHER,
+                              K_ZSUM};
 
 static tsne_status enqueue_repulsion(tsne_plan* pl, bool normalise)
 {
@@ -425,7 +444,8 @@ static void fill_sched(Sched& s, const tsne_sched* c)
 
 // Lay a plan over its workspace: the host image of the device record, the
 // launch prefix table, and the device state that must start at zero (the
-// geometry record, the schedule, status and counters, the cell counts).
+// geometry record, the schedule, status and counters, the sort's look-back
+// words).
 // Allocates nothing; synchronises the stream before returning.
 static tsne_status plan_init(tsne_plan* pl, const tsne_desc* desc, const Derived& o, char* b,
                              hipStream_t st)
@@ -472,14 +492,19 @@ static tsne_status plan_init(tsne_plan* pl, const tsne_desc* desc, const Derived
     h.iter = reinterpret_cast<int*>(b + off[R_SMALL] + 4);
     h.tickets = reinterpret_cast<unsigned*>(b + off[R_SMALL] + 16);
     h.box_part = reinterpret_cast<double*>(b + off[R_BOX]);
-    h.counts = reinterpret_cast<int*>(b + off[R_COUNTS]);
     h.cell_start = reinterpret_cast<int*>(b + off[R_CSTART]);
     h.item_start = reinterpret_cast<int*>(b + off[R_ISTART]);
     h.scan_part = reinterpret_cast<int*>(b + off[R_SCAN]);
     h.item_cell = reinterpret_cast<int*>(b + off[R_ICELL]);
     h.key = reinterpret_cast<int*>(b + off[R_KEY]);
-    h.rank = reinterpret_cast<int*>(b + off[R_RANK]);
+    h.kv = b + off[R_KV];
+    h.skey = reinterpret_cast<unsigned*>(b + off[R_SKEY]);
+    h.ghist = reinterpret_cast<unsigned*>(b + off[R_GHIST]);
+    h.look = reinterpret_cast<unsigned long long*>(b + off[R_LOOK]);
+    h.npass = o.npass;
+    h.ntiles_sort = o.ntiles_sort;
     h.perm = reinterpret_cast<int*>(b + off[R_PERM]);
+    h.h1keep = desc->keep_h1 ? reinterpret_cast<double*>(b + off[R_H1]) : nullptr;
     h.sY = b + off[R_SY];
     h.carry = b + off[R_CARRY];
     h.W = b + off[R_W];
@@ -530,7 +555,7 @@ static tsne_status plan_init(tsne_plan* pl, const tsne_desc* desc, const Derived
                     hip_ok(hipMemsetAsync(b + off[R_GEOM], 0, sizeof(Geom), st)) &&
                     hip_ok(hipMemsetAsync(b + off[R_SCHED], 0, sizeof(Sched), st)) &&
                     hip_ok(hipMemsetAsync(b + off[R_SMALL], 0, 64, st)) &&
-                    hip_ok(hipMemsetAsync(h.counts, 0, sizeof(int) * o.ncell_cap, st)) &&
+                    hip_ok(hipMemsetAsync(h.look, 0, off[R_LOOK + 1] - off[R_LOOK], st)) &&
                     hip_ok(hipStreamSynchronize(st));
     return ok ? TSNE_OK : TSNE_E_HIP;
 }
@@ -555,6 +580,7 @@ const char* tsne_status_str(tsne_status s)
     case TSNE_E_NONFINITE: return "non-finite coordinate in Y";
     case TSNE_E_HIP: return "HIP runtime error";
     case TSNE_E_STATE: return "call not valid in this plan state";
+    case TSNE_E_INTERNAL: return "internal device error (the binning did not complete)";
     }
     return "unknown status";
 }
@@ -871,6 +897,12 @@ tsne_status tsne_debug_export(tsne_plan* pl, int32_t what, void* dst, size_t* by
     case 0: src = pl->h.W; nb = (size_t)o.tsz * o.nc * grid; break;
     case 1: src = pl->h.V; nb = (size_t)o.tsz * o.np * grid; break;
     case 2: src = pl->h.R; nb = (size_t)o.tsz * pl->d.n * pl->d.s; break;
+    case 4: src = pl->h.perm; nb = sizeof(int) * pl->d.n; break;
+    case 5:
+        if (!pl->h.h1keep) return TSNE_E_STATE;
+        src = pl->h.h1keep;
+        nb = sizeof(double) * pl->d.n;
+        break;
     case 3: {
         Geom g;
         if (!hip_ok(hipStreamSynchronize(pl->st)) ||

@@ -19,16 +19,23 @@ constexpr int kMaxStages = 24;   // FFT radix stages
 constexpr int kMaxP = 6;         // Lagrange nodes per interval
 constexpr int kWave = 64;
 
+// Binning: stable least-significant-digit radix sort of the points by cell.
+constexpr int kKeyTile = 4096;     // points per block of the key kernel (256 threads x 16)
+constexpr int kSortTile = 2048;    // points per tile of a sort pass (256 threads x 8)
+constexpr int kDigitBitsMax = 9;   // at most 512 digit values per pass
+constexpr int kDigitBins = 1 << kDigitBitsMax;
+constexpr int kMaxSortPass = 3;    // cell indices of up to 27 bits
+
 // Kernel kinds with their own virtual-block tables.
 enum Kind : int {
-    K_ARGS = 0, K_BOX, K_KEY, K_SCAN_A, K_SCAN_B, K_SCATTER, K_SPREAD, K_FIX,
+    K_ARGS = 0, K_BOX, K_KEY, K_SORT0, K_SORT1, K_SORT2, K_BOUNDS, K_SCAN_A, K_SCAN_B, K_SPREAD, K_FIX,
     K_FFT_ROWS, K_FFT_COLS, K_FFT_IROWS, K_FFT_1D, K_GATHER, K_NORM, K_ATTR,
     K_UPDATE, K_SPEC0, K_SPEC1, K_SPEC2, K_GEOM, K_ZSUM, K_ATTR_ALL, K_ASUM, K_ATTR_T, K_ATTR_T_ALL,
     K_KL, K_KLSUM, K_KL_ATTR, K_NKINDS
 };
 
 // Status bits latched on the device (values of tsne_status).
-enum : int { ST_OK = 0, ST_CAPACITY = 4, ST_NONFINITE = 5 };
+enum : int { ST_OK = 0, ST_CAPACITY = 4, ST_NONFINITE = 5, ST_INTERNAL = 8 };
 
 // Geometry of the current iteration, written by the box kernel (double).
 struct Geom {
@@ -46,8 +53,8 @@ struct Geom {
     int n_cells;       // n_int^s
     int active;        // this iteration runs (set by the geometry kernel)
     int it;            // absolute index of this iteration
-    int pbuf;          // which permutation buffer holds this iteration's sorted order
-    int perm_valid;    // a sorted order from an earlier iteration exists
+    unsigned sort_epoch;   // counts the sorts of this plan (tags the look-back words)
+    int sort_bits;     // digit bits per radix pass this iteration
     int spec_dirty;    // spacing or FFT length changed: tables must be rebuilt
     double spec_h;     // spacing the current spectra were built for
     int spec_M;        // FFT lengths the current tables were built for
@@ -112,16 +119,19 @@ struct Inst {
     Sched* sched;
     int* status;
     int* iter;
-    unsigned* tickets;     // [8]
+    unsigned* tickets;     // [8]: tile tickets of the radix passes
     double* box_part;      // [nb_box][2*s+... ] partial min/max/sum
-    int* counts;           // [ncell_cap]
     int* cell_start;       // [ncell_cap + 1]
     int* item_start;       // [ncell_cap + 1]
     int* scan_part;        // [2 * nb_scan] tile sums
     int* item_cell;        // [items_cap]
-    int* key;              // [n]
-    int* rank;             // [n]
-    int* perm;             // [2][n] sorted position -> point (double buffered)
+    int* key;              // [n] cell of each point (point order)
+    void* kv;              // [2][n] (cell, point) pairs between radix passes (uint2)
+    unsigned* skey;        // [n] cell of each sorted position
+    int* perm;             // [n] sorted position -> point
+    unsigned* ghist;       // [kMaxSortPass][kDigitBins] digit counts over all points
+    unsigned long long* look;  // [npass][ntiles_sort][kDigitBins] look-back words
+    int npass, ntiles_sort;    // radix passes (from the cell capacity), sort tiles
     void* sY;              // [n][s] sorted positions
     void* carry;           // [2 * nwaves][1 + p^s * nc] spread carries
     void* W;               // [nc][n_cap][n_cap] (s = 2) or [nc][n_cap]
@@ -151,6 +161,7 @@ struct Inst {
     const uint32_t* epack; // [nnz] (row in block << 16) | column in block
     const void* eval;      // [nnz] values in tile order
     double* z_part;        // [nb_gather]
+    double* h1keep;        // [n] each point's K1 sum h1 of the last repulsion (point order), or null
     double* kl_part;       // [nb_kl][2] divergence partials (sum p log(p/K1), sum p)
     double* KLout;         // caller's divergence output (device, may be null)
     int nb_box, nb_gather, nb_scan, nwaves, nb_kl;

@@ -31,7 +31,7 @@ def form_code(form):
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported configuration",
           3: "workspace", 4: "capacity exceeded", 5: "non-finite coordinate",
-          6: "HIP runtime error", 7: "invalid state"}
+          6: "HIP runtime error", 7: "invalid state", 8: "internal device error"}
 
 
 class Desc(ctypes.Structure):
@@ -41,7 +41,7 @@ class Desc(ctypes.Structure):
                 ("interval_width", ctypes.c_double), ("nnz", ctypes.c_int64),
                 ("lanes_per_row", ctypes.c_int32), ("points_per_lane", ctypes.c_int32),
                 ("attr_slabs", ctypes.c_int32), ("attr_layout", ctypes.c_int32),
-                ("rect", ctypes.c_int32)]
+                ("rect", ctypes.c_int32), ("keep_h1", ctypes.c_int32)]
 
 
 class Sched(ctypes.Structure):
@@ -154,12 +154,13 @@ def _dt(dtype) -> int:
 
 def make_desc(n, s, dtype=torch.float32, p=5, policy="fixed", form="A", min_intervals=1,
               max_intervals=512, interval_width=0.75, nnz=0, lanes_per_row=0,
-              points_per_lane=0, attr_slabs=0, attr_layout=0, rect=False) -> Desc:
+              points_per_lane=0, attr_slabs=0, attr_layout=0, rect=False, keep_h1=False) -> Desc:
     pol = GRID_PAPER if policy in ("paper", GRID_PAPER) else GRID_FIXED
     frm = form_code(form)
     return Desc(int(n), int(s), _dt(dtype), int(p), pol, frm, int(min_intervals),
                 int(max_intervals), float(interval_width), int(nnz), int(lanes_per_row),
-                int(points_per_lane), int(attr_slabs), int(attr_layout), int(bool(rect)))
+                int(points_per_lane), int(attr_slabs), int(attr_layout), int(bool(rect)),
+                int(bool(keep_h1)))
 
 
 def workspace_bytes(desc: Desc) -> int:
@@ -178,10 +179,10 @@ class Plan:
     def __init__(self, n, s, dtype=torch.float32, p=5, policy="fixed", form="A",
                  min_intervals=1, max_intervals=512, interval_width=0.75, nnz=0,
                  lanes_per_row=0, points_per_lane=0, attr_slabs=0, attr_layout=0, device="cuda",
-                 stream=None, rect=False):
+                 stream=None, rect=False, keep_h1=False):
         self.desc = make_desc(n, s, dtype, p, policy, form, min_intervals, max_intervals,
                               interval_width, nnz, lanes_per_row, points_per_lane, attr_slabs,
-                              attr_layout, rect)
+                              attr_layout, rect, keep_h1)
         self.n, self.s = int(n), int(s)
         self.dtype = torch.float32 if self.desc.dtype == F32 else torch.float64
         self.device = torch.device(device)

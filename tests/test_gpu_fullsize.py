@@ -52,9 +52,9 @@ FORMS = [("A", 0.75), ("V", 0.85)]
 OFORM = {"A": oracle.FORM_A, "V": oracle.FORM_V}
 
 
-def _plan(T, n, s, dtype, P=None, cap=512, form="A", width=0.75):
+def _plan(T, n, s, dtype, P=None, cap=512, form="A", width=0.75, keep_h1=False):
     plan = T.Plan(n, s, dtype, p=5, policy="fixed", interval_width=width, max_intervals=cap,
-                  form=form, nnz=(P.nnz if P is not None else 0), device=DEV)
+                  form=form, nnz=(P.nnz if P is not None else 0), device=DEV, keep_h1=keep_h1)
     if P is not None:
         plan.bind_P(torch.from_numpy(P.row_ptr).to(DEV), torch.from_numpy(P.col).to(DEV),
                     torch.from_numpy(P.val).to(DEV, dtype))
@@ -66,13 +66,14 @@ def test_c3_sampled_rows(T, c3, form, width):
     print("case: full-size 2-D sampled rows, form %s" % form, flush=True)
     Y, P = c3
     n = Y.shape[0]
-    plan = _plan(T, n, 2, torch.float32, P, form=form, width=width)
+    plan = _plan(T, n, 2, torch.float32, P, form=form, width=width, keep_h1=True)
     Yt = torch.from_numpy(Y).to(DEV)
     F, Z = plan.repulsive(Yt)
     torch.cuda.synchronize()
     st = plan.query()
     assert st["status"] == 0
     R = np.frombuffer(plan.export(2), np.float32).reshape(n, 2).astype(np.float64)
+    h1g = np.frombuffer(plan.export(5), np.float64)
     Yd = Y.astype(np.float64)
     o, w, m = oracle.geometry(Yd, "fixed", 1, width)
     assert (m, w) == (st["n_int"], st["w_int"]) and tuple(o) == st["origin"]
@@ -91,11 +92,17 @@ def test_c3_sampled_rows(T, c3, form, width):
     # the oracle's Z (the interpolated Z is within its per-row h1 error of the
     # direct one: checked at the same rows)
     e_norm = rel(Fg[rows], num / ref["Z"])
-    e_h1 = rel(ref["h1"][rows], h1)
+    # each point's K1 sum h1 (Z = sum h1 - N): the GPU's against the direct sum
+    # at the sampled rows and against the interpolation oracle at every point
+    e_h1 = rel(h1g[rows], h1)
+    e_h1_full = rel(h1g, ref["h1"])
+    assert abs(h1g.sum() - n - Z.item()) <= 1e-9 * Z.item()
     print("  numerators vs direct %.2e (per component %s); F_rep vs interpolation oracle %s, "
-          "Z %.2e; normalised F_rep vs direct %.2e; oracle h1 vs direct %.2e"
-          % (e_direct, ["%.2e" % x for x in per_d], ["%.2e" % x for x in e_full], e_z, e_norm, e_h1))
+          "Z %.2e; normalised F_rep vs direct %.2e; h1 vs direct %.2e, vs oracle %.2e"
+          % (e_direct, ["%.2e" % x for x in per_d], ["%.2e" % x for x in e_full], e_z, e_norm,
+             e_h1, e_h1_full))
     assert e_direct < 1e-3 and max(per_d) < 1e-3 and e_norm < 1e-3 and e_h1 < 1e-3
+    assert e_h1_full < 1e-5
     # form A's numerator y'(d) h4 - h_{1+d} cancels in FP32; form V's does not
     assert max(e_full) < (1e-4 if form == "A" else 1e-5)
     assert e_z < 1e-6
