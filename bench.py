@@ -3,15 +3,20 @@
 
 Workload: N = 1,000,000 points in 2-D drawn from 50 Gaussian clusters (centres
 uniform in [-95, 95]^2, sd 2) with a random 90-neighbour P (about 9e7
-non-zeros), FP32, p = 5 Lagrange nodes per interval; the interval width and
-the launch knobs come from the autotuner (accuracy target 1e-3).  A step is
-one full iteration: box, binning, spreading, FFT convolution, gather and Z,
-attraction and the descent update, replayed from a captured HIP graph.
+non-zeros), FP32; the form, nodes per interval p, interval width and launch
+knobs come from the autotuner (accuracy target 1e-3).  A step is one full
+iteration: box, binning, spreading, FFT convolution, gather and Z, attraction
+and the descent update, replayed from a captured HIP graph.
 
-Prints one JSON line: iterations/s, the roofline of the dominant kernel (the
-CSR attraction, timed with HIP events on the plan's stream; its measured HBM
-traffic comes from the committed counter summary when that summary was taken
-on the same kernel source and launch knobs) and the CPU oracle timed on a
+Prints one JSON line: iterations/s; the accuracy of the normalised F_rep at
+the end of the run (over every point against the interpolation oracle, and at
+sampled rows against the direct sum); the roofline of the dominant kernel
+(the CSR attraction, timed with HIP events on the plan's stream; its measured
+HBM traffic comes from the committed counter summary when that summary was
+taken on the same kernel source and launch knobs); the paper's own form
+(charges 1 and y, Appendix) timed beside the tuned form; the serving workload
+(runs/s and p50/p99 latency of a 64-job continuous-batching server against
+the same trace served one job at a time); and the CPU oracle timed on a
 bounded sample of the same workload.
 """
 import argparse
@@ -91,6 +96,11 @@ def main():
     ap.add_argument("--slots", type=str, default="8",
                     help="serving: batch slots (jobs live at once); a comma list runs the "
                          "batched server once per value and reports each")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the serving leg of the default benchmark line")
+    ap.add_argument("--no-form-a", action="store_true",
+                    help="skip the paper-form (A) leg of the default benchmark line")
+    ap.add_argument("--form-a-steps", type=int, default=200)
     ap.add_argument("--copy-ref", action="store_true",
                     help="after the benchmark, copy a 512 MiB buffer three times (a plain copy "
                          "kernel of known size that scales HBM counters under a profiler)")
@@ -129,6 +139,7 @@ def main():
     max_int = 512                     # grid capacity (intervals per dimension)
     knobs = {}
     tuned = None
+    ti_table = []
     if not args.no_tune:
         # autotuner: interval width for the accuracy target, then launch knobs
         from paper_1712_09005_amd import autotune
@@ -138,6 +149,8 @@ def main():
             ti = autotune.tune_interp(Y, target=1e-3, safety=2.5, max_intervals=max_int,
                                       device=dev, log=log, forms=forms)
             args.form, args.p, args.width = ti["form"], ti["p"], ti["interval_width"]
+            max_int = max(max_int, ti.get("max_intervals", max_int))
+            ti_table = ti["table"]
         elif args.width is None:
             args.form = args.form or "A"
             tw = autotune.tune_width(Y, target=1e-3, safety=2.5, p=args.p, device=dev, log=log,
@@ -238,47 +251,27 @@ def main():
 
     pca_info = None if args.no_pca else pca_leg(args, dev)
 
-    # accuracy on sampled rows against the direct sum (repulsion numerators)
-    rel_err = None
-    cpu = None
+    # accuracy of the normalised repulsion at the final Y: every point against
+    # the interpolation oracle, sampled rows against the direct sum
+    acc = None
+    Yd = None
     if not args.no_cpu:
         import oracle
-        rng = np.random.default_rng(123)
-        rows = np.sort(rng.choice(n, 512, replace=False))
-        Fr, Z = plan.repulsive(Yt)
-        torch.cuda.synchronize()
-        Rnum = np.frombuffer(plan.export(2), np.float32).reshape(n, s)[rows].astype(np.float64)
         Yd = Yt.cpu().numpy().astype(np.float64)
-        h1, num = oracle.direct_sums(Yd, rows)
-        rel_err = float(np.linalg.norm(Rnum - num) / np.linalg.norm(num))
-        log("sampled repulsion numerators vs direct sum: rel err %.2e" % rel_err)
-        # CPU oracle baseline: direct per-row sums on a sample of rows, plus the
-        # full attraction and update, scaled to one iteration
-        Pd = inputs.CSR(P.row_ptr, P.col, P.val.astype(np.float64))
-        ta = time.perf_counter()
-        Fa_ref = oracle.attr(Yd, Pd)
-        t_attr_cpu = time.perf_counter() - ta
-        nrow = 256
-        while True:
-            sample = rng.choice(n, nrow, replace=False)
-            tb = time.perf_counter()
-            oracle.direct_sums(Yd, sample)
-            t_rows = time.perf_counter() - tb
-            if t_rows > args.cpu_seconds / 4 or nrow >= n:
-                break
-            nrow = min(n, int(nrow * max(2.0, (args.cpu_seconds / 4) / max(t_rows, 1e-3))))
-        tu = time.perf_counter()
-        oracle.update(Yd, np.zeros_like(Yd), np.ones_like(Yd), Fa_ref, np.zeros_like(Yd),
-                      12.0, 0.5, 200.0)
-        t_upd = time.perf_counter() - tu
-        t_iter = t_rows * n / nrow + t_attr_cpu + t_upd
-        cpu = {"value": 1.0 / t_iter, "unit": "iterations/s", "cores": oracle.threads(),
-               "kind": "oracle",
-               "sample": "direct O(N^2) repulsion for %d sampled rows (%.1f s, scaled by N/rows) "
-                         "+ full attraction (%.2f s) + update (%.2f s); FP64" %
-                         (nrow, t_rows, t_attr_cpu, t_upd)}
-        log("cpu oracle: %.3g s per iteration on %d threads" % (t_iter, oracle.threads()))
+        acc = accuracy(n, s, Yd, args.p, args.width, args.form, max_int, dev)
+        log("accuracy: %s" % acc)
 
+    form_a = None
+    if not args.no_form_a and args.form != "A" and tuned is not None and not args.no_cpu:
+        form_a = form_a_leg(args, dev, Y, P, tuned, ti_table, knobs, max_int)
+
+    serving = None
+    if not args.no_serve:
+        serving = serving_leg(args, dev, form="V", p=5, width=0.65, slots=[8])
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(args, n, Yd, P, args.p, args.width, args.form)
     out = {
         "metric": "t-SNE iters/s at N=1M 2D (rel err<=1e-3)",
         "value": ips,
@@ -297,8 +290,12 @@ def main():
                    "n": n, "s": s, "nnz": int(P.nnz), "p": args.p, "interval_width": args.width,
                    "n_int": q["n_int"], "fft_len": q["fft_len"], "max_intervals": max_int,
                    "form": args.form,
-                   "autotuned": tuned, "kl_divergence": kl_info, "pca": pca_info,
-                   "rel_err_rep_numerators_sampled": rel_err},
+                   "autotuned": tuned, "autotune_candidates": ti_table,
+                   "accuracy": acc,
+                   "rel_err_rep_numerators_sampled": acc["rel_err_numerators_vs_direct_sampled"]
+                   if acc else None,
+                   "form_a": form_a, "serving": serving,
+                   "kl_divergence": kl_info, "pca": pca_info},
         "roofline": {"bound": "hbm", "kernel": "attraction step: k_attr (+ k_asum when "
                                                "attr_slabs > 1)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -309,6 +306,246 @@ def main():
     print(json.dumps(out), flush=True)
     if args.copy_ref:
         copy_reference()
+
+
+def accuracy(n, s, Yd, p, width, form, max_int, dev, rows=512, seed=123):
+    """Error of the GPU repulsion at Yd (FP64 host copy of the embedding),
+    computed by a plan with the benchmark's grid settings that keeps each
+    point's h1:
+      - the normalised F_rep = R / Z per component over every point and Z,
+        against the whole interpolation oracle (Step 2 by FFT);
+      - at 512 sampled rows against the direct sum: the numerators R, the
+        normalised forces (over the oracle's Z) and h1 (Z = sum h1 - N)."""
+    import numpy as np
+    import oracle
+    import torch
+    from paper_1712_09005_amd import tsne
+    plan = tsne.Plan(n, s, torch.float32, p=p, policy="fixed", interval_width=width, form=form,
+                     max_intervals=max_int, device=dev, keep_h1=True)
+    Yt = torch.from_numpy(Yd.astype(np.float32)).to(dev)
+    F, Z = plan.repulsive(Yt)
+    torch.cuda.synchronize()
+    st = plan.query()
+    if st["status"] != 0:
+        raise SystemExit("device status %d in the accuracy check" % st["status"])
+    Fg = F.cpu().numpy().astype(np.float64)
+    R = np.frombuffer(plan.export(2), np.float32).reshape(n, s).astype(np.float64)
+    h1g = np.frombuffer(plan.export(5), np.float64)
+    Yd32 = Yt.cpu().numpy().astype(np.float64)           # the FP32 positions the GPU used
+    o, w, m = oracle.geometry(Yd32, "fixed", 1, width)
+    fm = {"A": oracle.FORM_A, "B": oracle.FORM_B, "V": oracle.FORM_V}[form]
+    ref = oracle.interp_rep_fft(Yd32, o, w, m, p, fm)
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    rng = np.random.default_rng(seed)
+    r = np.sort(rng.choice(n, min(rows, n), replace=False))
+    h1, num = oracle.direct_sums(Yd32, r)
+    return {"rel_err_frep_vs_interp_oracle": [rel(Fg[:, d], ref["F"][:, d]) for d in range(s)],
+            "rel_err_z_vs_interp_oracle": abs(float(Z.item()) - ref["Z"]) / ref["Z"],
+            "rel_err_frep_vs_direct_sampled": rel(Fg[r], num / ref["Z"]),
+            "rel_err_frep_vs_direct_sampled_per_component": [rel(Fg[r, d], num[:, d] / ref["Z"])
+                                                              for d in range(s)],
+            "rel_err_numerators_vs_direct_sampled": rel(R[r], num),
+            "rel_err_h1_vs_direct_sampled": rel(h1g[r], h1),
+            "interp_oracle_vs_direct_sampled": rel(ref["F"][r], num / ref["Z"]),
+            "sampled_rows": int(len(r)),
+            "note": "normalised F_rep = R / Z; the direct-sum reference at the sampled rows is "
+                    "the direct numerator over the interpolation oracle's Z (the direct Z needs "
+                    "all N^2 pairs); its per-row h1 error bounds Z's"}
+
+
+def form_a_leg(args, dev, Y, P, tuned, table, knobs, max_int):
+    """The paper's own form (Appendix: K1 with charge 1, K2 with charges 1 and
+    y) at its fastest (p, width) meeting the same target, from the same start:
+    iterations/s over the same graph-replayed step, and its accuracy."""
+    import numpy as np
+    import torch
+    from paper_1712_09005_amd import tsne
+    rows = [r for r in table if r["form"] == "A" and r["seconds"] is not None]
+    if not rows:
+        return None
+    best = min(rows, key=lambda r: r["seconds"])
+    form, p, w = best["form"], best["p"], best["interval_width"]
+    cap = max(max_int, best["max_intervals"])
+    n = Y.shape[0]
+    kn = dict(knobs)
+    kn.pop("points_per_lane", None)
+    plan = tsne.Plan(n, 2, torch.float32, p=p, policy="fixed", interval_width=w, form=form,
+                     max_intervals=cap, nnz=P.nnz, device=dev, **kn)
+    with torch.cuda.stream(plan.stream):
+        Yt = torch.from_numpy(Y).to(dev)
+        uY = torch.zeros_like(Yt)
+        gains = torch.ones_like(Yt)
+        rp = torch.from_numpy(P.row_ptr).to(dev)
+        col = torch.from_numpy(P.col).to(dev)
+        val = torch.from_numpy(P.val).to(dev)
+    torch.cuda.synchronize()
+    plan.bind_P(rp, col, val)
+    sched = tsne.Schedule()
+    plan.run(Yt, uY, gains, sched, 0, args.warmup)
+    torch.cuda.synchronize()
+    K = args.form_a_steps
+    t1 = time.perf_counter()
+    plan.run(Yt, uY, gains, sched, args.warmup, K)
+    plan.stream.synchronize()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    q = plan.query()
+    if q["status"] != 0:
+        return {"error": "device status %d" % q["status"]}
+    Yd = Yt.cpu().numpy().astype(np.float64)
+    del plan
+    acc = accuracy(n, 2, Yd, p, w, form, cap, dev)
+    out = {"form": form, "p": p, "interval_width": w, "estimate": best["estimate"], "steps": K,
+           "iterations_per_s": K / el, "ms_per_step": 1e3 * el / K, "n_int": q["n_int"],
+           "fft_len": q["fft_len"], "accuracy": acc,
+           "note": "the Appendix's charges; same inputs, start, schedule and attraction knobs as "
+                   "the headline"}
+    log("form A leg: %s" % {k: v for k, v in out.items() if k != "accuracy"})
+    return out
+
+
+def serving_leg(args, dev, form="V", p=5, width=0.65, slots=(8,), n_jobs=64):
+    """The serving workload: n_jobs embedding jobs (N log-uniform in [5e3,
+    2e5], 5-30 cluster 50-d mixtures, P from exact 90-NN at perplexity 30
+    built on the device before the clock), Poisson arrivals at twice the
+    sequential back-to-back rate, served by the continuous-batching server
+    and, on the same trace, one job at a time.  Returns runs/s, p50/p99
+    latency, the speed-up and the accuracy of the smallest jobs' final
+    embeddings in both modes."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1712_09005_amd import inputs, serve, tsne
+    t0 = time.time()
+    raw = inputs.serving_jobs(n_jobs)
+    specs = []
+    t_aff = 0.0
+    for y, x in raw:                       # affinities on the device, before the clock
+        Xt = torch.from_numpy(x).to(dev)
+        torch.cuda.synchronize()
+        ta0 = time.perf_counter()
+        rp_d, col_d, val_d = tsne.affinities(Xt, 90, 30.0)
+        torch.cuda.synchronize()
+        t_aff += time.perf_counter() - ta0
+        specs.append((y, inputs.CSR(rp_d.cpu().numpy(), col_d.cpu().numpy(), val_d.cpu().numpy())))
+    del raw
+    log("serving inputs: %d jobs, N from %d to %d (%.1f s; device affinities %.2f s in all)" % (
+        len(specs), min(y.shape[0] for y, _ in specs), max(y.shape[0] for y, _ in specs),
+        time.time() - t0, t_aff))
+
+    def jobs_at(arrivals):
+        return [serve.Job(j, float(a), y, P) for j, ((y, P), a) in enumerate(zip(specs, arrivals))]
+
+    lanes = 32
+    if not args.no_tune:
+        from paper_1712_09005_amd import autotune
+        lanes = autotune.tune_batch_lanes(specs[::8], p=p, device=dev, log=log)["lanes_per_row"]
+        log("autotuned lanes per row: %d" % lanes)
+    back_to_back = serve.sequential(jobs_at(np.zeros(len(specs))), interval_width=width, p=p,
+                                    lanes_per_row=lanes, device=dev, form=form)
+    rate = 2.0 * back_to_back["runs_per_s"]
+    arr = inputs.poisson_arrivals(len(specs), rate, seed=7)
+    log("sequential back-to-back: %.2f runs/s; Poisson rate %.2f/s" % (back_to_back["runs_per_s"], rate))
+    runs = {}
+    for k in slots:
+        srv = serve.Server(max_slots=k, hbm_budget=200 << 30, ticks_per_poll=10,
+                           interval_width=width, p=p, lanes_per_row=lanes, device=dev, form=form)
+        jobs_k = jobs_at(arr)
+        runs[k] = (srv.run(jobs_k), jobs_k)
+        log("batched, %d slots: %s" % (k, runs[k][0]))
+        del srv
+    batched, batched_jobs = runs[slots[0]]
+    seq_jobs = jobs_at(arr)
+    seq = serve.sequential(seq_jobs, interval_width=width, p=p, lanes_per_row=lanes, device=dev,
+                           form=form)
+    log("sequential: %s" % seq)
+    # equal accuracy: repulsion error of the final embeddings of the smallest jobs
+    acc = []
+    for jb, js in sorted(zip(batched_jobs, seq_jobs), key=lambda t: t[0].n)[:3]:
+        errs = []
+        for Yo in (jb.Y_out, js.Y_out):
+            plan = tsne.Plan(jb.n, 2, torch.float32, p=p, interval_width=width, form=form,
+                             max_intervals=serve.capacity_for(jb.n, width) * 2, device=dev)
+            Yt = torch.from_numpy(np.ascontiguousarray(Yo)).to(dev)
+            F, Z = plan.repulsive(Yt)
+            torch.cuda.synchronize()
+            Fd, Zd = oracle.direct_rep(Yo.astype(np.float64))
+            errs.append(float(np.linalg.norm(F.cpu().numpy() - Fd) / np.linalg.norm(Fd)))
+        acc.append({"job": jb.jid, "n": jb.n, "rel_err_batched": errs[0],
+                    "rel_err_sequential": errs[1],
+                    "batched_equals_sequential": bool(np.array_equal(jb.Y_out, js.Y_out))})
+    return {"workload": "%d jobs, N log-uniform [5e3, 2e5], 5-30 cluster 50-d mixtures, exact "
+                        "90-NN perplexity-30 P, Poisson arrivals at 2x the sequential rate, 1000 "
+                        "iterations each" % len(specs),
+            "runs_per_s": batched["runs_per_s"], "p50_latency_s": batched.get("p50_latency_s"),
+            "p99_latency_s": batched.get("p99_latency_s"), "batched": batched,
+            "sequential_same_trace": seq, "sequential_back_to_back": back_to_back,
+            "speedup_runs_per_s": batched["runs_per_s"] / seq["runs_per_s"],
+            "lanes_per_row": lanes, "form": form, "p": p, "interval_width": width,
+            "slots": slots[0], "batched_by_slots": {str(k): v[0] for k, v in runs.items()},
+            "accuracy_final_embeddings": acc}
+
+
+def cpu_baseline(args, n, Yd, P, p, width, form):
+    """The oracle timed on the host's cores: (c-1) the direct O(N^2) repulsion
+    on a sample of rows scaled by N / rows, plus the full attraction and the
+    update, is the reported iterations/s; beside it (c-2) the interpolation
+    oracle with Step 2 by FFT over the whole N = 1e6 embedding, and the
+    interpolation oracle with the direct Step 2 on the 2048-point check
+    workload."""
+    import numpy as np
+    import oracle
+    from paper_1712_09005_amd import inputs
+    rng = np.random.default_rng(321)
+    Pd = inputs.CSR(P.row_ptr, P.col, P.val.astype(np.float64))
+    ta = time.perf_counter()
+    Fa_ref = oracle.attr(Yd, Pd)
+    t_attr_cpu = time.perf_counter() - ta
+    nrow = 256
+    while True:
+        sample = rng.choice(n, nrow, replace=False)
+        tb = time.perf_counter()
+        oracle.direct_sums(Yd, sample)
+        t_rows = time.perf_counter() - tb
+        if t_rows > args.cpu_seconds / 4 or nrow >= n:
+            break
+        nrow = min(n, int(nrow * max(2.0, (args.cpu_seconds / 4) / max(t_rows, 1e-3))))
+    tu = time.perf_counter()
+    oracle.update(Yd, np.zeros_like(Yd), np.ones_like(Yd), Fa_ref, np.zeros_like(Yd),
+                  12.0, 0.5, 200.0)
+    t_upd = time.perf_counter() - tu
+    t_iter = t_rows * n / nrow + t_attr_cpu + t_upd
+    fm = {"A": oracle.FORM_A, "B": oracle.FORM_B, "V": oracle.FORM_V}[form]
+    o, w, m = oracle.geometry(Yd, "fixed", 1, width)
+    tf = time.perf_counter()
+    oracle.interp_rep_fft(Yd, o, w, m, p, fm)
+    t_fft = time.perf_counter() - tf
+    Y1 = inputs.mixture_embedding(2048, 2, 10, -30.0, 30.0, 2.0, seed=0).astype(np.float64)
+    o1, w1, m1 = oracle.geometry(Y1, "paper", 50)
+    tc = time.perf_counter()
+    oracle.interp_rep(Y1, o1, w1, m1, 3, oracle.FORM_A)
+    t_c1 = time.perf_counter() - tc
+    tc = time.perf_counter()
+    oracle.direct_rep(Y1)
+    t_c1d = time.perf_counter() - tc
+    log("cpu oracle: %.3g s per iteration on %d threads (direct); interpolation with FFT %.2f s"
+        % (t_iter, oracle.threads(), t_fft))
+    return {"value": 1.0 / t_iter, "unit": "iterations/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": "direct O(N^2) repulsion for %d sampled rows (%.1f s, scaled by N/rows) "
+                      "+ full attraction (%.2f s) + update (%.2f s); FP64" %
+                      (nrow, t_rows, t_attr_cpu, t_upd),
+            "interp_fft_repulsion_seconds": t_fft,
+            "interp_fft_iterations_per_s": 1.0 / (t_fft + t_attr_cpu + t_upd),
+            "interp_fft_note": "the interpolation oracle (spreading and gathering in C with "
+                               "OpenMP, Step 2 by numpy's FFT) over all N points, form %s, "
+                               "p = %d, width %g, plus the attraction and update" % (form, p, width),
+            "c1_interp_direct_step2_seconds": t_c1,
+            "c1_direct_seconds": t_c1d,
+            "c1_note": "N = 2048 check workload (paper policy, 50 intervals minimum, p = 3): "
+                       "interpolation with the direct Step 2, and the direct O(N^2) sum"}
 
 
 def pca_leg(args, dev, rank=50, k=50, l=52, its=2, reps=2):
@@ -499,81 +736,14 @@ def other_workloads(args):
         print(json.dumps(out), flush=True)
         return
     # serving: 64 jobs, Poisson arrivals at twice the sequential rate
-    from paper_1712_09005_amd import serve
-    t0 = time.time()
-    raw = inputs.serving_jobs(args.jobs)
-    specs = []
-    t_aff = 0.0
-    for y, x in raw:                       # affinities on the device, before the clock
-        Xt = torch.from_numpy(x).to(dev)
-        torch.cuda.synchronize()
-        ta0 = time.perf_counter()
-        rp_d, col_d, val_d = tsne.affinities(Xt, 90, 30.0)
-        torch.cuda.synchronize()
-        t_aff += time.perf_counter() - ta0
-        specs.append((y, inputs.CSR(rp_d.cpu().numpy(), col_d.cpu().numpy(), val_d.cpu().numpy())))
-    del raw
-    log("serving inputs: %d jobs, N from %d to %d (%.1f s; device affinities %.2f s in all)" % (
-        len(specs), min(y.shape[0] for y, _ in specs), max(y.shape[0] for y, _ in specs),
-        time.time() - t0, t_aff))
-
-    def jobs_at(arrivals):
-        return [serve.Job(j, float(a), y, P) for j, ((y, P), a) in enumerate(zip(specs, arrivals))]
-
-    # autotuner: lanes per row of the shared attraction launch, over a sample of jobs
-    lanes = 32
-    if not args.no_tune:
-        from paper_1712_09005_amd import autotune
-        lanes = autotune.tune_batch_lanes(specs[::8], p=args.p, device=dev, log=log)["lanes_per_row"]
-        log("autotuned lanes per row: %d" % lanes)
-    back_to_back = serve.sequential(jobs_at(np.zeros(len(specs))), interval_width=args.width,
-                                    p=args.p, lanes_per_row=lanes, device=dev, form=args.form)
-    rate = 2.0 * back_to_back["runs_per_s"]
-    arr = inputs.poisson_arrivals(len(specs), rate, seed=7)
-    log("sequential back-to-back: %.2f runs/s; Poisson rate %.2f/s" % (back_to_back["runs_per_s"], rate))
     slot_list = [int(x) for x in args.slots.split(",")]
-    runs = {}
-    for k in slot_list:
-        srv = serve.Server(max_slots=k, hbm_budget=200 << 30, ticks_per_poll=10,
-                           interval_width=args.width, p=args.p, lanes_per_row=lanes, device=dev,
-                           form=args.form)
-        jobs_k = jobs_at(arr)
-        runs[k] = (srv.run(jobs_k), jobs_k)
-        log("batched, %d slots: %s" % (k, runs[k][0]))
-        del srv
-    batched, batched_jobs = runs[slot_list[0]]
-    seq_jobs = jobs_at(arr)
-    seq = serve.sequential(seq_jobs, interval_width=args.width, p=args.p, lanes_per_row=lanes,
-                           device=dev, form=args.form)
-    log("sequential: %s" % seq)
-    # equal accuracy: repulsion error of the final embeddings of the smallest jobs
-    import oracle
-    acc = []
-    for jb, js in sorted(zip(batched_jobs, seq_jobs), key=lambda t: t[0].n)[:3]:
-        errs = []
-        for Yo in (jb.Y_out, js.Y_out):
-            plan = tsne.Plan(jb.n, 2, torch.float32, p=args.p, interval_width=args.width,
-                             form=args.form, max_intervals=serve.capacity_for(jb.n, args.width) * 2,
-                             device=dev)
-            Yt = torch.from_numpy(np.ascontiguousarray(Yo)).to(dev)
-            F, Z = plan.repulsive(Yt)
-            torch.cuda.synchronize()
-            Fd, Zd = oracle.direct_rep(Yo.astype(np.float64))
-            errs.append(float(np.linalg.norm(F.cpu().numpy() - Fd) / np.linalg.norm(Fd)))
-        acc.append({"job": jb.jid, "n": jb.n, "rel_err_batched": errs[0], "rel_err_sequential": errs[1]})
-    out = {"metric": "served t-SNE runs/s (64 jobs, 1000 iterations each)", "value": batched["runs_per_s"],
-           "unit": "runs/s", "n_gpus": 1, "steps": len(specs), "warmup": 0,
-           "ms_per_step": 1e3 * batched["makespan_s"] / len(specs), "higher_is_better": True,
+    sv = serving_leg(args, dev, form=args.form, p=args.p, width=args.width, slots=slot_list,
+                     n_jobs=args.jobs)
+    out = {"metric": "served t-SNE runs/s (64 jobs, 1000 iterations each)", "value": sv["runs_per_s"],
+           "unit": "runs/s", "n_gpus": 1, "steps": args.jobs, "warmup": 0,
+           "ms_per_step": 1e3 * sv["batched"]["makespan_s"] / args.jobs, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "64 jobs, N log-uniform [5e3, 2e5], 5-30 cluster 50-d mixtures, "
-                                  "exact 90-NN perplexity-30 P, Poisson arrivals at 2x the "
-                                  "sequential rate", "batched": batched, "sequential_same_trace": seq,
-                      "sequential_back_to_back": back_to_back, "lanes_per_row": lanes,
-                      "form": args.form, "p": args.p, "interval_width": args.width,
-                      "slots": slot_list[0],
-                      "batched_by_slots": {str(k): v[0] for k, v in runs.items()},
-                      "speedup_runs_per_s": batched["runs_per_s"] / seq["runs_per_s"],
-                      "accuracy_final_embeddings": acc}}
+           "config": sv}
     print(json.dumps(out), flush=True)
 
 

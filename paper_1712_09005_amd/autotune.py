@@ -33,8 +33,11 @@ import torch
 from . import tsne
 
 WIDTHS = (1.6, 1.5, 1.4, 1.3, 1.2, 1.1, 1.0, 0.95, 0.9, 0.85, 0.8, 0.75, 0.7, 0.65, 0.6,
-          0.55, 0.5, 0.45, 0.4, 0.35, 0.3)
-CSR_KNOBS = [(lpr, sl, 1) for lpr in (4, 8, 16, 32, 64) for sl in (1, 2, 4, 8)] + [(0, 0, 2)]
+          0.55, 0.5, 0.45, 0.4, 0.35, 0.3, 0.25, 0.2)
+PS = (3, 4, 5, 6)
+# CSR rows only: the LDS-tiled layout sums rows with LDS float atomics, so its
+# results depend on timing, and it never won (it stays available explicitly)
+CSR_KNOBS = [(lpr, sl, 1) for lpr in (4, 8, 16, 32, 64) for sl in (1, 2, 4, 8)]
 KPTS = (4, 8, 16)
 
 
@@ -240,12 +243,22 @@ def tune_width(Y, target=1e-3, safety=2.0, p=5, device="cuda:0", widths=WIDTHS,
     return out
 
 
-def tune_interp(Y, target=1e-3, safety=2.5, ps=(4, 5, 6), max_intervals=512, device="cuda:0",
+def max_capacity(p: int) -> int:
+    """Largest interval count a plan accepts at p nodes per interval (the
+    circulant of 2 N_int p nodes stays within 12288-point transforms)."""
+    return 12288 // (2 * p)
+
+
+def tune_interp(Y, target=1e-3, safety=2.5, ps=PS, max_intervals=512, device="cuda:0",
                 reps=10, cache="default", log=None, forms=("A",)) -> dict:
     """Form, nodes per interval p and interval width together: for each
     (form, p) the widest width meeting the accuracy target (tune_width), then
-    the choice whose FP32 repulsion at this Y is fastest.  Returns {"form",
-    "p", "interval_width", "estimate", "seconds", "table"}."""
+    the choice whose FP32 repulsion at this Y is fastest.  A choice whose box
+    needs more than max_intervals intervals is timed at the capacity it needs
+    (up to the library's largest).  Returns {"form", "p", "interval_width",
+    "estimate", "max_intervals", "seconds", "table"}; every (form, p) has a
+    table row {"form", "p", "interval_width", "estimate", "max_intervals",
+    "seconds", "note"} (seconds None when it was not timed, with the reason)."""
     cache = default_cache() if cache == "default" else cache
     dev = torch.device(device)
     n, s = Y.shape
@@ -260,15 +273,28 @@ def tune_interp(Y, target=1e-3, safety=2.5, ps=(4, 5, 6), max_intervals=512, dev
     table = []
     best = None
     for form, p in [(f, p) for f in forms for p in ps]:
+        row = {"form": form, "p": p, "interval_width": None, "estimate": None,
+               "max_intervals": None, "seconds": None, "note": ""}
+        table.append(row)
         try:
             tw = tune_width(Y, target=target, safety=safety, p=p, device=dev, cache=cache, log=log,
                             form=form)
-        except RuntimeError:
+        except RuntimeError as e:
+            row["note"] = str(e)
+            if log:
+                log("  form %s p=%d: %s" % (form, p, e))
             continue
         w = tw["interval_width"]
-        if L / w + 1 > max_intervals:
+        row.update(interval_width=w, estimate=tw["estimate"])
+        need = int(math.ceil(L / w)) + 1
+        cap = max(max_intervals, need)
+        if cap > max_capacity(p):
+            row["note"] = "needs %d intervals, above the largest capacity %d" % (need, max_capacity(p))
+            if log:
+                log("  form %s p=%d width %.3g: %s" % (form, p, w, row["note"]))
             continue
-        plan = tsne.Plan(n, s, torch.float32, p=p, interval_width=w, max_intervals=max_intervals,
+        row["max_intervals"] = cap
+        plan = tsne.Plan(n, s, torch.float32, p=p, interval_width=w, max_intervals=cap,
                          form=form, device=dev)
         with torch.cuda.stream(plan.stream):
             F = torch.empty_like(Yt)
@@ -276,18 +302,20 @@ def tune_interp(Y, target=1e-3, safety=2.5, ps=(4, 5, 6), max_intervals=512, dev
         torch.cuda.synchronize()
         t = time_launches(lambda: plan.repulsive(Yt, F, Z), plan.stream, reps)
         if plan.query()["status"] != 0:
+            row["note"] = "repulsion latched a device status"
             continue
-        table.append([form, p, w, tw["estimate"], t])
+        row["seconds"] = t
         if log:
-            log("  form %s p=%d width %.3g (estimate %.2e): repulsion %.1f us"
-                % (form, p, w, tw["estimate"], t * 1e6))
-        if best is None or t < best[4]:
-            best = (form, p, w, tw["estimate"], t)
+            log("  form %s p=%d width %.3g (estimate %.2e, %d intervals): repulsion %.1f us"
+                % (form, p, w, tw["estimate"], cap, t * 1e6))
+        if best is None or t < best["seconds"]:
+            best = row
         del plan
     if best is None:
         raise RuntimeError("no (form, p, width) meets the target %g" % target)
-    out = {"form": best[0], "p": best[1], "interval_width": best[2], "estimate": best[3],
-           "seconds": best[4], "table": table}
+    out = {"form": best["form"], "p": best["p"], "interval_width": best["interval_width"],
+           "estimate": best["estimate"], "max_intervals": best["max_intervals"],
+           "seconds": best["seconds"], "table": table}
     _store(cache, key, out)
     return out
 

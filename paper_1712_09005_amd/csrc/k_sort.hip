@@ -29,6 +29,7 @@ constexpr unsigned long long kLbAgg = 1ull << 30;   // the tile's own count
 constexpr unsigned long long kLbInc = 2ull << 30;   // count of this and all earlier tiles
 constexpr unsigned kLbCount = (1u << 30) - 1;
 constexpr int kSpinLimit = 1 << 20;                 // polls of one word before giving up
+constexpr int kLbWindow = 16;                       // earlier tiles requested at once
 
 __device__ __forceinline__ unsigned long long lb_word(unsigned epoch, unsigned long long flag,
                                                       unsigned count)
@@ -79,7 +80,9 @@ __device__ __forceinline__ void block_excl_scan_bins(unsigned* v, unsigned* wsum
 static_assert(kDigitBins == 2 * 256, "two bins per thread");
 
 // Cell of every point in point order, and the per-pass digit counts over all
-// points (LDS counts per block, one global add per non-zero bin).
+// points: the lanes of a wave holding the same digit add their count to LDS
+// once (clustered inputs put many points of a block on few digits), and the
+// block adds each non-zero count to the global counts once.
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_key(LaunchMap map)
 {
@@ -89,18 +92,24 @@ __global__ __launch_bounds__(256) void k_key(LaunchMap map)
         const Geom& G = *I.geom;
         const int np = I.npass, sb = G.sort_bits;
         const unsigned mask = (1u << sb) - 1u;
+        const unsigned long long lt = (1ull << (threadIdx.x & 63)) - 1ull;
         for (int k = threadIdx.x; k < np * kDigitBins; k += 256) hist[k] = 0;
         __syncthreads();
         const T* Y = static_cast<const T*>(I.Yin);
         const int64_t base = (int64_t)lb * kKeyTile;
-#pragma unroll 4
         for (int r = 0; r < kKeyTile / 256; ++r) {
             const int64_t i = base + r * 256 + threadIdx.x;
-            if (i < I.n) {
-                const unsigned key = (unsigned)cell_of<T, S>(Pt<T, S>::load(Y, i), G);
+            const bool valid = i < I.n;
+            unsigned key = 0;
+            if (valid) {
+                key = (unsigned)cell_of<T, S>(Pt<T, S>::load(Y, i), G);
                 I.key[i] = (int)key;
-                for (int p = 0; p < np; ++p)
-                    atomicAdd(&hist[p * kDigitBins + digit_of(key, p * sb, mask)], 1u);
+            }
+            for (int p = 0; p < np; ++p) {
+                const unsigned d = digit_of(key, p * sb, mask);
+                const unsigned long long peers = match_digit(d, valid, sb);
+                if (valid && (peers & lt) == 0ull)
+                    atomicAdd(&hist[p * kDigitBins + d], (unsigned)__popcll(peers));
             }
         }
         __syncthreads();
@@ -223,27 +232,40 @@ __global__ __launch_bounds__(256) void k_sort(LaunchMap map)
             if (dd >= nbins) continue;
             unsigned excl = 0;
             if (tile > 0) {
+                // windows of kLbWindow earlier tiles, nearest first: their words
+                // are requested together, then summed in order down to the
+                // first inclusive one (an entry not yet published is polled
+                // until it is, within kSpinLimit polls)
                 const unsigned long long* prev = I.look + ((int64_t)PASS * I.ntiles_sort) * kDigitBins + dd;
-                for (int j = tile - 1; j >= 0;) {
-                    unsigned long long w = __hip_atomic_load(prev + (int64_t)j * kDigitBins, __ATOMIC_RELAXED,
-                                                             __HIP_MEMORY_SCOPE_AGENT);
-                    int spins = 0;
-                    while ((unsigned)(w >> 32) != epoch || (w & (3ull << 30)) == 0) {
-                        if (++spins > kSpinLimit) {
-                            // an earlier tile never published: latch the
-                            // condition (the iteration's result is invalid)
-                            // instead of waiting for ever
-                            atomicCAS(I.status, 0, (int)ST_INTERNAL);
-                            w = lb_word(epoch, kLbInc, 0);
-                            break;
+                bool found = false;
+                for (int j = tile - 1; j >= 0 && !found; j -= kLbWindow) {
+                    unsigned long long w[kLbWindow];
+#pragma unroll
+                    for (int u = 0; u < kLbWindow; ++u)
+                        w[u] = (j - u >= 0) ? __hip_atomic_load(prev + (int64_t)(j - u) * kDigitBins,
+                                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                            : lb_word(epoch, kLbInc, 0);
+#pragma unroll
+                    for (int u = 0; u < kLbWindow; ++u) {
+                        if (found) break;
+                        unsigned long long x = w[u];
+                        int spins = 0;
+                        while ((unsigned)(x >> 32) != epoch || (x & (3ull << 30)) == 0) {
+                            if (++spins > kSpinLimit) {
+                                // an earlier tile never published: latch the
+                                // condition (the iteration's result is invalid)
+                                // instead of waiting for ever
+                                atomicCAS(I.status, 0, (int)ST_INTERNAL);
+                                x = lb_word(epoch, kLbInc, 0);
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                            x = __hip_atomic_load(prev + (int64_t)(j - u) * kDigitBins, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
                         }
-                        __builtin_amdgcn_s_sleep(1);
-                        w = __hip_atomic_load(prev + (int64_t)j * kDigitBins, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
+                        excl += (unsigned)(x & kLbCount);
+                        if (x & kLbInc) found = true;
                     }
-                    excl += (unsigned)(w & kLbCount);
-                    if (w & kLbInc) break;
-                    --j;
                 }
                 __hip_atomic_store(look + dd, lb_word(epoch, kLbInc, excl + run[dd]), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);

@@ -106,10 +106,13 @@ def test_interp_choice_meets_target(A, tmp_path):
     Y = inputs.mixture_embedding(n, 2, 8, -25, 25, 2.0, seed=23).astype(np.float64)
     r = A.tune_interp(Y, target=1e-3, safety=2.5, max_intervals=128, device=DEV, reps=3,
                       cache=str(tmp_path / "i.json"), forms=("A", "V"))
-    assert r["p"] in (4, 5, 6) and r["form"] in ("A", "V") and len(r["table"]) >= 2
+    assert r["p"] in A.PS and r["form"] in ("A", "V")
+    # one row per (form, p), the paper's p = 3 among them, each timed or with its reason
+    assert [(t["form"], t["p"]) for t in r["table"]] == [(f, p) for f in ("A", "V") for p in A.PS]
+    assert all(t["seconds"] is not None or t["note"] for t in r["table"])
     from paper_1712_09005_amd import tsne
     plan = tsne.Plan(n, 2, torch.float32, p=r["p"], interval_width=r["interval_width"],
-                     max_intervals=128, form=r["form"], device=DEV)
+                     max_intervals=r["max_intervals"], form=r["form"], device=DEV)
     F, _ = plan.repulsive(torch.from_numpy(Y.astype(np.float32)).to(DEV))
     Fd, _ = oracle.direct_rep(Y)
     e = rel(F.cpu().numpy(), Fd)

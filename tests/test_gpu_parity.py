@@ -240,15 +240,25 @@ def test_grids_form_v_match_oracle(T, dtype):
         assert rel(Vg[k], r["V"][k]) < (1e-9 if dtype == torch.float64 else 2e-5), k
 
 
-@pytest.mark.parametrize("p", [3, 4, 5])
+@pytest.mark.parametrize("p", [2, 3, 4, 5, 6])
 @pytest.mark.parametrize("form", ["A", "B", "V"])
-def test_repulsion_p_and_form(T, p, form):
-    print("case: p=%d form %s" % (p, form), flush=True)
-    Y = inputs.mixture_embedding(1500, 2, 5, -10, 10, 1.0, seed=2)
+@pytest.mark.parametrize("s", [1, 2])
+def test_repulsion_p_and_form(T, p, form, s):
+    """Every node count the library accepts (2..6), every form, 1-D and 2-D,
+    against the interpolation oracle in FP64 (and FP32 for the 2-D case)."""
+    print("case: p=%d form %s s=%d" % (p, form, s), flush=True)
+    Y = inputs.mixture_embedding(1500, s, 5, -10, 10, 1.0, seed=2)
     _, _, F, Z, st = gpu_rep(T, Y, torch.float64, p=p, policy="paper", min_int=20, max_int=64,
                              form=form)
+    assert st["status"] == 0
     (o, w, m), r = oracle_rep(Y, p, "paper", 1.0, 20, form)
+    assert st["n_int"] == m
     assert rel(F, r["F"]) < 1e-9 and abs(Z - r["Z"]) / r["Z"] < 1e-9
+    if s == 2:
+        _, _, F32, Z32, st = gpu_rep(T, Y, torch.float32, p=p, policy="paper", min_int=20,
+                                     max_int=64, form=form)
+        tol = 1e-5 if form == "V" else 1e-4
+        assert rel(F32, r["F"]) < tol and abs(Z32 - r["Z"]) / r["Z"] < tol
 
 
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-9), (torch.float32, 1e-4)])
