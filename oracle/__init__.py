@@ -230,8 +230,9 @@ def lagrange(p, t):
 
 
 def grid_conv(W, h, kernel, kind=KERNEL_TSNE):
-    """Step 2 directly on a 1-D [ng] or 2-D [ng1, ng0] (index [g1, g0]) grid.
-    kernel: 1 = K1, 2 = K2, 3 / 4 = the odd kernels z_0 K2, z_1 K2."""
+    """Step 2 directly on a 1-D [ng], 2-D [ng1, ng0] (index [g1, g0]) or 3-D
+    [ng2, ng1, ng0] grid.  kernel: 1 = K1, 2 = K2, 3 / 4 / 5 = the odd kernels
+    z_0 K2, z_1 K2, z_2 K2."""
     W = _f64(W)
     s = W.ndim
     ngv = np.array(W.shape[::-1], dtype=np.int32)         # [ng0(, ng1)]
@@ -336,8 +337,8 @@ def grid_conv_fft(W, h, kernel, kind=KERNEL_TSNE):
         lag = np.where(j < g, j, j - L).astype(np.float64)
         lag[g] = 0.0
         lags.append(lag)
-    grids = np.meshgrid(*lags, indexing="ij")             # axis order (g1,) g0
-    z = [h * grids[-1]] + ([h * grids[0]] if W.ndim == 2 else [])   # (z_0, z_1)
+    grids = np.meshgrid(*lags, indexing="ij")             # axis order (g2, g1,) g0
+    z = [h * grids[W.ndim - 1 - d] for d in range(W.ndim)]  # (z_0, z_1, z_2)
     T = np.asarray(_kernel_fn(kind, kernel)(z), dtype=np.float64)
     if T.ndim == 0:
         T = np.full(Lx, float(T))

@@ -15,8 +15,9 @@
  *   (1) direct sums: Z, the repulsive and attractive forces by their definitions
  *       (Section 1.1; Section 2, eq. (frep); Section 3);
  *   (2) the interpolation scheme with Step 2 done directly (Section 2.2 steps
- *       1-3 and Algorithm 1 without the FFT; Section 2.4 for s = 2; the
- *       Appendix for assembling the forces from the s+2 kernel sums);
+ *       1-3 and Algorithm 1 without the FFT; Section 2.4 for s = 2 and the
+ *       same tensor product for s = 3; the Appendix for assembling the forces
+ *       from the s+2 kernel sums);
  *   (3) the gradient-descent update (gradient of Section 1.1 with the
  *       exaggeration factor of Section 1.2 / Section 4; the step rule itself
  *       is not in the paper, see oracle_update).
@@ -256,142 +257,115 @@ static void locate(double y, double o, double w, int n_int, int* cell, double* t
     *t = u - (double)c;
 }
 
-/* Step 2 directly (eq. (equikereval2)): on a grid with ngv[d] nodes along
- * dimension d and spacing h,
- *   V[g] = sum_{g'} K(h (g - g')) W[g'],
- * where kernel selects K1 (1), K2 (2), or the odd vector kernels
- * G_d(z) = z_d K2(|z|^2) along dimension 0 (3) or 1 (4).  2-D grids are
- * indexed g1*ng0 + g0.  The kernel values come from a table over the lag
- * (|g0-g0'|, |g1-g1'|), with the sign of the lag along d for G_d: the
- * translation invariance that makes the matrix Toeplitz. */
+/* Grids of s = 1, 2 or 3 dimensions with ngv[d] nodes along dimension d are
+ * stored with dimension 0 fastest: node (g0, g1, g2) at g0 + ng0 (g1 + ng1 g2).
+ * Section 2.4 gives the tensor-product scheme for s = 2; the opening of
+ * Section 2 states the s + 2 sums for any s, and the same tensor product is
+ * used for s = 3. */
+static int64_t grid_size(int s, const int* ngv)
+{
+    int64_t t = 1;
+    for (int d = 0; d < s; ++d) t *= ngv[d];
+    return t;
+}
+
+/* Kernel value at the lag vector dg (in nodes) with spacing h: K1 (kernel 1),
+ * K2 (2), or the odd vector kernels G_d(z) = z_d K2(|z|^2) along dimension
+ * d = kernel - 3 (3, 4, 5), z = h dg with the sign of the lag. */
+static double kern_lag(int s, const int* dg, double h, int kind, int kernel)
+{
+    double r2 = 0.0;
+    for (int d = 0; d < s; ++d) r2 += (double)dg[d] * (double)dg[d];
+    r2 *= h * h;
+    if (kernel == 1) return kern1(kind, r2);
+    if (kernel == 2) return kern2(kind, r2);
+    return h * (double)dg[kernel - 3] * kern2(kind, r2);
+}
+
+/* Step 2 directly (eq. (equikereval2)): V[g] = sum_{g'} K(h (g - g')) W[g'],
+ * the kernel selected as in kern_lag.  The kernel values come from a table
+ * over the absolute lags (|dg0|, |dg1|, |dg2|), with the sign of the lag
+ * along d restored for G_d: the translation invariance that makes the matrix
+ * (block-)Toeplitz. */
 void oracle_grid_conv(int s, const int* ngv, double h, int kind, int kernel,
                       const double* W, double* V)
 {
-    const int ng = ngv[0], ng1 = (s == 2) ? ngv[1] : 1;
-    int64_t tn = (int64_t)ng * ng1;
+    int ng[3] = {1, 1, 1};
+    for (int d = 0; d < s; ++d) ng[d] = ngv[d];
+    const int64_t tn = (int64_t)ng[0] * ng[1] * ng[2];
     double* T = (double*)malloc((size_t)tn * sizeof(double));
     for (int64_t a = 0; a < tn; ++a) {
-        double dx = (double)(a % ng), dy = (s == 1) ? 0.0 : (double)(a / ng);
-        double r2 = h * h * (dx * dx + dy * dy);
-        if (kernel == 1) T[a] = kern1(kind, r2);
-        else if (kernel == 2) T[a] = kern2(kind, r2);
-        else if (kernel == 3) T[a] = h * dx * kern2(kind, r2);
-        else T[a] = h * dy * kern2(kind, r2);
+        int dg[3] = {(int)(a % ng[0]), (int)((a / ng[0]) % ng[1]), (int)(a / ((int64_t)ng[0] * ng[1]))};
+        T[a] = kern_lag(s, dg, h, kind, kernel);     /* odd kernels: |lag| here, sign below */
     }
-    if (s == 1) {
-#pragma omp parallel for schedule(static)
-        for (int g = 0; g < ng; ++g) {
-            double acc = 0.0;
-            for (int q = 0; q < ng; ++q) {
-                const double sg = (kernel == 3) ? (double)((g > q) - (g < q)) : 1.0;
-                acc += sg * T[abs(g - q)] * W[q];
-            }
-            V[g] = acc;
-        }
-    } else {
+    const int odd = (kernel >= 3) ? kernel - 3 : -1;
 #pragma omp parallel for schedule(dynamic, 4)
-        for (int64_t g = 0; g < tn; ++g) {
-            int g0 = (int)(g % ng), g1 = (int)(g / ng);
-            double acc = 0.0;
-            for (int q1 = 0; q1 < ng1; ++q1) {
-                const double* Trow = T + (int64_t)abs(g1 - q1) * ng;
-                const double* Wrow = W + (int64_t)q1 * ng;
-                const double s1 = (kernel == 4) ? (double)((g1 > q1) - (g1 < q1)) : 1.0;
-                for (int q0 = 0; q0 < ng; ++q0) {
-                    const double s0 = (kernel == 3) ? (double)((g0 > q0) - (g0 < q0)) : 1.0;
-                    acc += s0 * s1 * Trow[abs(g0 - q0)] * Wrow[q0];
+    for (int64_t g = 0; g < tn; ++g) {
+        const int g0 = (int)(g % ng[0]), g1 = (int)((g / ng[0]) % ng[1]),
+                  g2 = (int)(g / ((int64_t)ng[0] * ng[1]));
+        const int gg[3] = {g0, g1, g2};
+        double acc = 0.0;
+        for (int q2 = 0; q2 < ng[2]; ++q2)
+            for (int q1 = 0; q1 < ng[1]; ++q1) {
+                const int64_t trow = ((int64_t)abs(g2 - q2) * ng[1] + abs(g1 - q1)) * ng[0];
+                const int64_t wrow = ((int64_t)q2 * ng[1] + q1) * ng[0];
+                const int qq[3] = {0, q1, q2};
+                double sgn12 = 1.0;
+                if (odd == 1) sgn12 = (double)((gg[1] > qq[1]) - (gg[1] < qq[1]));
+                if (odd == 2) sgn12 = (double)((gg[2] > qq[2]) - (gg[2] < qq[2]));
+                for (int q0 = 0; q0 < ng[0]; ++q0) {
+                    const double s0 = (odd == 0) ? (double)((g0 > q0) - (g0 < q0)) : 1.0;
+                    acc += s0 * sgn12 * T[trow + abs(g0 - q0)] * W[wrow + q0];
                 }
             }
-            V[g] = acc;
-        }
+        V[g] = acc;
     }
     free(T);
 }
 
-/* The interpolation-based repulsion for s = 1 or 2 with the given box
- * (origin[s], interval width w, n_int[d] intervals along dimension d, p
- * nodes per interval).
- *
- * Charges (centred at the box centre c): form A {1, y'(d)}, form B
- * {1, y'(d), |y'|^2}; y' = y - c.  Potentials (s + 2 of them):
- *   pot[0] = K1 * 1 (form A)  or  K2 * |y'|^2 (form B)
- *   pot[1] = K2 * 1
- *   pot[2+d] = K2 * y'(d)
- * Form V (the vector-kernel variant, not in the paper): the single charge 1
- * and s + 1 potentials pot[0] = K1 * 1, pot[1+d] = G_d * 1 with the odd
- * kernels G_d(z) = z_d K2(|z|^2), so pot[1+d] at y_i is the numerator
- * sum_j (y_i(d) - y_j(d)) K2 itself, with no cancellation.
- * Step 1 spreads each charge onto the nodes of its point's interval (square),
- * Step 2 is oracle_grid_conv, Step 3 interpolates back (Section 2.2,
- * Algorithm 1; tensor-product nodes for s = 2, Section 2.4).  Assembly
- * (Appendix): h1 = pot[0] (form A) or
- * h1 = (1 + |y'|^2) pot[1] - 2 y'.pot[2..] + pot[0] (form B);
- * Z = sum_i h1_i - N K1(0); F_i(d) = (y'_i(d) pot[1]_i - pot[2+d]_i) / Z.
- *
- * Form V: h1 = pot[0], F_i(d) = pot[1+d]_i / Z.
- *
- * Outputs: F [n*s], Z; optional (may be NULL): Wout [C][ng^s] charge grids
- * (C = s+1 form A, s+2 form B, 1 form V; charge order 1, y'(0..s-1), |y'|^2),
- * Vout [P][ng^s] potential grids (P = s+2, or s+1 form V), phi [n][P]
- * potentials at the points, h1 [n].  Returns 0, or -1 on bad arguments. */
-int oracle_interp_rep(int64_t n, int s, const double* Y, const double* origin,
-                      double w, const int* n_int, int p, int form, int kind,
-                      double* F, double* Z, double* Wout, double* Vout,
-                      double* phi, double* h1out)
+/* Cell and Lagrange weights L[d][m] of one point along each dimension. */
+static void point_weights(int s, const double* y, const double* origin, double w,
+                          const int* n_int, int p, int* cell, double (*L)[16])
 {
-    if (s < 1 || s > 2 || p < 1 || n < 1) return -1;
-    for (int d = 0; d < s; ++d)
-        if (n_int[d] < 1) return -1;
-    int ng = n_int[0] * p;
-    int ngv[2] = {ng, (s == 2) ? n_int[1] * p : 1};
-    int64_t tn = (int64_t)ngv[0] * ngv[1];
-    int nc = (form == ORACLE_FORM_A) ? s + 1 : (form == ORACLE_FORM_B) ? s + 2 : 1;
-    int np = (form == ORACLE_FORM_V) ? s + 1 : s + 2;
-    double h = w / p;
-    double centre[2];
-    for (int d = 0; d < s; ++d) centre[d] = origin[d] + 0.5 * n_int[d] * w;
-
-    int* cells = (int*)malloc((size_t)n * s * sizeof(int));
-    double* wts = (double*)malloc((size_t)n * s * p * sizeof(double));
-    double* q = (double*)malloc((size_t)n * nc * sizeof(double));
-    for (int64_t i = 0; i < n; ++i) {
-        double r2c = 0.0;
-        q[i * nc + 0] = 1.0;
-        for (int d = 0; d < s; ++d) {
-            double t;
-            locate(Y[i * s + d], origin[d], w, n_int[d], &cells[i * s + d], &t);
-            oracle_lagrange(p, t, wts + (i * s + d) * p);
-            double yc = Y[i * s + d] - centre[d];
-            if (form != ORACLE_FORM_V) q[i * nc + 1 + d] = yc;
-            r2c += yc * yc;
-        }
-        if (form == ORACLE_FORM_B) q[i * nc + 1 + s] = r2c;
+    for (int d = 0; d < s; ++d) {
+        double t;
+        locate(y[d], origin[d], w, n_int[d], &cell[d], &t);
+        oracle_lagrange(p, t, L[d]);
     }
+}
 
-    /* Step 1: w_{m,l} = sum_{y_i in I_l} L_m(y_i) q_i */
-    double* W = (double*)calloc((size_t)nc * tn, sizeof(double));
-    for (int64_t i = 0; i < n; ++i) {
-        if (s == 1) {
-            for (int m = 0; m < p; ++m) {
-                int64_t g = (int64_t)cells[i] * p + m;
-                double l = wts[i * p + m];
-                for (int c = 0; c < nc; ++c) W[c * tn + g] += l * q[i * nc + c];
-            }
-        } else {
-            for (int m1 = 0; m1 < p; ++m1)
-                for (int m0 = 0; m0 < p; ++m0) {
-                    int64_t g0 = (int64_t)cells[i * 2 + 0] * p + m0;
-                    int64_t g1 = (int64_t)cells[i * 2 + 1] * p + m1;
-                    double l = wts[(i * 2 + 0) * p + m0] * wts[(i * 2 + 1) * p + m1];
-                    for (int c = 0; c < nc; ++c)
-                        W[c * tn + g1 * ng + g0] += l * q[i * nc + c];
-                }
-        }
+/* Node index and weight of the q-th of the p^s nodes of a point's interval
+ * (node offsets m_d = digits of q in base p, dimension 0 fastest); the weight
+ * is the product of the per-dimension Lagrange weights, dimension 0 first. */
+static int64_t node_of(int s, int q, int p, const int* cell, double (*L)[16], const int* ng,
+                       double* wt)
+{
+    int64_t g = 0, stride = 1;
+    double a = 1.0;
+    for (int d = 0; d < s; ++d) {
+        const int m = q % p;
+        q /= p;
+        g += (int64_t)(cell[d] * p + m) * stride;
+        stride *= ng[d];
+        a = (d == 0) ? L[0][m] : a * L[d][m];
     }
+    *wt = a;
+    return g;
+}
 
-    /* Step 2: v = K~ w for every (kernel, charge) pair */
-    double* V = (double*)malloc((size_t)np * tn * sizeof(double));
-    int pk[5], pc[5];
+static int ipow(int b, int e)
+{
+    int r = 1;
+    for (int k = 0; k < e; ++k) r *= b;
+    return r;
+}
+
+/* (kernel, charge) of each potential.  Charges (centred at the box centre c,
+ * y' = y - c): form A {1, y'(d)}, form B {1, y'(d), |y'|^2}, form V {1}.
+ * Potentials: form A/B pot[0] = K1 * 1 (A) or K2 * |y'|^2 (B), pot[1] = K2 * 1,
+ * pot[2+d] = K2 * y'(d); form V pot[0] = K1 * 1, pot[1+d] = G_d * 1. */
+static void pot_map(int s, int form, int* pk, int* pc)
+{
     if (form == ORACLE_FORM_V) {
         pk[0] = 1; pc[0] = 0;
         for (int d = 0; d < s; ++d) { pk[1 + d] = 3 + d; pc[1 + d] = 0; }
@@ -401,219 +375,210 @@ int oracle_interp_rep(int64_t n, int s, const double* Y, const double* origin,
         pk[1] = 2; pc[1] = 0;
         for (int d = 0; d < s; ++d) { pk[2 + d] = 2; pc[2 + d] = 1 + d; }
     }
-    for (int k = 0; k < np; ++k)
-        oracle_grid_conv(s, ngv, h, kind, pk[k], W + (int64_t)pc[k] * tn, V + (int64_t)k * tn);
+}
 
-    /* Step 3: phi(y_i) = sum_m L_m(y_i) v_{m,l} */
-    double* ph = (double*)calloc((size_t)n * np, sizeof(double));
-    for (int64_t i = 0; i < n; ++i) {
-        for (int k = 0; k < np; ++k) {
-            double acc = 0.0;
-            if (s == 1) {
-                for (int m = 0; m < p; ++m)
-                    acc += wts[i * p + m] * V[k * tn + (int64_t)cells[i] * p + m];
-            } else {
-                for (int m1 = 0; m1 < p; ++m1)
-                    for (int m0 = 0; m0 < p; ++m0) {
-                        int64_t g0 = (int64_t)cells[i * 2 + 0] * p + m0;
-                        int64_t g1 = (int64_t)cells[i * 2 + 1] * p + m1;
-                        acc += wts[(i * 2 + 0) * p + m0] * wts[(i * 2 + 1) * p + m1]
-                               * V[k * tn + g1 * ng + g0];
-                    }
-            }
-            ph[i * np + k] = acc;
-        }
+static int n_charges(int s, int form)
+{
+    return (form == ORACLE_FORM_A) ? s + 1 : (form == ORACLE_FORM_B) ? s + 2 : 1;
+}
+
+static int n_pots(int s, int form) { return (form == ORACLE_FORM_V) ? s + 1 : s + 2; }
+
+/* Charges of one point (see pot_map). */
+static void charges_of(int s, int form, const double* y, const double* centre, double* q)
+{
+    double r2c = 0.0;
+    q[0] = 1.0;
+    for (int d = 0; d < s; ++d) {
+        const double yc = y[d] - centre[d];
+        if (form != ORACLE_FORM_V) q[1 + d] = yc;
+        r2c += yc * yc;
     }
+    if (form == ORACLE_FORM_B) q[1 + s] = r2c;
+}
 
-    /* Assembly (Appendix) */
-    double z = 0.0;
-    double* h1 = (double*)malloc((size_t)n * sizeof(double));
-    for (int64_t i = 0; i < n; ++i) {
-        const double* f = ph + i * np;
-        double a;
-        if (form == ORACLE_FORM_A || form == ORACLE_FORM_V) {
-            a = f[0];
-        } else {
-            double r2c = q[i * nc + 1 + s], dot = 0.0;
-            for (int d = 0; d < s; ++d) dot += q[i * nc + 1 + d] * f[2 + d];
-            a = (1.0 + r2c) * f[1] - 2.0 * dot + f[0];
-        }
-        h1[i] = a;
-        z += a;
-    }
-    z -= (double)n * kern1(kind, 0.0);
-    for (int64_t i = 0; i < n; ++i)
-        for (int d = 0; d < s; ++d)
-            F[i * s + d] = (form == ORACLE_FORM_V)
-                               ? ph[i * np + 1 + d] / z
-                               : (q[i * nc + 1 + d] * ph[i * np + 1] - ph[i * np + 2 + d]) / z;
-    *Z = z;
-
-    if (Wout) memcpy(Wout, W, (size_t)nc * tn * sizeof(double));
-    if (Vout) memcpy(Vout, V, (size_t)np * tn * sizeof(double));
-    if (phi) memcpy(phi, ph, (size_t)n * np * sizeof(double));
-    if (h1out) memcpy(h1out, h1, (size_t)n * sizeof(double));
-    free(cells); free(wts); free(q); free(W); free(V); free(ph); free(h1);
+static int check_box(int s, int p, const int* n_int)
+{
+    if (s < 1 || s > 3 || p < 1 || p > 16) return -1;
+    for (int d = 0; d < s; ++d)
+        if (n_int[d] < 1) return -1;
     return 0;
 }
 
-/* Step 1 alone: the charge grids W [C][ng^s] of oracle_interp_rep. */
+/* Step 1 (Algorithm 1): the charge grids W [C][grid], w_{m,l} = sum over the
+ * points y_i of interval l of L_m(y_i) q_c(i) (tensor-product nodes). */
 int oracle_interp_spread(int64_t n, int s, const double* Y, const double* origin,
                          double w, const int* n_int, int p, int form, double* Wout)
 {
-    if (s < 1 || s > 2 || p < 1) return -1;
-    for (int d = 0; d < s; ++d)
-        if (n_int[d] < 1) return -1;
-    int ng = n_int[0] * p;
-    int64_t tn = (int64_t)ng * ((s == 2) ? n_int[1] * p : 1);
-    int nc = (form == ORACLE_FORM_A) ? s + 1 : (form == ORACLE_FORM_B) ? s + 2 : 1;
-    double centre[2], L0[16], L1[16];
+    if (check_box(s, p, n_int)) return -1;
+    int ng[3];
+    for (int d = 0; d < s; ++d) ng[d] = n_int[d] * p;
+    const int64_t tn = grid_size(s, ng);
+    const int nc = n_charges(s, form), pps = ipow(p, s);
+    double centre[3];
     for (int d = 0; d < s; ++d) centre[d] = origin[d] + 0.5 * n_int[d] * w;
     memset(Wout, 0, (size_t)nc * tn * sizeof(double));
     for (int64_t i = 0; i < n; ++i) {
-        int c0 = 0, c1 = 0;
-        double t0, t1 = 0.0, qv[4], r2c = 0.0;
-        locate(Y[i * s], origin[0], w, n_int[0], &c0, &t0);
-        oracle_lagrange(p, t0, L0);
-        if (s == 2) {
-            locate(Y[i * s + 1], origin[1], w, n_int[1], &c1, &t1);
-            oracle_lagrange(p, t1, L1);
-        } else {
-            L1[0] = 1.0;
+        int cell[3];
+        double L[3][16], qv[5];
+        point_weights(s, Y + i * s, origin, w, n_int, p, cell, L);
+        charges_of(s, form, Y + i * s, centre, qv);
+        for (int q = 0; q < pps; ++q) {
+            double l;
+            const int64_t g = node_of(s, q, p, cell, L, ng, &l);
+            for (int c = 0; c < nc; ++c) Wout[c * tn + g] += l * qv[c];
         }
-        qv[0] = 1.0;
-        for (int d = 0; d < s; ++d) {
-            qv[1 + d] = Y[i * s + d] - centre[d];
-            r2c += qv[1 + d] * qv[1 + d];
-        }
-        if (form == ORACLE_FORM_B) qv[1 + s] = r2c;
-        int p1 = (s == 2) ? p : 1;
-        for (int m1 = 0; m1 < p1; ++m1)
-            for (int m0 = 0; m0 < p; ++m0) {
-                int64_t g = (int64_t)(c1 * p + m1) * ((s == 2) ? ng : 0) + c0 * p + m0;
-                double l = L0[m0] * L1[m1];
-                for (int c = 0; c < nc; ++c) Wout[c * tn + g] += l * qv[c];
-            }
     }
     return 0;
 }
 
 /* Step 3 alone: phi [n][np] at every point from given potential grids
- * V [np][ng^s] (grid layout of oracle_interp_rep), phi_k(y_i) =
- * sum_m L_m(y_i) V_k[node m of the interval of y_i] (Section 2.2, Step 3;
- * tensor-product nodes for s = 2, Section 2.4). */
+ * V [np][grid], phi_k(y_i) = sum_m L_m(y_i) V_k[node m of the interval of
+ * y_i] (Section 2.2, Step 3; tensor-product nodes). */
 int oracle_interp_gather(int64_t n, int s, const double* Y, const double* origin,
                          double w, const int* n_int, int p, int np, const double* V,
                          double* phi)
 {
-    if (s < 1 || s > 2 || p < 1 || np < 1) return -1;
-    for (int d = 0; d < s; ++d)
-        if (n_int[d] < 1) return -1;
-    const int ng = n_int[0] * p;
-    const int64_t tn = (int64_t)ng * ((s == 2) ? n_int[1] * p : 1);
+    if (check_box(s, p, n_int) || np < 1) return -1;
+    int ng[3];
+    for (int d = 0; d < s; ++d) ng[d] = n_int[d] * p;
+    const int64_t tn = grid_size(s, ng);
+    const int pps = ipow(p, s);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
-        int c0 = 0, c1 = 0;
-        double t0, t1 = 0.0, L0[16], L1[16];
-        locate(Y[i * s], origin[0], w, n_int[0], &c0, &t0);
-        oracle_lagrange(p, t0, L0);
-        if (s == 2) {
-            locate(Y[i * s + 1], origin[1], w, n_int[1], &c1, &t1);
-            oracle_lagrange(p, t1, L1);
-        } else {
-            L1[0] = 1.0;
-        }
-        const int p1 = (s == 2) ? p : 1;
+        int cell[3];
+        double L[3][16];
+        point_weights(s, Y + i * s, origin, w, n_int, p, cell, L);
         for (int k = 0; k < np; ++k) {
             double acc = 0.0;
-            for (int m1 = 0; m1 < p1; ++m1)
-                for (int m0 = 0; m0 < p; ++m0) {
-                    const int64_t g = (int64_t)(c1 * p + m1) * ((s == 2) ? ng : 0) + c0 * p + m0;
-                    acc += L0[m0] * L1[m1] * V[(int64_t)k * tn + g];
-                }
+            for (int q = 0; q < pps; ++q) {
+                double l;
+                const int64_t g = node_of(s, q, p, cell, L, ng, &l);
+                acc += l * V[(int64_t)k * tn + g];
+            }
             phi[i * np + k] = acc;
         }
     }
     return 0;
 }
 
+/* The interpolation-based repulsion for s = 1, 2 or 3 with the given box
+ * (origin[s], interval width w, n_int[d] intervals along dimension d, p
+ * nodes per interval): Step 1 oracle_interp_spread, Step 2 oracle_grid_conv
+ * for every (kernel, charge) pair of pot_map, Step 3 oracle_interp_gather,
+ * then the assembly of the Appendix:
+ *   h1 = pot[0] (forms A and V) or (1 + |y'|^2) pot[1] - 2 y'.pot[2..] + pot[0] (B);
+ *   Z = sum_i h1_i - N K1(0);
+ *   F_i(d) = (y'_i(d) pot[1]_i - pot[2+d]_i) / Z (A, B) or pot[1+d]_i / Z (V).
+ * Outputs: F [n*s], Z; optional (may be NULL): Wout [C][grid] charge grids,
+ * Vout [P][grid] potential grids, phi [n][P] potentials at the points,
+ * h1 [n].  Returns 0, or -1 on bad arguments. */
+int oracle_interp_rep(int64_t n, int s, const double* Y, const double* origin,
+                      double w, const int* n_int, int p, int form, int kind,
+                      double* F, double* Z, double* Wout, double* Vout,
+                      double* phi, double* h1out)
+{
+    if (check_box(s, p, n_int) || n < 1) return -1;
+    int ng[3];
+    for (int d = 0; d < s; ++d) ng[d] = n_int[d] * p;
+    const int64_t tn = grid_size(s, ng);
+    const int nc = n_charges(s, form), np = n_pots(s, form);
+    const double h = w / p;
+    double centre[3];
+    for (int d = 0; d < s; ++d) centre[d] = origin[d] + 0.5 * n_int[d] * w;
+
+    double* W = (double*)malloc((size_t)nc * tn * sizeof(double));
+    oracle_interp_spread(n, s, Y, origin, w, n_int, p, form, W);
+    double* V = (double*)malloc((size_t)np * tn * sizeof(double));
+    int pk[6], pc[6];
+    pot_map(s, form, pk, pc);
+    for (int k = 0; k < np; ++k)
+        oracle_grid_conv(s, ng, h, kind, pk[k], W + (int64_t)pc[k] * tn, V + (int64_t)k * tn);
+    double* ph = (double*)malloc((size_t)n * np * sizeof(double));
+    oracle_interp_gather(n, s, Y, origin, w, n_int, p, np, V, ph);
+
+    double z = 0.0;
+    double* h1 = (double*)malloc((size_t)n * sizeof(double));
+    for (int64_t i = 0; i < n; ++i) {
+        const double* f = ph + i * np;
+        double qv[5];
+        charges_of(s, form, Y + i * s, centre, qv);
+        double a;
+        if (form == ORACLE_FORM_A || form == ORACLE_FORM_V) {
+            a = f[0];
+        } else {
+            double dot = 0.0;
+            for (int d = 0; d < s; ++d) dot += qv[1 + d] * f[2 + d];
+            a = (1.0 + qv[1 + s]) * f[1] - 2.0 * dot + f[0];
+        }
+        h1[i] = a;
+        z += a;
+    }
+    z -= (double)n * kern1(kind, 0.0);
+    for (int64_t i = 0; i < n; ++i) {
+        double qv[5];
+        charges_of(s, form, Y + i * s, centre, qv);
+        for (int d = 0; d < s; ++d)
+            F[i * s + d] = (form == ORACLE_FORM_V)
+                               ? ph[i * np + 1 + d] / z
+                               : (qv[1 + d] * ph[i * np + 1] - ph[i * np + 2 + d]) / z;
+    }
+    *Z = z;
+
+    if (Wout) memcpy(Wout, W, (size_t)nc * tn * sizeof(double));
+    if (Vout) memcpy(Vout, V, (size_t)np * tn * sizeof(double));
+    if (phi) memcpy(phi, ph, (size_t)n * np * sizeof(double));
+    if (h1out) memcpy(h1out, h1, (size_t)n * sizeof(double));
+    free(W); free(V); free(ph); free(h1);
+    return 0;
+}
+
 /* Per-point interpolated sums for a few listed rows, computing V only at the
  * nodes those rows read: each node value is the full direct sum of Step 2
  * over every node.  Needs the complete charge grids W (oracle_interp_spread).
- * Outputs phi [nrows][s+2] in the potential order of oracle_interp_rep. */
+ * Outputs phi [nrows][P] in the potential order of oracle_interp_rep. */
 int oracle_interp_rows(int64_t n, int s, const double* Y, const double* origin,
                        double w, const int* n_int, int p, int form, int kind,
                        const double* W, const int64_t* rows, int64_t nrows,
                        double* phi)
 {
     (void)n;
-    if (s < 1 || s > 2 || p < 1) return -1;
-    for (int d = 0; d < s; ++d)
-        if (n_int[d] < 1) return -1;
-    int ng = n_int[0] * p;
-    int ng1 = (s == 2) ? n_int[1] * p : 1;
-    int64_t tn = (int64_t)ng * ng1;
-    int np = (form == ORACLE_FORM_V) ? s + 1 : s + 2;
-    double h = w / p;
-    int pk[5], pc[5];
-    if (form == ORACLE_FORM_V) {
-        pk[0] = 1; pc[0] = 0;
-        for (int d = 0; d < s; ++d) { pk[1 + d] = 3 + d; pc[1 + d] = 0; }
-    } else {
-        if (form == ORACLE_FORM_A) { pk[0] = 1; pc[0] = 0; }
-        else                       { pk[0] = 2; pc[0] = s + 1; }
-        pk[1] = 2; pc[1] = 0;
-        for (int d = 0; d < s; ++d) { pk[2 + d] = 2; pc[2 + d] = 1 + d; }
-    }
-    /* kernel values by lag (|dg0|, |dg1|), as in oracle_grid_conv: K1, K2,
-     * then |z_0| K2 and |z_1| K2 (the odd kernels without their sign) */
-    double* T = (double*)malloc((size_t)4 * tn * sizeof(double));
-    for (int64_t a = 0; a < tn; ++a) {
-        double dx = (double)(a % ng), dy = (s == 1) ? 0.0 : (double)(a / ng);
-        double r2 = h * h * (dx * dx + dy * dy);
-        T[a] = kern1(kind, r2);
-        T[tn + a] = kern2(kind, r2);
-        T[2 * tn + a] = h * dx * kern2(kind, r2);
-        T[3 * tn + a] = h * dy * kern2(kind, r2);
-    }
+    if (check_box(s, p, n_int)) return -1;
+    int ng[3] = {1, 1, 1};
+    for (int d = 0; d < s; ++d) ng[d] = n_int[d] * p;
+    const int64_t tn = grid_size(s, ng);
+    const int np = n_pots(s, form), pps = ipow(p, s);
+    const double h = w / p;
+    int pk[6], pc[6];
+    pot_map(s, form, pk, pc);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t r = 0; r < nrows; ++r) {
-        int64_t i = rows[r];
-        int c0 = 0, c1 = 0;
-        double t0, t1 = 0.0, L0[16], L1[16];
-        locate(Y[i * s], origin[0], w, n_int[0], &c0, &t0);
-        oracle_lagrange(p, t0, L0);
-        if (s == 2) {
-            locate(Y[i * s + 1], origin[1], w, n_int[1], &c1, &t1);
-            oracle_lagrange(p, t1, L1);
-        } else {
-            L1[0] = 1.0;
-        }
-        int p1 = (s == 2) ? p : 1;
+        const int64_t i = rows[r];
+        int cell[3];
+        double L[3][16];
+        point_weights(s, Y + i * s, origin, w, n_int, p, cell, L);
         for (int k = 0; k < np; ++k) {
+            const double* Wc = W + (int64_t)pc[k] * tn;
             double acc = 0.0;
-            for (int m1 = 0; m1 < p1; ++m1)
-                for (int m0 = 0; m0 < p; ++m0) {
-                    int g0 = c0 * p + m0, g1 = (s == 2) ? c1 * p + m1 : 0;
-                    /* node value by the direct sum over all nodes */
-                    const double* Tk = T + (int64_t)(pk[k] - 1) * tn;
-                    const double* Wc = W + (int64_t)pc[k] * tn;
-                    double v = 0.0;
-                    for (int q1 = 0; q1 < ng1; ++q1) {
-                        const double* Trow = Tk + (int64_t)abs(g1 - q1) * ng;
-                        const double* Wrow = Wc + (int64_t)q1 * ng;
-                        const double s1 = (pk[k] == 4) ? (double)((g1 > q1) - (g1 < q1)) : 1.0;
-                        for (int q0 = 0; q0 < ng; ++q0) {
-                            const double s0 = (pk[k] == 3) ? (double)((g0 > q0) - (g0 < q0)) : 1.0;
-                            v += s0 * s1 * Trow[abs(g0 - q0)] * Wrow[q0];
-                        }
-                    }
-                    acc += L0[m0] * L1[m1] * v;
+            for (int q = 0; q < pps; ++q) {
+                double l;
+                const int64_t g = node_of(s, q, p, cell, L, ng, &l);
+                const int gg[3] = {(int)(g % ng[0]), (int)((g / ng[0]) % ng[1]),
+                                   (int)(g / ((int64_t)ng[0] * ng[1]))};
+                /* node value by the direct sum over all nodes */
+                double v = 0.0;
+                for (int64_t b = 0; b < tn; ++b) {
+                    const int qq[3] = {(int)(b % ng[0]), (int)((b / ng[0]) % ng[1]),
+                                       (int)(b / ((int64_t)ng[0] * ng[1]))};
+                    int dg[3];
+                    for (int d = 0; d < 3; ++d) dg[d] = gg[d] - qq[d];
+                    v += kern_lag(s, dg, h, kind, pk[k]) * Wc[b];
                 }
+                acc += l * v;
+            }
             phi[r * np + k] = acc;
         }
     }
-    free(T);
     return 0;
 }
 
