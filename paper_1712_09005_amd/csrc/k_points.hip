@@ -326,13 +326,10 @@ __global__ __launch_bounds__(256) void k_geom(LaunchMap map)
                 G.spec_h = G.h;
                 G.spec_M = G.M;
                 G.spec_My = G.My;
-                // radix sort of this iteration: digit width for the cell count,
-                // a new epoch for its look-back words, tile tickets from zero
+                // radix sort of this iteration: digit width for the cell count
                 const int nc1 = G.n_cells - 1;
                 const int bits = (nc1 > 0) ? 32 - __clz(nc1) : 1;
                 G.sort_bits = (bits + I.npass - 1) / I.npass;
-                G.sort_epoch += 1u;
-                for (int q = 0; q < I.npass; ++q) I.tickets[q] = 0u;
             }
         }
     } else if (threadIdx.x == 0) {
@@ -845,7 +842,8 @@ hipError_t launch_kind(int kind, const Cfg& c, const LaunchMap& map, const Launc
     case K_ATTR: case K_ATTR_ALL: case K_ATTR_T: case K_ATTR_T_ALL: case K_ASUM: case K_KL_ATTR:
     case K_KL: case K_KLSUM:
         return launch_attr_kind(kind, c, map, l, st);
-    case K_KEY: case K_SORT0: case K_SORT1: case K_SORT2: case K_BOUNDS: case K_SCAN_A: case K_SCAN_B:
+    case K_KEY: case K_HIST1: case K_HIST2: case K_TSCAN0: case K_TSCAN1: case K_TSCAN2:
+    case K_SORT0: case K_SORT1: case K_SORT2: case K_BOUNDS: case K_SCAN_A: case K_SCAN_B:
         return launch_sort_kind(kind, c, map, l, st);
     default:
         return c.dtype == 0 ? pts_s<float>(kind, c, map, l, st) : pts_s<double>(kind, c, map, l, st);

@@ -8,34 +8,25 @@
 // this iteration, not on atomics, launch timing or an earlier iteration, and
 // every floating-point sum taken over a cell's points later is reproducible.
 //
-//   k_key       cell of every point (point order) and the count of every digit
-//               value of every pass over all points;
-//   k_sort      one launch per pass: a tile of 2048 pairs is ranked stably by
-//               its digit in LDS, the tile's digit offsets come from a
-//               decoupled look-back over the tiles before it (tiles are taken
-//               in launch order from a ticket counter), and the tile is written
-//               out digit run by digit run; the last pass writes the sorted
-//               point indices, their cells and the sorted positions;
+// Each pass is reduce, scan, scatter over tiles of 2048 elements, and no
+// workgroup ever waits for another:
+//   k_key       cell of every point (point order), the first pass's digit
+//               count of every tile, and every pass's digit totals;
+//   k_hist      (passes after the first) the pass's digit count of every tile
+//               of the order the pass before wrote;
+//   k_tscan     per digit, an exclusive scan over the tiles of their counts,
+//               offset by the count of all smaller digits: each tile's first
+//               output position for each digit, in place of the counts;
+//   k_sort      a tile ranked stably by its digit in LDS and written out
+//               digit run by digit run at the positions k_tscan gave it; the
+//               last pass writes the sorted point indices, their cells and
+//               the sorted positions;
 //   k_bounds    first sorted position of every cell;
 //   k_scan_a/b  items (runs of at most kpts points of one cell) per cell and
 //               the item -> cell table used by the spreading kernel.
 #include "k_common.h"
 
 namespace tsne {
-
-// look-back word of one (tile, digit): the sort's epoch in the high 32 bits
-// (words of earlier iterations read as "not yet"), a flag and a count
-constexpr unsigned long long kLbAgg = 1ull << 30;   // the tile's own count
-constexpr unsigned long long kLbInc = 2ull << 30;   // count of this and all earlier tiles
-constexpr unsigned kLbCount = (1u << 30) - 1;
-constexpr int kSpinLimit = 1 << 20;                 // polls of one word before giving up
-constexpr int kLbWindow = 16;                       // earlier tiles requested at once
-
-__device__ __forceinline__ unsigned long long lb_word(unsigned epoch, unsigned long long flag,
-                                                      unsigned count)
-{
-    return ((unsigned long long)epoch << 32) | flag | (unsigned long long)count;
-}
 
 // Digits handled by a pass: sort_bits bits from pass * sort_bits up.
 __device__ __forceinline__ unsigned digit_of(unsigned key, int shift, unsigned mask)
@@ -56,7 +47,7 @@ __device__ __forceinline__ unsigned long long match_digit(unsigned d, bool valid
 }
 
 // Exclusive scan over kDigitBins values in LDS by 256 threads (two each),
-// in place; returns nothing, the total is not needed.
+// in place.
 __device__ __forceinline__ void block_excl_scan_bins(unsigned* v, unsigned* wsum)
 {
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -78,11 +69,19 @@ __device__ __forceinline__ void block_excl_scan_bins(unsigned* v, unsigned* wsum
 }
 
 static_assert(kDigitBins == 2 * 256, "two bins per thread");
+static_assert(kKeyTile == kSortTile, "the first pass's tiles are the key kernel's blocks");
 
-// Cell of every point in point order, and the per-pass digit counts over all
-// points: the lanes of a wave holding the same digit add their count to LDS
-// once (clustered inputs put many points of a block on few digits), and the
-// block adds each non-zero count to the global counts once.
+// Digit counts of one tile, per pass, in LDS (a block of 256 threads)
+// written out: the tile's row of the count table, all kDigitBins entries.
+__device__ __forceinline__ void put_tile_counts(const unsigned* hist, unsigned* row)
+{
+    const int t = threadIdx.x;
+    reinterpret_cast<uint2*>(row)[t] = make_uint2(hist[2 * t], hist[2 * t + 1]);
+}
+
+// Cell of every point in point order (stored for the first pass), the first
+// pass's digit counts of this tile, and every pass's digit totals over all
+// points (one global add per non-zero count of the tile).
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_key(LaunchMap map)
 {
@@ -92,30 +91,133 @@ __global__ __launch_bounds__(256) void k_key(LaunchMap map)
         const Geom& G = *I.geom;
         const int np = I.npass, sb = G.sort_bits;
         const unsigned mask = (1u << sb) - 1u;
-        const unsigned long long lt = (1ull << (threadIdx.x & 63)) - 1ull;
         for (int k = threadIdx.x; k < np * kDigitBins; k += 256) hist[k] = 0;
         __syncthreads();
         const T* Y = static_cast<const T*>(I.Yin);
         const int64_t base = (int64_t)lb * kKeyTile;
-        for (int r = 0; r < kKeyTile / 256; ++r) {
+        constexpr int PER = kKeyTile / 256;
+        Pt<T, S> y[PER];
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
             const int64_t i = base + r * 256 + threadIdx.x;
-            const bool valid = i < I.n;
-            unsigned key = 0;
-            if (valid) {
-                key = (unsigned)cell_of<T, S>(Pt<T, S>::load(Y, i), G);
+            if (i < I.n) y[r] = Pt<T, S>::load(Y, i);
+        }
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int64_t i = base + r * 256 + threadIdx.x;
+            if (i < I.n) {
+                const unsigned key = (unsigned)cell_of<T, S>(y[r], G);
                 I.key[i] = (int)key;
-            }
-            for (int p = 0; p < np; ++p) {
-                const unsigned d = digit_of(key, p * sb, mask);
-                const unsigned long long peers = match_digit(d, valid, sb);
-                if (valid && (peers & lt) == 0ull)
-                    atomicAdd(&hist[p * kDigitBins + d], (unsigned)__popcll(peers));
+                for (int p = 0; p < np; ++p)
+                    atomicAdd(&hist[p * kDigitBins + digit_of(key, p * sb, mask)], 1u);
             }
         }
         __syncthreads();
+        put_tile_counts(hist, I.tcnt + (int64_t)lb * kDigitBins);
         for (int k = threadIdx.x; k < np * kDigitBins; k += 256)
             if (hist[k]) atomicAdd(&I.ghist[k], hist[k]);
         __syncthreads();
+    }
+    VB_END
+}
+
+// Digit counts of every tile for a pass after the first, over the order the
+// pass before wrote.
+template <int PASS>
+__global__ __launch_bounds__(256) void k_hist(LaunchMap map)
+{
+    constexpr int KIND = (PASS == 1) ? K_HIST1 : K_HIST2;
+    constexpr int PER = kSortTile / 256;
+    __shared__ unsigned hist[kDigitBins];
+    VB_BEGIN_IF(map, KIND, (live(I) && PASS < I.npass))
+    {
+        const int sb = I.geom->sort_bits, shift = PASS * sb;
+        const unsigned mask = (1u << sb) - 1u;
+        const int64_t n = I.n;
+        hist[2 * threadIdx.x] = 0;
+        hist[2 * threadIdx.x + 1] = 0;
+        __syncthreads();
+        const uint2* kv_in = static_cast<const uint2*>(I.kv) + (int64_t)((PASS + 1) & 1) * n;
+        const int64_t base = (int64_t)lb * kSortTile;
+        unsigned key[PER];
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int64_t e = base + r * 256 + threadIdx.x;
+            key[r] = (e < n) ? kv_in[e].x : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < PER; ++r)
+            if (base + r * 256 + threadIdx.x < n) atomicAdd(&hist[digit_of(key[r], shift, mask)], 1u);
+        __syncthreads();
+        put_tile_counts(hist, I.tcnt + ((int64_t)PASS * I.ntiles_sort + lb) * kDigitBins);
+        __syncthreads();
+    }
+    VB_END
+}
+
+// Tile offsets of one pass, in place: for kScanDigits digits per block (a
+// lane each) and kScanWaves segments of the tiles (a wave each), the counts
+// are summed per segment, the segment sums scanned across the waves, and the
+// segment walked again writing each tile's first output position.
+template <int PASS>
+__global__ __launch_bounds__(kScanWaves * 64) void k_tscan(LaunchMap map)
+{
+    constexpr int KIND = K_TSCAN0 + PASS;
+    constexpr int U = 8;                               // counts loaded at once
+    __shared__ unsigned part[kScanWaves][kScanDigits];
+    __shared__ unsigned dbase[kScanDigits];
+    static_assert(kScanDigits == 64, "a lane per digit");
+    VB_BEGIN_IF(map, KIND, (live(I) && PASS < I.npass))
+    {
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const int d0 = lb * kScanDigits;
+        if (d0 < (1 << I.geom->sort_bits)) {              // the same for the whole block
+            const int d = d0 + lane;
+            const int nt = I.ntiles_sort;
+            const int seg = (nt + kScanWaves - 1) / kScanWaves;
+            const int ta = min(wv * seg, nt), tb = min(ta + seg, nt);
+            unsigned* col = I.tcnt + (int64_t)PASS * nt * kDigitBins + d;
+            const unsigned* gh = I.ghist + PASS * kDigitBins;
+            if (wv == 0) {
+                // count of all points with a smaller digit
+                unsigned below = 0;
+                for (int k = lane; k < d0; k += 64) below += gh[k];
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) below += __shfl_xor(below, o, 64);
+                const unsigned g = gh[d];
+                unsigned x = g;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const unsigned u = __shfl_up(x, o, 64);
+                    if (lane >= o) x += u;
+                }
+                dbase[lane] = below + x - g;
+            }
+            unsigned sum = 0;
+            for (int t = ta; t < tb; t += U) {
+                unsigned c[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) c[u] = (t + u < tb) ? col[(int64_t)(t + u) * kDigitBins] : 0u;
+#pragma unroll
+                for (int u = 0; u < U; ++u) sum += c[u];
+            }
+            part[wv][lane] = sum;
+            __syncthreads();
+            unsigned off = dbase[lane];
+            for (int w = 0; w < wv; ++w) off += part[w][lane];
+            for (int t = ta; t < tb; t += U) {
+                unsigned c[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) c[u] = (t + u < tb) ? col[(int64_t)(t + u) * kDigitBins] : 0u;
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (t + u < tb) {
+                        col[(int64_t)(t + u) * kDigitBins] = off;
+                        off += c[u];
+                    }
+            }
+            __syncthreads();
+        }
     }
     VB_END
 }
@@ -134,23 +236,24 @@ __global__ __launch_bounds__(256) void k_sort(LaunchMap map)
     __shared__ unsigned dbase[kDigitBins];        // first output position of each digit
     __shared__ uint2 stage[kSortTile];
     __shared__ unsigned wsum[4];
-    __shared__ unsigned ticket;
     VB_BEGIN_IF(map, KIND, (live(I) && PASS < I.npass))
     {
         const Geom& G = *I.geom;
         const int sb = G.sort_bits, shift = PASS * sb;
         const unsigned mask = (1u << sb) - 1u;
-        const int nbins = 1 << sb;
         const bool last = (PASS == I.npass - 1);
-        const unsigned epoch = G.sort_epoch;
         const int64_t n = I.n;
         const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-        if (t == 0) ticket = atomicAdd(&I.tickets[PASS], 1u);
+        const int tile = lb;
         for (int k = t; k < 2 * 4 * kDigitBins; k += 256) (&wcnt[0][0][0])[k] = 0;
         run[2 * t] = 0;
         run[2 * t + 1] = 0;
+        // this tile's first output position of each digit (from k_tscan)
+        const uint2 ofs = reinterpret_cast<const uint2*>(
+            I.tcnt + ((int64_t)PASS * I.ntiles_sort + tile) * kDigitBins)[t];
+        dbase[2 * t] = ofs.x;
+        dbase[2 * t + 1] = ofs.y;
         __syncthreads();
-        const int tile = (int)ticket;
         const int64_t base = (int64_t)tile * kSortTile;
         const uint2* kv_in = static_cast<const uint2*>(I.kv) + (int64_t)((PASS + 1) & 1) * n;
         uint2* kv_out = static_cast<uint2*>(I.kv) + (int64_t)(PASS & 1) * n;
@@ -208,70 +311,11 @@ __global__ __launch_bounds__(256) void k_sort(LaunchMap map)
             }
         }
         __syncthreads();
-        // publish the tile's counts, then look back over earlier tiles for
-        // the number of earlier elements of each digit
-        unsigned long long* look = I.look + ((int64_t)PASS * I.ntiles_sort + tile) * kDigitBins;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int dd = 2 * t + h;
-            if (dd < nbins)
-                __hip_atomic_store(look + dd, lb_word(epoch, tile == 0 ? kLbInc : kLbAgg, run[dd]),
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        // digit bases over all points: exclusive scan of the pass's counts
-        dbase[2 * t] = (2 * t < nbins) ? I.ghist[PASS * kDigitBins + 2 * t] : 0u;
-        dbase[2 * t + 1] = (2 * t + 1 < nbins) ? I.ghist[PASS * kDigitBins + 2 * t + 1] : 0u;
+        // first LDS slot of each digit: exclusive scan of the tile's counts
         dstart[2 * t] = run[2 * t];
         dstart[2 * t + 1] = run[2 * t + 1];
         __syncthreads();
-        block_excl_scan_bins(dbase, wsum);
         block_excl_scan_bins(dstart, wsum);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int dd = 2 * t + h;
-            if (dd >= nbins) continue;
-            unsigned excl = 0;
-            if (tile > 0) {
-                // windows of kLbWindow earlier tiles, nearest first: their words
-                // are requested together, then summed in order down to the
-                // first inclusive one (an entry not yet published is polled
-                // until it is, within kSpinLimit polls)
-                const unsigned long long* prev = I.look + ((int64_t)PASS * I.ntiles_sort) * kDigitBins + dd;
-                bool found = false;
-                for (int j = tile - 1; j >= 0 && !found; j -= kLbWindow) {
-                    unsigned long long w[kLbWindow];
-#pragma unroll
-                    for (int u = 0; u < kLbWindow; ++u)
-                        w[u] = (j - u >= 0) ? __hip_atomic_load(prev + (int64_t)(j - u) * kDigitBins,
-                                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                            : lb_word(epoch, kLbInc, 0);
-#pragma unroll
-                    for (int u = 0; u < kLbWindow; ++u) {
-                        if (found) break;
-                        unsigned long long x = w[u];
-                        int spins = 0;
-                        while ((unsigned)(x >> 32) != epoch || (x & (3ull << 30)) == 0) {
-                            if (++spins > kSpinLimit) {
-                                // an earlier tile never published: latch the
-                                // condition (the iteration's result is invalid)
-                                // instead of waiting for ever
-                                atomicCAS(I.status, 0, (int)ST_INTERNAL);
-                                x = lb_word(epoch, kLbInc, 0);
-                                break;
-                            }
-                            __builtin_amdgcn_s_sleep(1);
-                            x = __hip_atomic_load(prev + (int64_t)(j - u) * kDigitBins, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-                        }
-                        excl += (unsigned)(x & kLbCount);
-                        if (x & kLbInc) found = true;
-                    }
-                }
-                __hip_atomic_store(look + dd, lb_word(epoch, kLbInc, excl + run[dd]), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            }
-            dbase[dd] += excl;
-        }
         // stage the tile in digit order, then write it out run by run
 #pragma unroll
         for (int r = 0; r < PER; ++r)
@@ -444,6 +488,11 @@ static hipError_t launch_sort_ts(int kind, const LaunchMap& map, const Launch& l
     dim3 g(l.grid), b(l.block);
     switch (kind) {
     case K_KEY: hipLaunchKernelGGL((k_key<T, S>), g, b, 0, st, map); break;
+    case K_HIST1: hipLaunchKernelGGL(k_hist<1>, g, b, 0, st, map); break;
+    case K_HIST2: hipLaunchKernelGGL(k_hist<2>, g, b, 0, st, map); break;
+    case K_TSCAN0: hipLaunchKernelGGL(k_tscan<0>, g, b, 0, st, map); break;
+    case K_TSCAN1: hipLaunchKernelGGL(k_tscan<1>, g, b, 0, st, map); break;
+    case K_TSCAN2: hipLaunchKernelGGL(k_tscan<2>, g, b, 0, st, map); break;
     case K_SORT0: hipLaunchKernelGGL((k_sort<T, S, 0>), g, b, 0, st, map); break;
     case K_SORT1: hipLaunchKernelGGL((k_sort<T, S, 1>), g, b, 0, st, map); break;
     case K_SORT2: hipLaunchKernelGGL((k_sort<T, S, 2>), g, b, 0, st, map); break;

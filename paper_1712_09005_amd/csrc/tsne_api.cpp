@@ -71,7 +71,7 @@ struct Layout {
 
 enum Region {
     R_INST, R_PREFIX, R_GEOM, R_SCHED, R_SMALL, R_BOX, R_CSTART, R_ISTART, R_SCAN,
-    R_ICELL, R_KEY, R_KV, R_SKEY, R_GHIST, R_LOOK, R_PERM, R_SY, R_CARRY, R_W, R_X, R_XC, R_V, R_SPEC,
+    R_ICELL, R_KEY, R_KV, R_SKEY, R_GHIST, R_TCNT, R_PERM, R_SY, R_CARRY, R_W, R_X, R_XC, R_V, R_SPEC,
     R_TW, R_TWY, R_COS, R_CV, R_SPECTMP, R_KTAB, R_CCOS, R_R, R_FA, R_FAP, R_SPLIT, R_TOFF, R_EPACK,
     R_EVAL, R_ZPART, R_KLPART, R_H1, R_N
 };
@@ -206,6 +206,11 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     vb[K_SORT0] = o.ntiles_sort;
     vb[K_SORT1] = (o.npass > 1) ? o.ntiles_sort : 0;
     vb[K_SORT2] = (o.npass > 2) ? o.ntiles_sort : 0;
+    vb[K_HIST1] = vb[K_SORT1];
+    vb[K_HIST2] = vb[K_SORT2];
+    vb[K_TSCAN0] = kDigitBins / kScanDigits;
+    vb[K_TSCAN1] = (o.npass > 1) ? kDigitBins / kScanDigits : 0;
+    vb[K_TSCAN2] = (o.npass > 2) ? kDigitBins / kScanDigits : 0;
     vb[K_BOUNDS] = cdiv(n + 1, 256);
     vb[K_SCAN_A] = o.nb_scan;
     vb[K_SCAN_B] = o.nb_scan;
@@ -255,7 +260,7 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     sz[R_PREFIX] = sizeof(int) * K_NKINDS * 2;
     sz[R_GEOM] = sizeof(Geom);
     sz[R_SCHED] = sizeof(Sched);
-    sz[R_SMALL] = 64;                                   // status, iter, tickets[8]
+    sz[R_SMALL] = 64;                                   // status, iter
     sz[R_BOX] = sizeof(double) * 8 * o.nb_box;
     sz[R_CSTART] = sizeof(int) * (o.ncell_cap + 1);
     sz[R_ISTART] = sizeof(int) * (o.ncell_cap + 1);
@@ -265,7 +270,7 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     sz[R_KV] = (o.npass > 1) ? sizeof(uint32_t) * 2 * 2 * (size_t)n : 0;
     sz[R_SKEY] = sizeof(uint32_t) * n;
     sz[R_GHIST] = sizeof(uint32_t) * kMaxSortPass * kDigitBins;
-    sz[R_LOOK] = sizeof(uint64_t) * (size_t)o.npass * o.ntiles_sort * kDigitBins;
+    sz[R_TCNT] = sizeof(uint32_t) * (size_t)o.npass * o.ntiles_sort * kDigitBins;
     sz[R_PERM] = sizeof(int) * n;
     sz[R_SY] = (size_t)o.tsz * n * d->s;
     sz[R_CARRY] = (size_t)o.tsz * 2 * o.nwaves * nn * o.nc;
@@ -345,6 +350,9 @@ Launch launch_of(int kind, const Derived& o, int vblocks)
         l.block = 1024;
         l.lds = o.tile_lds;
         break;
+    case K_TSCAN0: case K_TSCAN1: case K_TSCAN2:
+        l.block = kScanWaves * 64;
+        break;
     default:
         break;
     }
@@ -399,12 +407,13 @@ static tsne_status enqueue(tsne_plan* pl, int kind)
 
 // Kernel order of one repulsion.  The table kernels (K_SPEC*) always run;
 // they return at once unless the box kernel found a new spacing or length.
-static const int kChain2[] = {K_BOX, K_GEOM, K_SPEC0, K_SPEC1, K_SPEC2, K_KEY, K_SORT0, K_SORT1,
-                              K_SORT2, K_BOUNDS, K_SCAN_A, K_SCAN_B, K_SPREAD, K_FIX, K_FFT_ROWS,
-                              K_FFT_COLS, K_FFT_IROWS, K_GATHER, K_ZSUM};
-static const int kChain1[] = {K_BOX, K_GEOM, K_SPEC0, K_SPEC1, K_KEY, K_SORT0, K_SORT1, K_SORT2,
-                              K_BOUNDS, K_SCAN_A, K_SCAN_B, K_SPREAD, K_FIX, K_FFT_1D, K_GATHER,
-                              K_ZSUM};
+static const int kChain2[] = {K_BOX, K_GEOM, K_SPEC0, K_SPEC1, K_SPEC2, K_KEY, K_TSCAN0, K_SORT0,
+                              K_HIST1, K_TSCAN1, K_SORT1, K_HIST2, K_TSCAN2, K_SORT2, K_BOUNDS,
+                              K_SCAN_A, K_SCAN_B, K_SPREAD, K_FIX, K_FFT_ROWS, K_FFT_COLS,
+                              K_FFT_IROWS, K_GATHER, K_ZSUM};
+static const int kChain1[] = {K_BOX, K_GEOM, K_SPEC0, K_SPEC1, K_KEY, K_TSCAN0, K_SORT0, K_HIST1,
+                              K_TSCAN1, K_SORT1, K_HIST2, K_TSCAN2, K_SORT2, K_BOUNDS, K_SCAN_A,
+                              K_SCAN_B, K_SPREAD, K_FIX, K_FFT_1D, K_GATHER, K_ZSUM};
 
 static tsne_status enqueue_repulsion(tsne_plan* pl, bool normalise)
 {
@@ -444,8 +453,7 @@ static void fill_sched(Sched& s, const tsne_sched* c)
 
 // Lay a plan over its workspace: the host image of the device record, the
 // launch prefix table, and the device state that must start at zero (the
-// geometry record, the schedule, status and counters, the sort's look-back
-// words).
+// geometry record, the schedule, status and counters).
 // Allocates nothing; synchronises the stream before returning.
 static tsne_status plan_init(tsne_plan* pl, const tsne_desc* desc, const Derived& o, char* b,
                              hipStream_t st)
@@ -490,7 +498,6 @@ static tsne_status plan_init(tsne_plan* pl, const tsne_desc* desc, const Derived
     h.sched = reinterpret_cast<Sched*>(b + off[R_SCHED]);
     h.status = reinterpret_cast<int*>(b + off[R_SMALL]);
     h.iter = reinterpret_cast<int*>(b + off[R_SMALL] + 4);
-    h.tickets = reinterpret_cast<unsigned*>(b + off[R_SMALL] + 16);
     h.box_part = reinterpret_cast<double*>(b + off[R_BOX]);
     h.cell_start = reinterpret_cast<int*>(b + off[R_CSTART]);
     h.item_start = reinterpret_cast<int*>(b + off[R_ISTART]);
@@ -500,7 +507,7 @@ static tsne_status plan_init(tsne_plan* pl, const tsne_desc* desc, const Derived
     h.kv = b + off[R_KV];
     h.skey = reinterpret_cast<unsigned*>(b + off[R_SKEY]);
     h.ghist = reinterpret_cast<unsigned*>(b + off[R_GHIST]);
-    h.look = reinterpret_cast<unsigned long long*>(b + off[R_LOOK]);
+    h.tcnt = reinterpret_cast<unsigned*>(b + off[R_TCNT]);
     h.npass = o.npass;
     h.ntiles_sort = o.ntiles_sort;
     h.perm = reinterpret_cast<int*>(b + off[R_PERM]);
@@ -555,7 +562,6 @@ static tsne_status plan_init(tsne_plan* pl, const tsne_desc* desc, const Derived
                     hip_ok(hipMemsetAsync(b + off[R_GEOM], 0, sizeof(Geom), st)) &&
                     hip_ok(hipMemsetAsync(b + off[R_SCHED], 0, sizeof(Sched), st)) &&
                     hip_ok(hipMemsetAsync(b + off[R_SMALL], 0, 64, st)) &&
-                    hip_ok(hipMemsetAsync(h.look, 0, off[R_LOOK + 1] - off[R_LOOK], st)) &&
                     hip_ok(hipStreamSynchronize(st));
     return ok ? TSNE_OK : TSNE_E_HIP;
 }

@@ -20,8 +20,10 @@ constexpr int kMaxP = 6;         // Lagrange nodes per interval
 constexpr int kWave = 64;
 
 // Binning: stable least-significant-digit radix sort of the points by cell.
-constexpr int kKeyTile = 4096;     // points per block of the key kernel (256 threads x 16)
+constexpr int kKeyTile = 2048;     // points per block of the key kernel (256 threads x 8)
 constexpr int kSortTile = 2048;    // points per tile of a sort pass (256 threads x 8)
+constexpr int kScanDigits = 64;    // digits per block of the tile-offset scan (a lane each)
+constexpr int kScanWaves = 16;     // tile segments per block of that scan (a wave each)
 constexpr int kDigitBitsMax = 9;   // at most 512 digit values per pass
 constexpr int kDigitBins = 1 << kDigitBitsMax;
 constexpr int kMaxSortPass = 3;    // cell indices of up to 27 bits
@@ -31,7 +33,7 @@ enum Kind : int {
     K_ARGS = 0, K_BOX, K_KEY, K_SORT0, K_SORT1, K_SORT2, K_BOUNDS, K_SCAN_A, K_SCAN_B, K_SPREAD, K_FIX,
     K_FFT_ROWS, K_FFT_COLS, K_FFT_IROWS, K_FFT_1D, K_GATHER, K_NORM, K_ATTR,
     K_UPDATE, K_SPEC0, K_SPEC1, K_SPEC2, K_GEOM, K_ZSUM, K_ATTR_ALL, K_ASUM, K_ATTR_T, K_ATTR_T_ALL,
-    K_KL, K_KLSUM, K_KL_ATTR, K_NKINDS
+    K_KL, K_KLSUM, K_KL_ATTR, K_HIST1, K_HIST2, K_TSCAN0, K_TSCAN1, K_TSCAN2, K_NKINDS
 };
 
 // Status bits latched on the device (values of tsne_status).
@@ -53,7 +55,6 @@ struct Geom {
     int n_cells;       // n_int^s
     int active;        // this iteration runs (set by the geometry kernel)
     int it;            // absolute index of this iteration
-    unsigned sort_epoch;   // counts the sorts of this plan (tags the look-back words)
     int sort_bits;     // digit bits per radix pass this iteration
     int spec_dirty;    // spacing or FFT length changed: tables must be rebuilt
     double spec_h;     // spacing the current spectra were built for
@@ -119,7 +120,6 @@ struct Inst {
     Sched* sched;
     int* status;
     int* iter;
-    unsigned* tickets;     // [8]: tile tickets of the radix passes
     double* box_part;      // [nb_box][2*s+... ] partial min/max/sum
     int* cell_start;       // [ncell_cap + 1]
     int* item_start;       // [ncell_cap + 1]
@@ -130,7 +130,8 @@ struct Inst {
     unsigned* skey;        // [n] cell of each sorted position
     int* perm;             // [n] sorted position -> point
     unsigned* ghist;       // [kMaxSortPass][kDigitBins] digit counts over all points
-    unsigned long long* look;  // [npass][ntiles_sort][kDigitBins] look-back words
+    unsigned* tcnt;        // [npass][ntiles_sort][kDigitBins] digit counts of every tile,
+                           // replaced by the tile's first output position per digit
     int npass, ntiles_sort;    // radix passes (from the cell capacity), sort tiles
     void* sY;              // [n][s] sorted positions
     void* carry;           // [2 * nwaves][1 + p^s * nc] spread carries

@@ -79,25 +79,31 @@ def test_run_twice_and_split_run_bitwise(T, form):
             assert np.array_equal(a, b), (k, name, int((a != b).sum()))
 
 
-def test_binning_is_the_stable_sort_by_cell(T):
+# (points, intervals capacity, interval width): one radix pass of at most 9
+# bits does not cover the capacity's cells, so these take two passes (few and
+# many tiles) and three passes (a capacity above 2^18 cells)
+BINNING = [(50_000, 128, 0.75), (300_001, 512, 0.1), (100_000, 600, 0.08)]
+
+
+@pytest.mark.parametrize("n,cap,width", BINNING)
+def test_binning_is_the_stable_sort_by_cell(T, n, cap, width):
     """The sorted permutation equals numpy's stable argsort of the cells the
     oracle assigns (same box, same interval rule), and the cell offsets are its
     run boundaries: exact, for a square and a rectangular box."""
     for rect in (False, True):
-        print("case: binning permutation rect=%s" % rect, flush=True)
-        n = 50_000
+        print("case: binning permutation n=%d cap=%d rect=%s" % (n, cap, rect), flush=True)
         Y = inputs.mixture_embedding(n, 2, 10, -20.0, 20.0, 1.5, seed=4)
         if rect:
             Y[:, 1] *= 0.3
-        plan = T.Plan(n, 2, torch.float32, p=5, policy="fixed", interval_width=0.75,
-                      max_intervals=128, form="V", rect=rect, device=DEV)
+        plan = T.Plan(n, 2, torch.float32, p=5, policy="fixed", interval_width=width,
+                      max_intervals=cap, form="V", rect=rect, device=DEV)
         plan.repulsive(torch.from_numpy(Y).to(DEV))
         torch.cuda.synchronize()
         st = plan.query()
         assert st["status"] == 0
         perm = np.frombuffer(plan.export(4), np.int32)
         cs = np.frombuffer(plan.export(3), np.int32)
-        o, w, m = oracle.geometry(Y.astype(np.float64), "fixed", 1, 0.75, rect=rect)
+        o, w, m = oracle.geometry(Y.astype(np.float64), "fixed", 1, width, rect=rect)
         mx, my = (m, m) if not rect else m
         assert (mx, my) == (st["n_int"], st["n_int_y"])
         cx = np.clip(np.floor((Y[:, 0].astype(np.float64) - o[0]) / w), 0, mx - 1).astype(np.int64)
