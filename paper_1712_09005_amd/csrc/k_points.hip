@@ -208,8 +208,6 @@ __global__ __launch_bounds__(256) void k_geom(LaunchMap map)
     Geom& G = *I.geom;
     const bool run = live_pre(I);
     if (run) {
-        // digit counts of this iteration's radix passes start from zero
-        for (int k = threadIdx.x; k < I.npass * kDigitBins; k += 256) I.ghist[k] = 0u;
         const int nb = I.nb_box;
         double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
         double sm[2] = {0.0, 0.0}, bad = 0.0;

@@ -10,17 +10,19 @@
 //
 // Each pass is reduce, scan, scatter over tiles of 2048 elements, and no
 // workgroup ever waits for another:
-//   k_key       cell of every point (point order), the first pass's digit
-//               count of every tile, and every pass's digit totals;
+//   k_key       cell of every point (point order) and the first pass's digit
+//               count of every tile;
 //   k_hist      (passes after the first) the pass's digit count of every tile
 //               of the order the pass before wrote;
-//   k_tscan     per digit, an exclusive scan over the tiles of their counts,
-//               offset by the count of all smaller digits: each tile's first
-//               output position for each digit, in place of the counts;
+//   k_tscan     the tiles in groups of group_tiles: per group and digit, an
+//               exclusive scan of the counts over the group's tiles (in place)
+//               and the group's total;
 //   k_sort      a tile ranked stably by its digit in LDS and written out
-//               digit run by digit run at the positions k_tscan gave it; the
-//               last pass writes the sorted point indices, their cells and
-//               the sorted positions;
+//               digit run by digit run: a digit's run starts at the count of
+//               all smaller digits (a scan of the totals over the groups),
+//               plus the digit's count in earlier groups, plus its count in
+//               earlier tiles of the group; the last pass writes the sorted
+//               point indices, their cells and the sorted positions;
 //   k_bounds    first sorted position of every cell;
 //   k_scan_a/b  items (runs of at most kpts points of one cell) per cell and
 //               the item -> cell table used by the spreading kernel.
@@ -79,19 +81,18 @@ __device__ __forceinline__ void put_tile_counts(const unsigned* hist, unsigned* 
     reinterpret_cast<uint2*>(row)[t] = make_uint2(hist[2 * t], hist[2 * t + 1]);
 }
 
-// Cell of every point in point order (stored for the first pass), the first
-// pass's digit counts of this tile, and every pass's digit totals over all
-// points (one global add per non-zero count of the tile).
+// Cell of every point in point order (stored for the first pass) and the
+// first pass's digit counts of this tile.
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_key(LaunchMap map)
 {
-    __shared__ unsigned hist[kMaxSortPass * kDigitBins];
+    __shared__ unsigned hist[kDigitBins];
     VB_BEGIN(map, K_KEY)
     if (live(I)) {
         const Geom& G = *I.geom;
-        const int np = I.npass, sb = G.sort_bits;
-        const unsigned mask = (1u << sb) - 1u;
-        for (int k = threadIdx.x; k < np * kDigitBins; k += 256) hist[k] = 0;
+        const unsigned mask = (1u << G.sort_bits) - 1u;
+        hist[2 * threadIdx.x] = 0;
+        hist[2 * threadIdx.x + 1] = 0;
         __syncthreads();
         const T* Y = static_cast<const T*>(I.Yin);
         const int64_t base = (int64_t)lb * kKeyTile;
@@ -108,14 +109,11 @@ __global__ __launch_bounds__(256) void k_key(LaunchMap map)
             if (i < I.n) {
                 const unsigned key = (unsigned)cell_of<T, S>(y[r], G);
                 I.key[i] = (int)key;
-                for (int p = 0; p < np; ++p)
-                    atomicAdd(&hist[p * kDigitBins + digit_of(key, p * sb, mask)], 1u);
+                atomicAdd(&hist[digit_of(key, 0, mask)], 1u);
             }
         }
         __syncthreads();
         put_tile_counts(hist, I.tcnt + (int64_t)lb * kDigitBins);
-        for (int k = threadIdx.x; k < np * kDigitBins; k += 256)
-            if (hist[k]) atomicAdd(&I.ghist[k], hist[k]);
         __syncthreads();
     }
     VB_END
@@ -155,62 +153,59 @@ __global__ __launch_bounds__(256) void k_hist(LaunchMap map)
     VB_END
 }
 
-// Tile offsets of one pass, in place: for kScanDigits digits per block (a
-// lane each) and kScanWaves segments of the tiles (a wave each), the counts
-// are summed per segment, the segment sums scanned across the waves, and the
-// segment walked again writing each tile's first output position.
+// Offsets within the groups of tiles for one pass, in place: a block takes
+// one group and kScanDigits digits (a lane each); its four waves split the
+// group's tiles, sum their counts, scan the sums across the waves and walk
+// their tiles again writing each tile's count of the digit in the group's
+// earlier tiles.  The last wave writes the group's total of the digit.
 template <int PASS>
-__global__ __launch_bounds__(kScanWaves * 64) void k_tscan(LaunchMap map)
+__global__ __launch_bounds__(256) void k_tscan(LaunchMap map)
 {
     constexpr int KIND = K_TSCAN0 + PASS;
-    constexpr int U = 8;                               // counts loaded at once
-    __shared__ unsigned part[kScanWaves][kScanDigits];
-    __shared__ unsigned dbase[kScanDigits];
+    constexpr int kU = 16;                             // counts loaded at once
+    __shared__ unsigned part[4][kScanDigits];
     static_assert(kScanDigits == 64, "a lane per digit");
     VB_BEGIN_IF(map, KIND, (live(I) && PASS < I.npass))
     {
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        const int d0 = lb * kScanDigits;
+        constexpr int nchunk = kDigitBins / kScanDigits;
+        const int grp = lb / nchunk, d0 = (lb - grp * nchunk) * kScanDigits;
         if (d0 < (1 << I.geom->sort_bits)) {              // the same for the whole block
             const int d = d0 + lane;
-            const int nt = I.ntiles_sort;
-            const int seg = (nt + kScanWaves - 1) / kScanWaves;
-            const int ta = min(wv * seg, nt), tb = min(ta + seg, nt);
+            const int nt = I.ntiles_sort, gt = I.group_tiles;
+            const int q = gt / 4;                          // tiles per wave
+            const int ta = min(grp * gt + wv * q, nt), tb = min(ta + q, nt);
             unsigned* col = I.tcnt + (int64_t)PASS * nt * kDigitBins + d;
-            const unsigned* gh = I.ghist + PASS * kDigitBins;
-            if (wv == 0) {
-                // count of all points with a smaller digit
-                unsigned below = 0;
-                for (int k = lane; k < d0; k += 64) below += gh[k];
+            unsigned c0[kU];
 #pragma unroll
-                for (int o = 32; o > 0; o >>= 1) below += __shfl_xor(below, o, 64);
-                const unsigned g = gh[d];
-                unsigned x = g;
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    const unsigned u = __shfl_up(x, o, 64);
-                    if (lane >= o) x += u;
-                }
-                dbase[lane] = below + x - g;
-            }
+            for (int u = 0; u < kU; ++u) c0[u] = (ta + u < tb) ? col[(int64_t)(ta + u) * kDigitBins] : 0u;
             unsigned sum = 0;
-            for (int t = ta; t < tb; t += U) {
-                unsigned c[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) c[u] = (t + u < tb) ? col[(int64_t)(t + u) * kDigitBins] : 0u;
+            for (int u = 0; u < kU; ++u) sum += c0[u];
+            for (int t = ta + kU; t < tb; t += kU) {
+                unsigned c[kU];
 #pragma unroll
-                for (int u = 0; u < U; ++u) sum += c[u];
+                for (int u = 0; u < kU; ++u) c[u] = (t + u < tb) ? col[(int64_t)(t + u) * kDigitBins] : 0u;
+#pragma unroll
+                for (int u = 0; u < kU; ++u) sum += c[u];
             }
             part[wv][lane] = sum;
             __syncthreads();
-            unsigned off = dbase[lane];
+            unsigned off = 0;
             for (int w = 0; w < wv; ++w) off += part[w][lane];
-            for (int t = ta; t < tb; t += U) {
-                unsigned c[U];
+            if (wv == 3) I.gtot[((int64_t)PASS * I.ngroups_sort + grp) * kDigitBins + d] = off + sum;
 #pragma unroll
-                for (int u = 0; u < U; ++u) c[u] = (t + u < tb) ? col[(int64_t)(t + u) * kDigitBins] : 0u;
+            for (int u = 0; u < kU; ++u)
+                if (ta + u < tb) {
+                    col[(int64_t)(ta + u) * kDigitBins] = off;
+                    off += c0[u];
+                }
+            for (int t = ta + kU; t < tb; t += kU) {
+                unsigned c[kU];
 #pragma unroll
-                for (int u = 0; u < U; ++u)
+                for (int u = 0; u < kU; ++u) c[u] = (t + u < tb) ? col[(int64_t)(t + u) * kDigitBins] : 0u;
+#pragma unroll
+                for (int u = 0; u < kU; ++u)
                     if (t + u < tb) {
                         col[(int64_t)(t + u) * kDigitBins] = off;
                         off += c[u];
@@ -225,13 +220,19 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_tscan(LaunchMap map)
 // One pass of the radix sort over the tiles of one instance (see the file
 // comment).  Pass 0 reads the cells of k_key with the identity order; later
 // passes read the (cell, index) pairs of the pass before.
+//
+// Wave w of the block holds the tile's elements w * 512 ... w * 512 + 511 and
+// ranks them, 64 at a time in element order, against counts of its own in
+// LDS, so the ranking needs no barrier; the waves' counts are then combined
+// once per digit (earlier waves first), which keeps the ranks stable.
 template <typename T, int S, int PASS>
 __global__ __launch_bounds__(256) void k_sort(LaunchMap map)
 {
-    constexpr int PER = kSortTile / 256;
+    constexpr int PER = kSortTile / 256;          // rounds of 64 elements per wave
+    constexpr int WCH = kSortTile / 4;            // elements per wave
     constexpr int KIND = K_SORT0 + PASS;
-    __shared__ unsigned wcnt[2][4][kDigitBins];   // per round parity and wave: tag << 16 | count
-    __shared__ unsigned run[kDigitBins];          // tile count of each digit so far
+    __shared__ unsigned whist[4][kDigitBins];     // per wave: count of each digit so far, then
+                                                  // the wave's first slot within the digit's run
     __shared__ unsigned dstart[kDigitBins];       // first LDS slot of each digit in the tile
     __shared__ unsigned dbase[kDigitBins];        // first output position of each digit
     __shared__ uint2 stage[kSortTile];
@@ -241,20 +242,33 @@ __global__ __launch_bounds__(256) void k_sort(LaunchMap map)
         const Geom& G = *I.geom;
         const int sb = G.sort_bits, shift = PASS * sb;
         const unsigned mask = (1u << sb) - 1u;
+        const int nbins = 1 << sb;
         const bool last = (PASS == I.npass - 1);
         const int64_t n = I.n;
         const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
         const int tile = lb;
-        for (int k = t; k < 2 * 4 * kDigitBins; k += 256) (&wcnt[0][0][0])[k] = 0;
-        run[2 * t] = 0;
-        run[2 * t + 1] = 0;
-        // this tile's first output position of each digit (from k_tscan)
+        for (int k = t; k < 4 * kDigitBins; k += 256) (&whist[0][0])[k] = 0;
+        // the digit's count in earlier groups and over all groups (k_tscan)
+        const int grp = tile / I.group_tiles, ng = I.ngroups_sort;
+        const unsigned* gt = I.gtot + (int64_t)PASS * ng * kDigitBins;
+        unsigned before[2] = {0u, 0u}, total[2] = {0u, 0u};
+        for (int g = 0; g < ng; ++g) {
+            const uint2 v = (2 * t < nbins) ? reinterpret_cast<const uint2*>(gt + (int64_t)g * kDigitBins)[t]
+                                            : make_uint2(0u, 0u);
+            if (g < grp) {
+                before[0] += v.x;
+                before[1] += v.y;
+            }
+            total[0] += v.x;
+            total[1] += v.y;
+        }
+        // the digit's count in earlier tiles of the group (k_tscan)
         const uint2 ofs = reinterpret_cast<const uint2*>(
             I.tcnt + ((int64_t)PASS * I.ntiles_sort + tile) * kDigitBins)[t];
-        dbase[2 * t] = ofs.x;
-        dbase[2 * t + 1] = ofs.y;
-        __syncthreads();
+        dbase[2 * t] = total[0];
+        dbase[2 * t + 1] = total[1];
         const int64_t base = (int64_t)tile * kSortTile;
+        const int64_t wbase = base + (int64_t)wv * WCH;
         const uint2* kv_in = static_cast<const uint2*>(I.kv) + (int64_t)((PASS + 1) & 1) * n;
         uint2* kv_out = static_cast<uint2*>(I.kv) + (int64_t)(PASS & 1) * n;
         unsigned key[PER];
@@ -262,7 +276,7 @@ __global__ __launch_bounds__(256) void k_sort(LaunchMap map)
         unsigned lrank[PER];
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
-            const int64_t e = base + r * 256 + t;
+            const int64_t e = wbase + r * 64 + lane;
             key[r] = 0;
             idx[r] = -1;
             lrank[r] = 0;
@@ -277,7 +291,11 @@ __global__ __launch_bounds__(256) void k_sort(LaunchMap map)
                 }
             }
         }
-        // stable ranks within the tile, round by round in element order
+        __syncthreads();
+        // stable ranks within the wave's elements, round by round in element
+        // order: each round reads the wave's counts, then the first lane of
+        // each digit adds the round's count (one wave: program order suffices)
+        unsigned* wh = whist[wv];
         const unsigned long long lt = (1ull << lane) - 1ull;
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
@@ -285,55 +303,70 @@ __global__ __launch_bounds__(256) void k_sort(LaunchMap map)
             const unsigned d = digit_of(key[r], shift, mask);
             const unsigned long long peers = match_digit(d, valid, sb);
             const unsigned wrank = (unsigned)__popcll(peers & lt);
-            const unsigned tag = (unsigned)(r + 1) << 16;
-            const int buf = r & 1;
-            if (valid && wrank == 0) wcnt[buf][wv][d] = tag | (unsigned)__popcll(peers);
-            __syncthreads();
-            if (valid) {
-                unsigned pre = run[d];
-                for (int w = 0; w < wv; ++w) {
-                    const unsigned x = wcnt[buf][w][d];
-                    if ((x & 0xffff0000u) == tag) pre += x & 0xffffu;
-                }
-                lrank[r] = pre + wrank;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int dd = 2 * t + h;
-                unsigned add = 0;
-#pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    const unsigned x = wcnt[buf][w][dd];
-                    if ((x & 0xffff0000u) == tag) add += x & 0xffffu;
-                }
-                run[dd] += add;
-            }
+            const unsigned cur = valid ? wh[d] : 0u;
+            lrank[r] = cur + wrank;
+            if (valid && wrank == 0) wh[d] = cur + (unsigned)__popcll(peers);
         }
         __syncthreads();
-        // first LDS slot of each digit: exclusive scan of the tile's counts
-        dstart[2 * t] = run[2 * t];
-        dstart[2 * t + 1] = run[2 * t + 1];
-        __syncthreads();
+        // per digit: the tile's count and each wave's first slot in the run
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int dd = 2 * t + h;
+            unsigned acc = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const unsigned c = whist[w][dd];
+                whist[w][dd] = acc;
+                acc += c;
+            }
+            dstart[dd] = acc;
+        }
+        // first LDS slot of each digit: exclusive scan of the tile's counts;
+        // first output position: the scan of the totals plus the counts in
+        // earlier groups and earlier tiles of the group
+        block_excl_scan_bins(dbase, wsum);
+        dbase[2 * t] += before[0] + ofs.x;
+        dbase[2 * t + 1] += before[1] + ofs.y;
         block_excl_scan_bins(dstart, wsum);
         // stage the tile in digit order, then write it out run by run
 #pragma unroll
         for (int r = 0; r < PER; ++r)
-            if (idx[r] >= 0) stage[dstart[digit_of(key[r], shift, mask)] + lrank[r]] = make_uint2(key[r], (unsigned)idx[r]);
+            if (idx[r] >= 0) {
+                const unsigned d = digit_of(key[r], shift, mask);
+                stage[dstart[d] + wh[d] + lrank[r]] = make_uint2(key[r], (unsigned)idx[r]);
+            }
         __syncthreads();
         const int tcount = (int)min<int64_t>(kSortTile, n - base);
         const T* Y = static_cast<const T*>(I.Yin);
-        for (int j = t; j < tcount; j += 256) {
-            const uint2 q = stage[j];
-            const unsigned d = digit_of(q.x, shift, mask);
-            const int64_t dst = (int64_t)dbase[d] + (j - (int)dstart[d]);
-            if (!last) {
-                kv_out[dst] = q;
-            } else {
-                I.perm[dst] = (int)q.y;
-                I.skey[dst] = q.x;
-                Pt<T, S>::load(Y, (int64_t)q.y).store(static_cast<T*>(I.sY), dst);
+        uint2 q[PER];
+        int64_t dst[PER];
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int j = r * 256 + t;
+            dst[r] = -1;
+            if (j < tcount) {
+                q[r] = stage[j];
+                const unsigned d = digit_of(q[r].x, shift, mask);
+                dst[r] = (int64_t)dbase[d] + (j - (int)dstart[d]);
             }
+        }
+        if (!last) {
+#pragma unroll
+            for (int r = 0; r < PER; ++r)
+                if (dst[r] >= 0) kv_out[dst[r]] = q[r];
+        } else {
+            // every gather of the tile in flight before the first store
+            Pt<T, S> y[PER];
+#pragma unroll
+            for (int r = 0; r < PER; ++r)
+                if (dst[r] >= 0) y[r] = Pt<T, S>::load(Y, (int64_t)q[r].y);
+#pragma unroll
+            for (int r = 0; r < PER; ++r)
+                if (dst[r] >= 0) {
+                    I.perm[dst[r]] = (int)q[r].y;
+                    I.skey[dst[r]] = q[r].x;
+                    y[r].store(static_cast<T*>(I.sY), dst[r]);
+                }
         }
         __syncthreads();
     }

@@ -71,14 +71,14 @@ struct Layout {
 
 enum Region {
     R_INST, R_PREFIX, R_GEOM, R_SCHED, R_SMALL, R_BOX, R_CSTART, R_ISTART, R_SCAN,
-    R_ICELL, R_KEY, R_KV, R_SKEY, R_GHIST, R_TCNT, R_PERM, R_SY, R_CARRY, R_W, R_X, R_XC, R_V, R_SPEC,
+    R_ICELL, R_KEY, R_KV, R_SKEY, R_TCNT, R_GTOT, R_PERM, R_SY, R_CARRY, R_W, R_X, R_XC, R_V, R_SPEC,
     R_TW, R_TWY, R_COS, R_CV, R_SPECTMP, R_KTAB, R_CCOS, R_R, R_FA, R_FAP, R_SPLIT, R_TOFF, R_EPACK,
     R_EVAL, R_ZPART, R_KLPART, R_H1, R_N
 };
 
 struct Derived {
     int s, p, nc, np, tsz, max_int, n_cap, M, half, ncell_cap, items_cap, kpts, lpr;
-    int npass, ntiles_sort;
+    int npass, ntiles_sort, group_tiles, ngroups_sort;
     int nstages, radix[kMaxStages], rmin;
     int slabs, slab_w;
     int tiled, tile_bi, tile_bj, tile_ni, tile_nj;
@@ -190,14 +190,19 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     o.col_group = 1;                                   // columns per block at capacity
     while (o.col_group < o.tile_w && (size_t)(2 * o.col_group) * pm <= o.col_lds) o.col_group *= 2;
     o.col_threads = std::max(256, pow2_at_least(cdiv((int64_t)(o.col_lds / csz), (int64_t)o.rmin * kMaxBfly)));
-    if (o.row_lds > 160 * 1024) return TSNE_E_UNSUPPORTED;
-    if (d->s == 2 && (o.col_threads > 1024 || o.col_lds > 160 * 1024)) return TSNE_E_UNSUPPORTED;
+    // the transforms also hold their stage plan in static LDS (under 256 bytes)
+    constexpr size_t kLdsMax = 160 * 1024 - 256;
+    if (o.row_lds > kLdsMax) return TSNE_E_UNSUPPORTED;
+    if (d->s == 2 && (o.col_threads > 1024 || o.col_lds > kLdsMax)) return TSNE_E_UNSUPPORTED;
 
     o.nb_box = std::min(512, std::max(1, cdiv(n, 256 * 4)));
     o.nb_gather = cdiv(n, 256);
     o.nb_kl = (int)std::min<int64_t>(2048, cdiv(n, 8));
     o.nb_scan = cdiv(o.ncell_cap, 1024);
     o.ntiles_sort = cdiv(n, kSortTile);
+    // groups of the offset scan: at most kScanGroups, of a multiple of 4 tiles
+    o.group_tiles = 4 * cdiv(cdiv(o.ntiles_sort, kScanGroups), 4);
+    o.ngroups_sort = cdiv(o.ntiles_sort, o.group_tiles);
 
     int* vb = o.vb;
     for (int k = 0; k < K_NKINDS; ++k) vb[k] = 0;
@@ -208,9 +213,9 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     vb[K_SORT2] = (o.npass > 2) ? o.ntiles_sort : 0;
     vb[K_HIST1] = vb[K_SORT1];
     vb[K_HIST2] = vb[K_SORT2];
-    vb[K_TSCAN0] = kDigitBins / kScanDigits;
-    vb[K_TSCAN1] = (o.npass > 1) ? kDigitBins / kScanDigits : 0;
-    vb[K_TSCAN2] = (o.npass > 2) ? kDigitBins / kScanDigits : 0;
+    vb[K_TSCAN0] = o.ngroups_sort * (kDigitBins / kScanDigits);
+    vb[K_TSCAN1] = (o.npass > 1) ? vb[K_TSCAN0] : 0;
+    vb[K_TSCAN2] = (o.npass > 2) ? vb[K_TSCAN0] : 0;
     vb[K_BOUNDS] = cdiv(n + 1, 256);
     vb[K_SCAN_A] = o.nb_scan;
     vb[K_SCAN_B] = o.nb_scan;
@@ -269,8 +274,8 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     sz[R_KEY] = sizeof(int) * n;
     sz[R_KV] = (o.npass > 1) ? sizeof(uint32_t) * 2 * 2 * (size_t)n : 0;
     sz[R_SKEY] = sizeof(uint32_t) * n;
-    sz[R_GHIST] = sizeof(uint32_t) * kMaxSortPass * kDigitBins;
     sz[R_TCNT] = sizeof(uint32_t) * (size_t)o.npass * o.ntiles_sort * kDigitBins;
+    sz[R_GTOT] = sizeof(uint32_t) * (size_t)o.npass * o.ngroups_sort * kDigitBins;
     sz[R_PERM] = sizeof(int) * n;
     sz[R_SY] = (size_t)o.tsz * n * d->s;
     sz[R_CARRY] = (size_t)o.tsz * 2 * o.nwaves * nn * o.nc;
@@ -349,9 +354,6 @@ Launch launch_of(int kind, const Derived& o, int vblocks)
     case K_ATTR_T: case K_ATTR_T_ALL:
         l.block = 1024;
         l.lds = o.tile_lds;
-        break;
-    case K_TSCAN0: case K_TSCAN1: case K_TSCAN2:
-        l.block = kScanWaves * 64;
         break;
     default:
         break;
@@ -506,8 +508,10 @@ static tsne_status plan_init(tsne_plan* pl, const tsne_desc* desc, const Derived
     h.key = reinterpret_cast<int*>(b + off[R_KEY]);
     h.kv = b + off[R_KV];
     h.skey = reinterpret_cast<unsigned*>(b + off[R_SKEY]);
-    h.ghist = reinterpret_cast<unsigned*>(b + off[R_GHIST]);
     h.tcnt = reinterpret_cast<unsigned*>(b + off[R_TCNT]);
+    h.gtot = reinterpret_cast<unsigned*>(b + off[R_GTOT]);
+    h.group_tiles = o.group_tiles;
+    h.ngroups_sort = o.ngroups_sort;
     h.npass = o.npass;
     h.ntiles_sort = o.ntiles_sort;
     h.perm = reinterpret_cast<int*>(b + off[R_PERM]);

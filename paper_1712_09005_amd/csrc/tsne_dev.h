@@ -23,7 +23,7 @@ constexpr int kWave = 64;
 constexpr int kKeyTile = 2048;     // points per block of the key kernel (256 threads x 8)
 constexpr int kSortTile = 2048;    // points per tile of a sort pass (256 threads x 8)
 constexpr int kScanDigits = 64;    // digits per block of the tile-offset scan (a lane each)
-constexpr int kScanWaves = 16;     // tile segments per block of that scan (a wave each)
+constexpr int kScanGroups = 16;    // at most this many groups of tiles per radix pass
 constexpr int kDigitBitsMax = 9;   // at most 512 digit values per pass
 constexpr int kDigitBins = 1 << kDigitBitsMax;
 constexpr int kMaxSortPass = 3;    // cell indices of up to 27 bits
@@ -129,10 +129,11 @@ struct Inst {
     void* kv;              // [2][n] (cell, point) pairs between radix passes (uint2)
     unsigned* skey;        // [n] cell of each sorted position
     int* perm;             // [n] sorted position -> point
-    unsigned* ghist;       // [kMaxSortPass][kDigitBins] digit counts over all points
     unsigned* tcnt;        // [npass][ntiles_sort][kDigitBins] digit counts of every tile,
                            // replaced by the tile's first output position per digit
+    unsigned* gtot;        // [npass][ngroups_sort][kDigitBins] digit counts of every group of tiles
     int npass, ntiles_sort;    // radix passes (from the cell capacity), sort tiles
+    int group_tiles, ngroups_sort;  // tiles per group of the offset scan (a multiple of 4), groups
     void* sY;              // [n][s] sorted positions
     void* carry;           // [2 * nwaves][1 + p^s * nc] spread carries
     void* W;               // [nc][n_cap][n_cap] (s = 2) or [nc][n_cap]
