@@ -22,6 +22,7 @@
 namespace tsne {
 
 constexpr int kMaxB = 4;   // butterflies per thread per stage (host-enforced)
+constexpr int kLd = 8;     // global loads a thread issues before it uses the first
 
 template <typename T>
 __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b)
@@ -226,14 +227,33 @@ __global__ __launch_bounds__(1024) void k_fft_rows(LaunchMap map)
             const T* W = static_cast<const T*>(I.W) + (int64_t)ch * n_cap * n_cap;
             const int* cs = I.cell_start;
             const int cya = ra / P, cyb = rb / P;
-            for (int g = threadIdx.x; g < M; g += blockDim.x) {
-                T a = (T)0, b = (T)0;
-                if (g < n) {
-                    const int cx = g / P;
-                    if (occupied(cs, cya * n_int + cx)) a = W[(int64_t)ra * n_cap + g];
-                    if (rb < ny && occupied(cs, cyb * n_int + cx)) b = W[(int64_t)rb * n_cap + g];
+            // kLd nodes per thread at a time: the cells' occupancy, then the
+            // grid values of occupied cells (unoccupied cells were not written)
+            const int nthr = blockDim.x;
+            for (int g0 = threadIdx.x; g0 < M; g0 += kLd * nthr) {
+                int oa[kLd], ob[kLd];
+#pragma unroll
+                for (int u = 0; u < kLd; ++u) {
+                    const int g = g0 + u * nthr;
+                    oa[u] = ob[u] = 0;
+                    if (g < n) {
+                        const int cx = g / P;
+                        oa[u] = occupied(cs, cya * n_int + cx);
+                        if (rb < ny) ob[u] = occupied(cs, cyb * n_int + cx);
+                    }
                 }
-                buf[lds_pad(g)] = {a, b};
+                T a[kLd], b[kLd];
+#pragma unroll
+                for (int u = 0; u < kLd; ++u) {
+                    const int g = g0 + u * nthr;
+                    a[u] = oa[u] ? W[(int64_t)ra * n_cap + g] : (T)0;
+                    b[u] = ob[u] ? W[(int64_t)rb * n_cap + g] : (T)0;
+                }
+#pragma unroll
+                for (int u = 0; u < kLd; ++u) {
+                    const int g = g0 + u * nthr;
+                    if (g < M) buf[lds_pad(g)] = {a[u], b[u]};
+                }
             }
             __syncthreads();
             block_fft<T>(buf, 1, I, G);
@@ -294,11 +314,23 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
         const int k00 = cg * Gc;
         const int tile = k00 >> (__ffs(tw_) - 1);
         const int64_t t0 = (int64_t)tile * n_cap * tw_ + (k00 - tile * tw_);
-        for (int idx = threadIdx.x; idx < (M << lgc); idx += blockDim.x) {
-            const int r = idx >> lgc, g = idx & (Gc - 1);   // consecutive threads: columns of a row
-            cplx<T> v = {(T)0, (T)0};
-            if (k00 + g < half && r < n) v = X[t0 + (int64_t)r * tw_ + g];
-            buf[g * PM + lds_pad(r)] = v;
+        // consecutive threads: columns of a row; kLd loads in flight per thread
+        const int nthr = blockDim.x, nel = M << lgc;
+        for (int i0 = threadIdx.x; i0 < nel; i0 += kLd * nthr) {
+            cplx<T> v[kLd];
+#pragma unroll
+            for (int u = 0; u < kLd; ++u) {
+                const int idx = i0 + u * nthr;
+                const int r = idx >> lgc, g = idx & (Gc - 1);
+                v[u] = {(T)0, (T)0};
+                if (idx < nel && k00 + g < half && r < n) v[u] = X[t0 + (int64_t)r * tw_ + g];
+            }
+#pragma unroll
+            for (int u = 0; u < kLd; ++u) {
+                const int idx = i0 + u * nthr;
+                const int r = idx >> lgc, g = idx & (Gc - 1);
+                if (idx < nel) buf[g * PM + lds_pad(r)] = v[u];
+            }
         }
         __syncthreads();
         block_fft<T>(buf, Gc, I, Gm, true);
@@ -311,22 +343,26 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
             const int k0 = k00 + g;
             const T* sp = static_cast<const T*>(I.spec) + (int64_t)kern * kslot + (int64_t)k0 * half_y;
             cplx<T>* col = buf + g * PM;
-            if (FORM == 2 && kern > 0) {
-                // times -i b, b odd in k1 for the kernel odd along dimension 1
-                for (int k1 = jt; k1 < M; k1 += tpc) {
+            // the spectrum's values kLd at a time, loaded before they are used
+            for (int kb = jt; kb < M; kb += kLd * tpc) {
+                T sv[kLd];
+#pragma unroll
+                for (int u = 0; u < kLd; ++u) {
+                    const int k1 = kb + u * tpc;
                     const bool up = k1 > M - k1;
-                    T sv = (k0 < half) ? sp[up ? M - k1 : k1] : (T)0;
-                    if (kern == 2 && up) sv = -sv;
-                    const int li = lds_pad(k1);
-                    const cplx<T> v = col[li];
-                    col[li] = {v.y * sv, v.x * sv};
+                    sv[u] = (k1 < M && k0 < half) ? sp[up ? M - k1 : k1] : (T)0;
+                    // times -i b, b odd in k1 for the kernel odd along dimension 1
+                    if (FORM == 2 && kern == 2 && up) sv[u] = -sv[u];
                 }
-            } else {
-                for (int k1 = jt; k1 < M; k1 += tpc) {
-                    const T sv = (k0 < half) ? sp[k1 <= M - k1 ? k1 : M - k1] : (T)0;
-                    const int li = lds_pad(k1);
-                    const cplx<T> v = col[li];
-                    col[li] = {v.x * sv, -v.y * sv};
+#pragma unroll
+                for (int u = 0; u < kLd; ++u) {
+                    const int k1 = kb + u * tpc;
+                    if (k1 < M) {
+                        const int li = lds_pad(k1);
+                        const cplx<T> v = col[li];
+                        if (FORM == 2 && kern > 0) col[li] = {v.y * sv[u], v.x * sv[u]};
+                        else col[li] = {v.x * sv[u], -v.y * sv[u]};
+                    }
                 }
             }
         }
@@ -368,16 +404,31 @@ __global__ __launch_bounds__(1024) void k_fft_irows(LaunchMap map)
             const cplx<T>* Xb = static_cast<const cplx<T>*>(I.Xc) + (int64_t)pb * I.ntiles * n_cap * tw_;
             const int mh = M / 2;
             const int ltw = __ffs(tw_) - 1;                // tile_w is a power of two
-            for (int k = threadIdx.x; k < M; k += blockDim.x) {
-                const bool up = k > mh;
-                const int kk = up ? M - k : k;
-                const int tile = kk >> ltw;
-                const int64_t off = (int64_t)tile * n_cap * tw_ + (kk & (tw_ - 1));
-                cplx<T> A = Xa[off + (int64_t)ra * tw_];
-                cplx<T> B = has_b ? Xb[off + (int64_t)rb * tw_] : cplx<T>{(T)0, (T)0};
-                if (up) { A = cconj(A); B = cconj(B); }
-                // Z = A + i B, stored conjugated (inverse by forward transform)
-                buf[lds_pad(k)] = {A.x - B.y, -(A.y + B.x)};
+            const int nthr = blockDim.x;
+            for (int k0 = threadIdx.x; k0 < M; k0 += kLd * nthr) {
+                cplx<T> A[kLd], B[kLd];
+#pragma unroll
+                for (int u = 0; u < kLd; ++u) {
+                    const int k = k0 + u * nthr;
+                    const int kk = (k > mh) ? M - k : k;
+                    const int tile = kk >> ltw;
+                    const int64_t off = (int64_t)tile * n_cap * tw_ + (kk & (tw_ - 1));
+                    A[u] = B[u] = cplx<T>{(T)0, (T)0};
+                    if (k < M) {
+                        A[u] = Xa[off + (int64_t)ra * tw_];
+                        if (has_b) B[u] = Xb[off + (int64_t)rb * tw_];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kLd; ++u) {
+                    const int k = k0 + u * nthr;
+                    if (k < M) {
+                        cplx<T> a = A[u], b = B[u];
+                        if (k > mh) { a = cconj(a); b = cconj(b); }
+                        // Z = A + i B, stored conjugated (inverse by forward transform)
+                        buf[lds_pad(k)] = {a.x - b.y, -(a.y + b.x)};
+                    }
+                }
             }
             __syncthreads();
             block_fft<T>(buf, 1, I, G);
@@ -410,23 +461,41 @@ __global__ __launch_bounds__(1024) void k_fft_1d(LaunchMap map)
         pot_of<1, FORM>(pot, ch, kern);
         const T* W = static_cast<const T*>(I.W) + (int64_t)ch * n_cap;
         const int* cs = I.cell_start;
-        for (int g = threadIdx.x; g < M; g += blockDim.x) {
-            T a = (T)0;
-            if (g < n && occupied(cs, g / P)) a = W[g];
-            buf[lds_pad(g)] = {a, (T)0};
+        const int nthr = blockDim.x;
+        for (int g0 = threadIdx.x; g0 < M; g0 += kLd * nthr) {
+            int oc[kLd];
+#pragma unroll
+            for (int u = 0; u < kLd; ++u) {
+                const int g = g0 + u * nthr;
+                oc[u] = (g < n) ? occupied(cs, g / P) : 0;
+            }
+            T a[kLd];
+#pragma unroll
+            for (int u = 0; u < kLd; ++u) a[u] = oc[u] ? W[g0 + u * nthr] : (T)0;
+#pragma unroll
+            for (int u = 0; u < kLd; ++u)
+                if (g0 + u * nthr < M) buf[lds_pad(g0 + u * nthr)] = {a[u], (T)0};
         }
         __syncthreads();
         block_fft<T>(buf, 1, I, G);
         const T* sp = static_cast<const T*>(I.spec) + (int64_t)kern * half;
-        for (int k = threadIdx.x; k < M; k += blockDim.x) {
-            const bool up = k > M - k;
-            const cplx<T> v = buf[lds_pad(k)];
-            if (FORM == 2 && kern > 0) {             // times -i b, b odd in k
-                const T sv = up ? -sp[M - k] : sp[k];
-                buf[lds_pad(k)] = {v.y * sv, v.x * sv};
-            } else {
-                const T sv = sp[up ? M - k : k];
-                buf[lds_pad(k)] = {v.x * sv, -v.y * sv};
+        for (int k0 = threadIdx.x; k0 < M; k0 += kLd * nthr) {
+            T sv[kLd];
+#pragma unroll
+            for (int u = 0; u < kLd; ++u) {
+                const int k = k0 + u * nthr;
+                const bool up = k > M - k;
+                sv[u] = (k < M) ? sp[up ? M - k : k] : (T)0;
+                if (FORM == 2 && kern > 0 && up) sv[u] = -sv[u];   // times -i b, b odd in k
+            }
+#pragma unroll
+            for (int u = 0; u < kLd; ++u) {
+                const int k = k0 + u * nthr;
+                if (k < M) {
+                    const cplx<T> v = buf[lds_pad(k)];
+                    if (FORM == 2 && kern > 0) buf[lds_pad(k)] = {v.y * sv[u], v.x * sv[u]};
+                    else buf[lds_pad(k)] = {v.x * sv[u], -v.y * sv[u]};
+                }
             }
         }
         __syncthreads();

@@ -252,9 +252,11 @@ __global__ __launch_bounds__(256) void k_sort(LaunchMap map)
         const int grp = tile / I.group_tiles, ng = I.ngroups_sort;
         const unsigned* gt = I.gtot + (int64_t)PASS * ng * kDigitBins;
         unsigned before[2] = {0u, 0u}, total[2] = {0u, 0u};
-        for (int g = 0; g < ng; ++g) {
-            const uint2 v = (2 * t < nbins) ? reinterpret_cast<const uint2*>(gt + (int64_t)g * kDigitBins)[t]
-                                            : make_uint2(0u, 0u);
+#pragma unroll
+        for (int g = 0; g < kScanGroups; ++g) {
+            const uint2 v = (g < ng && 2 * t < nbins)
+                                ? reinterpret_cast<const uint2*>(gt + (int64_t)g * kDigitBins)[t]
+                                : make_uint2(0u, 0u);
             if (g < grp) {
                 before[0] += v.x;
                 before[1] += v.y;
