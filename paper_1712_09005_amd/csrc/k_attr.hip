@@ -294,8 +294,16 @@ __global__ __launch_bounds__(256) void k_asum(LaunchMap map)
         const int64_t ns = I.n * S;
         if (k < ns) {
             const T* Fp = static_cast<const T*>(I.Fap);
+            // every slab's partial in flight at once, then summed in slab order
+            constexpr int kMaxSlabs = 8;
+            T q[kMaxSlabs];
+#pragma unroll
+            for (int sl = 0; sl < kMaxSlabs; ++sl)
+                if (sl < I.slabs) q[sl] = Fp[(int64_t)sl * ns + k];
             double a = 0.0;
-            for (int sl = 0; sl < I.slabs; ++sl) a += (double)Fp[(int64_t)sl * ns + k];
+#pragma unroll
+            for (int sl = 0; sl < kMaxSlabs; ++sl)
+                if (sl < I.slabs) a += (double)q[sl];
             static_cast<T*>(I.Fattr)[k] = (T)a;
         }
     }

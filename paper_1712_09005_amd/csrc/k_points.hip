@@ -362,19 +362,33 @@ __global__ __launch_bounds__(256) void k_spread(LaunchMap map)
         for (int k = 0; k < NN; ++k)
 #pragma unroll
             for (int q = 0; q < NC; ++q) acc[k][q] = (T)0;
+        int fi = 0, li = 0;                // the cell's first and one-past-last item
         if (valid) {
-            c = I.item_cell[t];
-            const int fi = I.item_start[c];
-            const int b = I.cell_start[c] + (t - fi) * I.kpts;
+            const int2 it = I.item_info[t];
+            c = it.x;
+            const int b = it.y;
+            fi = I.item_start[c];
+            li = I.item_start[c + 1];
             const int e = min(b + I.kpts, I.cell_start[c + 1]);
             const T* sY = static_cast<const T*>(I.sY);
             const double w = G.w, qs = G.qscale;
             const double o0 = G.origin[0], o1 = G.origin[S - 1];
             const double c0 = G.centre[0], c1 = G.centre[S - 1];
-            for (int pos = b; pos < e; ++pos) {
+            // positions loaded PF at a time, before the first is used (the
+            // first batch before the item's end is known: clamped to the array)
+            constexpr int PF = 4;
+            const int last = (int)I.n - 1;
+            int p0 = b;
+            do {
+              Pt<T, S> ypf[PF];
+#pragma unroll
+              for (int u = 0; u < PF; ++u) ypf[u] = Pt<T, S>::load(sY, min(p0 + u, last));
+#pragma unroll
+              for (int u = 0; u < PF; ++u) {
+                if (p0 + u >= e) break;
                 T q[NC];
                 T tx, ty = (T)0;
-                const Pt<T, S> yp = Pt<T, S>::load(sY, pos);
+                const Pt<T, S> yp = ypf[u];
                 const T yx = yp.v[0];
                 locate<T>(yx, o0, w, n_int, tx);
                 // centred, power-of-two scaled charges, rounded once from double
@@ -408,7 +422,9 @@ __global__ __launch_bounds__(256) void k_spread(LaunchMap map)
 #pragma unroll
                         for (int qq = 0; qq < NC; ++qq) acc[m0][qq] += Lx[m0] * q[qq];
                 }
-            }
+              }
+              p0 += PF;
+            } while (p0 < e);
         }
         // ---- segmented inclusive scan over the lanes of the wave, by cell
         const int cprev = __shfl_up(c, 1, 64);
@@ -430,7 +446,7 @@ __global__ __launch_bounds__(256) void k_spread(LaunchMap map)
         const bool run_end = (lane == 63) || ((hm >> (lane + 1)) & 1ull);
         if (valid && run_end) {
             const int t_first = t - (lane - run_start);
-            const bool complete = (t_first == I.item_start[c]) && (t == I.item_start[c + 1] - 1);
+            const bool complete = (t_first == fi) && (t == li - 1);
             if (complete) {
                 T* W = static_cast<T*>(I.W);
                 const int cx = c % n_int;
@@ -566,86 +582,131 @@ __global__ __launch_bounds__(256) void k_spread_fix(LaunchMap map)
 
 // phi_k(y_i) = sum_m L_m(y_i) V_k[node m of i's cell], then the Appendix
 // assembly: h1 (the K1 sum), numerators y'(d) h4 - h_{1+d} (form V: the
-// numerators are the odd-kernel potentials themselves).  One thread per
-// sorted position (neighbouring threads share their cell's nodes); results go
-// to the point's own index.  Z = sum_i h1_i - N, reduced in double.
+// numerators are the odd-kernel potentials themselves).  One thread per item
+// (up to kpts consecutive sorted points of one cell, the spreading kernel's
+// items): the cell's NP p^s node potentials are loaded once (held in
+// registers when they fit, FP32 with at most 100 values) and every point of
+// the item is interpolated from them; results go to the point's own index.
+// (Several threads per item, each loading the potentials, took longer: the
+// loads, not the latency, then dominate.)  Z = sum_i h1_i - N, reduced in
+// double: per thread over its item's points in order, then per block, then
+// over the blocks in k_zsum.
 template <typename T, int S, int P, int FORM>
 __global__ __launch_bounds__(256) void k_gather(LaunchMap map)
 {
     constexpr int NP = Shape<S, FORM>::NP;
+    constexpr int NN = (S == 2) ? P * P : P;
+    constexpr bool HOLD = (sizeof(T) == 4 && NP * NN <= 100) || NP * NN <= 32;
+    constexpr int PF = 8;                                // positions loaded at once
     __shared__ double sh[8];
     VB_BEGIN(map, K_GATHER)
     if (live(I)) {
         const Geom& G = *I.geom;
-        const int64_t pos = (int64_t)lb * 256 + threadIdx.x;
+        const int ncell = G.n_cells;
+        const int total = I.item_start[ncell];
+        const int t = lb * 256 + (int)threadIdx.x;
         double h1d = 0.0;
-        if (pos < I.n) {
+        if (t < total) {
             const int n_int = G.n_int, n_cap = I.n_cap;
+            const int2 it = I.item_info[t];
+            const int c = it.x, b = it.y;
+            const int e = min(b + I.kpts, I.cell_start[c + 1]);
+            const int cx = c % n_int, cy = (S == 2) ? c / n_int : 0;
             const T* sY = static_cast<const T*>(I.sY);
             const T* V = static_cast<const T*>(I.V);
+            const int64_t plane = (int64_t)n_cap * (S == 2 ? n_cap : 1);
+            // node (m1, m0) of the cell in potential k
+            auto vidx = [&](int k, int m) -> int64_t {
+                const int m1 = (S == 2) ? m / P : 0, m0 = m - m1 * P;
+                return (int64_t)k * plane + (int64_t)(cy * P + m1) * (S == 2 ? n_cap : 0) + cx * P + m0;
+            };
+            T vh[HOLD ? NP : 1][HOLD ? NN : 1];
+            if constexpr (HOLD) {
+#pragma unroll
+                for (int k = 0; k < NP; ++k)
+#pragma unroll
+                    for (int m = 0; m < NN; ++m) vh[k][m] = V[vidx(k, m)];
+            }
             const double w = G.w, qs = G.qscale;
-            T yv[2], tl[2];
-            int cl[2] = {0, 0};
-            const Pt<T, S> yp = Pt<T, S>::load(sY, pos);
-#pragma unroll
-            for (int d = 0; d < S; ++d) {
-                yv[d] = yp.v[d];
-                cl[d] = locate<T>(yv[d], G.origin[d], w, d == 0 ? n_int : G.n_int_y, tl[d]);
-            }
-            T Lx[P], Ly[P];
-            lagrange<T, P>(tl[0], Lx);
-            if (S == 2) lagrange<T, P>(tl[1], Ly);
-            T phi[NP];
-#pragma unroll
-            for (int k = 0; k < NP; ++k) {
-                T a = (T)0;
-                const T* Vk = V + (int64_t)k * n_cap * (S == 2 ? n_cap : 1);
-                if (S == 2) {
-#pragma unroll
-                    for (int m1 = 0; m1 < P; ++m1) {
-                        const T* row = Vk + (int64_t)(cl[1] * P + m1) * n_cap + cl[0] * P;
-                        T r = (T)0;
-#pragma unroll
-                        for (int m0 = 0; m0 < P; ++m0) r += Lx[m0] * row[m0];
-                        a += Ly[m1] * r;
-                    }
-                } else {
-                    const T* row = Vk + cl[0] * P;
-#pragma unroll
-                    for (int m0 = 0; m0 < P; ++m0) a += Lx[m0] * row[m0];
-                }
-                phi[k] = a;
-            }
-            // potentials: phi[1] = K2*1, phi[2+d] = K2*(y'(d) qs); phi[0] = K1*1 (A)
-            // or K2*(|y'|^2 qs^2) (B); form V: phi[0] = K1*1, phi[1+d] = (z_d K2)*1
-            // assembly in double: the numerator y'(d) h4 - h_{1+d} cancels
-            double yc[2];
-            double r2c = 0.0;
-#pragma unroll
-            for (int d = 0; d < S; ++d) {
-                yc[d] = (double)yv[d] - G.centre[d];
-                r2c += yc[d] * yc[d];
-            }
             const double inv_qs = 1.0 / qs;
-            double h1;
-            if (FORM == 0 || FORM == 2) {
-                h1 = (double)phi[0];
-            } else {
-                double dot = 0.0;
+            // positions PF at a time; the first batch is requested before the
+            // item's end is known (indices clamped to the array)
+            const int last = (int)I.n - 1;
+            int p0 = b;
+            do {
+                Pt<T, S> yp[PF];
+                int ip[PF];
 #pragma unroll
-                for (int d = 0; d < S; ++d) dot += yc[d] * (double)phi[(2 + d) % NP];
-                h1 = (1.0 + r2c) * (double)phi[1] - 2.0 * dot * inv_qs +
-                     (double)phi[0] * inv_qs * inv_qs;
-            }
-            const int i = I.perm[pos];
-            Pt<T, S> rv;
+                for (int u = 0; u < PF; ++u) {
+                    const int pos = min(p0 + u, last);
+                    yp[u] = Pt<T, S>::load(sY, pos);
+                    ip[u] = I.perm[pos];
+                }
 #pragma unroll
-            for (int d = 0; d < S; ++d)
-                rv.v[d] = (FORM == 2) ? phi[1 + d]
-                                      : (T)(yc[d] * (double)phi[1] - (double)phi[(2 + d) % NP] * inv_qs);
-            rv.store(static_cast<T*>(I.R), i);
-            if (I.h1keep) I.h1keep[i] = h1;
-            h1d = h1;
+                for (int u = 0; u < PF; ++u) {
+                    if (p0 + u >= e) break;
+                    T yv[2], tl[2];
+#pragma unroll
+                    for (int d = 0; d < S; ++d) {
+                        yv[d] = yp[u].v[d];
+                        locate<T>(yv[d], G.origin[d], w, d == 0 ? n_int : G.n_int_y, tl[d]);
+                    }
+                    T Lx[P], Ly[P];
+                    lagrange<T, P>(tl[0], Lx);
+                    if (S == 2) lagrange<T, P>(tl[1], Ly);
+                    T phi[NP];
+#pragma unroll
+                    for (int k = 0; k < NP; ++k) {
+                        T a = (T)0;
+                        if (S == 2) {
+#pragma unroll
+                            for (int m1 = 0; m1 < P; ++m1) {
+                                T r = (T)0;
+#pragma unroll
+                                for (int m0 = 0; m0 < P; ++m0)
+                                    r += Lx[m0] * (HOLD ? vh[HOLD ? k : 0][HOLD ? m1 * P + m0 : 0]
+                                                        : V[vidx(k, m1 * P + m0)]);
+                                a += Ly[m1] * r;
+                            }
+                        } else {
+#pragma unroll
+                            for (int m0 = 0; m0 < P; ++m0)
+                                a += Lx[m0] * (HOLD ? vh[HOLD ? k : 0][HOLD ? m0 : 0] : V[vidx(k, m0)]);
+                        }
+                        phi[k] = a;
+                    }
+                    // potentials: phi[1] = K2*1, phi[2+d] = K2*(y'(d) qs); phi[0] = K1*1 (A)
+                    // or K2*(|y'|^2 qs^2) (B); form V: phi[0] = K1*1, phi[1+d] = (z_d K2)*1
+                    // assembly in double: the numerator y'(d) h4 - h_{1+d} cancels
+                    double yc[2];
+                    double r2c = 0.0;
+#pragma unroll
+                    for (int d = 0; d < S; ++d) {
+                        yc[d] = (double)yv[d] - G.centre[d];
+                        r2c += yc[d] * yc[d];
+                    }
+                    double h1;
+                    if (FORM == 0 || FORM == 2) {
+                        h1 = (double)phi[0];
+                    } else {
+                        double dot = 0.0;
+#pragma unroll
+                        for (int d = 0; d < S; ++d) dot += yc[d] * (double)phi[(2 + d) % NP];
+                        h1 = (1.0 + r2c) * (double)phi[1] - 2.0 * dot * inv_qs +
+                             (double)phi[0] * inv_qs * inv_qs;
+                    }
+                    const int i = ip[u];
+                    Pt<T, S> rv;
+#pragma unroll
+                    for (int d = 0; d < S; ++d)
+                        rv.v[d] = (FORM == 2) ? phi[1 + d]
+                                              : (T)(yc[d] * (double)phi[1] - (double)phi[(2 + d) % NP] * inv_qs);
+                    rv.store(static_cast<T*>(I.R), i);
+                    if (I.h1keep) I.h1keep[i] = h1;
+                    h1d += h1;
+                }
+                p0 += PF;
+            } while (p0 < e);
         }
         const double bs = block_sum_d(h1d, sh);
         if (threadIdx.x == 0) I.z_part[lb] = bs;
@@ -736,14 +797,21 @@ __global__ __launch_bounds__(256) void k_update(LaunchMap map)
             if (I.slabs == 1) {
                 fa = Pt<T, S>::load(Fa, i);
             } else {
+                // every slab's partial in flight at once, then summed in slab order
+                constexpr int kMaxSlabs = 8;
+                Pt<T, S> q[kMaxSlabs];
+#pragma unroll
+                for (int sl = 0; sl < kMaxSlabs; ++sl)
+                    if (sl < I.slabs) q[sl] = Pt<T, S>::load(Fp + (int64_t)sl * ns, i);
                 double a[S];
 #pragma unroll
                 for (int d = 0; d < S; ++d) a[d] = 0.0;
-                for (int sl = 0; sl < I.slabs; ++sl) {
-                    const Pt<T, S> q = Pt<T, S>::load(Fp + (int64_t)sl * ns, i);
 #pragma unroll
-                    for (int d = 0; d < S; ++d) a[d] += (double)q.v[d];
-                }
+                for (int sl = 0; sl < kMaxSlabs; ++sl)
+                    if (sl < I.slabs) {
+#pragma unroll
+                        for (int d = 0; d < S; ++d) a[d] += (double)q[sl].v[d];
+                    }
 #pragma unroll
                 for (int d = 0; d < S; ++d) fa.v[d] = (T)a[d];
             }
