@@ -198,17 +198,24 @@ tsne_status tsne_bind_P(tsne_plan* plan, const int64_t* row_ptr,
  * writes F_rep [n, s] and *Z (device double). */
 tsne_status tsne_repulsive(tsne_plan* plan, const void* Y, void* F_rep, double* Z);
 
-/* Attraction over the bound P: writes F_attr [n, s]. */
+/* Attraction over the bound P (Section 3: the attractive term of the
+ * gradient is a sum over the non-zeros of P only, computed directly):
+ * F_attr,i = sum_j p_ij (y_i - y_j) / (1 + |y_i - y_j|^2).  Y [n, s] and
+ * F_attr [n, s] device, in the plan's dtype; TSNE_E_STATE without a bound P. */
 tsne_status tsne_attractive(tsne_plan* plan, const void* Y, void* F_attr);
 
-/* One full iteration at absolute iteration index iter (>= 0): repulsion,
- * attraction and the descent step of tsne_sched, updating Y, uY and gains in
- * place.  Sets the device iteration counter to iter + 1. */
+/* One full iteration at absolute iteration index iter (>= 0): the gradient
+ * of Section 1.1 split as in Sections 2 and 3, 4 (alpha F_attr - F_rep / Z)
+ * with the exaggeration alpha of tsne_sched, then the descent step of
+ * tsne_sched (gains, momentum), updating Y, uY and gains in place.  Sets the
+ * device iteration counter to iter + 1. */
 tsne_status tsne_step(tsne_plan* plan, void* Y, void* uY, void* gains,
                       const tsne_sched* sched, int32_t iter);
 
-/* n_iter iterations starting at absolute iteration iter0 (the schedule is
- * indexed by absolute iteration, so a run can be split and resumed).  The
+/* n_iter iterations (each as tsne_step: Section 1.1's gradient, its
+ * repulsion by Sections 2 and 2.4, its attraction by Section 3) starting at
+ * absolute iteration iter0 (the schedule is indexed by absolute iteration,
+ * so a run can be split and resumed).  The
  * iteration is captured once in a HIP graph (device-side iteration counter and
  * schedule) and replayed n_iter times. */
 tsne_status tsne_run(tsne_plan* plan, void* Y, void* uY, void* gains,
