@@ -25,8 +25,9 @@
  *   - Y is [n, s] row-major: y_i(d) = Y[i*s + d].  Arrays of per-point
  *     vectors (F_rep, F_attr, uY, gains) share that layout.  The element type
  *     is float (TSNE_F32) or double (TSNE_F64) as set in the descriptor.
- *     Each such array is aligned to a whole point (s times the element size),
- *     since kernels move a point's coordinates as one vector; every entry
+ *     Each such array is aligned to a whole point (s times the element size;
+ *     for s = 3 one element), since kernels move a point's coordinates as one
+ *     vector; every entry
  *     point that takes Y (and tsne_step, tsne_run, tsne_batch_admit for uY
  *     and gains) returns TSNE_E_ARG for one that is not.
  *   - F_rep follows the sign of the attractive/repulsive split of Section 1.1:
@@ -96,7 +97,12 @@ typedef enum { TSNE_FORM_A = 0, TSNE_FORM_B = 1, TSNE_FORM_V = 2 } tsne_form;
 
 typedef struct {
     int64_t n;               /* number of points, >= 2 (< 2^31) */
-    int32_t s;               /* embedding dimension: 1 or 2 */
+    int32_t s;               /* embedding dimension: 1, 2 or 3.  s = 3 (Section 2's
+                                sums for any s, tensor-product nodes on a cube): forms
+                                A and B, the square box, the CSR attraction in one
+                                slab, circulant lengths up to 400 per axis
+                                (2 max_intervals p <= 400); TSNE_E_UNSUPPORTED
+                                otherwise */
     int32_t dtype;           /* tsne_dtype of Y, forces, uY, gains, P values */
     int32_t p;               /* Lagrange nodes per interval, 2..6 (Section 2.3) */
     int32_t policy;          /* tsne_grid_policy */
@@ -163,6 +169,7 @@ typedef struct {
     int32_t n_int_y;         /* second axis (s = 2): N_int, nodes and FFT length; */
     int32_t n_nodes_y;       /* equal to the first axis' for the square box */
     int32_t fft_len_y;
+    double origin_z;         /* s = 3: box origin along the third axis */
 } tsne_stats;
 
 typedef struct tsne_plan tsne_plan;

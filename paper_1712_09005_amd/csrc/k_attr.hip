@@ -4,7 +4,7 @@
 //
 // Every kernel walks the virtual blocks of its kind over all instances of the
 // launch (VB_BEGIN/VB_END), so one launch serves a single plan or a batch.
-#include "launch.h"
+#include "k_common.h"
 
 namespace tsne {
 
@@ -160,6 +160,86 @@ __global__ __launch_bounds__(256) void k_attr(LaunchMap map)
     if constexpr (KL) {
         // a single-instance launch: the block's partials (klout is this
         // instance's array once the block has run a virtual block)
+        kla = block_sum_d(kla, klsh);
+        klp = block_sum_d(klp, klsh);
+        if (threadIdx.x == 0 && klout) {
+            klout[2 * blockIdx.x] = kla;
+            klout[2 * blockIdx.x + 1] = klp;
+        }
+    }
+}
+
+// The attraction and the divergence terms for s = 3 over CSR rows (Section 3;
+// Section 1.1 for the divergence): LPR lanes per row, each taking U
+// non-zeros per round with all their loads issued first (column and value
+// from the bound CSR, the neighbours' three coordinates); the row's lanes are
+// reduced in double.  One slab (the whole row).
+template <typename T, int LPR, int U, bool GATED, bool KL = false>
+__global__ __launch_bounds__(256) void k_attr3(LaunchMap map)
+{
+    constexpr int RPB = 256 / LPR;
+    __shared__ double klsh[8];
+    double kla = 0.0, klp = 0.0;
+    double* klout = nullptr;
+    VB_BEGIN_IF(map, GATED ? K_ATTR : K_ATTR_ALL, (!GATED || live(I)))
+    {
+        if (KL) klout = I.kl_part;
+        const int64_t n = I.n;
+        const int i = lb * RPB + (int)threadIdx.x / LPR;
+        const int sub = (int)threadIdx.x % LPR;
+        T a[3] = {(T)0, (T)0, (T)0};
+        const T* Y = static_cast<const T*>(I.Yin);
+        if (i < n) {
+            const T* val = static_cast<const T*>(I.val);
+            const int32_t* col = I.col;
+            const Pt<T, 3> yi = Pt<T, 3>::load(Y, i);
+            const int64_t b = I.row_ptr[i], e = I.row_ptr[i + 1];
+            for (int64_t k0 = b + sub; k0 < e; k0 += (int64_t)LPR * U) {
+                int jj[U];
+                T pp[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t k = k0 + (int64_t)u * LPR;
+                    const bool ok = k < e;
+                    jj[u] = ok ? col[k] : i;
+                    pp[u] = ok ? val[k] : (T)0;
+                }
+                Pt<T, 3> yj[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) yj[u] = Pt<T, 3>::load(Y, jj[u]);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    T d[3];
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) d[q] = yi.v[q] - yj[u].v[q];
+                    const T qv = (T)1 + d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                    if constexpr (KL) {
+                        if (pp[u] > (T)0) {
+                            kla += (double)pp[u] * (double)log(pp[u] * qv);
+                            klp += (double)pp[u];
+                        }
+                    } else {
+                        const T wgt = pp[u] * recip(qv);
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) a[q] += wgt * d[q];
+                    }
+                }
+            }
+        }
+        if constexpr (KL) continue;
+        double f[3] = {(double)a[0], (double)a[1], (double)a[2]};
+#pragma unroll
+        for (int o = LPR / 2; o > 0; o >>= 1)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) f[q] += __shfl_xor(f[q], o, 64);
+        if (i < n && sub == 0) {
+            T* F = static_cast<T*>(I.Fattr);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) F[(int64_t)i * 3 + q] = (T)f[q];
+        }
+    }
+    VB_END
+    if constexpr (KL) {
         kla = block_sum_d(kla, klsh);
         klp = block_sum_d(klp, klsh);
         if (threadIdx.x == 0 && klout) {
@@ -448,9 +528,45 @@ static hipError_t launch_attr(int kind, const Cfg& c, const LaunchMap& map, cons
     return hipGetLastError();
 }
 
+// s = 3: the CSR rows at the plan's lanes per row, one slab
+template <typename T>
+static hipError_t launch_attr3(int kind, const Cfg& c, const LaunchMap& map, const Launch& l,
+                               hipStream_t st)
+{
+    dim3 g(l.grid), b(l.block);
+    switch (kind) {
+    case K_ATTR:
+        if (c.lpr == 4) hipLaunchKernelGGL((k_attr3<T, 4, 8, true>), g, b, 0, st, map);
+        else if (c.lpr == 8) hipLaunchKernelGGL((k_attr3<T, 8, 4, true>), g, b, 0, st, map);
+        else if (c.lpr == 16) hipLaunchKernelGGL((k_attr3<T, 16, 3, true>), g, b, 0, st, map);
+        else if (c.lpr == 32) hipLaunchKernelGGL((k_attr3<T, 32, 3, true>), g, b, 0, st, map);
+        else hipLaunchKernelGGL((k_attr3<T, 64, 2, true>), g, b, 0, st, map);
+        break;
+    case K_ATTR_ALL:
+        if (c.lpr == 4) hipLaunchKernelGGL((k_attr3<T, 4, 8, false>), g, b, 0, st, map);
+        else if (c.lpr == 8) hipLaunchKernelGGL((k_attr3<T, 8, 4, false>), g, b, 0, st, map);
+        else if (c.lpr == 16) hipLaunchKernelGGL((k_attr3<T, 16, 3, false>), g, b, 0, st, map);
+        else if (c.lpr == 32) hipLaunchKernelGGL((k_attr3<T, 32, 3, false>), g, b, 0, st, map);
+        else hipLaunchKernelGGL((k_attr3<T, 64, 2, false>), g, b, 0, st, map);
+        break;
+    case K_KL_ATTR:
+        if (c.lpr == 4) hipLaunchKernelGGL((k_attr3<T, 4, 8, true, true>), g, b, 0, st, map);
+        else if (c.lpr == 8) hipLaunchKernelGGL((k_attr3<T, 8, 4, true, true>), g, b, 0, st, map);
+        else if (c.lpr == 16) hipLaunchKernelGGL((k_attr3<T, 16, 3, true, true>), g, b, 0, st, map);
+        else if (c.lpr == 32) hipLaunchKernelGGL((k_attr3<T, 32, 3, true, true>), g, b, 0, st, map);
+        else hipLaunchKernelGGL((k_attr3<T, 64, 2, true, true>), g, b, 0, st, map);
+        break;
+    case K_KLSUM: hipLaunchKernelGGL(k_klsum, g, b, 0, st, map); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_attr_kind(int kind, const Cfg& c, const LaunchMap& map, const Launch& l,
                             hipStream_t st)
 {
+    if (c.s == 3) return c.dtype == 0 ? launch_attr3<float>(kind, c, map, l, st)
+                                      : launch_attr3<double>(kind, c, map, l, st);
     if (c.dtype == 0)
         return c.s == 1 ? launch_attr<float, 1>(kind, c, map, l, st) : launch_attr<float, 2>(kind, c, map, l, st);
     return c.s == 1 ? launch_attr<double, 1>(kind, c, map, l, st) : launch_attr<double, 2>(kind, c, map, l, st);

@@ -73,15 +73,53 @@ template <typename T> struct Pt<T, 2> {
     }
 };
 
-// Cell of a point: x interval + n_int * y interval (s = 2), as the binning
-// and every later kernel see it.
+// Cell of a point: x interval + n_int * y interval (s >= 2) + n_int n_int_y
+// * z interval (s = 3), as the binning and every later kernel see it.
 template <typename T, int S>
 __device__ __forceinline__ int cell_of(const Pt<T, S>& y, const Geom& G)
 {
     T t;
     int key = locate<T>(y.v[0], G.origin[0], G.w, G.n_int, t);
-    if (S == 2) key += G.n_int * locate<T>(y.v[S - 1], G.origin[1], G.w, G.n_int_y, t);
+    if (S >= 2) key += G.n_int * locate<T>(y.v[1], G.origin[1], G.w, G.n_int_y, t);
+    if (S == 3) key += G.n_int * G.n_int_y * locate<T>(y.v[S - 1], G.origin[S - 1], G.w, G.n_int, t);
     return key;
 }
+
+// 1 / prod_{k != m} (m - k), the denominator of the Lagrange basis on nodes
+// m + 1/2 (in units of the node spacing).
+__host__ __device__ constexpr double lag_inv_denom(int P, int m)
+{
+    double d = 1.0;
+    for (int k = 0; k < P; ++k)
+        if (k != m) d *= (double)(m - k);
+    return 1.0 / d;
+}
+
+// Lagrange basis of Section 2.1 on the p equispaced nodes (m + 1/2)/p of the
+// unit interval, evaluated at t in [0, 1] (eq. (equinodes) for the nodes).
+template <typename T, int P>
+__device__ __forceinline__ void lagrange(T t, T (&L)[P])
+{
+    const T sv = t * (T)P;
+    T a[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) a[k] = sv - ((T)k + (T)0.5);
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+        T prod = (T)lag_inv_denom(P, m);
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+            if (k != m) prod *= a[k];
+        L[m] = prod;
+    }
+}
+
+// Charges and potentials per form: A {1, y'(d)} -> K1*1, K2*1, K2*y'(d);
+// B adds |y'|^2 and takes K2*|y'|^2 in place of K1*1; V (vector kernels)
+// has the one charge 1 -> K1*1 and (z_d K2)*1 for each dimension d.
+template <int S, int FORM> struct Shape {
+    static constexpr int NC = (FORM == 0) ? S + 1 : (FORM == 1) ? S + 2 : 1;
+    static constexpr int NP = (FORM == 2) ? S + 1 : S + 2;
+};
 
 }  // namespace tsne

@@ -163,14 +163,10 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int M, int PM, int G, in
 // being those of this iteration's first axis (Geom), or of its second axis
 // with yaxis set.
 template <typename T>
-__device__ __forceinline__ void block_fft(cplx<T>* buf, int G, const Inst& I, const Geom& Gm,
-                                          bool yaxis = false)
+__device__ __forceinline__ void block_fft_tw(cplx<T>* buf, int G, int M, int nst, const int* radix,
+                                             const int* tw_off, const cplx<T>* tw)
 {
-    const cplx<T>* tw = static_cast<const cplx<T>*>((yaxis && Gm.My != Gm.M) ? I.twy : I.tw);
-    const int M = yaxis ? Gm.My : Gm.M, PM = lds_stride(M);
-    const int nst = yaxis ? Gm.nstages_y : Gm.nstages;
-    const int* radix = yaxis ? Gm.radix_y : Gm.radix;
-    const int* tw_off = yaxis ? Gm.tw_off_y : Gm.tw_off;
+    const int PM = lds_stride(M);
     int Ns = 1;
     for (int s = 0; s < nst; ++s) {
         const int R = radix[s];
@@ -183,6 +179,15 @@ __device__ __forceinline__ void block_fft(cplx<T>* buf, int G, const Inst& I, co
         }
         Ns *= R;
     }
+}
+
+template <typename T>
+__device__ __forceinline__ void block_fft(cplx<T>* buf, int G, const Inst& I, const Geom& Gm,
+                                          bool yaxis = false)
+{
+    const cplx<T>* tw = static_cast<const cplx<T>*>((yaxis && Gm.My != Gm.M) ? I.twy : I.tw);
+    if (yaxis) block_fft_tw<T>(buf, G, Gm.My, Gm.nstages_y, Gm.radix_y, Gm.tw_off_y, tw);
+    else block_fft_tw<T>(buf, G, Gm.M, Gm.nstages, Gm.radix, Gm.tw_off, tw);
 }
 
 __device__ __forceinline__ bool okay(const Inst& I) { return live(I); }
@@ -782,6 +787,224 @@ __global__ __launch_bounds__(256) void k_spec2(LaunchMap map)
 
 // ---------------------------------------------------------------- dispatch
 
+// ---------------------------------------------------------------- 3-D convolution (s = 3)
+
+// Step 2 for s = 3 (Section 2, the s + 2 sums for any s; Section 2.4's
+// circulant embedding along each axis): the M^3 circulant product by three
+// passes of complex transforms over a complex grid per charge, the kernel
+// spectrum, and three passes back, each pass over kSeq3 sequences per block
+// (consecutive x, so a block's loads along y and z read kSeq3 consecutive
+// elements).  Grids are [grid][z][y][x] with this iteration's M per axis.
+// The inverse passes are forward transforms of the conjugate (the product's
+// conjugate is stored after the z pass); the real part of the last pass is the
+// potential, the spectrum being stored pre-scaled by 1/M^3.
+//   F3_X   charges:    rows (z, y < n) of W (x < n, rest zero) -> Xg rows
+//   F3_Y   charges:    y sequences, all of them (y >= n and z >= n read as
+//                      zero, so the z pass finds the zero padding in place)
+//   F3_Z   potentials: z sequences of the charge's Xg, times the kernel
+//                      spectrum, conjugated, transformed again; z < n kept in Xp
+//   F3_IY  potentials: y sequences of Xp for z < n; y < n kept
+//   F3_IX  potentials: x rows of Xp for z, y < n; the real part of x < n to V
+//   S3_X/Y/Z          the same plain passes over the FP64 kernel grids
+enum { F3_X = 0, F3_Y, F3_Z, F3_IY, F3_IX, S3_X, S3_Y, S3_Z };
+
+constexpr int kSeq3 = 16;           // sequences per block of a 3-D pass
+
+template <int MODE> struct F3Kind;
+template <> struct F3Kind<F3_X> { static constexpr int K = K_F3_X, AXIS = 0; };
+template <> struct F3Kind<F3_Y> { static constexpr int K = K_F3_Y, AXIS = 1; };
+template <> struct F3Kind<F3_Z> { static constexpr int K = K_F3_Z, AXIS = 2; };
+template <> struct F3Kind<F3_IY> { static constexpr int K = K_F3_IY, AXIS = 1; };
+template <> struct F3Kind<F3_IX> { static constexpr int K = K_F3_IX, AXIS = 0; };
+template <> struct F3Kind<S3_X> { static constexpr int K = K_S3_X, AXIS = 0; };
+template <> struct F3Kind<S3_Y> { static constexpr int K = K_S3_Y, AXIS = 1; };
+template <> struct F3Kind<S3_Z> { static constexpr int K = K_S3_Z, AXIS = 2; };
+
+// Kernel value of table kern (0: K1, 1: K2) at squared distance r2.
+__device__ __forceinline__ double kern3(int kern, double r2)
+{
+    const double a = 1.0 / (1.0 + r2);
+    return kern == 0 ? a : a * a;
+}
+
+// Signed lag of circulant index j: j for j <= M/2, j - M above.
+__device__ __forceinline__ int lag3(int j, int M) { return (2 * j <= M) ? j : j - M; }
+
+// One pass of the 3-D convolution (T: the element type of the pass).
+template <typename T, int FORM, int MODE>
+__global__ __launch_bounds__(kSeq3 * 32) void k_f3(LaunchMap map)
+{
+    constexpr int AXIS = F3Kind<MODE>::AXIS;
+    constexpr bool SPEC = MODE >= S3_X;
+    extern __shared__ __align__(16) char smem[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
+    VB_BEGIN_IF_SKIP(map, F3Kind<MODE>::K, (SPEC ? spec_needed(I) : okay(I)))
+    {
+        const Geom& G = *I.geom;
+        const int M = G.M, n = G.n, n_cap = I.n_cap, PM = lds_stride(M);
+        const int64_t M2 = (int64_t)M * M, M3 = M2 * M;
+        const int nthr = blockDim.x;
+        const int ngrid = SPEC ? 2 : (MODE == F3_X || MODE == F3_Y) ? I.nc : I.np;
+        const int bpg = (int)(M2 / kSeq3);                 // blocks per grid (16 divides M^2)
+        const int g = lb / bpg, j0 = (lb - g * bpg) * kSeq3;
+        if (g < ngrid) {
+            int ch = g, kern = 0;
+            if (MODE == F3_Z) {
+                // potential g: its charge and kernel (forms A and B)
+                if (g == 0) { ch = (FORM == 0) ? 0 : 4; kern = (FORM == 0) ? 0 : 1; }
+                else if (g == 1) { ch = 0; kern = 1; }
+                else { ch = g - 1; kern = 1; }
+            }
+            // sequence j (0 <= j < M^2) of the pass: its two fixed indices
+            // (a, b) = (z, y) for x rows, (z, x) for y, (y, x) for z; base
+            // offset and element stride in the grid
+            auto seq = [&](int j, int& a, int& b, int64_t& base, int64_t& stride) {
+                a = j / M;
+                b = j - a * M;
+                if (AXIS == 0) { base = (int64_t)a * M2 + (int64_t)b * M; stride = 1; }
+                else if (AXIS == 1) { base = (int64_t)a * M2 + b; stride = M; }
+                else { base = (int64_t)a * M + b; stride = M2; }
+            };
+            // is sequence j wanted at all / read as all zero
+            auto wanted = [&](int a, int b) -> bool {
+                if (MODE == F3_X || MODE == F3_IX) return a < n && b < n;
+                if (MODE == F3_IY) return a < n;
+                return true;
+            };
+            bool any = false;
+            for (int q = 0; q < kSeq3; ++q) {
+                int a, b;
+                int64_t base, stride;
+                seq(j0 + q, a, b, base, stride);
+                any = any || wanted(a, b);
+            }
+            if (any) {
+                typedef cplx<T> C;
+                const C* src;
+                C* dst;
+                if (SPEC) {
+                    src = static_cast<const C*>(I.specd) + (int64_t)g * M3;
+                    dst = static_cast<C*>(I.specd) + (int64_t)g * M3;
+                } else if (MODE == F3_X) {
+                    src = nullptr;
+                    dst = static_cast<C*>(I.X) + (int64_t)g * M3;
+                } else if (MODE == F3_Y) {
+                    src = static_cast<const C*>(I.X) + (int64_t)g * M3;
+                    dst = static_cast<C*>(I.X) + (int64_t)g * M3;
+                } else if (MODE == F3_Z) {
+                    src = static_cast<const C*>(I.X) + (int64_t)ch * M3;
+                    dst = static_cast<C*>(I.Xc) + (int64_t)g * M3;
+                } else {
+                    src = static_cast<const C*>(I.Xc) + (int64_t)g * M3;
+                    dst = static_cast<C*>(I.Xc) + (int64_t)g * M3;
+                }
+                const T* W = static_cast<const T*>(I.W) + (int64_t)g * n_cap * n_cap * n_cap;
+                // load: x rows element-major (consecutive threads along a row),
+                // y and z sequences sequence-major (consecutive x)
+                for (int idx = threadIdx.x; idx < kSeq3 * M; idx += nthr) {
+                    const int q = (AXIS == 0) ? idx / M : idx % kSeq3;
+                    const int r = (AXIS == 0) ? idx - q * M : idx / kSeq3;
+                    int a, b;
+                    int64_t base, stride;
+                    seq(j0 + q, a, b, base, stride);
+                    C v = {(T)0, (T)0};
+                    if (MODE == F3_X) {
+                        if (a < n && b < n && r < n)
+                            v.x = W[((int64_t)a * n_cap + b) * n_cap + r];
+                    } else if (MODE == F3_Y) {
+                        if (a < n && r < n) v = src[base + (int64_t)r * stride];
+                    } else if (wanted(a, b)) {
+                        v = src[base + (int64_t)r * stride];
+                    }
+                    buf[q * PM + lds_pad(r)] = v;
+                }
+                __syncthreads();
+                const C* tw = SPEC ? static_cast<const C*>(I.twd) : static_cast<const C*>(I.tw);
+                block_fft_tw<T>(buf, kSeq3, M, G.nstages, G.radix, G.tw_off, tw);
+                if (MODE == F3_Z) {
+                    // times the real kernel spectrum, conjugated; then the
+                    // transform of the conjugate (the inverse along z)
+                    const T* sp = static_cast<const T*>(I.spec) + (int64_t)kern * M3;
+                    for (int idx = threadIdx.x; idx < kSeq3 * M; idx += nthr) {
+                        const int q = idx % kSeq3, r = idx / kSeq3;
+                        int a, b;
+                        int64_t base, stride;
+                        seq(j0 + q, a, b, base, stride);
+                        const T sv = sp[base + (int64_t)r * stride];
+                        const C v = buf[q * PM + lds_pad(r)];
+                        buf[q * PM + lds_pad(r)] = {v.x * sv, -v.y * sv};
+                    }
+                    __syncthreads();
+                    block_fft_tw<T>(buf, kSeq3, M, G.nstages, G.radix, G.tw_off, tw);
+                }
+                // store
+                for (int idx = threadIdx.x; idx < kSeq3 * M; idx += nthr) {
+                    const int q = (AXIS == 0) ? idx / M : idx % kSeq3;
+                    const int r = (AXIS == 0) ? idx - q * M : idx / kSeq3;
+                    int a, b;
+                    int64_t base, stride;
+                    seq(j0 + q, a, b, base, stride);
+                    const C v = buf[q * PM + lds_pad(r)];
+                    if (MODE == F3_IX) {
+                        if (a < n && b < n && r < n)
+                            static_cast<T*>(I.V)[(((int64_t)g * n_cap + a) * n_cap + b) * n_cap + r] = v.x;
+                    } else if (MODE == F3_Z || MODE == F3_IY) {
+                        if (r < n && wanted(a, b)) dst[base + (int64_t)r * stride] = v;
+                    } else if (wanted(a, b)) {
+                        dst[base + (int64_t)r * stride] = v;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    VB_END
+}
+
+// Kernel grids for the spectra (FP64, when the spacing or M changed): the
+// circulant samples K(h lag) of K1 and K2 at every (z, y, x) of M^3, and the
+// stage twiddles of M in double and in the element type.
+template <typename T>
+__global__ __launch_bounds__(256) void k_s3_fill(LaunchMap map)
+{
+    VB_BEGIN_IF_SKIP(map, K_S3_FILL, spec_needed(I))
+    {
+        const Geom& G = *I.geom;
+        const int M = G.M;
+        const int64_t M2 = (int64_t)M * M, M3 = M2 * M;
+        const int64_t idx = (int64_t)lb * 256 + threadIdx.x;
+        if (idx < M - 1) {
+            stage_twiddle<double>(idx, M, G.nstages, G.radix, G.tw_off, I.twd);
+            stage_twiddle<T>(idx, M, G.nstages, G.radix, G.tw_off, I.tw);
+        }
+        if (idx < 2 * M3) {
+            const int kern = (int)(idx / M3);
+            const int64_t e = idx - kern * M3;
+            const int z = (int)(e / M2), y = (int)((e - (int64_t)z * M2) / M), x = (int)(e % M);
+            const double lx = lag3(x, M), ly = lag3(y, M), lz = lag3(z, M);
+            const double r2 = G.h * G.h * (lx * lx + ly * ly + lz * lz);
+            static_cast<cplx<double>*>(I.specd)[idx] = {kern3(kern, r2), 0.0};
+        }
+    }
+    VB_END
+}
+
+// The spectra: real parts of the transformed kernel grids, scaled by 1/M^3,
+// in the element type.
+template <typename T>
+__global__ __launch_bounds__(256) void k_s3_store(LaunchMap map)
+{
+    VB_BEGIN_IF_SKIP(map, K_S3_STORE, spec_needed(I))
+    {
+        const Geom& G = *I.geom;
+        const int64_t M3 = (int64_t)G.M * G.M * G.M;
+        const int64_t idx = (int64_t)lb * 256 + threadIdx.x;
+        if (idx < 2 * M3)
+            static_cast<T*>(I.spec)[idx] = (T)(static_cast<const cplx<double>*>(I.specd)[idx].x / (double)M3);
+    }
+    VB_END
+}
+
 // Allow up to the full 160 KB of LDS for a kernel's dynamic allocation.
 template <typename K>
 static void allow_lds(K kernel, size_t lds)
@@ -853,9 +1076,35 @@ static hipError_t fft_p(int kind, const Cfg& c, const LaunchMap& m, const Launch
     }
 }
 
+// s = 3 kinds: the convolution passes in the element type, the spectrum
+// passes in double.
+template <typename T, int FORM>
+static hipError_t f3_go(int kind, const LaunchMap& map, const Launch& l, hipStream_t st)
+{
+    dim3 g(l.grid), b(l.block);
+    switch (kind) {
+    case K_F3_X: allow_lds(k_f3<T, FORM, F3_X>, l.lds); hipLaunchKernelGGL((k_f3<T, FORM, F3_X>), g, b, l.lds, st, map); break;
+    case K_F3_Y: allow_lds(k_f3<T, FORM, F3_Y>, l.lds); hipLaunchKernelGGL((k_f3<T, FORM, F3_Y>), g, b, l.lds, st, map); break;
+    case K_F3_Z: allow_lds(k_f3<T, FORM, F3_Z>, l.lds); hipLaunchKernelGGL((k_f3<T, FORM, F3_Z>), g, b, l.lds, st, map); break;
+    case K_F3_IY: allow_lds(k_f3<T, FORM, F3_IY>, l.lds); hipLaunchKernelGGL((k_f3<T, FORM, F3_IY>), g, b, l.lds, st, map); break;
+    case K_F3_IX: allow_lds(k_f3<T, FORM, F3_IX>, l.lds); hipLaunchKernelGGL((k_f3<T, FORM, F3_IX>), g, b, l.lds, st, map); break;
+    case K_S3_X: allow_lds(k_f3<double, 0, S3_X>, l.lds); hipLaunchKernelGGL((k_f3<double, 0, S3_X>), g, b, l.lds, st, map); break;
+    case K_S3_Y: allow_lds(k_f3<double, 0, S3_Y>, l.lds); hipLaunchKernelGGL((k_f3<double, 0, S3_Y>), g, b, l.lds, st, map); break;
+    case K_S3_Z: allow_lds(k_f3<double, 0, S3_Z>, l.lds); hipLaunchKernelGGL((k_f3<double, 0, S3_Z>), g, b, l.lds, st, map); break;
+    case K_S3_FILL: hipLaunchKernelGGL((k_s3_fill<T>), g, b, 0, st, map); break;
+    case K_S3_STORE: hipLaunchKernelGGL((k_s3_store<T>), g, b, 0, st, map); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_fft_kind(int kind, const Cfg& c, const LaunchMap& map, const Launch& l,
                            hipStream_t st)
 {
+    if (c.s == 3) {
+        if (c.dtype == 0) return c.form == 0 ? f3_go<float, 0>(kind, map, l, st) : f3_go<float, 1>(kind, map, l, st);
+        return c.form == 0 ? f3_go<double, 0>(kind, map, l, st) : f3_go<double, 1>(kind, map, l, st);
+    }
     if (c.dtype == 0)
         return c.s == 1 ? fft_p<float, 1>(kind, c, map, l, st) : fft_p<float, 2>(kind, c, map, l, st);
     return c.s == 1 ? fft_p<double, 1>(kind, c, map, l, st) : fft_p<double, 2>(kind, c, map, l, st);

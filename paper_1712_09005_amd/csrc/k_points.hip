@@ -12,43 +12,6 @@ namespace tsne {
 
 // ---------------------------------------------------------------- helpers
 
-// 1 / prod_{k != m} (m - k), the denominator of the Lagrange basis on nodes
-// m + 1/2 (in units of the node spacing).
-__host__ __device__ constexpr double lag_inv_denom(int P, int m)
-{
-    double d = 1.0;
-    for (int k = 0; k < P; ++k)
-        if (k != m) d *= (double)(m - k);
-    return 1.0 / d;
-}
-
-// Lagrange basis of Section 2.1 on the p equispaced nodes (m + 1/2)/p of the
-// unit interval, evaluated at t in [0, 1] (eq. (equinodes) for the nodes).
-template <typename T, int P>
-__device__ __forceinline__ void lagrange(T t, T (&L)[P])
-{
-    const T sv = t * (T)P;
-    T a[P];
-#pragma unroll
-    for (int k = 0; k < P; ++k) a[k] = sv - ((T)k + (T)0.5);
-#pragma unroll
-    for (int m = 0; m < P; ++m) {
-        T prod = (T)lag_inv_denom(P, m);
-#pragma unroll
-        for (int k = 0; k < P; ++k)
-            if (k != m) prod *= a[k];
-        L[m] = prod;
-    }
-}
-
-// Charges and potentials per form: A {1, y'(d)} -> K1*1, K2*1, K2*y'(d);
-// B adds |y'|^2 and takes K2*|y'|^2 in place of K1*1; V (vector kernels)
-// has the one charge 1 -> K1*1 and (z_d K2)*1 for each dimension d.
-template <int S, int FORM> struct Shape {
-    static constexpr int NC = (FORM == 0) ? S + 1 : (FORM == 1) ? S + 2 : 1;
-    static constexpr int NP = (FORM == 2) ? S + 1 : S + 2;
-};
-
 // ---------------------------------------------------------------- per-call arguments
 
 __global__ void k_set_args(Inst* inst, CallArgs a)
@@ -84,11 +47,12 @@ hipError_t launch_set_args(Inst* inst, const CallArgs& a, hipStream_t st)
 // ---------------------------------------------------------------- box geometry
 
 // Per-block partial min / max / sum of the coordinates (double) and a
-// non-finite flag.  The geometry kernel reduces them.
+// non-finite flag, kBoxPart doubles per block (minima at 0, maxima at 4,
+// sums at 8, the flag at 12).  The geometry kernel reduces them.
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_box(LaunchMap map)
 {
-    __shared__ double sh[4][8];
+    __shared__ double sh[4][kBoxPart];
     VB_BEGIN(map, K_BOX)
     if (live_pre(I)) {
         const T* Y = static_cast<const T*>(I.Yin);
@@ -124,20 +88,20 @@ __global__ __launch_bounds__(256) void k_box(LaunchMap map)
         if (lane == 0) {
             for (int d = 0; d < S; ++d) {
                 sh[wv][d] = lo[d];
-                sh[wv][2 + d] = hi[d];
-                sh[wv][4 + d] = sm[d];
+                sh[wv][4 + d] = hi[d];
+                sh[wv][8 + d] = sm[d];
             }
-            sh[wv][6] = bad;
+            sh[wv][12] = bad;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            double* out = I.box_part + (int64_t)lb * 8;
+            double* out = I.box_part + (int64_t)lb * kBoxPart;
             for (int d = 0; d < S; ++d) {
                 out[d] = fmin(fmin(sh[0][d], sh[1][d]), fmin(sh[2][d], sh[3][d]));
-                out[2 + d] = fmax(fmax(sh[0][2 + d], sh[1][2 + d]), fmax(sh[2][2 + d], sh[3][2 + d]));
-                out[4 + d] = ((sh[0][4 + d] + sh[1][4 + d]) + sh[2][4 + d]) + sh[3][4 + d];
+                out[4 + d] = fmax(fmax(sh[0][4 + d], sh[1][4 + d]), fmax(sh[2][4 + d], sh[3][4 + d]));
+                out[8 + d] = ((sh[0][8 + d] + sh[1][8 + d]) + sh[2][8 + d]) + sh[3][8 + d];
             }
-            out[6] = fmax(fmax(sh[0][6], sh[1][6]), fmax(sh[2][6], sh[3][6]));
+            out[12] = fmax(fmax(sh[0][12], sh[1][12]), fmax(sh[2][12], sh[3][12]));
         }
     }
     VB_END
@@ -203,22 +167,22 @@ __device__ __forceinline__ bool axis_plan(int nodes, int Mcap, int& Mref, int& h
 template <int S>
 __global__ __launch_bounds__(256) void k_geom(LaunchMap map)
 {
-    __shared__ double sh[4][8];
+    __shared__ double sh[4][kBoxPart];
     VB_BEGIN(map, K_GEOM)
     Geom& G = *I.geom;
     const bool run = live_pre(I);
     if (run) {
         const int nb = I.nb_box;
-        double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
-        double sm[2] = {0.0, 0.0}, bad = 0.0;
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        double sm[3] = {0.0, 0.0, 0.0}, bad = 0.0;
         for (int b = threadIdx.x; b < nb; b += 256) {
-            const double* pp = I.box_part + (int64_t)b * 8;
+            const double* pp = I.box_part + (int64_t)b * kBoxPart;
             for (int d = 0; d < S; ++d) {
                 lo[d] = fmin(lo[d], pp[d]);
-                hi[d] = fmax(hi[d], pp[2 + d]);
-                sm[d] += pp[4 + d];
+                hi[d] = fmax(hi[d], pp[4 + d]);
+                sm[d] += pp[8 + d];
             }
-            bad = fmax(bad, pp[6]);
+            bad = fmax(bad, pp[12]);
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
@@ -234,20 +198,20 @@ __global__ __launch_bounds__(256) void k_geom(LaunchMap map)
         if (lane == 0) {
             for (int d = 0; d < S; ++d) {
                 sh[wv][d] = lo[d];
-                sh[wv][2 + d] = hi[d];
-                sh[wv][4 + d] = sm[d];
+                sh[wv][4 + d] = hi[d];
+                sh[wv][8 + d] = sm[d];
             }
-            sh[wv][6] = bad;
+            sh[wv][12] = bad;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            double glo[2], ghi[2], gsm[2];
+            double glo[3], ghi[3], gsm[3];
             for (int d = 0; d < S; ++d) {
                 glo[d] = fmin(fmin(sh[0][d], sh[1][d]), fmin(sh[2][d], sh[3][d]));
-                ghi[d] = fmax(fmax(sh[0][2 + d], sh[1][2 + d]), fmax(sh[2][2 + d], sh[3][2 + d]));
-                gsm[d] = ((sh[0][4 + d] + sh[1][4 + d]) + sh[2][4 + d]) + sh[3][4 + d];
+                ghi[d] = fmax(fmax(sh[0][4 + d], sh[1][4 + d]), fmax(sh[2][4 + d], sh[3][4 + d]));
+                gsm[d] = ((sh[0][8 + d] + sh[1][8 + d]) + sh[2][8 + d]) + sh[3][8 + d];
             }
-            const double gbad = fmax(fmax(sh[0][6], sh[1][6]), fmax(sh[2][6], sh[3][6]));
+            const double gbad = fmax(fmax(sh[0][12], sh[1][12]), fmax(sh[2][12], sh[3][12]));
             int st = 0;
             double L = 0.0;
             for (int d = 0; d < S; ++d) {
@@ -286,7 +250,7 @@ __global__ __launch_bounds__(256) void k_geom(LaunchMap map)
                 G.h = w / I.p;
                 // per-axis interval counts: the square box, or a rectangle of
                 // the same spacing whose narrower axes get their own counts
-                int ma[2] = {m, m};
+                int ma[3] = {m, m, m};
                 for (int d = 0; d < S; ++d) {
                     const double Ld = ghi[d] - glo[d];
                     if (I.rect && S == 2 && Ld < L) {
@@ -298,9 +262,10 @@ __global__ __launch_bounds__(256) void k_geom(LaunchMap map)
                 }
                 G.n_int = ma[0];
                 G.n = ma[0] * I.p;
-                G.n_int_y = (S == 2) ? ma[1] : 1;
-                G.n_y = (S == 2) ? ma[1] * I.p : 1;
-                G.n_cells = (S == 2) ? ma[0] * ma[1] : ma[0];
+                // s = 3 has the square box only: every axis has n_int intervals
+                G.n_int_y = (S >= 2) ? ma[1] : 1;
+                G.n_y = (S >= 2) ? ma[1] * I.p : 1;
+                G.n_cells = (S == 3) ? ma[0] * ma[1] * ma[2] : (S == 2) ? ma[0] * ma[1] : ma[0];
                 // explicit roundings (no contraction) so the origin is the
                 // correctly rounded value of mid - (m/2) w
                 for (int d = 0; d < S; ++d) {
@@ -714,6 +679,145 @@ __global__ __launch_bounds__(256) void k_gather(LaunchMap map)
     VB_END
 }
 
+// ---------------------------------------------------------------- s = 3
+
+// Step 1 for s = 3 (Section 2: the s + 2 sums hold for any s; Section 2.4's
+// tensor-product nodes on a cube): one thread per (cell, node) of the p^3
+// nodes of a cell, summing the cell's points' charges times the node's
+// Lagrange weight L_m0(x) L_m1(y) L_m2(z), in sorted (point index) order.
+// Every node of every cell is written, an empty cell's with zeros, so the
+// grid needs no clearing and no partial sums cross threads.
+template <typename T, int P, int FORM>
+__global__ __launch_bounds__(256) void k_spread3(LaunchMap map)
+{
+    constexpr int NC = Shape<3, FORM>::NC;
+    constexpr int NN = P * P * P;
+    VB_BEGIN(map, K_SPREAD3)
+    if (live(I)) {
+        const Geom& G = *I.geom;
+        const int64_t t = (int64_t)lb * 256 + threadIdx.x;
+        const int c = (int)(t / NN), m = (int)(t - (int64_t)c * NN);
+        if (c < G.n_cells) {
+            const int n_int = G.n_int, n_cap = I.n_cap;
+            const int cx = c % n_int, cy = (c / n_int) % n_int, cz = c / (n_int * n_int);
+            const int m0 = m % P, m1 = (m / P) % P, m2 = m / (P * P);
+            const T* sY = static_cast<const T*>(I.sY);
+            const double w = G.w, qs = G.qscale;
+            T acc[NC];
+#pragma unroll
+            for (int q = 0; q < NC; ++q) acc[q] = (T)0;
+            const int e = I.cell_start[c + 1];
+            for (int pos = I.cell_start[c]; pos < e; ++pos) {
+                const Pt<T, 3> yp = Pt<T, 3>::load(sY, pos);
+                T tl[3], q[NC];
+                double qd[3], r2 = 0.0;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    locate<T>(yp.v[d], G.origin[d], w, n_int, tl[d]);
+                    // centred, power-of-two scaled charges, rounded once from double
+                    qd[d] = ((double)yp.v[d] - G.centre[d]) * qs;
+                    r2 += qd[d] * qd[d];
+                }
+                q[0] = (T)1;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) q[1 + d] = (T)qd[d];
+                if (FORM == 1) q[NC - 1] = (T)r2;
+                T Lx[P], Ly[P], Lz[P];
+                lagrange<T, P>(tl[0], Lx);
+                lagrange<T, P>(tl[1], Ly);
+                lagrange<T, P>(tl[2], Lz);
+                const T wgt = Lz[m2] * Ly[m1] * Lx[m0];
+#pragma unroll
+                for (int qq = 0; qq < NC; ++qq) acc[qq] += wgt * q[qq];
+            }
+            T* W = static_cast<T*>(I.W);
+            const int64_t node = ((int64_t)(cz * P + m2) * n_cap + (cy * P + m1)) * n_cap + cx * P + m0;
+            const int64_t plane = (int64_t)n_cap * n_cap * n_cap;
+#pragma unroll
+            for (int qq = 0; qq < NC; ++qq) W[qq * plane + node] = acc[qq];
+        }
+    }
+    VB_END
+}
+
+// Step 3 for s = 3: one thread per sorted position, phi_k = sum over the
+// cell's p^3 nodes of L_m0(x) L_m1(y) L_m2(z) V_k, then the Appendix assembly
+// as for s = 1, 2 (forms A and B); Z partials per block in double.
+template <typename T, int P, int FORM>
+__global__ __launch_bounds__(256) void k_gather3(LaunchMap map)
+{
+    constexpr int NP = Shape<3, FORM>::NP;
+    __shared__ double sh[8];
+    VB_BEGIN(map, K_GATHER3)
+    if (live(I)) {
+        const Geom& G = *I.geom;
+        const int64_t pos = (int64_t)lb * 256 + threadIdx.x;
+        double h1d = 0.0;
+        if (pos < I.n) {
+            const int n_int = G.n_int, n_cap = I.n_cap;
+            const Pt<T, 3> yp = Pt<T, 3>::load(static_cast<const T*>(I.sY), pos);
+            T tl[3];
+            int cl[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) cl[d] = locate<T>(yp.v[d], G.origin[d], G.w, n_int, tl[d]);
+            T Lx[P], Ly[P], Lz[P];
+            lagrange<T, P>(tl[0], Lx);
+            lagrange<T, P>(tl[1], Ly);
+            lagrange<T, P>(tl[2], Lz);
+            const T* V = static_cast<const T*>(I.V);
+            const int64_t plane = (int64_t)n_cap * n_cap * n_cap;
+            T phi[NP];
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                T a = (T)0;
+#pragma unroll
+                for (int m2 = 0; m2 < P; ++m2) {
+                    T b = (T)0;
+#pragma unroll
+                    for (int m1 = 0; m1 < P; ++m1) {
+                        const T* row = V + k * plane +
+                                       ((int64_t)(cl[2] * P + m2) * n_cap + (cl[1] * P + m1)) * n_cap + cl[0] * P;
+                        T r = (T)0;
+#pragma unroll
+                        for (int m0 = 0; m0 < P; ++m0) r += Lx[m0] * row[m0];
+                        b += Ly[m1] * r;
+                    }
+                    a += Lz[m2] * b;
+                }
+                phi[k] = a;
+            }
+            // potentials: phi[1] = K2*1, phi[2+d] = K2*(y'(d) qs); phi[0] = K1*1 (A)
+            // or K2*(|y'|^2 qs^2) (B); the assembly in double
+            const double inv_qs = 1.0 / G.qscale;
+            double yc[3], r2c = 0.0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                yc[d] = (double)yp.v[d] - G.centre[d];
+                r2c += yc[d] * yc[d];
+            }
+            double h1;
+            if (FORM == 0) {
+                h1 = (double)phi[0];
+            } else {
+                double dot = 0.0;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) dot += yc[d] * (double)phi[2 + d];
+                h1 = (1.0 + r2c) * (double)phi[1] - 2.0 * dot * inv_qs + (double)phi[0] * inv_qs * inv_qs;
+            }
+            const int i = I.perm[pos];
+            Pt<T, 3> rv;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) rv.v[d] = (T)(yc[d] * (double)phi[1] - (double)phi[2 + d] * inv_qs);
+            rv.store(static_cast<T*>(I.R), i);
+            if (I.h1keep) I.h1keep[i] = h1;
+            h1d = h1;
+        }
+        const double bs = block_sum_d(h1d, sh);
+        if (threadIdx.x == 0) I.z_part[lb] = bs;
+    }
+    VB_END
+}
+
 // One block per instance: Z = sum_i h1_i - N (the self pairs, K1(0) = 1),
 // from the gather's block partials in a fixed order.
 __global__ __launch_bounds__(256) void k_zsum(LaunchMap map)
@@ -891,9 +995,47 @@ static hipError_t pts_p(int kind, const Cfg& c, const LaunchMap& m, const Launch
     }
 }
 
+// s = 3: forms A and B only
+template <typename T, int P, int FORM>
+static hipError_t launch_pts3(int kind, const LaunchMap& map, const Launch& l, hipStream_t st)
+{
+    dim3 g(l.grid), b(l.block);
+    switch (kind) {
+    case K_BOX: hipLaunchKernelGGL((k_box<T, 3>), g, b, 0, st, map); break;
+    case K_GEOM: hipLaunchKernelGGL((k_geom<3>), g, b, 0, st, map); break;
+    case K_SPREAD3: hipLaunchKernelGGL((k_spread3<T, P, FORM>), g, b, 0, st, map); break;
+    case K_GATHER3: hipLaunchKernelGGL((k_gather3<T, P, FORM>), g, b, 0, st, map); break;
+    case K_ZSUM: hipLaunchKernelGGL(k_zsum, g, b, 0, st, map); break;
+    case K_NORM: hipLaunchKernelGGL((k_norm<T, 3>), g, b, 0, st, map); break;
+    case K_UPDATE: hipLaunchKernelGGL((k_update<T, 3>), g, b, 0, st, map); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int P>
+static hipError_t pts3_form(int kind, const Cfg& c, const LaunchMap& m, const Launch& l, hipStream_t st)
+{
+    return c.form == 0 ? launch_pts3<T, P, 0>(kind, m, l, st) : launch_pts3<T, P, 1>(kind, m, l, st);
+}
+
+template <typename T>
+static hipError_t pts3_p(int kind, const Cfg& c, const LaunchMap& m, const Launch& l, hipStream_t st)
+{
+    switch (c.p) {
+    case 2: return pts3_form<T, 2>(kind, c, m, l, st);
+    case 3: return pts3_form<T, 3>(kind, c, m, l, st);
+    case 4: return pts3_form<T, 4>(kind, c, m, l, st);
+    case 5: return pts3_form<T, 5>(kind, c, m, l, st);
+    case 6: return pts3_form<T, 6>(kind, c, m, l, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 static hipError_t pts_s(int kind, const Cfg& c, const LaunchMap& m, const Launch& l, hipStream_t st)
 {
+    if (c.s == 3) return pts3_p<T>(kind, c, m, l, st);
     return c.s == 1 ? pts_p<T, 1>(kind, c, m, l, st) : pts_p<T, 2>(kind, c, m, l, st);
 }
 
@@ -904,6 +1046,8 @@ hipError_t launch_kind(int kind, const Cfg& c, const LaunchMap& map, const Launc
     switch (kind) {
     case K_FFT_ROWS: case K_FFT_COLS: case K_FFT_IROWS: case K_FFT_1D:
     case K_SPEC0: case K_SPEC1: case K_SPEC2:
+    case K_F3_X: case K_F3_Y: case K_F3_Z: case K_F3_IY: case K_F3_IX:
+    case K_S3_FILL: case K_S3_X: case K_S3_Y: case K_S3_Z: case K_S3_STORE:
         return launch_fft_kind(kind, c, map, l, st);
     case K_ATTR: case K_ATTR_ALL: case K_ATTR_T: case K_ATTR_T_ALL: case K_ASUM: case K_KL_ATTR:
     case K_KL: case K_KLSUM:

@@ -546,9 +546,11 @@ hipError_t launch_sort_kind(int kind, const Cfg& c, const LaunchMap& map, const 
                             hipStream_t st)
 {
     if (c.dtype == 0) return c.s == 1 ? launch_sort_ts<float, 1>(kind, map, l, st)
-                                      : launch_sort_ts<float, 2>(kind, map, l, st);
+                             : c.s == 2 ? launch_sort_ts<float, 2>(kind, map, l, st)
+                                        : launch_sort_ts<float, 3>(kind, map, l, st);
     return c.s == 1 ? launch_sort_ts<double, 1>(kind, map, l, st)
-                    : launch_sort_ts<double, 2>(kind, map, l, st);
+         : c.s == 2 ? launch_sort_ts<double, 2>(kind, map, l, st)
+                    : launch_sort_ts<double, 3>(kind, map, l, st);
 }
 
 }  // namespace tsne

@@ -19,6 +19,8 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxM = 12288;       // row transforms: 1024 threads x 4 butterflies x radix 3
+constexpr int kMaxM3 = 400;        // s = 3 passes: 32 threads x 4 butterflies per stage, so
+                                   // M / R <= 128 at every radix R of a ladder length <= 400
 constexpr int kMaxBfly = 4;          // must match the kernels' per-thread butterfly bound
 constexpr int kGridCap = 4096;       // virtual blocks are looped over beyond this
 
@@ -95,7 +97,10 @@ tsne_status derive(const tsne_desc* d, Derived& o)
 {
     if (!d) return TSNE_E_ARG;
     if (d->n < 2 || d->n > (int64_t)INT_MAX / 4) return TSNE_E_ARG;
-    if (d->s != 1 && d->s != 2) return TSNE_E_ARG;
+    if (d->s < 1 || d->s > 3) return TSNE_E_ARG;
+    // s = 3: forms A and B, the square box, the CSR attraction in one slab
+    if (d->s == 3 && (d->form == TSNE_FORM_V || d->rect != 0 || d->attr_layout == 2 || d->attr_slabs > 1))
+        return TSNE_E_UNSUPPORTED;
     if (d->dtype != TSNE_F32 && d->dtype != TSNE_F64) return TSNE_E_ARG;
     if (d->p < 2 || d->p > kMaxP) return TSNE_E_UNSUPPORTED;
     if (d->policy != TSNE_GRID_PAPER && d->policy != TSNE_GRID_FIXED) return TSNE_E_ARG;
@@ -131,7 +136,11 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     // the device picks a smaller ladder length when the box is smaller; every
     // ladder length has radix 3, 4 or 5 stages only
     o.rmin = 3;
-    o.ncell_cap = (d->s == 2) ? o.max_int * o.max_int : o.max_int;
+    // s = 3: the three-axis passes run 32 threads per transform (kMaxBfly
+    // butterflies each at radix 3), and hold M^3 complex grids
+    if (d->s == 3 && o.M > kMaxM3) return TSNE_E_UNSUPPORTED;
+    o.ncell_cap = (d->s == 3) ? o.max_int * o.max_int * o.max_int
+                : (d->s == 2) ? o.max_int * o.max_int : o.max_int;
     // radix passes of the binning: enough digits of at most kDigitBitsMax bits
     // for the largest cell index of the capacity
     {
@@ -150,6 +159,7 @@ tsne_status derive(const tsne_desc* d, Derived& o)
         const bool big = ybytes >= ((int64_t)4 << 20);
         int sl = d->attr_slabs ? d->attr_slabs : (big ? 4 : 1);
         if (sl != 1 && sl != 2 && sl != 4 && sl != 8) return TSNE_E_ARG;   // slabs map onto XCDs
+        if (d->s == 3) sl = 1;
         o.lpr = d->lanes_per_row ? d->lanes_per_row : (sl > 1 ? 4 : 32);
         if (d->nnz >= ((int64_t)1 << 31) || d->nnz == 0) sl = 1;   // split offsets are int32
         if (sl > d->n) sl = (int)d->n;
@@ -196,7 +206,8 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     if (d->s == 2 && (o.col_threads > 1024 || o.col_lds > kLdsMax)) return TSNE_E_UNSUPPORTED;
 
     o.nb_box = std::min(512, std::max(1, cdiv(n, 256 * 4)));
-    o.nb_gather = cdiv(o.items_cap, 256);               // one thread per item
+    o.nb_gather = (d->s == 3) ? cdiv(n, 256)             // s = 3: one thread per point
+                              : cdiv(o.items_cap, 256);   // one thread per item
     o.nb_kl = (int)std::min<int64_t>(2048, cdiv(n, 8));
     o.nb_scan = cdiv(o.ncell_cap, 1024);
     o.ntiles_sort = cdiv(n, kSortTile);
@@ -221,7 +232,18 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     vb[K_SCAN_B] = o.nb_scan;
     vb[K_SPREAD] = cdiv(o.items_cap, 256);
     vb[K_FIX] = cdiv(o.ncell_cap, 256);
-    if (d->s == 2) {
+    vb[K_GATHER] = o.nb_gather;
+    if (d->s == 3) {
+        // node-per-thread spreading, point-per-thread gathering, no items
+        vb[K_SCAN_A] = vb[K_SCAN_B] = vb[K_SPREAD] = vb[K_FIX] = vb[K_GATHER] = 0;
+        vb[K_SPREAD3] = (int)cdiv((int64_t)o.ncell_cap * o.p * o.p * o.p, 256);
+        vb[K_GATHER3] = o.nb_gather;
+        const int bpg = (int)((int64_t)o.M * o.M / 16);   // blocks of 16 sequences per grid
+        vb[K_F3_X] = vb[K_F3_Y] = o.nc * bpg;
+        vb[K_F3_Z] = vb[K_F3_IY] = vb[K_F3_IX] = o.np * bpg;
+        vb[K_S3_X] = vb[K_S3_Y] = vb[K_S3_Z] = 2 * bpg;
+        vb[K_S3_FILL] = vb[K_S3_STORE] = (int)cdiv(2 * (int64_t)o.M * o.M * o.M, 256);
+    } else if (d->s == 2) {
         vb[K_FFT_ROWS] = o.nc * cdiv(o.n_cap, 2);
         // whole tiles of tile_w / col_group groups each, per potential
         vb[K_FFT_COLS] = o.np * o.ntiles * (o.tile_w / o.col_group);
@@ -236,7 +258,6 @@ tsne_status derive(const tsne_desc* d, Derived& o)
         vb[K_SPEC1] = cdiv(2 * o.half, 256);
         vb[K_SPEC0] = cdiv(std::max(o.M, 2 * o.half), 256);
     }
-    vb[K_GATHER] = o.nb_gather;
     vb[K_NORM] = cdiv(n * d->s, 256);
     {
         const int nrb = cdiv(n, 256 / o.lpr);
@@ -258,15 +279,17 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     vb[K_KLSUM] = (d->nnz > 0) ? 1 : 0;
 
     // workspace layout
-    const int64_t grid = (d->s == 2) ? (int64_t)o.n_cap * o.n_cap : o.n_cap;
+    const int64_t grid = (d->s == 3) ? (int64_t)o.n_cap * o.n_cap * o.n_cap
+                       : (d->s == 2) ? (int64_t)o.n_cap * o.n_cap : o.n_cap;
     const int64_t nn = (d->s == 2) ? o.p * o.p : o.p;
+    const int64_t M3 = (int64_t)o.M * o.M * o.M;
     size_t sz[R_N];
     sz[R_INST] = sizeof(Inst);
     sz[R_PREFIX] = sizeof(int) * K_NKINDS * 2;
     sz[R_GEOM] = sizeof(Geom);
     sz[R_SCHED] = sizeof(Sched);
     sz[R_SMALL] = 64;                                   // status, iter
-    sz[R_BOX] = sizeof(double) * 8 * o.nb_box;
+    sz[R_BOX] = sizeof(double) * kBoxPart * o.nb_box;
     sz[R_CSTART] = sizeof(int) * (o.ncell_cap + 1);
     sz[R_ISTART] = sizeof(int) * (o.ncell_cap + 1);
     sz[R_SCAN] = sizeof(int) * o.nb_scan;
@@ -278,9 +301,18 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     sz[R_GTOT] = sizeof(uint32_t) * (size_t)o.npass * o.ngroups_sort * kDigitBins;
     sz[R_PERM] = sizeof(int) * n;
     sz[R_SY] = (size_t)o.tsz * n * d->s;
-    sz[R_CARRY] = (size_t)o.tsz * 2 * o.nwaves * nn * o.nc;
+    sz[R_CARRY] = (d->s == 3) ? 0 : (size_t)o.tsz * 2 * o.nwaves * nn * o.nc;
     sz[R_W] = (size_t)o.tsz * o.nc * grid;
-    if (d->s == 2) {
+    if (d->s == 3) {
+        // complex M^3 grids per charge and per potential, the two kernel
+        // spectra (element type), their FP64 complex build grids
+        sz[R_X] = (size_t)csz * o.nc * M3;
+        sz[R_XC] = (size_t)csz * o.np * M3;
+        sz[R_SPEC] = (size_t)o.tsz * 2 * M3;
+        sz[R_SPECTMP] = (size_t)16 * 2 * M3;
+        sz[R_KTAB] = 0;
+        sz[R_CCOS] = 0;
+    } else if (d->s == 2) {
         sz[R_X] = (size_t)csz * o.nc * o.ntiles * o.n_cap * o.tile_w;
         sz[R_XC] = (size_t)csz * o.np * o.ntiles * o.n_cap * o.tile_w;
         // one [half][half] slot per kernel table (form V: a third, the odd
@@ -302,7 +334,7 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     }
     sz[R_V] = (size_t)o.tsz * o.np * grid;
     sz[R_TW] = (size_t)csz * o.M;
-    sz[R_TWY] = (d->s == 2) ? (size_t)csz * o.M : 0;
+    sz[R_TWY] = (d->s == 2) ? (size_t)csz * o.M : (d->s == 3) ? (size_t)16 * o.M : 0;   // s = 3: FP64
     sz[R_COS] = sizeof(double) * 2 * o.M;               // cos, then sin
     sz[R_R] = (size_t)o.tsz * n * d->s;
     sz[R_FA] = (size_t)o.tsz * n * d->s;
@@ -354,6 +386,14 @@ Launch launch_of(int kind, const Derived& o, int vblocks)
     case K_ATTR_T: case K_ATTR_T_ALL:
         l.block = 1024;
         l.lds = o.tile_lds;
+        break;
+    case K_F3_X: case K_F3_Y: case K_F3_Z: case K_F3_IY: case K_F3_IX:
+        l.block = 16 * 32;                                 // 16 sequences, 32 threads each
+        l.lds = (size_t)16 * lds_stride(o.M) * 2 * o.tsz;
+        break;
+    case K_S3_X: case K_S3_Y: case K_S3_Z:
+        l.block = 16 * 32;
+        l.lds = (size_t)16 * lds_stride(o.M) * 16;         // FP64 complex
         break;
     default:
         break;
@@ -413,15 +453,27 @@ static const int kChain2[] = {K_BOX, K_GEOM, K_SPEC0, K_SPEC1, K_SPEC2, K_KEY, K
                               K_HIST1, K_TSCAN1, K_SORT1, K_HIST2, K_TSCAN2, K_SORT2, K_BOUNDS,
                               K_SCAN_A, K_SCAN_B, K_SPREAD, K_FIX, K_FFT_ROWS, K_FFT_COLS,
                               K_FFT_IROWS, K_GATHER, K_ZSUM};
+static const int kChain3[] = {K_BOX, K_GEOM, K_S3_FILL, K_S3_X, K_S3_Y, K_S3_Z, K_S3_STORE, K_KEY,
+                              K_TSCAN0, K_SORT0, K_HIST1, K_TSCAN1, K_SORT1, K_HIST2, K_TSCAN2,
+                              K_SORT2, K_BOUNDS, K_SPREAD3, K_F3_X, K_F3_Y, K_F3_Z, K_F3_IY,
+                              K_F3_IX, K_GATHER3, K_ZSUM};
 static const int kChain1[] = {K_BOX, K_GEOM, K_SPEC0, K_SPEC1, K_KEY, K_TSCAN0, K_SORT0, K_HIST1,
                               K_TSCAN1, K_SORT1, K_HIST2, K_TSCAN2, K_SORT2, K_BOUNDS, K_SCAN_A,
                               K_SCAN_B, K_SPREAD, K_FIX, K_FFT_1D, K_GATHER, K_ZSUM};
 
+// The repulsion chain of an embedding dimension and its length.
+static const int* chain_of(int s, int& nk)
+{
+    if (s == 3) { nk = (int)(sizeof(kChain3) / sizeof(int)); return kChain3; }
+    if (s == 2) { nk = (int)(sizeof(kChain2) / sizeof(int)); return kChain2; }
+    nk = (int)(sizeof(kChain1) / sizeof(int));
+    return kChain1;
+}
+
 static tsne_status enqueue_repulsion(tsne_plan* pl, bool normalise)
 {
-    const int* ch = (pl->d.s == 2) ? kChain2 : kChain1;
-    const int nk = (pl->d.s == 2) ? (int)(sizeof(kChain2) / sizeof(int))
-                                  : (int)(sizeof(kChain1) / sizeof(int));
+    int nk;
+    const int* ch = chain_of(pl->d.s, nk);
     for (int k = 0; k < nk; ++k) {
         tsne_status s = enqueue(pl, ch[k]);
         if (s != TSNE_OK) return s;
@@ -527,6 +579,8 @@ static tsne_status plan_init(tsne_plan* pl, const tsne_desc* desc, const Derived
     h.twy = b + off[R_TWY];
     h.costab = reinterpret_cast<double*>(b + off[R_COS]);
     h.spec_tmp = reinterpret_cast<double*>(b + off[R_SPECTMP]);
+    h.twd = (desc->s == 3) ? b + off[R_TWY] : nullptr;
+    h.specd = (desc->s == 3) ? b + off[R_SPECTMP] : nullptr;
     h.ktab = reinterpret_cast<double*>(b + off[R_KTAB]);
     h.ccos = reinterpret_cast<double*>(b + off[R_CCOS]);
     h.R = b + off[R_R];
@@ -720,11 +774,13 @@ tsne_status tsne_bind_P(tsne_plan* pl, const int64_t* row_ptr, const int32_t* co
     return TSNE_OK;
 }
 
-// Per-point arrays are accessed one point at a time as a vector (s
-// elements), so each must be aligned to a whole point.
+// Per-point arrays are accessed one point at a time as a vector (s = 1, 2
+// elements), so each must be aligned to a whole point; for s = 3 to one
+// element.
 static bool point_aligned(const tsne_desc& d, const void* p)
 {
-    const uintptr_t a = (uintptr_t)d.s * ((d.dtype == TSNE_F32) ? 4 : 8);
+    // s = 3 points are moved one coordinate at a time: element alignment
+    const uintptr_t a = (uintptr_t)((d.s == 3) ? 1 : d.s) * ((d.dtype == TSNE_F32) ? 4 : 8);
     return p && ((uintptr_t)p % a) == 0;
 }
 
@@ -887,11 +943,12 @@ tsne_status tsne_query(tsne_plan* pl, tsne_stats* out)
     out->max_intervals = pl->d.max_intervals;
     out->origin[0] = g.origin[0];
     out->origin[1] = g.origin[1];
+    out->origin_z = g.origin[2];
     out->w_int = g.w;
     out->box_side = g.side;
     out->Z = g.Z;
-    out->n_int_y = (pl->d.s == 2) ? g.n_int_y : 1;
-    out->n_nodes_y = (pl->d.s == 2) ? g.n_y : 1;
+    out->n_int_y = (pl->d.s >= 2) ? g.n_int_y : 1;
+    out->n_nodes_y = (pl->d.s >= 2) ? g.n_y : 1;
     out->fft_len_y = (pl->d.s == 2) ? g.My : 0;
     return TSNE_OK;
 }
@@ -900,7 +957,8 @@ tsne_status tsne_debug_export(tsne_plan* pl, int32_t what, void* dst, size_t* by
 {
     if (!pl || !bytes) return TSNE_E_ARG;
     const Derived& o = pl->o;
-    const size_t grid = (pl->d.s == 2) ? (size_t)o.n_cap * o.n_cap : (size_t)o.n_cap;
+    const size_t grid = (pl->d.s == 3) ? (size_t)o.n_cap * o.n_cap * o.n_cap
+                      : (pl->d.s == 2) ? (size_t)o.n_cap * o.n_cap : (size_t)o.n_cap;
     const void* src;
     size_t nb;
     switch (what) {
@@ -1067,9 +1125,8 @@ static tsne_status batch_enqueue_tick(tsne_batch* b)
 {
     const int nl = (int)b->live.size();
     LaunchMap map{b->dtable, b->dprefix, nl};
-    const int* ch = (b->s == 2) ? kChain2 : kChain1;
-    const int nk = (b->s == 2) ? (int)(sizeof(kChain2) / sizeof(int))
-                               : (int)(sizeof(kChain1) / sizeof(int));
+    int nk;
+    const int* ch = chain_of(b->s, nk);
     for (int i = 0; i <= nk + 2; ++i) {
         const int k = (i < nk) ? ch[i] : (i == nk ? K_ATTR : (i == nk + 1 ? K_ATTR_T : K_UPDATE));
         if (b->launch[k].grid <= 0) continue;

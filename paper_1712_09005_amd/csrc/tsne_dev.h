@@ -20,6 +20,7 @@ constexpr int kMaxP = 6;         // Lagrange nodes per interval
 constexpr int kWave = 64;
 
 // Binning: stable least-significant-digit radix sort of the points by cell.
+constexpr int kBoxPart = 16;      // doubles per block of the box partials
 constexpr int kKeyTile = 2048;     // points per block of the key kernel (256 threads x 8)
 constexpr int kSortTile = 2048;    // points per tile of a sort pass (256 threads x 8)
 constexpr int kScanDigits = 64;    // digits per block of the tile-offset scan (a lane each)
@@ -33,7 +34,9 @@ enum Kind : int {
     K_ARGS = 0, K_BOX, K_KEY, K_SORT0, K_SORT1, K_SORT2, K_BOUNDS, K_SCAN_A, K_SCAN_B, K_SPREAD, K_FIX,
     K_FFT_ROWS, K_FFT_COLS, K_FFT_IROWS, K_FFT_1D, K_GATHER, K_NORM, K_ATTR,
     K_UPDATE, K_SPEC0, K_SPEC1, K_SPEC2, K_GEOM, K_ZSUM, K_ATTR_ALL, K_ASUM, K_ATTR_T, K_ATTR_T_ALL,
-    K_KL, K_KLSUM, K_KL_ATTR, K_HIST1, K_HIST2, K_TSCAN0, K_TSCAN1, K_TSCAN2, K_NKINDS
+    K_KL, K_KLSUM, K_KL_ATTR, K_HIST1, K_HIST2, K_TSCAN0, K_TSCAN1, K_TSCAN2,
+    K_F3_X, K_F3_Y, K_F3_Z, K_F3_IY, K_F3_IX, K_S3_FILL, K_S3_X, K_S3_Y, K_S3_Z, K_S3_STORE,
+    K_SPREAD3, K_GATHER3, K_NKINDS
 };
 
 // Status bits latched on the device (values of tsne_status).
@@ -41,9 +44,9 @@ enum : int { ST_OK = 0, ST_CAPACITY = 4, ST_NONFINITE = 5, ST_INTERNAL = 8 };
 
 // Geometry of the current iteration, written by the box kernel (double).
 struct Geom {
-    double origin[2];
-    double centre[2];
-    double mean[2];
+    double origin[3];
+    double centre[3];
+    double mean[3];
     double w;          // interval width
     double inv_w;
     double h;          // node spacing w / p
@@ -144,6 +147,8 @@ struct Inst {
                            // half^2; s = 1: [2][half]; pre-scaled
     void* tw;              // [M] stage twiddle tables of this iteration's M (complex)
     void* twy;             // [M] the same for the second axis' length My
+    void* twd;             // s = 3: [M] the stage twiddles in double (kernel spectra)
+    void* specd;           // s = 3: [2][M^3] complex double, the kernel grids' transforms
     double* costab;        // [2][M] cos and sin(2 pi k / M) in double (s = 1)
     // s = 2 tables, each in a [half][half] slot of the capacity's half:
     double* spec_tmp;      // [K][..] first transform pass (double)

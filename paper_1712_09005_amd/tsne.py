@@ -59,7 +59,7 @@ class Stats(ctypes.Structure):
                 ("max_intervals", ctypes.c_int32), ("origin", ctypes.c_double * 2),
                 ("w_int", ctypes.c_double), ("box_side", ctypes.c_double), ("Z", ctypes.c_double),
                 ("n_int_y", ctypes.c_int32), ("n_nodes_y", ctypes.c_int32),
-                ("fft_len_y", ctypes.c_int32)]
+                ("fft_len_y", ctypes.c_int32), ("origin_z", ctypes.c_double)]
 
 
 @dataclass
@@ -295,7 +295,7 @@ class Plan:
                     iter=st.iter, max_intervals=st.max_intervals,
                     origin=(st.origin[0], st.origin[1]), w_int=st.w_int,
                     box_side=st.box_side, Z=st.Z, n_int_y=st.n_int_y, n_nodes_y=st.n_nodes_y,
-                    fft_len_y=st.fft_len_y)
+                    fft_len_y=st.fft_len_y, origin_z=st.origin_z)
 
     def export(self, what: int):
         """Internal array of the last iteration as a flat host buffer (bytes)."""

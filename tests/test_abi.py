@@ -44,7 +44,7 @@ def test_workspace_bytes_and_argument_checks(L):
     nb = tsne.workspace_bytes(d)
     assert 100 << 20 < nb < 4 << 30
     # invalid descriptors: zero bytes
-    for kw in (dict(n=1, s=2), dict(n=100, s=3), dict(n=100, s=2, p=9),
+    for kw in (dict(n=1, s=2), dict(n=100, s=4), dict(n=100, s=2, p=9),
                dict(n=100, s=2, max_intervals=0)):
         n = kw.pop("n")
         s = kw.pop("s")
@@ -104,7 +104,7 @@ def test_static_repulsion_argument_checks(L):
     from paper_1712_09005_amd import tsne
     z = ctypes.c_void_p(4096)
     assert L.tsne_repulsive_static(None, z, z, None, None) == 1
-    assert L.tsne_repulsive_static(ctypes.byref(tsne.make_desc(100, 3)), z, z, None, None) == 1
+    assert L.tsne_repulsive_static(ctypes.byref(tsne.make_desc(100, 4)), z, z, None, None) == 1
     assert L.tsne_repulsive_static(ctypes.byref(tsne.make_desc(100, 2, p=9)), z, z, None, None) == 2
     # a plan larger than the scratch array is refused with TSNE_E_WORKSPACE
     big = tsne.make_desc(1_000_000, 2, p=5, max_intervals=512)
