@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (vector and matrix)
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_attr_traffic_n1e6_2d.txt")
 ATTR_SOURCES = [os.path.join(ROOT, "paper_1712_09005_amd", "csrc", f)
-                for f in ("k_attr.hip", "tsne_dev.h", "launch.h")]
+                for f in ("k_attr.hip", "k_common.h", "tsne_dev.h", "launch.h")]
 
 
 def measured_traffic(knobs):

@@ -329,11 +329,10 @@ __global__ __launch_bounds__(256) void k_spread(LaunchMap map)
             for (int q = 0; q < NC; ++q) acc[k][q] = (T)0;
         int fi = 0, li = 0;                // the cell's first and one-past-last item
         if (valid) {
-            const int2 it = I.item_info[t];
-            c = it.x;
-            const int b = it.y;
+            c = I.item_cell[t];
             fi = I.item_start[c];
             li = I.item_start[c + 1];
+            const int b = I.cell_start[c] + (t - fi) * I.kpts;
             const int e = min(b + I.kpts, I.cell_start[c + 1]);
             const T* sY = static_cast<const T*>(I.sY);
             const double w = G.w, qs = G.qscale;
@@ -573,8 +572,8 @@ __global__ __launch_bounds__(256) void k_gather(LaunchMap map)
         double h1d = 0.0;
         if (t < total) {
             const int n_int = G.n_int, n_cap = I.n_cap;
-            const int2 it = I.item_info[t];
-            const int c = it.x, b = it.y;
+            const int c = I.item_cell[t];
+            const int b = I.cell_start[c] + (t - I.item_start[c]) * I.kpts;
             const int e = min(b + I.kpts, I.cell_start[c + 1]);
             const int cx = c % n_int, cy = (S == 2) ? c / n_int : 0;
             const T* sY = static_cast<const T*>(I.sY);

@@ -25,8 +25,8 @@
 //               point indices, their cells and the sorted positions;
 //   k_bounds    first sorted position of every cell;
 //   k_scan_a/b  items (runs of at most kpts points of one cell) per cell and
-//               each item's cell and first sorted position, used by the
-//               spreading and interpolation kernels.
+//               the item -> cell table used by the spreading and
+//               interpolation kernels.
 #include "k_common.h"
 
 namespace tsne {
@@ -451,7 +451,7 @@ __global__ __launch_bounds__(256) void k_scan_b(LaunchMap map)
     __shared__ int sh[4];
     __shared__ int off;
     __shared__ int nbig;
-    __shared__ int big[1024][4];         // (cell, first item, items, first position)
+    __shared__ int big[1024][3];         // (cell, first item, items)
     VB_BEGIN(map, K_SCAN_B)
     if (live(I)) {
         const int ncell = I.geom->n_cells;
@@ -471,12 +471,11 @@ __global__ __launch_bounds__(256) void k_scan_b(LaunchMap map)
             }
             __syncthreads();
             const int base = lb * 1024 + threadIdx.x * 4;
-            int iv[4], c0[4], it = 0;
+            int iv[4], it = 0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const int e = base + k;
-                c0[k] = (e < ncell) ? I.cell_start[e] : 0;
-                iv[k] = (e < ncell) ? items_of(I.cell_start[e + 1] - c0[k], I.kpts) : 0;
+                iv[k] = (e < ncell) ? items_of(I.cell_start[e + 1] - I.cell_start[e], I.kpts) : 0;
                 it += iv[k];
             }
             const int ii = wave_incl_scan(it);
@@ -492,13 +491,12 @@ __global__ __launch_bounds__(256) void k_scan_b(LaunchMap map)
                 if (e < ncell) {
                     I.item_start[e] = pi;
                     if (iv[k] <= kSerialItems) {
-                        for (int q = 0; q < iv[k]; ++q) I.item_info[pi + q] = make_int2(e, c0[k] + q * I.kpts);
+                        for (int q = 0; q < iv[k]; ++q) I.item_cell[pi + q] = e;
                     } else {
                         const int b = atomicAdd(&nbig, 1);   // at most one per cell of the tile
                         big[b][0] = e;
                         big[b][1] = pi;
                         big[b][2] = iv[k];
-                        big[b][3] = c0[k];
                     }
                     if (e == ncell - 1) I.item_start[ncell] = pi + iv[k];
                 }
@@ -506,11 +504,11 @@ __global__ __launch_bounds__(256) void k_scan_b(LaunchMap map)
             }
             // cells with many items (a small box holding many points): the
             // block's four waves take them in turn, each wave's lanes writing
-            // one cell's item entries
+            // one cell's item -> cell entries
             __syncthreads();
             for (int b = wv; b < nbig; b += 4) {
-                const int e = big[b][0], p0 = big[b][1], m = big[b][2], f0 = big[b][3];
-                for (int q = lane; q < m; q += 64) I.item_info[p0 + q] = make_int2(e, f0 + q * I.kpts);
+                const int e = big[b][0], p0 = big[b][1], m = big[b][2];
+                for (int q = lane; q < m; q += 64) I.item_cell[p0 + q] = e;
             }
             __syncthreads();
         }

@@ -293,7 +293,7 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     sz[R_CSTART] = sizeof(int) * (o.ncell_cap + 1);
     sz[R_ISTART] = sizeof(int) * (o.ncell_cap + 1);
     sz[R_SCAN] = sizeof(int) * o.nb_scan;
-    sz[R_ICELL] = 2 * sizeof(int) * o.items_cap;
+    sz[R_ICELL] = sizeof(int) * o.items_cap;
     sz[R_KEY] = sizeof(int) * n;
     sz[R_KV] = (o.npass > 1) ? sizeof(uint32_t) * 2 * 2 * (size_t)n : 0;
     sz[R_SKEY] = sizeof(uint32_t) * n;
@@ -556,7 +556,7 @@ static tsne_status plan_init(tsne_plan* pl, const tsne_desc* desc, const Derived
     h.cell_start = reinterpret_cast<int*>(b + off[R_CSTART]);
     h.item_start = reinterpret_cast<int*>(b + off[R_ISTART]);
     h.scan_part = reinterpret_cast<int*>(b + off[R_SCAN]);
-    h.item_info = reinterpret_cast<int2*>(b + off[R_ICELL]);
+    h.item_cell = reinterpret_cast<int*>(b + off[R_ICELL]);
     h.key = reinterpret_cast<int*>(b + off[R_KEY]);
     h.kv = b + off[R_KV];
     h.skey = reinterpret_cast<unsigned*>(b + off[R_SKEY]);

@@ -127,7 +127,7 @@ struct Inst {
     int* cell_start;       // [ncell_cap + 1]
     int* item_start;       // [ncell_cap + 1]
     int* scan_part;        // [2 * nb_scan] tile sums
-    int2* item_info;       // [items_cap] (cell, first sorted position) of each item
+    int* item_cell;        // [items_cap] cell of each item
     int* key;              // [n] cell of each point (point order)
     void* kv;              // [2][n] (cell, point) pairs between radix passes (uint2)
     unsigned* skey;        // [n] cell of each sorted position
