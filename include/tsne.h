@@ -116,9 +116,13 @@ typedef struct {
     int32_t attr_slabs;      /* CSR layout: column slabs of P, 0 (auto), 1, 2, 4 or 8;
                                 each slab is handled by 8/slabs of the 8 XCDs */
     int32_t attr_layout;     /* attraction: 0 auto, 1 CSR rows (lanes per row over
-                                the bound CSR), 2 tiles (P re-bucketed at bind time
-                                into row-block x column-block tiles, positions of
-                                both blocks staged in LDS) */
+                                the bound CSR), 2 row blocks (P re-bucketed at bind
+                                time by row block and 32 KB column window; each
+                                workgroup keeps its rows in LDS and sweeps the
+                                windows its non-zeros touch, staged in LDS; row
+                                sums in 64-bit fixed point, so the result does not
+                                depend on timing).  Layout 2 needs s <= 2; binding
+                                P then also rejects non-finite values (TSNE_E_ARG) */
     int32_t rect;            /* box shape (s = 2): 0 the square box of Section 2.4;
                                 1 a rectangle of equal spacing: the widest axis
                                 keeps the policy's N_int and w, a narrower axis d
@@ -196,8 +200,12 @@ tsne_status tsne_plan_destroy(tsne_plan* plan);
  * per-row slab split table in the workspace, and for FP32 plans with the CSR
  * layout copies (column, value) pairs into the workspace (enqueued on the
  * plan's stream): the attraction and the divergence then read the copy, so
- * a change to P's values takes effect at the next bind.  The arrays stay
- * borrowed (the tiled layout and FP64 plans read them directly). */
+ * a change to P's values takes effect at the next bind.  With attr_layout 2
+ * the values must be finite (TSNE_E_ARG otherwise) and are copied, re-bucketed
+ * by row block and column window, with the sweep steps and the fixed-point
+ * scale of the row sums (2^61 over the largest row sum of |p|, rounded down
+ * to a power of two).  The arrays stay borrowed (the divergence of the tiled
+ * layout and FP64 plans read them directly). */
 tsne_status tsne_bind_P(tsne_plan* plan, const int64_t* row_ptr,
                         const int32_t* col, const void* val);
 

@@ -35,9 +35,10 @@ from . import tsne
 WIDTHS = (1.6, 1.5, 1.4, 1.3, 1.2, 1.1, 1.0, 0.95, 0.9, 0.85, 0.8, 0.75, 0.7, 0.65, 0.6,
           0.55, 0.5, 0.45, 0.4, 0.35, 0.3, 0.25, 0.2)
 PS = (3, 4, 5, 6)
-# CSR rows only: the LDS-tiled layout sums rows with LDS float atomics, so its
-# results depend on timing, and it never won (it stays available explicitly)
-CSR_KNOBS = [(lpr, sl, 1) for lpr in (4, 8, 16, 32, 64) for sl in (1, 2, 4, 8)]
+# CSR rows at every lanes-per-row and slab count, and the row-block sweep over
+# LDS column windows (layout 2, whose 64-bit fixed-point row sums give the same
+# bits in any order; lanes and slabs do not apply to it)
+CSR_KNOBS = [(lpr, sl, 1) for lpr in (4, 8, 16, 32, 64) for sl in (1, 2, 4, 8)] + [(0, 0, 2)]
 KPTS = (4, 8, 16)
 
 

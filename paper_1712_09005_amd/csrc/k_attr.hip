@@ -1,6 +1,6 @@
 // Sparse-P kernels on gfx950: the attraction of Section 3 (CSR rows, with
-// optional XCD-aware column slabs, or LDS tiles) and the Kullback-Leibler
-// divergence of Section 1.1.
+// optional XCD-aware column slabs, or row blocks sweeping LDS column windows)
+// and the Kullback-Leibler divergence of Section 1.1.
 //
 // Every kernel walks the virtual blocks of its kind over all instances of the
 // launch (VB_BEGIN/VB_END), so one launch serves a single plan or a batch.
@@ -249,117 +249,170 @@ __global__ __launch_bounds__(256) void k_attr3(LaunchMap map)
     }
 }
 
-// Attraction over tiles of P: edges re-bucketed (at bind time) by row block of
-// tile_bi rows and column block of tile_bj columns, rows increasing within a
-// tile.  One 1024-thread workgroup per row block keeps that block's positions
-// and force sums in LDS and sweeps the column blocks in order.  The sweep is
-// software-pipelined two steps deep: the positions of column block J+2 and
-// the first edges of tile J+2 are requested while tile J is processed from LDS,
-// and block J+1 (requested a step earlier) is stored to the other half of a
-// double-buffered LDS area at the end of the step; each step costs one
-// barrier.  Every neighbour position comes from LDS instead of a random global
-// gather; per-row sums use LDS atomics in the element type.
+// Barrier for hand-offs through LDS only: each wave waits for its own LDS
+// accesses, not for its global loads, so prefetches stay in flight across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Attraction by row blocks (the sum over the non-zeros of P of Section 3,
+// arranged for LDS): each virtual block takes tile_bi rows, keeps their
+// positions and force sums in LDS and sweeps the column windows (tile_bj
+// points, 32 KB) that hold its non-zeros, in the sweep steps fixed at bind
+// time (one step: at most kTileStepEdges non-zeros of one window, rows
+// increasing).  Windows are double-buffered: step t takes its non-zeros
+// against buffer t mod 2 while the window and non-zeros of step t + 1 are in
+// flight, then stores that window into the other buffer; one LDS-only
+// barrier per step.  Every neighbour position is thus an LDS read instead of
+// a random L2 gather, the cost that bounds the CSR rows on a graph with no
+// locality.  Row sums are 64-bit fixed point (scale tscale, a power of two
+// chosen at bind time so that no row sum can overflow) added with LDS integer
+// atomics: integer addition commutes, so the result has the same bits in
+// whatever order the atomics land.  All loads are unconditional, at clamped
+// addresses (slots past a step's non-zeros carry weight zero), so the
+// compiler's wait counts leave the prefetches outstanding.
+// Global-memory view of a pointer taken from the instance record: loads
+// through it are vector-memory only (a generic pointer gives flat loads,
+// which every LDS wait also waits for).
+#define TSNE_GLOBAL __attribute__((address_space(1)))
+template <typename P> __device__ __forceinline__ const TSNE_GLOBAL P* gview(const void* p)
+{
+    return (const TSNE_GLOBAL P*)p;
+}
+// Constant-memory view of read-only data indexed uniformly across the block
+// (scalar loads, which the vector-memory waits do not drain).
+#define TSNE_CONST __attribute__((address_space(4)))
+template <typename P> __device__ __forceinline__ const TSNE_CONST P* cview(const void* p)
+{
+    return (const TSNE_CONST P*)p;
+}
+
+// One point of an [n][S] array through the global view, as one vector load
+// (a native vector type: the HIP vector structs cannot be copied out of a
+// qualified address space).
+template <typename T, int S> struct NativeVec { typedef T t; };
+template <> struct NativeVec<float, 2> { typedef float t __attribute__((ext_vector_type(2))); };
+template <> struct NativeVec<double, 2> { typedef double t __attribute__((ext_vector_type(2))); };
 template <typename T, int S>
-struct TileEdges {
-    static constexpr int UE = 4;   // edges per thread carried between steps
-    uint32_t k[UE];
-    T v[UE];
-};
+__device__ __forceinline__ typename Vec<T, S>::t gpoint(const void* base, int64_t i)
+{
+    typedef typename NativeVec<T, S>::t N;
+    const N q = gview<N>(base)[i];
+    if constexpr (S == 2) {
+        typename Vec<T, S>::t v;
+        v.x = q.x;
+        v.y = q.y;
+        return v;
+    } else {
+        return q;
+    }
+}
 
 template <typename T, int S, bool GATED>
 __global__ __launch_bounds__(1024) void k_attr_tile(LaunchMap map)
 {
     typedef typename Vec<T, S>::t V;
-    constexpr int NT = 1024;       // threads (the launch uses exactly this)
-    constexpr int UE = TileEdges<T, S>::UE;
-    constexpr int PJ = 4;          // positions per thread per column block (tile_bj <= 4096)
-    constexpr uint32_t kNone = 0xffffffffu;
+    constexpr int NT = 1024;
+    constexpr int UE = kTileStepEdges / NT;                             // non-zeros per thread and step
+    constexpr int WQ = kTileWindowBytes / (S * (int)sizeof(T)) / NT;     // window points per thread
     extern __shared__ __align__(16) char smem[];
     VB_BEGIN_IF(map, GATED ? K_ATTR_T : K_ATTR_T_ALL, (!GATED || live(I)))
     {
-        const int BI = I.tile_bi, BJ = I.tile_bj, nj = I.tile_nj;
-        const int64_t n = I.n;
+        // the record's fields through a constant view: scalar loads, kept in
+        // scalar registers (a vector copy of a base pointer would make the
+        // compiler wait for in-flight loads whenever it reuses registers)
+        const TSNE_CONST Inst& R = *cview<Inst>(&I);
+        const int BI = R.tile_bi, BJ = R.tile_bj;   // BJ = WQ NT
+        const int n = (int)R.n;
         const int tid = (int)threadIdx.x;
-        V* yI = reinterpret_cast<V*>(smem);
-        T* f = reinterpret_cast<T*>(yI + BI);
-        V* yJbuf = reinterpret_cast<V*>(f + (int64_t)BI * S);
-        const V* Y = static_cast<const V*>(I.Yin);
-        V zero;
-        if constexpr (S == 2) zero = V{(T)0, (T)0}; else zero = (T)0;
+        unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem);   // [BI][S]
+        V* yI = reinterpret_cast<V*>(acc + (size_t)BI * S);
+        V* win = yI + BI;                                                        // [2][BJ]
+        const void* Y = R.Yin;
+        const TSNE_GLOBAL uint32_t* ep = gview<uint32_t>(R.epack);
+        const TSNE_GLOBAL T* ev = gview<T>(R.eval);
+        const TSNE_CONST int* tsj = cview<int>(R.tsj);           // uniform: scalar loads
+        const TSNE_CONST int64_t* tse = cview<int64_t>(R.tse);
+        const double scale = R.tscale;
         const int i0 = lb * BI;
-        const int rows = (int)min((int64_t)BI, n - i0);
         for (int r = tid; r < BI; r += NT) {
-            yI[r] = (r < rows) ? Y[i0 + r] : zero;
 #pragma unroll
-            for (int d = 0; d < S; ++d) f[r * S + d] = (T)0;
+            for (int d = 0; d < S; ++d) acc[r * S + d] = 0ull;
+            yI[r] = gpoint<T, S>(Y, min(i0 + r, n - 1));   // rows past n: never referenced
         }
-        const int64_t* to = I.toff + (int64_t)lb * nj;
-        const uint32_t* ep = I.epack;
-        const T* ev = static_cast<const T*>(I.eval);
-        auto load_pos = [&](int J, V (&pos)[PJ]) {
-            const int64_t j0 = (int64_t)J * BJ;
+        const int s0 = cview<int>(R.tsb)[lb], s1 = cview<int>(R.tsb)[lb + 1];
+        const int64_t elast = R.nnz - 1;
+        V wA[WQ];
+        auto wload = [&](int J) {
 #pragma unroll
-            for (int q = 0; q < PJ; ++q) {
-                const int c = tid + q * NT;
-                pos[q] = (c < BJ && j0 + c < n) ? Y[j0 + c] : zero;
-            }
+            for (int q = 0; q < WQ; ++q) wA[q] = gpoint<T, S>(Y, min(J * BJ + tid + q * NT, n - 1));
         };
-        auto store_pos = [&](int J, const V (&pos)[PJ]) {
-            V* b = yJbuf + (J & 1) * BJ;
+        auto wstore = [&](int buf) {
 #pragma unroll
-            for (int q = 0; q < PJ; ++q) {
-                const int c = tid + q * NT;
-                if (c < BJ) b[c] = pos[q];
-            }
+            for (int q = 0; q < WQ; ++q) win[buf * BJ + tid + q * NT] = wA[q];
         };
-        auto load_edges = [&](int J, TileEdges<T, S>& e) {
-            const int64_t e0 = to[J], e1 = to[J + 1];
+        // a slot past the step's non-zeros loads the last non-zero and gets
+        // mask 0 (applied where the value is used, so the load stays in flight)
+        auto eload = [&](int st, uint32_t (&k)[UE], T (&v)[UE], T (&m)[UE]) {
+            const int64_t e0 = tse[st], e1 = tse[st + 1];
 #pragma unroll
             for (int u = 0; u < UE; ++u) {
-                const int64_t k = e0 + tid + (int64_t)u * NT;
-                e.k[u] = (k < e1) ? ep[k] : kNone;
-                e.v[u] = (k < e1) ? ev[k] : (T)0;
+                const int64_t e = e0 + tid + (int64_t)u * NT;
+                const int64_t ec = min(e, elast);
+                k[u] = ep[ec];
+                v[u] = ev[ec];
+                m[u] = (e < e1) ? (T)1 : (T)0;
             }
         };
-        auto edge = [&](uint32_t pk, T pv, const V* yJ) {
-            const int il = (int)(pk >> 16), jl = (int)(pk & 0xffffu);
-            const V a = yI[il], b = yJ[jl];
+        auto fx = [&](T c) -> unsigned long long {
+            return (unsigned long long)__double2ll_rn((double)c * scale);
+        };
+        auto edge = [&](uint32_t key, T pv, T m, const V* w) {
+            const int lr = (int)(key >> 16), lc = (int)(key & 0xffffu);
+            const V a = yI[lr], b = w[lc];
             T d0, d1 = (T)0;
             if constexpr (S == 2) { d0 = a.x - b.x; d1 = a.y - b.y; }
             else { d0 = a - b; }
-            const T wgt = pv * recip((T)1 + d0 * d0 + d1 * d1);
-            atomicAdd(&f[il * S], wgt * d0);
-            if (S == 2) atomicAdd(&f[il * S + 1], wgt * d1);
+            const T wgt = (pv * m) * recip((T)1 + d0 * d0 + d1 * d1);
+            const T c0 = wgt * d0, c1 = wgt * d1;
+            if (c0 != (T)0 || c1 != (T)0) {
+                atomicAdd(&acc[lr * S], fx(c0));
+                if (S == 2) atomicAdd(&acc[lr * S + 1], fx(c1));
+            }
         };
-        V posA[PJ], posB[PJ];
-        TileEdges<T, S> eA, eB, cur;
-        // prologue: block 0 staged; block 1 and the edges of tiles 0 and 1 requested
-        load_pos(0, posA);
-        store_pos(0, posA);
-        if (nj > 1) load_pos(1, posA);
-        load_edges(0, eA);
-        if (nj > 1) load_edges(1, eB);
-        for (int J = 0; J < nj; ++J) {
-            __syncthreads();   // block J staged, yI / f ready, the other buffer free
-            if (J + 2 < nj) load_pos(J + 2, posB);
-            cur = eA;
-            eA = eB;
-            if (J + 2 < nj) load_edges(J + 2, eB);
-            const V* yJ = yJbuf + (J & 1) * BJ;
+        uint32_t kA[UE], kB[UE];
+        T vA[UE], vB[UE], mA[UE], mB[UE];
+        // one step: request the next step's window and non-zeros, take this
+        // step's non-zeros, store the next window, barrier
+        auto step = [&](int st, const uint32_t (&kc)[UE], const T (&vc)[UE], const T (&mc)[UE],
+                        uint32_t (&kn)[UE], T (&vn)[UE], T (&mn)[UE]) {
+            const V* w = win + ((st - s0) & 1) * BJ;
+            const int sn = min(st + 1, s1 - 1);
+            wload(tsj[sn]);
+            eload(sn, kn, vn, mn);
 #pragma unroll
-            for (int u = 0; u < UE; ++u)
-                if (cur.k[u] != kNone) edge(cur.k[u], cur.v[u], yJ);
-            // a tile with more than NT * UE edges: the rest directly
-            const int64_t e1 = to[J + 1];
-            for (int64_t k = to[J] + (int64_t)NT * UE + tid; k < e1; k += NT) edge(ep[k], ev[k], yJ);
-            if (J + 1 < nj) store_pos(J + 1, posA);
-#pragma unroll
-            for (int q = 0; q < PJ; ++q) posA[q] = posB[q];
+            for (int u = 0; u < UE; ++u) edge(kc[u], vc[u], mc[u], w);
+            wstore((st + 1 - s0) & 1);
+            lds_barrier();
+        };
+        if (s1 > s0) {
+            wload(tsj[s0]);
+            wstore(0);
+            eload(s0, kA, vA, mA);
         }
-        __syncthreads();
-        T* F = static_cast<T*>(I.Fattr);
-        for (int r = tid; r < rows * S; r += NT) F[(int64_t)i0 * S + r] = f[r];
-        __syncthreads();
+        lds_barrier();
+        for (int st = s0; st < s1; st += 2) {
+            step(st, kA, vA, mA, kB, vB, mB);
+            if (st + 1 < s1) step(st + 1, kB, vB, mB, kA, vA, mA);
+        }
+        TSNE_GLOBAL T* F = (TSNE_GLOBAL T*)R.Fattr;
+        const int rows = min(BI, n - i0);
+        for (int r = tid; r < rows * S; r += NT)
+            F[(int64_t)i0 * S + r] = (T)((double)(long long)acc[r] / scale);
+        __syncthreads();   // the LDS is reused by the next virtual block
     }
     VB_END
 }

@@ -32,6 +32,7 @@ __global__ void k_set_args(Inst* inst, CallArgs a)
         inst->row_ptr = a.row_ptr;
         inst->col = a.col;
         inst->val = a.val;
+        inst->tscale = a.tscale;
     }
     if (a.set_sched) *inst->sched = a.sched;
     if (a.set_iter) *inst->iter = a.iter;

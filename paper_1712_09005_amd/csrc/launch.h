@@ -29,8 +29,9 @@ struct CallArgs {
     const int64_t* row_ptr;
     const int32_t* col;
     const void* val;
+    double tscale;  // fixed-point scale of the tiled attraction's row sums
     int set_ptrs;   // copy the pointer fields
-    int set_P;      // copy row_ptr/col/val
+    int set_P;      // copy row_ptr/col/val and tscale
     int set_iter;   // write *iter = iter
     int iter;
     int set_end;    // write iter_end

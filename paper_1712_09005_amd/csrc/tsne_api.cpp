@@ -67,16 +67,17 @@ int pow2_at_least(int x)
 }
 
 struct Layout {
-    size_t off[40];
+    size_t off[48];
     size_t total;
 };
 
 enum Region {
     R_INST, R_PREFIX, R_GEOM, R_SCHED, R_SMALL, R_BOX, R_CSTART, R_ISTART, R_SCAN,
     R_ICELL, R_KEY, R_KV, R_SKEY, R_TCNT, R_GTOT, R_PERM, R_SY, R_CARRY, R_W, R_X, R_XC, R_V, R_SPEC,
-    R_TW, R_TWY, R_COS, R_CV, R_SPECTMP, R_KTAB, R_CCOS, R_R, R_FA, R_FAP, R_SPLIT, R_TOFF, R_EPACK,
-    R_EVAL, R_ZPART, R_KLPART, R_H1, R_N
+    R_TW, R_TWY, R_COS, R_CV, R_SPECTMP, R_KTAB, R_CCOS, R_R, R_FA, R_FAP, R_SPLIT, R_TSE, R_TSJ,
+    R_TSB, R_EPACK, R_EVAL, R_ZPART, R_KLPART, R_H1, R_N
 };
+static_assert(R_N <= 48, "workspace regions exceed the layout table");
 
 struct Derived {
     int s, p, nc, np, tsz, max_int, n_cap, M, half, ncell_cap, items_cap, kpts, lpr;
@@ -84,6 +85,7 @@ struct Derived {
     int nstages, radix[kMaxStages], rmin;
     int slabs, slab_w;
     int tiled, tile_bi, tile_bj, tile_ni, tile_nj;
+    int64_t tile_steps;   // capacity of the sweep step list
     size_t tile_lds;
     int tile_w, ntiles, col_group;
     int nb_box, nb_gather, nb_scan, nwaves, nb_kl;
@@ -166,19 +168,24 @@ tsne_status derive(const tsne_desc* d, Derived& o)
         o.slabs = sl;
         o.slab_w = (int)((d->n + sl - 1) / sl);
     }
-    // attraction layout: CSR rows unless tiles are asked for.  Tiles: square
-    // blocks of 4096 (FP32) or 2048 (FP64) points; LDS holds the row block's
-    // positions and sums and two column blocks (128 KB in 2-D); the kernel
-    // stages at most 4 positions per thread per column block (4096 / 1024).
+    // attraction layout: CSR rows unless tiles are asked for.  Tiles: each
+    // workgroup takes a block of tile_bi rows (their positions and 64-bit
+    // fixed-point force sums in LDS) and sweeps column windows of 32 KB
+    // (tile_bj points), double-buffered in LDS; the LDS then holds
+    // tile_bi s (8 + element) + 64 KB bytes (157 KB for FP32 in 2-D).
+    // Sweep steps are the non-empty (row block, window) tiles, a tile with
+    // more than kTileStepEdges edges taking several steps.
     o.tiled = (d->nnz > 0) && d->attr_layout == 2;
-    o.tile_bi = (d->dtype == TSNE_F32) ? 4096 : 2048;
-    o.tile_bj = o.tile_bi;
-    o.tile_ni = (int)((d->n + o.tile_bi - 1) / o.tile_bi);
-    o.tile_nj = (int)((d->n + o.tile_bj - 1) / o.tile_bj);
     {
-        const size_t tsz_ = (d->dtype == TSNE_F32) ? 4 : 8;
-        o.tile_lds = (size_t)(2 * o.tile_bi + 2 * o.tile_bj) * d->s * tsz_;
+        const int tsz_ = (d->dtype == TSNE_F32) ? 4 : 8;
+        o.tile_bi = (d->dtype == TSNE_F32) ? 3968 : 1984;
+        o.tile_bj = kTileWindowBytes / (d->s * tsz_);
+        o.tile_ni = (int)((d->n + o.tile_bi - 1) / o.tile_bi);
+        o.tile_nj = (int)((d->n + o.tile_bj - 1) / o.tile_bj);
+        o.tile_lds = (size_t)o.tile_bi * d->s * (8 + tsz_) + 2 * (size_t)kTileWindowBytes;
+        o.tile_steps = (int64_t)o.tile_ni * o.tile_nj + (d->nnz + kTileStepEdges - 1) / kTileStepEdges;
     }
+    if (o.tiled && o.tile_steps > ((int64_t)1 << 30)) return TSNE_E_UNSUPPORTED;   // int step indices
     if (o.tiled) o.slabs = 1;
     const int64_t n = d->n;
     o.items_cap = cdiv(n, o.kpts) + (int)std::min<int64_t>(n, o.ncell_cap);
@@ -340,7 +347,9 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     sz[R_FA] = (size_t)o.tsz * n * d->s;
     sz[R_FAP] = (o.slabs > 1) ? (size_t)o.tsz * n * d->s * o.slabs : 0;
     sz[R_SPLIT] = (o.slabs > 1) ? sizeof(int) * (size_t)(o.slabs - 1) * n : 0;
-    sz[R_TOFF] = o.tiled ? sizeof(int64_t) * ((size_t)o.tile_ni * o.tile_nj + 1) : 0;
+    sz[R_TSE] = o.tiled ? sizeof(int64_t) * ((size_t)o.tile_steps + 1) : 0;
+    sz[R_TSJ] = o.tiled ? sizeof(int) * (size_t)o.tile_steps : 0;
+    sz[R_TSB] = o.tiled ? sizeof(int) * ((size_t)o.tile_ni + 1) : 0;
     // FP32 CSR rows: column and value of each non-zero packed into 8 bytes, so
     // the attraction streams one vector load per non-zero instead of two
     // (one spare pair: the kernel reads pairs two at a time, 16-byte aligned)
@@ -420,6 +429,7 @@ struct tsne_plan {
     hipGraph_t graph;
     bool args_valid;        // last_args mirrors the device record's pointers
     CallArgs last_args;
+    double tscale;          // fixed-point scale of the tiled attraction (set with P)
 };
 
 // Enqueue the per-call pointer update unless the device record already holds
@@ -598,7 +608,10 @@ static tsne_status plan_init(tsne_plan* pl, const tsne_desc* desc, const Derived
     h.tile_bj = o.tile_bj;
     h.tile_ni = o.tile_ni;
     h.tile_nj = o.tile_nj;
-    h.toff = reinterpret_cast<const int64_t*>(b + off[R_TOFF]);
+    h.tse = reinterpret_cast<const int64_t*>(b + off[R_TSE]);
+    h.tsj = reinterpret_cast<const int*>(b + off[R_TSJ]);
+    h.tsb = reinterpret_cast<const int*>(b + off[R_TSB]);
+    h.tscale = 0.0;
     h.cv = (off[R_CV + 1] > off[R_CV]) ? (const void*)(b + off[R_CV]) : nullptr;
     h.epack = reinterpret_cast<const uint32_t*>(b + off[R_EPACK]);
     h.eval = b + off[R_EVAL];
@@ -719,39 +732,73 @@ tsne_status tsne_bind_P(tsne_plan* pl, const int64_t* row_ptr, const int32_t* co
                                   split.size() * sizeof(int), hipMemcpyHostToDevice)))
                 return TSNE_E_HIP;
         }
-        // tiles: edges bucketed by (row block, column block), rows increasing
+        // tiles: edges bucketed by (row block, column window), rows increasing
+        // within a tile; the sweep steps of each row block are its non-empty
+        // tiles in window order, split into runs of at most kTileStepEdges
         if (pl->o.tiled) {
             const Derived& o = pl->o;
             const int64_t nnz = pl->d.nnz;
             const size_t tsz = (size_t)o.tsz;
             std::vector<char> vv(nnz * tsz), vt(nnz * tsz);
             if (!hip_ok(hipMemcpy(vv.data(), val, nnz * tsz, hipMemcpyDeviceToHost))) return TSNE_E_HIP;
-            std::vector<int64_t> toff((size_t)o.tile_ni * o.tile_nj + 1, 0);
+            std::vector<int64_t> tse;
+            std::vector<int> tsj, tsb(o.tile_ni + 1, 0);
+            tse.reserve((size_t)o.tile_steps + 1);
+            tsj.reserve((size_t)o.tile_steps);
             std::vector<uint32_t> pack(nnz);
             std::vector<int64_t> cnt(o.tile_nj);
             int64_t cur = 0;
+            double rmax = 0.0;   // largest sum of |p| over a row
             for (int I = 0; I < o.tile_ni; ++I) {
                 const int64_t r0 = (int64_t)I * o.tile_bi, r1 = std::min<int64_t>(n, r0 + o.tile_bi);
                 std::fill(cnt.begin(), cnt.end(), 0);
                 for (int64_t i = r0; i < r1; ++i)
                     for (int64_t k = rp[i]; k < rp[i + 1]; ++k) ++cnt[cc[k] / o.tile_bj];
+                tsb[I] = (int)tsj.size();
                 for (int J = 0; J < o.tile_nj; ++J) {
-                    toff[(size_t)I * o.tile_nj + J] = cur;
                     const int64_t c = cnt[J];
+                    for (int64_t q = 0; q < c; q += kTileStepEdges) {
+                        tsj.push_back(J);
+                        tse.push_back(cur + q);
+                    }
                     cnt[J] = cur;
                     cur += c;
                 }
-                for (int64_t i = r0; i < r1; ++i)
+                for (int64_t i = r0; i < r1; ++i) {
+                    double ra = 0.0;
                     for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
                         const int J = cc[k] / o.tile_bj;
                         const int64_t dst = cnt[J]++;
                         pack[dst] = ((uint32_t)(i - r0) << 16) | (uint32_t)(cc[k] - (int64_t)J * o.tile_bj);
                         std::memcpy(vt.data() + dst * tsz, vv.data() + k * tsz, tsz);
+                        double v;
+                        if (tsz == 4) {
+                            float f;
+                            std::memcpy(&f, vv.data() + k * tsz, 4);
+                            v = f;
+                        } else {
+                            std::memcpy(&v, vv.data() + k * tsz, 8);
+                        }
+                        if (!std::isfinite(v)) return TSNE_E_ARG;
+                        ra += std::fabs(v);
                     }
+                    rmax = std::max(rmax, ra);
+                }
             }
-            toff.back() = cur;
-            if (!hip_ok(hipMemcpy(const_cast<int64_t*>(pl->h.toff), toff.data(),
-                                  toff.size() * sizeof(int64_t), hipMemcpyHostToDevice)) ||
+            tsb[o.tile_ni] = (int)tsj.size();
+            tse.push_back(cur);
+            if ((int64_t)tsj.size() > o.tile_steps) return TSNE_E_INTERNAL;
+            // |p (y_i - y_j) / (1 + |y_i - y_j|^2)| <= |p| / 2, so a row's sum
+            // stays below rmax / 2; a power-of-two scale puts that under 2^60
+            // (each term's rounding adds at most 1/2)
+            pl->tscale = std::ldexp(1.0, 61 - std::max(-900, std::ilogb(std::max(rmax, 1e-300)) + 1));
+            pl->h.tscale = pl->tscale;
+            if (!hip_ok(hipMemcpy(const_cast<int64_t*>(pl->h.tse), tse.data(),
+                                  tse.size() * sizeof(int64_t), hipMemcpyHostToDevice)) ||
+                !hip_ok(hipMemcpy(const_cast<int*>(pl->h.tsj), tsj.data(),
+                                  tsj.size() * sizeof(int), hipMemcpyHostToDevice)) ||
+                !hip_ok(hipMemcpy(const_cast<int*>(pl->h.tsb), tsb.data(),
+                                  tsb.size() * sizeof(int), hipMemcpyHostToDevice)) ||
                 !hip_ok(hipMemcpy(const_cast<uint32_t*>(pl->h.epack), pack.data(),
                                   pack.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) ||
                 !hip_ok(hipMemcpy(const_cast<void*>(pl->h.eval), vt.data(), vt.size(),
@@ -769,6 +816,7 @@ tsne_status tsne_bind_P(tsne_plan* pl, const int64_t* row_ptr, const int32_t* co
     a.row_ptr = row_ptr;
     a.col = col;
     a.val = val;
+    a.tscale = pl->tscale;
     if (!hip_ok(launch_set_args(pl->dinst, a, pl->st))) return TSNE_E_HIP;
     pl->P_bound = pl->d.nnz > 0;
     return TSNE_OK;

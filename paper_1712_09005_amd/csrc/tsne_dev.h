@@ -21,6 +21,8 @@ constexpr int kWave = 64;
 
 // Binning: stable least-significant-digit radix sort of the points by cell.
 constexpr int kBoxPart = 16;      // doubles per block of the box partials
+constexpr int kTileWindowBytes = 32768;   // one LDS column window of the tiled attraction
+constexpr int kTileStepEdges = 2048;      // edges per sweep step (1024 threads x 2)
 constexpr int kKeyTile = 2048;     // points per block of the key kernel (256 threads x 8)
 constexpr int kSortTile = 2048;    // points per tile of a sort pass (256 threads x 8)
 constexpr int kScanDigits = 64;    // digits per block of the tile-offset scan (a lane each)
@@ -161,12 +163,15 @@ struct Inst {
     const int* split;      // [slabs - 1][n] first non-zero of each later slab per row
     int slabs;             // column slabs of P (1: no split)
     int slab_w;            // points per column slab
-    int tiled;             // attraction over LDS tiles
-    int tile_bi, tile_bj;  // rows / columns per tile
-    int tile_ni, tile_nj;  // tile grid
-    const int64_t* toff;   // [ni * nj + 1] first edge of each tile
-    const uint32_t* epack; // [nnz] (row in block << 16) | column in block
-    const void* eval;      // [nnz] values in tile order
+    int tiled;             // attraction by row blocks sweeping LDS column windows
+    int tile_bi, tile_bj;  // rows per row block / points per column window
+    int tile_ni, tile_nj;  // row blocks, column windows
+    const int* tsb;        // [ni + 1] first sweep step of each row block
+    const int* tsj;        // [steps] column window of each step
+    const int64_t* tse;    // [steps + 1] first edge of each step
+    const uint32_t* epack; // [nnz] (row in block << 16) | column in window, step order
+    const void* eval;      // [nnz] values in step order
+    double tscale;         // fixed-point scale of the row sums (set with P)
     double* z_part;        // [nb_gather]
     double* h1keep;        // [n] each point's K1 sum h1 of the last repulsion (point order), or null
     double* kl_part;       // [nb_kl][2] divergence partials (sum p log(p/K1), sum p)

@@ -325,6 +325,38 @@ def test_attraction(T, dtype, lpr, slabs, layout, n, s):
     assert rel(Fa, ref) < (1e-6 if dtype == torch.float32 else 1e-13)
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("s", [1, 2])
+def test_attraction_row_blocks_sparse(T, dtype, s):
+    """The row-block sweep (layout 2) where whole row blocks and many rows have
+    no non-zeros: rows 3000..8199 of 9000 have none, so with 3968-row blocks
+    (FP32) or 1984-row blocks (FP64) some blocks sweep no window at all.  Those
+    rows get exactly zero, the rest match the oracle, and a second call gives
+    the same bits (the row sums are fixed point)."""
+    print("case: attraction row blocks with empty blocks %s s=%d" % (dtype, s), flush=True)
+    n = 9000
+    rng = np.random.default_rng(11)
+    live = np.concatenate([np.arange(0, 3000), np.arange(8200, n)])
+    r = rng.choice(live, 40000)
+    c = rng.choice(live, 40000)
+    keep = r != c
+    P = inputs._csr_from_edges(n, r[keep], c[keep], np.exp(-rng.uniform(0, 5, keep.sum())))
+    Y = inputs.mixture_embedding(n, s, 10, -30, 30, 2.0, seed=2)
+    plan = T.Plan(n, s, dtype, nnz=P.nnz, attr_layout=2, max_intervals=128, device=DEV)
+    plan.bind_P(torch.from_numpy(P.row_ptr).to(DEV), torch.from_numpy(P.col).to(DEV),
+                torch.from_numpy(P.val).to(DEV, dtype))
+    Yt = torch.from_numpy(Y).to(DEV, dtype)
+    Fa1 = plan.attractive(Yt)
+    Fa2 = plan.attractive(Yt)
+    torch.cuda.synchronize()
+    assert torch.equal(Fa1, Fa2)
+    Fa = Fa1.cpu().numpy().reshape(n, s)
+    ref = oracle.attr(Y.astype(np.float64), inputs.CSR(P.row_ptr, P.col, P.val.astype(np.float64)))
+    ref = np.asarray(ref).reshape(n, s)
+    assert np.all(Fa[3000:8200] == 0)
+    assert rel(Fa, ref) < (1e-6 if dtype == torch.float32 else 1e-13)
+
+
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-9), (torch.float32, 1e-4)])
 @pytest.mark.parametrize("form", ["A", "V"])
 def test_step_vs_oracle(T, dtype, tol, form):
