@@ -208,9 +208,10 @@ def main():
     ips = K / elapsed
     log("timed: %d iterations in %.4f s -> %.1f it/s" % (K, elapsed, ips))
 
-    # dominant kernel: the attraction step (k_attr, plus k_asum summing the
-    # column-slab partials when slabs > 1), timed with HIP events on the
-    # plan's stream over R back-to-back calls through the C ABI
+    # dominant kernel: the attraction step (k_attr_tile for the row-block
+    # sweep; k_attr plus k_asum summing the column-slab partials for CSR rows
+    # with slabs > 1), timed with HIP events on the plan's stream over R
+    # back-to-back calls through the C ABI
     import ctypes
     R = 50
     with torch.cuda.stream(st_):
@@ -296,8 +297,10 @@ def main():
                    if acc else None,
                    "form_a": form_a, "serving": serving,
                    "kl_divergence": kl_info, "pca": pca_info},
-        "roofline": {"bound": "hbm", "kernel": "attraction step: k_attr (+ k_asum when "
-                                               "attr_slabs > 1)",
+        "roofline": {"bound": "hbm",
+                     "kernel": ("attraction step: k_attr_tile (row blocks over LDS column windows)"
+                                if knobs.get("attr_layout") == 2 else
+                                "attraction step: k_attr (+ k_asum when attr_slabs > 1)"),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(knobs),
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_us": t_attr * 1e6},

@@ -258,22 +258,6 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Attraction by row blocks (the sum over the non-zeros of P of Section 3,
-// arranged for LDS): each virtual block takes tile_bi rows, keeps their
-// positions and force sums in LDS and sweeps the column windows (tile_bj
-// points, 32 KB) that hold its non-zeros, in the sweep steps fixed at bind
-// time (one step: at most kTileStepEdges non-zeros of one window, rows
-// increasing).  Windows are double-buffered: step t takes its non-zeros
-// against buffer t mod 2 while the window and non-zeros of step t + 1 are in
-// flight, then stores that window into the other buffer; one LDS-only
-// barrier per step.  Every neighbour position is thus an LDS read instead of
-// a random L2 gather, the cost that bounds the CSR rows on a graph with no
-// locality.  Row sums are 64-bit fixed point (scale tscale, a power of two
-// chosen at bind time so that no row sum can overflow) added with LDS integer
-// atomics: integer addition commutes, so the result has the same bits in
-// whatever order the atomics land.  All loads are unconditional, at clamped
-// addresses (slots past a step's non-zeros carry weight zero), so the
-// compiler's wait counts leave the prefetches outstanding.
 // Global-memory view of a pointer taken from the instance record: loads
 // through it are vector-memory only (a generic pointer gives flat loads,
 // which every LDS wait also waits for).
@@ -311,7 +295,26 @@ __device__ __forceinline__ typename Vec<T, S>::t gpoint(const void* base, int64_
     }
 }
 
-template <typename T, int S, bool GATED>
+// Attraction by row blocks (the sum over the non-zeros of P of Section 3,
+// arranged for LDS): each virtual block takes tile_bi rows, keeps their
+// positions and force sums in LDS and sweeps the column windows (tile_bj
+// points, 32 KB) that hold its non-zeros, in the sweep steps fixed at bind
+// time (one step: at most kTileStepEdges non-zeros of one window, rows
+// increasing).  Windows are double-buffered in LDS: step t takes its
+// non-zeros against buffer t mod 2 and stores window t + 1 (requested a step
+// earlier) into the other buffer, while window t + 2 and the non-zeros of
+// step t + 1 are in flight; one LDS-only barrier per step.  Every neighbour position is thus an LDS read instead of
+// a random L2 gather, the cost that bounds the CSR rows on a graph with no
+// locality.  Row sums are 64-bit fixed point (scale tscale, a power of two
+// chosen at bind time so that no row sum can overflow) added with LDS integer
+// atomics: integer addition commutes, so the result has the same bits in
+// whatever order the atomics land.  All loads are unconditional, at clamped
+// addresses (slots past a step's non-zeros carry weight zero), so the
+// compiler's wait counts leave the prefetches outstanding.  KL: the same
+// sweep computes the Kullback-Leibler sums of Section 1.1 instead (as the CSR
+// kernel's divergence mode: FP64 per-thread sums, one pair of partials per
+// block for k_klsum), with no force sums.
+template <typename T, int S, bool GATED, bool KL = false>
 __global__ __launch_bounds__(1024) void k_attr_tile(LaunchMap map)
 {
     typedef typename Vec<T, S>::t V;
@@ -319,8 +322,12 @@ __global__ __launch_bounds__(1024) void k_attr_tile(LaunchMap map)
     constexpr int UE = kTileStepEdges / NT;                             // non-zeros per thread and step
     constexpr int WQ = kTileWindowBytes / (S * (int)sizeof(T)) / NT;     // window points per thread
     extern __shared__ __align__(16) char smem[];
-    VB_BEGIN_IF(map, GATED ? K_ATTR_T : K_ATTR_T_ALL, (!GATED || live(I)))
+    __shared__ double klsh[NT / 64];
+    double kla = 0.0, klp = 0.0;
+    double* klout = nullptr;
+    VB_BEGIN_IF(map, KL ? K_KL_T : GATED ? K_ATTR_T : K_ATTR_T_ALL, (!GATED || live(I)))
     {
+        if (KL) klout = I.kl_part;
         // the record's fields through a constant view: scalar loads, kept in
         // scalar registers (a vector copy of a base pointer would make the
         // compiler wait for in-flight loads whenever it reuses registers)
@@ -345,14 +352,16 @@ __global__ __launch_bounds__(1024) void k_attr_tile(LaunchMap map)
         }
         const int s0 = cview<int>(R.tsb)[lb], s1 = cview<int>(R.tsb)[lb + 1];
         const int64_t elast = R.nnz - 1;
-        V wA[WQ];
-        auto wload = [&](int J) {
+        // window registers: the window of the step after next is requested
+        // while this step's non-zeros are taken, and stored a step later
+        V wA[WQ], wB[WQ];
+        auto wload = [&](int J, V (&w)[WQ]) {
 #pragma unroll
-            for (int q = 0; q < WQ; ++q) wA[q] = gpoint<T, S>(Y, min(J * BJ + tid + q * NT, n - 1));
+            for (int q = 0; q < WQ; ++q) w[q] = gpoint<T, S>(Y, min(J * BJ + tid + q * NT, n - 1));
         };
-        auto wstore = [&](int buf) {
+        auto wstore = [&](int buf, const V (&w)[WQ]) {
 #pragma unroll
-            for (int q = 0; q < WQ; ++q) win[buf * BJ + tid + q * NT] = wA[q];
+            for (int q = 0; q < WQ; ++q) win[buf * BJ + tid + q * NT] = w[q];
         };
         // a slot past the step's non-zeros loads the last non-zero and gets
         // mask 0 (applied where the value is used, so the load stays in flight)
@@ -376,45 +385,78 @@ __global__ __launch_bounds__(1024) void k_attr_tile(LaunchMap map)
             T d0, d1 = (T)0;
             if constexpr (S == 2) { d0 = a.x - b.x; d1 = a.y - b.y; }
             else { d0 = a - b; }
-            const T wgt = (pv * m) * recip((T)1 + d0 * d0 + d1 * d1);
-            const T c0 = wgt * d0, c1 = wgt * d1;
-            if (c0 != (T)0 || c1 != (T)0) {
-                atomicAdd(&acc[lr * S], fx(c0));
-                if (S == 2) atomicAdd(&acc[lr * S + 1], fx(c1));
+            const T q = (T)1 + d0 * d0 + d1 * d1;
+            if constexpr (KL) {
+                const T pk = pv * m;
+                if (pk > (T)0) {
+                    kla += (double)pk * (double)log(pk * q);
+                    klp += (double)pk;
+                }
+            } else {
+                const T wgt = (pv * m) * recip(q);
+                const T c0 = wgt * d0, c1 = wgt * d1;
+                if (c0 != (T)0 || c1 != (T)0) {
+                    atomicAdd(&acc[lr * S], fx(c0));
+                    if (S == 2) atomicAdd(&acc[lr * S + 1], fx(c1));
+                }
             }
         };
         uint32_t kA[UE], kB[UE];
         T vA[UE], vB[UE], mA[UE], mB[UE];
-        // one step: request the next step's window and non-zeros, take this
-        // step's non-zeros, store the next window, barrier
-        auto step = [&](int st, const uint32_t (&kc)[UE], const T (&vc)[UE], const T (&mc)[UE],
-                        uint32_t (&kn)[UE], T (&vn)[UE], T (&mn)[UE]) {
+        // step t: holds window t + 1 and the non-zeros of t in registers;
+        // requests window t + 2 and the non-zeros of t + 1, takes its own
+        // non-zeros against LDS buffer t mod 2, stores window t + 1 into the
+        // other buffer, barrier
+        auto step = [&](int st, const V (&wc)[WQ], V (&wn)[WQ], const uint32_t (&kc)[UE],
+                        const T (&vc)[UE], const T (&mc)[UE], uint32_t (&kn)[UE], T (&vn)[UE],
+                        T (&mn)[UE]) {
             const V* w = win + ((st - s0) & 1) * BJ;
-            const int sn = min(st + 1, s1 - 1);
-            wload(tsj[sn]);
-            eload(sn, kn, vn, mn);
+            wload(tsj[min(st + 2, s1 - 1)], wn);
+            eload(min(st + 1, s1 - 1), kn, vn, mn);
 #pragma unroll
             for (int u = 0; u < UE; ++u) edge(kc[u], vc[u], mc[u], w);
-            wstore((st + 1 - s0) & 1);
+            wstore((st + 1 - s0) & 1, wc);
             lds_barrier();
         };
         if (s1 > s0) {
-            wload(tsj[s0]);
-            wstore(0);
+            wload(tsj[s0], wA);
+            wstore(0, wA);
+            wload(tsj[min(s0 + 1, s1 - 1)], wA);
             eload(s0, kA, vA, mA);
+            // the sweep starts with nothing in flight: the loop's registers
+            // then carry no load from before it, so the compiler places no
+            // full wait at the top of every iteration
+            __builtin_amdgcn_s_waitcnt(0);
         }
         lds_barrier();
-        for (int st = s0; st < s1; st += 2) {
-            step(st, kA, vA, mA, kB, vB, mB);
-            if (st + 1 < s1) step(st + 1, kB, vB, mB, kA, vA, mA);
+        // steps in pairs, the registers' roles swapped in the second (every
+        // path into the loop's top then comes from the same point), and a
+        // last single step
+        int st = s0;
+        for (; st + 1 < s1; st += 2) {
+            step(st, wA, wB, kA, vA, mA, kB, vB, mB);
+            step(st + 1, wB, wA, kB, vB, mB, kA, vA, mA);
         }
-        TSNE_GLOBAL T* F = (TSNE_GLOBAL T*)R.Fattr;
-        const int rows = min(BI, n - i0);
-        for (int r = tid; r < rows * S; r += NT)
-            F[(int64_t)i0 * S + r] = (T)((double)(long long)acc[r] / scale);
+        if (st < s1) step(st, wA, wB, kA, vA, mA, kB, vB, mB);
+        if constexpr (!KL) {
+            TSNE_GLOBAL T* F = (TSNE_GLOBAL T*)R.Fattr;
+            const int rows = min(BI, n - i0);
+            for (int r = tid; r < rows * S; r += NT)
+                F[(int64_t)i0 * S + r] = (T)((double)(long long)acc[r] / scale);
+        }
         __syncthreads();   // the LDS is reused by the next virtual block
     }
     VB_END
+    if constexpr (KL) {
+        // a single-instance launch: the block's partials (klout is the
+        // instance's array once the block has run a virtual block)
+        kla = block_sum_d(kla, klsh);
+        klp = block_sum_d(klp, klsh);
+        if (threadIdx.x == 0 && klout) {
+            klout[2 * blockIdx.x] = kla;
+            klout[2 * blockIdx.x + 1] = klp;
+        }
+    }
 }
 
 // Attraction entry point with slabs: F_attr = sum of the slab partials.
@@ -567,14 +609,20 @@ static hipError_t launch_attr(int kind, const Cfg& c, const LaunchMap& map, cons
     case K_ATTR_T:
         if (l.lds > 48 * 1024)
             (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_attr_tile<T, S, true>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)l.lds);
         hipLaunchKernelGGL((k_attr_tile<T, S, true>), g, b, l.lds, st, map);
         break;
     case K_ATTR_T_ALL:
         if (l.lds > 48 * 1024)
             (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_attr_tile<T, S, false>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)l.lds);
         hipLaunchKernelGGL((k_attr_tile<T, S, false>), g, b, l.lds, st, map);
+        break;
+    case K_KL_T:
+        if (l.lds > 48 * 1024)
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_attr_tile<T, S, true, true>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)l.lds);
+        hipLaunchKernelGGL((k_attr_tile<T, S, true, true>), g, b, l.lds, st, map);
         break;
     default: return hipErrorInvalidValue;
     }

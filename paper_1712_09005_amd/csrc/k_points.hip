@@ -1050,6 +1050,7 @@ hipError_t launch_kind(int kind, const Cfg& c, const LaunchMap& map, const Launc
     case K_S3_FILL: case K_S3_X: case K_S3_Y: case K_S3_Z: case K_S3_STORE:
         return launch_fft_kind(kind, c, map, l, st);
     case K_ATTR: case K_ATTR_ALL: case K_ATTR_T: case K_ATTR_T_ALL: case K_ASUM: case K_KL_ATTR:
+    case K_KL_T:
     case K_KL: case K_KLSUM:
         return launch_attr_kind(kind, c, map, l, st);
     case K_KEY: case K_HIST1: case K_HIST2: case K_TSCAN0: case K_TSCAN1: case K_TSCAN2:

@@ -281,8 +281,11 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     // the divergence runs as a mode of the CSR attraction pass (same virtual
     // blocks, one partial each), or over rows for the tiled layout
     vb[K_KL_ATTR] = vb[K_ATTR];
-    if (vb[K_KL_ATTR] > 0) o.nb_kl = std::min(vb[K_KL_ATTR], kGridCap);   // one partial per block
-    vb[K_KL] = (d->nnz > 0 && vb[K_KL_ATTR] == 0) ? o.nb_kl : 0;
+    vb[K_KL_T] = vb[K_ATTR_T];
+    // one partial per block of the attraction kernel's divergence mode
+    if (vb[K_KL_ATTR] > 0) o.nb_kl = std::min(vb[K_KL_ATTR], kGridCap);
+    if (vb[K_KL_T] > 0) o.nb_kl = std::min(vb[K_KL_T], kGridCap);
+    vb[K_KL] = (d->nnz > 0 && vb[K_KL_ATTR] == 0 && vb[K_KL_T] == 0) ? o.nb_kl : 0;
     vb[K_KLSUM] = (d->nnz > 0) ? 1 : 0;
 
     // workspace layout
@@ -392,7 +395,7 @@ Launch launch_of(int kind, const Derived& o, int vblocks)
         l.block = o.col_threads;
         l.lds = o.col_lds;
         break;
-    case K_ATTR_T: case K_ATTR_T_ALL:
+    case K_ATTR_T: case K_ATTR_T_ALL: case K_KL_T:
         l.block = 1024;
         l.lds = o.tile_lds;
         break;
@@ -876,7 +879,7 @@ tsne_status tsne_kl_divergence(tsne_plan* pl, const void* Y, double* kl)
     if (s != TSNE_OK) return s;
     s = enqueue_repulsion(pl, false);
     if (s != TSNE_OK) return s;
-    s = enqueue(pl, pl->o.vb[K_KL_ATTR] > 0 ? K_KL_ATTR : K_KL);
+    s = enqueue(pl, pl->o.vb[K_KL_ATTR] > 0 ? K_KL_ATTR : pl->o.vb[K_KL_T] > 0 ? K_KL_T : K_KL);
     if (s != TSNE_OK) return s;
     return enqueue(pl, K_KLSUM);
 }

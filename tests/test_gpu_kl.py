@@ -21,9 +21,10 @@ def T():
     return tsne
 
 
-def _plan(T, Y, P, dtype, w=0.75, cap=128):
+def _plan(T, Y, P, dtype, w=0.75, cap=128, layout=0):
     n, s = Y.shape
-    plan = T.Plan(n, s, dtype, p=5, interval_width=w, max_intervals=cap, nnz=P.nnz, device=DEV)
+    plan = T.Plan(n, s, dtype, p=5, interval_width=w, max_intervals=cap, nnz=P.nnz, device=DEV,
+                  attr_layout=layout)
     plan.bind_P(torch.from_numpy(P.row_ptr).to(DEV), torch.from_numpy(P.col).to(DEV),
                 torch.from_numpy(P.val).to(DEV, dtype))
     return plan
@@ -31,11 +32,14 @@ def _plan(T, Y, P, dtype, w=0.75, cap=128):
 
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 5e-5)])
 @pytest.mark.parametrize("n,s", [(3001, 2), (4001, 1)])
-def test_kl_vs_oracle(T, dtype, tol, n, s):
-    print("case: kl n=%d s=%d %s" % (n, s, dtype), flush=True)
+@pytest.mark.parametrize("layout", [1, 2])
+def test_kl_vs_oracle(T, dtype, tol, n, s, layout):
+    """The divergence through the CSR kernel's divergence mode (layout 1) and
+    through the row-block sweep's (layout 2)."""
+    print("case: kl n=%d s=%d %s layout %d" % (n, s, dtype, layout), flush=True)
     Y = inputs.mixture_embedding(n, s, 8, -20, 20, 1.5, seed=41)
     P = inputs.random_graph_P(n, 90, seed=42)
-    plan = _plan(T, Y, P, dtype)
+    plan = _plan(T, Y, P, dtype, layout=layout)
     Yt = torch.from_numpy(Y).to(DEV, dtype)
     kl = float(plan.kl_divergence(Yt).item())
     st = plan.query()
@@ -62,14 +66,16 @@ def test_kl_needs_P(T):
     assert e.value.code == 7
 
 
-def test_kl_full_size(T):
+@pytest.mark.parametrize("layout", [1, 2])
+def test_kl_full_size(T, layout):
     """N = 1e6, 2-D, FP32: the divergence minus (sum p) log Z equals the
-    oracle's sum of p log(p / K1) (its definition with Z = 1), O(nnz)."""
-    print("case: kl full size", flush=True)
+    oracle's sum of p log(p / K1) (its definition with Z = 1), O(nnz); CSR
+    rows and the row-block sweep."""
+    print("case: kl full size layout %d" % layout, flush=True)
     n = 1_000_000
     Y = inputs.mixture_embedding(n, 2, 50, -95.0, 95.0, 2.0, seed=0)
     P = inputs.random_graph_P(n, 90, seed=1)
-    plan = _plan(T, Y, P, torch.float32, w=0.9, cap=512)
+    plan = _plan(T, Y, P, torch.float32, w=0.9, cap=512, layout=layout)
     Yt = torch.from_numpy(Y).to(DEV)
     kl = float(plan.kl_divergence(Yt).item())
     Z = plan.query()["Z"]
