@@ -351,13 +351,16 @@ __global__ __launch_bounds__(1024) void k_attr_tile(LaunchMap map)
             yI[r] = gpoint<T, S>(Y, min(i0 + r, n - 1));   // rows past n: never referenced
         }
         const int s0 = cview<int>(R.tsb)[lb], s1 = cview<int>(R.tsb)[lb + 1];
-        const int64_t elast = R.nnz - 1;
         // window registers: the window of the step after next is requested
         // while this step's non-zeros are taken, and stored a step later
         V wA[WQ], wB[WQ];
+        // loads at a uniform base plus a 32-bit offset (scalar base address,
+        // no 64-bit index arithmetic per lane)
         auto wload = [&](int J, V (&w)[WQ]) {
+            const int j0 = J * BJ, lim = n - 1 - j0;   // >= 0: windows start below n
+            const void* base = static_cast<const char*>(Y) + (size_t)j0 * S * sizeof(T);
 #pragma unroll
-            for (int q = 0; q < WQ; ++q) w[q] = gpoint<T, S>(Y, min(J * BJ + tid + q * NT, n - 1));
+            for (int q = 0; q < WQ; ++q) w[q] = gpoint<T, S>(base, min(tid + q * NT, lim));
         };
         auto wstore = [&](int buf, const V (&w)[WQ]) {
 #pragma unroll
@@ -366,38 +369,50 @@ __global__ __launch_bounds__(1024) void k_attr_tile(LaunchMap map)
         // a slot past the step's non-zeros loads the last non-zero and gets
         // mask 0 (applied where the value is used, so the load stays in flight)
         auto eload = [&](int st, uint32_t (&k)[UE], T (&v)[UE], T (&m)[UE]) {
-            const int64_t e0 = tse[st], e1 = tse[st + 1];
+            const int64_t e0 = tse[st];
+            const int cnt = (int)(tse[st + 1] - e0);   // >= 1: steps hold non-zeros
+            const TSNE_GLOBAL uint32_t* epb = ep + e0;
+            const TSNE_GLOBAL T* evb = ev + e0;
 #pragma unroll
             for (int u = 0; u < UE; ++u) {
-                const int64_t e = e0 + tid + (int64_t)u * NT;
-                const int64_t ec = min(e, elast);
-                k[u] = ep[ec];
-                v[u] = ev[ec];
-                m[u] = (e < e1) ? (T)1 : (T)0;
+                const int e = tid + u * NT, ec = min(e, cnt - 1);
+                k[u] = epb[ec];
+                v[u] = evb[ec];
+                m[u] = (e < cnt) ? (T)1 : (T)0;
             }
         };
         auto fx = [&](T c) -> unsigned long long {
             return (unsigned long long)__double2ll_rn((double)c * scale);
         };
-        auto edge = [&](uint32_t key, T pv, T m, const V* w) {
-            const int lr = (int)(key >> 16), lc = (int)(key & 0xffffu);
-            const V a = yI[lr], b = w[lc];
-            T d0, d1 = (T)0;
-            if constexpr (S == 2) { d0 = a.x - b.x; d1 = a.y - b.y; }
-            else { d0 = a - b; }
-            const T q = (T)1 + d0 * d0 + d1 * d1;
-            if constexpr (KL) {
-                const T pk = pv * m;
-                if (pk > (T)0) {
-                    kla += (double)pk * (double)log(pk * q);
-                    klp += (double)pk;
-                }
-            } else {
-                const T wgt = (pv * m) * recip(q);
-                const T c0 = wgt * d0, c1 = wgt * d1;
-                if (c0 != (T)0 || c1 != (T)0) {
-                    atomicAdd(&acc[lr * S], fx(c0));
-                    if (S == 2) atomicAdd(&acc[lr * S + 1], fx(c1));
+        // a step's slots: every LDS read first, then the arithmetic, then the
+        // atomics of the slots with a non-zero term (masked slots have none)
+        auto edges = [&](const uint32_t (&key)[UE], const T (&pv)[UE], const T (&m)[UE], const V* w) {
+            V a[UE], b[UE];
+#pragma unroll
+            for (int u = 0; u < UE; ++u) {
+                a[u] = yI[key[u] >> 16];
+                b[u] = w[key[u] & 0xffffu];
+            }
+#pragma unroll
+            for (int u = 0; u < UE; ++u) {
+                T d0, d1 = (T)0;
+                if constexpr (S == 2) { d0 = a[u].x - b[u].x; d1 = a[u].y - b[u].y; }
+                else { d0 = a[u] - b[u]; }
+                const T q = (T)1 + d0 * d0 + d1 * d1;
+                const T pk = pv[u] * m[u];
+                if constexpr (KL) {
+                    if (pk > (T)0) {
+                        kla += (double)pk * (double)log(pk * q);
+                        klp += (double)pk;
+                    }
+                } else {
+                    const T wgt = pk * recip(q);
+                    const T c0 = wgt * d0, c1 = wgt * d1;
+                    if (c0 != (T)0 || c1 != (T)0) {
+                        const int lr = (int)(key[u] >> 16);
+                        atomicAdd(&acc[lr * S], fx(c0));
+                        if (S == 2) atomicAdd(&acc[lr * S + 1], fx(c1));
+                    }
                 }
             }
         };
@@ -413,8 +428,7 @@ __global__ __launch_bounds__(1024) void k_attr_tile(LaunchMap map)
             const V* w = win + ((st - s0) & 1) * BJ;
             wload(tsj[min(st + 2, s1 - 1)], wn);
             eload(min(st + 1, s1 - 1), kn, vn, mn);
-#pragma unroll
-            for (int u = 0; u < UE; ++u) edge(kc[u], vc[u], mc[u], w);
+            edges(kc, vc, mc, w);
             wstore((st + 1 - s0) & 1, wc);
             lds_barrier();
         };
