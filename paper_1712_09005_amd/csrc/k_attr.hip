@@ -258,22 +258,6 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Global-memory view of a pointer taken from the instance record: loads
-// through it are vector-memory only (a generic pointer gives flat loads,
-// which every LDS wait also waits for).
-#define TSNE_GLOBAL __attribute__((address_space(1)))
-template <typename P> __device__ __forceinline__ const TSNE_GLOBAL P* gview(const void* p)
-{
-    return (const TSNE_GLOBAL P*)p;
-}
-// Constant-memory view of read-only data indexed uniformly across the block
-// (scalar loads, which the vector-memory waits do not drain).
-#define TSNE_CONST __attribute__((address_space(4)))
-template <typename P> __device__ __forceinline__ const TSNE_CONST P* cview(const void* p)
-{
-    return (const TSNE_CONST P*)p;
-}
-
 // One point of an [n][S] array through the global view, as one vector load
 // (a native vector type: the HIP vector structs cannot be copied out of a
 // qualified address space).

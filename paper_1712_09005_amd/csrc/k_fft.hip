@@ -137,9 +137,10 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int M, int PM, int G, in
 #pragma unroll
             for (int r = 0; r < R; ++r) v[b][r] = src[lds_pad(j + r * Mr)];
             if (Ns > 1) {
-                const cplx<T>* t = tws + k * (R - 1);
+                // through the global view: vector-memory loads, which the LDS
+                // waits of the stage do not wait for
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], t[r - 1]);
+                for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], gload_c<T>(tws, k * (R - 1) + r - 1));
             }
             Dft<T, R>::run(v[b]);
             dst[b] = a * Ns * R + k;
@@ -167,10 +168,13 @@ __device__ __forceinline__ void block_fft_tw(cplx<T>* buf, int G, int M, int nst
                                              const int* tw_off, const cplx<T>* tw)
 {
     const int PM = lds_stride(M);
+    // the stage plan through the constant view: scalar loads
+    const TSNE_CONST int* rad = cview<int>(radix);
+    const TSNE_CONST int* two = cview<int>(tw_off);
     int Ns = 1;
     for (int s = 0; s < nst; ++s) {
-        const int R = radix[s];
-        const cplx<T>* tws = tw + tw_off[s];
+        const int R = rad[s];
+        const cplx<T>* tws = tw + two[s];
         switch (R) {
         case 2: fft_stage<T, 2>(buf, M, PM, G, Ns, tws); break;
         case 3: fft_stage<T, 3>(buf, M, PM, G, Ns, tws); break;

@@ -190,6 +190,30 @@ struct LaunchMap {
 
 template <typename T> struct cplx { T x, y; };
 
+// Global-memory view of a pointer taken from the instance record: loads
+// through it are vector-memory only (a generic pointer gives flat loads,
+// which every LDS wait also waits for).
+#define TSNE_GLOBAL __attribute__((address_space(1)))
+template <typename P> __device__ __forceinline__ const TSNE_GLOBAL P* gview(const void* p)
+{
+    return (const TSNE_GLOBAL P*)p;
+}
+// Constant-memory view of read-only data indexed uniformly across the block
+// (scalar loads, which the vector-memory waits do not drain).
+#define TSNE_CONST __attribute__((address_space(4)))
+template <typename P> __device__ __forceinline__ const TSNE_CONST P* cview(const void* p)
+{
+    return (const TSNE_CONST P*)p;
+}
+
+// One complex element through the global view, as one vector load.
+template <typename T> __device__ __forceinline__ cplx<T> gload_c(const void* base, int64_t i)
+{
+    typedef T N __attribute__((ext_vector_type(2)));
+    const N q = gview<N>(base)[i];
+    return {q.x, q.y};
+}
+
 __device__ __forceinline__ int find_inst(const int* __restrict__ pre, int ninst, int vb)
 {
     int lo = 0, hi = ninst - 1;
