@@ -189,9 +189,12 @@ template <typename T>
 __device__ __forceinline__ void block_fft(cplx<T>* buf, int G, const Inst& I, const Geom& Gm,
                                           bool yaxis = false)
 {
-    const cplx<T>* tw = static_cast<const cplx<T>*>((yaxis && Gm.My != Gm.M) ? I.twy : I.tw);
-    if (yaxis) block_fft_tw<T>(buf, G, Gm.My, Gm.nstages_y, Gm.radix_y, Gm.tw_off_y, tw);
-    else block_fft_tw<T>(buf, G, Gm.M, Gm.nstages, Gm.radix, Gm.tw_off, tw);
+    // the geometry through the constant view (scalar loads; a generic
+    // reference gives flat loads, which the LDS waits also wait for)
+    const TSNE_CONST Geom& C = *cview<Geom>(&Gm);
+    const cplx<T>* tw = static_cast<const cplx<T>*>((yaxis && C.My != C.M) ? I.twy : I.tw);
+    if (yaxis) block_fft_tw<T>(buf, G, C.My, C.nstages_y, &Gm.radix_y[0], &Gm.tw_off_y[0], tw);
+    else block_fft_tw<T>(buf, G, C.M, C.nstages, &Gm.radix[0], &Gm.tw_off[0], tw);
 }
 
 __device__ __forceinline__ bool okay(const Inst& I) { return live(I); }
@@ -332,7 +335,7 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
                 const int idx = i0 + u * nthr;
                 const int r = idx >> lgc, g = idx & (Gc - 1);
                 v[u] = {(T)0, (T)0};
-                if (idx < nel && k00 + g < half && r < n) v[u] = X[t0 + (int64_t)r * tw_ + g];
+                if (idx < nel && k00 + g < half && r < n) v[u] = gload_c<T>(X, t0 + (int64_t)r * tw_ + g);
             }
 #pragma unroll
             for (int u = 0; u < kLd; ++u) {
@@ -359,7 +362,7 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
                 for (int u = 0; u < kLd; ++u) {
                     const int k1 = kb + u * tpc;
                     const bool up = k1 > M - k1;
-                    sv[u] = (k1 < M && k0 < half) ? sp[up ? M - k1 : k1] : (T)0;
+                    sv[u] = (k1 < M && k0 < half) ? gview<T>(sp)[up ? M - k1 : k1] : (T)0;
                     // times -i b, b odd in k1 for the kernel odd along dimension 1
                     if (FORM == 2 && kern == 2 && up) sv[u] = -sv[u];
                 }
@@ -380,7 +383,7 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
         cplx<T>* Xc = static_cast<cplx<T>*>(I.Xc) + (int64_t)pot * I.ntiles * n_cap * tw_;
         for (int idx = threadIdx.x; idx < (n << lgc); idx += blockDim.x) {
             const int r = idx >> lgc, g = idx & (Gc - 1);
-            if (k00 + g < half) Xc[t0 + (int64_t)r * tw_ + g] = cconj(buf[g * PM + lds_pad(r)]);
+            if (k00 + g < half) gstore_c<T>(Xc, t0 + (int64_t)r * tw_ + g, cconj(buf[g * PM + lds_pad(r)]));
         }
         __syncthreads();
         }
@@ -494,7 +497,7 @@ __global__ __launch_bounds__(1024) void k_fft_1d(LaunchMap map)
             for (int u = 0; u < kLd; ++u) {
                 const int k = k0 + u * nthr;
                 const bool up = k > M - k;
-                sv[u] = (k < M) ? sp[up ? M - k : k] : (T)0;
+                sv[u] = (k < M) ? gview<T>(sp)[up ? M - k : k] : (T)0;
                 if (FORM == 2 && kern > 0 && up) sv[u] = -sv[u];   // times -i b, b odd in k
             }
 #pragma unroll

@@ -213,6 +213,15 @@ template <typename T> __device__ __forceinline__ cplx<T> gload_c(const void* bas
     const N q = gview<N>(base)[i];
     return {q.x, q.y};
 }
+// One complex element stored through the global view, as one vector store.
+template <typename T> __device__ __forceinline__ void gstore_c(void* base, int64_t i, cplx<T> v)
+{
+    typedef T N __attribute__((ext_vector_type(2)));
+    N q;
+    q.x = v.x;
+    q.y = v.y;
+    ((TSNE_GLOBAL N*)base)[i] = q;
+}
 
 __device__ __forceinline__ int find_inst(const int* __restrict__ pre, int ninst, int vb)
 {
