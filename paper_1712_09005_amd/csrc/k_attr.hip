@@ -370,15 +370,23 @@ __global__ __launch_bounds__(1024) void k_attr_tile(LaunchMap map)
         };
         // a step's slots: every LDS read first, then the arithmetic, then the
         // atomics of the slots with a non-zero term (masked slots have none)
+        // A wave whose lanes all lie past the step's non-zeros in a slot
+        // skips that slot (a wave-uniform branch; steps fill about 70% of
+        // their slots at C3).
         auto edges = [&](const uint32_t (&key)[UE], const T (&pv)[UE], const T (&m)[UE], const V* w) {
             V a[UE], b[UE];
+            bool any[UE];
 #pragma unroll
             for (int u = 0; u < UE; ++u) {
-                a[u] = yI[key[u] >> 16];
-                b[u] = w[key[u] & 0xffffu];
+                any[u] = __builtin_amdgcn_ballot_w64(m[u] != (T)0) != 0;
+                if (any[u]) {
+                    a[u] = yI[key[u] >> 16];
+                    b[u] = w[key[u] & 0xffffu];
+                }
             }
 #pragma unroll
             for (int u = 0; u < UE; ++u) {
+                if (!any[u]) continue;
                 T d0, d1 = (T)0;
                 if constexpr (S == 2) { d0 = a[u].x - b[u].x; d1 = a[u].y - b[u].y; }
                 else { d0 = a[u] - b[u]; }
