@@ -885,28 +885,31 @@ __global__ __launch_bounds__(256) void k_update(LaunchMap map)
         const Sched& sc = *I.sched;
         double alpha, mom;
         sched_at(sc, G.it, alpha, mom);
-        const int64_t i = (int64_t)lb * 256 + threadIdx.x;
-        if (i < I.n) {
-            const T invz = (T)(1.0 / G.Z);
-            T* Y = static_cast<T*>(I.Y);
-            T* uY = static_cast<T*>(I.uY);
-            T* gains = static_cast<T*>(I.gains);
-            const T* Fa = static_cast<const T*>(I.Fattr);
-            const T* Fp = static_cast<const T*>(I.Fap);
-            const T* R = static_cast<const T*>(I.R);
-            const int64_t ns = I.n * S;
-            // the point's S components are loaded and stored as one vector
-            // per array (8 or 16 bytes in 2-D)
-            Pt<T, S> fa, r, u, g, y;
+        const T invz = (T)(1.0 / G.Z);
+        T* Y = static_cast<T*>(I.Y);
+        T* uY = static_cast<T*>(I.uY);
+        T* gains = static_cast<T*>(I.gains);
+        const T* Fa = static_cast<const T*>(I.Fattr);
+        const T* Fp = static_cast<const T*>(I.Fap);
+        const T* R = static_cast<const T*>(I.R);
+        const int64_t n = I.n, ns = n * S;
+        // kUpdPts points per thread, 256 apart: all their loads are issued
+        // first, then the arithmetic, then the stores; each point's S
+        // components move as one vector per array (8 or 16 bytes in 2-D)
+        const int64_t i0 = (int64_t)lb * (256 * kUpdPts) + threadIdx.x;
+        Pt<T, S> fa[kUpdPts], r[kUpdPts], u[kUpdPts], g[kUpdPts], y[kUpdPts];
+#pragma unroll
+        for (int q = 0; q < kUpdPts; ++q) {
+            const int64_t i = min(i0 + (int64_t)q * 256, n - 1);   // past n: a repeat, not stored
             if (I.slabs == 1) {
-                fa = Pt<T, S>::load(Fa, i);
+                fa[q] = Pt<T, S>::load(Fa, i);
             } else {
                 // every slab's partial in flight at once, then summed in slab order
                 constexpr int kMaxSlabs = 8;
-                Pt<T, S> q[kMaxSlabs];
+                Pt<T, S> p[kMaxSlabs];
 #pragma unroll
                 for (int sl = 0; sl < kMaxSlabs; ++sl)
-                    if (sl < I.slabs) q[sl] = Pt<T, S>::load(Fp + (int64_t)sl * ns, i);
+                    if (sl < I.slabs) p[sl] = Pt<T, S>::load(Fp + (int64_t)sl * ns, i);
                 double a[S];
 #pragma unroll
                 for (int d = 0; d < S; ++d) a[d] = 0.0;
@@ -914,30 +917,39 @@ __global__ __launch_bounds__(256) void k_update(LaunchMap map)
                 for (int sl = 0; sl < kMaxSlabs; ++sl)
                     if (sl < I.slabs) {
 #pragma unroll
-                        for (int d = 0; d < S; ++d) a[d] += (double)q[sl].v[d];
+                        for (int d = 0; d < S; ++d) a[d] += (double)p[sl].v[d];
                     }
 #pragma unroll
-                for (int d = 0; d < S; ++d) fa.v[d] = (T)a[d];
+                for (int d = 0; d < S; ++d) fa[q].v[d] = (T)a[d];
             }
-            r = Pt<T, S>::load(R, i);
-            u = Pt<T, S>::load(uY, i);
-            g = Pt<T, S>::load(gains, i);
-            y = Pt<T, S>::load(Y, i);
+            r[q] = Pt<T, S>::load(R, i);
+            u[q] = Pt<T, S>::load(uY, i);
+            g[q] = Pt<T, S>::load(gains, i);
+            y[q] = Pt<T, S>::load(Y, i);
+        }
+#pragma unroll
+        for (int q = 0; q < kUpdPts; ++q) {
 #pragma unroll
             for (int d = 0; d < S; ++d) {
-                const T grad = (T)4 * ((T)alpha * fa.v[d] - r.v[d] * invz);
-                T gd = ((grad > (T)0) != (u.v[d] > (T)0)) ? g.v[d] + (T)sc.gain_inc
-                                                          : g.v[d] * (T)sc.gain_dec;
+                const T grad = (T)4 * ((T)alpha * fa[q].v[d] - r[q].v[d] * invz);
+                T gd = ((grad > (T)0) != (u[q].v[d] > (T)0)) ? g[q].v[d] + (T)sc.gain_inc
+                                                             : g[q].v[d] * (T)sc.gain_dec;
                 if (gd < (T)sc.gain_min) gd = (T)sc.gain_min;
-                g.v[d] = gd;
-                const T un = (T)mom * u.v[d] - (T)sc.eta * gd * grad;
-                u.v[d] = un;
-                const T yd = sc.recentre ? (y.v[d] - (T)G.mean[d]) : y.v[d];
-                y.v[d] = yd + un;
+                g[q].v[d] = gd;
+                const T un = (T)mom * u[q].v[d] - (T)sc.eta * gd * grad;
+                u[q].v[d] = un;
+                const T yd = sc.recentre ? (y[q].v[d] - (T)G.mean[d]) : y[q].v[d];
+                y[q].v[d] = yd + un;
             }
-            g.store(gains, i);
-            u.store(uY, i);
-            y.store(Y, i);
+        }
+#pragma unroll
+        for (int q = 0; q < kUpdPts; ++q) {
+            const int64_t i = i0 + (int64_t)q * 256;
+            if (i < n) {
+                g[q].store(gains, i);
+                u[q].store(uY, i);
+                y[q].store(Y, i);
+            }
         }
     }
     VB_END

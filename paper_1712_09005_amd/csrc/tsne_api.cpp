@@ -275,7 +275,7 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     }
     vb[K_ATTR_ALL] = vb[K_ATTR];
     vb[K_ASUM] = (d->nnz > 0 && o.slabs > 1) ? cdiv(n * d->s, 256) : 0;
-    vb[K_UPDATE] = cdiv(n, 256);
+    vb[K_UPDATE] = cdiv(n, 256 * kUpdPts);
     vb[K_GEOM] = 1;
     vb[K_ZSUM] = 1;
     // the divergence runs as a mode of the CSR attraction pass (same virtual

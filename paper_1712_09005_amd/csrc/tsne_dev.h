@@ -21,6 +21,7 @@ constexpr int kWave = 64;
 
 // Binning: stable least-significant-digit radix sort of the points by cell.
 constexpr int kBoxPart = 16;      // doubles per block of the box partials
+constexpr int kUpdPts = 4;              // points per thread of the update kernel
 constexpr int kTileWindowBytes = 32768;   // one LDS column window of the tiled attraction
 constexpr int kTileStepEdges = 2048;      // edges per sweep step (1024 threads x 2)
 constexpr int kKeyTile = 2048;     // points per block of the key kernel (256 threads x 8)
