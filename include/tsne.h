@@ -204,8 +204,9 @@ tsne_status tsne_plan_destroy(tsne_plan* plan);
  * the values must be finite (TSNE_E_ARG otherwise) and are copied, re-bucketed
  * by row block and column window, with the sweep steps and the fixed-point
  * scale of the row sums (2^61 over the largest row sum of |p|, rounded down
- * to a power of two).  The arrays stay borrowed (the divergence of the tiled
- * layout and FP64 plans read them directly). */
+ * to a power of two).  The arrays stay borrowed: the CSR layout reads
+ * row_ptr (and, in FP64, col and val) at every call; the row-block layout
+ * reads only its copy. */
 tsne_status tsne_bind_P(tsne_plan* plan, const int64_t* row_ptr,
                         const int32_t* col, const void* val);
 

@@ -493,55 +493,10 @@ __global__ __launch_bounds__(256) void k_asum(LaunchMap map)
 
 // ---------------------------------------------------------------- KL divergence
 
-// Kullback-Leibler divergence of Section 1.1 from one pass over P:
-// C = sum p_ij log(p_ij / q_ij) with q_ij = K1_ij / Z, split as
-// sum p log(p (1 + |y_i - y_j|^2)) + (sum p) log Z.  32 lanes per row, the
-// logarithm in the element type, FP64 sums; each virtual block strides over
-// rows and leaves its two partial sums, which k_klsum adds in a fixed order
-// with the Z of the same call.
-template <typename T, int S>
-__global__ __launch_bounds__(256) void k_kl(LaunchMap map)
-{
-    constexpr int LPR = 32, RPB = 256 / LPR;
-    typedef typename Vec<T, S>::t V;
-    __shared__ double sh[8];
-    VB_BEGIN(map, K_KL)
-    if (live(I)) {
-        const int64_t n = I.n;
-        const int sub = (int)threadIdx.x % LPR;
-        const V* Y = static_cast<const V*>(I.Yin);
-        const T* val = static_cast<const T*>(I.val);
-        double a = 0.0, ps = 0.0;
-        for (int64_t i = (int64_t)lb * RPB + (int)threadIdx.x / LPR; i < n;
-             i += (int64_t)I.nb_kl * RPB) {
-            const V yi = Y[i];
-            const int64_t e = I.row_ptr[i + 1];
-            for (int64_t k = I.row_ptr[i] + sub; k < e; k += LPR) {
-                const T pk = val[k];
-                if (!(pk > (T)0)) continue;
-                const V yj = Y[I.col[k]];
-                T d2;
-                if constexpr (S == 2) {
-                    const T d0 = yi.x - yj.x, d1 = yi.y - yj.y;
-                    d2 = d0 * d0 + d1 * d1;
-                } else {
-                    const T d0 = yi - yj;
-                    d2 = d0 * d0;
-                }
-                a += (double)pk * (double)log(pk * ((T)1 + d2));
-                ps += (double)pk;
-            }
-        }
-        a = block_sum_d(a, sh);
-        ps = block_sum_d(ps, sh);
-        if (threadIdx.x == 0) {
-            I.kl_part[2 * lb] = a;
-            I.kl_part[2 * lb + 1] = ps;
-        }
-    }
-    VB_END
-}
-
+// C = sum p_ij log(p_ij / q_ij) with q_ij = K1_ij / Z (Section 1.1), split as
+// sum p log(p (1 + |y_i - y_j|^2)) + (sum p) log Z: the attraction kernel's
+// divergence mode leaves the first two sums as FP64 partials per block; this
+// kernel adds them in block order and applies the Z of the same call.
 __global__ __launch_bounds__(256) void k_klsum(LaunchMap map)
 {
     __shared__ double sh[8];
@@ -610,7 +565,6 @@ static hipError_t launch_attr(int kind, const Cfg& c, const LaunchMap& map, cons
         else if (c.lpr == 32) hipLaunchKernelGGL((k_attr<T, S, 32, 3, true, PK, true>), g, b, 0, st, map);
         else hipLaunchKernelGGL((k_attr<T, S, 64, 2, true, PK, true>), g, b, 0, st, map);
         break;
-    case K_KL: hipLaunchKernelGGL((k_kl<T, S>), g, b, 0, st, map); break;
     case K_KLSUM: hipLaunchKernelGGL(k_klsum, g, b, 0, st, map); break;
     case K_ATTR_T:
         if (l.lds > 48 * 1024)

@@ -1063,7 +1063,7 @@ hipError_t launch_kind(int kind, const Cfg& c, const LaunchMap& map, const Launc
         return launch_fft_kind(kind, c, map, l, st);
     case K_ATTR: case K_ATTR_ALL: case K_ATTR_T: case K_ATTR_T_ALL: case K_ASUM: case K_KL_ATTR:
     case K_KL_T:
-    case K_KL: case K_KLSUM:
+    case K_KLSUM:
         return launch_attr_kind(kind, c, map, l, st);
     case K_KEY: case K_HIST1: case K_HIST2: case K_TSCAN0: case K_TSCAN1: case K_TSCAN2:
     case K_SORT0: case K_SORT1: case K_SORT2: case K_BOUNDS: case K_SCAN_A: case K_SCAN_B:

@@ -285,7 +285,6 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     // one partial per block of the attraction kernel's divergence mode
     if (vb[K_KL_ATTR] > 0) o.nb_kl = std::min(vb[K_KL_ATTR], kGridCap);
     if (vb[K_KL_T] > 0) o.nb_kl = std::min(vb[K_KL_T], kGridCap);
-    vb[K_KL] = (d->nnz > 0 && vb[K_KL_ATTR] == 0 && vb[K_KL_T] == 0) ? o.nb_kl : 0;
     vb[K_KLSUM] = (d->nnz > 0) ? 1 : 0;
 
     // workspace layout
@@ -879,7 +878,7 @@ tsne_status tsne_kl_divergence(tsne_plan* pl, const void* Y, double* kl)
     if (s != TSNE_OK) return s;
     s = enqueue_repulsion(pl, false);
     if (s != TSNE_OK) return s;
-    s = enqueue(pl, pl->o.vb[K_KL_ATTR] > 0 ? K_KL_ATTR : pl->o.vb[K_KL_T] > 0 ? K_KL_T : K_KL);
+    s = enqueue(pl, pl->o.vb[K_KL_T] > 0 ? K_KL_T : K_KL_ATTR);
     if (s != TSNE_OK) return s;
     return enqueue(pl, K_KLSUM);
 }

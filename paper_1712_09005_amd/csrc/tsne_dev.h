@@ -37,7 +37,7 @@ enum Kind : int {
     K_ARGS = 0, K_BOX, K_KEY, K_SORT0, K_SORT1, K_SORT2, K_BOUNDS, K_SCAN_A, K_SCAN_B, K_SPREAD, K_FIX,
     K_FFT_ROWS, K_FFT_COLS, K_FFT_IROWS, K_FFT_1D, K_GATHER, K_NORM, K_ATTR,
     K_UPDATE, K_SPEC0, K_SPEC1, K_SPEC2, K_GEOM, K_ZSUM, K_ATTR_ALL, K_ASUM, K_ATTR_T, K_ATTR_T_ALL,
-    K_KL, K_KLSUM, K_KL_ATTR, K_HIST1, K_HIST2, K_TSCAN0, K_TSCAN1, K_TSCAN2,
+    K_KLSUM, K_KL_ATTR, K_HIST1, K_HIST2, K_TSCAN0, K_TSCAN1, K_TSCAN2,
     K_F3_X, K_F3_Y, K_F3_Z, K_F3_IY, K_F3_IX, K_S3_FILL, K_S3_X, K_S3_Y, K_S3_Z, K_S3_STORE,
     K_SPREAD3, K_GATHER3, K_KL_T, K_NKINDS
 };
