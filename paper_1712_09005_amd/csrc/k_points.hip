@@ -63,15 +63,27 @@ __global__ __launch_bounds__(256) void k_box(LaunchMap map)
         double bad = 0.0;
 #pragma unroll
         for (int d = 0; d < S; ++d) { lo[d] = INFINITY; hi[d] = -INFINITY; sm[d] = 0.0; }
-        for (int64_t i = (int64_t)lb * 256 + threadIdx.x; i < n; i += (int64_t)nb * 256) {
-            const Pt<T, S> y = Pt<T, S>::load(Y, i);
+        // four points a round, their loads in flight together (a point past
+        // n loads the round's first point and is not counted)
+        const int64_t stride = (int64_t)nb * 256;
+        for (int64_t i0 = (int64_t)lb * 256 + threadIdx.x; i0 < n; i0 += 4 * stride) {
+            Pt<T, S> y[4];
 #pragma unroll
-            for (int d = 0; d < S; ++d) {
-                const double v = (double)y.v[d];
-                if (!isfinite(v)) bad = 1.0;
-                lo[d] = fmin(lo[d], v);
-                hi[d] = fmax(hi[d], v);
-                sm[d] += v;
+            for (int q = 0; q < 4; ++q) {
+                const int64_t i = i0 + q * stride;
+                y[q] = Pt<T, S>::load(Y, i < n ? i : i0);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (i0 + q * stride >= n) continue;
+#pragma unroll
+                for (int d = 0; d < S; ++d) {
+                    const double v = (double)y[q].v[d];
+                    if (!isfinite(v)) bad = 1.0;
+                    lo[d] = fmin(lo[d], v);
+                    hi[d] = fmax(hi[d], v);
+                    sm[d] += v;
+                }
             }
         }
 #pragma unroll
@@ -172,12 +184,15 @@ __global__ __launch_bounds__(256) void k_geom(LaunchMap map)
     VB_BEGIN(map, K_GEOM)
     Geom& G = *I.geom;
     const bool run = live_pre(I);
+    // the record's fields through the constant view: scalar loads, issued
+    // together instead of one round trip after each store to the geometry
+    const TSNE_CONST Inst& R = *cview<Inst>(&I);
     if (run) {
-        const int nb = I.nb_box;
+        const int nb = R.nb_box;
         double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
         double sm[3] = {0.0, 0.0, 0.0}, bad = 0.0;
         for (int b = threadIdx.x; b < nb; b += 256) {
-            const double* pp = I.box_part + (int64_t)b * kBoxPart;
+            const double* pp = R.box_part + (int64_t)b * kBoxPart;
             for (int d = 0; d < S; ++d) {
                 lo[d] = fmin(lo[d], pp[d]);
                 hi[d] = fmax(hi[d], pp[4 + d]);
@@ -217,55 +232,55 @@ __global__ __launch_bounds__(256) void k_geom(LaunchMap map)
             double L = 0.0;
             for (int d = 0; d < S; ++d) {
                 if (ghi[d] - glo[d] > L) L = ghi[d] - glo[d];
-                G.mean[d] = gsm[d] / (double)I.n;
+                G.mean[d] = gsm[d] / (double)R.n;
             }
             if (gbad != 0.0) st = ST_NONFINITE;
             if (L < 1e-6) L = 1e-6;
             int m;
             double w;
-            if (I.policy == 0) {
+            if (R.policy == 0) {
                 m = (int)fmin(ceil(L), 2.0e9);
-                if (m < I.min_int) m = I.min_int;
+                if (m < R.min_int) m = R.min_int;
                 w = L / m;
-            } else if (L < I.interval_width * I.min_int) {
+            } else if (L < R.interval_width * R.min_int) {
                 // a box narrower than min_int intervals: shrink the intervals
                 // to L / min_int, as the paper's interval count does
-                m = I.min_int;
+                m = R.min_int;
                 w = L / m;
             } else {
-                w = I.interval_width;
+                w = R.interval_width;
                 m = (int)fmin(ceil(L / w), 2.0e9);
-                if (m < I.min_int) m = I.min_int;
+                if (m < R.min_int) m = R.min_int;
             }
-            if (st == 0 && m > I.max_int) st = ST_CAPACITY;
+            if (st == 0 && m > R.max_int) st = ST_CAPACITY;
             if (st != 0) {
-                *I.status = st;            // latched; the iteration is not committed
+                *R.status = st;            // latched; the iteration is not committed
                 G.active = 0;
             } else {
                 G.active = 1;
-                G.it = *I.iter;
-                if (I.counting) *I.iter = G.it + 1;
+                G.it = *R.iter;
+                if (R.counting) *R.iter = G.it + 1;
                 G.side = L;
                 G.w = w;
                 G.inv_w = 1.0 / w;
-                G.h = w / I.p;
+                G.h = w / R.p;
                 // per-axis interval counts: the square box, or a rectangle of
                 // the same spacing whose narrower axes get their own counts
                 int ma[3] = {m, m, m};
                 for (int d = 0; d < S; ++d) {
                     const double Ld = ghi[d] - glo[d];
-                    if (I.rect && S == 2 && Ld < L) {
+                    if (R.rect && S == 2 && Ld < L) {
                         int md = (int)ceil(Ld / w);
-                        if (md < I.min_int) md = I.min_int;
+                        if (md < R.min_int) md = R.min_int;
                         if (md > m) md = m;
                         ma[d] = md;
                     }
                 }
                 G.n_int = ma[0];
-                G.n = ma[0] * I.p;
+                G.n = ma[0] * R.p;
                 // s = 3 has the square box only: every axis has n_int intervals
                 G.n_int_y = (S >= 2) ? ma[1] : 1;
-                G.n_y = (S >= 2) ? ma[1] * I.p : 1;
+                G.n_y = (S >= 2) ? ma[1] * R.p : 1;
                 G.n_cells = (S == 3) ? ma[0] * ma[1] * ma[2] : (S == 2) ? ma[0] * ma[1] : ma[0];
                 // explicit roundings (no contraction) so the origin is the
                 // correctly rounded value of mid - (m/2) w
@@ -277,13 +292,13 @@ __global__ __launch_bounds__(256) void k_geom(LaunchMap map)
                 // power-of-two charge scale: |(y - centre) * qscale| < 1
                 G.qscale = ldexp(1.0, -(ilogb(0.5 * m * w) + 1));
                 // circulant lengths with hysteresis, per axis
-                axis_plan(G.n, I.M, G.M, G.half, G.nstages, G.radix, G.tw_off);
+                axis_plan(G.n, R.M, G.M, G.half, G.nstages, G.radix, G.tw_off);
                 if (S == 2 &&
-                    axis_plan(G.n_y, I.M, G.My, G.half_y, G.nstages_y, G.radix_y, G.tw_off_y)) {
+                    axis_plan(G.n_y, R.M, G.My, G.half_y, G.nstages_y, G.radix_y, G.tw_off_y)) {
                     // columns per block: as many as the LDS holds (power of two)
-                    const int csz = 2 * ((I.tile_w == 16) ? 4 : 8);
-                    int g = I.tile_w;
-                    while (g > 1 && (int64_t)g * lds_stride(G.My) * csz > I.col_lds) g >>= 1;
+                    const int csz = 2 * ((R.tile_w == 16) ? 4 : 8);
+                    int g = R.tile_w;
+                    while (g > 1 && (int64_t)g * lds_stride(G.My) * csz > R.col_lds) g >>= 1;
                     G.col_group = g;
                 }
                 G.spec_dirty = (G.h != G.spec_h || G.M != G.spec_M || (S == 2 && G.My != G.spec_My)) ? 1 : 0;
@@ -293,7 +308,7 @@ __global__ __launch_bounds__(256) void k_geom(LaunchMap map)
                 // radix sort of this iteration: digit width for the cell count
                 const int nc1 = G.n_cells - 1;
                 const int bits = (nc1 > 0) ? 32 - __clz(nc1) : 1;
-                G.sort_bits = (bits + I.npass - 1) / I.npass;
+                G.sort_bits = (bits + R.npass - 1) / R.npass;
             }
         }
     } else if (threadIdx.x == 0) {
