@@ -115,14 +115,17 @@ typedef struct {
     int32_t points_per_lane; /* spreading points per lane: 0 (auto), 1..64 */
     int32_t attr_slabs;      /* CSR layout: column slabs of P, 0 (auto), 1, 2, 4 or 8;
                                 each slab is handled by 8/slabs of the 8 XCDs */
-    int32_t attr_layout;     /* attraction: 0 auto, 1 CSR rows (lanes per row over
-                                the bound CSR), 2 row blocks (P re-bucketed at bind
-                                time by row block and 32 KB column window; each
+    int32_t attr_layout;     /* attraction: 1 CSR rows (lanes per row over the bound
+                                CSR), 2 row blocks (P re-bucketed at bind time by
+                                blocks of about n/256 rows, at most 3968 (FP32) or
+                                1984 (FP64), and 32 KB column windows; each
                                 workgroup keeps its rows in LDS and sweeps the
                                 windows its non-zeros touch, staged in LDS; row
                                 sums in 64-bit fixed point, so the result does not
-                                depend on timing).  Layout 2 needs s <= 2; binding
-                                P then also rejects non-finite values (TSNE_E_ARG) */
+                                depend on timing).  0 auto: row blocks when s <= 2,
+                                n >= 100,000 and lanes_per_row and attr_slabs are
+                                0, else CSR rows.  Layout 2 needs s <= 2; binding P
+                                then also rejects non-finite values (TSNE_E_ARG) */
     int32_t rect;            /* box shape (s = 2): 0 the square box of Section 2.4;
                                 1 a rectangle of equal spacing: the widest axis
                                 keeps the policy's N_int and w, a narrower axis d

@@ -168,17 +168,25 @@ tsne_status derive(const tsne_desc* d, Derived& o)
         o.slabs = sl;
         o.slab_w = (int)((d->n + sl - 1) / sl);
     }
-    // attraction layout: CSR rows unless tiles are asked for.  Tiles: each
-    // workgroup takes a block of tile_bi rows (their positions and 64-bit
-    // fixed-point force sums in LDS) and sweeps column windows of 32 KB
-    // (tile_bj points), double-buffered in LDS; the LDS then holds
-    // tile_bi s (8 + element) + 64 KB bytes (157 KB for FP32 in 2-D).
+    // attraction layout: CSR rows or row blocks.  Row blocks: each workgroup
+    // takes a block of tile_bi rows (their positions and 64-bit fixed-point
+    // force sums in LDS) and sweeps column windows of 32 KB (tile_bj points),
+    // double-buffered in LDS; the LDS then holds tile_bi s (8 + element) +
+    // 64 KB bytes (157 KB for FP32 in 2-D at 3968 rows).
     // Sweep steps are the non-empty (row block, window) tiles, a tile with
     // more than kTileStepEdges edges taking several steps.
-    o.tiled = (d->nnz > 0) && d->attr_layout == 2;
+    // automatic layout (no CSR knob given): row blocks from 100,000 points in
+    // one or two dimensions, where they matched or beat the best CSR rows
+    // (N = 1e5 to 1e6, FP32 and FP64, random 90-neighbour P)
+    const bool auto_rows = d->attr_layout == 0 && d->lanes_per_row == 0 && d->attr_slabs == 0 &&
+                           d->s <= 2 && d->n >= 100000;
+    o.tiled = (d->nnz > 0) && (d->attr_layout == 2 || auto_rows);
     {
         const int tsz_ = (d->dtype == TSNE_F32) ? 4 : 8;
-        o.tile_bi = (d->dtype == TSNE_F32) ? 3968 : 1984;
+        // rows per block: enough blocks for every CU (about n / 256, a
+        // multiple of 64), at most what the LDS holds beside the windows
+        const int64_t cap_bi = (d->dtype == TSNE_F32) ? 3968 : 1984;
+        o.tile_bi = (int)std::min<int64_t>(cap_bi, std::max<int64_t>(64, 64 * cdiv(cdiv(d->n, 256), 64)));
         o.tile_bj = kTileWindowBytes / (d->s * tsz_);
         o.tile_ni = (int)((d->n + o.tile_bi - 1) / o.tile_bi);
         o.tile_nj = (int)((d->n + o.tile_bj - 1) / o.tile_bj);

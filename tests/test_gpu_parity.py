@@ -329,10 +329,10 @@ def test_attraction(T, dtype, lpr, slabs, layout, n, s):
 @pytest.mark.parametrize("s", [1, 2])
 def test_attraction_row_blocks_sparse(T, dtype, s):
     """The row-block sweep (layout 2) where whole row blocks and many rows have
-    no non-zeros: rows 3000..8199 of 9000 have none, so with 3968-row blocks
-    (FP32) or 1984-row blocks (FP64) some blocks sweep no window at all.  Those
-    rows get exactly zero, the rest match the oracle, and a second call gives
-    the same bits (the row sums are fixed point)."""
+    no non-zeros: rows 3000..8199 of 9000 have none, so with 64-row blocks at
+    this n some 80 blocks sweep no window at all.  Those rows get exactly zero,
+    the rest match the oracle, and a second call gives the same bits (the row
+    sums are fixed point)."""
     print("case: attraction row blocks with empty blocks %s s=%d" % (dtype, s), flush=True)
     n = 9000
     rng = np.random.default_rng(11)
