@@ -123,7 +123,7 @@ typedef struct {
                                 windows its non-zeros touch, staged in LDS; row
                                 sums in 64-bit fixed point, so the result does not
                                 depend on timing).  0 auto: row blocks when s <= 2,
-                                n >= 100,000 and lanes_per_row and attr_slabs are
+                                n >= 300,000 and lanes_per_row and attr_slabs are
                                 0, else CSR rows.  Layout 2 needs s <= 2; binding P
                                 then also rejects non-finite values (TSNE_E_ARG) */
     int32_t rect;            /* box shape (s = 2): 0 the square box of Section 2.4;

@@ -283,7 +283,7 @@ __device__ __forceinline__ typename Vec<T, S>::t gpoint(const void* base, int64_
 // arranged for LDS): each virtual block takes tile_bi rows, keeps their
 // positions and force sums in LDS and sweeps the column windows (tile_bj
 // points, 32 KB) that hold its non-zeros, in the sweep steps fixed at bind
-// time (one step: at most kTileStepEdges non-zeros of one window, rows
+// time (one step: at most tile_step_edges non-zeros of one window, rows
 // increasing).  Windows are double-buffered in LDS: step t takes its
 // non-zeros against buffer t mod 2 and stores window t + 1 (requested a step
 // earlier) into the other buffer, while window t + 2 and the non-zeros of
@@ -303,8 +303,8 @@ __global__ __launch_bounds__(1024) void k_attr_tile(LaunchMap map)
 {
     typedef typename Vec<T, S>::t V;
     constexpr int NT = 1024;
-    constexpr int UE = kTileStepEdges / NT;                             // non-zeros per thread and step
     constexpr int WQ = kTileWindowBytes / (S * (int)sizeof(T)) / NT;     // window points per thread
+    constexpr int UE = tile_step_edges(WQ * NT) / NT;                   // non-zeros per thread and step
     extern __shared__ __align__(16) char smem[];
     __shared__ double klsh[NT / 64];
     double kla = 0.0, klp = 0.0;

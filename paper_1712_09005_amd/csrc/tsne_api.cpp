@@ -174,12 +174,13 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     // double-buffered in LDS; the LDS then holds tile_bi s (8 + element) +
     // 64 KB bytes (157 KB for FP32 in 2-D at 3968 rows).
     // Sweep steps are the non-empty (row block, window) tiles, a tile with
-    // more than kTileStepEdges edges taking several steps.
-    // automatic layout (no CSR knob given): row blocks from 100,000 points in
-    // one or two dimensions, where they matched or beat the best CSR rows
-    // (N = 1e5 to 1e6, FP32 and FP64, random 90-neighbour P)
+    // more than tile_step_edges(tile_bj) edges taking several steps.
+    // automatic layout (no CSR knob given): row blocks from 300,000 points in
+    // one or two dimensions, where they beat the best CSR rows by 15 % or more
+    // (random 90-neighbour P, FP32 and FP64).  At 1e5 the two are level on
+    // random P and CSR rows win on a kNN P, whose columns cluster by row.
     const bool auto_rows = d->attr_layout == 0 && d->lanes_per_row == 0 && d->attr_slabs == 0 &&
-                           d->s <= 2 && d->n >= 100000;
+                           d->s <= 2 && d->n >= 300000;
     o.tiled = (d->nnz > 0) && (d->attr_layout == 2 || auto_rows);
     {
         const int tsz_ = (d->dtype == TSNE_F32) ? 4 : 8;
@@ -191,7 +192,8 @@ tsne_status derive(const tsne_desc* d, Derived& o)
         o.tile_ni = (int)((d->n + o.tile_bi - 1) / o.tile_bi);
         o.tile_nj = (int)((d->n + o.tile_bj - 1) / o.tile_bj);
         o.tile_lds = (size_t)o.tile_bi * d->s * (8 + tsz_) + 2 * (size_t)kTileWindowBytes;
-        o.tile_steps = (int64_t)o.tile_ni * o.tile_nj + (d->nnz + kTileStepEdges - 1) / kTileStepEdges;
+        const int se = tile_step_edges(o.tile_bj);
+        o.tile_steps = (int64_t)o.tile_ni * o.tile_nj + (d->nnz + se - 1) / se;
     }
     if (o.tiled && o.tile_steps > ((int64_t)1 << 30)) return TSNE_E_UNSUPPORTED;   // int step indices
     if (o.tiled) o.slabs = 1;
@@ -744,7 +746,7 @@ tsne_status tsne_bind_P(tsne_plan* pl, const int64_t* row_ptr, const int32_t* co
         }
         // tiles: edges bucketed by (row block, column window), rows increasing
         // within a tile; the sweep steps of each row block are its non-empty
-        // tiles in window order, split into runs of at most kTileStepEdges
+        // tiles in window order, split into runs of at most tile_step_edges
         if (pl->o.tiled) {
             const Derived& o = pl->o;
             const int64_t nnz = pl->d.nnz;
@@ -767,7 +769,7 @@ tsne_status tsne_bind_P(tsne_plan* pl, const int64_t* row_ptr, const int32_t* co
                 tsb[I] = (int)tsj.size();
                 for (int J = 0; J < o.tile_nj; ++J) {
                     const int64_t c = cnt[J];
-                    for (int64_t q = 0; q < c; q += kTileStepEdges) {
+                    for (int64_t q = 0; q < c; q += tile_step_edges(o.tile_bj)) {
                         tsj.push_back(J);
                         tse.push_back(cur + q);
                     }

@@ -23,7 +23,12 @@ constexpr int kWave = 64;
 constexpr int kBoxPart = 16;      // doubles per block of the box partials
 constexpr int kUpdPts = 4;              // points per thread of the update kernel
 constexpr int kTileWindowBytes = 32768;   // one LDS column window of the tiled attraction
-constexpr int kTileStepEdges = 2048;      // edges per sweep step (1024 threads x 2)
+// non-zeros per sweep step of the tiled attraction: 1024 threads x 2, or x 3
+// when a column window holds 8192 points (FP32 in 1-D).  A tile (about n/256
+// rows by one window) holds about k w / 256 non-zeros for k per row and w
+// points per window: 1440 at k = 90 and w = 4096, 2880 at w = 8192, which
+// would take two steps of 2048.
+constexpr int tile_step_edges(int window_points) { return window_points >= 8192 ? 3072 : 2048; }
 constexpr int kKeyTile = 2048;     // points per block of the key kernel (256 threads x 8)
 constexpr int kSortTile = 2048;    // points per tile of a sort pass (256 threads x 8)
 constexpr int kScanDigits = 64;    // digits per block of the tile-offset scan (a lane each)
