@@ -95,15 +95,13 @@ template <typename T> struct Dft<T, 5> {
     }
 };
 
-// floor(x / d) for 0 <= x < 2^24 and 0 < d < 2^15, with rd = 1/d in float:
-// the float estimate is within one of the quotient, one correction fixes it.
-__device__ __forceinline__ int fdiv(int x, int d, float rd)
+// floor(j / d) for 0 <= j < 2^21 and 0 < d < 2^21, with h = 1 / (2 d) to
+// within one ulp: (j + 1/2) / d lies at least 1 / (2 d) from every integer,
+// and the float product (2 j + 1) h is within (j + 1/2) 2^-22 / d of it, which
+// is less, so truncating it gives the quotient with no correction step.
+__device__ __forceinline__ int fdiv(int j, float h)
 {
-    int q = (int)((float)x * rd);
-    const int r = x - q * d;
-    if (r < 0) q -= 1;
-    else if (r >= d) q += 1;
-    return q;
+    return (int)((float)(2 * j + 1) * h);
 }
 
 // One Stockham stage of radix R over G transforms of length M stored at
@@ -116,14 +114,15 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int M, int PM, int G, in
                                           const cplx<T>* __restrict__ tws)
 {
     const int Mr = M / R;
-    const float rNs = 1.0f / (float)Ns;
+    const float hNs = 0.5f * __builtin_amdgcn_rcpf((float)Ns);   // 1 / (2 Ns), one ulp
     // the threads split evenly over the G transforms (G and the block size are
     // powers of two), so a thread's transform is fixed for the whole stage
-    const int tpc = (int)blockDim.x / G;
-    const int g = (int)threadIdx.x >> (__ffs(tpc) - 1);
-    const int jt = (int)threadIdx.x - g * tpc;
-    const int nbt = (Mr + tpc - 1) / tpc;
-    const cplx<T>* src = buf + g * PM;
+    const int lt = __ffs((int)blockDim.x) - __ffs(G);   // log2 of the threads per transform
+    const int tpc = 1 << lt;
+    const int g = (int)threadIdx.x >> lt;
+    const int jt = (int)threadIdx.x & (tpc - 1);
+    const int nbt = (Mr + tpc - 1) >> lt;
+    const cplx<T>* src = buf + __mul24(g, PM);
     cplx<T> v[kMaxB][R];
     int dst[kMaxB];
 #pragma unroll
@@ -132,8 +131,7 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int M, int PM, int G, in
         const int j = jt + b * tpc;
         dst[b] = -1;
         if (j < Mr) {
-            const int a = fdiv(j, Ns, rNs);
-            const int k = j - a * Ns;
+            const int k = j - __mul24(fdiv(j, hNs), Ns);   // j = a Ns + k
 #pragma unroll
             for (int r = 0; r < R; ++r) v[b][r] = src[lds_pad(j + r * Mr)];
             if (Ns > 1) {
@@ -143,17 +141,22 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int M, int PM, int G, in
                 for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], gload_c<T>(tws, k * (R - 1) + r - 1));
             }
             Dft<T, R>::run(v[b]);
-            dst[b] = a * Ns * R + k;
+            dst[b] = __mul24(j - k, R) + k;            // a Ns R + k
         }
     }
     __syncthreads();
-    cplx<T>* out = buf + g * PM;
+    cplx<T>* out = buf + __mul24(g, PM);
+    // the outputs' offsets r Ns, uniform: scalar registers, added to the
+    // thread's index (else the compiler folds them into 64-bit multiply-adds)
+    int rns[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) rns[r] = __builtin_amdgcn_readfirstlane(r * Ns);
 #pragma unroll
     for (int b = 0; b < kMaxB; ++b) {
         if (b >= nbt) break;
         if (dst[b] >= 0) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) out[lds_pad(dst[b] + r * Ns)] = v[b][r];
+            for (int r = 0; r < R; ++r) out[lds_pad(dst[b] + rns[r])] = v[b][r];
         }
     }
     __syncthreads();
@@ -223,8 +226,12 @@ template <int S, int FORM> struct Pots {
 
 // ---------------------------------------------------------------- 2-D passes
 
+// Row passes (512 or 1024 threads): FP32 kernels are held to 80 registers, six
+// waves per SIMD, where the compiler would take a few more and fit five.
+template <typename T> constexpr int kRowWaves = (sizeof(T) == 4) ? 6 : 4;
+
 template <typename T, int P>
-__global__ __launch_bounds__(1024) void k_fft_rows(LaunchMap map)
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kRowWaves<T>))) void k_fft_rows(LaunchMap map)
 {
     extern __shared__ __align__(16) char smem[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
@@ -277,8 +284,10 @@ __global__ __launch_bounds__(1024) void k_fft_rows(LaunchMap map)
                 const cplx<T> A = {(z.x + zc.x) * hlf, (z.y - zc.y) * hlf};
                 const cplx<T> B = {(z.y + zc.y) * hlf, (zc.x - z.x) * hlf};
                 const int tile = k >> ltw, kk = k & (tw_ - 1);
-                X[((int64_t)tile * n_cap + ra) * tw_ + kk] = A;
-                if (rb < ny) X[((int64_t)tile * n_cap + rb) * tw_ + kk] = B;
+                // within one channel every offset fits 31 bits (n_cap <= 6144)
+                const int off = __mul24(tile, n_cap * tw_) + kk;
+                X[off + ra * tw_] = A;
+                if (rb < ny) X[off + rb * tw_] = B;
             }
             __syncthreads();
         }
@@ -335,13 +344,13 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
                 const int idx = i0 + u * nthr;
                 const int r = idx >> lgc, g = idx & (Gc - 1);
                 v[u] = {(T)0, (T)0};
-                if (idx < nel && k00 + g < half && r < n) v[u] = gload_c<T>(X, t0 + (int64_t)r * tw_ + g);
+                if (idx < nel && k00 + g < half && r < n) v[u] = gload_c<T>(X, t0 + (__mul24(r, tw_) + g));
             }
 #pragma unroll
             for (int u = 0; u < kLd; ++u) {
                 const int idx = i0 + u * nthr;
                 const int r = idx >> lgc, g = idx & (Gc - 1);
-                if (idx < nel) buf[g * PM + lds_pad(r)] = v[u];
+                if (idx < nel) buf[__mul24(g, PM) + lds_pad(r)] = v[u];
             }
         }
         __syncthreads();
@@ -354,7 +363,7 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
             const int jt = (int)threadIdx.x - g * tpc;
             const int k0 = k00 + g;
             const T* sp = static_cast<const T*>(I.spec) + (int64_t)kern * kslot + (int64_t)k0 * half_y;
-            cplx<T>* col = buf + g * PM;
+            cplx<T>* col = buf + __mul24(g, PM);
             // the spectrum's values kLd at a time, loaded before they are used
             for (int kb = jt; kb < M; kb += kLd * tpc) {
                 T sv[kLd];
@@ -383,7 +392,7 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
         cplx<T>* Xc = static_cast<cplx<T>*>(I.Xc) + (int64_t)pot * I.ntiles * n_cap * tw_;
         for (int idx = threadIdx.x; idx < (n << lgc); idx += blockDim.x) {
             const int r = idx >> lgc, g = idx & (Gc - 1);
-            if (k00 + g < half) gstore_c<T>(Xc, t0 + (int64_t)r * tw_ + g, cconj(buf[g * PM + lds_pad(r)]));
+            if (k00 + g < half) gstore_c<T>(Xc, t0 + (__mul24(r, tw_) + g), cconj(buf[__mul24(g, PM) + lds_pad(r)]));
         }
         __syncthreads();
         }
@@ -392,7 +401,7 @@ __global__ __launch_bounds__(1024) void k_fft_cols(LaunchMap map)
 }
 
 template <typename T, int S, int NP>
-__global__ __launch_bounds__(1024) void k_fft_irows(LaunchMap map)
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kRowWaves<T>))) void k_fft_irows(LaunchMap map)
 {
     extern __shared__ __align__(16) char smem[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
@@ -838,8 +847,11 @@ __device__ __forceinline__ double kern3(int kern, double r2)
 __device__ __forceinline__ int lag3(int j, int M) { return (2 * j <= M) ? j : j - M; }
 
 // One pass of the 3-D convolution (T: the element type of the pass).
+// FP32: at most 128 registers (four waves per SIMD); FP64 kernels take two.
+template <typename T> constexpr int kF3Waves = (sizeof(T) == 4) ? 4 : 2;
+
 template <typename T, int FORM, int MODE>
-__global__ __launch_bounds__(kSeq3 * 32) void k_f3(LaunchMap map)
+__global__ __launch_bounds__(kSeq3 * 32) __attribute__((amdgpu_waves_per_eu(kF3Waves<T>))) void k_f3(LaunchMap map)
 {
     constexpr int AXIS = F3Kind<MODE>::AXIS;
     constexpr bool SPEC = MODE >= S3_X;
@@ -923,7 +935,7 @@ __global__ __launch_bounds__(kSeq3 * 32) void k_f3(LaunchMap map)
                     } else if (wanted(a, b)) {
                         v = src[base + (int64_t)r * stride];
                     }
-                    buf[q * PM + lds_pad(r)] = v;
+                    buf[__mul24(q, PM) + lds_pad(r)] = v;
                 }
                 __syncthreads();
                 const C* tw = SPEC ? static_cast<const C*>(I.twd) : static_cast<const C*>(I.tw);
@@ -938,8 +950,8 @@ __global__ __launch_bounds__(kSeq3 * 32) void k_f3(LaunchMap map)
                         int64_t base, stride;
                         seq(j0 + q, a, b, base, stride);
                         const T sv = sp[base + (int64_t)r * stride];
-                        const C v = buf[q * PM + lds_pad(r)];
-                        buf[q * PM + lds_pad(r)] = {v.x * sv, -v.y * sv};
+                        const C v = buf[__mul24(q, PM) + lds_pad(r)];
+                        buf[__mul24(q, PM) + lds_pad(r)] = {v.x * sv, -v.y * sv};
                     }
                     __syncthreads();
                     block_fft_tw<T>(buf, kSeq3, M, G.nstages, G.radix, G.tw_off, tw);
@@ -951,7 +963,7 @@ __global__ __launch_bounds__(kSeq3 * 32) void k_f3(LaunchMap map)
                     int a, b;
                     int64_t base, stride;
                     seq(j0 + q, a, b, base, stride);
-                    const C v = buf[q * PM + lds_pad(r)];
+                    const C v = buf[__mul24(q, PM) + lds_pad(r)];
                     if (MODE == F3_IX) {
                         if (a < n && b < n && r < n)
                             static_cast<T*>(I.V)[(((int64_t)g * n_cap + a) * n_cap + b) * n_cap + r] = v.x;
