@@ -357,6 +357,60 @@ def test_attraction_row_blocks_sparse(T, dtype, s):
     assert rel(Fa, ref) < (1e-6 if dtype == torch.float32 else 1e-13)
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("s", [1, 2])
+def test_attraction_row_blocks_step_splits(T, dtype, s):
+    """The row-block sweep cuts a tile's non-zeros into steps of 2048 (3072
+    where a 32 KB window holds 8192 points: FP32 in 1-D).  Three tiles hold
+    exactly two steps, one step and one non-zero, and one non-zero short of a
+    step; the remaining rows get random non-zeros.  Against the oracle, and the
+    same bits on a second call."""
+    n = 20000
+    el = 4 if dtype == torch.float32 else 8
+    wpts = 32768 // (s * el)                         # points per column window
+    step = 3072 if wpts >= 8192 else 2048
+    bi = 64 * -(-(-(-n // 256)) // 64)               # rows per block at this n: 128
+    print("case: attraction step splits %s s=%d step=%d" % (dtype, s, step), flush=True)
+    rng = np.random.default_rng(17)
+    rs, cs = [], []
+    # windows past the first: no tile of these rows meets the diagonal
+    wins = (1, 2, 1)
+    for blk, win, cnt in ((0, wins[0], 2 * step), (1, wins[1], step + 1), (2, wins[2], step - 1)):
+        r0, c0 = blk * bi, win * wpts
+        ncol = min(wpts, n - c0)
+        cells = rng.choice(bi * ncol, cnt, replace=False)
+        r, c = r0 + cells // ncol, c0 + cells % ncol
+        keep = r != c
+        rs.append(r[keep])
+        cs.append(c[keep])
+    r = rng.integers(3 * bi, n, 40000)
+    c = rng.integers(0, n, 40000)
+    keep = r != c
+    rs.append(r[keep])
+    cs.append(c[keep])
+    r, c = np.concatenate(rs), np.concatenate(cs)
+    import scipy.sparse as sp
+    a = sp.csr_matrix((np.exp(-rng.uniform(0, 5, r.size)), (r, c)), shape=(n, n))
+    a.sum_duplicates()
+    a.sort_indices()
+    P = inputs.CSR(a.indptr.astype(np.int64), a.indices.astype(np.int32),
+                   (a.data / a.data.sum()).astype(np.float32))
+    tiles = [np.count_nonzero((P.col[P.row_ptr[k * bi]:P.row_ptr[(k + 1) * bi]] // wpts) == wins[k])
+             for k in range(3)]
+    assert tiles == [2 * step, step + 1, step - 1]
+    Y = inputs.mixture_embedding(n, s, 10, -30, 30, 2.0, seed=3)
+    plan = T.Plan(n, s, dtype, nnz=P.nnz, attr_layout=2, max_intervals=128, device=DEV)
+    plan.bind_P(torch.from_numpy(P.row_ptr).to(DEV), torch.from_numpy(P.col).to(DEV),
+                torch.from_numpy(P.val).to(DEV, dtype))
+    Yt = torch.from_numpy(Y).to(DEV, dtype)
+    Fa1 = plan.attractive(Yt)
+    Fa2 = plan.attractive(Yt)
+    torch.cuda.synchronize()
+    assert torch.equal(Fa1, Fa2)
+    ref = oracle.attr(Y.astype(np.float64), inputs.CSR(P.row_ptr, P.col, P.val.astype(np.float64)))
+    assert rel(Fa1.cpu().numpy(), ref) < (1e-6 if dtype == torch.float32 else 1e-13)
+
+
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-9), (torch.float32, 1e-4)])
 @pytest.mark.parametrize("form", ["A", "V"])
 def test_step_vs_oracle(T, dtype, tol, form):
