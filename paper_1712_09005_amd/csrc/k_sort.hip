@@ -409,6 +409,7 @@ __global__ __launch_bounds__(256) void k_bounds(LaunchMap map)
 // Exclusive scans of the per-cell item counts (items are runs of at most
 // kpts points of one cell), tile sums first.
 __device__ __forceinline__ int items_of(int count, int kpts) { return (count + kpts - 1) / kpts; }
+static_assert(kScanCells == 256, "a thread per cell of a tile");
 
 __global__ __launch_bounds__(256) void k_scan_a(LaunchMap map)
 {
@@ -416,13 +417,8 @@ __global__ __launch_bounds__(256) void k_scan_a(LaunchMap map)
     VB_BEGIN(map, K_SCAN_A)
     if (live(I)) {
         const int ncell = I.geom->n_cells;
-        const int base = lb * 1024 + threadIdx.x * 4;
-        int it = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int e = base + k;
-            if (e < ncell) it += items_of(I.cell_start[e + 1] - I.cell_start[e], I.kpts);
-        }
+        const int e = lb * kScanCells + threadIdx.x;
+        int it = (e < ncell) ? items_of(I.cell_start[e + 1] - I.cell_start[e], I.kpts) : 0;
         it = wave_sum(it);
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
         __syncthreads();
@@ -451,11 +447,11 @@ __global__ __launch_bounds__(256) void k_scan_b(LaunchMap map)
     __shared__ int sh[4];
     __shared__ int off;
     __shared__ int nbig;
-    __shared__ int big[1024][3];         // (cell, first item, items)
+    __shared__ int big[kScanCells][3];   // (cell, first item, items)
     VB_BEGIN(map, K_SCAN_B)
     if (live(I)) {
         const int ncell = I.geom->n_cells;
-        const int ntile = (ncell + 1023) / 1024;
+        const int ntile = (ncell + kScanCells - 1) / kScanCells;
         if (lb < ntile) {
             // offset of this tile: sum of earlier tile sums
             int oi = 0;
@@ -470,45 +466,35 @@ __global__ __launch_bounds__(256) void k_scan_b(LaunchMap map)
                 nbig = 0;
             }
             __syncthreads();
-            const int base = lb * 1024 + threadIdx.x * 4;
-            int iv[4], it = 0;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int e = base + k;
-                iv[k] = (e < ncell) ? items_of(I.cell_start[e + 1] - I.cell_start[e], I.kpts) : 0;
-                it += iv[k];
-            }
-            const int ii = wave_incl_scan(it);
+            // one cell per thread
+            const int e = lb * kScanCells + threadIdx.x;
+            const int iv = (e < ncell) ? items_of(I.cell_start[e + 1] - I.cell_start[e], I.kpts) : 0;
+            const int ii = wave_incl_scan(iv);
             __syncthreads();
             if (lane == 63) sh[wv] = ii;
             __syncthreads();
             int pi = off;
             for (int w = 0; w < wv; ++w) pi += sh[w];
-            pi += ii - it;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int e = base + k;
-                if (e < ncell) {
-                    I.item_start[e] = pi;
-                    if (iv[k] <= kSerialItems) {
-                        for (int q = 0; q < iv[k]; ++q) I.item_cell[pi + q] = e;
-                    } else {
-                        const int b = atomicAdd(&nbig, 1);   // at most one per cell of the tile
-                        big[b][0] = e;
-                        big[b][1] = pi;
-                        big[b][2] = iv[k];
-                    }
-                    if (e == ncell - 1) I.item_start[ncell] = pi + iv[k];
+            pi += ii - iv;
+            if (e < ncell) {
+                I.item_start[e] = pi;
+                if (iv <= kSerialItems) {
+                    for (int q = 0; q < iv; ++q) I.item_cell[pi + q] = e;
+                } else {
+                    const int b = atomicAdd(&nbig, 1);   // at most one per cell of the tile
+                    big[b][0] = e;
+                    big[b][1] = pi;
+                    big[b][2] = iv;
                 }
-                pi += iv[k];
+                if (e == ncell - 1) I.item_start[ncell] = pi + iv;
             }
             // cells with many items (a small box holding many points): the
             // block's four waves take them in turn, each wave's lanes writing
             // one cell's item -> cell entries
             __syncthreads();
             for (int b = wv; b < nbig; b += 4) {
-                const int e = big[b][0], p0 = big[b][1], m = big[b][2];
-                for (int q = lane; q < m; q += 64) I.item_cell[p0 + q] = e;
+                const int c = big[b][0], p0 = big[b][1], m = big[b][2];
+                for (int q = lane; q < m; q += 64) I.item_cell[p0 + q] = c;
             }
             __syncthreads();
         }

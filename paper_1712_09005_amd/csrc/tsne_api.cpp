@@ -226,7 +226,7 @@ tsne_status derive(const tsne_desc* d, Derived& o)
     o.nb_gather = (d->s == 3) ? cdiv(n, 256)             // s = 3: one thread per point
                               : cdiv(o.items_cap, 256);   // one thread per item
     o.nb_kl = (int)std::min<int64_t>(2048, cdiv(n, 8));
-    o.nb_scan = cdiv(o.ncell_cap, 1024);
+    o.nb_scan = cdiv(o.ncell_cap, kScanCells);
     o.ntiles_sort = cdiv(n, kSortTile);
     // groups of the offset scan: at most kScanGroups, of a multiple of 4 tiles
     o.group_tiles = 4 * cdiv(cdiv(o.ntiles_sort, kScanGroups), 4);

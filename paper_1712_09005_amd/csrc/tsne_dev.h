@@ -31,6 +31,7 @@ constexpr int kTileWindowBytes = 32768;   // one LDS column window of the tiled 
 constexpr int tile_step_edges(int window_points) { return window_points >= 8192 ? 3072 : 2048; }
 constexpr int kKeyTile = 2048;     // points per block of the key kernel (256 threads x 8)
 constexpr int kSortTile = 2048;    // points per tile of a sort pass (256 threads x 8)
+constexpr int kScanCells = 256;   // cells per tile of the item scans (a thread each)
 constexpr int kScanDigits = 64;    // digits per block of the tile-offset scan (a lane each)
 constexpr int kScanGroups = 16;    // at most this many groups of tiles per radix pass
 constexpr int kDigitBitsMax = 9;   // at most 512 digit values per pass
