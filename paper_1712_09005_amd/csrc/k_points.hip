@@ -880,7 +880,7 @@ __global__ __launch_bounds__(256) void k_norm(LaunchMap map)
 
 // ---------------------------------------------------------------- update
 
-__device__ __forceinline__ void sched_at(const Sched& sc, int it, double& alpha, double& mom)
+__device__ __forceinline__ void sched_at(const TSNE_CONST Sched& sc, int it, double& alpha, double& mom)
 {
     if (it >= sc.le_start) alpha = sc.le_alpha;
     else if (it < sc.ee_stop) alpha = sc.ee_alpha;
@@ -896,18 +896,21 @@ __global__ __launch_bounds__(256) void k_update(LaunchMap map)
 {
     VB_BEGIN(map, K_UPDATE)
     if (live(I)) {
-        const Geom& G = *I.geom;
-        const Sched& sc = *I.sched;
+        // the record, geometry and schedule through the constant view: scalar
+        // loads, issued beside the vector loads of the points
+        const TSNE_CONST Inst& Rc = *cview<Inst>(&I);
+        const TSNE_CONST Geom& G = *cview<Geom>(Rc.geom);
+        const TSNE_CONST Sched& sc = *cview<Sched>(Rc.sched);
         double alpha, mom;
         sched_at(sc, G.it, alpha, mom);
         const T invz = (T)(1.0 / G.Z);
-        T* Y = static_cast<T*>(I.Y);
-        T* uY = static_cast<T*>(I.uY);
-        T* gains = static_cast<T*>(I.gains);
-        const T* Fa = static_cast<const T*>(I.Fattr);
-        const T* Fp = static_cast<const T*>(I.Fap);
-        const T* R = static_cast<const T*>(I.R);
-        const int64_t n = I.n, ns = n * S;
+        T* Y = static_cast<T*>(Rc.Y);
+        T* uY = static_cast<T*>(Rc.uY);
+        T* gains = static_cast<T*>(Rc.gains);
+        const T* Fa = static_cast<const T*>(Rc.Fattr);
+        const T* Fp = static_cast<const T*>(Rc.Fap);
+        const T* R = static_cast<const T*>(Rc.R);
+        const int64_t n = Rc.n, ns = n * S;
         // kUpdPts points per thread, 256 apart: all their loads are issued
         // first, then the arithmetic, then the stores; each point's S
         // components move as one vector per array (8 or 16 bytes in 2-D)
@@ -916,7 +919,7 @@ __global__ __launch_bounds__(256) void k_update(LaunchMap map)
 #pragma unroll
         for (int q = 0; q < kUpdPts; ++q) {
             const int64_t i = min(i0 + (int64_t)q * 256, n - 1);   // past n: a repeat, not stored
-            if (I.slabs == 1) {
+            if (Rc.slabs == 1) {
                 fa[q] = Pt<T, S>::load(Fa, i);
             } else {
                 // every slab's partial in flight at once, then summed in slab order
@@ -924,13 +927,13 @@ __global__ __launch_bounds__(256) void k_update(LaunchMap map)
                 Pt<T, S> p[kMaxSlabs];
 #pragma unroll
                 for (int sl = 0; sl < kMaxSlabs; ++sl)
-                    if (sl < I.slabs) p[sl] = Pt<T, S>::load(Fp + (int64_t)sl * ns, i);
+                    if (sl < Rc.slabs) p[sl] = Pt<T, S>::load(Fp + (int64_t)sl * ns, i);
                 double a[S];
 #pragma unroll
                 for (int d = 0; d < S; ++d) a[d] = 0.0;
 #pragma unroll
                 for (int sl = 0; sl < kMaxSlabs; ++sl)
-                    if (sl < I.slabs) {
+                    if (sl < Rc.slabs) {
 #pragma unroll
                         for (int d = 0; d < S; ++d) a[d] += (double)p[sl].v[d];
                     }
