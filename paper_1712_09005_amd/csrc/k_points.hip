@@ -581,19 +581,23 @@ __global__ __launch_bounds__(256) void k_gather(LaunchMap map)
     __shared__ double sh[8];
     VB_BEGIN(map, K_GATHER)
     if (live(I)) {
-        const Geom& G = *I.geom;
+        // the record and geometry through the constant view (scalar loads),
+        // the item tables through the global view (no flat loads)
+        const TSNE_CONST Inst& Rc = *cview<Inst>(&I);
+        const TSNE_CONST Geom& G = *cview<Geom>(Rc.geom);
         const int ncell = G.n_cells;
-        const int total = I.item_start[ncell];
+        const int total = cview<int>(Rc.item_start)[ncell];
         const int t = lb * 256 + (int)threadIdx.x;
         double h1d = 0.0;
         if (t < total) {
-            const int n_int = G.n_int, n_cap = I.n_cap;
-            const int c = I.item_cell[t];
-            const int b = I.cell_start[c] + (t - I.item_start[c]) * I.kpts;
-            const int e = min(b + I.kpts, I.cell_start[c + 1]);
+            const TSNE_GLOBAL int* cstart = gview<int>(Rc.cell_start);
+            const int n_int = G.n_int, n_cap = Rc.n_cap;
+            const int c = gview<int>(Rc.item_cell)[t];
+            const int b = cstart[c] + (t - gview<int>(Rc.item_start)[c]) * Rc.kpts;
+            const int e = min(b + Rc.kpts, cstart[c + 1]);
             const int cx = c % n_int, cy = (S == 2) ? c / n_int : 0;
-            const T* sY = static_cast<const T*>(I.sY);
-            const T* V = static_cast<const T*>(I.V);
+            const T* sY = static_cast<const T*>(Rc.sY);
+            const T* V = static_cast<const T*>(Rc.V);
             const int64_t plane = (int64_t)n_cap * (S == 2 ? n_cap : 1);
             // node (m1, m0) of the cell in potential k
             auto vidx = [&](int k, int m) -> int64_t {
