@@ -74,6 +74,10 @@ __device__ __forceinline__ void block_excl_scan_bins(unsigned* v, unsigned* wsum
 static_assert(kDigitBins == 2 * 256, "two bins per thread");
 static_assert(kKeyTile == kSortTile, "the first pass's tiles are the key kernel's blocks");
 
+// A pair of 32-bit words as a native vector (loads and stores through the
+// global view)
+typedef unsigned U2 __attribute__((ext_vector_type(2)));
+
 // Digit counts of one tile, per pass, in LDS (a block of 256 threads)
 // written out: the tile's row of the count table, all kDigitBins entries.
 __device__ __forceinline__ void put_tile_counts(const unsigned* hist, unsigned* row)
@@ -226,8 +230,11 @@ __global__ __launch_bounds__(256) void k_tscan(LaunchMap map)
 // ranks them, 64 at a time in element order, against counts of its own in
 // LDS, so the ranking needs no barrier; the waves' counts are then combined
 // once per digit (earlier waves first), which keeps the ranks stable.
+// FP32 in one or two dimensions: at most 168 registers, three waves per SIMD.
+template <typename T, int S> constexpr int kSortWaves = (sizeof(T) == 4 && S <= 2) ? 3 : 1;
+
 template <typename T, int S, int PASS>
-__global__ __launch_bounds__(256) void k_sort(LaunchMap map)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kSortWaves<T, S>))) void k_sort(LaunchMap map)
 {
     constexpr int PER = kSortTile / 256;          // rounds of 64 elements per wave
     constexpr int WCH = kSortTile / 4;            // elements per wave
@@ -251,13 +258,14 @@ __global__ __launch_bounds__(256) void k_sort(LaunchMap map)
         for (int k = t; k < 4 * kDigitBins; k += 256) (&whist[0][0])[k] = 0;
         // the digit's count in earlier groups and over all groups (k_tscan)
         const int grp = tile / I.group_tiles, ng = I.ngroups_sort;
-        const unsigned* gt = I.gtot + (int64_t)PASS * ng * kDigitBins;
+        // tables and pairs through the global view: vector-memory accesses,
+        // which the LDS waits of the ranking and staging do not wait for
+        const TSNE_GLOBAL unsigned* gt = gview<unsigned>(I.gtot) + (int64_t)PASS * ng * kDigitBins;
         unsigned before[2] = {0u, 0u}, total[2] = {0u, 0u};
 #pragma unroll
         for (int g = 0; g < kScanGroups; ++g) {
-            const uint2 v = (g < ng && 2 * t < nbins)
-                                ? reinterpret_cast<const uint2*>(gt + (int64_t)g * kDigitBins)[t]
-                                : make_uint2(0u, 0u);
+            U2 v = {0u, 0u};
+            if (g < ng && 2 * t < nbins) v = reinterpret_cast<const TSNE_GLOBAL U2*>(gt + (int64_t)g * kDigitBins)[t];
             if (g < grp) {
                 before[0] += v.x;
                 before[1] += v.y;
@@ -266,14 +274,14 @@ __global__ __launch_bounds__(256) void k_sort(LaunchMap map)
             total[1] += v.y;
         }
         // the digit's count in earlier tiles of the group (k_tscan)
-        const uint2 ofs = reinterpret_cast<const uint2*>(
-            I.tcnt + ((int64_t)PASS * I.ntiles_sort + tile) * kDigitBins)[t];
+        const U2 ofs = reinterpret_cast<const TSNE_GLOBAL U2*>(
+            gview<unsigned>(I.tcnt) + ((int64_t)PASS * I.ntiles_sort + tile) * kDigitBins)[t];
         dbase[2 * t] = total[0];
         dbase[2 * t + 1] = total[1];
         const int64_t base = (int64_t)tile * kSortTile;
         const int64_t wbase = base + (int64_t)wv * WCH;
-        const uint2* kv_in = static_cast<const uint2*>(I.kv) + (int64_t)((PASS + 1) & 1) * n;
-        uint2* kv_out = static_cast<uint2*>(I.kv) + (int64_t)(PASS & 1) * n;
+        const TSNE_GLOBAL U2* kv_in = gview<U2>(I.kv) + (int64_t)((PASS + 1) & 1) * n;
+        TSNE_GLOBAL U2* kv_out = (TSNE_GLOBAL U2*)I.kv + (int64_t)(PASS & 1) * n;
         unsigned key[PER];
         int idx[PER];
         unsigned lrank[PER];
@@ -285,10 +293,10 @@ __global__ __launch_bounds__(256) void k_sort(LaunchMap map)
             lrank[r] = 0;
             if (e < n) {
                 if (PASS == 0) {
-                    key[r] = (unsigned)I.key[e];
+                    key[r] = (unsigned)gview<int>(I.key)[e];
                     idx[r] = (int)e;
                 } else {
-                    const uint2 q = kv_in[e];
+                    const U2 q = kv_in[e];
                     key[r] = q.x;
                     idx[r] = (int)q.y;
                 }
@@ -356,7 +364,12 @@ __global__ __launch_bounds__(256) void k_sort(LaunchMap map)
         if (!last) {
 #pragma unroll
             for (int r = 0; r < PER; ++r)
-                if (dst[r] >= 0) kv_out[dst[r]] = q[r];
+                if (dst[r] >= 0) {
+                    U2 w;
+                    w.x = q[r].x;
+                    w.y = q[r].y;
+                    kv_out[dst[r]] = w;
+                }
         } else {
             // every gather of the tile in flight before the first store
             Pt<T, S> y[PER];
@@ -366,8 +379,8 @@ __global__ __launch_bounds__(256) void k_sort(LaunchMap map)
 #pragma unroll
             for (int r = 0; r < PER; ++r)
                 if (dst[r] >= 0) {
-                    I.perm[dst[r]] = (int)q[r].y;
-                    I.skey[dst[r]] = q[r].x;
+                    ((TSNE_GLOBAL int*)I.perm)[dst[r]] = (int)q[r].y;
+                    ((TSNE_GLOBAL unsigned*)I.skey)[dst[r]] = q[r].x;
                     y[r].store(static_cast<T*>(I.sY), dst[r]);
                 }
         }
